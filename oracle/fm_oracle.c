@@ -1,0 +1,800 @@
+/*
+ * fm_oracle.c -- plain, slow, double-precision CPU oracle for the one-loop flow of the
+ * N-patch coupling function V(k1,k2,k3) of the two-dimensional Hubbard model, following
+ * D. Rohe and C. Honerkamp, "Quasi-particle functional Renormalisation Group calculations
+ * in the two-dimensional half-filled Hubbard model at finite temperatures"
+ * (arXiv:2005.00827).
+ *
+ * TEST INFRASTRUCTURE. This file is the checker for the HIP library, not part of it. Only
+ * the test suite, the smoke check and the benchmark's CPU-baseline leg load it. It shares
+ * no source, header, table, constant or generator with the HIP library; the two sides see
+ * only the same seeded inputs.
+ *
+ * What it computes, in the order the method states it:
+ *   - the dispersion of Sec. 2.1 (Eq. free_dispersion_xi) on a half-shifted L x L loop grid;
+ *   - angular Fermi-surface patches (Sec. 3.2 text on angular resolutions; App. A, Step 2 on
+ *     projecting onto the patch), or "identity" patching where every loop point is its own
+ *     patch and all momenta are exact (a test mode);
+ *   - the one-loop vertex flow (App. A, Eqs. vertex_flow_general, vertex_flow_simple,
+ *     vertex_flow_feedback_Z) written out for a spin-rotation-invariant static vertex with
+ *     the particle-particle, crossed and direct particle-hole terms, in a temperature flow
+ *     with scale s = ln T, each internal line weighted by the Z of its patch;
+ *   - fixed-step RK4 and Dormand-Prince 5(4) integration in ln T, with the stop rule
+ *     "largest |V| above a threshold" (Sec. 3.2, definition of U*(T)).
+ * The paper states the vertex flow only in shorthand and for the interaction flow; the
+ * explicit channel formula and the temperature-flow weight used here are readings that
+ * the tests pin against second-order perturbation theory, closed forms and a generic
+ * spin-resolved flow.
+ *
+ * Conventions (shared only as definitions, not as code):
+ *   loop point index j = jx + L*jy, k = -pi + 2 pi (j + 1/2) / L per axis;
+ *   transfers live on the unshifted grid q = 2 pi m / L, stored as (mx, my) mod L;
+ *   V is row-major V[(a*N + b)*N + c] with a, b the patches of the incoming k1, k2 and c
+ *   the patch of the outgoing k3 (spin of k1); k4 = k1 + k2 - k3 is implicit.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------------------ */
+/* Public structs (mirrored by ctypes in oracle.py).                                    */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+    double t, tp, mu;   /* Eq. free_dispersion_xi: hopping t, next-nearest t', chem. potential */
+    int N, L;           /* patch count, loop grid side */
+    int identity;       /* 1: patch = loop point (N = L*L), exact momenta */
+    unsigned channels;  /* bit 1: particle-particle, bit 2: crossed ph, bit 4: direct ph */
+} orc_model;
+
+typedef struct {
+    double T0, T_end;
+    int integrator;     /* 0: classical RK4, fixed steps in ln T; 1: Dormand-Prince 5(4) */
+    int n_steps;        /* RK4 step count */
+    double rtol, atol, h0, h_min;
+    double v_max;       /* stop when max |V| exceeds this */
+    int n_z;            /* 0: Z = 1 on every line */
+    const double *z_lnT; /* [n_z] ascending ln T nodes */
+    const double *z_tab; /* [n_z][N] */
+} orc_flowcfg;
+
+typedef struct {
+    double T_c, T_final, max_abs_V;
+    int status, n_accepted, n_rejected, n_rhs;
+} orc_result;
+
+enum { ORC_RUNNING = 0, ORC_DIVERGED = 1, ORC_NONFINITE = 2, ORC_REACHED_TEND = 3,
+       ORC_STEPFAIL = 4 };
+
+/* ------------------------------------------------------------------------------------ */
+/* Lattice, dispersion and patches.                                                    */
+/* ------------------------------------------------------------------------------------ */
+
+/* Eq. free_dispersion_xi: xi(k) = -2t(cos kx + cos ky) - 4t' cos kx cos ky - mu. */
+static double disp(const orc_model *m, double kx, double ky)
+{
+    return -2.0 * m->t * (cos(kx) + cos(ky)) - 4.0 * m->tp * cos(kx) * cos(ky) - m->mu;
+}
+
+/* Half-shifted loop grid: no point on the zone boundary or at Gamma. */
+static double grid_k(int j, int L) { return -M_PI + 2.0 * M_PI * (j + 0.5) / L; }
+
+/* Sector centres theta_a = theta_off + 2 pi a / N.  With N % 8 == 0 the centres contain the
+ * antinodal (theta = 0) and nodal (theta = pi/4) directions, as in the paper's count of
+ * seven patches from antinode to node giving 48 in total (Sec. 3.2). */
+static double theta_off(int N)
+{
+    if (N == 1 || N % 8 == 0) return 0.0;
+    if (N % 8 == 4) return M_PI / N;
+    return NAN;
+}
+
+static int patch_of(double kx, double ky, int N, double *margin)
+{
+    double x = (atan2(ky, kx) - theta_off(N)) * N / (2.0 * M_PI);
+    double r = (double)lround(x);
+    if (margin) *margin = 0.5 - fabs(x - r);
+    long p = ((long)r) % N;
+    if (p < 0) p += N;
+    return (int)p;
+}
+
+/* Fermi-surface point on the ray at angle th: the first sign change of xi between Gamma and
+ * the zone edge, found by a 4096-sample scan and bisection; no sign change means the sample
+ * of smallest |xi| is used. */
+static void fs_point(const orc_model *m, double th, double *kx, double *ky)
+{
+    const int ns = 4096;
+    double c = cos(th), s = sin(th);
+    double rmax = M_PI / fmax(fabs(c), fabs(s));
+    double f0 = disp(m, 0.0, 0.0);
+    double r_best = 0.0, f_best = fabs(f0);
+    if (f0 == 0.0) { *kx = 0.0; *ky = 0.0; return; }
+    double r_prev = 0.0, f_prev = f0;
+    for (int i = 1; i <= ns; ++i) {
+        double r = rmax * i / ns;
+        double f = disp(m, r * c, r * s);
+        if ((f_prev < 0.0 && f >= 0.0) || (f_prev > 0.0 && f <= 0.0)) {
+            double lo = r_prev, hi = r;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double fm = disp(m, mid * c, mid * s);
+                if ((f_prev < 0.0 && fm < 0.0) || (f_prev > 0.0 && fm > 0.0)) lo = mid;
+                else hi = mid;
+            }
+            *kx = hi * c; *ky = hi * s;
+            return;
+        }
+        if (fabs(f) < f_best) { f_best = fabs(f); r_best = r; }
+        r_prev = r; f_prev = f;
+    }
+    *kx = r_best * c; *ky = r_best * s;
+}
+
+static int mod_l(long x, int L) { long r = x % L; return (int)(r < 0 ? r + L : r); }
+
+typedef struct {
+    int N, L, np, identity;
+    double *xi;      /* [np] */
+    int *patch;      /* [np] */
+    int *anchor;     /* [N][2]: snapped k_F index (angular) or the loop index (identity) */
+    int pp_shift;    /* k_a + k_b on the index grid: anchor sum + pp_shift */
+    double margin;   /* smallest distance of a loop point to a sector boundary, in sectors */
+} geom;
+
+static void geom_free(geom *g)
+{
+    free(g->xi); free(g->patch); free(g->anchor);
+    memset(g, 0, sizeof(*g));
+}
+
+static int geom_build(const orc_model *m, geom *g)
+{
+    memset(g, 0, sizeof(*g));
+    int L = m->L, N = m->N;
+    if (L < 2 || (L & 1)) return -1;
+    if (m->identity) { if (N != L * L) return -1; }
+    else if (N < 1 || isnan(theta_off(N)) || (L % 4)) return -1;
+    g->N = N; g->L = L; g->np = L * L; g->identity = m->identity;
+    g->xi = (double *)malloc(sizeof(double) * g->np);
+    g->patch = (int *)malloc(sizeof(int) * g->np);
+    g->anchor = (int *)malloc(sizeof(int) * 2 * N);
+    g->margin = 0.5;
+    for (int jy = 0; jy < L; ++jy)
+        for (int jx = 0; jx < L; ++jx) {
+            int j = jx + L * jy;
+            double kx = grid_k(jx, L), ky = grid_k(jy, L);
+            g->xi[j] = disp(m, kx, ky);
+            if (m->identity) {
+                g->patch[j] = j;
+            } else {
+                double mg;
+                g->patch[j] = patch_of(kx, ky, N, &mg);
+                if (mg < g->margin) g->margin = mg;
+            }
+        }
+    if (m->identity) {
+        for (int a = 0; a < N; ++a) { g->anchor[2 * a] = a % L; g->anchor[2 * a + 1] = a / L; }
+        g->pp_shift = 1;
+    } else {
+        for (int a = 0; a < N; ++a) {
+            double kx, ky;
+            fs_point(m, theta_off(N) + 2.0 * M_PI * a / N, &kx, &ky);
+            g->anchor[2 * a] = mod_l(lround(kx * L / (2.0 * M_PI)), L);
+            g->anchor[2 * a + 1] = mod_l(lround(ky * L / (2.0 * M_PI)), L);
+        }
+        g->pp_shift = 0;
+    }
+    return 0;
+}
+
+/* Transfers as flat indices mx + L*my. */
+static int q_pp(const geom *g, int a, int b)
+{
+    int L = g->L;
+    int mx = mod_l(g->anchor[2 * a] + g->anchor[2 * b] + g->pp_shift, L);
+    int my = mod_l(g->anchor[2 * a + 1] + g->anchor[2 * b + 1] + g->pp_shift, L);
+    return mx + L * my;
+}
+static int q_diff(const geom *g, int x, int y) /* k_x - k_y */
+{
+    int L = g->L;
+    int mx = mod_l(g->anchor[2 * x] - g->anchor[2 * y], L);
+    int my = mod_l(g->anchor[2 * x + 1] - g->anchor[2 * y + 1], L);
+    return mx + L * my;
+}
+/* Partner of loop point j: pp: q - k_j;  ph: k_j + q. */
+static int partner_pp(int L, int q, int j)
+{
+    return mod_l((q % L) - (j % L) - 1, L) + L * mod_l((q / L) - (j / L) - 1, L);
+}
+static int partner_ph(int L, int q, int j)
+{
+    return mod_l((q % L) + (j % L), L) + L * mod_l((q / L) + (j / L), L);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Bubble weights.                                                                      */
+/*                                                                                      */
+/* chi(x,y;T) = -(f(x) - f(y))/(x - y) with the Fermi function f, i.e. the static         */
+/* particle-hole bubble of two bare lines (App. A, Step 1: bare lines (i w - xi)^-1); the   */
+/* particle-particle bubble is chi(x,-y).  With a = x/2T, b = y/2T,                        */
+/*   chi = (tanh a - tanh b) / (4T (a - b)),                                             */
+/*   T d/dT chi = -phi[a,b] / (4T),  phi(u) = u sech^2 u,  phi[a,b] its divided difference.*/
+/* The divided difference is evaluated through the exact identity                        */
+/*   phi[a,b] = sech^2 a - b * sinh(a+b) sech a sech b * (tanh a - tanh b)/(a-b),          */
+/* (from a sech^2 a - b sech^2 b = (a-b) sech^2 a + b (sech^2 a - sech^2 b) and            */
+/*  sech^2 a - sech^2 b = -sinh(a+b) sinh(a-b) sech^2 a sech^2 b), with every sinh*sech*sech */
+/* product formed from exponentials of non-positive arguments.                           */
+/* ------------------------------------------------------------------------------------ */
+
+/* sinh(s) sech(a) sech(b) for |s| <= |a| + |b|. */
+static double sh_sech_sech(double s, double a, double b)
+{
+    double as = fabs(s), aa = fabs(a), ab = fabs(b);
+    if (as == 0.0) return 0.0;
+    double num = -2.0 * expm1(-2.0 * as) * exp(as - aa - ab);
+    double den = (1.0 + exp(-2.0 * aa)) * (1.0 + exp(-2.0 * ab));
+    return copysign(num / den, s);
+}
+
+static double sech2(double a)
+{
+    double e = exp(-2.0 * fabs(a));
+    return 4.0 * e / ((1.0 + e) * (1.0 + e));
+}
+
+/* (tanh a - tanh b)/(a - b) = sinh(a-b)/(a-b) sech a sech b. */
+static double tanh_dd(double a, double b)
+{
+    double d = a - b;
+    if (d == 0.0) return sech2(a);
+    return sh_sech_sech(d, a, b) / d;
+}
+
+/* phi[a,b] is symmetric; the identity is used with |a| >= |b|: its second term equals
+ * b (sech^2 b - sech^2 a)/(a - b), which for |b| > |a| would nearly cancel sech^2 a. */
+double orc_phi_dd(double a, double b)
+{
+    if (fabs(a) < fabs(b)) { double t = a; a = b; b = t; }
+    return sech2(a) - b * sh_sech_sech(a + b, a, b) * tanh_dd(a, b);
+}
+
+double orc_chi_ph(double x, double y, double T) { return tanh_dd(x / (2 * T), y / (2 * T)) / (4 * T); }
+double orc_chi_pp(double x, double y, double T) { return orc_chi_ph(x, -y, T); }
+double orc_chidot_ph(double x, double y, double T) { return -orc_phi_dd(x / (2 * T), y / (2 * T)) / (4 * T); }
+double orc_chidot_pp(double x, double y, double T) { return orc_chidot_ph(x, -y, T); }
+
+/* ------------------------------------------------------------------------------------ */
+/* Geometry query (for host-side tests).                                                */
+/* ------------------------------------------------------------------------------------ */
+int orc_geometry(const orc_model *m, double *xi_out, int *patch_out, int *anchor_out,
+                 double *margin_out)
+{
+    geom g;
+    if (geom_build(m, &g)) return -1;
+    if (xi_out) memcpy(xi_out, g.xi, sizeof(double) * g.np);
+    if (patch_out) memcpy(patch_out, g.patch, sizeof(int) * g.np);
+    if (anchor_out) memcpy(anchor_out, g.anchor, sizeof(int) * 2 * g.N);
+    if (margin_out) *margin_out = g.margin;
+    geom_free(&g);
+    return 0;
+}
+
+/* Distinct transfers: counts of {q_pp(a,b)} and {k_x - k_y}. */
+int orc_transfer_counts(const orc_model *m, int *n_pp, int *n_ph)
+{
+    geom g;
+    if (geom_build(m, &g)) return -1;
+    char *s1 = (char *)calloc(g.np, 1), *s2 = (char *)calloc(g.np, 1);
+    int c1 = 0, c2 = 0;
+    for (int a = 0; a < g.N; ++a)
+        for (int b = 0; b < g.N; ++b) {
+            int q = q_pp(&g, a, b);
+            if (!s1[q]) { s1[q] = 1; ++c1; }
+            q = q_diff(&g, a, b);
+            if (!s2[q]) { s2[q] = 1; ++c2; }
+        }
+    *n_pp = c1; *n_ph = c2;
+    free(s1); free(s2); geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Right-hand side, direct form.                                                        */
+/*                                                                                      */
+/* With W_X(j) = Z[pi(j)] Z[pi(j')] T d/dT chi_X(xi_j, xi_j') and sum_j = (1/L^2) sum over  */
+/* the loop grid, the temperature-flow derivative dV/d ln T (a,b,c) is                   */
+/*   - sum_j W_pp(j; q_pp)  V(a,b,pj) V(pj,pj',c)                j' = q_pp - j            */
+/*   + sum_j W_ph(j; q_cr)  V(a,pj,pj') V(pj',b,c)               j' = j + q_cr            */
+/*   + sum_j W_ph(j; q_d) [-2 V(a,pj,c) V(pj',b,pj)                                        */
+/*                         + V(pj,a,c) V(pj',b,pj) + V(a,pj,c) V(b,pj',pj)]  j' = j + q_d  */
+/* where pj = pi(j), q_pp = k1 + k2, q_cr = k3 - k2, q_d = k1 - k3.  This is the one-loop   */
+/* diagram of Eq. vertex_flow_general with the particle-particle, crossed and direct        */
+/* particle-hole terms written out for the spin-rotation-invariant coupling function       */
+/* (App. A: separating spin and momentum dependence), Z inserted on internal lines as in   */
+/* Eq. vertex_flow_feedback_Z with Z projected onto the patch of each line.               */
+/* ------------------------------------------------------------------------------------ */
+
+#define VIX(N, a, b, c) ((((size_t)(a)) * (N) + (b)) * (N) + (c))
+
+static void fill_weights(const geom *g, double T, const double *Z, int pp, int q, double *w)
+{
+    int L = g->L;
+    for (int j = 0; j < g->np; ++j) {
+        int jp = pp ? partner_pp(L, q, j) : partner_ph(L, q, j);
+        double chid = pp ? orc_chidot_pp(g->xi[j], g->xi[jp], T)
+                         : orc_chidot_ph(g->xi[j], g->xi[jp], T);
+        double z = Z ? Z[g->patch[j]] * Z[g->patch[jp]] : 1.0;
+        w[j] = z * chid;
+    }
+}
+
+static double rhs_one(const geom *g, unsigned ch, const double *V, int a, int b, int c,
+                      const double *wpp, int qpp, const double *wcr, int qcr,
+                      const double *wd, int qd)
+{
+    int N = g->N, L = g->L;
+    double s = 0.0;
+    if (ch & 1u)
+        for (int j = 0; j < g->np; ++j) {
+            int pj = g->patch[j], pq = g->patch[partner_pp(L, qpp, j)];
+            s -= wpp[j] * V[VIX(N, a, b, pj)] * V[VIX(N, pj, pq, c)];
+        }
+    if (ch & 2u)
+        for (int j = 0; j < g->np; ++j) {
+            int pj = g->patch[j], pq = g->patch[partner_ph(L, qcr, j)];
+            s += wcr[j] * V[VIX(N, a, pj, pq)] * V[VIX(N, pq, b, c)];
+        }
+    if (ch & 4u)
+        for (int j = 0; j < g->np; ++j) {
+            int pj = g->patch[j], pq = g->patch[partner_ph(L, qd, j)];
+            s += wd[j] * (-2.0 * V[VIX(N, a, pj, c)] * V[VIX(N, pq, b, pj)]
+                          + V[VIX(N, pj, a, c)] * V[VIX(N, pq, b, pj)]
+                          + V[VIX(N, a, pj, c)] * V[VIX(N, b, pq, pj)]);
+        }
+    return s / (double)g->np;
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+/* Weight tables for every transfer that occurs, keyed by the flat transfer index. */
+typedef struct { double **pp, **ph; } wcache;
+
+static void wcache_build(const geom *g, unsigned ch, double T, const double *Z, wcache *wc)
+{
+    int np = g->np, N = g->N;
+    wc->pp = (double **)calloc(np, sizeof(double *));
+    wc->ph = (double **)calloc(np, sizeof(double *));
+    char *need_pp = (char *)calloc(np, 1), *need_ph = (char *)calloc(np, 1);
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            if (ch & 1u) need_pp[q_pp(g, a, b)] = 1;
+            if (ch & 6u) need_ph[q_diff(g, a, b)] = 1;
+        }
+    int *list = (int *)malloc(sizeof(int) * 2 * np);
+    int n = 0;
+    for (int q = 0; q < np; ++q) {
+        if (need_pp[q]) { wc->pp[q] = (double *)malloc(sizeof(double) * np); list[n++] = q; }
+        if (need_ph[q]) { wc->ph[q] = (double *)malloc(sizeof(double) * np); list[n++] = -1 - q; }
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < n; ++i) {
+        int q = list[i] >= 0 ? list[i] : -1 - list[i];
+        int pp = list[i] >= 0;
+        fill_weights(g, T, Z, pp, q, pp ? wc->pp[q] : wc->ph[q]);
+    }
+    free(list); free(need_pp); free(need_ph);
+}
+
+static void wcache_free(const geom *g, wcache *wc)
+{
+    for (int q = 0; q < g->np; ++q) { free(wc->pp[q]); free(wc->ph[q]); }
+    free(wc->pp); free(wc->ph);
+}
+
+static void rhs_geom(const geom *g, unsigned ch, double T, const double *Z, const double *V,
+                     double *dV)
+{
+    int N = g->N;
+    wcache wc;
+    wcache_build(g, ch, T, Z, &wc);
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b)
+            for (int c = 0; c < N; ++c) {
+                int qpp = q_pp(g, a, b), qcr = q_diff(g, c, b), qd = q_diff(g, a, c);
+                dV[VIX(N, a, b, c)] = rhs_one(g, ch, V, a, b, c, wc.pp[qpp], qpp,
+                                              wc.ph[qcr], qcr, wc.ph[qd], qd);
+            }
+    wcache_free(g, &wc);
+}
+
+int orc_rhs(const orc_model *m, double T, const double *Z, const double *V, double *dV,
+            int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    rhs_geom(&g, m->channels, T, Z, V, dV);
+    geom_free(&g);
+    return 0;
+}
+
+/* Sampled outputs: weights computed per output, nothing cached. */
+int orc_rhs_points(const orc_model *m, double T, const double *Z, const double *V, int n,
+                   const int *abc, double *out, int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        double *wpp = (double *)malloc(sizeof(double) * g.np);
+        double *wcr = (double *)malloc(sizeof(double) * g.np);
+        double *wd = (double *)malloc(sizeof(double) * g.np);
+#pragma omp for schedule(dynamic)
+        for (int i = 0; i < n; ++i) {
+            int a = abc[3 * i], b = abc[3 * i + 1], c = abc[3 * i + 2];
+            int qpp = q_pp(&g, a, b), qcr = q_diff(&g, c, b), qd = q_diff(&g, a, c);
+            fill_weights(&g, T, Z, 1, qpp, wpp);
+            fill_weights(&g, T, Z, 0, qcr, wcr);
+            fill_weights(&g, T, Z, 0, qd, wd);
+            out[i] = rhs_one(&g, m->channels, V, a, b, c, wpp, qpp, wcr, qcr, wd, qd);
+        }
+        free(wpp); free(wcr); free(wd);
+    }
+    geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Right-hand side, binned form: the same sums regrouped by the patch pair (a',b') of the  */
+/* two internal lines, B_q(a',b') = sum over j with pi(j)=a', pi(j')=b' of T d/dT chi.    */
+/* Exists only to check that regrouping against the direct form.                          */
+/* ------------------------------------------------------------------------------------ */
+int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *V, double *dV,
+                   int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    int N = g.N, L = g.L, np = g.np;
+    unsigned ch = m->channels;
+    size_t NN = (size_t)N * N;
+    double **bpp = (double **)calloc(np, sizeof(double *));
+    double **bph = (double **)calloc(np, sizeof(double *));
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            int q = q_pp(&g, a, b);
+            if (!bpp[q]) bpp[q] = (double *)calloc(NN, sizeof(double));
+            q = q_diff(&g, a, b);
+            if (!bph[q]) bph[q] = (double *)calloc(NN, sizeof(double));
+        }
+#pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < np; ++q) {
+        for (int j = 0; j < np; ++j) {
+            if (bpp[q]) {
+                int jp = partner_pp(L, q, j);
+                bpp[q][(size_t)g.patch[j] * N + g.patch[jp]] += orc_chidot_pp(g.xi[j], g.xi[jp], T);
+            }
+            if (bph[q]) {
+                int jp = partner_ph(L, q, j);
+                bph[q][(size_t)g.patch[j] * N + g.patch[jp]] += orc_chidot_ph(g.xi[j], g.xi[jp], T);
+            }
+        }
+    }
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b)
+            for (int c = 0; c < N; ++c) {
+                const double *Bp = bpp[q_pp(&g, a, b)];
+                const double *Bc = bph[q_diff(&g, c, b)];
+                const double *Bd = bph[q_diff(&g, a, c)];
+                double s = 0.0;
+                for (int x = 0; x < N; ++x)
+                    for (int y = 0; y < N; ++y) {
+                        double zz = Z ? Z[x] * Z[y] : 1.0;
+                        size_t xy = (size_t)x * N + y;
+                        if (ch & 1u) s -= zz * Bp[xy] * V[VIX(N, a, b, x)] * V[VIX(N, x, y, c)];
+                        if (ch & 2u) s += zz * Bc[xy] * V[VIX(N, a, x, y)] * V[VIX(N, y, b, c)];
+                        if (ch & 4u)
+                            s += zz * Bd[xy] * (-2.0 * V[VIX(N, a, x, c)] * V[VIX(N, y, b, x)]
+                                                + V[VIX(N, x, a, c)] * V[VIX(N, y, b, x)]
+                                                + V[VIX(N, a, x, c)] * V[VIX(N, b, y, x)]);
+                    }
+                dV[VIX(N, a, b, c)] = s / (double)np;
+            }
+    for (int q = 0; q < np; ++q) { free(bpp[q]); free(bph[q]); }
+    free(bpp); free(bph);
+    geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Quasi-particle weights along the flow: a table Z_a(T_i), linear in ln T, clamped.       */
+/* ------------------------------------------------------------------------------------ */
+static void z_at(const orc_flowcfg *f, int N, double lnT, double *Z)
+{
+    if (f->n_z <= 0) { for (int a = 0; a < N; ++a) Z[a] = 1.0; return; }
+    int n = f->n_z;
+    if (n == 1 || lnT <= f->z_lnT[0]) { memcpy(Z, f->z_tab, sizeof(double) * N); return; }
+    if (lnT >= f->z_lnT[n - 1]) { memcpy(Z, f->z_tab + (size_t)(n - 1) * N, sizeof(double) * N); return; }
+    int i = 0;
+    while (i + 1 < n - 1 && f->z_lnT[i + 1] <= lnT) ++i;
+    double w = (lnT - f->z_lnT[i]) / (f->z_lnT[i + 1] - f->z_lnT[i]);
+    for (int a = 0; a < N; ++a)
+        Z[a] = (1.0 - w) * f->z_tab[(size_t)i * N + a] + w * f->z_tab[(size_t)(i + 1) * N + a];
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Integrators in s = ln T.                                                             */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+    const geom *g;
+    const orc_model *m;
+    const orc_flowcfg *f;
+    double *Z;
+    long n_rhs;
+} flowctx;
+
+static void eval_f(flowctx *cx, double s, const double *V, double *k)
+{
+    z_at(cx->f, cx->g->N, s, cx->Z);
+    rhs_geom(cx->g, cx->m->channels, exp(s), cx->f->n_z > 0 ? cx->Z : NULL, V, k);
+    cx->n_rhs++;
+}
+
+static double max_abs(const double *V, size_t n, int *finite)
+{
+    double m = 0.0;
+    *finite = 1;
+    for (size_t i = 0; i < n; ++i) {
+        if (!isfinite(V[i])) { *finite = 0; return INFINITY; }
+        if (fabs(V[i]) > m) m = fabs(V[i]);
+    }
+    return m;
+}
+
+/* Dormand & Prince (1980), RK5(4)7M: nodes, coupling, 5th-order weights (= last coupling
+ * row, first-same-as-last) and the 5th-minus-4th-order error weights. */
+static const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0},
+    {1.0 / 5},
+    {3.0 / 40, 9.0 / 40},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656},
+    {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+static const double DP_E[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920,
+                               -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
+
+int orc_dopri_tableau(double *c, double *a, double *e)
+{
+    memcpy(c, DP_C, sizeof(DP_C));
+    memcpy(a, DP_A, sizeof(DP_A));
+    memcpy(e, DP_E, sizeof(DP_E));
+    return 0;
+}
+
+/* One Dormand-Prince attempt from (s, V) with step h, k[0] = f(s, V) given.  Fills k[1..6],
+ * Vn = the 5th-order solution (also the last stage's argument), returns the scaled error
+ * norm max_i |E_i| / (atol + rtol max(|V_i|, |Vn_i|)), or INFINITY if anything is
+ * non-finite. */
+static double dopri_attempt(flowctx *cx, double s, double h, const double *V, double **k,
+                            double *Vn, double *tmp, size_t n)
+{
+    const orc_flowcfg *f = cx->f;
+    for (int st = 1; st < 7; ++st) {
+        double *arg = (st == 6) ? Vn : tmp;
+        for (size_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int l = 0; l < st; ++l) acc += DP_A[st][l] * k[l][i];
+            arg[i] = V[i] + h * acc;
+        }
+        eval_f(cx, s + DP_C[st] * h, arg, k[st]);
+    }
+    double err = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        double e = 0.0;
+        for (int l = 0; l < 7; ++l) e += DP_E[l] * k[l][i];
+        e = fabs(h * e);
+        double sc = f->atol + f->rtol * fmax(fabs(V[i]), fabs(Vn[i]));
+        double r = e / sc;
+        if (!isfinite(r) || !isfinite(Vn[i])) return INFINITY;
+        if (r > err) err = r;
+    }
+    return err;
+}
+
+static double step_factor(double err)
+{
+    if (err == 0.0) return 5.0;
+    double fac = 0.9 * pow(err, -0.2);
+    return fmin(5.0, fmax(0.2, fac));
+}
+
+/* Stop rule: the largest |V| above v_max (or a non-finite value) ends the flow; T_c is
+ * interpolated linearly in (ln T, ln max|V|) across the last accepted step. */
+static int stop_test(const orc_flowcfg *f, double s_prev, double m_prev, double s_new,
+                     double m_new, int finite, double *lnTc)
+{
+    if (!finite) { *lnTc = s_new; return ORC_NONFINITE; }
+    if (m_new > f->v_max) {
+        if (m_prev > 0.0 && m_new != m_prev)
+            *lnTc = s_prev + (log(f->v_max) - log(m_prev)) * (s_new - s_prev) /
+                                 (log(m_new) - log(m_prev));
+        else
+            *lnTc = s_new;
+        return ORC_DIVERGED;
+    }
+    return ORC_RUNNING;
+}
+
+/*
+ * Full flow from V = U at T0.  trace (optional) receives (ln T, max|V|) after every accepted
+ * step, starting with the initial point; *n_trace is its length (capped at max_trace).
+ */
+int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
+             orc_result *res, double *trace, int max_trace, int *n_trace, int nthreads)
+{
+    geom g;
+    if (!(f->T0 > f->T_end) || !(f->T_end > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    size_t n = (size_t)g.N * g.N * g.N;
+    double *V = (double *)malloc(sizeof(double) * n);
+    double *Vn = (double *)malloc(sizeof(double) * n);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    double *kb = (double *)malloc(sizeof(double) * n * 7);
+    double *k[7];
+    for (int i = 0; i < 7; ++i) k[i] = kb + (size_t)i * n;
+    double *Z = (double *)malloc(sizeof(double) * g.N);
+    flowctx cx = {&g, m, f, Z, 0};
+    for (size_t i = 0; i < n; ++i) V[i] = U;
+
+    double s0 = log(f->T0), s_end = log(f->T_end), s = s0;
+    int finite, status = ORC_RUNNING, nacc = 0, nrej = 0, ntr = 0;
+    double mV = max_abs(V, n, &finite), lnTc = NAN;
+    if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
+    if (!finite) { status = ORC_NONFINITE; lnTc = s; }
+    else if (mV > f->v_max) { status = ORC_DIVERGED; lnTc = s; }
+
+    if (status == ORC_RUNNING && f->integrator == 0) {
+        double h = (s_end - s0) / f->n_steps;
+        for (int st = 0; st < f->n_steps && status == ORC_RUNNING; ++st) {
+            double sn = s0 + st * h;
+            eval_f(&cx, sn, V, k[0]);
+            for (size_t i = 0; i < n; ++i) tmp[i] = V[i] + 0.5 * h * k[0][i];
+            eval_f(&cx, sn + 0.5 * h, tmp, k[1]);
+            for (size_t i = 0; i < n; ++i) tmp[i] = V[i] + 0.5 * h * k[1][i];
+            eval_f(&cx, sn + 0.5 * h, tmp, k[2]);
+            for (size_t i = 0; i < n; ++i) tmp[i] = V[i] + h * k[2][i];
+            eval_f(&cx, sn + h, tmp, k[3]);
+            for (size_t i = 0; i < n; ++i)
+                V[i] += h / 6.0 * (k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i]);
+            double s_new = (st + 1 == f->n_steps) ? s_end : s0 + (st + 1) * h;
+            double m_new = max_abs(V, n, &finite);
+            ++nacc;
+            status = stop_test(f, s, mV, s_new, m_new, finite, &lnTc);
+            s = s_new; mV = m_new;
+            if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
+        }
+        if (status == ORC_RUNNING) status = ORC_REACHED_TEND;
+    } else if (status == ORC_RUNNING) {
+        double span = fabs(s_end - s0);
+        double h = f->h0 != 0.0 ? f->h0 : (s_end - s0) / 200.0;
+        double hmin = f->h_min > 0.0 ? f->h_min : 1e-8 * span;
+        eval_f(&cx, s, V, k[0]);
+        while (status == ORC_RUNNING) {
+            if (s <= s_end) { status = ORC_REACHED_TEND; break; }
+            int last = (s + h <= s_end);
+            double ht = last ? (s_end - s) : h;
+            double err = dopri_attempt(&cx, s, ht, V, k, Vn, tmp, n);
+            if (err <= 1.0) {
+                double s_new = last ? s_end : s + ht;
+                double m_new = max_abs(Vn, n, &finite);
+                memcpy(V, Vn, sizeof(double) * n);
+                memcpy(k[0], k[6], sizeof(double) * n);
+                ++nacc;
+                status = stop_test(f, s, mV, s_new, m_new, finite, &lnTc);
+                s = s_new; mV = m_new;
+                if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
+                h = ht * step_factor(err);
+            } else {
+                ++nrej;
+                h = isfinite(err) ? ht * step_factor(err) : 0.5 * ht;
+            }
+            if (status == ORC_RUNNING && fabs(h) < hmin) status = ORC_STEPFAIL;
+        }
+    }
+    if (res) {
+        res->status = status;
+        res->T_c = (status == ORC_DIVERGED || status == ORC_NONFINITE) ? exp(lnTc) : NAN;
+        res->T_final = exp(s);
+        res->max_abs_V = mV;
+        res->n_accepted = nacc;
+        res->n_rejected = nrej;
+        res->n_rhs = (int)cx.n_rhs;
+    }
+    if (V_out) memcpy(V_out, V, sizeof(double) * n);
+    if (n_trace) *n_trace = ntr;
+    free(V); free(Vn); free(tmp); free(kb); free(Z);
+    geom_free(&g);
+    return 0;
+}
+
+/*
+ * One step from (lnT, V) with step *h, for step-by-step comparison.  RK4: always accepted,
+ * *h unchanged.  Dormand-Prince: k1 evaluated here (no carry-over between calls); on
+ * acceptance V and lnT advance; *h becomes the proposed next step either way.
+ */
+int orc_step(const orc_model *m, const orc_flowcfg *f, double *lnT, double *h, double *V,
+             int *accepted, double *err_out, int nthreads)
+{
+    geom g;
+    if (geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    size_t n = (size_t)g.N * g.N * g.N;
+    double *Vn = (double *)malloc(sizeof(double) * n);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    double *kb = (double *)malloc(sizeof(double) * n * 7);
+    double *k[7];
+    for (int i = 0; i < 7; ++i) k[i] = kb + (size_t)i * n;
+    double *Z = (double *)malloc(sizeof(double) * g.N);
+    flowctx cx = {&g, m, f, Z, 0};
+    double s = *lnT, hh = *h;
+    eval_f(&cx, s, V, k[0]);
+    if (f->integrator == 0) {
+        for (size_t i = 0; i < n; ++i) tmp[i] = V[i] + 0.5 * hh * k[0][i];
+        eval_f(&cx, s + 0.5 * hh, tmp, k[1]);
+        for (size_t i = 0; i < n; ++i) tmp[i] = V[i] + 0.5 * hh * k[1][i];
+        eval_f(&cx, s + 0.5 * hh, tmp, k[2]);
+        for (size_t i = 0; i < n; ++i) tmp[i] = V[i] + hh * k[2][i];
+        eval_f(&cx, s + hh, tmp, k[3]);
+        for (size_t i = 0; i < n; ++i)
+            V[i] += hh / 6.0 * (k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i]);
+        *lnT = s + hh;
+        *accepted = 1;
+        if (err_out) *err_out = 0.0;
+    } else {
+        double err = dopri_attempt(&cx, s, hh, V, k, Vn, tmp, n);
+        if (err_out) *err_out = err;
+        if (err <= 1.0) {
+            memcpy(V, Vn, sizeof(double) * n);
+            *lnT = s + hh;
+            *accepted = 1;
+            *h = hh * step_factor(err);
+        } else {
+            *accepted = 0;
+            *h = isfinite(err) ? hh * step_factor(err) : 0.5 * hh;
+        }
+    }
+    free(Vn); free(tmp); free(kb); free(Z);
+    geom_free(&g);
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

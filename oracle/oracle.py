@@ -1,0 +1,252 @@
+"""ctypes wrapper of the double-precision CPU oracle (``fm_oracle.c``).
+
+TEST INFRASTRUCTURE. The oracle checks the HIP library; it is not part of it. Only the test
+suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import this
+module. It shares no code with ``paper_2005_00827_amd``; both sides only receive the same
+seeded inputs from ``paper_2005_00827_amd.inputs``.
+
+Functions mirror the definitions written out in ``fm_oracle.c``:
+
+* geometry of the half-shifted loop grid, angular patches and snapped Fermi points
+  (Sec. 2.1 Eq. free_dispersion_xi; Sec. 3.2 on angular patch resolutions);
+* the bubble weights chi and T d/dT chi;
+* the one-loop flow right-hand side dV/d ln T (App. A, Eqs. vertex_flow_general and
+  vertex_flow_feedback_Z, written out per channel), direct and binned;
+* RK4 / Dormand-Prince flows in ln T with the stop rule of Sec. 3.2 (largest |V| above a
+  threshold).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from ctypes import POINTER, c_double, c_int, c_uint
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CH_PP, CH_CR, CH_D, CH_ALL = 1, 2, 4, 7
+RUNNING, DIVERGED, NONFINITE, REACHED_TEND, STEPFAIL = 0, 1, 2, 3, 4
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("t", c_double), ("tp", c_double), ("mu", c_double), ("N", c_int),
+                ("L", c_int), ("identity", c_int), ("channels", c_uint)]
+
+
+class FlowCfg(ctypes.Structure):
+    _fields_ = [("T0", c_double), ("T_end", c_double), ("integrator", c_int),
+                ("n_steps", c_int), ("rtol", c_double), ("atol", c_double),
+                ("h0", c_double), ("h_min", c_double), ("v_max", c_double),
+                ("n_z", c_int), ("z_lnT", POINTER(c_double)), ("z_tab", POINTER(c_double))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("T_c", c_double), ("T_final", c_double), ("max_abs_V", c_double),
+                ("status", c_int), ("n_accepted", c_int), ("n_rejected", c_int),
+                ("n_rhs", c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        d, i = c_double, c_int
+        pd, pi = POINTER(c_double), POINTER(c_int)
+        pm, pf, pr = POINTER(Model), POINTER(FlowCfg), POINTER(Result)
+        sig = {
+            "orc_phi_dd": (d, [d, d]),
+            "orc_chi_ph": (d, [d, d, d]), "orc_chi_pp": (d, [d, d, d]),
+            "orc_chidot_ph": (d, [d, d, d]), "orc_chidot_pp": (d, [d, d, d]),
+            "orc_geometry": (i, [pm, pd, pi, pi, pd]),
+            "orc_transfer_counts": (i, [pm, pi, pi]),
+            "orc_rhs": (i, [pm, d, pd, pd, pd, i]),
+            "orc_rhs_binned": (i, [pm, d, pd, pd, pd, i]),
+            "orc_rhs_points": (i, [pm, d, pd, pd, i, pi, pd, i]),
+            "orc_flow": (i, [pm, pf, d, pd, pr, pd, i, pi, i]),
+            "orc_step": (i, [pm, pf, pd, pd, pd, pi, pd, i]),
+            "orc_dopri_tableau": (i, [pd, pd, pd]),
+            "orc_num_threads": (i, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _pd(a):
+    return a.ctypes.data_as(POINTER(c_double)) if a is not None else None
+
+
+def _pi(a):
+    return a.ctypes.data_as(POINTER(c_int)) if a is not None else None
+
+
+def model(N, L, t=1.0, tp=0.0, mu=0.0, identity=False, channels=CH_ALL) -> Model:
+    return Model(float(t), float(tp), float(mu), int(N), int(L), int(bool(identity)),
+                 int(channels))
+
+
+def n_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------------------
+# weights
+# --------------------------------------------------------------------------------------
+def phi_dd(a, b):
+    return lib().orc_phi_dd(float(a), float(b))
+
+
+def chi_ph(x, y, T):
+    return lib().orc_chi_ph(float(x), float(y), float(T))
+
+
+def chi_pp(x, y, T):
+    return lib().orc_chi_pp(float(x), float(y), float(T))
+
+
+def chidot_ph(x, y, T):
+    return lib().orc_chidot_ph(float(x), float(y), float(T))
+
+
+def chidot_pp(x, y, T):
+    return lib().orc_chidot_pp(float(x), float(y), float(T))
+
+
+# --------------------------------------------------------------------------------------
+# geometry
+# --------------------------------------------------------------------------------------
+def geometry(m: Model):
+    """Returns (xi[L*L], patch[L*L], anchor[N,2], min boundary margin in sectors)."""
+    np_ = m.L * m.L
+    xi = np.zeros(np_, np.float64)
+    patch = np.zeros(np_, np.int32)
+    anchor = np.zeros((m.N, 2), np.int32)
+    margin = c_double(0.0)
+    rc = lib().orc_geometry(ctypes.byref(m), _pd(xi), _pi(patch), _pi(anchor),
+                            ctypes.byref(margin))
+    if rc:
+        raise ValueError("oracle geometry rejected N=%d L=%d" % (m.N, m.L))
+    return xi, patch, anchor, margin.value
+
+
+def transfer_counts(m: Model):
+    a, b = c_int(0), c_int(0)
+    if lib().orc_transfer_counts(ctypes.byref(m), ctypes.byref(a), ctypes.byref(b)):
+        raise ValueError("bad model")
+    return a.value, b.value
+
+
+# --------------------------------------------------------------------------------------
+# right-hand side
+# --------------------------------------------------------------------------------------
+def _zarg(Z, N):
+    if Z is None:
+        return None
+    Z = np.ascontiguousarray(Z, np.float64)
+    assert Z.shape == (N,)
+    return Z
+
+
+def rhs(m: Model, T, V, Z=None, nthreads=0, binned=False):
+    N = m.N
+    V = np.ascontiguousarray(V, np.float64).reshape(N * N * N)
+    Z = _zarg(Z, N)
+    out = np.zeros_like(V)
+    fn = lib().orc_rhs_binned if binned else lib().orc_rhs
+    if fn(ctypes.byref(m), float(T), _pd(Z), _pd(V), _pd(out), int(nthreads)):
+        raise ValueError("oracle rhs rejected its arguments")
+    return out.reshape(N, N, N)
+
+
+def rhs_points(m: Model, T, V, abc, Z=None, nthreads=0):
+    N = m.N
+    V = np.ascontiguousarray(V, np.float64).reshape(N * N * N)
+    Z = _zarg(Z, N)
+    abc = np.ascontiguousarray(abc, np.int32).reshape(-1, 3)
+    out = np.zeros(abc.shape[0], np.float64)
+    if lib().orc_rhs_points(ctypes.byref(m), float(T), _pd(Z), _pd(V), abc.shape[0],
+                            _pi(abc), _pd(out), int(nthreads)):
+        raise ValueError("oracle rhs_points rejected its arguments")
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# flows
+# --------------------------------------------------------------------------------------
+def flowcfg(T0=1.0, T_end=0.01, integrator=0, n_steps=200, rtol=1e-6, atol=None, U=1.0,
+            h0=0.0, h_min=0.0, v_max=20.0, z_lnT=None, z_tab=None):
+    """Build a FlowCfg; keeps references to the Z arrays on the returned object."""
+    if atol is None:
+        atol = 1e-9 * max(1.0, abs(U))
+    cfg = FlowCfg(float(T0), float(T_end), int(integrator), int(n_steps), float(rtol),
+                  float(atol), float(h0), float(h_min), float(v_max), 0, None, None)
+    if z_tab is not None:
+        z_lnT = np.ascontiguousarray(z_lnT, np.float64)
+        z_tab = np.ascontiguousarray(z_tab, np.float64)
+        assert z_tab.shape[0] == z_lnT.shape[0]
+        cfg.n_z = z_lnT.shape[0]
+        cfg.z_lnT = _pd(z_lnT)
+        cfg.z_tab = _pd(z_tab)
+        cfg._keep = (z_lnT, z_tab)
+    return cfg
+
+
+def flow(m: Model, cfg: FlowCfg, U, nthreads=0, max_trace=100000):
+    N = m.N
+    V = np.zeros(N * N * N, np.float64)
+    res = Result()
+    trace = np.zeros((max_trace, 2), np.float64)
+    ntr = c_int(0)
+    if lib().orc_flow(ctypes.byref(m), ctypes.byref(cfg), float(U), _pd(V), ctypes.byref(res),
+                      _pd(trace), max_trace, ctypes.byref(ntr), int(nthreads)):
+        raise ValueError("oracle flow rejected its arguments")
+    return V.reshape(N, N, N), res.as_dict(), trace[: ntr.value].copy()
+
+
+def step(m: Model, cfg: FlowCfg, lnT, h, V, nthreads=0):
+    """One step; returns (lnT, h_next, V, accepted, err)."""
+    N = m.N
+    V = np.ascontiguousarray(V, np.float64).reshape(N * N * N).copy()
+    lt, hh, acc, err = c_double(lnT), c_double(h), c_int(0), c_double(0.0)
+    if lib().orc_step(ctypes.byref(m), ctypes.byref(cfg), ctypes.byref(lt), ctypes.byref(hh),
+                      _pd(V), ctypes.byref(acc), ctypes.byref(err), int(nthreads)):
+        raise ValueError("oracle step rejected its arguments")
+    return lt.value, hh.value, V.reshape(N, N, N), bool(acc.value), err.value
+
+
+def dopri_tableau():
+    c = np.zeros(7)
+    a = np.zeros((7, 6))
+    e = np.zeros(7)
+    lib().orc_dopri_tableau(_pd(c), _pd(a), _pd(e))
+    return c, a, e
+
+
+def tc_interp(s_prev, m_prev, s_new, m_new, v_max):
+    """The stop rule's crossing point, for tests: ln T_c linear in ln max|V|."""
+    return s_prev + (math.log(v_max) - math.log(m_prev)) * (s_new - s_prev) / (
+        math.log(m_new) - math.log(m_prev))
