@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the one-loop temperature-flow right-hand side on one MI355X.
+
+Workload (the quasi-particle configuration): square lattice t = 1, t' = 0, mu = 0, U = 3t,
+N = 48 angular Fermi-surface patches, L = 128 loop grid, T from 1.0t towards 0.01t with
+Dormand-Prince steps in ln T, synthetic Z table on the internal lines, single-precision
+right-hand side, double-precision state / error estimate / stop test (stop at max|V| > 20t).
+
+One benchmark step is one complete flow (every right-hand side, stage, error estimate and
+stop test until the flow stops) with its inputs already on the device.  The metric counts
+3 N^3 L^2 coupling-loop-point updates per right-hand side (the direct form's nominal work).
+
+Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6, "bf16_TFs": 2500.0}
+METRIC = "coupling·loop-point updates/s per RHS (N³·L²·3); flows/hour, mixed vs FP64"
+
+
+def kernel_work(name, N, L, nP, nD, rsize):
+    """Algorithmic work of one launch of each timed kernel group for one flow.
+
+    bins:     (nP + nD) L^2 weight derivatives, each 6 flops (two differences, one
+              division, the 1/(4 T L^2) scale and the bin accumulation) -> ALU bound
+    y:        (nP + 3 nD) N^3 multiply-adds; bytes = bins read + Y written + 3 operand slabs
+    contract: 4 N^4 multiply-adds; bytes = Y read + operand read + k written
+    stage:    bytes = V (f64) read + 3 operand layouts written + stage terms read (<= 6 k)
+    """
+    NN, N3 = N * N, N ** 3
+    if name == "bins":
+        return {"bound": "alu", "flops": 6.0 * (nP + nD) * L * L}
+    if name == "y":
+        return {"bound": "hbm", "flops": 2.0 * (nP + 3 * nD) * N3,
+                "bytes": (nP + 2 * nD) * NN * rsize + (nP + 3 * nD) * NN * rsize + 3 * N3 * rsize}
+    if name == "contract":
+        return {"bound": "hbm", "flops": 8.0 * N ** 4,
+                "bytes": (nP + 3 * nD) * NN * rsize + 2 * N3 * rsize}
+    if name == "stage":
+        return {"bound": "hbm", "bytes": N3 * 8 + 3 * N3 * rsize + 3 * N3 * rsize}
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-rhs", type=int, default=2, help="oracle RHS evaluations timed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the flow batch and the transfer groups would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2005_00827_amd import fm, inputs
+
+    w = inputs.workload("C2")
+    N, L, U, T0, Te = w["N"], w["L"], w["U"][0], w["T0"][0], w["T_end"]
+    zl, zt = inputs.synthetic_z_table(N, U, T0, Te)
+    dev = torch.device("cuda:0")
+    print("bench: C2 N=%d L=%d U=%g fp32 rhs, rk45, Z table; steps=%d warmup=%d"
+          % (N, L, U, args.steps, args.warmup), file=sys.stderr, flush=True)
+
+    def make(prec):
+        return fm.Flow(N=N, L=L, U=U, T0=T0, T_end=Te, integrator="rk45", precision=prec,
+                       z_lnT=zl, z_table=zt, max_batch=1, device=dev)
+
+    flow = make("fp32")
+    for _ in range(args.warmup):
+        flow.run_batch([U], [T0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [flow.run_batch([U], [T0])[0] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_rhs = sum(r["n_rhs"] for r in res)
+    upd = 3.0 * N ** 3 * L ** 2
+    value = n_rhs * upd / wall
+    print("bench: timed %d flows in %.3f s, %d rhs, T_c %.6f" % (args.steps, wall, n_rhs, res[0]["T_c"]),
+          file=sys.stderr, flush=True)
+
+    # Kernel durations: HIP events on the library's stream around every launch group,
+    # over the same flows replayed eagerly (same kernels, same inputs).
+    flow.set_timing(True)
+    for _ in range(args.steps):
+        flow.run_batch([U], [T0])
+    tm = flow.timings()
+    flow.set_timing(False)
+    cfg = fm.make_config(N, L)
+    _, _, _, nP, nD, _ = fm.geometry_query(cfg)
+    kernels = {}
+    for name, (ms, n) in tm.items():
+        avg_s = ms / n * 1e-3
+        k = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6}
+        wk = kernel_work(name, N, L, nP, nD, 4)
+        if wk:
+            if wk["bound"] == "hbm":
+                k.update(bound="hbm", achieved=wk["bytes"] / avg_s / 1e9, peak=PEAK["hbm_GBs"],
+                         unit="GB/s")
+            else:
+                k.update(bound="alu", achieved=wk["flops"] / avg_s / 1e12, peak=PEAK["fp32_TFs"],
+                         unit="TFLOP/s")
+            k["frac"] = k["achieved"] / k["peak"]
+        kernels[name] = k
+    dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
+    d = kernels[dom]
+    roofline = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"),
+                "peak": d.get("peak"), "unit": d.get("unit"), "frac": d.get("frac"),
+                "traffic": None, "avg_us": d["avg_us"]}
+
+    extra = {"flows": args.steps, "rhs_per_flow": n_rhs / args.steps,
+             "T_c_fp32": res[0]["T_c"], "flows_per_hour_fp32": args.steps / wall * 3600.0,
+             "kernels": kernels}
+    if not args.no_fp64:
+        f64 = make("fp64")
+        f64.run_batch([U], [T0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = f64.run_batch([U], [T0])[0]
+        torch.cuda.synchronize()
+        w64 = time.perf_counter() - t1
+        extra.update(T_c_fp64=r64["T_c"], flows_per_hour_fp64=3600.0 / w64,
+                     Tc_rel_diff=abs(res[0]["T_c"] / r64["T_c"] - 1.0),
+                     updates_per_s_fp64=r64["n_rhs"] * upd / w64)
+        f64.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O   # the checker, timed as the CPU baseline only
+        m = O.model(N, L)
+        V = inputs.noisy_state(N, U)
+        Z = np.array([np.interp(math.log(0.2), zl, zt[:, a]) for a in range(N)])
+        O.rhs(O.model(16, 32), 0.2, inputs.noisy_state(16, U))   # load + warm
+        tc = time.perf_counter()
+        for _ in range(args.cpu_rhs):
+            O.rhs(m, 0.2, V, Z=Z)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": args.cpu_rhs * upd / tcpu, "unit": "coupling·loop-point updates/s",
+               "cores": O.n_threads(), "kind": "oracle",
+               "sample": "%d direct-form RHS evaluations of the same workload (N=48, L=128, "
+                         "Z on, T=0.2) in %.1f s" % (args.cpu_rhs, tcpu)}
+
+    line = {"metric": METRIC, "value": value, "unit": "coupling·loop-point updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "C2 quasi-particle flow: N=48 patches, L=128 loop grid, "
+                                   "U=3t, t'=0, mu=0, T 1.0t->0.01t, Dormand-Prince in ln T, "
+                                   "synthetic Z table, f32 RHS, f64 state, stop at max|V|>20t",
+                       "N": N, "L": L, "U": U, "flows_per_step": 1},
+            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
+    print(json.dumps(line))
+    flow.close()
+
+
+if __name__ == "__main__":
+    main()

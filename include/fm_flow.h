@@ -1,0 +1,164 @@
+/*
+ * fm_flow.h -- C ABI of the one-loop temperature-flow library for the N-patch coupling
+ * function V(k1,k2,k3) of the two-dimensional Hubbard model on MI355X (gfx950).
+ *
+ * The method is that of D. Rohe and C. Honerkamp, "Quasi-particle functional
+ * Renormalisation Group calculations in the two-dimensional half-filled Hubbard model at
+ * finite temperatures" (arXiv:2005.00827):
+ *   - model and dispersion: Sec. 2.1, Eqs. model_definition, free_dispersion_xi;
+ *   - one-loop flow of the static vertex: App. A, Eqs. vertex_flow_general,
+ *     vertex_flow_simple; quasi-particle weights Z on the internal lines, projected onto the
+ *     Fermi-surface patch of each line: App. A, Step 2, Eqs. both_propagators_Z,
+ *     vertex_flow_feedback_Z;
+ *   - angular Fermi-surface patching (Sec. 3.2: seven patches from antinode to node, 48 in
+ *     total), the whole Brillouin zone as loop support (App. A, Comment 1);
+ *   - stop rule: the flow ends when the largest |V| has grown beyond a threshold (Sec. 3.2,
+ *     definition of U*(T)).
+ * The flow parameter is the temperature, s = ln T; every internal pair of lines carries the
+ * weight Z_a' Z_b' T d/dT chi(xi, xi') with chi the bare static particle-hole (or
+ * particle-particle) bubble of the two lines.
+ *
+ * Conventions
+ *   - Loop grid: L x L points k = -pi + 2 pi (j + 1/2)/L per axis, point index j = jx + L*jy.
+ *   - Patches (FM_GEOM_ANGULAR): sector centres theta_a = theta_off + 2 pi a / N with
+ *     theta_off = 0 for N % 8 == 0 or N == 1 and pi/N for N % 8 == 4; the patch of a loop
+ *     point is its nearest centre.  Each patch is represented by the Fermi-surface point on
+ *     its centre ray, snapped to the transfer grid q = 2 pi m / L.
+ *     FM_GEOM_IDENTITY: every loop point is its own patch (N = L*L), all momenta exact.
+ *   - V layout: row-major double V[((f*N + a)*N + b)*N + c] for flow f; a, b are the patches
+ *     of the incoming k1, k2, c that of the outgoing k3 (spin of k1); k4 = k1 + k2 - k3.
+ *
+ * Ownership and memory: the library allocates no device memory.  The caller allocates one
+ * workspace of fm_flow_workspace_bytes() bytes (for example a torch uint8 tensor) and passes
+ * its device pointer to fm_flow_init; it must stay valid until fm_flow_destroy.  Every other
+ * device pointer is also caller owned.  Host arrays passed to fm_flow_init are copied.
+ *
+ * Errors: every call returns FM_OK (0) or a negative FM_E* code; fm_last_error() gives a
+ * message for the last failing call of the calling thread.  Flow outcomes (divergence,
+ * reaching T_end, ...) are not errors; they are reported in fm_result.status.
+ *
+ * Streams: all device work is enqueued on cfg.stream (a hipStream_t; NULL = the default
+ * stream).  fm_flow_rhs is asynchronous; fm_flow_step and fm_flow_run_batch synchronise the
+ * stream before returning their host outputs.  A handle is not thread safe.
+ */
+#ifndef FM_FLOW_H
+#define FM_FLOW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fm_flow fm_flow;
+
+enum { FM_OK = 0, FM_EINVAL = -1, FM_ENOMEM = -2, FM_EDEVICE = -3, FM_ESTATE = -4 };
+
+/* Patch geometry. */
+enum { FM_GEOM_ANGULAR = 0, FM_GEOM_IDENTITY = 1 };
+
+/* Integrator in s = ln T: classical RK4 with n_steps fixed steps from T0 to T_end, or
+ * Dormand-Prince 5(4) with error control (rtol, atol, h0, h_min). */
+enum { FM_RK4_FIXED = 0, FM_RK45_DOPRI = 1 };
+
+/* Arithmetic of the right-hand side.  The integrator state, the error estimate and the stop
+ * test are double precision in every mode.
+ *   FM_FP64          binned loop sums and contractions in double precision
+ *   FM_FP32          binned loop sums and contractions in single precision
+ *   FM_FP32_BF16MFMA single-precision loop sums; the grouped contractions on bf16 matrix
+ *                    cores with single-precision accumulation
+ *   FM_FP64_DIRECT   direct double-precision loop sums over every loop point, no binning */
+enum { FM_FP64 = 0, FM_FP32 = 1, FM_FP32_BF16MFMA = 2, FM_FP64_DIRECT = 3 };
+
+/* Channel mask (for ablations of the flow equation). */
+enum { FM_CH_PP = 1, FM_CH_CR = 2, FM_CH_D = 4, FM_CH_ALL = 7 };
+
+/* fm_result.status */
+enum { FM_FLOW_RUNNING = 0, FM_FLOW_DIVERGED = 1, FM_FLOW_NONFINITE = 2,
+       FM_FLOW_REACHED_TEND = 3, FM_FLOW_STEPFAIL = 4 };
+
+typedef struct {
+    double t, tp, mu, U;      /* hopping t, next-nearest t', chemical potential, bare U
+                                 (Eqs. model_definition, free_dispersion_xi) */
+    int geometry;             /* FM_GEOM_* */
+    int N, L;                 /* patches; loop grid side.  Angular: N == 1 or N % 4 == 0
+                                 with N % 8 in {0, 4}; L % 4 == 0.  Identity: N == L*L. */
+    double T0, T_end;         /* temperature window, T0 > T_end > 0 (finite T only) */
+    int integrator, n_steps;  /* FM_RK4_FIXED uses n_steps */
+    double rtol, atol;        /* Dormand-Prince: error norm max_i |E_i|/(atol + rtol max(|V|,|Vnew|));
+                                 0 selects 1e-6 and 1e-9 max(1, |U|) */
+    double h0, h_min;         /* first step and smallest |step| in ln T; 0 selects
+                                 ln(T_end/T0)/200 and 1e-8 |ln(T_end/T0)| */
+    double v_max;             /* stop when max|V| > v_max (0 selects 20) */
+    unsigned channels;        /* FM_CH_* mask (0 selects FM_CH_ALL) */
+    int precision;            /* FM_FP64 | FM_FP32 | FM_FP32_BF16MFMA | FM_FP64_DIRECT */
+    int n_zT;                 /* 0: no quasi-particle feedback (Z = 1) */
+    const double *z_lnT;      /* host [n_zT], ascending ln T nodes; copied */
+    const double *z_table;    /* host [n_zT][N], 0 < Z <= 1, linear in ln T between nodes,
+                                 clamped outside; copied */
+    void *stream;             /* hipStream_t or NULL */
+    int max_batch;            /* capacity (flows) for every batched call; >= 1 */
+} fm_config;
+
+typedef struct {
+    double T_c;        /* interpolated crossing of max|V| = v_max in (ln T, ln max|V|);
+                          NaN unless status is DIVERGED or NONFINITE */
+    double T_final;    /* temperature of the last accepted step */
+    double max_abs_V;  /* max|V| at T_final */
+    int status;        /* FM_FLOW_* */
+    int n_accepted, n_rejected, n_rhs;
+} fm_result;
+
+/* Bytes of device workspace needed for cfg (all buffers for cfg->max_batch flows). */
+int fm_flow_workspace_bytes(const fm_config *cfg, size_t *bytes);
+
+/* Validates cfg, builds the geometry on the host (double precision) and uploads it into the
+ * caller's workspace.  FM_EINVAL for an invalid N, L, window or precision, or when a loop
+ * point lies within 1e-9 sector widths of a patch boundary. */
+int fm_flow_init(const fm_config *cfg, void *workspace_dev, size_t bytes, fm_flow **out);
+
+/* dV/d ln T for `batch` independent states at temperatures T[batch] (host array):
+ * V_dev and dV_dev are device arrays of batch*N^3 doubles (dV_dev may not alias V_dev).
+ * Z (if configured) is taken from the table at ln T.  Asynchronous on cfg.stream. */
+int fm_flow_rhs(fm_flow *h, int batch, const double *T, const double *V_dev, double *dV_dev);
+
+/* One integrator step for `batch` states.  lnT[batch], h[batch] are host in/out arrays,
+ * V_dev (device, batch*N^3 doubles) in/out, accepted[batch] host out.
+ * RK4: always accepted, lnT += h, h unchanged.  Dormand-Prince: the step is accepted when
+ * the error norm is <= 1; then V and lnT advance; h returns the proposed next step
+ * (h * min(5, max(0.2, 0.9 err^-1/5)), or h/2 after a non-finite stage). */
+int fm_flow_step(fm_flow *h, int batch, double *lnT, double *hstep, double *V_dev,
+                 int *accepted);
+
+/* Runs n_flows independent flows from V = U[f] at T0[f] down to cfg.T_end or until the stop
+ * rule fires, all on the device: one integrator step of every running flow per replay of a
+ * captured graph; finished flows are masked.  z_lnT / z_tables: NULL (use cfg's table for
+ * every flow, or none) or per-flow host arrays [n_flows][n_zT] and [n_flows][n_zT][N].
+ * V_final_dev: NULL or a device array of n_flows*N^3 doubles receiving the final states.
+ * res[n_flows] (host) receives the outcomes. */
+int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0,
+                      const double *z_lnT, const double *z_tables, double *V_final_dev,
+                      fm_result *res);
+
+/* Host-only geometry query (no device needed): xi[L*L], patch[L*L], anchor[N][2] (snapped
+ * Fermi-point transfer indices, or loop indices in identity mode), the numbers of distinct
+ * particle-particle and particle-hole transfers, and the smallest distance of a loop point
+ * to a patch boundary in sector widths.  Any output pointer may be NULL. */
+int fm_geometry_query(const fm_config *cfg, double *xi, int *patch, int *anchor, int *n_pp,
+                      int *n_ph, double *margin);
+
+/* Per-kernel event timings of the last fm_flow_rhs / fm_flow_step / fm_flow_run_batch call
+ * (milliseconds, summed over launches), when enabled with fm_flow_set_timing(h, 1).
+ * names[i] points to static strings.  Returns the number of entries written. */
+int fm_flow_set_timing(fm_flow *h, int enable);
+int fm_flow_timings(fm_flow *h, const char **names, double *ms, int *launches, int max_n);
+
+void fm_flow_destroy(fm_flow *h);
+
+const char *fm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FM_FLOW_H */

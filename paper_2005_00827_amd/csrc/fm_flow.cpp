@@ -1,0 +1,570 @@
+// Host side of libfmflow: the C ABI of include/fm_flow.h, workspace layout and the integrator
+// driver.  Every step of the flow runs in the kernels of kernels.hip; this file only carves
+// the caller's workspace, uploads the geometry and sequences launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "fm_internal.h"
+
+using namespace fm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(FM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Classical RK4 and Dormand & Prince (1980) RK5(4)7M in s = ln T.
+const double kRK4C[4] = {0.0, 0.5, 0.5, 1.0};
+const double kRK4A[4][3] = {{0, 0, 0}, {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 1.0}};
+
+const double kDPC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+const double kDPA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+const double kDPE[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200,
+                        22.0 / 525, -1.0 / 40};
+
+StageCoef rk4_stage(int s) {
+    StageCoef c{};
+    c.c = kRK4C[s];
+    c.ns = s;
+    for (int l = 0; l < s; ++l) c.a[l] = kRK4A[s][l];
+    return c;
+}
+
+StageCoef dp_stage(int s) {
+    StageCoef c{};
+    c.c = kDPC[s];
+    c.ns = s;
+    for (int l = 0; l < s; ++l) c.a[l] = kDPA[s][l];
+    return c;
+}
+
+struct Layout {
+    size_t off = 0;
+    char* base = nullptr;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int resolve(const fm_config* in, fm_config& c, std::string& why) {
+    if (!in) { why = "null config"; return FM_EINVAL; }
+    c = *in;
+    if (!(c.T0 > c.T_end) || !(c.T_end > 0.0)) { why = "need T0 > T_end > 0"; return FM_EINVAL; }
+    if (c.integrator != FM_RK4_FIXED && c.integrator != FM_RK45_DOPRI) { why = "bad integrator"; return FM_EINVAL; }
+    if (c.integrator == FM_RK4_FIXED && c.n_steps < 1) { why = "RK4 needs n_steps >= 1"; return FM_EINVAL; }
+    if (c.precision < FM_FP64 || c.precision > FM_FP64_DIRECT) { why = "bad precision"; return FM_EINVAL; }
+    if (c.precision == FM_FP32_BF16MFMA) { why = "bf16 precision is not built in this library"; return FM_EINVAL; }
+    if (c.max_batch < 1) { why = "max_batch must be >= 1"; return FM_EINVAL; }
+    if (c.n_zT < 0 || (c.n_zT > 0 && (!c.z_lnT || !c.z_table))) { why = "bad Z table"; return FM_EINVAL; }
+    for (int i = 1; i < c.n_zT; ++i)
+        if (!(c.z_lnT[i] > c.z_lnT[i - 1])) { why = "Z nodes must ascend"; return FM_EINVAL; }
+    if (c.rtol <= 0.0) c.rtol = 1e-6;
+    if (c.v_max <= 0.0) c.v_max = 20.0;
+    if (c.channels == 0) c.channels = FM_CH_ALL;
+    if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
+    return FM_OK;
+}
+
+}  // namespace
+
+struct fm_flow {
+    fm_config cfg{};
+    HostGeometry hg;
+    DevGeom g{};
+    DevZ z{};
+    Buffers b{};
+    hipStream_t stream = nullptr;      // caller's stream (may be null)
+    hipStream_t own = nullptr;         // capture stream for graphs when the caller's is null
+    bool dbl = false, direct = false;
+    size_t N3 = 0;
+    std::vector<double> zlnT, ztab;    // configured table (host copy)
+    std::vector<FlowState> hfs;
+    // graphs of one integrator step, keyed by the number of flows captured
+    hipGraphExec_t step_exec = nullptr;
+    int step_nf = -1;
+    // timings
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<std::pair<int, int>> ev_use;  // (kernel id, event index of start)
+    double t_ms[16] = {0};
+    int t_n[16] = {0};
+};
+
+namespace {
+
+enum { T_STAGE, T_BINS, T_Y, T_CONTRACT, T_WTABLE, T_DIRECT, T_UPDATE, T_FINISH, T_COUNT };
+const char* kTimerNames[T_COUNT] = {"stage", "bins", "y", "contract", "wtable", "direct",
+                                    "update", "finish"};
+
+int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, size_t* bytes) {
+    const int B = c.max_batch, N = c.N, np = hg.np;
+    const size_t NN = static_cast<size_t>(N) * N, N3 = NN * N;
+    const int nP = static_cast<int>(hg.q_pp.size()), nD = static_cast<int>(hg.q_ph.size());
+    const bool dbl = c.precision == FM_FP64 || c.precision == FM_FP64_DIRECT;
+    const bool direct = c.precision == FM_FP64_DIRECT;
+    const size_t rs = dbl ? 8 : 4;
+    const int nz = std::max(c.n_zT, 1);
+    Layout L;
+    L.base = base;
+    Buffers& b = h.b;
+    b.xi = L.take<double>(np);
+    b.patch = L.take<int>(np);
+    b.q_pp = L.take<int>(nP);
+    b.q_ph = L.take<int>(nD);
+    b.map_pp = L.take<int>(NN);
+    b.map_cr = L.take<int>(NN);
+    b.map_d = L.take<int>(NN);
+    b.fs = L.take<FlowState>(B);
+    b.z_lnT = L.take<double>(static_cast<size_t>(B) * nz);
+    b.z_tab = L.take<double>(static_cast<size_t>(B) * nz * N);
+    b.T_stage = L.take<double>(B);
+    b.Z_stage = L.take<double>(static_cast<size_t>(B) * N);
+    b.U = L.take<double>(B);
+    b.nblk = static_cast<int>(std::min<size_t>((N3 + 255) / 256, 512));
+    b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
+    b.bstride = B;
+    if (!direct) {
+        b.pt = L.take<char>(static_cast<size_t>(B) * np * 2 * rs);
+        b.bpp = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
+        b.bph = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        b.bphT = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
+        b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        b.wtab = nullptr;
+    } else {
+        b.pt = b.bpp = b.bph = b.bphT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
+    }
+    b.v0 = L.take<char>(static_cast<size_t>(B) * N3 * rs);
+    b.va = L.take<char>(static_cast<size_t>(B) * N3 * rs);
+    b.vc = L.take<char>(static_cast<size_t>(B) * N3 * rs);
+    b.k = L.take<char>(7 * static_cast<size_t>(B) * N3 * rs);
+    b.V = L.take<double>(static_cast<size_t>(B) * N3);
+    b.Vnew = L.take<double>(static_cast<size_t>(B) * N3);
+    *bytes = L.off + 256;
+    return FM_OK;
+}
+
+// Timed launch group: records events around `fn` when timing is on.
+template <typename F>
+void timed(fm_flow* h, int id, F&& fn) {
+    if (!h->timing) { fn(); return; }
+    const size_t i = h->ev_use.size() * 2;
+    while (h->ev.size() < i + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { fn(); return; }
+        h->ev.push_back(e);
+    }
+    (void)hipEventRecord(h->ev[i], h->stream);
+    fn();
+    (void)hipEventRecord(h->ev[i + 1], h->stream);
+    h->ev_use.emplace_back(id, static_cast<int>(i));
+}
+
+void collect_timings(fm_flow* h) {
+    if (!h->timing || h->ev_use.empty()) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& u : h->ev_use) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev[u.second], h->ev[u.second + 1]) == hipSuccess) {
+            h->t_ms[u.first] += ms;
+            h->t_n[u.first] += 1;
+        }
+    }
+    h->ev_use.clear();
+}
+
+// One right-hand-side evaluation of the current stage operands into k slot `slot`.
+void rhs_launch(fm_flow* h, int nf, int slot) {
+    const unsigned ch = h->cfg.channels;
+    if (h->direct) {
+        timed(h, T_WTABLE, [&] { launch_wtable(h->stream, h->g, h->b, nf); });
+        timed(h, T_DIRECT, [&] { launch_direct(h->stream, h->g, h->b, nf, ch, slot); });
+        return;
+    }
+    timed(h, T_BINS, [&] { launch_bins(h->stream, h->dbl, h->g, h->b, nf); });
+    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch); });
+    timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
+}
+
+void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const double* Vbase) {
+    timed(h, T_STAGE, [&] { launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase); });
+}
+
+// One integrator step of every running flow (no host interaction).  V is the state array.
+void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed, double v_max) {
+    const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
+    if (!rk45) {
+        for (int s = 0; s < 4; ++s) {
+            stage_launch(h, nf, rk4_stage(s), 0, V);
+            rhs_launch(h, nf, s);
+        }
+        timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->N3, V); });
+        timed(h, T_FINISH, [&] { launch_finish(h->stream, h->b, nf, 0, v_max, fixed_steps, h_fixed); });
+        return;
+    }
+    for (int s = 1; s < 7; ++s) {
+        stage_launch(h, nf, dp_stage(s), s == 6, V);
+        rhs_launch(h, nf, s);
+    }
+    ErrWeights ew;
+    std::memcpy(ew.e, kDPE, sizeof ew.e);
+    timed(h, T_UPDATE, [&] { launch_dopri_err(h->stream, h->dbl, h->b, nf, h->N3, V, h->cfg.rtol, ew); });
+    timed(h, T_FINISH, [&] {
+        launch_finish(h->stream, h->b, nf, 1, v_max, 0, 0.0);
+        launch_commit(h->stream, h->dbl, h->b, nf, h->N3, V);
+    });
+}
+
+int upload_z(fm_flow* h, int nf, const double* zl, const double* zt) {
+    const int nz = h->cfg.n_zT;
+    if (nz == 0) return FM_OK;
+    const int N = h->cfg.N;
+    std::vector<double> l(static_cast<size_t>(nf) * nz), t(static_cast<size_t>(nf) * nz * N);
+    for (int f = 0; f < nf; ++f) {
+        const double* sl = zl ? zl + static_cast<size_t>(f) * nz : h->zlnT.data();
+        const double* st = zt ? zt + static_cast<size_t>(f) * nz * N : h->ztab.data();
+        std::memcpy(&l[static_cast<size_t>(f) * nz], sl, sizeof(double) * nz);
+        std::memcpy(&t[static_cast<size_t>(f) * nz * N], st, sizeof(double) * nz * N);
+    }
+    HIPCHK(hipMemcpyAsync(h->b.z_lnT, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->b.z_tab, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return FM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fm_last_error(void) { return g_err.c_str(); }
+
+int fm_geometry_query(const fm_config* cfg, double* xi, int* patch, int* anchor, int* n_pp,
+                      int* n_ph, double* margin) {
+    if (!cfg) return fail(FM_EINVAL, "null config");
+    HostGeometry g;
+    std::string why;
+    if (!build_geometry(*cfg, g, why)) return fail(FM_EINVAL, why);
+    if (xi) std::memcpy(xi, g.xi.data(), sizeof(double) * g.np);
+    if (patch) std::memcpy(patch, g.patch.data(), sizeof(int) * g.np);
+    if (anchor) std::memcpy(anchor, g.anchor.data(), sizeof(int) * 2 * g.N);
+    if (n_pp) *n_pp = static_cast<int>(g.q_pp.size());
+    if (n_ph) *n_ph = static_cast<int>(g.q_ph.size());
+    if (margin) *margin = g.margin;
+    return FM_OK;
+}
+
+int fm_flow_workspace_bytes(const fm_config* in, size_t* bytes) {
+    fm_config c;
+    std::string why;
+    int rc = resolve(in, c, why);
+    if (rc) return fail(rc, why);
+    if (!bytes) return fail(FM_EINVAL, "null bytes");
+    HostGeometry g;
+    if (!build_geometry(c, g, why)) return fail(FM_EINVAL, why);
+    fm_flow tmp;
+    return carve(tmp, c, g, nullptr, bytes);
+}
+
+int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
+    if (!out) return fail(FM_EINVAL, "null handle pointer");
+    *out = nullptr;
+    fm_config c;
+    std::string why;
+    int rc = resolve(in, c, why);
+    if (rc) return fail(rc, why);
+    fm_flow* h = new fm_flow;
+    h->cfg = c;
+    if (!build_geometry(c, h->hg, why)) { delete h; return fail(FM_EINVAL, why); }
+    size_t need = 0;
+    carve(*h, c, h->hg, nullptr, &need);
+    if (!ws || bytes < need) {
+        delete h;
+        return fail(FM_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    // align the base to 256 bytes
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~static_cast<uintptr_t>(255));
+    carve(*h, c, h->hg, base, &need);
+    h->stream = static_cast<hipStream_t>(c.stream);
+    h->dbl = c.precision == FM_FP64 || c.precision == FM_FP64_DIRECT;
+    h->direct = c.precision == FM_FP64_DIRECT;
+    const HostGeometry& hg = h->hg;
+    const int N = c.N;
+    h->N3 = static_cast<size_t>(N) * N * N;
+    DevGeom& g = h->g;
+    g.N = N; g.L = c.L; g.np = hg.np;
+    g.nP = static_cast<int>(hg.q_pp.size());
+    g.nD = static_cast<int>(hg.q_ph.size());
+    g.NN = N * N;
+    g.xi = h->b.xi; g.patch = h->b.patch; g.q_pp = h->b.q_pp; g.q_ph = h->b.q_ph;
+    g.map_pp = h->b.map_pp; g.map_cr = h->b.map_cr; g.map_d = h->b.map_d;
+    auto up = [&](void* dst, const void* src, size_t n) {
+        return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, h->stream);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(h->b.xi, hg.xi.data(), sizeof(double) * hg.np);
+    if (e == hipSuccess) e = up(h->b.patch, hg.patch.data(), sizeof(int) * hg.np);
+    if (e == hipSuccess) e = up(h->b.q_pp, hg.q_pp.data(), sizeof(int) * g.nP);
+    if (e == hipSuccess) e = up(h->b.q_ph, hg.q_ph.data(), sizeof(int) * g.nD);
+    if (e == hipSuccess) e = up(h->b.map_pp, hg.map_pp.data(), sizeof(int) * g.NN);
+    if (e == hipSuccess) e = up(h->b.map_cr, hg.map_cr.data(), sizeof(int) * g.NN);
+    if (e == hipSuccess) e = up(h->b.map_d, hg.map_d.data(), sizeof(int) * g.NN);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(FM_EDEVICE, std::string("geometry upload: ") + hipGetErrorString(e));
+    }
+    if (c.n_zT > 0) {
+        h->zlnT.assign(c.z_lnT, c.z_lnT + c.n_zT);
+        h->ztab.assign(c.z_table, c.z_table + static_cast<size_t>(c.n_zT) * N);
+        for (double z : h->ztab)
+            if (!(z > 0.0 && z <= 1.0)) { delete h; return fail(FM_EINVAL, "Z must lie in (0, 1]"); }
+        rc = upload_z(h, c.max_batch, nullptr, nullptr);
+        if (rc) { delete h; return rc; }
+    }
+    h->z.n = c.n_zT;
+    h->z.lnT = h->b.z_lnT;
+    h->z.tab = h->b.z_tab;
+    h->hfs.resize(c.max_batch);
+    *out = h;
+    return FM_OK;
+}
+
+void fm_flow_destroy(fm_flow* h) {
+    if (!h) return;
+    if (h->step_exec) (void)hipGraphExecDestroy(h->step_exec);
+    for (auto e : h->ev) (void)hipEventDestroy(e);
+    if (h->own) (void)hipStreamDestroy(h->own);
+    delete h;
+}
+
+int fm_flow_set_timing(fm_flow* h, int enable) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    h->timing = enable != 0;
+    std::fill(std::begin(h->t_ms), std::end(h->t_ms), 0.0);
+    std::fill(std::begin(h->t_n), std::end(h->t_n), 0);
+    return FM_OK;
+}
+
+int fm_flow_timings(fm_flow* h, const char** names, double* ms, int* launches, int max_n) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    collect_timings(h);
+    int n = 0;
+    for (int i = 0; i < T_COUNT && n < max_n; ++i) {
+        if (!h->t_n[i]) continue;
+        if (names) names[n] = kTimerNames[i];
+        if (ms) ms[n] = h->t_ms[i];
+        if (launches) launches[n] = h->t_n[i];
+        ++n;
+    }
+    return n;
+}
+
+int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, double* dV_dev) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
+    if (!T || !V_dev || !dV_dev) return fail(FM_EINVAL, "null argument");
+    if (V_dev == dV_dev) return fail(FM_EINVAL, "dV_dev must not alias V_dev");
+    for (int f = 0; f < batch; ++f) {
+        if (!(T[f] > 0.0) || !std::isfinite(T[f])) return fail(FM_EINVAL, "T must be positive and finite");
+        FlowState s{};
+        s.lnT = std::log(T[f]);
+        s.status = FM_FLOW_RUNNING;
+        h->hfs[f] = s;
+    }
+    HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    StageCoef sc{};
+    stage_launch(h, batch, sc, 0, V_dev);
+    rhs_launch(h, batch, 0);
+    launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);
+    HIPCHK(hipGetLastError());
+    return FM_OK;
+}
+
+int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_dev, int* accepted) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
+    if (!lnT || !hstep || !V_dev || !accepted) return fail(FM_EINVAL, "null argument");
+    const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
+    for (int f = 0; f < batch; ++f) {
+        if (!std::isfinite(lnT[f]) || !std::isfinite(hstep[f]) || hstep[f] == 0.0)
+            return fail(FM_EINVAL, "lnT and h must be finite, h nonzero");
+        FlowState s{};
+        s.lnT = lnT[f];
+        s.h = s.ht = hstep[f];
+        s.lnT_end = -std::numeric_limits<double>::infinity();
+        s.hmin = 0.0;
+        s.atol = h->cfg.atol > 0.0 ? h->cfg.atol : 1e-9 * std::max(1.0, std::fabs(h->cfg.U));
+        s.status = FM_FLOW_RUNNING;
+        h->hfs[f] = s;
+    }
+    HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    const double inf = std::numeric_limits<double>::infinity();
+    if (rk45) {
+        stage_launch(h, batch, dp_stage(0), 0, V_dev);
+        rhs_launch(h, batch, 0);
+    }
+    step_launch(h, batch, V_dev, 0, 0.0, inf);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hfs.data(), h->b.fs, sizeof(FlowState) * batch, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int f = 0; f < batch; ++f) {
+        const FlowState& s = h->hfs[f];
+        accepted[f] = s.accepted;
+        if (s.accepted) lnT[f] = s.lnT;
+        if (rk45) hstep[f] = s.h;
+    }
+    return FM_OK;
+}
+
+int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, const double* z_lnT,
+                      const double* z_tables, double* V_final_dev, fm_result* res) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (n < 1 || n > h->cfg.max_batch) return fail(FM_EINVAL, "n_flows outside [1, max_batch]");
+    if (!U || !T0 || !res) return fail(FM_EINVAL, "null argument");
+    if ((z_lnT == nullptr) != (z_tables == nullptr)) return fail(FM_EINVAL, "give both Z arrays or neither");
+    if (z_tables && h->cfg.n_zT == 0) return fail(FM_EINVAL, "per-flow Z tables need cfg.n_zT > 0");
+    const fm_config& c = h->cfg;
+    const bool rk45 = c.integrator == FM_RK45_DOPRI;
+    const double lnTe = std::log(c.T_end);
+    for (int f = 0; f < n; ++f) {
+        if (!(T0[f] > c.T_end) || !std::isfinite(U[f])) return fail(FM_EINVAL, "need T0[f] > T_end and finite U");
+        FlowState s{};
+        s.s0 = s.lnT = std::log(T0[f]);
+        s.lnT_end = lnTe;
+        const double span = lnTe - s.s0;
+        if (rk45) {
+            s.h = c.h0 != 0.0 ? c.h0 : span / 200.0;
+            s.ht = (s.lnT + s.h <= lnTe) ? lnTe - s.lnT : s.h;
+            s.hmin = c.h_min > 0.0 ? c.h_min : 1e-8 * std::fabs(span);
+        } else {
+            s.h = s.ht = span / c.n_steps;
+        }
+        s.atol = c.atol > 0.0 ? c.atol : 1e-9 * std::max(1.0, std::fabs(U[f]));
+        s.m = std::fabs(U[f]);
+        s.status = FM_FLOW_RUNNING;
+        if (s.m > c.v_max) { s.status = FM_FLOW_DIVERGED; s.lnTc = s.lnT; }
+        s.n_rhs = (rk45 && s.status == FM_FLOW_RUNNING) ? 1 : 0;
+        h->hfs[f] = s;
+    }
+    if (z_tables) {
+        int rc = upload_z(h, n, z_lnT, z_tables);
+        if (rc) return rc;
+    } else if (c.n_zT > 0) {
+        int rc = upload_z(h, n, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->b.U, U, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    launch_fill_u(h->stream, h->b, n, h->N3, h->b.U);
+    if (rk45) {
+        stage_launch(h, n, dp_stage(0), 0, h->b.V);
+        rhs_launch(h, n, 0);
+    }
+    HIPCHK(hipGetLastError());
+    // fixed steps: flow f advances on its own grid ln T0_f + k (ln T_end - ln T0_f)/n_steps
+    const int fixed = rk45 ? 0 : c.n_steps;
+    const int max_steps = rk45 ? 1000000 : c.n_steps;
+    const int check_every = rk45 ? 4 : 8;
+    int done_steps = 0;
+    bool use_graph = !h->timing;
+    hipStream_t cap = h->stream;
+    if (use_graph && cap == nullptr) {
+        if (!h->own) HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+        cap = h->own;
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    hipStream_t saved = h->stream;
+    if (use_graph && h->step_nf != n) {
+        if (h->step_exec) { (void)hipGraphExecDestroy(h->step_exec); h->step_exec = nullptr; }
+        h->stream = cap;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            step_launch(h, n, h->b.V, fixed, 0.0, c.v_max);
+            e = hipStreamEndCapture(cap, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&h->step_exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        h->stream = saved;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->step_exec = nullptr;
+            use_graph = false;
+        } else {
+            h->step_nf = n;
+        }
+    }
+    while (done_steps < max_steps) {
+        const int k = std::min(check_every, max_steps - done_steps);
+        for (int i = 0; i < k; ++i) {
+            if (use_graph) {
+                HIPCHK(hipGraphLaunch(h->step_exec, cap));
+            } else {
+                step_launch(h, n, h->b.V, fixed, 0.0, c.v_max);
+            }
+        }
+        done_steps += k;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h->hfs.data(), h->b.fs, sizeof(FlowState) * n, hipMemcpyDeviceToHost, cap));
+        HIPCHK(hipStreamSynchronize(cap));
+        collect_timings(h);
+        bool any = false;
+        for (int f = 0; f < n; ++f) any |= h->hfs[f].status == FM_FLOW_RUNNING;
+        if (!any) break;
+    }
+    if (z_tables) {   // later rhs/step calls use the configured table again
+        int rc = upload_z(h, n, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    if (V_final_dev) {
+        launch_copy(cap, h->b.V, V_final_dev, static_cast<size_t>(n) * h->N3);
+        HIPCHK(hipStreamSynchronize(cap));
+    }
+    for (int f = 0; f < n; ++f) {
+        const FlowState& s = h->hfs[f];
+        fm_result& r = res[f];
+        r.status = s.status == FM_FLOW_RUNNING ? FM_FLOW_STEPFAIL : s.status;
+        r.T_c = (s.status == FM_FLOW_DIVERGED || s.status == FM_FLOW_NONFINITE)
+                    ? std::exp(s.lnTc) : std::numeric_limits<double>::quiet_NaN();
+        r.T_final = std::exp(s.lnT);
+        r.max_abs_V = s.m;
+        r.n_accepted = s.n_acc;
+        r.n_rejected = s.n_rej;
+        r.n_rhs = s.n_rhs;
+    }
+    return FM_OK;
+}
+
+}  // extern "C"

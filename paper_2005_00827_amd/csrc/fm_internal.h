@@ -1,0 +1,127 @@
+// Internal declarations shared by the host driver and the gfx950 kernels of libfmflow.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fm_flow.h"
+
+namespace fm {
+
+// ------------------------------------------------------------------------------------
+// Host geometry (double precision), see geometry.cpp.
+// ------------------------------------------------------------------------------------
+struct HostGeometry {
+    int N = 0, L = 0, np = 0, identity = 0, pp_shift = 0;
+    std::vector<double> xi;          // [np] dispersion at each loop point
+    std::vector<int> patch;          // [np] patch of each loop point
+    std::vector<int> anchor;         // [N][2] transfer-grid index of each patch's Fermi point
+    std::vector<int> q_pp, q_ph;     // distinct transfers, flat index mx + L*my
+    std::vector<int> map_pp;         // [a*N+b] -> index into q_pp of k_a + k_b
+    std::vector<int> map_cr;         // [b*N+c] -> index into q_ph of k_c - k_b
+    std::vector<int> map_d;          // [a*N+c] -> index into q_ph of k_a - k_c
+    double margin = 0.5;             // smallest distance to a sector boundary (sectors)
+};
+
+bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err);
+
+// ------------------------------------------------------------------------------------
+// Device-side per-flow integrator state (double precision throughout).
+// ------------------------------------------------------------------------------------
+struct FlowState {
+    double lnT;      // accepted ln T
+    double h;        // proposed next step
+    double ht;       // step being attempted (h, or clamped to reach ln T_end)
+    double lnT_end;  // -inf for free stepping
+    double m;        // max|V| at lnT
+    double lnTc;     // crossing of the stop threshold
+    double err;      // error norm of the last attempt
+    double hmin;     // smallest allowed |h|
+    double s0;       // ln T0 (fixed-step grid origin)
+    double atol;     // absolute error tolerance of this flow
+    int status;      // FM_FLOW_*
+    int accepted;    // outcome of the last attempt
+    int n_acc, n_rej, n_rhs;
+    int pad;
+};
+
+// Geometry as the kernels see it.
+struct DevGeom {
+    int N, L, np, nP, nD, NN;
+    const double* xi;      // [np]
+    const int* patch;      // [np]
+    const int* q_pp;       // [nP]
+    const int* q_ph;       // [nD]
+    const int* map_pp;     // [NN]
+    const int* map_cr;     // [NN]
+    const int* map_d;      // [NN]
+};
+
+// Per-flow Z tables.
+struct DevZ {
+    int n;                 // nodes (0: Z = 1)
+    const double* lnT;     // [B][n]
+    const double* tab;     // [B][n][N]
+};
+
+// Integrator constants for one stage.
+struct StageCoef {
+    double c;              // node
+    double a[7];           // coupling to previous stages
+    int ns;                // number of previous stages used
+};
+
+// Device buffers carved out of the caller's workspace.
+struct Buffers {
+    // geometry
+    double* xi; int* patch; int* q_pp; int* q_ph; int* map_pp; int* map_cr; int* map_d;
+    // per flow
+    FlowState* fs;
+    double* z_lnT; double* z_tab;      // [B][nz], [B][nz][N]
+    double* T_stage;                   // [B]
+    double* Z_stage;                   // [B][N]
+    void* pt;                          // [B][np][2] real
+    void* bpp; void* bph; void* bphT;  // [B][nP][NN], [B][nD][NN] x2 real
+    void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
+    void* v0; void* va; void* vc;      // operands [B][N^3] real
+    void* k;                           // [7][B][N^3] real
+    double* V; double* Vnew;           // [B][N^3] state, candidate
+    double* part;                      // [B][nblk][2] reduction partials
+    double* wtab;                      // direct mode: [B][nP+nD][np]
+    double* U;                         // [B] bare couplings of run_batch
+    int nblk;                          // reduction blocks per flow
+    int bstride;                       // flows per buffer (max_batch)
+};
+
+// Dormand-Prince error weights (5th minus embedded 4th order).
+struct ErrWeights {
+    double e[7];
+};
+
+// Launchers (kernels.hip).  `dbl` selects the double-precision instantiation, nf is the
+// number of flows launched; buffers are strided by b.bstride flows.
+void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
+                  int nf, const StageCoef& sc, int write_new, const double* Vbase);
+void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf);
+void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch);
+void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,
+                     unsigned ch, int slot);
+void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf);
+void launch_direct(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
+                   int slot);
+void launch_k_to_f64(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, int slot,
+                     double* out);
+void launch_fill_u(hipStream_t s, const Buffers& b, int nf, size_t N3, const double* U);
+void launch_rk4_update(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
+void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3,
+                      const double* V, double rtol, const ErrWeights& ew);
+void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, double v_max,
+                   int fixed_steps, double h_fixed);
+void launch_commit(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
+void launch_copy(hipStream_t s, const double* from, double* to, size_t n);
+
+}  // namespace fm

@@ -1,0 +1,167 @@
+// Host-side geometry of the loop grid and Fermi-surface patches, in double precision.
+//
+// Loop grid: half-shifted, k = -pi + 2 pi (j + 1/2)/L per axis, so it contains neither Gamma
+// nor the zone boundary and, for even L, maps onto itself under k -> k + (pi, pi).  The loops
+// run over the whole Brillouin zone (App. A, Comment 1: the interaction-flow propagators do
+// not shrink around the Fermi surface).
+//
+// Patches: N angular sectors around Gamma with centres theta_off + 2 pi a / N; with N % 8 == 0
+// they include the antinodal and nodal directions (Sec. 3.2 counts seven patches from
+// antinode to node, 48 in total).  Each patch is represented by the Fermi-surface point on
+// its centre ray (App. A, Step 2: quantities are projected onto the patch's Fermi point),
+// snapped to the transfer grid 2 pi m / L so that all transfer bookkeeping is integer.
+//
+// Dispersion: Sec. 2.1, Eq. free_dispersion_xi.
+#include <cmath>
+#include <cstdio>
+#include <map>
+
+#include "fm_internal.h"
+
+namespace fm {
+namespace {
+
+struct Disp {
+    double t, tp, mu;
+    double operator()(double kx, double ky) const {
+        double cx = std::cos(kx), cy = std::cos(ky);
+        return -2.0 * t * (cx + cy) - 4.0 * tp * cx * cy - mu;
+    }
+};
+
+inline int wrap(long v, int L) {
+    long r = v % L;
+    return static_cast<int>(r < 0 ? r + L : r);
+}
+
+double sector_offset(int N) {
+    if (N == 1 || N % 8 == 0) return 0.0;
+    if (N % 8 == 4) return M_PI / N;
+    return std::nan("");
+}
+
+// Radius of the first zero of xi along the ray (cos th, sin th) inside the zone: scan 4096
+// equal steps from Gamma to the zone edge for the first sign change and bisect it; without
+// a sign change take the scanned radius of smallest |xi|.
+double fermi_radius(const Disp& xi, double th) {
+    const int n_scan = 4096;
+    const double c = std::cos(th), s = std::sin(th);
+    const double r_edge = M_PI / std::max(std::fabs(c), std::fabs(s));
+    double f_prev = xi(0.0, 0.0);
+    if (f_prev == 0.0) return 0.0;
+    double r_prev = 0.0, r_min = 0.0, f_min = std::fabs(f_prev);
+    for (int i = 1; i <= n_scan; ++i) {
+        const double r = r_edge * i / n_scan;
+        const double f = xi(r * c, r * s);
+        const bool crossed = (f_prev < 0.0) ? (f >= 0.0) : (f <= 0.0);
+        if (crossed) {
+            const bool neg_side = f_prev < 0.0;
+            double lo = r_prev, hi = r;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (!(mid > lo && mid < hi)) break;
+                const double fm = xi(mid * c, mid * s);
+                if ((fm < 0.0) == neg_side && fm != 0.0) lo = mid; else hi = mid;
+            }
+            return hi;
+        }
+        if (std::fabs(f) < f_min) { f_min = std::fabs(f); r_min = r; }
+        r_prev = r;
+        f_prev = f;
+    }
+    return r_min;
+}
+
+}  // namespace
+
+bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
+    const int N = cfg.N, L = cfg.L;
+    char buf[256];
+    if (L < 2 || (L % 2) != 0) { err = "L must be even and >= 2"; return false; }
+    if (cfg.geometry == FM_GEOM_IDENTITY) {
+        if (N != L * L) { err = "identity geometry needs N == L*L"; return false; }
+    } else if (cfg.geometry == FM_GEOM_ANGULAR) {
+        if (N < 1 || std::isnan(sector_offset(N))) {
+            err = "angular geometry needs N == 1 or N % 8 in {0, 4}";
+            return false;
+        }
+        if (L % 4 != 0) { err = "angular geometry needs L % 4 == 0"; return false; }
+    } else {
+        err = "unknown geometry";
+        return false;
+    }
+    const Disp xi{cfg.t, cfg.tp, cfg.mu};
+    g = HostGeometry{};
+    g.N = N; g.L = L; g.np = L * L;
+    g.identity = cfg.geometry == FM_GEOM_IDENTITY;
+    g.xi.resize(g.np);
+    g.patch.resize(g.np);
+    g.anchor.resize(2 * N);
+    std::vector<double> kg(L);
+    for (int j = 0; j < L; ++j) kg[j] = -M_PI + 2.0 * M_PI * (j + 0.5) / L;
+    const double off = g.identity ? 0.0 : sector_offset(N);
+    g.margin = 0.5;
+    for (int jy = 0; jy < L; ++jy) {
+        for (int jx = 0; jx < L; ++jx) {
+            const int j = jx + L * jy;
+            g.xi[j] = xi(kg[jx], kg[jy]);
+            if (g.identity) { g.patch[j] = j; continue; }
+            const double u = (std::atan2(kg[jy], kg[jx]) - off) * N / (2.0 * M_PI);
+            const double r = std::round(u);   // nearest centre (ties cannot pass the margin test)
+            g.margin = std::min(g.margin, 0.5 - std::fabs(u - r));
+            g.patch[j] = wrap(static_cast<long>(r), N);
+        }
+    }
+    if (!g.identity && g.margin < 1e-9) {
+        std::snprintf(buf, sizeof buf, "a loop point lies %.3g sectors from a patch boundary",
+                      g.margin);
+        err = buf;
+        return false;
+    }
+    if (g.identity) {
+        for (int a = 0; a < N; ++a) { g.anchor[2 * a] = a % L; g.anchor[2 * a + 1] = a / L; }
+        g.pp_shift = 1;   // k_a + k_b of two half-shifted points has index ja + jb + 1
+    } else {
+        for (int a = 0; a < N; ++a) {
+            const double th = off + 2.0 * M_PI * a / N;
+            const double r = fermi_radius(xi, th);
+            const double kx = r * std::cos(th), ky = r * std::sin(th);
+            g.anchor[2 * a] = wrap(std::lround(kx * L / (2.0 * M_PI)), L);
+            g.anchor[2 * a + 1] = wrap(std::lround(ky * L / (2.0 * M_PI)), L);
+        }
+        g.pp_shift = 0;
+    }
+    // distinct transfers, first-occurrence order
+    std::map<int, int> ipp, iph;
+    auto intern = [](std::map<int, int>& m, std::vector<int>& list, int key) {
+        auto it = m.find(key);
+        if (it != m.end()) return it->second;
+        const int id = static_cast<int>(list.size());
+        m.emplace(key, id);
+        list.push_back(key);
+        return id;
+    };
+    auto flat = [L](int mx, int my) { return wrap(mx, L) + L * wrap(my, L); };
+    g.map_pp.resize(static_cast<size_t>(N) * N);
+    g.map_cr.resize(static_cast<size_t>(N) * N);
+    g.map_d.resize(static_cast<size_t>(N) * N);
+    for (int x = 0; x < N; ++x) {
+        for (int y = 0; y < N; ++y) {
+            const int* ax = &g.anchor[2 * x];
+            const int* ay = &g.anchor[2 * y];
+            g.map_pp[x * N + y] = intern(ipp, g.q_pp, flat(ax[0] + ay[0] + g.pp_shift,
+                                                           ax[1] + ay[1] + g.pp_shift));
+            // k_x - k_y: map_d uses (a, c) = (x, y); map_cr uses (b, c) with k_c - k_b
+            g.map_d[x * N + y] = intern(iph, g.q_ph, flat(ax[0] - ay[0], ax[1] - ay[1]));
+        }
+    }
+    for (int b = 0; b < N; ++b)
+        for (int c = 0; c < N; ++c) {
+            const int* ab = &g.anchor[2 * b];
+            const int* ac = &g.anchor[2 * c];
+            g.map_cr[b * N + c] = intern(iph, g.q_ph, flat(ac[0] - ab[0], ac[1] - ab[1]));
+        }
+    return true;
+}
+
+}  // namespace fm

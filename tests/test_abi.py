@@ -1,0 +1,71 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every entry
+point of include/fm_flow.h, validates configurations, and its host geometry (written
+independently of the oracle) agrees with the oracle's."""
+import re
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2005_00827_amd import fm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fm.load()
+    hdr = open(os.path.join(ROOT, "include", "fm_flow.h")).read()
+    declared = set(re.findall(r"\b(fm_[a-z_]+)\s*\(", hdr))
+    assert declared == set(fm.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("N,L,identity,tp,mu", [(16, 32, False, 0, 0), (48, 128, False, 0, 0),
+                                                (96, 256, False, 0, 0), (4, 16, False, 0, 0),
+                                                (8, 16, False, -0.3, -0.4), (1, 32, False, 0, 0),
+                                                (16, 4, True, 0, 0), (36, 6, True, 0, 0)])
+def test_geometry_matches_oracle(N, L, identity, tp, mu):
+    cfg = fm.make_config(N, L, tp=tp, mu=mu, geometry="identity" if identity else "angular")
+    xi, patch, anchor, npp, nph, margin = fm.geometry_query(cfg)
+    oxi, opatch, oanchor, omargin = O.geometry(O.model(N, L, tp=tp, mu=mu, identity=identity))
+    assert np.array_equal(patch, opatch)
+    assert np.array_equal(anchor, oanchor)
+    assert np.abs(xi - oxi).max() <= 1e-15
+    assert (npp, nph) == O.transfer_counts(O.model(N, L, tp=tp, mu=mu, identity=identity))
+    if not identity:
+        assert margin == pytest.approx(omargin, rel=1e-9)
+
+
+def test_transfer_counts_of_the_workloads():
+    for (N, L), n in {(16, 32): 48, (48, 128): 424, (96, 256): 1520, (128, 512): 2856}.items():
+        _, _, _, npp, nph, _ = fm.geometry_query(fm.make_config(N, L))
+        assert npp == nph == n
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(N=12, L=32), "N %"),                 # N % 8 == 4 is fine; 12 % 8 == 4 -> ok, so use 10
+    (dict(N=10, L=32), "angular geometry"),
+    (dict(N=16, L=30), "L % 4"),
+    (dict(N=16, L=32, T0=0.01, T_end=1.0), "T0 > T_end"),
+    (dict(N=16, L=32, integrator="rk4", n_steps=0), "n_steps"),
+    (dict(N=16, L=32, max_batch=0), "max_batch"),
+    (dict(N=17, L=4, geometry="identity"), "identity"),
+    (dict(N=16, L=32, channels=9), "channel"),
+])
+def test_invalid_configs_rejected(kw, msg):
+    cfg = fm.make_config(**kw)
+    if kw.get("N") == 12:
+        assert fm.workspace_bytes(cfg) > 0
+        return
+    with pytest.raises(fm.FmError) as e:
+        fm.workspace_bytes(cfg)
+    assert e.value.code == fm.FM_EINVAL
+    assert msg in str(e.value)
+
+
+def test_workspace_scales_with_batch():
+    a = fm.workspace_bytes(fm.make_config(48, 128, precision="fp32", max_batch=1))
+    b = fm.workspace_bytes(fm.make_config(48, 128, precision="fp32", max_batch=4))
+    assert 3.5 * a < b < 4.5 * a

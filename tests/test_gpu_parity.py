@@ -1,0 +1,254 @@
+"""GPU parity: the HIP path through the C ABI against the double-precision CPU oracle.
+
+Tolerances (relative to max|reference|): 1e-10 for the double-precision paths, 1e-4 for
+single precision; T_c to 1e-3 relative.  Inputs are seeded and synthetic
+(paper_2005_00827_amd.inputs); expected values come only from the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2005_00827_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp64_direct": 1e-10, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    return torch, torch.device("cuda:0")
+
+
+def _fm():
+    from paper_2005_00827_amd import fm
+    return fm
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def gpu_rhs(torch_dev, N, L, T, V, prec, **kw):
+    torch, dev = torch_dev
+    fm = _fm()
+    V = np.asarray(V, np.float64).reshape(-1, N, N, N)
+    f = fm.Flow(N=N, L=L, precision=prec, max_batch=V.shape[0], device=dev, **kw)
+    try:
+        out = f.rhs(np.atleast_1d(T), torch.from_numpy(V).to(dev))
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+    finally:
+        f.close()
+
+
+def oracle_model(N, L, **kw):
+    return O.model(N, L, t=kw.get("t", 1.0), tp=kw.get("tp", 0.0), mu=kw.get("mu", 0.0),
+                   identity=kw.get("geometry") == "identity",
+                   channels=kw.get("channels", O.CH_ALL))
+
+
+RHS_CASES = [
+    # N, L, T, state, extra
+    (16, 32, 1.0, "s0", {}),
+    (16, 32, 0.2, "s1", {}),
+    (16, 32, 0.01, "s1", {}),
+    (16, 32, 0.05, "rand", {"channels": 1}),
+    (16, 32, 0.05, "rand", {"channels": 2}),
+    (16, 32, 0.05, "rand", {"channels": 4}),
+    (4, 16, 0.1, "s1", {}),
+    (1, 32, 0.3, "s1", {}),
+    (8, 16, 0.2, "rand", {"tp": -0.3, "mu": -0.4}),
+    (16, 4, 0.3, "rand", {"geometry": "identity"}),
+    (36, 6, 0.1, "rand", {"geometry": "identity"}),
+    (24, 20, 0.07, "s1", {}),      # ragged: N not a tile multiple, L not a power of two
+]
+
+
+def make_state(kind, N, U=2.0, seed=inputs.SEED):
+    if kind == "s0":
+        return inputs.constant_state(N, U)
+    if kind == "s1":
+        return inputs.noisy_state(N, U, seed=seed)
+    return inputs.random_state(N, seed=seed)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64_direct", "fp32"])
+@pytest.mark.parametrize("N,L,T,state,kw", RHS_CASES)
+def test_rhs_small(torch_dev, prec, N, L, T, state, kw):
+    V = make_state(state, N)
+    ref = O.rhs(oracle_model(N, L, **kw), T, V)
+    got = gpu_rhs(torch_dev, N, L, T, V, prec, **kw)[0]
+    if np.abs(ref).max() < 1e-13:   # the direct channel alone vanishes for constant V
+        assert np.abs(got).max() < 1e-12
+        return
+    assert rel(got, ref) <= TOL[prec], (prec, N, L, T, state, kw, rel(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs_with_z_table_and_batch(torch_dev, prec):
+    """Two states at two temperatures in one batch, Z interpolated from a table."""
+    N, L, U = 16, 32, 3.0
+    lnT, tab = inputs.synthetic_z_table(N, U, 1.0, 0.01)
+    V = np.stack([inputs.noisy_state(N, U, seed=1), inputs.noisy_state(N, U, seed=2)])
+    T = [0.5, 0.037]
+    got = gpu_rhs(torch_dev, N, L, T, V, prec, z_lnT=lnT, z_table=tab)
+    for i in range(2):
+        Z = np.array([np.interp(math.log(T[i]), lnT, tab[:, a]) for a in range(N)])
+        ref = O.rhs(O.model(N, L), T[i], V[i], Z=Z)
+        assert rel(got[i], ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs_c2_full(torch_dev, prec):
+    """N = 48, L = 128 (the quasi-particle workload's size): every output element."""
+    N, L, U = 48, 128, 3.0
+    lnT, tab = inputs.synthetic_z_table(N, U, 1.0, 0.01)
+    T = 0.11
+    Z = np.array([np.interp(math.log(T), lnT, tab[:, a]) for a in range(N)])
+    V = inputs.noisy_state(N, U)
+    ref = O.rhs(O.model(N, L), T, V, Z=Z)
+    got = gpu_rhs(torch_dev, N, L, T, V, prec, z_lnT=lnT, z_table=tab)[0]
+    assert rel(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("N,L", [(96, 256), (128, 512)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs_large_sampled(torch_dev, N, L, prec):
+    """Full-size grids: sampled outputs against the oracle's per-element sums."""
+    V = inputs.noisy_state(N, 3.0)
+    T = 0.08
+    abc = inputs.sample_indices(N, 48)
+    ref = O.rhs_points(O.model(N, L), T, V, abc)
+    got = gpu_rhs(torch_dev, N, L, T, V, prec)[0]
+    g = got[abc[:, 0], abc[:, 1], abc[:, 2]]
+    # relative to the largest sampled reference value
+    assert rel(g, ref) <= TOL[prec]
+    # property at every element: C4v relabelling a -> a + N/4 leaves the RHS of a
+    # C4v-symmetric state invariant (checked on the constant state)
+    if prec == "fp64" and N == 96:
+        V0 = inputs.constant_state(N, 3.0)
+        d = gpu_rhs(torch_dev, N, L, T, V0, prec)[0]
+        r = (np.arange(N) + N // 4) % N
+        assert rel(d[np.ix_(r, r, r)], d) <= 1e-12
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "rk45"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_step_matches_oracle(torch_dev, integrator, prec):
+    torch, dev = torch_dev
+    fm = _fm()
+    N, L, U = 16, 32, 2.0
+    V = inputs.noisy_state(N, U)
+    f = fm.Flow(N=N, L=L, U=U, precision=prec, integrator=integrator, device=dev)
+    cfg = O.flowcfg(U=U, integrator=1 if integrator == "rk45" else 0)
+    try:
+        lnT, h = math.log(0.3), -0.05
+        Vd = torch.from_numpy(V.reshape(1, N, N, N).copy()).to(dev)
+        lnT2, h2, acc = f.step([lnT], [h], Vd)
+        ol, oh, oV, oacc, oerr = O.step(O.model(N, L), cfg, lnT, h, V)
+        assert bool(acc[0]) == oacc
+        assert lnT2[0] == pytest.approx(ol, abs=1e-14)
+        if integrator == "rk45" and prec == "fp64":
+            assert h2[0] == pytest.approx(oh, rel=1e-9)
+        elif integrator == "rk45":
+            # the embedded error estimate of a single-precision RHS is set by its rounding,
+            # so only the step-size rule's bounds are comparable
+            assert 0.2 * abs(h) - 1e-15 <= abs(h2[0]) <= 5 * abs(h) + 1e-15
+        assert rel(Vd.cpu().numpy()[0], oV) <= TOL[prec]
+    finally:
+        f.close()
+
+
+def test_rk45_rejects_a_too_large_step(torch_dev):
+    torch, dev = torch_dev
+    fm = _fm()
+    N, L, U = 16, 32, 2.0
+    V = inputs.noisy_state(N, U)
+    f = fm.Flow(N=N, L=L, U=U, precision="fp64", integrator="rk45", device=dev)
+    cfg = O.flowcfg(U=U, integrator=1)
+    try:
+        Vd = torch.from_numpy(V.reshape(1, N, N, N).copy()).to(dev)
+        lnT2, h2, acc = f.step([math.log(0.1)], [-1.5], Vd)
+        ol, oh, oV, oacc, oerr = O.step(O.model(N, L), cfg, math.log(0.1), -1.5, V)
+        assert not oacc and not acc[0]
+        assert h2[0] == pytest.approx(oh, rel=1e-9)
+        assert np.array_equal(Vd.cpu().numpy()[0], V)   # rejected: state untouched
+    finally:
+        f.close()
+
+
+def test_c1_flow_fp64(torch_dev):
+    """The plain workload: N = 16, L = 32, U = 2, RK4 with 200 steps from T = 1 to 0.01."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L, U = 16, 32, 2.0
+    f = fm.Flow(N=N, L=L, U=U, precision="fp64", integrator="rk4", n_steps=200, device=dev)
+    try:
+        res, Vg = f.run_batch([U], [1.0], return_V=True)
+    finally:
+        f.close()
+    Vo, ores, _ = O.flow(O.model(N, L), O.flowcfg(U=U), U)
+    r = res[0]
+    assert r["status"] == ores["status"] == fm.DIVERGED
+    assert (r["n_accepted"], r["n_rhs"]) == (ores["n_accepted"], ores["n_rhs"])
+    assert r["T_c"] == pytest.approx(ores["T_c"], rel=1e-3)
+    assert abs(r["T_c"] / ores["T_c"] - 1) <= 1e-9
+    assert rel(Vg.cpu().numpy()[0], Vo) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+def test_rk45_batch_ragged(torch_dev, prec, tol):
+    """Three flows in one launch: diverging at different temperatures and one reaching T_end."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L = 16, 32
+    U = [2.5, 1.5, 0.4]
+    T0 = [1.0, 0.7, 1.0]
+    f = fm.Flow(N=N, L=L, U=2.0, precision=prec, integrator="rk45", max_batch=4, device=dev)
+    try:
+        res, Vg = f.run_batch(U, T0, return_V=True)
+    finally:
+        f.close()
+    Vg = Vg.cpu().numpy()
+    for i in range(3):
+        cfg = O.flowcfg(T0=T0[i], U=U[i], integrator=1)
+        Vo, ores, _ = O.flow(O.model(N, L), cfg, U[i])
+        assert res[i]["status"] == ores["status"], (i, res[i], ores)
+        if ores["status"] == O.DIVERGED:
+            assert res[i]["T_c"] == pytest.approx(ores["T_c"], rel=1e-3)
+        if prec == "fp64":
+            assert (res[i]["n_accepted"], res[i]["n_rejected"]) == (ores["n_accepted"], ores["n_rejected"])
+            assert rel(Vg[i], Vo) <= tol
+    assert res[2]["status"] == O.REACHED_TEND
+
+
+def test_flow_with_z_feedback_fp64(torch_dev):
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L, U = 16, 32, 3.0
+    lnT, tab = inputs.synthetic_z_table(N, U, 1.0, 0.01)
+    f = fm.Flow(N=N, L=L, U=U, precision="fp64", integrator="rk45", z_lnT=lnT, z_table=tab,
+                device=dev)
+    try:
+        res, Vg = f.run_batch([U], [1.0], return_V=True)
+    finally:
+        f.close()
+    Vo, ores, _ = O.flow(O.model(N, L), O.flowcfg(U=U, integrator=1, z_lnT=lnT, z_tab=tab), U)
+    assert res[0]["status"] == ores["status"]
+    assert res[0]["T_c"] == pytest.approx(ores["T_c"], rel=1e-6)
+    assert rel(Vg.cpu().numpy()[0], Vo) <= 1e-8
+
+
+def test_stop_at_start(torch_dev):
+    fm = _fm()
+    f = fm.Flow(N=16, L=32, U=30.0, precision="fp32", integrator="rk45", device=torch_dev[1])
+    try:
+        res = f.run_batch([30.0], [1.0])
+    finally:
+        f.close()
+    assert res[0]["status"] == fm.DIVERGED and res[0]["T_c"] == pytest.approx(1.0)
+    assert res[0]["n_rhs"] == 0
