@@ -143,6 +143,22 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.map_pp = L.take<int>(NN);
     b.map_cr = L.take<int>(NN);
     b.map_d = L.take<int>(NN);
+    const int nRp = static_cast<int>(hg.rep_pp.size()), nRd = static_cast<int>(hg.rep_ph.size());
+    b.rep_pp = L.take<int>(nRp);
+    b.rep_ph = L.take<int>(nRd);
+    b.qrep_pp = L.take<int>(nP);
+    b.qg_pp = L.take<int>(nP);
+    b.qrep_ph = L.take<int>(nD);
+    b.qg_ph = L.take<int>(nD);
+    b.pinv = L.take<int>(8 * static_cast<size_t>(N));
+    b.pp_off = L.take<int>(nP + 1);
+    b.pp_pairs = L.take<int>(NN);
+    b.cr_off = L.take<int>(nD + 1);
+    b.cr_pairs = L.take<int>(NN);
+    b.d_off = L.take<int>(nD + 1);
+    b.d_pairs = L.take<int>(NN);
+    b.item_q = L.take<int>(hg.item_q.size());
+    b.item_p0 = L.take<int>(hg.item_p0.size());
     b.fs = L.take<FlowState>(B);
     b.z_lnT = L.take<double>(static_cast<size_t>(B) * nz);
     b.z_tab = L.take<double>(static_cast<size_t>(B) * nz * N);
@@ -153,23 +169,22 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
     b.bstride = B;
     if (!direct) {
-        b.pt = L.take<char>(static_cast<size_t>(B) * np * 2 * rs);
-        b.bpp = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
-        b.bph = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
-        b.bphT = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        b.pt = L.take<char>(static_cast<size_t>(B) * np * 4 * rs);
+        b.bins = L.take<char>(static_cast<size_t>(B) * (nRp + nRd) * NN * rs);
         b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
         b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.wtab = nullptr;
     } else {
-        b.pt = b.bpp = b.bph = b.bphT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.pt = b.bins = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
     }
     b.v0 = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.va = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.vc = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.k = L.take<char>(7 * static_cast<size_t>(B) * N3 * rs);
+    b.kpart = direct ? nullptr : L.take<char>(3 * static_cast<size_t>(B) * N3 * rs);
     b.V = L.take<double>(static_cast<size_t>(B) * N3);
     b.Vnew = L.take<double>(static_cast<size_t>(B) * N3);
     *bytes = L.off + 256;
@@ -218,8 +233,11 @@ void rhs_launch(fm_flow* h, int nf, int slot) {
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
 
-void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const double* Vbase) {
-    timed(h, T_STAGE, [&] { launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase); });
+void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const double* Vbase,
+                  int kslot) {
+    timed(h, T_STAGE, [&] {
+        launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase, kslot);
+    });
 }
 
 // One integrator step of every running flow (no host interaction).  V is the state array.
@@ -227,7 +245,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed,
     const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
     if (!rk45) {
         for (int s = 0; s < 4; ++s) {
-            stage_launch(h, nf, rk4_stage(s), 0, V);
+            stage_launch(h, nf, rk4_stage(s), 0, V, s);
             rhs_launch(h, nf, s);
         }
         timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->N3, V); });
@@ -235,7 +253,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed,
         return;
     }
     for (int s = 1; s < 7; ++s) {
-        stage_launch(h, nf, dp_stage(s), s == 6, V);
+        stage_launch(h, nf, dp_stage(s), s == 6, V, s);
         rhs_launch(h, nf, s);
     }
     ErrWeights ew;
@@ -329,6 +347,17 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.NN = N * N;
     g.xi = h->b.xi; g.patch = h->b.patch; g.q_pp = h->b.q_pp; g.q_ph = h->b.q_ph;
     g.map_pp = h->b.map_pp; g.map_cr = h->b.map_cr; g.map_d = h->b.map_d;
+    g.nRp = static_cast<int>(hg.rep_pp.size());
+    g.nRd = static_cast<int>(hg.rep_ph.size());
+    g.rep_pp = h->b.rep_pp; g.rep_ph = h->b.rep_ph;
+    g.qrep_pp = h->b.qrep_pp; g.qg_pp = h->b.qg_pp;
+    g.qrep_ph = h->b.qrep_ph; g.qg_ph = h->b.qg_ph;
+    g.pinv = h->b.pinv;
+    g.pp_off = h->b.pp_off; g.pp_pairs = h->b.pp_pairs;
+    g.cr_off = h->b.cr_off; g.cr_pairs = h->b.cr_pairs;
+    g.d_off = h->b.d_off; g.d_pairs = h->b.d_pairs;
+    g.item_q = h->b.item_q; g.item_p0 = h->b.item_p0;
+    for (int k = 0; k < 3; ++k) g.n_items[k] = hg.n_items[k];
     auto up = [&](void* dst, const void* src, size_t n) {
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, h->stream);
     };
@@ -340,6 +369,24 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = up(h->b.map_pp, hg.map_pp.data(), sizeof(int) * g.NN);
     if (e == hipSuccess) e = up(h->b.map_cr, hg.map_cr.data(), sizeof(int) * g.NN);
     if (e == hipSuccess) e = up(h->b.map_d, hg.map_d.data(), sizeof(int) * g.NN);
+    auto upv = [&](int* dst, const std::vector<int>& v) {
+        return v.empty() ? hipSuccess : up(dst, v.data(), sizeof(int) * v.size());
+    };
+    if (e == hipSuccess) e = upv(h->b.rep_pp, hg.rep_pp);
+    if (e == hipSuccess) e = upv(h->b.rep_ph, hg.rep_ph);
+    if (e == hipSuccess) e = upv(h->b.qrep_pp, hg.qrep_pp);
+    if (e == hipSuccess) e = upv(h->b.qg_pp, hg.qg_pp);
+    if (e == hipSuccess) e = upv(h->b.qrep_ph, hg.qrep_ph);
+    if (e == hipSuccess) e = upv(h->b.qg_ph, hg.qg_ph);
+    if (e == hipSuccess) e = upv(h->b.pinv, hg.pinv);
+    if (e == hipSuccess) e = upv(h->b.pp_off, hg.pp_off);
+    if (e == hipSuccess) e = upv(h->b.pp_pairs, hg.pp_pairs);
+    if (e == hipSuccess) e = upv(h->b.cr_off, hg.cr_off);
+    if (e == hipSuccess) e = upv(h->b.cr_pairs, hg.cr_pairs);
+    if (e == hipSuccess) e = upv(h->b.d_off, hg.d_off);
+    if (e == hipSuccess) e = upv(h->b.d_pairs, hg.d_pairs);
+    if (e == hipSuccess) e = upv(h->b.item_q, hg.item_q);
+    if (e == hipSuccess) e = upv(h->b.item_p0, hg.item_p0);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -405,7 +452,7 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
     }
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     StageCoef sc{};
-    stage_launch(h, batch, sc, 0, V_dev);
+    stage_launch(h, batch, sc, 0, V_dev, 0);
     rhs_launch(h, batch, 0);
     launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);
     HIPCHK(hipGetLastError());
@@ -432,7 +479,7 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     const double inf = std::numeric_limits<double>::infinity();
     if (rk45) {
-        stage_launch(h, batch, dp_stage(0), 0, V_dev);
+        stage_launch(h, batch, dp_stage(0), 0, V_dev, 0);
         rhs_launch(h, batch, 0);
     }
     step_launch(h, batch, V_dev, 0, 0.0, inf);
@@ -489,7 +536,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     HIPCHK(hipMemcpyAsync(h->b.U, U, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
     launch_fill_u(h->stream, h->b, n, h->N3, h->b.U);
     if (rk45) {
-        stage_launch(h, n, dp_stage(0), 0, h->b.V);
+        stage_launch(h, n, dp_stage(0), 0, h->b.V, 0);
         rhs_launch(h, n, 0);
     }
     HIPCHK(hipGetLastError());

@@ -25,6 +25,21 @@ struct HostGeometry {
     std::vector<int> map_cr;         // [b*N+c] -> index into q_ph of k_c - k_b
     std::vector<int> map_d;          // [a*N+c] -> index into q_ph of k_a - k_c
     double margin = 0.5;             // smallest distance to a sector boundary (sectors)
+
+    // Point-group reduction.  The eight operations o = 4*swap + 2*flip_x + flip_y act on
+    // loop indices, transfer indices and (through perm) patch labels.  Bins of transfer
+    // q = o(r) are those of its representative r with both patch labels mapped by o^-1.
+    bool sym = false;                // the geometry is invariant under all eight
+    std::vector<int> pinv;           // [8][N] patch permutation of o^-1
+    std::vector<int> rep_pp, rep_ph; // representative transfers (flat index)
+    std::vector<int> qrep_pp, qg_pp; // [nP] representative index and operation
+    std::vector<int> qrep_ph, qg_ph; // [nD]
+    // Output pairs grouped by transfer (CSR): pp pairs (a,b), crossed (b,c), direct (a,c),
+    // each packed as x*N + y.
+    std::vector<int> pp_off, pp_pairs, cr_off, cr_pairs, d_off, d_pairs;
+    // Phase-2b work items: (transfer, first pair) with at most 8 pairs each, per channel
+    std::vector<int> item_q, item_p0;
+    int n_items[3] = {0, 0, 0};
 };
 
 bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err);
@@ -52,6 +67,19 @@ struct FlowState {
 // Geometry as the kernels see it.
 struct DevGeom {
     int N, L, np, nP, nD, NN;
+    int nRp, nRd;          // representative transfers (pp, ph)
+    const int* rep_pp;     // [nRp]
+    const int* rep_ph;     // [nRd]
+    const int* qrep_pp;    // [nP]
+    const int* qg_pp;      // [nP]
+    const int* qrep_ph;    // [nD]
+    const int* qg_ph;      // [nD]
+    const int* pinv;       // [8][N]
+    const int* pp_off; const int* pp_pairs;
+    const int* cr_off; const int* cr_pairs;
+    const int* d_off;  const int* d_pairs;
+    const int* item_q; const int* item_p0;
+    int n_items[3];
     const double* xi;      // [np]
     const int* patch;      // [np]
     const int* q_pp;       // [nP]
@@ -84,11 +112,15 @@ struct Buffers {
     double* z_lnT; double* z_tab;      // [B][nz], [B][nz][N]
     double* T_stage;                   // [B]
     double* Z_stage;                   // [B][N]
-    void* pt;                          // [B][np][2] real
-    void* bpp; void* bph; void* bphT;  // [B][nP][NN], [B][nD][NN] x2 real
+    int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
+    int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
+    int* item_q; int* item_p0;
+    void* pt;                          // [B][np] (a, phi(a), patch, 0) real4
+    void* bins;                        // [B][nRp + nRd][NN] real, representative transfers
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
     void* v0; void* va; void* vc;      // operands [B][N^3] real
     void* k;                           // [7][B][N^3] real
+    void* kpart;                       // [B][3][N^3] real: per-channel right-hand sides
     double* V; double* Vnew;           // [B][N^3] state, candidate
     double* part;                      // [B][nblk][2] reduction partials
     double* wtab;                      // direct mode: [B][nP+nD][np]
@@ -105,7 +137,7 @@ struct ErrWeights {
 // Launchers (kernels.hip).  `dbl` selects the double-precision instantiation, nf is the
 // number of flows launched; buffers are strided by b.bstride flows.
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
-                  int nf, const StageCoef& sc, int write_new, const double* Vbase);
+                  int nf, const StageCoef& sc, int write_new, const double* Vbase, int kslot);
 void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf);
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch);
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,

@@ -72,6 +72,106 @@ double fermi_radius(const Disp& xi, double th) {
     return r_min;
 }
 
+// Point-group operation o on a loop index (half-shifted grid: k -> -k is j -> L-1-j).
+inline void op_point(int o, int L, int jx, int jy, int& ox, int& oy) {
+    int x = (o & 4) ? jy : jx, y = (o & 4) ? jx : jy;
+    if (o & 2) x = L - 1 - x;
+    if (o & 1) y = L - 1 - y;
+    ox = x; oy = y;
+}
+
+// The same operation on a transfer index (unshifted grid: q -> -q is m -> -m mod L).
+inline int op_transfer(int o, int L, int m) {
+    const int mx = m % L, my = m / L;
+    int x = (o & 4) ? my : mx, y = (o & 4) ? mx : my;
+    if (o & 2) x = (L - x) % L;
+    if (o & 1) y = (L - y) % L;
+    return x + L * y;
+}
+
+void build_symmetry(HostGeometry& g) {
+    const int N = g.N, L = g.L;
+    std::vector<int> perm(8 * static_cast<size_t>(N), -1);
+    bool ok = true;
+    for (int o = 0; o < 8 && ok; ++o) {
+        for (int jy = 0; jy < L && ok; ++jy)
+            for (int jx = 0; jx < L && ok; ++jx) {
+                int ox, oy;
+                op_point(o, L, jx, jy, ox, oy);
+                const int j = jx + L * jy, oj = ox + L * oy;
+                const double d = std::fabs(g.xi[oj] - g.xi[j]);
+                if (d > 1e-12 * std::max(1.0, std::fabs(g.xi[j]))) { ok = false; break; }
+                int& p = perm[o * static_cast<size_t>(N) + g.patch[j]];
+                if (p < 0) p = g.patch[oj];
+                else if (p != g.patch[oj]) ok = false;
+            }
+        for (int a = 0; a < N && ok; ++a)
+            if (perm[o * static_cast<size_t>(N) + a] < 0) ok = false;
+    }
+    g.sym = ok;
+    g.pinv.assign(8 * static_cast<size_t>(N), 0);
+    for (int o = 0; o < 8; ++o)
+        for (int a = 0; a < N; ++a) {
+            if (ok) g.pinv[o * static_cast<size_t>(N) + perm[o * static_cast<size_t>(N) + a]] = a;
+            else g.pinv[o * static_cast<size_t>(N) + a] = a;
+        }
+    auto reduce = [&](const std::vector<int>& q, std::vector<int>& reps, std::vector<int>& qrep,
+                      std::vector<int>& qg) {
+        std::map<int, int> idx;
+        for (size_t i = 0; i < q.size(); ++i) idx.emplace(q[i], static_cast<int>(i));
+        qrep.assign(q.size(), -1);
+        qg.assign(q.size(), 0);
+        reps.clear();
+        for (size_t i = 0; i < q.size(); ++i) {
+            if (qrep[i] >= 0) continue;
+            const int r = static_cast<int>(reps.size());
+            reps.push_back(q[i]);
+            qrep[i] = r;
+            qg[i] = 0;
+            if (!ok) continue;
+            for (int o = 1; o < 8; ++o) {
+                auto it = idx.find(op_transfer(o, L, q[i]));
+                if (it != idx.end() && qrep[it->second] < 0) {
+                    qrep[it->second] = r;
+                    qg[it->second] = o;
+                }
+            }
+        }
+    };
+    reduce(g.q_pp, g.rep_pp, g.qrep_pp, g.qg_pp);
+    reduce(g.q_ph, g.rep_ph, g.qrep_ph, g.qg_ph);
+}
+
+void csr(const std::vector<int>& map, int nq, std::vector<int>& off, std::vector<int>& pairs) {
+    off.assign(nq + 1, 0);
+    for (int v : map) off[v + 1]++;
+    for (int i = 0; i < nq; ++i) off[i + 1] += off[i];
+    pairs.assign(map.size(), 0);
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (size_t xy = 0; xy < map.size(); ++xy) pairs[fill[map[xy]]++] = static_cast<int>(xy);
+}
+
+void build_pairs(HostGeometry& g) {
+    csr(g.map_pp, static_cast<int>(g.q_pp.size()), g.pp_off, g.pp_pairs);
+    csr(g.map_cr, static_cast<int>(g.q_ph.size()), g.cr_off, g.cr_pairs);
+    csr(g.map_d, static_cast<int>(g.q_ph.size()), g.d_off, g.d_pairs);
+    const int chunk = 8;   // pairs per phase-2b work item (the kernel's kChunk)
+    g.item_q.clear();
+    g.item_p0.clear();
+    const std::vector<int>* offs[3] = {&g.pp_off, &g.cr_off, &g.d_off};
+    for (int k = 0; k < 3; ++k) {
+        const std::vector<int>& off = *offs[k];
+        int n = 0;
+        for (size_t q = 0; q + 1 < off.size(); ++q)
+            for (int p = off[q]; p < off[q + 1]; p += chunk) {
+                g.item_q.push_back(static_cast<int>(q));
+                g.item_p0.push_back(p);
+                ++n;
+            }
+        g.n_items[k] = n;
+    }
+}
+
 }  // namespace
 
 bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
@@ -161,6 +261,8 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
             const int* ac = &g.anchor[2 * c];
             g.map_cr[b * N + c] = intern(iph, g.q_ph, flat(ac[0] - ab[0], ac[1] - ab[1]));
         }
+    build_symmetry(g);
+    build_pairs(g);
     return true;
 }
 

@@ -67,15 +67,18 @@ template <typename R> struct WeightCut;
 template <> struct WeightCut<float> { static constexpr float v = 0.1f; };
 template <> struct WeightCut<double> { static constexpr double v = 0.01; };
 
+__device__ inline float quot(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+__device__ inline double quot(double x, double y) { return x / y; }
+
 template <typename R>
 __device__ inline R phi_dd(R a, R pa, R b, R pb) {
     const R d = a - b;
-    if (fabs(d) >= WeightCut<R>::v) return (pa - pb) / d;
+    if (fabs(d) >= WeightCut<R>::v) return quot(pa - pb, d);
     const R m = R(0.5) * (a + b);
     const R e = exp(R(-2) * fabs(m));
-    const R den = R(1) + e;
-    const R s = R(4) * e / (den * den);
-    const R tau = copysign((R(1) - e) / den, m);
+    const R rden = quot(R(1), R(1) + e);
+    const R s = R(4) * e * rden * rden;
+    const R tau = copysign((R(1) - e) * rden, m);
     const R t2 = tau * tau;
     const R mt = m * tau;
     const R d2 = d * d;
@@ -102,14 +105,16 @@ __device__ inline bool running(const FlowState* fs, int f) { return fs[f].status
 
 // ------------------------------------------------------------------------------------
 // Stage argument V_s = V + h sum_l a_l k_l (double), Z and T of the stage, operand layouts
-//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z).
+//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z);
+// also clears the stage's k slot and the representative bins (both accumulated later).
 // ------------------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_stage(DevGeom g, DevZ z, const FlowState* fs,
                                                     StageCoef sc, int write_new,
-                                                    const double* Vbase, const R* K,
+                                                    const double* Vbase, R* K, int kslot,
                                                     double* Vnew, R* v0, R* va, R* vc,
-                                                    double* T_stage, double* Z_stage, int B) {
+                                                    double* T_stage, double* Z_stage,
+                                                    R* bins, size_t nbins, int B) {
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const int N = g.N, NN = g.NN;
@@ -122,8 +127,9 @@ __global__ void __launch_bounds__(kThreads) k_stage(DevGeom g, DevZ z, const Flo
             Z_stage[static_cast<size_t>(f) * N + a] = z_interp(z, f, N, a, lnTs);
     }
     const double* Vf = Vbase + f * N3;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    R* Ks = K + (static_cast<size_t>(kslot) * B + f) * N3;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3; i += stride) {
         double acc = 0.0;
         for (int l = 0; l < sc.ns; ++l) acc += sc.a[l] * static_cast<double>(K[(static_cast<size_t>(l) * B + f) * N3 + i]);
         const double v = Vf[i] + ht * acc;
@@ -135,113 +141,139 @@ __global__ void __launch_bounds__(kThreads) k_stage(DevGeom g, DevZ z, const Flo
         v0[f * N3 + i] = r;
         va[f * N3 + static_cast<size_t>(zz) * NN + x * N + y] = r;
         vc[f * N3 + static_cast<size_t>(zz) * NN + y * N + x] = r;
+        Ks[i] = R(0);
+    }
+    if (bins) {
+        R* bf = bins + f * nbins;
+        for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < nbins; i += stride)
+            bf[i] = R(0);
     }
 }
 
-// Per-point quantities of the stage: a_j = xi_j / 2T and phi(a_j).
+// Per-point quantities of the stage: a_j = xi_j / 2T, phi(a_j) and the patch of j.
+template <typename R> struct Pt4;
+template <> struct Pt4<float> { using T = float4; };
+template <> struct Pt4<double> { using T = double4; };
+
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_points(DevGeom g, const FlowState* fs,
-                                                     const double* T_stage, R* pt) {
+                                                     const double* T_stage,
+                                                     typename Pt4<R>::T* pt) {
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= g.np) return;
     const double a = g.xi[j] / (2.0 * T_stage[f]);
-    R* p = pt + (static_cast<size_t>(f) * g.np + j) * 2;
-    p[0] = static_cast<R>(a);
-    p[1] = static_cast<R>(phi_d(a));
+    typename Pt4<R>::T v;
+    v.x = static_cast<R>(a);
+    v.y = static_cast<R>(phi_d(a));
+    v.z = static_cast<R>(g.patch[j]);
+    v.w = R(0);
+    pt[static_cast<size_t>(f) * g.np + j] = v;
 }
 
 // ------------------------------------------------------------------------------------
-// Phase 1: bins.  One workgroup per (transfer, flow); the N x N bin matrix lives in LDS.
-// blockIdx.x < nP: particle-particle transfer; otherwise particle-hole.
+// Phase 1: bins of the representative transfers.  Block (rep, slice, flow): the slice's
+// rows of the loop grid; each thread walks along one row segment, carries the running sum of
+// consecutive points that fall into the same patch pair and adds it to the LDS bin matrix
+// when the pair changes; the block then adds its LDS bins into the global bins (cleared by
+// the stage kernel) scaled by -1/(4 T L^2).
 // ------------------------------------------------------------------------------------
+template <typename R>
+__device__ inline R weight_dd(R a, R pa, R b, R pb) { return phi_dd<R>(a, pa, b, pb); }
+
+constexpr int kBinThreads = 1024;
+
 template <typename R, bool kLds>
-__global__ void __launch_bounds__(kThreads) k_bins(DevGeom g, const FlowState* fs,
-                                                   const double* T_stage, const R* pt,
-                                                   R* bpp, R* bph, R* bphT) {
+__global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState* fs,
+                                                      const double* T_stage,
+                                                      const typename Pt4<R>::T* pt, R* bins) {
+    using P4 = typename Pt4<R>::T;
+    constexpr int kSeg = 8;     // points loaded ahead per work unit
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
-    const int q = blockIdx.x;
-    const int N = g.N, NN = g.NN, L = g.L, np = g.np;
-    const bool pp = q < g.nP;
-    const int m = pp ? g.q_pp[q] : g.q_ph[q - g.nP];
-    R* out = pp ? bpp + (static_cast<size_t>(f) * g.nP + q) * NN
-                : bph + (static_cast<size_t>(f) * g.nD + (q - g.nP)) * NN;
-    R* bins = kLds ? reinterpret_cast<R*>(smem_raw) : out;
+    const int r = blockIdx.x;
+    const int N = g.N, NN = g.NN, L = g.L;
+    const int nR = g.nRp + g.nRd;
+    const bool pp = r < g.nRp;
+    const int m = pp ? g.rep_pp[r] : g.rep_ph[r - g.nRp];
+    const int mx = m % L, my = m / L;
+    R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
+    const R scale = static_cast<R>(-1.0 / (4.0 * T_stage[f] * g.np));
+    R* lb = kLds ? reinterpret_cast<R*>(smem_raw) : out;
     if (kLds) {
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) bins[i] = R(0);
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) lb[i] = R(0);
         __syncthreads();
     }
-    const R scale = static_cast<R>(-1.0 / (4.0 * T_stage[f] * np));
-    const R* P = pt + static_cast<size_t>(f) * np * 2;
-    for (int j = threadIdx.x; j < np; j += blockDim.x) {
-        const int jp = pp ? partner_pp(m, j, L) : partner_ph(m, j, L);
-        const R a = P[2 * j], pa = P[2 * j + 1];
-        R b = P[2 * jp], pb = P[2 * jp + 1];
-        if (pp) { b = -b; pb = -pb; }   // chi_pp(x, y) = chi_ph(x, -y); phi is odd
-        const R w = scale * phi_dd<R>(a, pa, b, pb);
-        atomicAdd(&bins[g.patch[j] * N + g.patch[jp]], w);
+    const P4* P = pt + static_cast<size_t>(f) * g.np;
+    const int nseg = (L + kSeg - 1) / kSeg;          // work units per row
+    for (int t = threadIdx.x; t < L * nseg; t += blockDim.x) {
+        const int jy = t % L;                          // lanes of a wave sit on different rows
+        const int x0 = (t / L) * kSeg;
+        int py = pp ? my - jy - 1 : jy + my;
+        if (py < 0) py += L;
+        if (py >= L) py -= L;
+        int px = pp ? mx - x0 - 1 : x0 + mx;
+        if (px < 0) px += L;
+        if (px >= L) px -= L;
+        const P4* row = P + static_cast<size_t>(jy) * L;
+        const P4* prow = P + static_cast<size_t>(py) * L;
+        P4 u[kSeg], v[kSeg];
+#pragma unroll
+        for (int i = 0; i < kSeg; ++i) {
+            const int jx = min(x0 + i, L - 1);
+            u[i] = row[jx];
+            v[i] = prow[px];
+            if (pp) { px = px == 0 ? L - 1 : px - 1; }
+            else { px = px == L - 1 ? 0 : px + 1; }
+        }
+        int cur = -1;
+        R acc = R(0);
+#pragma unroll
+        for (int i = 0; i < kSeg; ++i) {
+            if (x0 + i >= L) break;
+            const R b = pp ? -v[i].x : v[i].x;       // chi_pp(x, y) = chi_ph(x, -y), phi odd
+            const R pb = pp ? -v[i].y : v[i].y;
+            const R w = phi_dd<R>(u[i].x, u[i].y, b, pb);
+            const int key = static_cast<int>(u[i].z) * N + static_cast<int>(v[i].z);
+            if (key == cur) {
+                acc += w;
+            } else {
+                if (cur >= 0) atomicAdd(&lb[cur], kLds ? acc : acc * scale);
+                cur = key;
+                acc = w;
+            }
+        }
+        if (cur >= 0) atomicAdd(&lb[cur], kLds ? acc : acc * scale);
     }
     if (!kLds) return;
     __syncthreads();
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) out[i] = bins[i];
-    if (!pp) {
-        R* outT = bphT + (static_cast<size_t>(f) * g.nD + (q - g.nP)) * NN;
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            const int bb = i / N, aa = i - bb * N;   // outT[b'][a'] = bins[a'][b']
-            outT[i] = bins[aa * N + bb];
-        }
-    }
-}
-
-// Transposed copy for the global-atomic fallback of k_bins.
-template <typename R>
-__global__ void __launch_bounds__(kThreads) k_transpose_bins(DevGeom g, const FlowState* fs,
-                                                             const R* bph, R* bphT) {
-    const int f = blockIdx.z;
-    if (!running(fs, f)) return;
-    const int q = blockIdx.y;
-    const int N = g.N, NN = g.NN;
-    const R* in = bph + (static_cast<size_t>(f) * g.nD + q) * NN;
-    R* out = bphT + (static_cast<size_t>(f) * g.nD + q) * NN;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NN; i += gridDim.x * blockDim.x) {
-        const int bb = i / N, aa = i - bb * N;
-        out[i] = in[aa * N + bb];
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(kThreads) k_zero(R* p, size_t n) {
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        p[i] = R(0);
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) out[i] = lb[i] * scale;
 }
 
 // ------------------------------------------------------------------------------------
 // Phase 2a: grouped products.  For group g (one patch index) and kind k:
-//   C[q][n] = sum_kk A[q][kk] Bm[kk][n],  A[q][kk] = Asrc[q][g][kk] Z_g Z_kk,
-//   Bm[kk][n] = Vsrc[g][kk][n],
-// stored as Y[q][g][n] (kind 0) or Y[q][n][g] (kinds 1..3):
-//   kind 0 (pp):     Asrc = Bpp,  Vsrc = v0 -> Y1[q][a'][c]
-//   kind 1 (crossed):Asrc = BphT, Vsrc = vc -> Y2[q][a][b']
-//   kind 2 (direct): Asrc = Bph,  Vsrc = va -> Y3[q][b][a']
-//   kind 3 (direct): Asrc = Bph,  Vsrc = vc -> Y4[q][b][a']
+//   C[q][n] = sum_kk A[q][kk] Bm[kk][n],  Bm[kk][n] = Vsrc[g][kk][n],
+//   A[q][kk] = Z_g Z_kk B_q(row, col) with B_q(x, y) = Brep_r(pinv_o x, pinv_o y), q = o(r),
+// stored as Y[q][g][n]:
+//   kind 0 (pp):      (row, col) = (g, kk), Vsrc = v0 -> Y1[q][a'][c]
+//   kind 1 (crossed): (row, col) = (kk, g), Vsrc = vc -> Y2[q][b'][a]
+//   kind 2 (direct):  (row, col) = (g, kk), Vsrc = va -> Y3[q][a'][b]
+//   kind 3 (direct):  (row, col) = (g, kk), Vsrc = vc -> Y4[q][a'][b]
 // 64 x 64 output tile, K in steps of 16, 4 x 4 per thread.
 // ------------------------------------------------------------------------------------
 template <typename R>
 struct YArgs {
-    const R* A[4];
     const R* Vs[4];
     R* Y[4];
-    int M[4];
     int on[4];
 };
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
-                                                const double* Z_stage, YArgs<R> args, int B) {
+                                                const double* Z_stage, const R* bins,
+                                                YArgs<R> args) {
     constexpr int TM = 64, TN = 64, TK = 16;
     __shared__ R As[TK][TM + 4];
     __shared__ R Bs[TK][TN + 4];
@@ -249,13 +281,17 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     const int f = blockIdx.z / 4;
     if (!running(fs, f) || !args.on[kind]) return;
     const int N = g.N, NN = g.NN;
-    const int M = args.M[kind];
+    const bool ppk = kind == 0;
+    const int M = ppk ? g.nP : g.nD;
     const int ntn = (N + TN - 1) / TN;
     const int tm = blockIdx.x / ntn, tn = blockIdx.x - tm * ntn;
     if (tm * TM >= M) return;
     const int grp = blockIdx.y;
     const size_t N3 = static_cast<size_t>(NN) * N;
-    const R* A = args.A[kind] + static_cast<size_t>(f) * M * NN + static_cast<size_t>(grp) * N;
+    const int nR = g.nRp + g.nRd;
+    const R* Bf = bins + static_cast<size_t>(f) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int* qrep = ppk ? g.qrep_pp : g.qrep_ph;
+    const int* qg = ppk ? g.qg_pp : g.qg_ph;
     const R* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
     const double* Zf = Z_stage + static_cast<size_t>(f) * N;
     const R zg = static_cast<R>(Zf[grp]);
@@ -265,14 +301,35 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) acc[i][jj] = R(0);
+    // A-tile loads: thread t always loads column kk = t % TK of rows t / TK + 16 i, so the
+    // row metadata (representative bins, permutation, permuted group index) is fixed.
+    const int kk_t = threadIdx.x % TK;
+    const R* rowp[4];
+    const int* pir[4];
+    int gxr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = tm * TM + threadIdx.x / TK + 16 * i;
+        if (q < M) {
+            pir[i] = g.pinv + qg[q] * N;
+            gxr[i] = pir[i][grp];
+            rowp[i] = Bf + static_cast<size_t>(qrep[q]) * NN;
+        } else {
+            pir[i] = nullptr; gxr[i] = 0; rowp[i] = nullptr;
+        }
+    }
     for (int k0 = 0; k0 < N; k0 += TK) {
-        // A tile: 64 rows x 16 k
-        for (int e = threadIdx.x; e < TM * TK; e += blockDim.x) {
-            const int r = e / TK, kk = e - r * TK;
-            const int q = tm * TM + r, k = k0 + kk;
+        const int k = k0 + kk_t;
+        const R zk = k < N ? zg * static_cast<R>(Zf[k]) : R(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = threadIdx.x / TK + 16 * i;
             R v = R(0);
-            if (q < M && k < N) v = A[static_cast<size_t>(q) * NN + k] * zg * static_cast<R>(Zf[k]);
-            As[kk][r] = v;
+            if (rowp[i] && k < N) {
+                const int kx = pir[i][k];
+                v = (kind == 1 ? rowp[i][kx * N + gxr[i]] : rowp[i][gxr[i] * N + kx]) * zk;
+            }
+            As[kk_t][rr] = v;
         }
         for (int e = threadIdx.x; e < TK * TN; e += blockDim.x) {
             const int kk = e / TN, c = e - kk * TN;
@@ -302,59 +359,124 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int n = tn * TN + tx * 4 + jj;
-            if (n >= N) continue;
-            const size_t o = kind == 0 ? static_cast<size_t>(q) * NN + grp * N + n
-                                       : static_cast<size_t>(q) * NN + n * N + grp;
-            Y[o] = acc[i][jj];
+            if (n < N) Y[static_cast<size_t>(q) * NN + grp * N + n] = acc[i][jj];
         }
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Phase 2b: one thread per output (a,b,c); all three channels.
+// Phase 2b: per transfer q, a small product over the output pairs that use q.
+//   kind 0 (pp, pairs (a,b)):     k(a,b,n) -= sum_x V(a,b,x)            Y1[q][x][n]
+//   kind 1 (crossed, pairs (b,c)):k(n,b,c) += sum_x V(x,b,c)            Y2[q][x][n]
+//   kind 2 (direct, pairs (a,c)): k(a,n,c) += sum_x (V(x,a,c) - 2V(a,x,c)) Y3[q][x][n]
+//                                                 + V(a,x,c)             Y4[q][x][n]
+// The pairs' vectors are staged in LDS (kChunk at a time); every thread then owns
+// independent (pair, n) outputs, reading Y rows coalesced over n.  Every output element
+// receives exactly one contribution per channel (added atomically: channels run in
+// different blocks).
 // ------------------------------------------------------------------------------------
+constexpr int kChunk = 8;      // output pairs per work item
+constexpr int kXg = 16;        // rows of Y prefetched per group
+
+// One wave per work item (kind, q, first pair, count <= kChunk).  The item's pair vectors
+// are staged in LDS (zero-padded to kChunk), each lane owns one free index n and keeps
+// kChunk accumulators; Y rows are read coalesced over n, kXg rows in flight at a time.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_contract(DevGeom g, const FlowState* fs,
-                                                       const R* v0, const R* y1, const R* y2,
-                                                       const R* y3, const R* y4, R* K,
-                                                       unsigned ch) {
+__global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
+                                                 const R* v0, const R* y1, const R* y2,
+                                                 const R* y3, const R* y4, R* K, unsigned ch) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
+    const int it = blockIdx.x;
+    const int kind = it < g.n_items[0] ? 0 : (it < g.n_items[0] + g.n_items[1] ? 1 : 2);
+    if (kind == 0 && !(ch & FM_CH_PP)) return;
+    if (kind == 1 && !(ch & FM_CH_CR)) return;
+    if (kind == 2 && !(ch & FM_CH_D)) return;
+    const int q = g.item_q[it];
+    const int p0 = g.item_p0[it];
+    const int nq = kind == 0 ? g.nP : g.nD;
+    const int* off = kind == 0 ? g.pp_off : (kind == 1 ? g.cr_off : g.d_off);
+    const int* pairs = kind == 0 ? g.pp_pairs : (kind == 1 ? g.cr_pairs : g.d_pairs);
+    const int cnt = min(kChunk, off[q + 1] - p0);
     const int N = g.N, NN = g.NN;
     const size_t N3 = static_cast<size_t>(NN) * N;
-    const size_t o = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
-    if (o >= N3) return;
-    const int a = static_cast<int>(o / NN);
-    const int b = static_cast<int>((o / N) % N);
-    const int c = static_cast<int>(o % N);
     const R* V = v0 + f * N3;
-    R s = R(0);
-    if (ch & FM_CH_PP) {
-        const R* Y = y1 + (static_cast<size_t>(f) * g.nP + g.map_pp[a * N + b]) * NN;
-        const R* Vab = V + static_cast<size_t>(a) * NN + b * N;
-        R t = R(0);
-        for (int x = 0; x < N; ++x) t += Vab[x] * Y[x * N + c];
-        s -= t;
-    }
-    if (ch & FM_CH_CR) {
-        const R* Y = y2 + (static_cast<size_t>(f) * g.nD + g.map_cr[b * N + c]) * NN + a * N;
-        R t = R(0);
-        for (int x = 0; x < N; ++x) t += Y[x] * V[static_cast<size_t>(x) * NN + b * N + c];
-        s += t;
-    }
-    if (ch & FM_CH_D) {
-        const size_t qo = (static_cast<size_t>(f) * g.nD + g.map_d[a * N + c]) * NN + b * N;
-        const R* Y3 = y3 + qo;
-        const R* Y4 = y4 + qo;
-        R t = R(0);
-        for (int x = 0; x < N; ++x) {
-            const R vaxc = V[static_cast<size_t>(a) * NN + x * N + c];
-            const R vxac = V[static_cast<size_t>(x) * NN + a * N + c];
-            t += (vxac - R(2) * vaxc) * Y3[x] + vaxc * Y4[x];
+    const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
+    const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
+    R* Kf = K + 3 * f * N3 + static_cast<size_t>(kind) * N3;   // [f][channel][N^3]
+    R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
+    R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
+    for (int e = threadIdx.x; e < kChunk * N; e += blockDim.x) {
+        const int i = e / N, x = e - i * N;
+        R a = R(0), b = R(0);
+        if (i < cnt) {
+            const int xy = pairs[p0 + i];
+            const int u = xy / N, w = xy - u * N;
+            if (kind == 0) {
+                a = V[static_cast<size_t>(xy) * N + x];
+            } else if (kind == 1) {
+                a = V[static_cast<size_t>(x) * NN + u * N + w];
+            } else {
+                b = V[static_cast<size_t>(u) * NN + x * N + w];
+                a = V[static_cast<size_t>(x) * NN + u * N + w] - R(2) * b;
+            }
         }
-        s += t;
+        vu[x * kChunk + i] = a;
+        if (kind == 2) vw[x * kChunk + i] = b;
     }
-    K[f * N3 + o] = s;
+    __syncthreads();
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        R acc[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) acc[i] = R(0);
+        for (int xg = 0; xg < N; xg += kXg) {
+            R ya[kXg], yb[kXg];
+#pragma unroll
+            for (int j = 0; j < kXg; ++j) {
+                const int x = min(xg + j, N - 1);
+                ya[j] = Ya[static_cast<size_t>(x) * N + n];
+                if (kind == 2) yb[j] = Yb[static_cast<size_t>(x) * N + n];
+            }
+#pragma unroll
+            for (int j = 0; j < kXg; ++j) {
+                if (xg + j >= N) break;
+                const R* u = vu + (xg + j) * kChunk;
+                const R* w = vw + (xg + j) * kChunk;
+#pragma unroll
+                for (int i = 0; i < kChunk; ++i) {
+                    acc[i] += u[i] * ya[j];
+                    if (kind == 2) acc[i] += w[i] * yb[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+            if (i >= cnt) break;
+            const int xy = pairs[p0 + i];
+            const int a = xy / N, c = xy - a * N;
+            if (kind == 0) Kf[static_cast<size_t>(xy) * N + n] = -acc[i];
+            else if (kind == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = acc[i];
+            else Kf[static_cast<size_t>(a) * NN + n * N + c] = acc[i];
+        }
+    }
+}
+
+// k = k_pp + k_cr + k_d (channels that are masked off contribute zero).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_combine(const FlowState* fs, const R* part, R* K,
+                                                      size_t N3, unsigned ch) {
+    const int f = blockIdx.y;
+    if (!running(fs, f)) return;
+    const R* p = part + 3 * f * N3;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        R v = R(0);
+        if (ch & FM_CH_PP) v += p[i];
+        if (ch & FM_CH_CR) v += p[N3 + i];
+        if (ch & FM_CH_D) v += p[2 * N3 + i];
+        K[f * N3 + i] = v;
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -629,72 +751,71 @@ R* kslot_ptr(const Buffers& b, int slot, size_t N3) {
 
 template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
-             const StageCoef& sc, int write_new, const double* Vbase) {
+             const StageCoef& sc, int write_new, const double* Vbase, int kslot) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
+    // bins are cleared only where phase 1 accumulates them with global atomics
+    const bool zero_bins = b.bins && static_cast<size_t>(g.NN) * sizeof(R) > 65536;
+    const size_t nbins = static_cast<size_t>(g.nRp + g.nRd) * g.NN;
     hipLaunchKernelGGL(k_stage<R>, grid_for(N3, nf), dim3(kThreads), 0, s, g, z, b.fs, sc,
-                       write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+                       write_new, Vbase, static_cast<R*>(b.k), kslot, b.Vnew,
                        static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
-                       b.T_stage, b.Z_stage, b.bstride);
+                       b.T_stage, b.Z_stage, zero_bins ? static_cast<R*>(b.bins) : nullptr,
+                       zero_bins ? nbins : 0, b.bstride);
 }
 
 template <typename R>
 void bins_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {
+    using P4 = typename Pt4<R>::T;
     hipLaunchKernelGGL(k_points<R>, dim3((g.np + kThreads - 1) / kThreads, nf), dim3(kThreads),
-                       0, s, g, b.fs, b.T_stage, static_cast<R*>(b.pt));
+                       0, s, g, b.fs, b.T_stage, static_cast<P4*>(b.pt));
+    const int nR = g.nRp + g.nRd;
+    const dim3 grid(nR, nf);
     const size_t lds = static_cast<size_t>(g.NN) * sizeof(R);
-    const dim3 grid(g.nP + g.nD, nf);
-    if (lds <= 65536) {
-        hipLaunchKernelGGL((k_bins<R, true>), grid, dim3(kThreads), lds, s, g, b.fs, b.T_stage,
-                           static_cast<const R*>(b.pt), static_cast<R*>(b.bpp),
-                           static_cast<R*>(b.bph), static_cast<R*>(b.bphT));
-    } else {
-        const size_t n1 = static_cast<size_t>(nf) * g.nP * g.NN;
-        const size_t n2 = static_cast<size_t>(nf) * g.nD * g.NN;
-        hipLaunchKernelGGL(k_zero<R>, dim3(4096), dim3(kThreads), 0, s, static_cast<R*>(b.bpp), n1);
-        hipLaunchKernelGGL(k_zero<R>, dim3(4096), dim3(kThreads), 0, s, static_cast<R*>(b.bph), n2);
-        hipLaunchKernelGGL((k_bins<R, false>), grid, dim3(kThreads), 0, s, g, b.fs, b.T_stage,
-                           static_cast<const R*>(b.pt), static_cast<R*>(b.bpp),
-                           static_cast<R*>(b.bph), static_cast<R*>(b.bphT));
-        hipLaunchKernelGGL(k_transpose_bins<R>, dim3((g.NN + kThreads - 1) / kThreads, g.nD, nf),
-                           dim3(kThreads), 0, s, g, b.fs, static_cast<const R*>(b.bph),
-                           static_cast<R*>(b.bphT));
-    }
+    if (lds <= 65536)
+        hipLaunchKernelGGL((k_bins<R, true>), grid, dim3(kBinThreads), lds, s, g, b.fs, b.T_stage,
+                           static_cast<const P4*>(b.pt), static_cast<R*>(b.bins));
+    else
+        hipLaunchKernelGGL((k_bins<R, false>), grid, dim3(kBinThreads), 0, s, g, b.fs, b.T_stage,
+                           static_cast<const P4*>(b.pt), static_cast<R*>(b.bins));
 }
 
 template <typename R>
 void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch) {
     YArgs<R> a;
-    a.A[0] = static_cast<const R*>(b.bpp);  a.Vs[0] = static_cast<const R*>(b.v0);
-    a.A[1] = static_cast<const R*>(b.bphT); a.Vs[1] = static_cast<const R*>(b.vc);
-    a.A[2] = static_cast<const R*>(b.bph);  a.Vs[2] = static_cast<const R*>(b.va);
-    a.A[3] = static_cast<const R*>(b.bph);  a.Vs[3] = static_cast<const R*>(b.vc);
+    a.Vs[0] = static_cast<const R*>(b.v0);
+    a.Vs[1] = static_cast<const R*>(b.vc);
+    a.Vs[2] = static_cast<const R*>(b.va);
+    a.Vs[3] = static_cast<const R*>(b.vc);
     a.Y[0] = static_cast<R*>(b.y1); a.Y[1] = static_cast<R*>(b.y2);
     a.Y[2] = static_cast<R*>(b.y3); a.Y[3] = static_cast<R*>(b.y4);
-    a.M[0] = g.nP; a.M[1] = a.M[2] = a.M[3] = g.nD;
     a.on[0] = (ch & FM_CH_PP) != 0;
     a.on[1] = (ch & FM_CH_CR) != 0;
     a.on[2] = a.on[3] = (ch & FM_CH_D) != 0;
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     const int tiles = ((mmax + 63) / 64) * ((g.N + 63) / 64);
     hipLaunchKernelGGL(k_y<R>, dim3(tiles, g.N, 4 * nf), dim3(kThreads), 0, s, g, b.fs,
-                       b.Z_stage, a, nf);
+                       b.Z_stage, static_cast<const R*>(b.bins), a);
 }
 
 template <typename R>
 void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
-    hipLaunchKernelGGL(k_contract<R>, dim3((N3 + kThreads - 1) / kThreads, nf), dim3(kThreads),
-                       0, s, g, b.fs, static_cast<const R*>(b.v0), static_cast<const R*>(b.y1),
+    const size_t lds = 2 * static_cast<size_t>(kChunk) * g.N * sizeof(R);
+    const int items = g.n_items[0] + g.n_items[1] + g.n_items[2];
+    hipLaunchKernelGGL(k_contract<R>, dim3(items, nf), dim3(64), lds, s, g, b.fs,
+                       static_cast<const R*>(b.v0), static_cast<const R*>(b.y1),
                        static_cast<const R*>(b.y2), static_cast<const R*>(b.y3),
-                       static_cast<const R*>(b.y4), kslot_ptr<R>(b, slot, N3), ch);
+                       static_cast<const R*>(b.y4), static_cast<R*>(b.kpart), ch);
+    hipLaunchKernelGGL(k_combine<R>, grid_for(N3, nf), dim3(kThreads), 0, s, b.fs,
+                       static_cast<const R*>(b.kpart), kslot_ptr<R>(b, slot, N3), N3, ch);
 }
 
 }  // namespace
 
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
-                  int nf, const StageCoef& sc, int write_new, const double* Vbase) {
-    if (dbl) stage_t<double>(s, g, z, b, nf, sc, write_new, Vbase);
-    else stage_t<float>(s, g, z, b, nf, sc, write_new, Vbase);
+                  int nf, const StageCoef& sc, int write_new, const double* Vbase, int kslot) {
+    if (dbl) stage_t<double>(s, g, z, b, nf, sc, write_new, Vbase, kslot);
+    else stage_t<float>(s, g, z, b, nf, sc, write_new, Vbase, kslot);
 }
 
 void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf) {
