@@ -82,7 +82,6 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.integrator != FM_RK4_FIXED && c.integrator != FM_RK45_DOPRI) { why = "bad integrator"; return FM_EINVAL; }
     if (c.integrator == FM_RK4_FIXED && c.n_steps < 1) { why = "RK4 needs n_steps >= 1"; return FM_EINVAL; }
     if (c.precision < FM_FP64 || c.precision > FM_FP64_DIRECT) { why = "bad precision"; return FM_EINVAL; }
-    if (c.precision == FM_FP32_BF16MFMA) { why = "bf16 precision is not built in this library"; return FM_EINVAL; }
     if (c.max_batch < 1) { why = "max_batch must be >= 1"; return FM_EINVAL; }
     if (c.n_zT < 0 || (c.n_zT > 0 && (!c.z_lnT || !c.z_table))) { why = "bad Z table"; return FM_EINVAL; }
     for (int i = 1; i < c.n_zT; ++i)
@@ -169,15 +168,16 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
     b.bstride = B;
     if (!direct) {
-        b.pt = L.take<char>(static_cast<size_t>(B) * np * 4 * rs);
+        b.pt = L.take<char>(static_cast<size_t>(B) * np * 16);   // float4 or double2
         b.bins = L.take<char>(static_cast<size_t>(B) * (nRp + nRd) * NN * rs);
+        b.binsT = L.take<char>(static_cast<size_t>(B) * nRd * NN * rs);
         b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
         b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.wtab = nullptr;
     } else {
-        b.pt = b.bins = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.pt = b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
     }
     b.v0 = L.take<char>(static_cast<size_t>(B) * N3 * rs);
@@ -229,7 +229,8 @@ void rhs_launch(fm_flow* h, int nf, int slot) {
         return;
     }
     timed(h, T_BINS, [&] { launch_bins(h->stream, h->dbl, h->g, h->b, nf); });
-    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch); });
+    const int mma = h->cfg.precision == FM_FP32_BF16MFMA ? 2 : (h->cfg.precision == FM_FP32 ? 1 : 0);
+    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch, mma); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
 

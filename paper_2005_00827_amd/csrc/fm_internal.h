@@ -115,8 +115,9 @@ struct Buffers {
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0;
-    void* pt;                          // [B][np] (a, phi(a), patch, 0) real4
+    void* pt;                          // [B][np] per-point stage quantities (16 bytes)
     void* bins;                        // [B][nRp + nRd][NN] real, representative transfers
+    void* binsT;                       // [B][nRd][NN] real, particle-hole bins transposed
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
     void* v0; void* va; void* vc;      // operands [B][N^3] real
     void* k;                           // [7][B][N^3] real
@@ -139,7 +140,9 @@ struct ErrWeights {
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
                   int nf, const StageCoef& sc, int write_new, const double* Vbase, int kslot);
 void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf);
-void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch);
+// mma: 0 VALU, 1 f32 matrix cores, 2 bf16 matrix cores (single precision only, N <= 128)
+void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
+              int mma);
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,
                      unsigned ch, int slot);
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf);

@@ -13,8 +13,9 @@
 // patches (a', b') of T d/dT chi(xi_j, xi_j'), j' = q - j (particle-particle) or j + q
 // (particle-hole).  The bins are an exact regrouping of the loop sum.
 //
-// Phase 1 (k_points, k_bins): bubble-weight derivatives on the fly for every transfer q and
-//   loop point j, summed into per-transfer bin matrices held in LDS.  ALU bound.
+// Phase 1 (k_points, k_bins): bubble-weight derivatives on the fly for every loop point j
+//   and every representative transfer q (one per orbit of the lattice point group), summed
+//   into per-transfer bin matrices held in LDS.
 // Phase 2a (k_y): per-transfer grouped products Y_q = B_q x V-slab, four kinds.
 // Phase 2b (k_contract): the remaining contraction over one patch index per channel, all
 //   three channels fused per output element.
@@ -150,106 +151,132 @@ __global__ void __launch_bounds__(kThreads) k_stage(DevGeom g, DevZ z, const Flo
     }
 }
 
-// Per-point quantities of the stage: a_j = xi_j / 2T, phi(a_j) and the patch of j.
-template <typename R> struct Pt4;
-template <> struct Pt4<float> { using T = float4; };
-template <> struct Pt4<double> { using T = double4; };
+// Per-point quantities of the stage, with a_j = xi_j / 2T:
+//   single precision: (a, phi(a), phi'(a), phi3(a)); double precision: (a, phi(a)),
+// where phi' = s (1 - 2 a tau) and the third derivative
+//   phi3 = s (-6 (1 - 3 tau^2) + 8 a tau (2 - 3 tau^2)),  s = sech^2 a, tau = tanh a
+// (evaluated in double precision).
+template <typename R> struct PtT;
+template <> struct PtT<float> { using T = float4; };
+template <> struct PtT<double> { using T = double2; };
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_points(DevGeom g, const FlowState* fs,
                                                      const double* T_stage,
-                                                     typename Pt4<R>::T* pt) {
+                                                     typename PtT<R>::T* pt) {
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= g.np) return;
     const double a = g.xi[j] / (2.0 * T_stage[f]);
-    typename Pt4<R>::T v;
+    typename PtT<R>::T v;
     v.x = static_cast<R>(a);
     v.y = static_cast<R>(phi_d(a));
-    v.z = static_cast<R>(g.patch[j]);
-    v.w = R(0);
+    if constexpr (sizeof(R) == 4) {
+        const double e = exp(-2.0 * fabs(a));
+        const double rd = 1.0 / (1.0 + e);
+        const double sh = 4.0 * e * rd * rd;
+        const double tau = copysign((1.0 - e) * rd, a);
+        const double t2 = tau * tau, at = a * tau;
+        v.z = static_cast<R>(sh * (1.0 - 2.0 * at));
+        v.w = static_cast<R>(sh * (-6.0 * (1.0 - 3.0 * t2) + 8.0 * at * (2.0 - 3.0 * t2)));
+    }
     pt[static_cast<size_t>(f) * g.np + j] = v;
 }
 
-// ------------------------------------------------------------------------------------
-// Phase 1: bins of the representative transfers.  Block (rep, slice, flow): the slice's
-// rows of the loop grid; each thread walks along one row segment, carries the running sum of
-// consecutive points that fall into the same patch pair and adds it to the LDS bin matrix
-// when the pair changes; the block then adds its LDS bins into the global bins (cleared by
-// the stage kernel) scaled by -1/(4 T L^2).
-// ------------------------------------------------------------------------------------
-template <typename R>
-__device__ inline R weight_dd(R a, R pa, R b, R pb) { return phi_dd<R>(a, pa, b, pb); }
+// Single-precision weight phi[a,b] without branches: away from a == b the quotient;
+// within |a - b| < 0.05 the trapezoid value with its end correction,
+//   phi[a,b] = (phi'(a) + phi'(b))/2 - (a-b)^2 (phi3(a) + phi3(b))/24 + O((a-b)^4).
+__device__ inline float phi_dd_pt(float4 u, float4 v) {
+    const float d = u.x - v.x;
+    const float qt = (u.y - v.y) * __builtin_amdgcn_rcpf(d);
+    const float sr = 0.5f * (u.z + v.z) - (d * d) * (u.w + v.w) * (1.0f / 24.0f);
+    return fabsf(d) >= 0.05f ? qt : sr;
+}
+__device__ inline double phi_dd_pt(double2 u, double2 v) { return phi_dd<double>(u.x, u.y, v.x, v.y); }
+// Particle-particle partner: chi_pp(x, y) = chi_ph(x, -y); a and phi are odd in a, phi'
+// and phi3 even.
+__device__ inline float4 flip(float4 v) { return make_float4(-v.x, -v.y, v.z, v.w); }
+__device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 
+// ------------------------------------------------------------------------------------
+// Phase 1: bins of the representative transfers.  One 1024-thread block per
+// (representative, flow).  A work unit is kSeg consecutive points of one row with their
+// partners; lanes of a wave take different rows.  Each thread loads all points of its unit
+// at once, carries the running sum of consecutive pairs that fall into the same patch
+// pair, and adds it to the LDS bin matrix when the pair changes.  The block finally writes
+// the bins scaled by -1/(4 T L^2).
+//   kMode 0: bins and the loop grid's patch table (u16) in LDS, kSeg = 16 (8 in double)
+//   kMode 1: bins in LDS, patches read from global memory, kSeg = 8
+//   kMode 2: bins accumulated with global atomics (cleared by the stage kernel), kSeg = 8
+// ------------------------------------------------------------------------------------
 constexpr int kBinThreads = 1024;
+constexpr int kBinBatch = 8;   // points per thread with loads in flight together
 
-template <typename R, bool kLds>
+// Grid (representative, flow).  Thread t takes points j = t + kBinThreads i, so a wave covers
+// consecutive points of a row and every load (own point, partner, patches) is coalesced.
+// kMode 0: bins in LDS (added with LDS atomics), stored scaled by -1/(4 T L^2); 1: global
+// atomics into bins cleared by the stage kernel.  The block also writes the transpose for
+// particle-hole representatives (read by the crossed channel).
+template <typename R, int kMode>
 __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState* fs,
                                                       const double* T_stage,
-                                                      const typename Pt4<R>::T* pt, R* bins) {
-    using P4 = typename Pt4<R>::T;
-    constexpr int kSeg = 8;     // points loaded ahead per work unit
+                                                      const typename PtT<R>::T* pt, R* bins,
+                                                      R* binsT) {
+    using PT = typename PtT<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
-    if (!running(fs, f)) return;
+    if (!running(fs, f)) return;                      // uniform over the block
     const int r = blockIdx.x;
-    const int N = g.N, NN = g.NN, L = g.L;
+    const int N = g.N, NN = g.NN, L = g.L, np = g.np;
     const int nR = g.nRp + g.nRd;
     const bool pp = r < g.nRp;
     const int m = pp ? g.rep_pp[r] : g.rep_ph[r - g.nRp];
     const int mx = m % L, my = m / L;
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
-    const R scale = static_cast<R>(-1.0 / (4.0 * T_stage[f] * g.np));
-    R* lb = kLds ? reinterpret_cast<R*>(smem_raw) : out;
-    if (kLds) {
+    const R scale = static_cast<R>(-1.0 / (4.0 * T_stage[f] * np));
+    R* lb = reinterpret_cast<R*>(smem_raw);
+    const PT* P = pt + static_cast<size_t>(f) * np;
+    if (kMode == 0)
         for (int i = threadIdx.x; i < NN; i += blockDim.x) lb[i] = R(0);
-        __syncthreads();
-    }
-    const P4* P = pt + static_cast<size_t>(f) * g.np;
-    const int nseg = (L + kSeg - 1) / kSeg;          // work units per row
-    for (int t = threadIdx.x; t < L * nseg; t += blockDim.x) {
-        const int jy = t % L;                          // lanes of a wave sit on different rows
-        const int x0 = (t / L) * kSeg;
-        int py = pp ? my - jy - 1 : jy + my;
-        if (py < 0) py += L;
-        if (py >= L) py -= L;
-        int px = pp ? mx - x0 - 1 : x0 + mx;
-        if (px < 0) px += L;
-        if (px >= L) px -= L;
-        const P4* row = P + static_cast<size_t>(jy) * L;
-        const P4* prow = P + static_cast<size_t>(py) * L;
-        P4 u[kSeg], v[kSeg];
+    __syncthreads();                                   // every thread of the block
+    R* acc = kMode == 0 ? lb : out;
+    for (int j0 = threadIdx.x; j0 < np; j0 += kBinBatch * kBinThreads) {
+        PT u[kBinBatch], v[kBinBatch];
+        int pa[kBinBatch], pq[kBinBatch];
 #pragma unroll
-        for (int i = 0; i < kSeg; ++i) {
-            const int jx = min(x0 + i, L - 1);
-            u[i] = row[jx];
-            v[i] = prow[px];
-            if (pp) { px = px == 0 ? L - 1 : px - 1; }
-            else { px = px == L - 1 ? 0 : px + 1; }
+        for (int i = 0; i < kBinBatch; ++i) {
+            const int j = min(j0 + i * kBinThreads, np - 1);
+            const int jy = j / L, jx = j - jy * L;
+            int px = pp ? mx - jx - 1 : jx + mx;
+            int py = pp ? my - jy - 1 : jy + my;
+            px += px < 0 ? L : (px >= L ? -L : 0);
+            py += py < 0 ? L : (py >= L ? -L : 0);
+            const int jp = py * L + px;
+            u[i] = P[j];
+            v[i] = P[jp];
+            pa[i] = g.patch[j];
+            pq[i] = g.patch[jp];
         }
-        int cur = -1;
-        R acc = R(0);
+        // every loaded value is used (no early exit), so the loads stay batched
 #pragma unroll
-        for (int i = 0; i < kSeg; ++i) {
-            if (x0 + i >= L) break;
-            const R b = pp ? -v[i].x : v[i].x;       // chi_pp(x, y) = chi_ph(x, -y), phi odd
-            const R pb = pp ? -v[i].y : v[i].y;
-            const R w = phi_dd<R>(u[i].x, u[i].y, b, pb);
-            const int key = static_cast<int>(u[i].z) * N + static_cast<int>(v[i].z);
-            if (key == cur) {
-                acc += w;
-            } else {
-                if (cur >= 0) atomicAdd(&lb[cur], kLds ? acc : acc * scale);
-                cur = key;
-                acc = w;
-            }
+        for (int i = 0; i < kBinBatch; ++i) {
+            const R w = phi_dd_pt(u[i], pp ? flip(v[i]) : v[i]);
+            const R wv = j0 + i * kBinThreads < np ? w : R(0);
+            atomicAdd(&acc[pa[i] * N + pq[i]], kMode == 0 ? wv : wv * scale);
         }
-        if (cur >= 0) atomicAdd(&lb[cur], kLds ? acc : acc * scale);
     }
-    if (!kLds) return;
-    __syncthreads();
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) out[i] = lb[i] * scale;
+    __syncthreads();                                   // every thread of the block
+    R* outT = pp ? nullptr : binsT + (static_cast<size_t>(f) * g.nRd + (r - g.nRp)) * NN;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        const int bb = i / N, aa = i - bb * N;
+        if (kMode == 0) {
+            out[i] = lb[i] * scale;
+            if (outT) outT[i] = lb[aa * N + bb] * scale;
+        } else if (outT) {
+            outT[i] = out[aa * N + bb];
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -273,7 +300,7 @@ struct YArgs {
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
                                                 const double* Z_stage, const R* bins,
-                                                YArgs<R> args) {
+                                                const R* binsT, YArgs<R> args) {
     constexpr int TM = 64, TN = 64, TK = 16;
     __shared__ R As[TK][TM + 4];
     __shared__ R Bs[TK][TN + 4];
@@ -289,13 +316,18 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     const int grp = blockIdx.y;
     const size_t N3 = static_cast<size_t>(NN) * N;
     const int nR = g.nRp + g.nRd;
-    const R* Bf = bins + static_cast<size_t>(f) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
+    // kind 1 reads the transposed particle-hole bins, so every kind reads a contiguous row
+    const R* Bf = kind == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
+                            : bins + static_cast<size_t>(f) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
     const int* qrep = ppk ? g.qrep_pp : g.qrep_ph;
     const int* qg = ppk ? g.qg_pp : g.qg_ph;
     const R* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
     const double* Zf = Z_stage + static_cast<size_t>(f) * N;
     const R zg = static_cast<R>(Zf[grp]);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    __shared__ int pis[8 * 256];
+    for (int i = threadIdx.x; i < 8 * N && i < 8 * 256; i += blockDim.x) pis[i] = g.pinv[i];
+    __syncthreads();
     R acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -311,7 +343,7 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     for (int i = 0; i < 4; ++i) {
         const int q = tm * TM + threadIdx.x / TK + 16 * i;
         if (q < M) {
-            pir[i] = g.pinv + qg[q] * N;
+            pir[i] = (N <= 256 ? pis : g.pinv) + qg[q] * N;
             gxr[i] = pir[i][grp];
             rowp[i] = Bf + static_cast<size_t>(qrep[q]) * NN;
         } else {
@@ -326,8 +358,7 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
             const int rr = threadIdx.x / TK + 16 * i;
             R v = R(0);
             if (rowp[i] && k < N) {
-                const int kx = pir[i][k];
-                v = (kind == 1 ? rowp[i][kx * N + gxr[i]] : rowp[i][gxr[i] * N + kx]) * zk;
+                v = rowp[i][gxr[i] * N + pir[i][k]] * zk;
             }
             As[kk_t][rr] = v;
         }
@@ -364,6 +395,139 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     }
 }
 
+// Phase 2a on matrix cores (single-precision storage, N <= 128).  Same products as k_y;
+// the block computes 64 transfers x N outputs of one group g: four waves of 16 rows, n in
+// 16-wide tiles, k staged through LDS KC at a time (all of k at once for N <= 64), all loads
+// of a stage issued together.  kBF16 = false: v_mfma_f32_16x16x4_f32 (operands f32); true:
+// v_mfma_f32_16x16x32_bf16 (operands rounded to bf16, f32 accumulation).  Fragment layouts
+// (wave64): A row = lane % 16, B column = lane % 16, the k index from lane / 16 (times 8 for
+// bf16, plus the element index); D row = 4 (lane / 16) + r, column = lane % 16.
+typedef float fm_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 fm_bf8 __attribute__((ext_vector_type(8)));
+
+template <bool kBF16, int KC>
+__global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
+                                                     const double* Z_stage, const float* bins,
+                                                     const float* binsT, YArgs<float> args) {
+    constexpr int TQ = 64, KS = KC + 4, NT = 8;
+    __shared__ __align__(16) float As[TQ][KS];      // A[q][k]
+    __shared__ __align__(16) float Bt[16 * NT][KS]; // B^T[n][k]
+    __shared__ int pis[8 * 16 * NT];                 // patch permutations (N <= 128)
+    __shared__ int rrep[TQ], rperm[TQ];              // per row: representative, permutation
+    __shared__ float zs[16 * NT];                    // Z of the stage
+    const int kind = blockIdx.z % 4;
+    const int f = blockIdx.z / 4;
+    if (!running(fs, f) || !args.on[kind]) return;
+    const int N = g.N, NN = g.NN;
+    const bool ppk = kind == 0;
+    const int M = ppk ? g.nP : g.nD;
+    const int tq = blockIdx.x;
+    if (tq * TQ >= M) return;
+    const int grp = blockIdx.y;
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    const int nR = g.nRp + g.nRd;
+    const float* Bf = kind == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
+                                : bins + static_cast<size_t>(f) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int* qrep = ppk ? g.qrep_pp : g.qrep_ph;
+    const int* qg = ppk ? g.qg_pp : g.qg_ph;
+    const float* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
+    const double* Zf = Z_stage + static_cast<size_t>(f) * N;
+    for (int i = threadIdx.x; i < 8 * N; i += blockDim.x) pis[i] = g.pinv[i];
+    for (int i = threadIdx.x; i < TQ; i += blockDim.x) {
+        const int q = tq * TQ + i;
+        rrep[i] = q < M ? qrep[q] : -1;
+        rperm[i] = q < M ? qg[q] : 0;
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) zs[i] = static_cast<float>(Zf[i]);
+    __syncthreads();
+    const float zg = zs[grp];
+    const int ntile = (N + 15) / 16;
+    const int Np = ntile * 16;
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    fm_f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < N; k0 += KC) {
+        // A: element e -> row e / KC, column e % KC (columns consecutive over lanes).  All
+        // loads of the stage go to registers first so they are in flight together.
+        constexpr int kA = TQ * KC / kThreads;
+        constexpr int kB = KC * 16 * NT / kThreads;
+        float av[kA], bv[kB];
+#pragma unroll
+        for (int i = 0; i < kA; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            const int rr = e / KC, kk = e - rr * KC;
+            const int k = k0 + kk;
+            const int rep = rrep[rr];
+            const int kc = min(k, N - 1);
+            const int* pi = pis + rperm[rr] * N;
+            const float x = Bf[static_cast<size_t>(max(rep, 0)) * NN + pi[grp] * N + pi[kc]];
+            av[i] = (rep >= 0 && k < N) ? x * (zg * zs[kc]) : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            const int kk = e / Np, n = e - kk * Np;
+            const int kr = k0 + kk;
+            const float x = Vg[static_cast<size_t>(min(kr, N - 1)) * N + min(n, N - 1)];
+            bv[i] = (kk < KC && kr < N && n < N) ? x : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < kA; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            As[e / KC][e % KC] = av[i];
+        }
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            const int kk = e / Np, n = e - kk * Np;
+            if (kk < KC) Bt[n][kk] = bv[i];
+        }
+        __syncthreads();
+        if (kBF16) {
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 32) {
+                fm_bf8 a;
+                const float* ar = &As[wv * 16 + lane % 16][kk + 8 * (lane / 16)];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[e] = static_cast<__bf16>(ar[e]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (t >= ntile) break;
+                    fm_bf8 b;
+                    const float* br = &Bt[t * 16 + lane % 16][kk + 8 * (lane / 16)];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) b[e] = static_cast<__bf16>(br[e]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 4) {
+                const float a = As[wv * 16 + lane % 16][kk + lane / 16];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (t >= ntile) break;
+                    const float b = Bt[t * 16 + lane % 16][kk + lane / 16];
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float* Y = args.Y[kind] + static_cast<size_t>(f) * M * NN;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (t >= ntile) break;
+        const int n = t * 16 + lane % 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = tq * TQ + wv * 16 + 4 * (lane / 16) + r;
+            if (q < M && n < N) Y[static_cast<size_t>(q) * NN + grp * N + n] = acc[t][r];
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // Phase 2b: per transfer q, a small product over the output pairs that use q.
 //   kind 0 (pp, pairs (a,b)):     k(a,b,n) -= sum_x V(a,b,x)            Y1[q][x][n]
@@ -376,11 +540,98 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
 // different blocks).
 // ------------------------------------------------------------------------------------
 constexpr int kChunk = 8;      // output pairs per work item
-constexpr int kXg = 16;        // rows of Y prefetched per group
 
-// One wave per work item (kind, q, first pair, count <= kChunk).  The item's pair vectors
-// are staged in LDS (zero-padded to kChunk), each lane owns one free index n and keeps
-// kChunk accumulators; Y rows are read coalesced over n, kXg rows in flight at a time.
+template <typename R> struct YGroup;              // rows of Y held in registers per lane
+template <> struct YGroup<float> { static constexpr int v = 48; };
+template <> struct YGroup<double> { static constexpr int v = 24; };
+// the direct channel holds two Y columns, so half as many rows each
+
+// One wave per work item (kind, q, first pair, count <= kChunk).  Each lane owns one free
+// index n: its column of Y (a group of rows at a time) is loaded into registers while the
+// item's pair vectors are gathered into LDS (zero-padded to kChunk, laid out [x][pair] so
+// one x is a 128-bit broadcast read), so every group costs one memory round trip.
+template <typename R, int KIND>
+__device__ __attribute__((always_inline)) inline void contract_item(
+    const DevGeom& g, const R* V, const R* Ya, const R* Yb, const int* pairs, int cnt, R* vu,
+    R* vw, R* Kf) {
+    constexpr int G = KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v;
+    const int N = g.N, NN = g.NN;
+    for (int n0 = 0; n0 < N; n0 += 64) {
+        const int n = min(n0 + static_cast<int>(threadIdx.x), N - 1);
+        R acc[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) acc[i] = R(0);
+        for (int xg = 0; xg < N; xg += G) {
+            R ya[G], yb[KIND == 2 ? G : 1];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int x = min(xg + j, N - 1);
+                ya[j] = Ya[static_cast<size_t>(x) * N + n];
+                if (KIND == 2) yb[j] = Yb[static_cast<size_t>(x) * N + n];
+            }
+            if (n0 == 0 && xg == 0) {
+                // gather the pair vectors while the first Y rows are in flight (at most
+                // kChunk * 128 values, kVec per lane, loaded to registers before any store)
+                constexpr int kVec = kChunk * 128 / 64;
+                R av[kVec], bv[kVec];
+#pragma unroll
+                for (int v = 0; v < kVec; ++v) {
+                    const int e = min(static_cast<int>(threadIdx.x) + 64 * v, kChunk * N - 1);
+                    const int i = e / N, x = e - i * N;
+                    const int xy = pairs[min(i, cnt - 1)];
+                    const int u = xy / N, w = xy - u * N;
+                    const size_t ia = KIND == 0 ? static_cast<size_t>(xy) * N + x
+                                                : static_cast<size_t>(x) * NN + u * N + w;
+                    av[v] = V[ia];
+                    bv[v] = KIND == 2 ? V[static_cast<size_t>(u) * NN + x * N + w] : R(0);
+                }
+#pragma unroll
+                for (int v = 0; v < kVec; ++v) {
+                    const int e = threadIdx.x + 64 * v;
+                    const int ec = min(e, kChunk * N - 1);
+                    const int i = ec / N, x = ec - i * N;
+                    const bool ok = e < kChunk * N;
+                    const bool live = i < cnt;          // padding pairs contribute zero
+                    const R a = live ? av[v] : R(0), b = live ? bv[v] : R(0);
+                    if (ok) {
+                        if (KIND == 2) {
+                            vu[x * kChunk + i] = a - R(2) * b;
+                            vw[x * kChunk + i] = b;
+                        } else {
+                            vu[x * kChunk + i] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            // rows past N repeat row N-1 (clamped loads) and are weighted by zero
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int x = min(xg + j, N - 1);
+                const R mask = xg + j < N ? R(1) : R(0);
+                const R* u = vu + x * kChunk;
+#pragma unroll
+                for (int i = 0; i < kChunk; ++i) acc[i] += u[i] * (mask * ya[j]);
+                if (KIND == 2) {
+                    const R* w = vw + x * kChunk;
+#pragma unroll
+                    for (int i = 0; i < kChunk; ++i) acc[i] += w[i] * (mask * yb[j]);
+                }
+            }
+        }
+        if (n0 + static_cast<int>(threadIdx.x) >= N) continue;
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+            if (i >= cnt) break;
+            const int xy = pairs[i];
+            const int a = xy / N, c = xy - a * N;
+            if (KIND == 0) Kf[static_cast<size_t>(xy) * N + n] = -acc[i];
+            else if (KIND == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = acc[i];
+            else Kf[static_cast<size_t>(a) * NN + n * N + c] = acc[i];
+        }
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
                                                  const R* v0, const R* y1, const R* y2,
@@ -399,67 +650,16 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     const int* off = kind == 0 ? g.pp_off : (kind == 1 ? g.cr_off : g.d_off);
     const int* pairs = kind == 0 ? g.pp_pairs : (kind == 1 ? g.cr_pairs : g.d_pairs);
     const int cnt = min(kChunk, off[q + 1] - p0);
-    const int N = g.N, NN = g.NN;
-    const size_t N3 = static_cast<size_t>(NN) * N;
+    const size_t N3 = static_cast<size_t>(g.NN) * g.N;
     const R* V = v0 + f * N3;
-    const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
-    const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
+    const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * g.NN;
+    const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * g.NN;
     R* Kf = K + 3 * f * N3 + static_cast<size_t>(kind) * N3;   // [f][channel][N^3]
     R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
-    R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
-    for (int e = threadIdx.x; e < kChunk * N; e += blockDim.x) {
-        const int i = e / N, x = e - i * N;
-        R a = R(0), b = R(0);
-        if (i < cnt) {
-            const int xy = pairs[p0 + i];
-            const int u = xy / N, w = xy - u * N;
-            if (kind == 0) {
-                a = V[static_cast<size_t>(xy) * N + x];
-            } else if (kind == 1) {
-                a = V[static_cast<size_t>(x) * NN + u * N + w];
-            } else {
-                b = V[static_cast<size_t>(u) * NN + x * N + w];
-                a = V[static_cast<size_t>(x) * NN + u * N + w] - R(2) * b;
-            }
-        }
-        vu[x * kChunk + i] = a;
-        if (kind == 2) vw[x * kChunk + i] = b;
-    }
-    __syncthreads();
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
-        R acc[kChunk];
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) acc[i] = R(0);
-        for (int xg = 0; xg < N; xg += kXg) {
-            R ya[kXg], yb[kXg];
-#pragma unroll
-            for (int j = 0; j < kXg; ++j) {
-                const int x = min(xg + j, N - 1);
-                ya[j] = Ya[static_cast<size_t>(x) * N + n];
-                if (kind == 2) yb[j] = Yb[static_cast<size_t>(x) * N + n];
-            }
-#pragma unroll
-            for (int j = 0; j < kXg; ++j) {
-                if (xg + j >= N) break;
-                const R* u = vu + (xg + j) * kChunk;
-                const R* w = vw + (xg + j) * kChunk;
-#pragma unroll
-                for (int i = 0; i < kChunk; ++i) {
-                    acc[i] += u[i] * ya[j];
-                    if (kind == 2) acc[i] += w[i] * yb[j];
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-            if (i >= cnt) break;
-            const int xy = pairs[p0 + i];
-            const int a = xy / N, c = xy - a * N;
-            if (kind == 0) Kf[static_cast<size_t>(xy) * N + n] = -acc[i];
-            else if (kind == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = acc[i];
-            else Kf[static_cast<size_t>(a) * NN + n * N + c] = acc[i];
-        }
-    }
+    R* vw = vu + kChunk * g.N;                          // [N][kChunk] (direct only)
+    if (kind == 0) contract_item<R, 0>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
+    else if (kind == 1) contract_item<R, 1>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
+    else contract_item<R, 2>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
 }
 
 // k = k_pp + k_cr + k_d (channels that are masked off contribute zero).
@@ -750,11 +950,16 @@ R* kslot_ptr(const Buffers& b, int slot, size_t N3) {
 }
 
 template <typename R>
+int bins_mode(const DevGeom& g) {
+    return static_cast<size_t>(g.NN) * sizeof(R) <= 65536 ? 0 : 1;
+}
+
+template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
              const StageCoef& sc, int write_new, const double* Vbase, int kslot) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
     // bins are cleared only where phase 1 accumulates them with global atomics
-    const bool zero_bins = b.bins && static_cast<size_t>(g.NN) * sizeof(R) > 65536;
+    const bool zero_bins = b.bins && bins_mode<R>(g) == 1;
     const size_t nbins = static_cast<size_t>(g.nRp + g.nRd) * g.NN;
     hipLaunchKernelGGL(k_stage<R>, grid_for(N3, nf), dim3(kThreads), 0, s, g, z, b.fs, sc,
                        write_new, Vbase, static_cast<R*>(b.k), kslot, b.Vnew,
@@ -765,22 +970,24 @@ void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, i
 
 template <typename R>
 void bins_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {
-    using P4 = typename Pt4<R>::T;
+    using PT = typename PtT<R>::T;
     hipLaunchKernelGGL(k_points<R>, dim3((g.np + kThreads - 1) / kThreads, nf), dim3(kThreads),
-                       0, s, g, b.fs, b.T_stage, static_cast<P4*>(b.pt));
-    const int nR = g.nRp + g.nRd;
-    const dim3 grid(nR, nf);
-    const size_t lds = static_cast<size_t>(g.NN) * sizeof(R);
-    if (lds <= 65536)
-        hipLaunchKernelGGL((k_bins<R, true>), grid, dim3(kBinThreads), lds, s, g, b.fs, b.T_stage,
-                           static_cast<const P4*>(b.pt), static_cast<R*>(b.bins));
+                       0, s, g, b.fs, b.T_stage, static_cast<PT*>(b.pt));
+    const dim3 grid(g.nRp + g.nRd, nf);
+    const PT* pt = static_cast<const PT*>(b.pt);
+    R* bins = static_cast<R*>(b.bins);
+    R* binsT = static_cast<R*>(b.binsT);
+    if (bins_mode<R>(g) == 0)
+        hipLaunchKernelGGL((k_bins<R, 0>), grid, dim3(kBinThreads),
+                           static_cast<size_t>(g.NN) * sizeof(R), s, g, b.fs, b.T_stage, pt,
+                           bins, binsT);
     else
-        hipLaunchKernelGGL((k_bins<R, false>), grid, dim3(kBinThreads), 0, s, g, b.fs, b.T_stage,
-                           static_cast<const P4*>(b.pt), static_cast<R*>(b.bins));
+        hipLaunchKernelGGL((k_bins<R, 1>), grid, dim3(kBinThreads), 0, s, g, b.fs, b.T_stage,
+                           pt, bins, binsT);
 }
 
 template <typename R>
-void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch) {
+void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int mma) {
     YArgs<R> a;
     a.Vs[0] = static_cast<const R*>(b.v0);
     a.Vs[1] = static_cast<const R*>(b.vc);
@@ -792,9 +999,26 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch)
     a.on[1] = (ch & FM_CH_CR) != 0;
     a.on[2] = a.on[3] = (ch & FM_CH_D) != 0;
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
+    if constexpr (sizeof(R) == 4) {
+        if (mma > 0 && g.N <= 128) {
+            const YArgs<float>& af = reinterpret_cast<const YArgs<float>&>(a);
+            const dim3 grid((mmax + 63) / 64, g.N, 4 * nf);
+            const float* bn = static_cast<const float*>(b.bins);
+            const float* bt = static_cast<const float*>(b.binsT);
+            const bool wide = g.N > 64;   // k in stages of 32 instead of all at once
+            if (mma == 2) {
+                if (wide) hipLaunchKernelGGL((k_y_mfma<true, 32>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
+                else hipLaunchKernelGGL((k_y_mfma<true, 64>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
+            } else {
+                if (wide) hipLaunchKernelGGL((k_y_mfma<false, 32>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
+                else hipLaunchKernelGGL((k_y_mfma<false, 64>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
+            }
+            return;
+        }
+    }
     const int tiles = ((mmax + 63) / 64) * ((g.N + 63) / 64);
     hipLaunchKernelGGL(k_y<R>, dim3(tiles, g.N, 4 * nf), dim3(kThreads), 0, s, g, b.fs,
-                       b.Z_stage, static_cast<const R*>(b.bins), a);
+                       b.Z_stage, static_cast<const R*>(b.bins), static_cast<const R*>(b.binsT), a);
 }
 
 template <typename R>
@@ -823,9 +1047,10 @@ void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, in
     else bins_t<float>(s, g, b, nf);
 }
 
-void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch) {
-    if (dbl) y_t<double>(s, g, b, nf, ch);
-    else y_t<float>(s, g, b, nf, ch);
+void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
+              int mma) {
+    if (dbl) y_t<double>(s, g, b, nf, ch, 0);
+    else y_t<float>(s, g, b, nf, ch, mma);
 }
 
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,
