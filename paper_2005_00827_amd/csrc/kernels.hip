@@ -201,23 +201,45 @@ __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 
 // ------------------------------------------------------------------------------------
 // Phase 1: bins of the representative transfers.  One 1024-thread block per
-// (representative, flow).  A work unit is kSeg consecutive points of one row with their
-// partners; lanes of a wave take different rows.  Each thread loads all points of its unit
-// at once, carries the running sum of consecutive pairs that fall into the same patch
-// pair, and adds it to the LDS bin matrix when the pair changes.  The block finally writes
-// the bins scaled by -1/(4 T L^2).
-//   kMode 0: bins and the loop grid's patch table (u16) in LDS, kSeg = 16 (8 in double)
-//   kMode 1: bins in LDS, patches read from global memory, kSeg = 8
-//   kMode 2: bins accumulated with global atomics (cleared by the stage kernel), kSeg = 8
+// (representative, flow) accumulates the N x N bin matrix in LDS and stores it scaled by
+// -1/(4 T L^2) (plus its transpose for particle-hole representatives, which the crossed
+// channel reads).
+//
+// Lane layout: the 16 lanes of a DPP row take 16 consecutive loop points, so every load
+// (own point, partner, both patches) is a contiguous segment.  Consecutive points mostly
+// share their patch pair, so a segmented scan over the row (DPP shifts 1, 2, 4, 8) sums
+// each run of equal keys and only the last lane of a run issues the LDS atomic.  The four
+// rows of a wave work in bands a quarter of the grid apart, so their keys rarely collide.
 // ------------------------------------------------------------------------------------
 constexpr int kBinThreads = 1024;
-constexpr int kBinBatch = 8;   // points per thread with loads in flight together
+constexpr int kBinBatch = 4;   // 16-point units per row with loads in flight together
 
-// Grid (representative, flow).  Thread t takes points j = t + kBinThreads i, so a wave covers
-// consecutive points of a row and every load (own point, partner, patches) is coalesced.
-// kMode 0: bins in LDS (added with LDS atomics), stored scaled by -1/(4 T L^2); 1: global
-// atomics into bins cleared by the stage kernel.  The block also writes the transpose for
-// particle-hole representatives (read by the crossed channel).
+template <int kCtrl>
+__device__ inline float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
+template <int kCtrl>
+__device__ inline double dpp_f(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), kCtrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), kCtrl, 0xf, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+template <int kCtrl>
+__device__ inline int dpp_i(int v) { return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xf, 0xf, false); }
+
+// One step of the segmented inclusive scan within a 16-lane row: lane s combines with lane
+// s - d (values from the same step), (v1, h1) + (v2, h2) = (h2 ? v2 : v1 + v2, h1 | h2).
+template <int D, typename R>
+__device__ inline void seg_step(R& v, int& h, int s) {
+    const R vp = dpp_f<0x110 | D>(v);   // row_shr:D
+    const int hp = dpp_i<0x110 | D>(h);
+    if (s >= D) {
+        if (!h) v += vp;
+        h |= hp;
+    }
+}
+
 template <typename R, int kMode>
 __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState* fs,
                                                       const double* T_stage,
@@ -241,12 +263,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
         for (int i = threadIdx.x; i < NN; i += blockDim.x) lb[i] = R(0);
     __syncthreads();                                   // every thread of the block
     R* acc = kMode == 0 ? lb : out;
-    for (int j0 = threadIdx.x; j0 < np; j0 += kBinBatch * kBinThreads) {
+    // 64 rows of 16 lanes per block; row rr works on band rr of 64 contiguous bands of units
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int s = lane & 15;
+    const int band = (lane >> 4) * (kBinThreads / 64) + wv;
+    const int nunits = (np + 15) / 16;
+    const int per_band = (nunits + 63) / 64;
+    const int u_begin = band * per_band;
+    const int u_end = min(u_begin + per_band, nunits);
+    for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
         PT u[kBinBatch], v[kBinBatch];
         int pa[kBinBatch], pq[kBinBatch];
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
-            const int j = min(j0 + i * kBinThreads, np - 1);
+            const int j = min((u0 + i) * 16 + s, np - 1);
             const int jy = j / L, jx = j - jy * L;
             int px = pp ? mx - jx - 1 : jx + mx;
             int py = pp ? my - jy - 1 : jy + my;
@@ -258,12 +288,21 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
             pa[i] = g.patch[j];
             pq[i] = g.patch[jp];
         }
-        // every loaded value is used (no early exit), so the loads stay batched
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
+            const int j = (u0 + i) * 16 + s;
+            const bool ok = u0 + i < u_end && j < np;
             const R w = phi_dd_pt(u[i], pp ? flip(v[i]) : v[i]);
-            const R wv = j0 + i * kBinThreads < np ? w : R(0);
-            atomicAdd(&acc[pa[i] * N + pq[i]], kMode == 0 ? wv : wv * scale);
+            R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
+            const int key = pa[i] * N + pq[i];
+            const int kprev = dpp_i<0x111>(key);   // row_shr:1
+            const int knext = dpp_i<0x101>(key);   // row_shl:1
+            int h = (s == 0 || kprev != key) ? 1 : 0;
+            seg_step<1>(x, h, s);
+            seg_step<2>(x, h, s);
+            seg_step<4>(x, h, s);
+            seg_step<8>(x, h, s);
+            if (s == 15 || knext != key) atomicAdd(&acc[key], x);
         }
     }
     __syncthreads();                                   // every thread of the block
@@ -395,137 +434,159 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     }
 }
 
-// Phase 2a on matrix cores (single-precision storage, N <= 128).  Same products as k_y;
-// the block computes 64 transfers x N outputs of one group g: four waves of 16 rows, n in
-// 16-wide tiles, k staged through LDS KC at a time (all of k at once for N <= 64), all loads
-// of a stage issued together.  kBF16 = false: v_mfma_f32_16x16x4_f32 (operands f32); true:
-// v_mfma_f32_16x16x32_bf16 (operands rounded to bf16, f32 accumulation).  Fragment layouts
-// (wave64): A row = lane % 16, B column = lane % 16, the k index from lane / 16 (times 8 for
-// bf16, plus the element index); D row = 4 (lane / 16) + r, column = lane % 16.
+// Phase 2a on matrix cores (single-precision storage, N <= 128).  Same products as k_y.
+// One wave computes, for one group g, a column chunk of NT 16-wide tiles and a run of
+// 16-row tiles of transfers.  Both operands go straight from memory into the MFMA register
+// layout (no LDS staging):
+//   B[k][n] = Vsrc[g][k][n] is loaded once per wave (KE values per lane and tile; for
+//     the direct channel two such operands, va and vc, share one A);
+//   A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k) is gathered per row tile, the patch
+//     permutations and Z read from LDS.
+// kBF16 = false: v_mfma_f32_16x16x4_f32, lane holds k = 4 e + lane / 16 (e < KE);
+// kBF16 = true:  v_mfma_f32_16x16x32_bf16, k = 32 (e / 8) + 8 (lane / 16) + e % 8.
+// A row and B column = lane % 16; D row = 4 (lane / 16) + r, column = lane % 16.
+// k >= N (and n >= N) are zero in both operands.
 typedef float fm_f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 fm_bf8 __attribute__((ext_vector_type(8)));
 
-template <bool kBF16, int KC>
-__global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
-                                                     const double* Z_stage, const float* bins,
-                                                     const float* binsT, YArgs<float> args) {
-    constexpr int TQ = 64, KS = KC + 4, NT = 8;
-    __shared__ __align__(16) float As[TQ][KS];      // A[q][k]
-    __shared__ __align__(16) float Bt[16 * NT][KS]; // B^T[n][k]
-    __shared__ int pis[8 * 16 * NT];                 // patch permutations (N <= 128)
-    __shared__ int rrep[TQ], rperm[TQ];              // per row: representative, permutation
-    __shared__ float zs[16 * NT];                    // Z of the stage
-    const int kind = blockIdx.z % 4;
-    const int f = blockIdx.z / 4;
-    if (!running(fs, f) || !args.on[kind]) return;
-    const int N = g.N, NN = g.NN;
-    const bool ppk = kind == 0;
-    const int M = ppk ? g.nP : g.nD;
-    const int tq = blockIdx.x;
-    if (tq * TQ >= M) return;
-    const int grp = blockIdx.y;
-    const size_t N3 = static_cast<size_t>(NN) * N;
-    const int nR = g.nRp + g.nRd;
-    const float* Bf = kind == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
-                                : bins + static_cast<size_t>(f) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
-    const int* qrep = ppk ? g.qrep_pp : g.qrep_ph;
-    const int* qg = ppk ? g.qg_pp : g.qg_ph;
-    const float* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
-    const double* Zf = Z_stage + static_cast<size_t>(f) * N;
-    for (int i = threadIdx.x; i < 8 * N; i += blockDim.x) pis[i] = g.pinv[i];
-    for (int i = threadIdx.x; i < TQ; i += blockDim.x) {
-        const int q = tq * TQ + i;
-        rrep[i] = q < M ? qrep[q] : -1;
-        rperm[i] = q < M ? qg[q] : 0;
-    }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) zs[i] = static_cast<float>(Zf[i]);
-    __syncthreads();
-    const float zg = zs[grp];
-    const int ntile = (N + 15) / 16;
-    const int Np = ntile * 16;
-    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-    fm_f4 acc[NT];
+template <bool kBF16>
+__device__ inline int mfma_k(int e, int lane) {
+    return kBF16 ? 32 * (e >> 3) + 8 * (lane >> 4) + (e & 7) : 4 * e + (lane >> 4);
+}
+
+template <bool kBF16, int KE, int NT, bool kTwo>
+__device__ inline void mfma_tile(const float (&a)[KE], const float (&b0)[NT][KE],
+                                 const float (&b1)[NT][KE], fm_f4 (&c0)[NT], fm_f4 (&c1)[NT]) {
+    if constexpr (kBF16) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < N; k0 += KC) {
-        // A: element e -> row e / KC, column e % KC (columns consecutive over lanes).  All
-        // loads of the stage go to registers first so they are in flight together.
-        constexpr int kA = TQ * KC / kThreads;
-        constexpr int kB = KC * 16 * NT / kThreads;
-        float av[kA], bv[kB];
+        for (int s = 0; s < KE / 8; ++s) {
+            fm_bf8 av;
 #pragma unroll
-        for (int i = 0; i < kA; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            const int rr = e / KC, kk = e - rr * KC;
-            const int k = k0 + kk;
-            const int rep = rrep[rr];
-            const int kc = min(k, N - 1);
-            const int* pi = pis + rperm[rr] * N;
-            const float x = Bf[static_cast<size_t>(max(rep, 0)) * NN + pi[grp] * N + pi[kc]];
-            av[i] = (rep >= 0 && k < N) ? x * (zg * zs[kc]) : 0.f;
-        }
+            for (int e = 0; e < 8; ++e) av[e] = static_cast<__bf16>(a[8 * s + e]);
 #pragma unroll
-        for (int i = 0; i < kB; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            const int kk = e / Np, n = e - kk * Np;
-            const int kr = k0 + kk;
-            const float x = Vg[static_cast<size_t>(min(kr, N - 1)) * N + min(n, N - 1)];
-            bv[i] = (kk < KC && kr < N && n < N) ? x : 0.f;
-        }
+            for (int t = 0; t < NT; ++t) {
+                fm_bf8 bv;
 #pragma unroll
-        for (int i = 0; i < kA; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            As[e / KC][e % KC] = av[i];
-        }
+                for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(b0[t][8 * s + e]);
+                c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c0[t], 0, 0, 0);
+                if constexpr (kTwo) {
 #pragma unroll
-        for (int i = 0; i < kB; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            const int kk = e / Np, n = e - kk * Np;
-            if (kk < KC) Bt[n][kk] = bv[i];
-        }
-        __syncthreads();
-        if (kBF16) {
-#pragma unroll
-            for (int kk = 0; kk < KC; kk += 32) {
-                fm_bf8 a;
-                const float* ar = &As[wv * 16 + lane % 16][kk + 8 * (lane / 16)];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) a[e] = static_cast<__bf16>(ar[e]);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    if (t >= ntile) break;
-                    fm_bf8 b;
-                    const float* br = &Bt[t * 16 + lane % 16][kk + 8 * (lane / 16)];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) b[e] = static_cast<__bf16>(br[e]);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int kk = 0; kk < KC; kk += 4) {
-                const float a = As[wv * 16 + lane % 16][kk + lane / 16];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    if (t >= ntile) break;
-                    const float b = Bt[t * 16 + lane % 16][kk + lane / 16];
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+                    for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(b1[t][8 * s + e]);
+                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c1[t], 0, 0, 0);
                 }
             }
         }
-        __syncthreads();
+    } else {
+#pragma unroll
+        for (int e = 0; e < KE; ++e) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b0[t][e], c0[t], 0, 0, 0);
+                if constexpr (kTwo)
+                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b1[t][e], c1[t], 0, 0, 0);
+            }
+        }
     }
-    float* Y = args.Y[kind] + static_cast<size_t>(f) * M * NN;
+}
+
+template <bool kBF16, int KE, int NT, bool kTwo>
+__device__ inline void y_wave(int N, int NN, int M, int grp, int n0, int t_begin, int t_end,
+                              const float* Bf, const int* qrep, const int* qg, const int* pis,
+                              const float* zs, const float* V0, const float* V1, float* Y0,
+                              float* Y1) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15;
+    float b0[NT][KE], b1[NT][KE];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        if (t >= ntile) break;
-        const int n = t * 16 + lane % 16;
+        const int n = n0 + 16 * t + col;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int q = tq * TQ + wv * 16 + 4 * (lane / 16) + r;
-            if (q < M && n < N) Y[static_cast<size_t>(q) * NN + grp * N + n] = acc[t][r];
+        for (int e = 0; e < KE; ++e) {
+            const int k = mfma_k<kBF16>(e, lane);
+            const size_t ia = static_cast<size_t>(min(k, N - 1)) * N + min(n, N - 1);
+            const bool ok = k < N && n < N;
+            const float x0 = V0[ia];
+            b0[t][e] = ok ? x0 : 0.f;
+            if constexpr (kTwo) {
+                const float x1 = V1[ia];
+                b1[t][e] = ok ? x1 : 0.f;
+            }
         }
     }
+    const float zg = zs[grp];
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        const int q = min(tile * 16 + col, M - 1);
+        const int rep = qrep[q];
+        const int* pi = pis + qg[q] * N;
+        const float* row = Bf + static_cast<size_t>(rep) * NN + pi[grp] * N;
+        float a[KE];
+#pragma unroll
+        for (int e = 0; e < KE; ++e) {
+            const int k = mfma_k<kBF16>(e, lane);
+            const int kc = min(k, N - 1);
+            const float x = row[pi[kc]];
+            a[e] = k < N ? x * (zg * zs[kc]) : 0.f;
+        }
+        fm_f4 c0[NT], c1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c0[t] = c1[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
+        mfma_tile<kBF16, KE, NT, kTwo>(a, b0, b1, c0, c1);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = n0 + 16 * t + col;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int qq = tile * 16 + 4 * (lane >> 4) + r;
+                if (qq < M && n < N) {
+                    const size_t o = static_cast<size_t>(qq) * NN + grp * N + n;
+                    Y0[o] = c0[t][r];
+                    if constexpr (kTwo) Y1[o] = c1[t][r];
+                }
+            }
+        }
+    }
+}
+
+// Grid: x = blocks of 4 waves over row-tile runs, y = group * nchunk + column chunk,
+// z = 3 * flow + channel (0 pp -> Y1, 1 crossed -> Y2, 2 direct -> Y3 and Y4).
+template <bool kBF16, int KE, int NT>
+__global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
+                                                     const double* Z_stage, const float* bins,
+                                                     const float* binsT, YArgs<float> args,
+                                                     int tiles_per_wave, int nchunk) {
+    __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
+    __shared__ float zs[128];                         // Z of the stage
+    const int ch = blockIdx.z % 3;
+    const int f = blockIdx.z / 3;
+    if (!running(fs, f) || !args.on[ch == 2 ? 2 : ch]) return;
+    const int N = g.N, NN = g.NN;
+    const int M = ch == 0 ? g.nP : g.nD;
+    const int grp = blockIdx.y / nchunk;
+    const int n0 = (blockIdx.y - grp * nchunk) * 16 * NT;
+    const int ntiles = (M + 15) / 16;
+    const int wv = threadIdx.x >> 6;
+    const int t_begin = (blockIdx.x * 4 + wv) * tiles_per_wave;
+    const int t_end = min(t_begin + tiles_per_wave, ntiles);
+    for (int i = threadIdx.x; i < 8 * N; i += blockDim.x) pis[i] = g.pinv[i];
+    const double* Zf = Z_stage + static_cast<size_t>(f) * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) zs[i] = static_cast<float>(Zf[i]);
+    __syncthreads();                                   // every thread of the block
+    if (t_begin >= t_end) return;
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    const int nR = g.nRp + g.nRd;
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
+                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
+    const int* qg = ch == 0 ? g.qg_pp : g.qg_ph;
+    const size_t slab = f * N3 + static_cast<size_t>(grp) * NN;
+    const size_t yoff = static_cast<size_t>(f) * M * NN;
+    if (ch == 2)
+        y_wave<kBF16, KE, NT, true>(N, NN, M, grp, n0, t_begin, t_end, Bf, qrep, qg, pis, zs,
+                                    args.Vs[2] + slab, args.Vs[3] + slab, args.Y[2] + yoff,
+                                    args.Y[3] + yoff);
+    else
+        y_wave<kBF16, KE, NT, false>(N, NN, M, grp, n0, t_begin, t_end, Bf, qrep, qg, pis, zs,
+                                     args.Vs[ch] + slab, nullptr, args.Y[ch] + yoff, nullptr);
 }
 
 // ------------------------------------------------------------------------------------
@@ -986,6 +1047,44 @@ void bins_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {
                            pt, bins, binsT);
 }
 
+// Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
+// tiles per wave) and a run of row tiles per wave sized for about 4096 waves.
+template <bool kBF16, int KE, int NT>
+void y_mfma_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+               const YArgs<float>& a) {
+    const int mmax = g.nP > g.nD ? g.nP : g.nD;
+    const int ntiles = (mmax + 15) / 16;
+    const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
+    const long waves1 = static_cast<long>(ntiles) * g.N * nchunk * 3 * nf;
+    int tpw = static_cast<int>((waves1 + 4095) / 4096);
+    tpw = tpw < 1 ? 1 : (tpw > 8 ? 8 : tpw);
+    const int bx = (ntiles + 4 * tpw - 1) / (4 * tpw);
+    const dim3 grid(bx, g.N * nchunk, 3 * nf);
+    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage,
+                       static_cast<const float*>(b.bins), static_cast<const float*>(b.binsT), a,
+                       tpw, nchunk);
+}
+
+inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+                          const YArgs<float>& a, bool bf16) {
+    const int N = g.N;
+    if (bf16) {
+        if (N <= 16) y_mfma_go<true, 8, 1>(s, g, b, nf, a);
+        else if (N <= 32) y_mfma_go<true, 8, 2>(s, g, b, nf, a);
+        else if (N <= 48) y_mfma_go<true, 16, 3>(s, g, b, nf, a);
+        else if (N <= 64) y_mfma_go<true, 16, 2>(s, g, b, nf, a);
+        else if (N <= 96) y_mfma_go<true, 24, 2>(s, g, b, nf, a);
+        else y_mfma_go<true, 32, 2>(s, g, b, nf, a);
+    } else {
+        if (N <= 16) y_mfma_go<false, 4, 1>(s, g, b, nf, a);
+        else if (N <= 32) y_mfma_go<false, 8, 2>(s, g, b, nf, a);
+        else if (N <= 48) y_mfma_go<false, 12, 3>(s, g, b, nf, a);
+        else if (N <= 64) y_mfma_go<false, 16, 2>(s, g, b, nf, a);
+        else if (N <= 96) y_mfma_go<false, 24, 2>(s, g, b, nf, a);
+        else y_mfma_go<false, 32, 2>(s, g, b, nf, a);
+    }
+}
+
 template <typename R>
 void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int mma) {
     YArgs<R> a;
@@ -1001,18 +1100,7 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     if constexpr (sizeof(R) == 4) {
         if (mma > 0 && g.N <= 128) {
-            const YArgs<float>& af = reinterpret_cast<const YArgs<float>&>(a);
-            const dim3 grid((mmax + 63) / 64, g.N, 4 * nf);
-            const float* bn = static_cast<const float*>(b.bins);
-            const float* bt = static_cast<const float*>(b.binsT);
-            const bool wide = g.N > 64;   // k in stages of 32 instead of all at once
-            if (mma == 2) {
-                if (wide) hipLaunchKernelGGL((k_y_mfma<true, 32>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
-                else hipLaunchKernelGGL((k_y_mfma<true, 64>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
-            } else {
-                if (wide) hipLaunchKernelGGL((k_y_mfma<false, 32>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
-                else hipLaunchKernelGGL((k_y_mfma<false, 64>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage, bn, bt, af);
-            }
+            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma == 2);
             return;
         }
     }
