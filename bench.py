@@ -28,27 +28,58 @@ PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6, "bf16_TFs": 2500
 METRIC = "coupling·loop-point updates/s per RHS (N³·L²·3); flows/hour, mixed vs FP64"
 
 
-def kernel_work(name, N, L, nP, nD, rsize):
+def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None):
     """Algorithmic work of one launch of each timed kernel group for one flow.
 
-    bins:     (nP + nD) L^2 weight derivatives, each 6 flops (two differences, one
-              division, the 1/(4 T L^2) scale and the bin accumulation) -> ALU bound
-    y:        (nP + 3 nD) N^3 multiply-adds; bytes = bins read + Y written + 3 operand slabs
+    bins:     (nRp + nRd) L^2 weight derivatives (orbit representatives), each 6 flops (two
+              differences, one division, the 1/(4 T L^2) scale and the bin accumulation)
+    y:        (nP + 3 nD) N^3 multiply-adds; bytes = representative bins read (plus the
+              transposed particle-hole bins) + 3 operand slabs read + Y written
     contract: 4 N^4 multiply-adds; bytes = Y read + operand read + k written
     stage:    bytes = V (f64) read + 3 operand layouts written + stage terms read (<= 6 k)
     """
     NN, N3 = N * N, N ** 3
+    nRp = nP if nRp is None else nRp
+    nRd = nD if nRd is None else nRd
     if name == "bins":
-        return {"bound": "alu", "flops": 6.0 * (nP + nD) * L * L}
+        return {"bound": "alu", "flops": 6.0 * (nRp + nRd) * L * L}
     if name == "y":
         return {"bound": "hbm", "flops": 2.0 * (nP + 3 * nD) * N3,
-                "bytes": (nP + 2 * nD) * NN * rsize + (nP + 3 * nD) * NN * rsize + 3 * N3 * rsize}
+                "bytes": (nRp + 2 * nRd) * NN * rsize + 3 * N3 * rsize + (nP + 3 * nD) * NN * rsize}
     if name == "contract":
         return {"bound": "hbm", "flops": 8.0 * N ** 4,
                 "bytes": (nP + 3 * nD) * NN * rsize + 2 * N3 * rsize}
     if name == "stage":
         return {"bound": "hbm", "bytes": N3 * 8 + 3 * N3 * rsize + 3 * N3 * rsize}
     return None
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2005_00827_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(group):
+    """HBM bytes per launch of a kernel group from the committed counter summary.
+
+    The summary holds FETCH_SIZE + WRITE_SIZE per dispatch (scaled by the copy-kernel
+    calibration) and the SHA-256 of the kernel source it was taken with; when the source
+    has changed since, the figure no longer describes the kernel and None is returned.
+    """
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for ln in fh:
+            if ":" in ln and not ln.startswith((" ", "#", "$")):
+                k, v = ln.split(":", 1)
+                kv[k.strip()] = v.strip()
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    key = "bytes_per_launch_" + group
+    if kv.get("kernel_source_sha256") != sha or key not in kv:
+        return None
+    return float(kv[key])
 
 
 def main():
@@ -58,7 +89,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-rhs", type=int, default=2, help="oracle RHS evaluations timed")
+    ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations timed")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain device-to-device copy of this many MiB three times "
+                         "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -80,6 +114,14 @@ def main():
     def make(prec):
         return fm.Flow(N=N, L=L, U=U, T0=T0, T_end=Te, integrator="rk45", precision=prec,
                        z_lnT=zl, z_table=zt, max_batch=1, device=dev)
+
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     flow = make("fp32")
     for _ in range(args.warmup):
@@ -104,11 +146,12 @@ def main():
     flow.set_timing(False)
     cfg = fm.make_config(N, L)
     _, _, _, nP, nD, _ = fm.geometry_query(cfg)
+    nRp, nRd = fm.representative_counts(cfg)
     kernels = {}
     for name, (ms, n) in tm.items():
         avg_s = ms / n * 1e-3
         k = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6}
-        wk = kernel_work(name, N, L, nP, nD, 4)
+        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd)
         if wk:
             if wk["bound"] == "hbm":
                 k.update(bound="hbm", achieved=wk["bytes"] / avg_s / 1e9, peak=PEAK["hbm_GBs"],
@@ -122,7 +165,7 @@ def main():
     d = kernels[dom]
     roofline = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"),
                 "peak": d.get("peak"), "unit": d.get("unit"), "frac": d.get("frac"),
-                "traffic": None, "avg_us": d["avg_us"]}
+                "traffic": measured_traffic(dom), "avg_us": d["avg_us"]}
 
     extra = {"flows": args.steps, "rhs_per_flow": n_rhs / args.steps,
              "T_c_fp32": res[0]["T_c"], "flows_per_hour_fp32": args.steps / wall * 3600.0,

@@ -142,10 +142,13 @@ int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0
 
 /* Host-only geometry query (no device needed): xi[L*L], patch[L*L], anchor[N][2] (snapped
  * Fermi-point transfer indices, or loop indices in identity mode), the numbers of distinct
- * particle-particle and particle-hole transfers, and the smallest distance of a loop point
- * to a patch boundary in sector widths.  Any output pointer may be NULL. */
+ * particle-particle and particle-hole transfers, the smallest distance of a loop point to a
+ * patch boundary in sector widths, and n_rep[2]: the numbers of particle-particle and
+ * particle-hole transfers whose bins phase 1 computes (orbit representatives under the
+ * square's point group when the geometry has that symmetry, else all transfers).  Any
+ * output pointer may be NULL. */
 int fm_geometry_query(const fm_config *cfg, double *xi, int *patch, int *anchor, int *n_pp,
-                      int *n_ph, double *margin);
+                      int *n_ph, double *margin, int *n_rep);
 
 /* Per-kernel event timings of the last fm_flow_rhs / fm_flow_step / fm_flow_run_batch call
  * (milliseconds, summed over launches), when enabled with fm_flow_set_timing(h, 1).

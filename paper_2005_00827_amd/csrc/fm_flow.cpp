@@ -290,7 +290,7 @@ extern "C" {
 const char* fm_last_error(void) { return g_err.c_str(); }
 
 int fm_geometry_query(const fm_config* cfg, double* xi, int* patch, int* anchor, int* n_pp,
-                      int* n_ph, double* margin) {
+                      int* n_ph, double* margin, int* n_rep) {
     if (!cfg) return fail(FM_EINVAL, "null config");
     HostGeometry g;
     std::string why;
@@ -301,6 +301,10 @@ int fm_geometry_query(const fm_config* cfg, double* xi, int* patch, int* anchor,
     if (n_pp) *n_pp = static_cast<int>(g.q_pp.size());
     if (n_ph) *n_ph = static_cast<int>(g.q_ph.size());
     if (margin) *margin = g.margin;
+    if (n_rep) {
+        n_rep[0] = static_cast<int>(g.rep_pp.size());
+        n_rep[1] = static_cast<int>(g.rep_ph.size());
+    }
     return FM_OK;
 }
 

@@ -78,7 +78,7 @@ def load():
         "fm_flow_rhs": (c_int, [c_void_p, c_int, pd, c_void_p, c_void_p]),
         "fm_flow_step": (c_int, [c_void_p, c_int, pd, pd, c_void_p, pi]),
         "fm_flow_run_batch": (c_int, [c_void_p, c_int, pd, pd, pd, pd, c_void_p, pr]),
-        "fm_geometry_query": (c_int, [pc, pd, pi, pi, pi, pi, pd]),
+        "fm_geometry_query": (c_int, [pc, pd, pi, pi, pi, pi, pd, pi]),
         "fm_flow_set_timing": (c_int, [c_void_p, c_int]),
         "fm_flow_timings": (c_int, [c_void_p, POINTER(c_char_p), pd, pi, c_int]),
         "fm_flow_destroy": (None, [c_void_p]),
@@ -142,8 +142,17 @@ def geometry_query(cfg: Config):
     anchor = np.zeros((cfg.N, 2), np.int32)
     npp, nph, mg = c_int(0), c_int(0), c_double(0)
     _check(load().fm_geometry_query(ctypes.byref(cfg), _pd(xi), _pi(patch), _pi(anchor),
-                                    ctypes.byref(npp), ctypes.byref(nph), ctypes.byref(mg)))
+                                    ctypes.byref(npp), ctypes.byref(nph), ctypes.byref(mg),
+                                    None))
     return xi, patch, anchor, npp.value, nph.value, mg.value
+
+
+def representative_counts(cfg: Config):
+    """Host-only: numbers of particle-particle and particle-hole transfers binned by phase 1."""
+    rep = np.zeros(2, np.int32)
+    _check(load().fm_geometry_query(ctypes.byref(cfg), None, None, None, None, None, None,
+                                    _pi(rep)))
+    return int(rep[0]), int(rep[1])
 
 
 def workspace_bytes(cfg: Config) -> int:

@@ -44,6 +44,28 @@ def test_transfer_counts_of_the_workloads():
         assert npp == nph == n
 
 
+def _orbit_count(ms, L):
+    """Orbits of transfer indices (mx, my) mod L under the square's point group: sign flips
+    of either axis and the axis swap act on the unshifted transfer grid as m -> -m and
+    (mx, my) -> (my, mx), for particle-particle and particle-hole transfers alike."""
+    def canon(m):
+        mx, my = m
+        return min(((sx * a) % L, (sy * b) % L) for a, b in ((mx, my), (my, mx))
+                   for sx in (1, -1) for sy in (1, -1))
+    return len({canon(m) for m in ms})
+
+
+@pytest.mark.parametrize("N,L,tp,mu", [(16, 32, 0, 0), (48, 128, 0, 0), (8, 16, -0.3, -0.4),
+                                       (96, 256, 0, 0)])
+def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
+    _, _, anchor, _ = O.geometry(O.model(N, L, tp=tp, mu=mu))
+    a = np.asarray(anchor).reshape(N, 2)
+    qpp = {((a[x, 0] + a[y, 0]) % L, (a[x, 1] + a[y, 1]) % L) for x in range(N) for y in range(N)}
+    qph = {((a[y, 0] - a[x, 0]) % L, (a[y, 1] - a[x, 1]) % L) for x in range(N) for y in range(N)}
+    nrp, nrd = fm.representative_counts(fm.make_config(N, L, tp=tp, mu=mu))
+    assert (nrp, nrd) == (_orbit_count(qpp, L), _orbit_count(qph, L))
+
+
 @pytest.mark.parametrize("kw,msg", [
     (dict(N=12, L=32), "N %"),                 # N % 8 == 4 is fine; 12 % 8 == 4 -> ok, so use 10
     (dict(N=10, L=32), "angular geometry"),
