@@ -31,17 +31,19 @@ METRIC = "coupling·loop-point updates/s per RHS (N³·L²·3); flows/hour, mixe
 def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None):
     """Algorithmic work of one launch of each timed kernel group for one flow.
 
-    bins:     (nRp + nRd) L^2 weight derivatives (orbit representatives), each 6 flops (two
-              differences, one division, the 1/(4 T L^2) scale and the bin accumulation)
+    stage_bins: phase 1 of the stage (the stage argument in the same launch is minor):
+              (nRp + nRd) L^2 weight derivatives (orbit representatives), each counted as
+              6 flops (two differences, one division, the 1/(4 T L^2) scale and the bin
+              accumulation) -- the point quantities the kernel evaluates on the fly are not
+              counted
     y:        (nP + 3 nD) N^3 multiply-adds; bytes = representative bins read (plus the
               transposed particle-hole bins) + 3 operand slabs read + Y written
     contract: 4 N^4 multiply-adds; bytes = Y read + operand read + k written
-    stage:    bytes = V (f64) read + 3 operand layouts written + stage terms read (<= 6 k)
     """
     NN, N3 = N * N, N ** 3
     nRp = nP if nRp is None else nRp
     nRd = nD if nRd is None else nRd
-    if name == "bins":
+    if name == "stage_bins":
         return {"bound": "alu", "flops": 6.0 * (nRp + nRd) * L * L}
     if name == "y":
         return {"bound": "hbm", "flops": 2.0 * (nP + 3 * nD) * N3,
@@ -49,8 +51,6 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None):
     if name == "contract":
         return {"bound": "hbm", "flops": 8.0 * N ** 4,
                 "bytes": (nP + 3 * nD) * NN * rsize + 2 * N3 * rsize}
-    if name == "stage":
-        return {"bound": "hbm", "bytes": N3 * 8 + 3 * N3 * rsize + 3 * N3 * rsize}
     return None
 
 

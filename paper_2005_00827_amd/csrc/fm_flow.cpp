@@ -120,8 +120,8 @@ struct fm_flow {
 
 namespace {
 
-enum { T_STAGE, T_BINS, T_Y, T_CONTRACT, T_WTABLE, T_DIRECT, T_UPDATE, T_FINISH, T_COUNT };
-const char* kTimerNames[T_COUNT] = {"stage", "bins", "y", "contract", "wtable", "direct",
+enum { T_STAGE, T_Y, T_CONTRACT, T_WTABLE, T_DIRECT, T_UPDATE, T_FINISH, T_COUNT };
+const char* kTimerNames[T_COUNT] = {"stage_bins", "y", "contract", "wtable", "direct",
                                     "update", "finish"};
 
 int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, size_t* bytes) {
@@ -168,7 +168,6 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
     b.bstride = B;
     if (!direct) {
-        b.pt = L.take<char>(static_cast<size_t>(B) * np * 16);   // float4 or double2
         b.bins = L.take<char>(static_cast<size_t>(B) * (nRp + nRd) * NN * rs);
         b.binsT = L.take<char>(static_cast<size_t>(B) * nRd * NN * rs);
         b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
@@ -177,14 +176,13 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.wtab = nullptr;
     } else {
-        b.pt = b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
     }
     b.v0 = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.va = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.vc = L.take<char>(static_cast<size_t>(B) * N3 * rs);
-    b.k = L.take<char>(7 * static_cast<size_t>(B) * N3 * rs);
-    b.kpart = direct ? nullptr : L.take<char>(3 * static_cast<size_t>(B) * N3 * rs);
+    b.k = L.take<char>(7 * 3 * static_cast<size_t>(B) * N3 * rs);
     b.V = L.take<double>(static_cast<size_t>(B) * N3);
     b.Vnew = L.take<double>(static_cast<size_t>(B) * N3);
     *bytes = L.off + 256;
@@ -228,16 +226,14 @@ void rhs_launch(fm_flow* h, int nf, int slot) {
         timed(h, T_DIRECT, [&] { launch_direct(h->stream, h->g, h->b, nf, ch, slot); });
         return;
     }
-    timed(h, T_BINS, [&] { launch_bins(h->stream, h->dbl, h->g, h->b, nf); });
     const int mma = h->cfg.precision == FM_FP32_BF16MFMA ? 2 : (h->cfg.precision == FM_FP32 ? 1 : 0);
     timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch, mma); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
 
-void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const double* Vbase,
-                  int kslot) {
+void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const double* Vbase) {
     timed(h, T_STAGE, [&] {
-        launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase, kslot);
+        launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase);
     });
 }
 
@@ -246,7 +242,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed,
     const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
     if (!rk45) {
         for (int s = 0; s < 4; ++s) {
-            stage_launch(h, nf, rk4_stage(s), 0, V, s);
+            stage_launch(h, nf, rk4_stage(s), 0, V);
             rhs_launch(h, nf, s);
         }
         timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->N3, V); });
@@ -254,7 +250,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed,
         return;
     }
     for (int s = 1; s < 7; ++s) {
-        stage_launch(h, nf, dp_stage(s), s == 6, V, s);
+        stage_launch(h, nf, dp_stage(s), s == 6, V);
         rhs_launch(h, nf, s);
     }
     ErrWeights ew;
@@ -457,7 +453,7 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
     }
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     StageCoef sc{};
-    stage_launch(h, batch, sc, 0, V_dev, 0);
+    stage_launch(h, batch, sc, 0, V_dev);
     rhs_launch(h, batch, 0);
     launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);
     HIPCHK(hipGetLastError());
@@ -484,7 +480,7 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     const double inf = std::numeric_limits<double>::infinity();
     if (rk45) {
-        stage_launch(h, batch, dp_stage(0), 0, V_dev, 0);
+        stage_launch(h, batch, dp_stage(0), 0, V_dev);
         rhs_launch(h, batch, 0);
     }
     step_launch(h, batch, V_dev, 0, 0.0, inf);
@@ -541,7 +537,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     HIPCHK(hipMemcpyAsync(h->b.U, U, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
     launch_fill_u(h->stream, h->b, n, h->N3, h->b.U);
     if (rk45) {
-        stage_launch(h, n, dp_stage(0), 0, h->b.V, 0);
+        stage_launch(h, n, dp_stage(0), 0, h->b.V);
         rhs_launch(h, n, 0);
     }
     HIPCHK(hipGetLastError());

@@ -115,13 +115,11 @@ struct Buffers {
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0;
-    void* pt;                          // [B][np] per-point stage quantities (16 bytes)
     void* bins;                        // [B][nRp + nRd][NN] real, representative transfers
     void* binsT;                       // [B][nRd][NN] real, particle-hole bins transposed
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
     void* v0; void* va; void* vc;      // operands [B][N^3] real
-    void* k;                           // [7][B][N^3] real
-    void* kpart;                       // [B][3][N^3] real: per-channel right-hand sides
+    void* k;                           // [7][B][3][N^3] real: per stage, flow and channel
     double* V; double* Vnew;           // [B][N^3] state, candidate
     double* part;                      // [B][nblk][2] reduction partials
     double* wtab;                      // direct mode: [B][nP+nD][np]
@@ -137,9 +135,9 @@ struct ErrWeights {
 
 // Launchers (kernels.hip).  `dbl` selects the double-precision instantiation, nf is the
 // number of flows launched; buffers are strided by b.bstride flows.
+// Stage argument and operand layouts; with bins, phase 1 of the stage in the same launch.
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
-                  int nf, const StageCoef& sc, int write_new, const double* Vbase, int kslot);
-void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf);
+                  int nf, const StageCoef& sc, int write_new, const double* Vbase);
 // mma: 0 VALU, 1 f32 matrix cores, 2 bf16 matrix cores (single precision only, N <= 128)
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
               int mma);

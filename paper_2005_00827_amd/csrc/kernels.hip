@@ -13,13 +13,15 @@
 // patches (a', b') of T d/dT chi(xi_j, xi_j'), j' = q - j (particle-particle) or j + q
 // (particle-hole).  The bins are an exact regrouping of the loop sum.
 //
-// Phase 1 (k_points, k_bins): bubble-weight derivatives on the fly for every loop point j
-//   and every representative transfer q (one per orbit of the lattice point group), summed
-//   into per-transfer bin matrices held in LDS.
-// Phase 2a (k_y): per-transfer grouped products Y_q = B_q x V-slab, four kinds.
-// Phase 2b (k_contract): the remaining contraction over one patch index per channel, all
-//   three channels fused per output element.
-// Integrator (k_stage, k_rk4_update, k_dopri_err, k_finish, k_commit): double precision.
+// Stage and phase 1 (k_stage_bins, one launch): the stage argument and its operand layouts,
+//   and in the same grid the bubble-weight derivatives, evaluated on the fly for every loop
+//   point j and every representative transfer q (one per orbit of the lattice point group),
+//   summed into per-transfer bin matrices held in LDS.
+// Phase 2a (k_y_mfma on matrix cores, k_y on vector units): per-transfer grouped products
+//   Y_q = B_q x V-slab, four kinds.
+// Phase 2b (k_contract): the remaining contraction over one patch index per channel,
+//   written straight into the stage's k slot, one part per channel.
+// Integrator (k_rk4_update, k_dopri_err, k_finish, k_commit): double precision.
 // Direct path (k_wtable, k_direct): the same sums over every loop point, no bins.
 #include <hip/hip_runtime.h>
 
@@ -104,35 +106,40 @@ __device__ inline double z_interp(const DevZ& z, int f, int N, int a, double lnT
 
 __device__ inline bool running(const FlowState* fs, int f) { return fs[f].status == FM_FLOW_RUNNING; }
 
+// k of stage l, flow f, element i.  A k slot holds the three channel right-hand sides
+// [slot][flow][pp, crossed, direct][N^3]; their sum is taken in that order.
+template <typename R>
+__device__ inline R kval(const R* K, int l, int B, int f, size_t N3, size_t i) {
+    const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3 + i;
+    R v = p[0];
+    v += p[N3];
+    v += p[2 * N3];
+    return v;
+}
+
 // ------------------------------------------------------------------------------------
 // Stage argument V_s = V + h sum_l a_l k_l (double), Z and T of the stage, operand layouts
-//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z);
-// also clears the stage's k slot and the representative bins (both accumulated later).
+//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z).
 // ------------------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_stage(DevGeom g, DevZ z, const FlowState* fs,
-                                                    StageCoef sc, int write_new,
-                                                    const double* Vbase, R* K, int kslot,
-                                                    double* Vnew, R* v0, R* va, R* vc,
-                                                    double* T_stage, double* Z_stage,
-                                                    R* bins, size_t nbins, int B) {
-    const int f = blockIdx.y;
-    if (!running(fs, f)) return;
+__device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowState& st, int f,
+                                  const StageCoef& sc, int write_new, const double* Vbase,
+                                  const R* K, double* Vnew, R* v0, R* va, R* vc,
+                                  double* T_stage, double* Z_stage, int B, int blk, int nblk) {
     const int N = g.N, NN = g.NN;
     const size_t N3 = static_cast<size_t>(NN) * N;
-    const double ht = fs[f].ht;
-    const double lnTs = fs[f].lnT + sc.c * ht;
-    if (blockIdx.x == 0) {
+    const double ht = st.ht;
+    const double lnTs = st.lnT + sc.c * ht;
+    if (blk == 0) {
         if (threadIdx.x == 0) T_stage[f] = exp(lnTs);
         for (int a = threadIdx.x; a < N; a += blockDim.x)
             Z_stage[static_cast<size_t>(f) * N + a] = z_interp(z, f, N, a, lnTs);
     }
     const double* Vf = Vbase + f * N3;
-    R* Ks = K + (static_cast<size_t>(kslot) * B + f) * N3;
-    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3; i += stride) {
+    const size_t stride = static_cast<size_t>(nblk) * blockDim.x;
+    for (size_t i = blk * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3; i += stride) {
         double acc = 0.0;
-        for (int l = 0; l < sc.ns; ++l) acc += sc.a[l] * static_cast<double>(K[(static_cast<size_t>(l) * B + f) * N3 + i]);
+        for (int l = 0; l < sc.ns; ++l) acc += sc.a[l] * static_cast<double>(kval(K, l, B, f, N3, i));
         const double v = Vf[i] + ht * acc;
         if (write_new) Vnew[f * N3 + i] = v;
         const int x = static_cast<int>(i / NN);
@@ -142,46 +149,31 @@ __global__ void __launch_bounds__(kThreads) k_stage(DevGeom g, DevZ z, const Flo
         v0[f * N3 + i] = r;
         va[f * N3 + static_cast<size_t>(zz) * NN + x * N + y] = r;
         vc[f * N3 + static_cast<size_t>(zz) * NN + y * N + x] = r;
-        Ks[i] = R(0);
-    }
-    if (bins) {
-        R* bf = bins + f * nbins;
-        for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < nbins; i += stride)
-            bf[i] = R(0);
     }
 }
 
-// Per-point quantities of the stage, with a_j = xi_j / 2T:
-//   single precision: (a, phi(a), phi'(a), phi3(a)); double precision: (a, phi(a)),
-// where phi' = s (1 - 2 a tau) and the third derivative
-//   phi3 = s (-6 (1 - 3 tau^2) + 8 a tau (2 - 3 tau^2)),  s = sech^2 a, tau = tanh a
-// (evaluated in double precision).
+// Point quantities at the stage temperature, a = xi / 2T:
+//   single precision (a, phi(a), phi'(a), phi3(a)), double precision (a, phi(a)),
+// where phi(u) = u sech^2 u, phi' = s (1 - 2 a tau) and the third derivative
+//   phi3 = s (-6 (1 - 3 tau^2) + 8 a tau (2 - 3 tau^2)),  s = sech^2 a, tau = tanh a,
+// with s and tau from e = exp(-2|a|) <= 1 (no overflow): s = 4e/(1+e)^2, |tau| = (1-e)/(1+e).
 template <typename R> struct PtT;
 template <> struct PtT<float> { using T = float4; };
 template <> struct PtT<double> { using T = double2; };
 
-template <typename R>
-__global__ void __launch_bounds__(kThreads) k_points(DevGeom g, const FlowState* fs,
-                                                     const double* T_stage,
-                                                     typename PtT<R>::T* pt) {
-    const int f = blockIdx.y;
-    if (!running(fs, f)) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= g.np) return;
-    const double a = g.xi[j] / (2.0 * T_stage[f]);
-    typename PtT<R>::T v;
-    v.x = static_cast<R>(a);
-    v.y = static_cast<R>(phi_d(a));
-    if constexpr (sizeof(R) == 4) {
-        const double e = exp(-2.0 * fabs(a));
-        const double rd = 1.0 / (1.0 + e);
-        const double sh = 4.0 * e * rd * rd;
-        const double tau = copysign((1.0 - e) * rd, a);
-        const double t2 = tau * tau, at = a * tau;
-        v.z = static_cast<R>(sh * (1.0 - 2.0 * at));
-        v.w = static_cast<R>(sh * (-6.0 * (1.0 - 3.0 * t2) + 8.0 * at * (2.0 - 3.0 * t2)));
-    }
-    pt[static_cast<size_t>(f) * g.np + j] = v;
+__device__ inline float4 point_q(double xi, double inv2T, float) {
+    const float a = static_cast<float>(xi * inv2T);
+    const float e = __expf(-2.0f * fabsf(a));
+    const float rd = __builtin_amdgcn_rcpf(1.0f + e);
+    const float sh = 4.0f * e * rd * rd;
+    const float tau = copysignf((1.0f - e) * rd, a);
+    const float t2 = tau * tau, at = a * tau;
+    return make_float4(a, a * sh, sh * (1.0f - 2.0f * at),
+                       sh * (-6.0f * (1.0f - 3.0f * t2) + 8.0f * at * (2.0f - 3.0f * t2)));
+}
+__device__ inline double2 point_q(double xi, double twoT, double) {
+    const double a = xi / twoT;
+    return make_double2(a, phi_d(a));
 }
 
 // Single-precision weight phi[a,b] without branches: away from a == b the quotient;
@@ -203,13 +195,15 @@ __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 // Phase 1: bins of the representative transfers.  One 1024-thread block per
 // (representative, flow) accumulates the N x N bin matrix in LDS and stores it scaled by
 // -1/(4 T L^2) (plus its transpose for particle-hole representatives, which the crossed
-// channel reads).
+// channel reads).  Point quantities are evaluated on the fly from xi.
 //
 // Lane layout: the 16 lanes of a DPP row take 16 consecutive loop points, so every load
-// (own point, partner, both patches) is a contiguous segment.  Consecutive points mostly
+// (own xi, partner xi, both patches) is a contiguous segment.  Consecutive points mostly
 // share their patch pair, so a segmented scan over the row (DPP shifts 1, 2, 4, 8) sums
-// each run of equal keys and only the last lane of a run issues the LDS atomic.  The four
+// each run of equal keys and only the last lane of a run issues the atomic.  The four
 // rows of a wave work in bands a quarter of the grid apart, so their keys rarely collide.
+//   kMode 0: bins in LDS; kMode 1 (bin matrix above 64 KB): the block accumulates its own
+//   representative's bins in global memory with atomics, after clearing them.
 // ------------------------------------------------------------------------------------
 constexpr int kBinThreads = 1024;
 constexpr int kBinBatch = 4;   // 16-point units per row with loads in flight together
@@ -241,28 +235,21 @@ __device__ inline void seg_step(R& v, int& h, int s) {
 }
 
 template <typename R, int kMode>
-__global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState* fs,
-                                                      const double* T_stage,
-                                                      const typename PtT<R>::T* pt, R* bins,
-                                                      R* binsT) {
+__device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bins, R* binsT,
+                                 R* lb) {
     using PT = typename PtT<R>::T;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int f = blockIdx.y;
-    if (!running(fs, f)) return;                      // uniform over the block
-    const int r = blockIdx.x;
     const int N = g.N, NN = g.NN, L = g.L, np = g.np;
     const int nR = g.nRp + g.nRd;
     const bool pp = r < g.nRp;
     const int m = pp ? g.rep_pp[r] : g.rep_ph[r - g.nRp];
     const int mx = m % L, my = m / L;
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
-    const R scale = static_cast<R>(-1.0 / (4.0 * T_stage[f] * np));
-    R* lb = reinterpret_cast<R*>(smem_raw);
-    const PT* P = pt + static_cast<size_t>(f) * np;
-    if (kMode == 0)
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) lb[i] = R(0);
-    __syncthreads();                                   // every thread of the block
+    const R scale = static_cast<R>(-1.0 / (4.0 * T * np));
+    const double tp = sizeof(R) == 4 ? 1.0 / (2.0 * T) : 2.0 * T;   // 1/2T (float) or 2T
     R* acc = kMode == 0 ? lb : out;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) acc[i] = R(0);
+    if (kMode == 1) __threadfence();
+    __syncthreads();                                   // every thread of the block
     // 64 rows of 16 lanes per block; row rr works on band rr of 64 contiguous bands of units
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = lane & 15;
@@ -272,7 +259,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
     const int u_begin = band * per_band;
     const int u_end = min(u_begin + per_band, nunits);
     for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
-        PT u[kBinBatch], v[kBinBatch];
+        double xu[kBinBatch], xv[kBinBatch];
         int pa[kBinBatch], pq[kBinBatch];
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
@@ -283,8 +270,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
             px += px < 0 ? L : (px >= L ? -L : 0);
             py += py < 0 ? L : (py >= L ? -L : 0);
             const int jp = py * L + px;
-            u[i] = P[j];
-            v[i] = P[jp];
+            xu[i] = g.xi[j];
+            xv[i] = g.xi[jp];
             pa[i] = g.patch[j];
             pq[i] = g.patch[jp];
         }
@@ -292,7 +279,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
         for (int i = 0; i < kBinBatch; ++i) {
             const int j = (u0 + i) * 16 + s;
             const bool ok = u0 + i < u_end && j < np;
-            const R w = phi_dd_pt(u[i], pp ? flip(v[i]) : v[i]);
+            const PT pu = point_q(xu[i], tp, R(0));
+            const PT pv = point_q(xv[i], tp, R(0));
+            const R w = phi_dd_pt(pu, pp ? flip(pv) : pv);
             R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
             const int key = pa[i] * N + pq[i];
             const int kprev = dpp_i<0x111>(key);   // row_shr:1
@@ -305,6 +294,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
             if (s == 15 || knext != key) atomicAdd(&acc[key], x);
         }
     }
+    if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
     R* outT = pp ? nullptr : binsT + (static_cast<size_t>(f) * g.nRd + (r - g.nRp)) * NN;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
@@ -315,6 +305,29 @@ __global__ void __launch_bounds__(kBinThreads) k_bins(DevGeom g, const FlowState
         } else if (outT) {
             outT[i] = out[aa * N + bb];
         }
+    }
+}
+
+// One launch per stage: blocks [0, nRb) bin the representatives (phase 1, which needs only
+// T), the remaining blocks form the stage argument and its operand layouts.  Grid (nRb +
+// stage blocks, flows).
+template <typename R, int kMode>
+__global__ void __launch_bounds__(kBinThreads) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
+                                                            StageCoef sc, int write_new,
+                                                            const double* Vbase, const R* K,
+                                                            double* Vnew, R* v0, R* va, R* vc,
+                                                            double* T_stage, double* Z_stage,
+                                                            R* bins, R* binsT, int nRb, int B) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int f = blockIdx.y;
+    if (!running(fs, f)) return;                      // uniform over the block
+    const FlowState st = fs[f];
+    if (static_cast<int>(blockIdx.x) < nRb) {
+        const double T = exp(st.lnT + sc.c * st.ht);
+        bins_part<R, kMode>(g, f, blockIdx.x, T, bins, binsT, reinterpret_cast<R*>(smem_raw));
+    } else {
+        stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
+                      B, blockIdx.x - nRb, gridDim.x - nRb);
     }
 }
 
@@ -696,48 +709,43 @@ __device__ __attribute__((always_inline)) inline void contract_item(
 template <typename R>
 __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
                                                  const R* v0, const R* y1, const R* y2,
-                                                 const R* y3, const R* y4, R* K, unsigned ch) {
+                                                 const R* y3, const R* y4, R* K, unsigned ch,
+                                                 int slot, int B) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const int it = blockIdx.x;
     const int kind = it < g.n_items[0] ? 0 : (it < g.n_items[0] + g.n_items[1] ? 1 : 2);
-    if (kind == 0 && !(ch & FM_CH_PP)) return;
-    if (kind == 1 && !(ch & FM_CH_CR)) return;
-    if (kind == 2 && !(ch & FM_CH_D)) return;
     const int q = g.item_q[it];
     const int p0 = g.item_p0[it];
     const int nq = kind == 0 ? g.nP : g.nD;
     const int* off = kind == 0 ? g.pp_off : (kind == 1 ? g.cr_off : g.d_off);
     const int* pairs = kind == 0 ? g.pp_pairs : (kind == 1 ? g.cr_pairs : g.d_pairs);
     const int cnt = min(kChunk, off[q + 1] - p0);
-    const size_t N3 = static_cast<size_t>(g.NN) * g.N;
+    const int N = g.N, NN = g.NN;
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    // k slot part of this channel: [slot][flow][channel][N^3]
+    R* Kf = K + ((static_cast<size_t>(slot) * B + f) * 3 + kind) * N3;
+    const unsigned bit = kind == 0 ? FM_CH_PP : (kind == 1 ? FM_CH_CR : FM_CH_D);
+    if (!(ch & bit)) {   // a channel that is switched off contributes zero
+        for (int e = threadIdx.x; e < cnt * N; e += blockDim.x) {
+            const int i = e / N, n = e - i * N;
+            const int xy = pairs[p0 + i];
+            const int a = xy / N, c = xy - a * N;
+            if (kind == 0) Kf[static_cast<size_t>(xy) * N + n] = R(0);
+            else if (kind == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = R(0);
+            else Kf[static_cast<size_t>(a) * NN + n * N + c] = R(0);
+        }
+        return;
+    }
     const R* V = v0 + f * N3;
-    const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * g.NN;
-    const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * g.NN;
-    R* Kf = K + 3 * f * N3 + static_cast<size_t>(kind) * N3;   // [f][channel][N^3]
+    const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
+    const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
     R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
-    R* vw = vu + kChunk * g.N;                          // [N][kChunk] (direct only)
+    R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
     if (kind == 0) contract_item<R, 0>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
     else if (kind == 1) contract_item<R, 1>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
     else contract_item<R, 2>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
-}
-
-// k = k_pp + k_cr + k_d (channels that are masked off contribute zero).
-template <typename R>
-__global__ void __launch_bounds__(kThreads) k_combine(const FlowState* fs, const R* part, R* K,
-                                                      size_t N3, unsigned ch) {
-    const int f = blockIdx.y;
-    if (!running(fs, f)) return;
-    const R* p = part + 3 * f * N3;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        R v = R(0);
-        if (ch & FM_CH_PP) v += p[i];
-        if (ch & FM_CH_CR) v += p[N3 + i];
-        if (ch & FM_CH_D) v += p[2 * N3 + i];
-        K[f * N3 + i] = v;
-    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -799,7 +807,10 @@ __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState*
                            + vajc * V[static_cast<size_t>(b) * NN + pq * N + pj]);
         }
     }
-    K[f * N3 + static_cast<size_t>(a) * NN + b * N + c] = -s1 + s2 + s3;
+    const size_t o = f * 3 * N3 + static_cast<size_t>(a) * NN + b * N + c;   // slot parts
+    K[o] = -s1;
+    K[o + N3] = s2;
+    K[o + 2 * N3] = s3;
 }
 
 // ------------------------------------------------------------------------------------
@@ -812,7 +823,7 @@ __global__ void __launch_bounds__(kThreads) k_to_f64(const FlowState* fs, const 
     if (!running(fs, f)) return;
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
          i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        out[f * N3 + i] = static_cast<double>(K[f * N3 + i]);
+        out[f * N3 + i] = static_cast<double>(kval(K, 0, 0, f, N3, i));
 }
 
 __global__ void __launch_bounds__(kThreads) k_fill_u(double* V, const double* U, size_t N3) {
@@ -850,10 +861,10 @@ __global__ void __launch_bounds__(kThreads) k_rk4_update(const FlowState* fs, co
     double mx = 0.0;
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
          i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const double k0 = K[(0 * static_cast<size_t>(B) + f) * N3 + i];
-        const double k1 = K[(1 * static_cast<size_t>(B) + f) * N3 + i];
-        const double k2 = K[(2 * static_cast<size_t>(B) + f) * N3 + i];
-        const double k3 = K[(3 * static_cast<size_t>(B) + f) * N3 + i];
+        const double k0 = kval(K, 0, B, f, N3, i);
+        const double k1 = kval(K, 1, B, f, N3, i);
+        const double k2 = kval(K, 2, B, f, N3, i);
+        const double k3 = kval(K, 3, B, f, N3, i);
         const double v = V[f * N3 + i] + h / 6.0 * (k0 + 2.0 * k1 + 2.0 * k2 + k3);
         V[f * N3 + i] = v;
         mx = fmax(mx, isfinite(v) ? fabs(v) : INFINITY);
@@ -881,7 +892,7 @@ __global__ void __launch_bounds__(kThreads) k_dopri_err(const FlowState* fs, con
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
          i += static_cast<size_t>(gridDim.x) * blockDim.x) {
         double e = 0.0;
-        for (int l = 0; l < 7; ++l) e += ew.e[l] * static_cast<double>(K[(static_cast<size_t>(l) * B + f) * N3 + i]);
+        for (int l = 0; l < 7; ++l) e += ew.e[l] * static_cast<double>(kval(K, l, B, f, N3, i));
         e = fabs(h * e);
         const double vn = Vnew[f * N3 + i];
         const double sc = at + rtol * fmax(fabs(V[f * N3 + i]), fabs(vn));
@@ -970,16 +981,21 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
     fs[f] = st;
 }
 
-// After an accepted Dormand-Prince step: V = Vnew and k0 = k6 (first same as last).
+// After an accepted Dormand-Prince step: V = Vnew and k0 = k6 (first same as last), all
+// three channel parts.
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_commit(const FlowState* fs, double* V,
                                                      const double* Vnew, R* K, size_t N3, int B) {
     const int f = blockIdx.y;
     if (!fs[f].accepted) return;
+    R* k0 = K + static_cast<size_t>(f) * 3 * N3;
+    const R* k6 = K + (6 * static_cast<size_t>(B) + f) * 3 * N3;
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
          i += static_cast<size_t>(gridDim.x) * blockDim.x) {
         V[f * N3 + i] = Vnew[f * N3 + i];
-        K[static_cast<size_t>(f) * N3 + i] = K[(6 * static_cast<size_t>(B) + f) * N3 + i];
+        k0[i] = k6[i];
+        k0[N3 + i] = k6[N3 + i];
+        k0[2 * N3 + i] = k6[2 * N3 + i];
     }
 }
 
@@ -1006,8 +1022,8 @@ inline dim3 grid_for(size_t n, int nf, int cap = 2048) {
 }
 
 template <typename R>
-R* kslot_ptr(const Buffers& b, int slot, size_t N3) {
-    return static_cast<R*>(b.k) + static_cast<size_t>(slot) * b.bstride * N3;
+R* kslot_ptr(const Buffers& b, int slot, size_t N3) {   // slot base: [flow][channel][N^3]
+    return static_cast<R*>(b.k) + static_cast<size_t>(slot) * b.bstride * 3 * N3;
 }
 
 template <typename R>
@@ -1015,36 +1031,29 @@ int bins_mode(const DevGeom& g) {
     return static_cast<size_t>(g.NN) * sizeof(R) <= 65536 ? 0 : 1;
 }
 
+// Stage argument plus, when bins exist, phase 1 of the same stage in one launch.
 template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
-             const StageCoef& sc, int write_new, const double* Vbase, int kslot) {
+             const StageCoef& sc, int write_new, const double* Vbase) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
-    // bins are cleared only where phase 1 accumulates them with global atomics
-    const bool zero_bins = b.bins && bins_mode<R>(g) == 1;
-    const size_t nbins = static_cast<size_t>(g.nRp + g.nRd) * g.NN;
-    hipLaunchKernelGGL(k_stage<R>, grid_for(N3, nf), dim3(kThreads), 0, s, g, z, b.fs, sc,
-                       write_new, Vbase, static_cast<R*>(b.k), kslot, b.Vnew,
-                       static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
-                       b.T_stage, b.Z_stage, zero_bins ? static_cast<R*>(b.bins) : nullptr,
-                       zero_bins ? nbins : 0, b.bstride);
-}
-
-template <typename R>
-void bins_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {
-    using PT = typename PtT<R>::T;
-    hipLaunchKernelGGL(k_points<R>, dim3((g.np + kThreads - 1) / kThreads, nf), dim3(kThreads),
-                       0, s, g, b.fs, b.T_stage, static_cast<PT*>(b.pt));
-    const dim3 grid(g.nRp + g.nRd, nf);
-    const PT* pt = static_cast<const PT*>(b.pt);
+    const int nRb = b.bins ? g.nRp + g.nRd : 0;
+    size_t ns = (N3 + kBinThreads - 1) / kBinThreads;
+    ns = ns > 512 ? 512 : ns;
+    const dim3 grid(static_cast<unsigned>(nRb + ns), nf);
+    const bool lds = nRb > 0 && bins_mode<R>(g) == 0;
+    const size_t shm = lds ? static_cast<size_t>(g.NN) * sizeof(R) : 0;
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
-    if (bins_mode<R>(g) == 0)
-        hipLaunchKernelGGL((k_bins<R, 0>), grid, dim3(kBinThreads),
-                           static_cast<size_t>(g.NN) * sizeof(R), s, g, b.fs, b.T_stage, pt,
-                           bins, binsT);
+    if (nRb == 0 || lds)
+        hipLaunchKernelGGL((k_stage_bins<R, 0>), grid, dim3(kBinThreads), shm, s, g, z, b.fs, sc,
+                           write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+                           static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
+                           b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
     else
-        hipLaunchKernelGGL((k_bins<R, 1>), grid, dim3(kBinThreads), 0, s, g, b.fs, b.T_stage,
-                           pt, bins, binsT);
+        hipLaunchKernelGGL((k_stage_bins<R, 1>), grid, dim3(kBinThreads), 0, s, g, z, b.fs, sc,
+                           write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+                           static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
+                           b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
@@ -1111,28 +1120,20 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
 
 template <typename R>
 void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
-    const size_t N3 = static_cast<size_t>(g.NN) * g.N;
     const size_t lds = 2 * static_cast<size_t>(kChunk) * g.N * sizeof(R);
     const int items = g.n_items[0] + g.n_items[1] + g.n_items[2];
     hipLaunchKernelGGL(k_contract<R>, dim3(items, nf), dim3(64), lds, s, g, b.fs,
                        static_cast<const R*>(b.v0), static_cast<const R*>(b.y1),
                        static_cast<const R*>(b.y2), static_cast<const R*>(b.y3),
-                       static_cast<const R*>(b.y4), static_cast<R*>(b.kpart), ch);
-    hipLaunchKernelGGL(k_combine<R>, grid_for(N3, nf), dim3(kThreads), 0, s, b.fs,
-                       static_cast<const R*>(b.kpart), kslot_ptr<R>(b, slot, N3), N3, ch);
+                       static_cast<const R*>(b.y4), static_cast<R*>(b.k), ch, slot, b.bstride);
 }
 
 }  // namespace
 
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
-                  int nf, const StageCoef& sc, int write_new, const double* Vbase, int kslot) {
-    if (dbl) stage_t<double>(s, g, z, b, nf, sc, write_new, Vbase, kslot);
-    else stage_t<float>(s, g, z, b, nf, sc, write_new, Vbase, kslot);
-}
-
-void launch_bins(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf) {
-    if (dbl) bins_t<double>(s, g, b, nf);
-    else bins_t<float>(s, g, b, nf);
+                  int nf, const StageCoef& sc, int write_new, const double* Vbase) {
+    if (dbl) stage_t<double>(s, g, z, b, nf, sc, write_new, Vbase);
+    else stage_t<float>(s, g, z, b, nf, sc, write_new, Vbase);
 }
 
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
