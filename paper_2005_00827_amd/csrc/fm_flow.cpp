@@ -8,7 +8,10 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "fm_internal.h"
@@ -90,6 +93,10 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.v_max <= 0.0) c.v_max = 20.0;
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
+    if (c.tile_rows != 0 && c.tile_rows != 1 && c.tile_rows != 2 && c.tile_rows != 4) {
+        why = "tile_rows must be 0, 1, 2 or 4";
+        return FM_EINVAL;
+    }
     return FM_OK;
 }
 
@@ -107,6 +114,8 @@ struct fm_flow {
     size_t N3 = 0;
     std::vector<double> zlnT, ztab;    // configured table (host copy)
     std::vector<FlowState> hfs;
+    // phase-2a row tiles per wavefront (cfg.tile_rows, or tuned for tuned_nf flows)
+    int tpw = 0, tuned_nf = -1;
     // graphs of one integrator step, keyed by the number of flows captured
     hipGraphExec_t step_exec = nullptr;
     int step_nf = -1;
@@ -227,7 +236,7 @@ void rhs_launch(fm_flow* h, int nf, int slot) {
         return;
     }
     const int mma = h->cfg.precision == FM_FP32_BF16MFMA ? 2 : (h->cfg.precision == FM_FP32 ? 1 : 0);
-    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch, mma); });
+    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch, mma, h->tpw); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
 
@@ -235,6 +244,55 @@ void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const 
     timed(h, T_STAGE, [&] {
         launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase);
     });
+}
+
+// Phase-2a tile choice: cfg.tile_rows when set, else the fastest of 1, 2 and 4 row tiles per
+// wavefront, timed with events on the operands of a stage at the flows' current state.
+// Every later stage recomputes these products, so the timing runs change no result.
+// Choices are kept for the process, per shape and number of flows.
+using TuneKey = std::tuple<int, int, int, int, int, double, double, double>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
+    const fm_config& c = h->cfg;
+    const int mma = c.precision == FM_FP32_BF16MFMA ? 2 : (c.precision == FM_FP32 ? 1 : 0);
+    if (h->dbl || h->direct || mma == 0 || c.N > 128) return FM_OK;
+    if (c.tile_rows > 0) { h->tpw = c.tile_rows; return FM_OK; }
+    if (h->tuned_nf == nf) return FM_OK;
+    const TuneKey key{c.N, c.L, c.precision, nf, c.geometry, c.t, c.tp, c.mu};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) { h->tpw = it->second; h->tuned_nf = nf; return FM_OK; }
+    }
+    StageCoef sc{};
+    launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, 0, Vbase);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = 1;
+    float best_ms = std::numeric_limits<float>::infinity();
+    for (int tpw : {1, 2, 4}) {
+        launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, tpw);
+        (void)hipEventRecord(e0, h->stream);
+        for (int r = 0; r < 5; ++r) launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, tpw);
+        (void)hipEventRecord(e1, h->stream);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ms < best_ms) {
+            best_ms = ms;
+            best = tpw;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    h->tpw = best;
+    h->tuned_nf = nf;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return FM_OK;
 }
 
 // One integrator step of every running flow (no host interaction).  V is the state array.
@@ -452,6 +510,7 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
         h->hfs[f] = s;
     }
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
     StageCoef sc{};
     stage_launch(h, batch, sc, 0, V_dev);
     rhs_launch(h, batch, 0);
@@ -478,6 +537,7 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
         h->hfs[f] = s;
     }
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
     const double inf = std::numeric_limits<double>::infinity();
     if (rk45) {
         stage_launch(h, batch, dp_stage(0), 0, V_dev);
@@ -536,6 +596,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * n, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->b.U, U, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
     launch_fill_u(h->stream, h->b, n, h->N3, h->b.U);
+    if (int rc = ensure_tuned(h, n, h->b.V)) return rc;
     if (rk45) {
         stage_launch(h, n, dp_stage(0), 0, h->b.V);
         rhs_launch(h, n, 0);

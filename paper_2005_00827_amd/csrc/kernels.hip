@@ -467,24 +467,34 @@ __device__ inline int mfma_k(int e, int lane) {
     return kBF16 ? 32 * (e >> 3) + 8 * (lane >> 4) + (e & 7) : 4 * e + (lane >> 4);
 }
 
+// LDS row stride of a B chunk of W = 16 NT columns: a fragment read touches rows k..k+3
+// (16 consecutive columns each); a stride of 16 mod 32 words spreads them over the banks.
+template <int NT>
+constexpr int b_stride() { return (16 * NT) % 32 == 16 ? 16 * NT : 16 * NT + 16; }
+
+// One 16-row tile on the matrix cores: c0 += A B0 (and c1 += A B1 for the direct channel),
+// B fragments read from LDS (Bs0/Bs1: [4 KE][b_stride] floats, zero beyond N).
 template <bool kBF16, int KE, int NT, bool kTwo>
-__device__ inline void mfma_tile(const float (&a)[KE], const float (&b0)[NT][KE],
-                                 const float (&b1)[NT][KE], fm_f4 (&c0)[NT], fm_f4 (&c1)[NT]) {
+__device__ inline void mfma_tile(const float (&a)[KE], const float* Bs0, const float* Bs1,
+                                 fm_f4 (&c0)[NT], fm_f4 (&c1)[NT], int lane) {
+    constexpr int S = b_stride<NT>();
+    const int col = lane & 15;
     if constexpr (kBF16) {
 #pragma unroll
         for (int s = 0; s < KE / 8; ++s) {
             fm_bf8 av;
 #pragma unroll
             for (int e = 0; e < 8; ++e) av[e] = static_cast<__bf16>(a[8 * s + e]);
+            const int kb = 32 * s + 8 * (lane >> 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 fm_bf8 bv;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(b0[t][8 * s + e]);
+                for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(Bs0[(kb + e) * S + 16 * t + col]);
                 c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c0[t], 0, 0, 0);
                 if constexpr (kTwo) {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(b1[t][8 * s + e]);
+                    for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(Bs1[(kb + e) * S + 16 * t + col]);
                     c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c1[t], 0, 0, 0);
                 }
             }
@@ -492,114 +502,136 @@ __device__ inline void mfma_tile(const float (&a)[KE], const float (&b0)[NT][KE]
     } else {
 #pragma unroll
         for (int e = 0; e < KE; ++e) {
+            const int k = 4 * e + (lane >> 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b0[t][e], c0[t], 0, 0, 0);
+                c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], Bs0[k * S + 16 * t + col], c0[t], 0, 0, 0);
                 if constexpr (kTwo)
-                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b1[t][e], c1[t], 0, 0, 0);
+                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], Bs1[k * S + 16 * t + col], c1[t], 0, 0, 0);
             }
         }
     }
 }
 
-template <bool kBF16, int KE, int NT, bool kTwo>
-__device__ inline void y_wave(int N, int NN, int M, int grp, int n0, int t_begin, int t_end,
-                              const float* Bf, const int* qrep, const int* qg, const int* pis,
-                              const float* zs, const float* V0, const float* V1, float* Y0,
-                              float* Y1) {
-    const int lane = threadIdx.x & 63;
-    const int col = lane & 15;
-    float b0[NT][KE], b1[NT][KE];
+// A operand of one row tile: lane row q = 16 tile + lane % 16 (rep r, operation o), k-values
+// of the lane: A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k), zero for k >= N.
+template <bool kBF16, int KE>
+__device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, int grp,
+                                int rep, int op, const int* pis, const float* zs, float zg,
+                                int lane) {
+    const int* pi = pis + op * N;
+    const float* row = Bf + static_cast<size_t>(rep) * NN + pi[grp] * N;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int n = n0 + 16 * t + col;
-#pragma unroll
-        for (int e = 0; e < KE; ++e) {
-            const int k = mfma_k<kBF16>(e, lane);
-            const size_t ia = static_cast<size_t>(min(k, N - 1)) * N + min(n, N - 1);
-            const bool ok = k < N && n < N;
-            const float x0 = V0[ia];
-            b0[t][e] = ok ? x0 : 0.f;
-            if constexpr (kTwo) {
-                const float x1 = V1[ia];
-                b1[t][e] = ok ? x1 : 0.f;
-            }
-        }
+    for (int e = 0; e < KE; ++e) {
+        const int k = mfma_k<kBF16>(e, lane);
+        const int kc = min(k, N - 1);
+        const float x = row[pi[kc]];
+        a[e] = k < N ? x * (zg * zs[kc]) : 0.f;
     }
+}
+
+template <bool kBF16, int KE, int NT, bool kTwo, int TPW>
+__device__ inline void y_tiles(const float* Bf, int NN, int N, int M, int grp, int n0,
+                               int t_begin, int ntiles, const int (&rep)[TPW],
+                               const int (&op)[TPW], const int* pis, const float* zs,
+                               const float* Bs0, const float* Bs1, float* Y0, float* Y1,
+                               int lane) {
+    const int col = lane & 15;
     const float zg = zs[grp];
-    for (int tile = t_begin; tile < t_end; ++tile) {
-        const int q = min(tile * 16 + col, M - 1);
-        const int rep = qrep[q];
-        const int* pi = pis + qg[q] * N;
-        const float* row = Bf + static_cast<size_t>(rep) * NN + pi[grp] * N;
-        float a[KE];
+    float a[2][KE];
+    gather_a<kBF16, KE>(a[0], Bf, NN, N, grp, rep[0], op[0], pis, zs, zg, lane);
 #pragma unroll
-        for (int e = 0; e < KE; ++e) {
-            const int k = mfma_k<kBF16>(e, lane);
-            const int kc = min(k, N - 1);
-            const float x = row[pi[kc]];
-            a[e] = k < N ? x * (zg * zs[kc]) : 0.f;
-        }
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = t_begin + t;
+        if (tile >= ntiles) break;                     // uniform over the wave
+        if (t + 1 < TPW && tile + 1 < ntiles)
+            gather_a<kBF16, KE>(a[(t + 1) & 1], Bf, NN, N, grp, rep[t + 1], op[t + 1], pis, zs,
+                                zg, lane);
         fm_f4 c0[NT], c1[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) c0[t] = c1[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
-        mfma_tile<kBF16, KE, NT, kTwo>(a, b0, b1, c0, c1);
+        for (int u = 0; u < NT; ++u) c0[u] = c1[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+        mfma_tile<kBF16, KE, NT, kTwo>(a[t & 1], Bs0, Bs1, c0, c1, lane);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int n = n0 + 16 * t + col;
+        for (int u = 0; u < NT; ++u) {
+            const int n = n0 + 16 * u + col;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int qq = tile * 16 + 4 * (lane >> 4) + r;
                 if (qq < M && n < N) {
                     const size_t o = static_cast<size_t>(qq) * NN + grp * N + n;
-                    Y0[o] = c0[t][r];
-                    if constexpr (kTwo) Y1[o] = c1[t][r];
+                    Y0[o] = c0[u][r];
+                    if constexpr (kTwo) Y1[o] = c1[u][r];
                 }
             }
         }
     }
 }
 
-// Grid: x = blocks of 4 waves over row-tile runs, y = group * nchunk + column chunk,
-// z = 3 * flow + channel (0 pp -> Y1, 1 crossed -> Y2, 2 direct -> Y3 and Y4).
-template <bool kBF16, int KE, int NT>
+// Grid: x = blocks of 4 waves, each wave TPW consecutive row tiles; y = group * nchunk +
+// column chunk; z = 3 * flow + channel (0 pp -> Y1, 1 crossed -> Y2, 2 direct -> Y3, Y4).
+// The block stages its B chunk(s) in LDS once; every wave gathers its tiles' A operands
+// straight into MFMA layout, the next tile's gather in flight during the current tile.
+template <bool kBF16, int KE, int NT, int TPW>
 __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
                                                      const double* Z_stage, const float* bins,
                                                      const float* binsT, YArgs<float> args,
-                                                     int tiles_per_wave, int nchunk) {
+                                                     int nchunk) {
+    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT;
     __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
     __shared__ float zs[128];                         // Z of the stage
+    __shared__ __align__(16) float Bs[2][KP * S];     // B chunks [k][n]
     const int ch = blockIdx.z % 3;
     const int f = blockIdx.z / 3;
-    if (!running(fs, f) || !args.on[ch == 2 ? 2 : ch]) return;
+    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
     const int N = g.N, NN = g.NN;
     const int M = ch == 0 ? g.nP : g.nD;
     const int grp = blockIdx.y / nchunk;
-    const int n0 = (blockIdx.y - grp * nchunk) * 16 * NT;
+    const int n0 = (blockIdx.y - grp * nchunk) * W;
     const int ntiles = (M + 15) / 16;
-    const int wv = threadIdx.x >> 6;
-    const int t_begin = (blockIdx.x * 4 + wv) * tiles_per_wave;
-    const int t_end = min(t_begin + tiles_per_wave, ntiles);
-    for (int i = threadIdx.x; i < 8 * N; i += blockDim.x) pis[i] = g.pinv[i];
-    const double* Zf = Z_stage + static_cast<size_t>(f) * N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) zs[i] = static_cast<float>(Zf[i]);
-    __syncthreads();                                   // every thread of the block
-    if (t_begin >= t_end) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15;
+    const int t_begin = (blockIdx.x * 4 + wv) * TPW;
+    const bool two = ch == 2;
+    const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
+    const int* qg = ch == 0 ? g.qg_pp : g.qg_ph;
+    int rep[TPW], op[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int q = min((t_begin + t) * 16 + col, M - 1);
+        rep[t] = qrep[q];
+        op[t] = qg[q];
+    }
+    for (int i = threadIdx.x; i < 8 * N; i += kThreads) pis[i] = g.pinv[i];
+    if (threadIdx.x < N) zs[threadIdx.x] = static_cast<float>(Z_stage[static_cast<size_t>(f) * N + threadIdx.x]);
     const size_t N3 = static_cast<size_t>(NN) * N;
+    const size_t slab = f * N3 + static_cast<size_t>(grp) * NN;
+    const float* V0 = args.Vs[two ? 2 : ch] + slab;
+    const float* V1 = args.Vs[3] + slab;
+    for (int e = threadIdx.x; e < KP * W; e += kThreads) {
+        const int k = e / W, n = e - k * W;            // W is a compile-time constant
+        const bool ok = k < N && n0 + n < N;
+        const size_t ia = static_cast<size_t>(min(k, N - 1)) * N + min(n0 + n, N - 1);
+        const float x0 = V0[ia];
+        Bs[0][k * S + n] = ok ? x0 : 0.f;
+        if (two) {
+            const float x1 = V1[ia];
+            Bs[1][k * S + n] = ok ? x1 : 0.f;
+        }
+    }
+    __syncthreads();                                   // every thread of the block
+    if (t_begin >= ntiles) return;
     const int nR = g.nRp + g.nRd;
     const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
                               : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
-    const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
-    const int* qg = ch == 0 ? g.qg_pp : g.qg_ph;
-    const size_t slab = f * N3 + static_cast<size_t>(grp) * NN;
     const size_t yoff = static_cast<size_t>(f) * M * NN;
-    if (ch == 2)
-        y_wave<kBF16, KE, NT, true>(N, NN, M, grp, n0, t_begin, t_end, Bf, qrep, qg, pis, zs,
-                                    args.Vs[2] + slab, args.Vs[3] + slab, args.Y[2] + yoff,
-                                    args.Y[3] + yoff);
+    if (two)
+        y_tiles<kBF16, KE, NT, true, TPW>(Bf, NN, N, M, grp, n0, t_begin, ntiles, rep, op, pis,
+                                          zs, Bs[0], Bs[1], args.Y[2] + yoff, args.Y[3] + yoff,
+                                          lane);
     else
-        y_wave<kBF16, KE, NT, false>(N, NN, M, grp, n0, t_begin, t_end, Bf, qrep, qg, pis, zs,
-                                     args.Vs[ch] + slab, nullptr, args.Y[ch] + yoff, nullptr);
+        y_tiles<kBF16, KE, NT, false, TPW>(Bf, NN, N, M, grp, n0, t_begin, ntiles, rep, op,
+                                           pis, zs, Bs[0], Bs[1], args.Y[ch] + yoff, nullptr,
+                                           lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1057,45 +1089,57 @@ void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, i
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
-// tiles per wave) and a run of row tiles per wave sized for about 4096 waves.
-template <bool kBF16, int KE, int NT>
+// tiles per wave); TPW row tiles per wave is a tuning choice (tuned_tpw, 0 = by size).
+template <bool kBF16, int KE, int NT, int TPW>
 void y_mfma_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                const YArgs<float>& a) {
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     const int ntiles = (mmax + 15) / 16;
     const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
-    const long waves1 = static_cast<long>(ntiles) * g.N * nchunk * 3 * nf;
-    int tpw = static_cast<int>((waves1 + 4095) / 4096);
-    tpw = tpw < 1 ? 1 : (tpw > 8 ? 8 : tpw);
-    const int bx = (ntiles + 4 * tpw - 1) / (4 * tpw);
+    const int bx = (ntiles + 4 * TPW - 1) / (4 * TPW);
     const dim3 grid(bx, g.N * nchunk, 3 * nf);
-    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT>), grid, dim3(kThreads), 0, s, g, b.fs, b.Z_stage,
-                       static_cast<const float*>(b.bins), static_cast<const float*>(b.binsT), a,
-                       tpw, nchunk);
+    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT, TPW>), grid, dim3(kThreads), 0, s, g, b.fs,
+                       b.Z_stage, static_cast<const float*>(b.bins),
+                       static_cast<const float*>(b.binsT), a, nchunk);
+}
+
+template <bool kBF16, int KE, int NT>
+void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+                const YArgs<float>& a, int tpw) {
+    if (tpw <= 0) {   // about 4096 waves
+        const int mmax = g.nP > g.nD ? g.nP : g.nD;
+        const long w1 = static_cast<long>((mmax + 15) / 16) * g.N *
+                        ((g.N + 16 * NT - 1) / (16 * NT)) * 3 * nf;
+        tpw = w1 <= 4096 ? 1 : (w1 <= 8192 ? 2 : 4);
+    }
+    if (tpw == 1) y_mfma_go<kBF16, KE, NT, 1>(s, g, b, nf, a);
+    else if (tpw == 2) y_mfma_go<kBF16, KE, NT, 2>(s, g, b, nf, a);
+    else y_mfma_go<kBF16, KE, NT, 4>(s, g, b, nf, a);
 }
 
 inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
-                          const YArgs<float>& a, bool bf16) {
+                          const YArgs<float>& a, bool bf16, int tpw) {
     const int N = g.N;
     if (bf16) {
-        if (N <= 16) y_mfma_go<true, 8, 1>(s, g, b, nf, a);
-        else if (N <= 32) y_mfma_go<true, 8, 2>(s, g, b, nf, a);
-        else if (N <= 48) y_mfma_go<true, 16, 3>(s, g, b, nf, a);
-        else if (N <= 64) y_mfma_go<true, 16, 2>(s, g, b, nf, a);
-        else if (N <= 96) y_mfma_go<true, 24, 2>(s, g, b, nf, a);
-        else y_mfma_go<true, 32, 2>(s, g, b, nf, a);
+        if (N <= 16) y_mfma_tpw<true, 8, 1>(s, g, b, nf, a, tpw);
+        else if (N <= 32) y_mfma_tpw<true, 8, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 48) y_mfma_tpw<true, 16, 3>(s, g, b, nf, a, tpw);
+        else if (N <= 64) y_mfma_tpw<true, 16, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 96) y_mfma_tpw<true, 24, 2>(s, g, b, nf, a, tpw);
+        else y_mfma_tpw<true, 32, 2>(s, g, b, nf, a, tpw);
     } else {
-        if (N <= 16) y_mfma_go<false, 4, 1>(s, g, b, nf, a);
-        else if (N <= 32) y_mfma_go<false, 8, 2>(s, g, b, nf, a);
-        else if (N <= 48) y_mfma_go<false, 12, 3>(s, g, b, nf, a);
-        else if (N <= 64) y_mfma_go<false, 16, 2>(s, g, b, nf, a);
-        else if (N <= 96) y_mfma_go<false, 24, 2>(s, g, b, nf, a);
-        else y_mfma_go<false, 32, 2>(s, g, b, nf, a);
+        if (N <= 16) y_mfma_tpw<false, 4, 1>(s, g, b, nf, a, tpw);
+        else if (N <= 32) y_mfma_tpw<false, 8, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 48) y_mfma_tpw<false, 12, 3>(s, g, b, nf, a, tpw);
+        else if (N <= 64) y_mfma_tpw<false, 16, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 96) y_mfma_tpw<false, 24, 2>(s, g, b, nf, a, tpw);
+        else y_mfma_tpw<false, 32, 2>(s, g, b, nf, a, tpw);
     }
 }
 
 template <typename R>
-void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int mma) {
+void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int mma,
+         int tpw) {
     YArgs<R> a;
     a.Vs[0] = static_cast<const R*>(b.v0);
     a.Vs[1] = static_cast<const R*>(b.vc);
@@ -1109,7 +1153,7 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     if constexpr (sizeof(R) == 4) {
         if (mma > 0 && g.N <= 128) {
-            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma == 2);
+            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma == 2, tpw);
             return;
         }
     }
@@ -1137,9 +1181,9 @@ void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, cons
 }
 
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
-              int mma) {
-    if (dbl) y_t<double>(s, g, b, nf, ch, 0);
-    else y_t<float>(s, g, b, nf, ch, mma);
+              int mma, int tpw) {
+    if (dbl) y_t<double>(s, g, b, nf, ch, 0, 0);
+    else y_t<float>(s, g, b, nf, ch, mma, tpw);
 }
 
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,

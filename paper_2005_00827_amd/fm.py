@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
                 ("rtol", c_double), ("atol", c_double), ("h0", c_double), ("h_min", c_double),
                 ("v_max", c_double), ("channels", c_uint), ("precision", c_int),
                 ("n_zT", c_int), ("z_lnT", POINTER(c_double)), ("z_table", POINTER(c_double)),
-                ("stream", c_void_p), ("max_batch", c_int)]
+                ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -107,7 +107,7 @@ def _pi(a):
 def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, T_end=0.01,
                 integrator="rk4", n_steps=200, rtol=0.0, atol=0.0, h0=0.0, h_min=0.0,
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
-                stream=None, max_batch=1):
+                stream=None, max_batch=1, tile_rows=0):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
     cfg.geometry = GEOM_IDENTITY if geometry == "identity" else GEOM_ANGULAR
@@ -130,6 +130,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
         keep = [zl, zt]
     cfg.stream = stream
     cfg.max_batch = int(max_batch)
+    cfg.tile_rows = int(tile_rows)
     cfg._keep = keep
     return cfg
 
