@@ -146,6 +146,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     Buffers& b = h.b;
     b.xi = L.take<double>(np);
     b.patch = L.take<int>(np);
+    b.xp = L.take<int2>(np);
     b.q_pp = L.take<int>(nP);
     b.q_ph = L.take<int>(nD);
     b.map_pp = L.take<int>(NN);
@@ -404,7 +405,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.nP = static_cast<int>(hg.q_pp.size());
     g.nD = static_cast<int>(hg.q_ph.size());
     g.NN = N * N;
-    g.xi = h->b.xi; g.patch = h->b.patch; g.q_pp = h->b.q_pp; g.q_ph = h->b.q_ph;
+    g.xi = h->b.xi; g.patch = h->b.patch; g.xp = h->b.xp; g.q_pp = h->b.q_pp; g.q_ph = h->b.q_ph;
     g.map_pp = h->b.map_pp; g.map_cr = h->b.map_cr; g.map_d = h->b.map_d;
     g.nRp = static_cast<int>(hg.rep_pp.size());
     g.nRd = static_cast<int>(hg.rep_ph.size());
@@ -423,6 +424,13 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(h->b.xi, hg.xi.data(), sizeof(double) * hg.np);
     if (e == hipSuccess) e = up(h->b.patch, hg.patch.data(), sizeof(int) * hg.np);
+    std::vector<int2> xp(hg.np);
+    for (int j = 0; j < hg.np; ++j) {
+        const float x = static_cast<float>(hg.xi[j]);
+        std::memcpy(&xp[j].x, &x, sizeof x);
+        xp[j].y = hg.patch[j];
+    }
+    if (e == hipSuccess) e = up(h->b.xp, xp.data(), sizeof(int2) * hg.np);
     if (e == hipSuccess) e = up(h->b.q_pp, hg.q_pp.data(), sizeof(int) * g.nP);
     if (e == hipSuccess) e = up(h->b.q_ph, hg.q_ph.data(), sizeof(int) * g.nD);
     if (e == hipSuccess) e = up(h->b.map_pp, hg.map_pp.data(), sizeof(int) * g.NN);

@@ -82,6 +82,7 @@ struct DevGeom {
     int n_items[3];
     const double* xi;      // [np]
     const int* patch;      // [np]
+    const int2* xp;        // [np] (xi as float bits, patch): single-precision phase 1
     const int* q_pp;       // [nP]
     const int* q_ph;       // [nD]
     const int* map_pp;     // [NN]
@@ -106,7 +107,7 @@ struct StageCoef {
 // Device buffers carved out of the caller's workspace.
 struct Buffers {
     // geometry
-    double* xi; int* patch; int* q_pp; int* q_ph; int* map_pp; int* map_cr; int* map_d;
+    double* xi; int* patch; int2* xp; int* q_pp; int* q_ph; int* map_pp; int* map_cr; int* map_d;
     // per flow
     FlowState* fs;
     double* z_lnT; double* z_tab;      // [B][nz], [B][nz][N]

@@ -152,7 +152,8 @@ __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowSta
     }
 }
 
-// Point quantities at the stage temperature, a = xi / 2T:
+// Point quantities at the stage temperature, a = xi / 2T (single precision: xi rounded to
+// float times 1/2T rounded to float):
 //   single precision (a, phi(a), phi'(a), phi3(a)), double precision (a, phi(a)),
 // where phi(u) = u sech^2 u, phi' = s (1 - 2 a tau) and the third derivative
 //   phi3 = s (-6 (1 - 3 tau^2) + 8 a tau (2 - 3 tau^2)),  s = sech^2 a, tau = tanh a,
@@ -161,8 +162,8 @@ template <typename R> struct PtT;
 template <> struct PtT<float> { using T = float4; };
 template <> struct PtT<double> { using T = double2; };
 
-__device__ inline float4 point_q(double xi, double inv2T, float) {
-    const float a = static_cast<float>(xi * inv2T);
+__device__ inline float4 point_q(float xi, float inv2T) {
+    const float a = xi * inv2T;
     const float e = __expf(-2.0f * fabsf(a));
     const float rd = __builtin_amdgcn_rcpf(1.0f + e);
     const float sh = 4.0f * e * rd * rd;
@@ -171,7 +172,7 @@ __device__ inline float4 point_q(double xi, double inv2T, float) {
     return make_float4(a, a * sh, sh * (1.0f - 2.0f * at),
                        sh * (-6.0f * (1.0f - 3.0f * t2) + 8.0f * at * (2.0f - 3.0f * t2)));
 }
-__device__ inline double2 point_q(double xi, double twoT, double) {
+__device__ inline double2 point_q(double xi, double twoT) {
     const double a = xi / twoT;
     return make_double2(a, phi_d(a));
 }
@@ -206,7 +207,21 @@ __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 //   representative's bins in global memory with atomics, after clearing them.
 // ------------------------------------------------------------------------------------
 constexpr int kBinThreads = 1024;
-constexpr int kBinBatch = 4;   // 16-point units per row with loads in flight together
+// 16-point units per row whose loads are in flight together
+template <typename R> struct BinBatch;
+template <> struct BinBatch<float> { static constexpr int v = 16; };
+template <> struct BinBatch<double> { static constexpr int v = 4; };
+
+// xi and patch of loop point j: single precision reads the packed (float xi, patch) table.
+__device__ inline void xi_patch(const DevGeom& g, int j, float& x, int& p) {
+    const int2 v = g.xp[j];
+    x = __int_as_float(v.x);
+    p = v.y;
+}
+__device__ inline void xi_patch(const DevGeom& g, int j, double& x, int& p) {
+    x = g.xi[j];
+    p = g.patch[j];
+}
 
 template <int kCtrl>
 __device__ inline float dpp_f(float v) {
@@ -245,7 +260,8 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int mx = m % L, my = m / L;
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
     const R scale = static_cast<R>(-1.0 / (4.0 * T * np));
-    const double tp = sizeof(R) == 4 ? 1.0 / (2.0 * T) : 2.0 * T;   // 1/2T (float) or 2T
+    const R tp = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * T) : 2.0 * T);   // 1/2T or 2T
+    constexpr int kBinBatch = BinBatch<R>::v;
     R* acc = kMode == 0 ? lb : out;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) acc[i] = R(0);
     if (kMode == 1) __threadfence();
@@ -259,7 +275,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int u_begin = band * per_band;
     const int u_end = min(u_begin + per_band, nunits);
     for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
-        double xu[kBinBatch], xv[kBinBatch];
+        R xu[kBinBatch], xv[kBinBatch];
         int pa[kBinBatch], pq[kBinBatch];
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
@@ -270,17 +286,15 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
             px += px < 0 ? L : (px >= L ? -L : 0);
             py += py < 0 ? L : (py >= L ? -L : 0);
             const int jp = py * L + px;
-            xu[i] = g.xi[j];
-            xv[i] = g.xi[jp];
-            pa[i] = g.patch[j];
-            pq[i] = g.patch[jp];
+            xi_patch(g, j, xu[i], pa[i]);
+            xi_patch(g, jp, xv[i], pq[i]);
         }
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
             const int j = (u0 + i) * 16 + s;
             const bool ok = u0 + i < u_end && j < np;
-            const PT pu = point_q(xu[i], tp, R(0));
-            const PT pv = point_q(xv[i], tp, R(0));
+            const PT pu = point_q(xu[i], tp);
+            const PT pv = point_q(xv[i], tp);
             const R w = phi_dd_pt(pu, pp ? flip(pv) : pv);
             R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
             const int key = pa[i] * N + pq[i];
@@ -640,10 +654,10 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
 //   kind 1 (crossed, pairs (b,c)):k(n,b,c) += sum_x V(x,b,c)            Y2[q][x][n]
 //   kind 2 (direct, pairs (a,c)): k(a,n,c) += sum_x (V(x,a,c) - 2V(a,x,c)) Y3[q][x][n]
 //                                                 + V(a,x,c)             Y4[q][x][n]
-// The pairs' vectors are staged in LDS (kChunk at a time); every thread then owns
-// independent (pair, n) outputs, reading Y rows coalesced over n.  Every output element
-// receives exactly one contribution per channel (added atomically: channels run in
-// different blocks).
+// The pairs' vectors are staged in LDS (kChunk at a time, read from the operand layout in
+// which they are contiguous); every thread then owns independent (pair, n) outputs, reading
+// Y rows coalesced over n.  Every output element receives exactly one contribution per
+// channel, stored in that channel's part of the k slot (no atomics).
 // ------------------------------------------------------------------------------------
 constexpr int kChunk = 8;      // output pairs per work item
 
@@ -658,8 +672,8 @@ template <> struct YGroup<double> { static constexpr int v = 24; };
 // one x is a 128-bit broadcast read), so every group costs one memory round trip.
 template <typename R, int KIND>
 __device__ __attribute__((always_inline)) inline void contract_item(
-    const DevGeom& g, const R* V, const R* Ya, const R* Yb, const int* pairs, int cnt, R* vu,
-    R* vw, R* Kf) {
+    const DevGeom& g, const R* V, const R* VA, const R* VC, const R* Ya, const R* Yb,
+    const int* pairs, int cnt, R* vu, R* vw, R* Kf) {
     constexpr int G = KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v;
     const int N = g.N, NN = g.NN;
     for (int n0 = 0; n0 < N; n0 += 64) {
@@ -686,10 +700,12 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                     const int i = e / N, x = e - i * N;
                     const int xy = pairs[min(i, cnt - 1)];
                     const int u = xy / N, w = xy - u * N;
+                    // contiguous in x: V(u,w,x) = v0[u][w][x], V(x,u,w) = vc[w][u][x],
+                    // V(u,x,w) = va[w][u][x]
                     const size_t ia = KIND == 0 ? static_cast<size_t>(xy) * N + x
-                                                : static_cast<size_t>(x) * NN + u * N + w;
-                    av[v] = V[ia];
-                    bv[v] = KIND == 2 ? V[static_cast<size_t>(u) * NN + x * N + w] : R(0);
+                                                : static_cast<size_t>(w) * NN + u * N + x;
+                    av[v] = KIND == 0 ? V[ia] : VC[ia];
+                    bv[v] = KIND == 2 ? VA[ia] : R(0);
                 }
 #pragma unroll
                 for (int v = 0; v < kVec; ++v) {
@@ -740,9 +756,10 @@ __device__ __attribute__((always_inline)) inline void contract_item(
 
 template <typename R>
 __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
-                                                 const R* v0, const R* y1, const R* y2,
-                                                 const R* y3, const R* y4, R* K, unsigned ch,
-                                                 int slot, int B) {
+                                                 const R* v0, const R* va, const R* vc,
+                                                 const R* y1, const R* y2, const R* y3,
+                                                 const R* y4, R* K, unsigned ch, int slot,
+                                                 int B) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
@@ -771,13 +788,15 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
         return;
     }
     const R* V = v0 + f * N3;
+    const R* VA = va + f * N3;
+    const R* VC = vc + f * N3;
     const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
     const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
     R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
     R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
-    if (kind == 0) contract_item<R, 0>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
-    else if (kind == 1) contract_item<R, 1>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
-    else contract_item<R, 2>(g, V, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
+    if (kind == 0) contract_item<R, 0>(g, V, VA, VC, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
+    else if (kind == 1) contract_item<R, 1>(g, V, VA, VC, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
+    else contract_item<R, 2>(g, V, VA, VC, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1167,7 +1186,8 @@ void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsig
     const size_t lds = 2 * static_cast<size_t>(kChunk) * g.N * sizeof(R);
     const int items = g.n_items[0] + g.n_items[1] + g.n_items[2];
     hipLaunchKernelGGL(k_contract<R>, dim3(items, nf), dim3(64), lds, s, g, b.fs,
-                       static_cast<const R*>(b.v0), static_cast<const R*>(b.y1),
+                       static_cast<const R*>(b.v0), static_cast<const R*>(b.va),
+                       static_cast<const R*>(b.vc), static_cast<const R*>(b.y1),
                        static_cast<const R*>(b.y2), static_cast<const R*>(b.y3),
                        static_cast<const R*>(b.y4), static_cast<R*>(b.k), ch, slot, b.bstride);
 }
