@@ -82,6 +82,36 @@ def measured_traffic(group):
     return float(kv[key])
 
 
+def batched_sweep(fm, inputs, torch, dev):
+    """The 64-flow sweep (U in {1.0, ..., 4.5} x 8 start temperatures, N=48, L=128, no Z,
+    ragged stops) in one batch: flows/hour in single precision and in the plain FP64 path,
+    and the largest relative T_c difference between them."""
+    w = inputs.workload("C4")
+    U, T0 = w["U"], w["T0"]
+    out = {}
+    tc = {}
+    for prec in ("fp32", "fp64"):
+        f = fm.Flow(N=w["N"], L=w["L"], U=U[0], T0=max(T0), T_end=w["T_end"], integrator="rk45",
+                    precision=prec, max_batch=len(U), device=dev)
+        if prec == "fp32":
+            f.run_batch(U, T0)          # first call picks the tile shape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = f.run_batch(U, T0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        f.close()
+        tc[prec] = [r["T_c"] for r in res]
+        out["flows_per_hour_" + prec] = len(U) / dt * 3600.0
+        out["seconds_" + prec] = dt
+        out["rhs_" + prec] = int(sum(r["n_rhs"] for r in res))
+        out["updates_per_s_" + prec] = out["rhs_" + prec] * 3.0 * w["N"] ** 3 * w["L"] ** 2 / dt
+    d = [abs(a / b - 1.0) for a, b in zip(tc["fp32"], tc["fp64"]) if math.isfinite(a) and math.isfinite(b)]
+    out["diverged"] = len(d)
+    out["Tc_max_rel_diff"] = max(d) if d else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +119,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the batched U x T0 sweep (64 flows) in the extra section")
     ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations timed")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB three times "
@@ -182,6 +214,9 @@ def main():
                      Tc_rel_diff=abs(res[0]["T_c"] / r64["T_c"] - 1.0),
                      updates_per_s_fp64=r64["n_rhs"] * upd / w64)
         f64.close()
+
+    if not args.no_sweep:
+        extra["sweep_64_flows"] = batched_sweep(fm, inputs, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -86,7 +86,9 @@ typedef struct {
     double T0, T_end;         /* temperature window, T0 > T_end > 0 (finite T only) */
     int integrator, n_steps;  /* FM_RK4_FIXED uses n_steps */
     double rtol, atol;        /* Dormand-Prince: error norm max_i |E_i|/(atol + rtol max(|V|,|Vnew|));
-                                 0 selects 1e-6 and 1e-9 max(1, |U|) */
+                                 0 selects rtol 1e-6 (1e-4 for FM_FP32_BF16MFMA, whose
+                                 right-hand side resolves about 3 digits) and atol
+                                 1e-9 max(1, |U|) */
     double h0, h_min;         /* first step and smallest |step| in ln T; 0 selects
                                  ln(T_end/T0)/200 and 1e-8 |ln(T_end/T0)| */
     double v_max;             /* stop when max|V| > v_max (0 selects 20) */

@@ -630,16 +630,20 @@ static double step_factor(double err)
     return fmin(5.0, fmax(0.2, fac));
 }
 
-/* Stop rule: the largest |V| above v_max (or a non-finite value) ends the flow; T_c is
- * interpolated linearly in (ln T, ln max|V|) across the last accepted step. */
+/* Stop rule (Sec. 3.2: the flow is followed until the coupling grows beyond a threshold):
+ * the largest |V| above v_max (or a non-finite value) ends the flow.  T_c is where
+ * max|V| = v_max, found by interpolating 1/max|V| linearly in ln T across the last accepted
+ * step: near an instability the one-loop flow grows like a simple pole in the scale
+ * (for one patch 1/v = 1/U - [c(T) - c(T0)] exactly), so 1/max|V| is nearly linear and the
+ * crossing does not depend on where the step boundaries fall. */
 static int stop_test(const orc_flowcfg *f, double s_prev, double m_prev, double s_new,
                      double m_new, int finite, double *lnTc)
 {
     if (!finite) { *lnTc = s_new; return ORC_NONFINITE; }
     if (m_new > f->v_max) {
         if (m_prev > 0.0 && m_new != m_prev)
-            *lnTc = s_prev + (log(f->v_max) - log(m_prev)) * (s_new - s_prev) /
-                                 (log(m_new) - log(m_prev));
+            *lnTc = s_prev + (1.0 / m_prev - 1.0 / f->v_max) * (s_new - s_prev) /
+                                 (1.0 / m_prev - 1.0 / m_new);
         else
             *lnTc = s_new;
         return ORC_DIVERGED;

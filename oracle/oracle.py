@@ -247,6 +247,6 @@ def dopri_tableau():
 
 
 def tc_interp(s_prev, m_prev, s_new, m_new, v_max):
-    """The stop rule's crossing point, for tests: ln T_c linear in ln max|V|."""
-    return s_prev + (math.log(v_max) - math.log(m_prev)) * (s_new - s_prev) / (
-        math.log(m_new) - math.log(m_prev))
+    """The stop rule's crossing point, for tests: 1/max|V| linear in ln T."""
+    return s_prev + (1.0 / m_prev - 1.0 / v_max) * (s_new - s_prev) / (
+        1.0 / m_prev - 1.0 / m_new)

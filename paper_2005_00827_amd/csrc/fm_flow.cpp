@@ -89,7 +89,9 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.n_zT < 0 || (c.n_zT > 0 && (!c.z_lnT || !c.z_table))) { why = "bad Z table"; return FM_EINVAL; }
     for (int i = 1; i < c.n_zT; ++i)
         if (!(c.z_lnT[i] > c.z_lnT[i - 1])) { why = "Z nodes must ascend"; return FM_EINVAL; }
-    if (c.rtol <= 0.0) c.rtol = 1e-6;
+    // the relative tolerance must not ask for more than the right-hand side resolves:
+    // bf16 operands carry about 3 significant digits, so their default is 1e-4
+    if (c.rtol <= 0.0) c.rtol = c.precision == FM_FP32_BF16MFMA ? 1e-4 : 1e-6;
     if (c.v_max <= 0.0) c.v_max = 20.0;
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }

@@ -959,6 +959,14 @@ __global__ void __launch_bounds__(kThreads) k_dopri_err(const FlowState* fs, con
     }
 }
 
+// ln T where max|V| = v_max within the last accepted step [s, s_new] (max|V| from m to
+// mv > v_max): 1/max|V| interpolated linearly in ln T, exact for the pole-like growth of the
+// coupling near an instability.
+__device__ inline double crossing(double s, double m, double s_new, double mv, double v_max) {
+    if (!(m > 0.0) || mv == m) return s_new;
+    return s + (1.0 / m - 1.0 / v_max) * (s_new - s) / (1.0 / m - 1.0 / mv);
+}
+
 __device__ inline double step_factor(double err) {
     if (err == 0.0) return 5.0;
     return fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.2)));
@@ -996,9 +1004,7 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
         if (!finite) { st.status = FM_FLOW_NONFINITE; st.lnTc = s_new; }
         else if (mv > v_max) {
             st.status = FM_FLOW_DIVERGED;
-            st.lnTc = (st.m > 0.0 && mv != st.m)
-                          ? s + (log(v_max) - log(st.m)) * (s_new - s) / (log(mv) - log(st.m))
-                          : s_new;
+            st.lnTc = crossing(s, st.m, s_new, mv, v_max);
         }
         st.lnT = s_new;
         st.m = mv;
@@ -1013,9 +1019,7 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
             st.n_acc += 1;
             if (mv > v_max) {
                 st.status = FM_FLOW_DIVERGED;
-                st.lnTc = (st.m > 0.0 && mv != st.m)
-                              ? s + (log(v_max) - log(st.m)) * (s_new - s) / (log(mv) - log(st.m))
-                              : s_new;
+                st.lnTc = crossing(s, st.m, s_new, mv, v_max);
             }
             st.lnT = s_new;
             st.m = mv;

@@ -109,7 +109,7 @@ def test_n1_attractive_tc(integrator, n):
     V, res, tr = O.flow(O.model(1, L1), cfg, U)
     assert res["status"] == O.DIVERGED
     assert res["T_c"] == pytest.approx(tc, rel=1e-3)
-    # the stop rule: the crossing interpolated in (ln T, ln max|V|) over the last step
+    # the stop rule: the crossing of 1/max|V| = 1/v_max, linear in ln T over the last step
     (s0, m0), (s1, m1) = tr[-2], tr[-1]
     assert m0 <= vmax < m1
     assert math.log(res["T_c"]) == pytest.approx(O.tc_interp(s0, m0, s1, m1, vmax), abs=1e-14)
