@@ -101,8 +101,9 @@ typedef struct {
     void *stream;             /* hipStream_t or NULL */
     int max_batch;            /* capacity (flows) for every batched call; >= 1 */
     int tile_rows;            /* single-precision phase 2a: 16-row transfer tiles per
-                                 wavefront, 1, 2 or 4; 0 = chosen by timing the candidates
-                                 on the first call (kept per shape for the process) */
+                                 wavefront (>= 1, values past all tiles of a group are
+                                 clamped); 0 = chosen by timing 1, 2, 4, ... and all on the
+                                 first call (kept per shape for the process) */
 } fm_config;
 
 typedef struct {

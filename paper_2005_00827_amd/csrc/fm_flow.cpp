@@ -95,10 +95,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.v_max <= 0.0) c.v_max = 20.0;
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
-    if (c.tile_rows != 0 && c.tile_rows != 1 && c.tile_rows != 2 && c.tile_rows != 4) {
-        why = "tile_rows must be 0, 1, 2 or 4";
-        return FM_EINVAL;
-    }
+    if (c.tile_rows < 0) { why = "tile_rows must be >= 0"; return FM_EINVAL; }
     return FM_OK;
 }
 
@@ -249,8 +246,10 @@ void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const 
     });
 }
 
-// Phase-2a tile choice: cfg.tile_rows when set, else the fastest of 1, 2 and 4 row tiles per
-// wavefront, timed with events on the operands of a stage at the flows' current state.
+// Phase-2a tile choice: cfg.tile_rows when set, else the fastest of 1, 2, 4, ... row tiles
+// per wavefront up to all of a group's tiles in one block (few blocks, each staging its B
+// chunk once, against many blocks with more parallelism), timed with events on the operands
+// of a stage at the flows' current state.
 // Every later stage recomputes these products, so the timing runs change no result.
 // Choices are kept for the process, per shape and number of flows.
 using TuneKey = std::tuple<int, int, int, int, int, double, double, double>;
@@ -276,7 +275,12 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     HIPCHK(hipEventCreate(&e1));
     int best = 1;
     float best_ms = std::numeric_limits<float>::infinity();
-    for (int tpw : {1, 2, 4}) {
+    const int ntiles = (std::max(h->g.nP, h->g.nD) + 15) / 16;
+    const int maxt = (ntiles + 3) / 4;
+    std::vector<int> cand;
+    for (int t = 1; t < maxt; t *= 2) cand.push_back(t);
+    cand.push_back(maxt);
+    for (int tpw : cand) {
         launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, tpw);
         (void)hipEventRecord(e0, h->stream);
         for (int r = 0; r < 5; ++r) launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, tpw);

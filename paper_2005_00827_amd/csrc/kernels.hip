@@ -544,27 +544,39 @@ __device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, 
     }
 }
 
-template <bool kBF16, int KE, int NT, bool kTwo, int TPW>
-__device__ inline void y_tiles(const float* Bf, int NN, int N, int M, int grp, int n0,
-                               int t_begin, int ntiles, const int (&rep)[TPW],
-                               const int (&op)[TPW], const int* pis, const float* zs,
-                               const float* Bs0, const float* Bs1, float* Y0, float* Y1,
-                               int lane) {
+// Representative and operation of the lane's row in row tile `tile` (clamped to the last
+// transfer, so tiles past the end read valid entries).
+__device__ inline void tile_rep(const int* qrep, const int* qg, int M, int tile, int col,
+                                int& rep, int& op) {
+    const int q = min(tile * 16 + col, M - 1);
+    rep = qrep[q];
+    op = qg[q];
+}
+
+// Row tiles [t_begin, t_end) of one wavefront: the A gather of tile t+1 and the table
+// entries of tile t+2 are in flight while tile t runs on the matrix cores and is stored.
+template <bool kBF16, int KE, int NT, bool kTwo>
+__device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, int NN, int N,
+                               int M, int grp, int n0, int t_begin, int t_end, const int* pis,
+                               const float* zs, const float* Bs0, const float* Bs1, float* Y0,
+                               float* Y1, int lane) {
     const int col = lane & 15;
     const float zg = zs[grp];
-    float a[2][KE];
-    gather_a<kBF16, KE>(a[0], Bf, NN, N, grp, rep[0], op[0], pis, zs, zg, lane);
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int tile = t_begin + t;
-        if (tile >= ntiles) break;                     // uniform over the wave
-        if (t + 1 < TPW && tile + 1 < ntiles)
-            gather_a<kBF16, KE>(a[(t + 1) & 1], Bf, NN, N, grp, rep[t + 1], op[t + 1], pis, zs,
-                                zg, lane);
+    int r0, o0, r1, o1;
+    tile_rep(qrep, qg, M, t_begin, col, r0, o0);
+    tile_rep(qrep, qg, M, t_begin + 1, col, r1, o1);
+    float a0[KE], a1[KE];
+    gather_a<kBF16, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, lane);
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        // B fragments are re-read from LDS every tile instead of being kept in registers
+        asm volatile("" ::: "memory");
+        int r2, o2;
+        tile_rep(qrep, qg, M, tile + 2, col, r2, o2);
+        if (tile + 1 < t_end) gather_a<kBF16, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, lane);
         fm_f4 c0[NT], c1[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u) c0[u] = c1[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
-        mfma_tile<kBF16, KE, NT, kTwo>(a[t & 1], Bs0, Bs1, c0, c1, lane);
+        mfma_tile<kBF16, KE, NT, kTwo>(a0, Bs0, Bs1, c0, c1, lane);
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             const int n = n0 + 16 * u + col;
@@ -578,18 +590,22 @@ __device__ inline void y_tiles(const float* Bf, int NN, int N, int M, int grp, i
                 }
             }
         }
+#pragma unroll
+        for (int e = 0; e < KE; ++e) a0[e] = a1[e];
+        r1 = r2;
+        o1 = o2;
     }
 }
 
-// Grid: x = blocks of 4 waves, each wave TPW consecutive row tiles; y = group * nchunk +
+// Grid: x = blocks of 4 waves, each wave `tpw` consecutive row tiles; y = group * nchunk +
 // column chunk; z = 3 * flow + channel (0 pp -> Y1, 1 crossed -> Y2, 2 direct -> Y3, Y4).
-// The block stages its B chunk(s) in LDS once; every wave gathers its tiles' A operands
-// straight into MFMA layout, the next tile's gather in flight during the current tile.
-template <bool kBF16, int KE, int NT, int TPW>
+// The block stages its B chunk(s) in LDS once and reuses them for all 4 tpw row tiles;
+// every wave gathers its tiles' A operands straight into MFMA layout.
+template <bool kBF16, int KE, int NT>
 __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
                                                      const double* Z_stage, const float* bins,
                                                      const float* binsT, YArgs<float> args,
-                                                     int nchunk) {
+                                                     int nchunk, int tpw) {
     constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT;
     __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
     __shared__ float zs[128];                         // Z of the stage
@@ -603,18 +619,11 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const int n0 = (blockIdx.y - grp * nchunk) * W;
     const int ntiles = (M + 15) / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int col = lane & 15;
-    const int t_begin = (blockIdx.x * 4 + wv) * TPW;
+    const int t_begin = (blockIdx.x * 4 + wv) * tpw;
+    const int t_end = min(t_begin + tpw, ntiles);
     const bool two = ch == 2;
     const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
     const int* qg = ch == 0 ? g.qg_pp : g.qg_ph;
-    int rep[TPW], op[TPW];
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int q = min((t_begin + t) * 16 + col, M - 1);
-        rep[t] = qrep[q];
-        op[t] = qg[q];
-    }
     for (int i = threadIdx.x; i < 8 * N; i += kThreads) pis[i] = g.pinv[i];
     if (threadIdx.x < N) zs[threadIdx.x] = static_cast<float>(Z_stage[static_cast<size_t>(f) * N + threadIdx.x]);
     const size_t N3 = static_cast<size_t>(NN) * N;
@@ -633,19 +642,17 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
         }
     }
     __syncthreads();                                   // every thread of the block
-    if (t_begin >= ntiles) return;
+    if (t_begin >= t_end) return;
     const int nR = g.nRp + g.nRd;
     const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
                               : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     if (two)
-        y_tiles<kBF16, KE, NT, true, TPW>(Bf, NN, N, M, grp, n0, t_begin, ntiles, rep, op, pis,
-                                          zs, Bs[0], Bs[1], args.Y[2] + yoff, args.Y[3] + yoff,
-                                          lane);
+        y_tiles<kBF16, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
+                                     Bs[0], Bs[1], args.Y[2] + yoff, args.Y[3] + yoff, lane);
     else
-        y_tiles<kBF16, KE, NT, false, TPW>(Bf, NN, N, M, grp, n0, t_begin, ntiles, rep, op,
-                                           pis, zs, Bs[0], Bs[1], args.Y[ch] + yoff, nullptr,
-                                           lane);
+        y_tiles<kBF16, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
+                                      Bs[0], Bs[1], args.Y[ch] + yoff, nullptr, lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1112,32 +1119,20 @@ void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, i
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
-// tiles per wave); TPW row tiles per wave is a tuning choice (tuned_tpw, 0 = by size).
-template <bool kBF16, int KE, int NT, int TPW>
-void y_mfma_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
-               const YArgs<float>& a) {
-    const int mmax = g.nP > g.nD ? g.nP : g.nD;
-    const int ntiles = (mmax + 15) / 16;
-    const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
-    const int bx = (ntiles + 4 * TPW - 1) / (4 * TPW);
-    const dim3 grid(bx, g.N * nchunk, 3 * nf);
-    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT, TPW>), grid, dim3(kThreads), 0, s, g, b.fs,
-                       b.Z_stage, static_cast<const float*>(b.bins),
-                       static_cast<const float*>(b.binsT), a, nchunk);
-}
-
+// tiles per wave); row tiles per wavefront `tpw` is a tuning choice (0: one).
 template <bool kBF16, int KE, int NT>
 void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                 const YArgs<float>& a, int tpw) {
-    if (tpw <= 0) {   // about 4096 waves
-        const int mmax = g.nP > g.nD ? g.nP : g.nD;
-        const long w1 = static_cast<long>((mmax + 15) / 16) * g.N *
-                        ((g.N + 16 * NT - 1) / (16 * NT)) * 3 * nf;
-        tpw = w1 <= 4096 ? 1 : (w1 <= 8192 ? 2 : 4);
-    }
-    if (tpw == 1) y_mfma_go<kBF16, KE, NT, 1>(s, g, b, nf, a);
-    else if (tpw == 2) y_mfma_go<kBF16, KE, NT, 2>(s, g, b, nf, a);
-    else y_mfma_go<kBF16, KE, NT, 4>(s, g, b, nf, a);
+    const int mmax = g.nP > g.nD ? g.nP : g.nD;
+    const int ntiles = (mmax + 15) / 16;
+    const int maxt = (ntiles + 3) / 4;
+    tpw = tpw <= 0 ? 1 : (tpw > maxt ? maxt : tpw);
+    const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
+    const int bx = (ntiles + 4 * tpw - 1) / (4 * tpw);
+    const dim3 grid(bx, g.N * nchunk, 3 * nf);
+    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT>), grid, dim3(kThreads), 0, s, g, b.fs,
+                       b.Z_stage, static_cast<const float*>(b.bins),
+                       static_cast<const float*>(b.binsT), a, nchunk, tpw);
 }
 
 inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,

@@ -75,7 +75,7 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=16, L=32, max_batch=0), "max_batch"),
     (dict(N=17, L=4, geometry="identity"), "identity"),
     (dict(N=16, L=32, channels=9), "channel"),
-    (dict(N=16, L=32, tile_rows=3), "tile_rows"),
+    (dict(N=16, L=32, tile_rows=-1), "tile_rows"),
 ])
 def test_invalid_configs_rejected(kw, msg):
     cfg = fm.make_config(**kw)

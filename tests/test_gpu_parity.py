@@ -88,12 +88,12 @@ def test_rhs_small(torch_dev, prec, N, L, T, state, kw):
     assert rel(got, ref) <= TOL[prec], (prec, N, L, T, state, kw, rel(got, ref))
 
 
-@pytest.mark.parametrize("tile_rows", [1, 2, 4])
+@pytest.mark.parametrize("tile_rows", [1, 2, 3, 100])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("N,L", [(32, 64), (48, 64)])
 def test_rhs_every_phase2a_tile_choice(torch_dev, prec, tile_rows, N, L):
-    """Each row-tile count per wavefront the tuner can pick gives the oracle's RHS (12 and
-    more transfer tiles, so runs of 1, 2 and 4 tiles end ragged)."""
+    """Row-tile counts per wavefront, up to all of a group's tiles (100 is clamped), give the
+    oracle's RHS (12 and more transfer tiles, so runs of 2 and 3 tiles end ragged)."""
     V = inputs.noisy_state(N, 2.5)
     ref = O.rhs(O.model(N, L), 0.09, V)
     got = gpu_rhs(torch_dev, N, L, 0.09, V, prec, tile_rows=tile_rows)[0]
