@@ -159,6 +159,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.qrep_ph = L.take<int>(nD);
     b.qg_ph = L.take<int>(nD);
     b.pinv = L.take<int>(8 * static_cast<size_t>(N));
+    b.pI = L.take<int>(N);
     b.pp_off = L.take<int>(nP + 1);
     b.pp_pairs = L.take<int>(NN);
     b.cr_off = L.take<int>(nD + 1);
@@ -419,6 +420,14 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.qrep_pp = h->b.qrep_pp; g.qg_pp = h->b.qg_pp;
     g.qrep_ph = h->b.qrep_ph; g.qg_ph = h->b.qg_ph;
     g.pinv = h->b.pinv;
+    g.pI = h->b.pI;
+    g.inv_ok = hg.inv_ok ? 1 : 0;
+    g.inv_rot = 0;
+    if (hg.inv_ok && N % 2 == 0) {
+        g.inv_rot = 1;
+        for (int a = 0; a < N; ++a)
+            if (hg.inv_perm[a] != (a + N / 2) % N) g.inv_rot = 0;
+    }
     g.pp_off = h->b.pp_off; g.pp_pairs = h->b.pp_pairs;
     g.cr_off = h->b.cr_off; g.cr_pairs = h->b.cr_pairs;
     g.d_off = h->b.d_off; g.d_pairs = h->b.d_pairs;
@@ -452,6 +461,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.qrep_ph, hg.qrep_ph);
     if (e == hipSuccess) e = upv(h->b.qg_ph, hg.qg_ph);
     if (e == hipSuccess) e = upv(h->b.pinv, hg.pinv);
+    if (e == hipSuccess) e = upv(h->b.pI, hg.inv_perm);
     if (e == hipSuccess) e = upv(h->b.pp_off, hg.pp_off);
     if (e == hipSuccess) e = upv(h->b.pp_pairs, hg.pp_pairs);
     if (e == hipSuccess) e = upv(h->b.cr_off, hg.cr_off);

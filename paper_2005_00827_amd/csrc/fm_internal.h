@@ -31,6 +31,8 @@ struct HostGeometry {
     // q = o(r) are those of its representative r with both patch labels mapped by o^-1.
     bool sym = false;                // the geometry is invariant under all eight
     std::vector<int> pinv;           // [8][N] patch permutation of o^-1
+    bool inv_ok = false;             // the geometry is invariant under k -> -k alone
+    std::vector<int> inv_perm;       // [N] patch permutation of k -> -k
     std::vector<int> rep_pp, rep_ph; // representative transfers (flat index)
     std::vector<int> qrep_pp, qg_pp; // [nP] representative index and operation
     std::vector<int> qrep_ph, qg_ph; // [nD]
@@ -75,6 +77,9 @@ struct DevGeom {
     const int* qrep_ph;    // [nD]
     const int* qg_ph;      // [nD]
     const int* pinv;       // [8][N]
+    const int* pI;         // [N] patch permutation of k -> -k
+    int inv_ok;            // pI is valid (k -> -k maps patches and dispersion onto themselves)
+    int inv_rot;           // pI[a] = (a + N/2) mod N
     const int* pp_off; const int* pp_pairs;
     const int* cr_off; const int* cr_pairs;
     const int* d_off;  const int* d_pairs;
@@ -114,6 +119,7 @@ struct Buffers {
     double* T_stage;                   // [B]
     double* Z_stage;                   // [B][N]
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
+    int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0;
     void* bins;                        // [B][nRp + nRd][NN] real, representative transfers

@@ -109,6 +109,29 @@ void build_symmetry(HostGeometry& g) {
             if (perm[o * static_cast<size_t>(N) + a] < 0) ok = false;
     }
     g.sym = ok;
+    // inversion k -> -k alone (operation 3), used to pair the particle-hole loop points of
+    // phase 1: needs xi(-k) = xi(k) and a patch permutation P with patch(-k) = P(patch(k))
+    {
+        std::vector<int> p(N, -1);
+        bool iok = true;
+        for (int jy = 0; jy < L && iok; ++jy)
+            for (int jx = 0; jx < L && iok; ++jx) {
+                int ox, oy;
+                op_point(3, L, jx, jy, ox, oy);
+                const int j = jx + L * jy, oj = ox + L * oy;
+                if (std::fabs(g.xi[oj] - g.xi[j]) > 1e-12 * std::max(1.0, std::fabs(g.xi[j]))) iok = false;
+                else if (p[g.patch[j]] < 0) p[g.patch[j]] = g.patch[oj];
+                else if (p[g.patch[j]] != g.patch[oj]) iok = false;
+            }
+        std::vector<int> seen(N, 0);
+        for (int a = 0; a < N && iok; ++a) {
+            if (p[a] < 0 || seen[p[a]]) iok = false;
+            else seen[p[a]] = 1;
+        }
+        g.inv_ok = iok;
+        g.inv_perm.resize(N);
+        for (int a = 0; a < N; ++a) g.inv_perm[a] = iok ? p[a] : a;
+    }
     g.pinv.assign(8 * static_cast<size_t>(N), 0);
     for (int o = 0; o < 8; ++o)
         for (int a = 0; a < N; ++a) {

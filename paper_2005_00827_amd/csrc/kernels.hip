@@ -206,10 +206,12 @@ __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 //   kMode 0: bins in LDS; kMode 1 (bin matrix above 64 KB): the block accumulates its own
 //   representative's bins in global memory with atomics, after clearing them.
 // ------------------------------------------------------------------------------------
-constexpr int kBinThreads = 1024;
+// Block size of stage and phase 1: 1024 threads for few (flow, representative) pairs, so
+// one flow's bins spread over many waves; 256 when there are many, so several blocks share
+// a CU and one block's fill and drain overlap another's work.
 // 16-point units per row whose loads are in flight together
 template <typename R> struct BinBatch;
-template <> struct BinBatch<float> { static constexpr int v = 16; };
+template <> struct BinBatch<float> { static constexpr int v = 8; };
 template <> struct BinBatch<double> { static constexpr int v = 4; };
 
 // xi and patch of loop point j: single precision reads the packed (float xi, patch) table.
@@ -249,7 +251,36 @@ __device__ inline void seg_step(R& v, int& h, int s) {
     }
 }
 
-template <typename R, int kMode>
+// Pairing (exact, halves the weight evaluations): the particle-particle partner map
+// j -> q - j and the particle-hole map j -> -(j + q) are involutions s of the loop grid, per
+// axis j -> (c - 1 - j) mod L (c = q, resp. -q), whose pairs carry equal weights.  The pair
+// of s(j) has key (pi(j'), pi(j)) (particle-particle) or (P pi(j'), P pi(j)) (particle-hole,
+// P the patch permutation of k -> -k), so each unordered pair {j, s(j)} is evaluated once
+// and added under both keys.  Rows pair up as jy <-> (c - 1 - jy) mod L: one row of each
+// pair is visited in full; in a row that s fixes (two when c - 1 is even) the columns pair
+// up the same way and one column of each pair is visited; the at most four points that s
+// fixes are their own pair and are added once, at the end.  Without the inversion symmetry
+// the particle-hole sum visits every point once.
+struct Half {
+    int h1, h2, nfix, c;   // [0, h1) and [c + 1, c + 1 + h2) are one side; fixed c/2, c/2 + L/2
+};
+__device__ inline Half half_of(int cc, int L) {
+    const int c = (cc + 2 * L - 1) % L;
+    return Half{(c + 1) / 2, (L - c - 1) / 2, c % 2 == 0 ? 2 : 0, c};
+}
+__device__ inline int half_map(const Half& h, int i) { return i < h.h1 ? i : h.c + 1 + (i - h.h1); }
+__device__ inline int half_fix(const Half& h, int i, int L) { return h.c / 2 + i * (L / 2); }
+
+// Patch permutation of k -> -k: a rotation by half a turn for angular patches, else the table.
+__device__ inline int inv_patch(const DevGeom& g, int a) {
+    if (g.inv_rot) {
+        const int b = a + g.N / 2;
+        return b >= g.N ? b - g.N : b;
+    }
+    return g.pI[a];
+}
+
+template <typename R, int kMode, int BT>
 __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bins, R* binsT,
                                  R* lb) {
     using PT = typename PtT<R>::T;
@@ -262,16 +293,23 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const R scale = static_cast<R>(-1.0 / (4.0 * T * np));
     const R tp = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * T) : 2.0 * T);   // 1/2T or 2T
     constexpr int kBinBatch = BinBatch<R>::v;
+    const bool half = (pp || g.inv_ok) && L % 2 == 0;
+    const Half hy = half_of(pp ? my : L - my, L), hx = half_of(pp ? mx : L - mx, L);
+    const int nrow = half ? hy.h1 + hy.h2 : L;            // rows visited in full
+    const int ncol = hx.h1 + hx.h2;                        // columns visited in a fixed row
+    const int npt = nrow * L + (half ? hy.nfix * ncol : 0);
     R* acc = kMode == 0 ? lb : out;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) acc[i] = R(0);
     if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
-    // 64 rows of 16 lanes per block; row rr works on band rr of 64 contiguous bands of units
+    // BT/16 rows of 16 lanes per block; row rr works on band rr of BT/16 contiguous bands of
+    // units, the 4 rows of a wave a quarter of the bands apart
+    constexpr int kBands = BT / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = lane & 15;
-    const int band = (lane >> 4) * (kBinThreads / 64) + wv;
-    const int nunits = (np + 15) / 16;
-    const int per_band = (nunits + 63) / 64;
+    const int band = (lane >> 4) * (BT / 64) + wv;
+    const int nunits = (npt + 15) / 16;
+    const int per_band = (nunits + kBands - 1) / kBands;
     const int u_begin = band * per_band;
     const int u_end = min(u_begin + per_band, nunits);
     for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
@@ -279,25 +317,33 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
         int pa[kBinBatch], pq[kBinBatch];
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
-            const int j = min((u0 + i) * 16 + s, np - 1);
-            const int jy = j / L, jx = j - jy * L;
+            const int p = min((u0 + i) * 16 + s, npt - 1);
+            int jx, jy;
+            if (p < nrow * L) {
+                const int rr = p / L;
+                jx = p - rr * L;
+                jy = half ? half_map(hy, rr) : rr;
+            } else {                                       // a row fixed by s
+                const int q2 = p - nrow * L, fr = q2 / ncol;
+                jy = half_fix(hy, fr, L);
+                jx = half_map(hx, q2 - fr * ncol);
+            }
             int px = pp ? mx - jx - 1 : jx + mx;
             int py = pp ? my - jy - 1 : jy + my;
             px += px < 0 ? L : (px >= L ? -L : 0);
             py += py < 0 ? L : (py >= L ? -L : 0);
-            const int jp = py * L + px;
-            xi_patch(g, j, xu[i], pa[i]);
-            xi_patch(g, jp, xv[i], pq[i]);
+            xi_patch(g, jy * L + jx, xu[i], pa[i]);
+            xi_patch(g, py * L + px, xv[i], pq[i]);
         }
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
-            const int j = (u0 + i) * 16 + s;
-            const bool ok = u0 + i < u_end && j < np;
+            const bool ok = u0 + i < u_end && (u0 + i) * 16 + s < npt;
             const PT pu = point_q(xu[i], tp);
             const PT pv = point_q(xv[i], tp);
             const R w = phi_dd_pt(pu, pp ? flip(pv) : pv);
             R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
             const int key = pa[i] * N + pq[i];
+            const int key2 = pp ? pq[i] * N + pa[i] : inv_patch(g, pq[i]) * N + inv_patch(g, pa[i]);
             const int kprev = dpp_i<0x111>(key);   // row_shr:1
             const int knext = dpp_i<0x101>(key);   // row_shl:1
             int h = (s == 0 || kprev != key) ? 1 : 0;
@@ -305,8 +351,27 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
             seg_step<2>(x, h, s);
             seg_step<4>(x, h, s);
             seg_step<8>(x, h, s);
-            if (s == 15 || knext != key) atomicAdd(&acc[key], x);
+            if (s == 15 || knext != key) {     // key2 is a bijective function of key
+                atomicAdd(&acc[key], x);
+                if (half) atomicAdd(&acc[key2], x);
+            }
         }
+    }
+    // points fixed by s: their own pair, added once
+    if (half && static_cast<int>(threadIdx.x) < hy.nfix * hx.nfix) {
+        const int jy = half_fix(hy, threadIdx.x >> 1, L), jx = half_fix(hx, threadIdx.x & 1, L);
+        int px = pp ? mx - jx - 1 : jx + mx;
+        int py = pp ? my - jy - 1 : jy + my;
+        px += px < 0 ? L : (px >= L ? -L : 0);
+        py += py < 0 ? L : (py >= L ? -L : 0);
+        R xa, xb;
+        int qa, qb;
+        xi_patch(g, jy * L + jx, xa, qa);
+        xi_patch(g, py * L + px, xb, qb);
+        const PT pu = point_q(xa, tp);
+        const PT pv = point_q(xb, tp);
+        const R w = phi_dd_pt(pu, pp ? flip(pv) : pv);
+        atomicAdd(&acc[qa * N + qb], kMode == 0 ? w : w * scale);
     }
     if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
@@ -325,8 +390,8 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
 // One launch per stage: blocks [0, nRb) bin the representatives (phase 1, which needs only
 // T), the remaining blocks form the stage argument and its operand layouts.  Grid (nRb +
 // stage blocks, flows).
-template <typename R, int kMode>
-__global__ void __launch_bounds__(kBinThreads) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
+template <typename R, int kMode, int BT>
+__global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
                                                             StageCoef sc, int write_new,
                                                             const double* Vbase, const R* K,
                                                             double* Vnew, R* v0, R* va, R* vc,
@@ -338,7 +403,7 @@ __global__ void __launch_bounds__(kBinThreads) k_stage_bins(DevGeom g, DevZ z, c
     const FlowState st = fs[f];
     if (static_cast<int>(blockIdx.x) < nRb) {
         const double T = exp(st.lnT + sc.c * st.ht);
-        bins_part<R, kMode>(g, f, blockIdx.x, T, bins, binsT, reinterpret_cast<R*>(smem_raw));
+        bins_part<R, kMode, BT>(g, f, blockIdx.x, T, bins, binsT, reinterpret_cast<R*>(smem_raw));
     } else {
         stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
                       B, blockIdx.x - nRb, gridDim.x - nRb);
@@ -1094,28 +1159,40 @@ int bins_mode(const DevGeom& g) {
 }
 
 // Stage argument plus, when bins exist, phase 1 of the same stage in one launch.
-template <typename R>
-void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
-             const StageCoef& sc, int write_new, const double* Vbase) {
+template <typename R, int BT>
+void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
+              const StageCoef& sc, int write_new, const double* Vbase, int nRb, int ept) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
-    const int nRb = b.bins ? g.nRp + g.nRd : 0;
-    size_t ns = (N3 + kBinThreads - 1) / kBinThreads;
-    ns = ns > 512 ? 512 : ns;
+    size_t ns = (N3 + static_cast<size_t>(BT) * ept - 1) / (static_cast<size_t>(BT) * ept);
+    ns = ns > 1024 ? 1024 : ns;
     const dim3 grid(static_cast<unsigned>(nRb + ns), nf);
     const bool lds = nRb > 0 && bins_mode<R>(g) == 0;
     const size_t shm = lds ? static_cast<size_t>(g.NN) * sizeof(R) : 0;
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
     if (nRb == 0 || lds)
-        hipLaunchKernelGGL((k_stage_bins<R, 0>), grid, dim3(kBinThreads), shm, s, g, z, b.fs, sc,
+        hipLaunchKernelGGL((k_stage_bins<R, 0, BT>), grid, dim3(BT), shm, s, g, z, b.fs, sc,
                            write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
     else
-        hipLaunchKernelGGL((k_stage_bins<R, 1>), grid, dim3(kBinThreads), 0, s, g, z, b.fs, sc,
+        hipLaunchKernelGGL((k_stage_bins<R, 1, BT>), grid, dim3(BT), 0, s, g, z, b.fs, sc,
                            write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
+}
+
+// Stage argument plus, when bins exist, phase 1 of the same stage in one launch.  Few
+// (flow, representative) pairs (at most one per CU): 1024-thread blocks, one stage element
+// per thread; many: 256-thread blocks, four stage elements per thread.
+template <typename R>
+void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
+             const StageCoef& sc, int write_new, const double* Vbase) {
+    const int nRb = b.bins ? g.nRp + g.nRd : 0;
+    if (static_cast<long>(nRb) * nf <= 256)
+        stage_go<R, 1024>(s, g, z, b, nf, sc, write_new, Vbase, nRb, 1);
+    else
+        stage_go<R, 256>(s, g, z, b, nf, sc, write_new, Vbase, nRb, 4);
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
