@@ -112,6 +112,47 @@ def batched_sweep(fm, inputs, torch, dev):
     return out
 
 
+def large_batch(fm, inputs, torch, dev):
+    """16 flows, U = 1 + 3i/15, N=128, L=512, synthetic Z per flow, T 1 -> 0.01: flows/hour for
+    the bf16 and fp32 right-hand sides against the plain FP64 path, T_c agreement, and the
+    per-kernel timings (HIP events, eager replay) of the bf16 run."""
+    import numpy as np
+    w = inputs.workload("C5")
+    N, L, U, T0 = w["N"], w["L"], w["U"], w["T0"]
+    tabs = [inputs.synthetic_z_table(N, u, 1.0, w["T_end"]) for u in U]
+    zl = np.stack([t[0] for t in tabs])
+    zt = np.stack([t[1] for t in tabs])
+    out, tc = {}, {}
+    for prec in ("bf16", "fp32", "fp64"):
+        f = fm.Flow(N=N, L=L, U=U[0], T0=1.0, T_end=w["T_end"], integrator="rk45", precision=prec,
+                    z_lnT=zl[0], z_table=zt[0], max_batch=len(U), device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = f.run_batch(U, T0, z_lnT=zl, z_tables=zt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if prec == "bf16":
+            f.set_timing(True)
+            f.run_batch(U, T0, z_lnT=zl, z_tables=zt)
+            out["kernels_bf16"] = {k: {"launches": n, "avg_us": ms / n * 1e3}
+                                   for k, (ms, n) in f.timings().items()}
+            f.set_timing(False)
+        f.close()
+        rhs = int(sum(r["n_rhs"] for r in res))
+        tc[prec] = [r["T_c"] for r in res]
+        out["flows_per_hour_" + prec] = len(U) / dt * 3600.0
+        out["seconds_" + prec] = dt
+        out["rhs_" + prec] = rhs
+        out["updates_per_s_" + prec] = rhs * 3.0 * N ** 3 * L ** 2 / dt
+    for prec in ("bf16", "fp32"):
+        d = [abs(a / b - 1.0) for a, b in zip(tc[prec], tc["fp64"])
+             if math.isfinite(a) and math.isfinite(b)]
+        out["Tc_max_rel_diff_" + prec] = max(d) if d else None
+    out["note"] = ("first bf16/fp32 call includes the phase-2a tile tuning; bf16 runs at its "
+                   "default rtol 1e-4, fp32 and fp64 at 1e-6")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,7 +162,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the batched U x T0 sweep (64 flows) in the extra section")
-    ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations timed")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large batch (16 flows, N=128, L=512) in the extra section")
+    ap.add_argument("--cpu-rhs", type=int, default=6, help="oracle RHS evaluations timed")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -217,6 +260,8 @@ def main():
 
     if not args.no_sweep:
         extra["sweep_64_flows"] = batched_sweep(fm, inputs, torch, dev)
+    if not args.no_large:
+        extra["large_16_flows"] = large_batch(fm, inputs, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
