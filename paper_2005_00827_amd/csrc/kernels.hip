@@ -551,14 +551,18 @@ __device__ inline int mfma_k(int e, int lane) {
 template <int NT>
 constexpr int b_stride() { return (16 * NT) % 32 == 16 ? 16 * NT : 16 * NT + 16; }
 
-// One 16-row tile on the matrix cores: c0 += A B0 (and c1 += A B1 for the direct channel),
-// B fragments read from LDS (Bs0/Bs1: [4 KE][b_stride] floats, zero beyond N).
+// One 16-row tile on the matrix cores: c0 += A B0 (and c1 += A B1 for the direct channel).
+// FP32: B fragments read from LDS as [k][n] floats (stride b_stride); BF16: B staged as
+// bf16, transposed [n][k] with row stride KP + 8, so a lane's 8 consecutive k of one column
+// are a single 16-byte read.  Both zero beyond N.
 template <bool kBF16, int KE, int NT, bool kTwo>
-__device__ inline void mfma_tile(const float (&a)[KE], const float* Bs0, const float* Bs1,
+__device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const void* Bs1v,
                                  fm_f4 (&c0)[NT], fm_f4 (&c1)[NT], int lane) {
-    constexpr int S = b_stride<NT>();
     const int col = lane & 15;
     if constexpr (kBF16) {
+        constexpr int KBS = 4 * KE + 8;
+        const __bf16* Bh0 = static_cast<const __bf16*>(Bs0v);
+        const __bf16* Bh1 = static_cast<const __bf16*>(Bs1v);
 #pragma unroll
         for (int s = 0; s < KE / 8; ++s) {
             fm_bf8 av;
@@ -567,18 +571,18 @@ __device__ inline void mfma_tile(const float (&a)[KE], const float* Bs0, const f
             const int kb = 32 * s + 8 * (lane >> 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                fm_bf8 bv;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(Bs0[(kb + e) * S + 16 * t + col]);
+                const fm_bf8 bv = *reinterpret_cast<const fm_bf8*>(Bh0 + (16 * t + col) * KBS + kb);
                 c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c0[t], 0, 0, 0);
                 if constexpr (kTwo) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) bv[e] = static_cast<__bf16>(Bs1[(kb + e) * S + 16 * t + col]);
-                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c1[t], 0, 0, 0);
+                    const fm_bf8 bw = *reinterpret_cast<const fm_bf8*>(Bh1 + (16 * t + col) * KBS + kb);
+                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw, c1[t], 0, 0, 0);
                 }
             }
         }
     } else {
+        constexpr int S = b_stride<NT>();
+        const float* Bs0 = static_cast<const float*>(Bs0v);
+        const float* Bs1 = static_cast<const float*>(Bs1v);
 #pragma unroll
         for (int e = 0; e < KE; ++e) {
             const int k = 4 * e + (lane >> 4);
@@ -623,7 +627,7 @@ __device__ inline void tile_rep(const int* qrep, const int* qg, int M, int tile,
 template <bool kBF16, int KE, int NT, bool kTwo>
 __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, int NN, int N,
                                int M, int grp, int n0, int t_begin, int t_end, const int* pis,
-                               const float* zs, const float* Bs0, const float* Bs1, float* Y0,
+                               const float* zs, const void* Bs0, const void* Bs1, float* Y0,
                                float* Y1, int lane) {
     const int col = lane & 15;
     const float zg = zs[grp];
@@ -662,29 +666,39 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
     }
 }
 
-// Grid: x = blocks of 4 waves, each wave `tpw` consecutive row tiles; y = group * nchunk +
-// column chunk; z = 3 * flow + channel (0 pp -> Y1, 1 crossed -> Y2, 2 direct -> Y3, Y4).
+// 1D grid.  A work group is (row-tile run x, group g, channel, flow), numbered
+// w = ((flow * 3 + channel) * N + g) * bx + x; its nchunk column chunks read the same A rows.
+// Workgroups are dealt to the 8 XCDs round-robin, so the chunks of one work group get
+// block ids 8 apart (same XCD, launched together) and its A rows come from one L2:
+//   id = (w / 8) * 8 nchunk + chunk * 8 + w % 8.
 // The block stages its B chunk(s) in LDS once and reuses them for all 4 tpw row tiles;
 // every wave gathers its tiles' A operands straight into MFMA layout.
 template <bool kBF16, int KE, int NT>
 __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
                                                      const double* Z_stage, const float* bins,
                                                      const float* binsT, YArgs<float> args,
-                                                     int nchunk, int tpw) {
-    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT;
+                                                     int nchunk, int tpw, int bx, int nwork) {
+    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
+    constexpr int kBytes = kBF16 ? W * KBS * 2 : KP * S * 4;   // one B chunk
     __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
     __shared__ float zs[128];                         // Z of the stage
-    __shared__ __align__(16) float Bs[2][KP * S];     // B chunks [k][n]
-    const int ch = blockIdx.z % 3;
-    const int f = blockIdx.z / 3;
-    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
+    __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks
+    const int id = blockIdx.x;
+    const int rem = id % (8 * nchunk);
+    const int work = (id / (8 * nchunk)) * 8 + rem % 8;
+    const int chunk = rem / 8;
+    if (work >= nwork) return;                        // padding of the last 8 work groups
     const int N = g.N, NN = g.NN;
+    const int xr = work % bx;
+    const int grp = (work / bx) % N;
+    const int ch = (work / (bx * N)) % 3;
+    const int f = work / (bx * N * 3);
+    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
     const int M = ch == 0 ? g.nP : g.nD;
-    const int grp = blockIdx.y / nchunk;
-    const int n0 = (blockIdx.y - grp * nchunk) * W;
+    const int n0 = chunk * W;
     const int ntiles = (M + 15) / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int t_begin = (blockIdx.x * 4 + wv) * tpw;
+    const int t_begin = (xr * 4 + wv) * tpw;
     const int t_end = min(t_begin + tpw, ntiles);
     const bool two = ch == 2;
     const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
@@ -699,11 +713,16 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
         const int k = e / W, n = e - k * W;            // W is a compile-time constant
         const bool ok = k < N && n0 + n < N;
         const size_t ia = static_cast<size_t>(min(k, N - 1)) * N + min(n0 + n, N - 1);
-        const float x0 = V0[ia];
-        Bs[0][k * S + n] = ok ? x0 : 0.f;
-        if (two) {
-            const float x1 = V1[ia];
-            Bs[1][k * S + n] = ok ? x1 : 0.f;
+        const float x0 = ok ? V0[ia] : 0.f;
+        const float x1 = (two && ok) ? V1[ia] : 0.f;
+        if constexpr (kBF16) {
+            __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
+            Bh[n * KBS + k] = static_cast<__bf16>(x0);
+            if (two) Bh[W * KBS + n * KBS + k] = static_cast<__bf16>(x1);
+        } else {
+            float* Bf32 = reinterpret_cast<float*>(Braw);
+            Bf32[k * S + n] = x0;
+            if (two) Bf32[KP * S + k * S + n] = x1;
         }
     }
     __syncthreads();                                   // every thread of the block
@@ -712,12 +731,14 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
                               : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
     const size_t yoff = static_cast<size_t>(f) * M * NN;
+    const void* B0 = Braw;
+    const void* B1 = Braw + kBytes;
     if (two)
         y_tiles<kBF16, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                     Bs[0], Bs[1], args.Y[2] + yoff, args.Y[3] + yoff, lane);
+                                     B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane);
     else
         y_tiles<kBF16, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                      Bs[0], Bs[1], args.Y[ch] + yoff, nullptr, lane);
+                                      B0, B1, args.Y[ch] + yoff, nullptr, lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1206,10 +1227,12 @@ void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
     tpw = tpw <= 0 ? 1 : (tpw > maxt ? maxt : tpw);
     const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
     const int bx = (ntiles + 4 * tpw - 1) / (4 * tpw);
-    const dim3 grid(bx, g.N * nchunk, 3 * nf);
-    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT>), grid, dim3(kThreads), 0, s, g, b.fs,
-                       b.Z_stage, static_cast<const float*>(b.bins),
-                       static_cast<const float*>(b.binsT), a, nchunk, tpw);
+    const long nwork = static_cast<long>(bx) * g.N * 3 * nf;
+    const long nblocks = (nwork + 7) / 8 * 8 * nchunk;
+    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+                       dim3(kThreads), 0, s, g, b.fs, b.Z_stage, static_cast<const float*>(b.bins),
+                       static_cast<const float*>(b.binsT), a, nchunk, tpw, bx,
+                       static_cast<int>(nwork));
 }
 
 inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
@@ -1219,9 +1242,9 @@ inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int
         if (N <= 16) y_mfma_tpw<true, 8, 1>(s, g, b, nf, a, tpw);
         else if (N <= 32) y_mfma_tpw<true, 8, 2>(s, g, b, nf, a, tpw);
         else if (N <= 48) y_mfma_tpw<true, 16, 3>(s, g, b, nf, a, tpw);
-        else if (N <= 64) y_mfma_tpw<true, 16, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 96) y_mfma_tpw<true, 24, 2>(s, g, b, nf, a, tpw);
-        else y_mfma_tpw<true, 32, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 64) y_mfma_tpw<true, 16, 4>(s, g, b, nf, a, tpw);
+        else if (N <= 96) y_mfma_tpw<true, 24, 3>(s, g, b, nf, a, tpw);
+        else y_mfma_tpw<true, 32, 4>(s, g, b, nf, a, tpw);
     } else {
         if (N <= 16) y_mfma_tpw<false, 4, 1>(s, g, b, nf, a, tpw);
         else if (N <= 32) y_mfma_tpw<false, 8, 2>(s, g, b, nf, a, tpw);
