@@ -168,6 +168,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.d_pairs = L.take<int>(NN);
     b.item_q = L.take<int>(hg.item_q.size());
     b.item_p0 = L.take<int>(hg.item_p0.size());
+    b.item_rec = L.take<int>(hg.item_rec.size());
     b.fs = L.take<FlowState>(B);
     b.z_lnT = L.take<double>(static_cast<size_t>(B) * nz);
     b.z_tab = L.take<double>(static_cast<size_t>(B) * nz * N);
@@ -431,7 +432,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.pp_off = h->b.pp_off; g.pp_pairs = h->b.pp_pairs;
     g.cr_off = h->b.cr_off; g.cr_pairs = h->b.cr_pairs;
     g.d_off = h->b.d_off; g.d_pairs = h->b.d_pairs;
-    g.item_q = h->b.item_q; g.item_p0 = h->b.item_p0;
+    g.item_q = h->b.item_q; g.item_p0 = h->b.item_p0; g.item_rec = h->b.item_rec;
     for (int k = 0; k < 3; ++k) g.n_items[k] = hg.n_items[k];
     auto up = [&](void* dst, const void* src, size_t n) {
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, h->stream);
@@ -470,6 +471,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.d_pairs, hg.d_pairs);
     if (e == hipSuccess) e = upv(h->b.item_q, hg.item_q);
     if (e == hipSuccess) e = upv(h->b.item_p0, hg.item_p0);
+    if (e == hipSuccess) e = upv(h->b.item_rec, hg.item_rec);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;

@@ -41,6 +41,7 @@ struct HostGeometry {
     std::vector<int> pp_off, pp_pairs, cr_off, cr_pairs, d_off, d_pairs;
     // Phase-2b work items: (transfer, first pair) with at most 8 pairs each, per channel
     std::vector<int> item_q, item_p0;
+    std::vector<int> item_rec;       // [items][16]: transfer, pair count, channel, first pair, 8 pairs
     int n_items[3] = {0, 0, 0};
 };
 
@@ -84,6 +85,7 @@ struct DevGeom {
     const int* cr_off; const int* cr_pairs;
     const int* d_off;  const int* d_pairs;
     const int* item_q; const int* item_p0;
+    const int* item_rec;   // [items][16] (one 64-byte record per phase-2b work item)
     int n_items[3];
     const double* xi;      // [np]
     const int* patch;      // [np]
@@ -121,7 +123,7 @@ struct Buffers {
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
-    int* item_q; int* item_p0;
+    int* item_q; int* item_p0; int* item_rec;
     void* bins;                        // [B][nRp + nRd][NN] real, representative transfers
     void* binsT;                       // [B][nRd][NN] real, particle-hole bins transposed
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real

@@ -181,14 +181,22 @@ void build_pairs(HostGeometry& g) {
     const int chunk = 8;   // pairs per phase-2b work item (the kernel's kChunk)
     g.item_q.clear();
     g.item_p0.clear();
+    g.item_rec.clear();
     const std::vector<int>* offs[3] = {&g.pp_off, &g.cr_off, &g.d_off};
+    const std::vector<int>* prs[3] = {&g.pp_pairs, &g.cr_pairs, &g.d_pairs};
     for (int k = 0; k < 3; ++k) {
         const std::vector<int>& off = *offs[k];
+        const std::vector<int>& pr = *prs[k];
         int n = 0;
         for (size_t q = 0; q + 1 < off.size(); ++q)
             for (int p = off[q]; p < off[q + 1]; p += chunk) {
                 g.item_q.push_back(static_cast<int>(q));
                 g.item_p0.push_back(p);
+                // record: transfer, pair count, 2 spare, then the pairs (padded with the last)
+                const int cnt = std::min(chunk, off[q + 1] - p);
+                int rec[16] = {static_cast<int>(q), cnt, k, p};
+                for (int i = 0; i < chunk; ++i) rec[4 + i] = pr[p + std::min(i, cnt - 1)];
+                g.item_rec.insert(g.item_rec.end(), rec, rec + 16);
                 ++n;
             }
         g.n_items[k] = n;

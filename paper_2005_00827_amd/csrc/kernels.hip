@@ -628,12 +628,9 @@ template <bool kBF16, int KE, int NT, bool kTwo>
 __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, int NN, int N,
                                int M, int grp, int n0, int t_begin, int t_end, const int* pis,
                                const float* zs, const void* Bs0, const void* Bs1, float* Y0,
-                               float* Y1, int lane) {
+                               float* Y1, int lane, int r0, int o0, int r1, int o1) {
     const int col = lane & 15;
     const float zg = zs[grp];
-    int r0, o0, r1, o1;
-    tile_rep(qrep, qg, M, t_begin, col, r0, o0);
-    tile_rep(qrep, qg, M, t_begin + 1, col, r1, o1);
     float a0[KE], a1[KE];
     gather_a<kBF16, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, lane);
     for (int tile = t_begin; tile < t_end; ++tile) {
@@ -703,6 +700,10 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const bool two = ch == 2;
     const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
     const int* qg = ch == 0 ? g.qg_pp : g.qg_ph;
+    // the first two tiles' transfer tables need no LDS: in flight across the barrier
+    int r0, o0, r1, o1;
+    tile_rep(qrep, qg, M, t_begin, lane & 15, r0, o0);
+    tile_rep(qrep, qg, M, t_begin + 1, lane & 15, r1, o1);
     for (int i = threadIdx.x; i < 8 * N; i += kThreads) pis[i] = g.pinv[i];
     if (threadIdx.x < N) zs[threadIdx.x] = static_cast<float>(Z_stage[static_cast<size_t>(f) * N + threadIdx.x]);
     const size_t N3 = static_cast<size_t>(NN) * N;
@@ -735,10 +736,11 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const void* B1 = Braw + kBytes;
     if (two)
         y_tiles<kBF16, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                     B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane);
+                                     B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane, r0, o0,
+                                     r1, o1);
     else
         y_tiles<kBF16, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                      B0, B1, args.Y[ch] + yoff, nullptr, lane);
+                                      B0, B1, args.Y[ch] + yoff, nullptr, lane, r0, o0, r1, o1);
 }
 
 // ------------------------------------------------------------------------------------
@@ -858,12 +860,12 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     if (!running(fs, f)) return;
     const int it = blockIdx.x;
     const int kind = it < g.n_items[0] ? 0 : (it < g.n_items[0] + g.n_items[1] ? 1 : 2);
-    const int q = g.item_q[it];
-    const int p0 = g.item_p0[it];
+    // one record per item (uniform address: scalar loads): transfer, count, pairs
+    const int* rec = g.item_rec + static_cast<size_t>(it) * 16;
+    const int q = rec[0];
+    const int cnt = rec[1];
+    const int* pairs = rec + 4;
     const int nq = kind == 0 ? g.nP : g.nD;
-    const int* off = kind == 0 ? g.pp_off : (kind == 1 ? g.cr_off : g.d_off);
-    const int* pairs = kind == 0 ? g.pp_pairs : (kind == 1 ? g.cr_pairs : g.d_pairs);
-    const int cnt = min(kChunk, off[q + 1] - p0);
     const int N = g.N, NN = g.NN;
     const size_t N3 = static_cast<size_t>(NN) * N;
     // k slot part of this channel: [slot][flow][channel][N^3]
@@ -872,7 +874,7 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     if (!(ch & bit)) {   // a channel that is switched off contributes zero
         for (int e = threadIdx.x; e < cnt * N; e += blockDim.x) {
             const int i = e / N, n = e - i * N;
-            const int xy = pairs[p0 + i];
+            const int xy = pairs[i];
             const int a = xy / N, c = xy - a * N;
             if (kind == 0) Kf[static_cast<size_t>(xy) * N + n] = R(0);
             else if (kind == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = R(0);
@@ -887,9 +889,9 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
     R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
     R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
-    if (kind == 0) contract_item<R, 0>(g, V, VA, VC, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
-    else if (kind == 1) contract_item<R, 1>(g, V, VA, VC, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
-    else contract_item<R, 2>(g, V, VA, VC, Ya, Yb, pairs + p0, cnt, vu, vw, Kf);
+    if (kind == 0) contract_item<R, 0>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    else if (kind == 1) contract_item<R, 1>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    else contract_item<R, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
 }
 
 // ------------------------------------------------------------------------------------
