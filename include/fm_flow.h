@@ -67,8 +67,11 @@ enum { FM_RK4_FIXED = 0, FM_RK45_DOPRI = 1 };
  *   FM_FP32          binned loop sums and contractions in single precision
  *   FM_FP32_BF16MFMA single-precision loop sums; the grouped contractions on bf16 matrix
  *                    cores with single-precision accumulation
- *   FM_FP64_DIRECT   direct double-precision loop sums over every loop point, no binning */
-enum { FM_FP64 = 0, FM_FP32 = 1, FM_FP32_BF16MFMA = 2, FM_FP64_DIRECT = 3 };
+ *   FM_FP64_DIRECT   direct double-precision loop sums over every loop point, no binning
+ *   FM_FP32_BF16X3   as FM_FP32_BF16MFMA, with each operand split into two bf16 parts and
+ *                    three bf16 products per contraction step (about 16 significant bits
+ *                    per product, close to single precision at bf16 matrix-core rates) */
+enum { FM_FP64 = 0, FM_FP32 = 1, FM_FP32_BF16MFMA = 2, FM_FP64_DIRECT = 3, FM_FP32_BF16X3 = 4 };
 
 /* Channel mask (for ablations of the flow equation). */
 enum { FM_CH_PP = 1, FM_CH_CR = 2, FM_CH_D = 4, FM_CH_ALL = 7 };
@@ -93,7 +96,8 @@ typedef struct {
                                  ln(T_end/T0)/200 and 1e-8 |ln(T_end/T0)| */
     double v_max;             /* stop when max|V| > v_max (0 selects 20) */
     unsigned channels;        /* FM_CH_* mask (0 selects FM_CH_ALL) */
-    int precision;            /* FM_FP64 | FM_FP32 | FM_FP32_BF16MFMA | FM_FP64_DIRECT */
+    int precision;            /* FM_FP64 | FM_FP32 | FM_FP32_BF16MFMA | FM_FP64_DIRECT |
+                                 FM_FP32_BF16X3 */
     int n_zT;                 /* 0: no quasi-particle feedback (Z = 1) */
     const double *z_lnT;      /* host [n_zT], ascending ln T nodes; copied */
     const double *z_table;    /* host [n_zT][N], 0 < Z <= 1, linear in ln T between nodes,

@@ -84,7 +84,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (!(c.T0 > c.T_end) || !(c.T_end > 0.0)) { why = "need T0 > T_end > 0"; return FM_EINVAL; }
     if (c.integrator != FM_RK4_FIXED && c.integrator != FM_RK45_DOPRI) { why = "bad integrator"; return FM_EINVAL; }
     if (c.integrator == FM_RK4_FIXED && c.n_steps < 1) { why = "RK4 needs n_steps >= 1"; return FM_EINVAL; }
-    if (c.precision < FM_FP64 || c.precision > FM_FP64_DIRECT) { why = "bad precision"; return FM_EINVAL; }
+    if (c.precision < FM_FP64 || c.precision > FM_FP32_BF16X3) { why = "bad precision"; return FM_EINVAL; }
     if (c.max_batch < 1) { why = "max_batch must be >= 1"; return FM_EINVAL; }
     if (c.n_zT < 0 || (c.n_zT > 0 && (!c.z_lnT || !c.z_table))) { why = "bad Z table"; return FM_EINVAL; }
     for (int i = 1; i < c.n_zT; ++i)
@@ -200,6 +200,17 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     return FM_OK;
 }
 
+// Phase-2a product mode of a precision: 0 vector units (double), 1 f32 matrix cores, 2 bf16,
+// 3 split bf16.
+int mma_mode(int precision) {
+    switch (precision) {
+        case FM_FP32: return 1;
+        case FM_FP32_BF16MFMA: return 2;
+        case FM_FP32_BF16X3: return 3;
+        default: return 0;
+    }
+}
+
 // Timed launch group: records events around `fn` when timing is on.
 template <typename F>
 void timed(fm_flow* h, int id, F&& fn) {
@@ -237,7 +248,7 @@ void rhs_launch(fm_flow* h, int nf, int slot) {
         timed(h, T_DIRECT, [&] { launch_direct(h->stream, h->g, h->b, nf, ch, slot); });
         return;
     }
-    const int mma = h->cfg.precision == FM_FP32_BF16MFMA ? 2 : (h->cfg.precision == FM_FP32 ? 1 : 0);
+    const int mma = mma_mode(h->cfg.precision);
     timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch, mma, h->tpw); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
@@ -260,7 +271,7 @@ std::map<TuneKey, int> g_tune;
 
 int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     const fm_config& c = h->cfg;
-    const int mma = c.precision == FM_FP32_BF16MFMA ? 2 : (c.precision == FM_FP32 ? 1 : 0);
+    const int mma = mma_mode(c.precision);
     if (h->dbl || h->direct || mma == 0 || c.N > 128) return FM_OK;
     if (c.tile_rows > 0) { h->tpw = c.tile_rows; return FM_OK; }
     if (h->tuned_nf == nf) return FM_OK;

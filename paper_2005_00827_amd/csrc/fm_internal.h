@@ -147,7 +147,8 @@ struct ErrWeights {
 // Stage argument and operand layouts; with bins, phase 1 of the stage in the same launch.
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
                   int nf, const StageCoef& sc, int write_new, const double* Vbase);
-// mma: 0 VALU, 1 f32 matrix cores, 2 bf16 matrix cores (single precision only, N <= 128);
+// mma: 0 VALU, 1 f32 matrix cores, 2 bf16 matrix cores, 3 split-bf16 matrix cores (single
+// precision only, N <= 128);
 // tpw: row tiles per wavefront on matrix cores (1, 2, 4; 0 = by size)
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
               int mma, int tpw);

@@ -534,16 +534,20 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
 //     the direct channel two such operands, va and vc, share one A);
 //   A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k) is gathered per row tile, the patch
 //     permutations and Z read from LDS.
-// kBF16 = false: v_mfma_f32_16x16x4_f32, lane holds k = 4 e + lane / 16 (e < KE);
-// kBF16 = true:  v_mfma_f32_16x16x32_bf16, k = 32 (e / 8) + 8 (lane / 16) + e % 8.
+// kM = 0: v_mfma_f32_16x16x4_f32, lane holds k = 4 e + lane / 16 (e < KE);
+// kM = 1: v_mfma_f32_16x16x32_bf16, k = 32 (e / 8) + 8 (lane / 16) + e % 8, operands rounded
+//         to bf16;
+// kM = 2: the same layout with each operand split x = hi + lo (both bf16, lo = bf16(x - hi)):
+//         A B = hi hi + hi lo + lo hi in three bf16 MFMAs (lo lo, of relative size 2^-16
+//         squared, dropped), about 16 significant bits per product, f32 accumulation.
 // A row and B column = lane % 16; D row = 4 (lane / 16) + r, column = lane % 16.
 // k >= N (and n >= N) are zero in both operands.
 typedef float fm_f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 fm_bf8 __attribute__((ext_vector_type(8)));
 
-template <bool kBF16>
+template <int kM>
 __device__ inline int mfma_k(int e, int lane) {
-    return kBF16 ? 32 * (e >> 3) + 8 * (lane >> 4) + (e & 7) : 4 * e + (lane >> 4);
+    return kM > 0 ? 32 * (e >> 3) + 8 * (lane >> 4) + (e & 7) : 4 * e + (lane >> 4);
 }
 
 // LDS row stride of a B chunk of W = 16 NT columns: a fragment read touches rows k..k+3
@@ -552,30 +556,46 @@ template <int NT>
 constexpr int b_stride() { return (16 * NT) % 32 == 16 ? 16 * NT : 16 * NT + 16; }
 
 // One 16-row tile on the matrix cores: c0 += A B0 (and c1 += A B1 for the direct channel).
-// FP32: B fragments read from LDS as [k][n] floats (stride b_stride); BF16: B staged as
-// bf16, transposed [n][k] with row stride KP + 8, so a lane's 8 consecutive k of one column
-// are a single 16-byte read.  Both zero beyond N.
-template <bool kBF16, int KE, int NT, bool kTwo>
+// kM = 0: B fragments read from LDS as [k][n] floats (stride b_stride).  kM > 0: B staged as
+// bf16, transposed [n][k] with row stride 4 KE + 8, so a lane's 8 consecutive k of one column
+// are a single 16-byte read; kM = 2 keeps a second plane with the low parts right after the
+// first.  Both zero beyond N.
+template <int kM, int KE, int NT, bool kTwo>
 __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const void* Bs1v,
                                  fm_f4 (&c0)[NT], fm_f4 (&c1)[NT], int lane) {
     const int col = lane & 15;
-    if constexpr (kBF16) {
+    if constexpr (kM > 0) {
         constexpr int KBS = 4 * KE + 8;
+        constexpr int PL = 16 * NT * KBS;              // elements per plane
         const __bf16* Bh0 = static_cast<const __bf16*>(Bs0v);
         const __bf16* Bh1 = static_cast<const __bf16*>(Bs1v);
 #pragma unroll
         for (int s = 0; s < KE / 8; ++s) {
-            fm_bf8 av;
+            fm_bf8 ah, al;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = static_cast<__bf16>(a[8 * s + e]);
+            for (int e = 0; e < 8; ++e) {
+                ah[e] = static_cast<__bf16>(a[8 * s + e]);
+                if constexpr (kM == 2) al[e] = static_cast<__bf16>(a[8 * s + e] - static_cast<float>(ah[e]));
+            }
             const int kb = 32 * s + 8 * (lane >> 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const fm_bf8 bv = *reinterpret_cast<const fm_bf8*>(Bh0 + (16 * t + col) * KBS + kb);
-                c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c0[t], 0, 0, 0);
+                const int o = (16 * t + col) * KBS + kb;
+                const fm_bf8 bh = *reinterpret_cast<const fm_bf8*>(Bh0 + o);
+                if constexpr (kM == 2) {
+                    const fm_bf8 bl = *reinterpret_cast<const fm_bf8*>(Bh0 + PL + o);
+                    c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c0[t], 0, 0, 0);
+                    c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c0[t], 0, 0, 0);
+                }
+                c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c0[t], 0, 0, 0);
                 if constexpr (kTwo) {
-                    const fm_bf8 bw = *reinterpret_cast<const fm_bf8*>(Bh1 + (16 * t + col) * KBS + kb);
-                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw, c1[t], 0, 0, 0);
+                    const fm_bf8 wh = *reinterpret_cast<const fm_bf8*>(Bh1 + o);
+                    if constexpr (kM == 2) {
+                        const fm_bf8 wl = *reinterpret_cast<const fm_bf8*>(Bh1 + PL + o);
+                        c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, c1[t], 0, 0, 0);
+                        c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wl, c1[t], 0, 0, 0);
+                    }
+                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wh, c1[t], 0, 0, 0);
                 }
             }
         }
@@ -598,7 +618,7 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
 
 // A operand of one row tile: lane row q = 16 tile + lane % 16 (rep r, operation o), k-values
 // of the lane: A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k), zero for k >= N.
-template <bool kBF16, int KE>
+template <int kM, int KE>
 __device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, int grp,
                                 int rep, int op, const int* pis, const float* zs, float zg,
                                 int lane) {
@@ -606,7 +626,7 @@ __device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, 
     const float* row = Bf + static_cast<size_t>(rep) * NN + pi[grp] * N;
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
-        const int k = mfma_k<kBF16>(e, lane);
+        const int k = mfma_k<kM>(e, lane);
         const int kc = min(k, N - 1);
         const float x = row[pi[kc]];
         a[e] = k < N ? x * (zg * zs[kc]) : 0.f;
@@ -624,7 +644,7 @@ __device__ inline void tile_rep(const int* qrep, const int* qg, int M, int tile,
 
 // Row tiles [t_begin, t_end) of one wavefront: the A gather of tile t+1 and the table
 // entries of tile t+2 are in flight while tile t runs on the matrix cores and is stored.
-template <bool kBF16, int KE, int NT, bool kTwo>
+template <int kM, int KE, int NT, bool kTwo>
 __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, int NN, int N,
                                int M, int grp, int n0, int t_begin, int t_end, const int* pis,
                                const float* zs, const void* Bs0, const void* Bs1, float* Y0,
@@ -632,17 +652,17 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
     const int col = lane & 15;
     const float zg = zs[grp];
     float a0[KE], a1[KE];
-    gather_a<kBF16, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, lane);
+    gather_a<kM, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, lane);
     for (int tile = t_begin; tile < t_end; ++tile) {
         // B fragments are re-read from LDS every tile instead of being kept in registers
         asm volatile("" ::: "memory");
         int r2, o2;
         tile_rep(qrep, qg, M, tile + 2, col, r2, o2);
-        if (tile + 1 < t_end) gather_a<kBF16, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, lane);
+        if (tile + 1 < t_end) gather_a<kM, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, lane);
         fm_f4 c0[NT], c1[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u) c0[u] = c1[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
-        mfma_tile<kBF16, KE, NT, kTwo>(a0, Bs0, Bs1, c0, c1, lane);
+        mfma_tile<kM, KE, NT, kTwo>(a0, Bs0, Bs1, c0, c1, lane);
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             const int n = n0 + 16 * u + col;
@@ -670,13 +690,13 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
 //   id = (w / 8) * 8 nchunk + chunk * 8 + w % 8.
 // The block stages its B chunk(s) in LDS once and reuses them for all 4 tpw row tiles;
 // every wave gathers its tiles' A operands straight into MFMA layout.
-template <bool kBF16, int KE, int NT>
+template <int kM, int KE, int NT>
 __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
                                                      const double* Z_stage, const float* bins,
                                                      const float* binsT, YArgs<float> args,
                                                      int nchunk, int tpw, int bx, int nwork) {
     constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
-    constexpr int kBytes = kBF16 ? W * KBS * 2 : KP * S * 4;   // one B chunk
+    constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
     __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
     __shared__ float zs[128];                         // Z of the stage
     __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks
@@ -716,10 +736,15 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
         const size_t ia = static_cast<size_t>(min(k, N - 1)) * N + min(n0 + n, N - 1);
         const float x0 = ok ? V0[ia] : 0.f;
         const float x1 = (two && ok) ? V1[ia] : 0.f;
-        if constexpr (kBF16) {
+        if constexpr (kM > 0) {
             __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
-            Bh[n * KBS + k] = static_cast<__bf16>(x0);
-            if (two) Bh[W * KBS + n * KBS + k] = static_cast<__bf16>(x1);
+            const __bf16 h0 = static_cast<__bf16>(x0), h1 = static_cast<__bf16>(x1);
+            Bh[n * KBS + k] = h0;
+            if (two) Bh[kBytes / 2 + n * KBS + k] = h1;
+            if constexpr (kM == 2) {                   // low parts: the second plane
+                Bh[W * KBS + n * KBS + k] = static_cast<__bf16>(x0 - static_cast<float>(h0));
+                if (two) Bh[kBytes / 2 + W * KBS + n * KBS + k] = static_cast<__bf16>(x1 - static_cast<float>(h1));
+            }
         } else {
             float* Bf32 = reinterpret_cast<float*>(Braw);
             Bf32[k * S + n] = x0;
@@ -735,11 +760,11 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const void* B0 = Braw;
     const void* B1 = Braw + kBytes;
     if (two)
-        y_tiles<kBF16, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
+        y_tiles<kM, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
                                      B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane, r0, o0,
                                      r1, o1);
     else
-        y_tiles<kBF16, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
+        y_tiles<kM, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
                                       B0, B1, args.Y[ch] + yoff, nullptr, lane, r0, o0, r1, o1);
 }
 
@@ -1220,7 +1245,7 @@ void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, i
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
 // tiles per wave); row tiles per wavefront `tpw` is a tuning choice (0: one).
-template <bool kBF16, int KE, int NT>
+template <int kM, int KE, int NT>
 void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                 const YArgs<float>& a, int tpw) {
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
@@ -1231,29 +1256,36 @@ void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
     const int bx = (ntiles + 4 * tpw - 1) / (4 * tpw);
     const long nwork = static_cast<long>(bx) * g.N * 3 * nf;
     const long nblocks = (nwork + 7) / 8 * 8 * nchunk;
-    hipLaunchKernelGGL((k_y_mfma<kBF16, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+    hipLaunchKernelGGL((k_y_mfma<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
                        dim3(kThreads), 0, s, g, b.fs, b.Z_stage, static_cast<const float*>(b.bins),
                        static_cast<const float*>(b.binsT), a, nchunk, tpw, bx,
                        static_cast<int>(nwork));
 }
 
 inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
-                          const YArgs<float>& a, bool bf16, int tpw) {
+                          const YArgs<float>& a, int mode, int tpw) {
     const int N = g.N;
-    if (bf16) {
-        if (N <= 16) y_mfma_tpw<true, 8, 1>(s, g, b, nf, a, tpw);
-        else if (N <= 32) y_mfma_tpw<true, 8, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 48) y_mfma_tpw<true, 16, 3>(s, g, b, nf, a, tpw);
-        else if (N <= 64) y_mfma_tpw<true, 16, 4>(s, g, b, nf, a, tpw);
-        else if (N <= 96) y_mfma_tpw<true, 24, 3>(s, g, b, nf, a, tpw);
-        else y_mfma_tpw<true, 32, 4>(s, g, b, nf, a, tpw);
+    if (mode == 2) {         // bf16 operands
+        if (N <= 16) y_mfma_tpw<1, 8, 1>(s, g, b, nf, a, tpw);
+        else if (N <= 32) y_mfma_tpw<1, 8, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 48) y_mfma_tpw<1, 16, 3>(s, g, b, nf, a, tpw);
+        else if (N <= 64) y_mfma_tpw<1, 16, 4>(s, g, b, nf, a, tpw);
+        else if (N <= 96) y_mfma_tpw<1, 24, 3>(s, g, b, nf, a, tpw);
+        else y_mfma_tpw<1, 32, 4>(s, g, b, nf, a, tpw);
+    } else if (mode == 3) {  // split bf16 operands (two planes in LDS)
+        if (N <= 16) y_mfma_tpw<2, 8, 1>(s, g, b, nf, a, tpw);
+        else if (N <= 32) y_mfma_tpw<2, 8, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 48) y_mfma_tpw<2, 16, 3>(s, g, b, nf, a, tpw);
+        else if (N <= 64) y_mfma_tpw<2, 16, 4>(s, g, b, nf, a, tpw);
+        else if (N <= 96) y_mfma_tpw<2, 24, 3>(s, g, b, nf, a, tpw);
+        else y_mfma_tpw<2, 32, 2>(s, g, b, nf, a, tpw);
     } else {
-        if (N <= 16) y_mfma_tpw<false, 4, 1>(s, g, b, nf, a, tpw);
-        else if (N <= 32) y_mfma_tpw<false, 8, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 48) y_mfma_tpw<false, 12, 3>(s, g, b, nf, a, tpw);
-        else if (N <= 64) y_mfma_tpw<false, 16, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 96) y_mfma_tpw<false, 24, 2>(s, g, b, nf, a, tpw);
-        else y_mfma_tpw<false, 32, 2>(s, g, b, nf, a, tpw);
+        if (N <= 16) y_mfma_tpw<0, 4, 1>(s, g, b, nf, a, tpw);
+        else if (N <= 32) y_mfma_tpw<0, 8, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 48) y_mfma_tpw<0, 12, 3>(s, g, b, nf, a, tpw);
+        else if (N <= 64) y_mfma_tpw<0, 16, 2>(s, g, b, nf, a, tpw);
+        else if (N <= 96) y_mfma_tpw<0, 24, 2>(s, g, b, nf, a, tpw);
+        else y_mfma_tpw<0, 32, 2>(s, g, b, nf, a, tpw);
     }
 }
 
@@ -1273,7 +1305,7 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     if constexpr (sizeof(R) == 4) {
         if (mma > 0 && g.N <= 128) {
-            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma == 2, tpw);
+            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma, tpw);
             return;
         }
     }

@@ -19,11 +19,12 @@ LIB_PATH = os.path.join(HERE, "libfmflow.so")
 FM_OK, FM_EINVAL, FM_ENOMEM, FM_EDEVICE, FM_ESTATE = 0, -1, -2, -3, -4
 GEOM_ANGULAR, GEOM_IDENTITY = 0, 1
 RK4_FIXED, RK45_DOPRI = 0, 1
-FP64, FP32, FP32_BF16MFMA, FP64_DIRECT = 0, 1, 2, 3
+FP64, FP32, FP32_BF16MFMA, FP64_DIRECT, FP32_BF16X3 = 0, 1, 2, 3, 4
 CH_PP, CH_CR, CH_D, CH_ALL = 1, 2, 4, 7
 RUNNING, DIVERGED, NONFINITE, REACHED_TEND, STEPFAIL = 0, 1, 2, 3, 4
 
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": FP32_BF16MFMA, "fp64_direct": FP64_DIRECT}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": FP32_BF16MFMA, "fp64_direct": FP64_DIRECT,
+              "bf16x3": FP32_BF16X3}
 INTEGRATORS = {"rk4": RK4_FIXED, "rk45": RK45_DOPRI}
 
 # every entry point declared in include/fm_flow.h
