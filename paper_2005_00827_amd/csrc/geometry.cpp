@@ -209,6 +209,7 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
     const int N = cfg.N, L = cfg.L;
     char buf[256];
     if (L < 2 || (L % 2) != 0) { err = "L must be even and >= 2"; return false; }
+    if (L > 2048) { err = "L must be <= 2048"; return false; }
     if (cfg.geometry == FM_GEOM_IDENTITY) {
         if (N != L * L) { err = "identity geometry needs N == L*L"; return false; }
     } else if (cfg.geometry == FM_GEOM_ANGULAR) {

@@ -192,6 +192,38 @@ __device__ inline double phi_dd_pt(double2 u, double2 v) { return phi_dd<double>
 __device__ inline float4 flip(float4 v) { return make_float4(-v.x, -v.y, v.z, v.w); }
 __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 
+// Single-precision weight of one loop-point pair for phase 1, straight from xi: the same
+// values as phi_dd_pt(point_q(.), point_q(.)), with tanh entering only as |a| tanh|a| and
+// tanh^2 (no sign), and phi', phi3 and the trapezoid evaluated only when a lane of the
+// wave has |a - b| < 0.05 (the branch is uniform over the wave).
+__device__ inline float pair_weight(float xu, float xv, float inv2T, bool pp) {
+    const float a = xu * inv2T;
+    const float b0 = xv * inv2T;
+    const float b = pp ? -b0 : b0;
+    const float aa = fabsf(a), ab = fabsf(b);
+    const float ea = __expf(-2.0f * aa), eb = __expf(-2.0f * ab);
+    const float ra = __builtin_amdgcn_rcpf(1.0f + ea), rb = __builtin_amdgcn_rcpf(1.0f + eb);
+    const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;   // sech^2
+    const float d = a - b;
+    float w = (a * sa - b * sb) * __builtin_amdgcn_rcpf(d);
+    const bool near = fabsf(d) < 0.05f;
+    if (__ballot(near)) {
+        if (near) {
+            const float ta = (1.0f - ea) * ra, tb = (1.0f - eb) * rb;     // tanh|a|, tanh|b|
+            const float xa = aa * ta, xb = ab * tb, qa = ta * ta, qb = tb * tb;
+            const float d1 = sa * (1.0f - 2.0f * xa) + sb * (1.0f - 2.0f * xb);
+            const float d3 = sa * (-6.0f * (1.0f - 3.0f * qa) + 8.0f * xa * (2.0f - 3.0f * qa)) +
+                             sb * (-6.0f * (1.0f - 3.0f * qb) + 8.0f * xb * (2.0f - 3.0f * qb));
+            w = 0.5f * d1 - (d * d) * d3 * (1.0f / 24.0f);
+        }
+    }
+    return w;
+}
+__device__ inline double pair_weight(double xu, double xv, double twoT, bool pp) {
+    const double2 u = point_q(xu, twoT), v = point_q(xv, twoT);
+    return phi_dd_pt(u, pp ? flip(v) : v);
+}
+
 // ------------------------------------------------------------------------------------
 // Phase 1: bins of the representative transfers.  One 1024-thread block per
 // (representative, flow) accumulates the N x N bin matrix in LDS and stores it scaled by
@@ -298,6 +330,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int nrow = half ? hy.h1 + hy.h2 : L;            // rows visited in full
     const int ncol = hx.h1 + hx.h2;                        // columns visited in a fixed row
     const int npt = nrow * L + (half ? hy.nfix * ncol : 0);
+    const float invL = 1.0f / static_cast<float>(L);
     R* acc = kMode == 0 ? lb : out;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) acc[i] = R(0);
     if (kMode == 1) __threadfence();
@@ -318,16 +351,12 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
             const int p = min((u0 + i) * 16 + s, npt - 1);
-            int jx, jy;
-            if (p < nrow * L) {
-                const int rr = p / L;
-                jx = p - rr * L;
-                jy = half ? half_map(hy, rr) : rr;
-            } else {                                       // a row fixed by s
-                const int q2 = p - nrow * L, fr = q2 / ncol;
-                jy = half_fix(hy, fr, L);
-                jx = half_map(hx, q2 - fr * ncol);
-            }
+            // p < nrow L: row rr of the visited rows; else column of a row fixed by s
+            const int rr = static_cast<int>((p + 0.5f) * invL);       // p / L (L <= 2048)
+            const int q2 = p - nrow * L, fr = q2 >= ncol ? 1 : 0;
+            const bool mainpart = q2 < 0;
+            const int jx = mainpart ? p - rr * L : half_map(hx, q2 - fr * ncol);
+            const int jy = mainpart ? (half ? half_map(hy, rr) : rr) : half_fix(hy, fr, L);
             int px = pp ? mx - jx - 1 : jx + mx;
             int py = pp ? my - jy - 1 : jy + my;
             px += px < 0 ? L : (px >= L ? -L : 0);
@@ -338,9 +367,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
             const bool ok = u0 + i < u_end && (u0 + i) * 16 + s < npt;
-            const PT pu = point_q(xu[i], tp);
-            const PT pv = point_q(xv[i], tp);
-            const R w = phi_dd_pt(pu, pp ? flip(pv) : pv);
+            const R w = pair_weight(xu[i], xv[i], tp, pp);
             R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
             const int key = pa[i] * N + pq[i];
             const int key2 = pp ? pq[i] * N + pa[i] : inv_patch(g, pq[i]) * N + inv_patch(g, pa[i]);
@@ -368,9 +395,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
         int qa, qb;
         xi_patch(g, jy * L + jx, xa, qa);
         xi_patch(g, py * L + px, xb, qb);
-        const PT pu = point_q(xa, tp);
-        const PT pv = point_q(xb, tp);
-        const R w = phi_dd_pt(pu, pp ? flip(pv) : pv);
+        const R w = pair_weight(xa, xb, tp, pp);
         atomicAdd(&acc[qa * N + qb], kMode == 0 ? w : w * scale);
     }
     if (kMode == 1) __threadfence();
