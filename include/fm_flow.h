@@ -160,6 +160,16 @@ int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0
 int fm_geometry_query(const fm_config *cfg, double *xi, int *patch, int *anchor, int *n_pp,
                       int *n_ph, double *margin, int *n_rep);
 
+/* Measurement: average duration (milliseconds) of one launch of a right-hand-side kernel
+ * group on the state the handle holds (the first `batch` flows, replayed as running at their
+ * current temperature; their status is restored): group 0 stage argument and phase 1,
+ * 1 phase-2a products, 2 phase-2b contraction (the direct kernel in FM_FP64_DIRECT).  The
+ * group is launched `reps` times back to back on cfg->stream between two HIP events; every
+ * launch recomputes the same products from the same inputs.  It overwrites the stage
+ * operands, bins, products and k slot 0, all of which the next integrator step recomputes.
+ * Synchronous.  FM_EINVAL for a bad group, batch or reps. */
+int fm_flow_kernel_time(fm_flow *h, int group, int batch, int reps, double *avg_ms);
+
 /* Per-kernel event timings of the last fm_flow_rhs / fm_flow_step / fm_flow_run_batch call
  * (milliseconds, summed over launches), when enabled with fm_flow_set_timing(h, 1).
  * names[i] points to static strings.  Returns the number of entries written. */

@@ -121,7 +121,10 @@ struct fm_flow {
     // timings
     bool timing = false;
     std::vector<hipEvent_t> ev;
-    std::vector<std::pair<int, int>> ev_use;  // (kernel id, event index of start)
+    std::vector<std::pair<int, int>> ev_use;  // (kernel id, event index of start; end = start + 1)
+    int ev_last = -1;                  // event ending the last timed group, if nothing followed
+    size_t ev_next = 0;                // next free event
+    std::vector<int> ev_end;           // end event of each entry of ev_use
     double t_ms[16] = {0};
     int t_n[16] = {0};
 };
@@ -211,33 +214,53 @@ int mma_mode(int precision) {
     }
 }
 
-// Timed launch group: records events around `fn` when timing is on.
+// Timed launch group: records events around `fn` when timing is on.  Back-to-back groups
+// share one event (the end of one is the start of the next), so an interval holds one
+// event record and matches a profiler's duration of serialized kernels.  Untimed work
+// between groups must call untimed() first.
 template <typename F>
 void timed(fm_flow* h, int id, F&& fn) {
     if (!h->timing) { fn(); return; }
-    const size_t i = h->ev_use.size() * 2;
-    while (h->ev.size() < i + 2) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { fn(); return; }
-        h->ev.push_back(e);
+    auto ev_at = [&](size_t i) -> bool {
+        while (h->ev.size() <= i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            h->ev.push_back(e);
+        }
+        return true;
+    };
+    int start = h->ev_last;
+    if (start < 0) {
+        start = static_cast<int>(h->ev_next);
+        if (!ev_at(start)) { fn(); return; }
+        (void)hipEventRecord(h->ev[start], h->stream);
+        ++h->ev_next;
     }
-    (void)hipEventRecord(h->ev[i], h->stream);
+    const int end = static_cast<int>(h->ev_next);
+    if (!ev_at(end)) { fn(); h->ev_last = -1; return; }
     fn();
-    (void)hipEventRecord(h->ev[i + 1], h->stream);
-    h->ev_use.emplace_back(id, static_cast<int>(i));
+    (void)hipEventRecord(h->ev[end], h->stream);
+    ++h->ev_next;
+    h->ev_use.emplace_back(id, start);
+    h->ev_end.push_back(end);
+    h->ev_last = end;
 }
+void untimed(fm_flow* h) { h->ev_last = -1; }
 
 void collect_timings(fm_flow* h) {
-    if (!h->timing || h->ev_use.empty()) return;
+    if (!h->timing || h->ev_use.empty()) { h->ev_last = -1; h->ev_next = 0; return; }
     (void)hipStreamSynchronize(h->stream);
-    for (auto& u : h->ev_use) {
+    for (size_t k = 0; k < h->ev_use.size(); ++k) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h->ev[u.second], h->ev[u.second + 1]) == hipSuccess) {
-            h->t_ms[u.first] += ms;
-            h->t_n[u.first] += 1;
+        if (hipEventElapsedTime(&ms, h->ev[h->ev_use[k].second], h->ev[h->ev_end[k]]) == hipSuccess) {
+            h->t_ms[h->ev_use[k].first] += ms;
+            h->t_n[h->ev_use[k].first] += 1;
         }
     }
     h->ev_use.clear();
+    h->ev_end.clear();
+    h->ev_last = -1;
+    h->ev_next = 0;
 }
 
 // One right-hand-side evaluation of the current stage operands into k slot `slot`.
@@ -515,6 +538,10 @@ void fm_flow_destroy(fm_flow* h) {
 int fm_flow_set_timing(fm_flow* h, int enable) {
     if (!h) return fail(FM_EINVAL, "null handle");
     h->timing = enable != 0;
+    h->ev_use.clear();
+    h->ev_end.clear();
+    h->ev_last = -1;
+    h->ev_next = 0;
     std::fill(std::begin(h->t_ms), std::end(h->t_ms), 0.0);
     std::fill(std::begin(h->t_n), std::end(h->t_n), 0);
     return FM_OK;
@@ -534,6 +561,54 @@ int fm_flow_timings(fm_flow* h, const char** names, double* ms, int* launches, i
     return n;
 }
 
+int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_ms) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
+    if (reps < 1 || !avg_ms) return fail(FM_EINVAL, "need reps >= 1 and an output");
+    if (group < 0 || group > 2 || (h->direct && group == 1))
+        return fail(FM_EINVAL, "group: 0 stage and phase 1, 1 phase 2a, 2 phase 2b");
+    // flows replayed as running at their current temperature; their status is restored
+    std::vector<FlowState> saved(batch);
+    HIPCHK(hipMemcpyAsync(saved.data(), h->b.fs, sizeof(FlowState) * batch, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<FlowState> run = saved;
+    for (auto& f : run) { f.status = FM_FLOW_RUNNING; f.ht = 0.0; }
+    HIPCHK(hipMemcpyAsync(h->b.fs, run.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    const StageCoef sc{};
+    auto once = [&] {
+        const int mma = mma_mode(h->cfg.precision);
+        if (group == 0)
+            launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, 0, h->b.V);
+        else if (group == 1)
+            launch_y(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, mma, h->tpw);
+        else if (h->direct)
+            launch_direct(h->stream, h->g, h->b, batch, h->cfg.channels, 0);
+        else
+            launch_contract(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, 0);
+    };
+    // inputs of the later groups: one stage and phase 1 first
+    launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, 0, h->b.V);
+    if (h->direct) launch_wtable(h->stream, h->g, h->b, batch);
+    once();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    (void)hipEventRecord(e0, h->stream);
+    for (int r = 0; r < reps; ++r) once();
+    (void)hipEventRecord(e1, h->stream);
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(FM_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(h->b.fs, saved.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipGetLastError());
+    *avg_ms = ms / reps;
+    return FM_OK;
+}
+
 int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, double* dV_dev) {
     if (!h) return fail(FM_EINVAL, "null handle");
     if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
@@ -548,6 +623,7 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
     }
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
+    untimed(h);
     StageCoef sc{};
     stage_launch(h, batch, sc, 0, V_dev);
     rhs_launch(h, batch, 0);
@@ -575,6 +651,7 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     }
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
+    untimed(h);
     const double inf = std::numeric_limits<double>::infinity();
     if (rk45) {
         stage_launch(h, batch, dp_stage(0), 0, V_dev);
@@ -634,6 +711,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     HIPCHK(hipMemcpyAsync(h->b.U, U, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
     launch_fill_u(h->stream, h->b, n, h->N3, h->b.U);
     if (int rc = ensure_tuned(h, n, h->b.V)) return rc;
+    untimed(h);
     if (rk45) {
         stage_launch(h, n, dp_stage(0), 0, h->b.V);
         rhs_launch(h, n, 0);

@@ -30,7 +30,7 @@ INTEGRATORS = {"rk4": RK4_FIXED, "rk45": RK45_DOPRI}
 # every entry point declared in include/fm_flow.h
 EXPORTS = ("fm_flow_workspace_bytes", "fm_flow_init", "fm_flow_rhs", "fm_flow_step",
            "fm_flow_run_batch", "fm_geometry_query", "fm_flow_set_timing", "fm_flow_timings",
-           "fm_flow_destroy", "fm_last_error")
+           "fm_flow_kernel_time", "fm_flow_destroy", "fm_last_error")
 
 
 class Config(ctypes.Structure):
@@ -82,6 +82,7 @@ def load():
         "fm_geometry_query": (c_int, [pc, pd, pi, pi, pi, pi, pd, pi]),
         "fm_flow_set_timing": (c_int, [c_void_p, c_int]),
         "fm_flow_timings": (c_int, [c_void_p, POINTER(c_char_p), pd, pi, c_int]),
+        "fm_flow_kernel_time": (c_int, [c_void_p, c_int, c_int, c_int, pd]),
         "fm_flow_destroy": (None, [c_void_p]),
         "fm_last_error": (c_char_p, []),
     }
@@ -242,6 +243,14 @@ class Flow:
 
     def set_timing(self, on=True):
         _check(load().fm_flow_set_timing(self.h, int(bool(on))))
+
+    def kernel_time(self, group, batch=1, reps=50):
+        """Average launch duration (ms) of kernel group 0 (stage + phase 1), 1 (phase 2a) or
+        2 (phase 2b), replayed back to back on the handle's current state."""
+        out = c_double(0.0)
+        _check(load().fm_flow_kernel_time(self.h, int(group), int(batch), int(reps),
+                                          ctypes.byref(out)))
+        return out.value
 
     def timings(self):
         names = (c_char_p * 16)()

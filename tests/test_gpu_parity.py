@@ -303,6 +303,27 @@ def test_flow_with_z_feedback_fp64(torch_dev):
     assert rel(Vg.cpu().numpy()[0], Vo) <= 1e-8
 
 
+def test_kernel_time_replay_leaves_the_flow_state(torch_dev):
+    """The kernel replay measurement times each group and restores the flows: the next run
+    agrees with the one before it (to the rounding of phase 1's atomic bin sums, whose order
+    varies from run to run)."""
+    fm = _fm()
+    torch, dev = torch_dev
+    f = fm.Flow(N=16, L=32, U=2.5, precision="fp64", integrator="rk45", max_batch=2, device=dev)
+    try:
+        r1 = f.run_batch([2.5, 2.0], [1.0, 0.8])
+        for g in (0, 1, 2):
+            assert f.kernel_time(g, batch=2, reps=3) > 0.0
+        r2 = f.run_batch([2.5, 2.0], [1.0, 0.8])
+        with pytest.raises(fm.FmError):
+            f.kernel_time(3, batch=1, reps=1)
+    finally:
+        f.close()
+    for x, y in zip(r1, r2):
+        assert x["status"] == y["status"] == fm.DIVERGED
+        assert abs(x["T_c"] / y["T_c"] - 1.0) < 1e-10
+
+
 def test_stop_at_start(torch_dev):
     fm = _fm()
     f = fm.Flow(N=16, L=32, U=30.0, precision="fp32", integrator="rk45", device=torch_dev[1])
