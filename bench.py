@@ -28,14 +28,16 @@ PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6, "bf16_TFs": 2500
 METRIC = "coupling·loop-point updates/s per RHS (N³·L²·3); flows/hour, mixed vs FP64"
 
 
-def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None):
+def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5):
     """Algorithmic work of one launch of each timed kernel group for one flow.
 
-    stage_bins: phase 1 of the stage (the stage argument in the same launch is minor):
-              (nRp + nRd) L^2 weight derivatives (orbit representatives), each counted as
-              6 flops (two differences, one division, the 1/(4 T L^2) scale and the bin
-              accumulation) -- the point quantities the kernel evaluates on the fly are not
-              counted
+    stage_bins: phase 1 of every stage node of a Dormand-Prince step (nsets = 5 distinct
+              nodes; the stage argument in the same launch is minor): nsets (nRp + nRd) L^2
+              weight derivatives (orbit representatives), each counted as 6 flops (two
+              differences, one division, the 1/(4 T L^2) scale and the bin accumulation) --
+              the point quantities the kernel evaluates on the fly are not counted
+    stage:    the stage argument alone: V read (f64), on average four earlier k slots of
+              three channel parts read, three operand layouts written
     y:        (nP + 3 nD) N^3 multiply-adds; bytes = representative bins read (plus the
               transposed particle-hole bins) + 3 operand slabs read + Y written
     contract: 4 N^4 multiply-adds; bytes = Y read + operand read + k written
@@ -44,7 +46,9 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None):
     nRp = nP if nRp is None else nRp
     nRd = nD if nRd is None else nRd
     if name == "stage_bins":
-        return {"bound": "alu", "flops": 6.0 * (nRp + nRd) * L * L}
+        return {"bound": "alu", "flops": 6.0 * nsets * (nRp + nRd) * L * L}
+    if name == "stage":
+        return {"bound": "hbm", "bytes": N3 * (8 + 4 * 3 * rsize + 3 * rsize)}
     if name == "y":
         return {"bound": "hbm", "flops": 2.0 * (nP + 3 * nD) * N3,
                 "bytes": (nRp + 2 * nRd) * NN * rsize + 3 * N3 * rsize + (nP + 3 * nD) * NN * rsize}
@@ -240,7 +244,7 @@ def main():
     # Per-launch durations of the three RHS kernel groups: each launched 200 times back to
     # back on the flow's final state between two HIP events on the library's stream (the
     # serialized-launch cost is included, host gaps are not).
-    groups = {"stage_bins": 0, "y": 1, "contract": 2}
+    groups = {"stage_bins": 0, "y": 1, "contract": 2, "stage": 3}
     replay = {name: flow.kernel_time(gid, 1, 200) * 1e3 for name, gid in groups.items()}
     for name, us in replay.items():
         k = kernels.setdefault(name, {})
@@ -250,7 +254,8 @@ def main():
             k["replay_achieved_GBs"] = wk["bytes"] / (us * 1e-6) / 1e9
         elif wk:
             k["replay_achieved_TFs"] = wk["flops"] / (us * 1e-6) / 1e12
-    dom = max(groups, key=lambda n: replay[n])
+    # dominant: the largest share of a flow's time (per-launch duration x launches per flow)
+    dom = max(groups, key=lambda n: replay[n] * kernels[n].get("launches", 0))
     wk = kernel_work(dom, N, L, nP, nD, 4, nRp, nRd)
     avg_s = replay[dom] * 1e-6
     if wk["bound"] == "hbm":
@@ -259,6 +264,7 @@ def main():
         ach, peak, unit = wk["flops"] / avg_s / 1e12, PEAK["fp32_TFs"], "TFLOP/s"
     roofline = {"kernel": dom, "bound": wk["bound"], "achieved": ach, "peak": peak, "unit": unit,
                 "frac": ach / peak, "traffic": measured_traffic(dom), "avg_us": replay[dom],
+                "launches_per_flow": kernels[dom].get("launches", 0) / args.steps,
                 "timing": "200 back-to-back launches on the flow's final state, HIP events on "
                           "the library stream"}
 

@@ -66,6 +66,34 @@ StageCoef dp_stage(int s) {
     return c;
 }
 
+// Bins of one integrator step: phase 1 depends on the stage temperature only, so the first
+// stage launch of a step bins every distinct node of the step (Dormand-Prince: 1/5, 3/10,
+// 4/5, 8/9, 1 for stages 2-7, whose last two share c = 1; RK4: 0, 1/2, 1), and each stage's
+// phase 2a reads the set of its node.
+struct StepPlan {
+    BinPlan bp{};
+    int set[7] = {0, 0, 0, 0, 0, 0, 0};
+    int first = 0;           // the stage whose launch computes the bins
+};
+
+StepPlan step_plan(bool rk45) {
+    StepPlan p;
+    p.first = rk45 ? 1 : 0;
+    const int last = rk45 ? 7 : 4;
+    for (int s = p.first; s < last; ++s) {
+        const double c = rk45 ? kDPC[s] : kRK4C[s];
+        int k = 0;
+        while (k < p.bp.n && p.bp.c[k] != c) ++k;
+        if (k == p.bp.n) p.bp.c[p.bp.n++] = c;
+        p.set[s] = k;
+    }
+    return p;
+}
+
+// One node (the stage temperature of a lone right-hand side or a step's first stage).
+const BinPlan kOneNode{1, {0.0}};
+const BinPlan kNoBins{0, {0.0}};
+
 struct Layout {
     size_t off = 0;
     char* base = nullptr;
@@ -131,9 +159,9 @@ struct fm_flow {
 
 namespace {
 
-enum { T_STAGE, T_Y, T_CONTRACT, T_WTABLE, T_DIRECT, T_UPDATE, T_FINISH, T_COUNT };
+enum { T_STAGE, T_Y, T_CONTRACT, T_WTABLE, T_DIRECT, T_UPDATE, T_FINISH, T_STAGE_ONLY, T_COUNT };
 const char* kTimerNames[T_COUNT] = {"stage_bins", "y", "contract", "wtable", "direct",
-                                    "update", "finish"};
+                                    "update", "finish", "stage"};
 
 int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, size_t* bytes) {
     const int B = c.max_batch, N = c.N, np = hg.np;
@@ -182,8 +210,10 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
     b.bstride = B;
     if (!direct) {
-        b.bins = L.take<char>(static_cast<size_t>(B) * (nRp + nRd) * NN * rs);
-        b.binsT = L.take<char>(static_cast<size_t>(B) * nRd * NN * rs);
+        const size_t S = static_cast<size_t>(step_plan(c.integrator == FM_RK45_DOPRI).bp.n);
+        b.nbset = static_cast<int>(S);
+        b.bins = L.take<char>(S * B * (nRp + nRd) * NN * rs);
+        b.binsT = L.take<char>(S * B * nRd * NN * rs);
         b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
         b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
@@ -191,6 +221,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         b.wtab = nullptr;
     } else {
         b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.nbset = 0;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
     }
     b.v0 = L.take<char>(static_cast<size_t>(B) * N3 * rs);
@@ -263,8 +294,9 @@ void collect_timings(fm_flow* h) {
     h->ev_next = 0;
 }
 
-// One right-hand-side evaluation of the current stage operands into k slot `slot`.
-void rhs_launch(fm_flow* h, int nf, int slot) {
+// One right-hand-side evaluation of the current stage operands into k slot `slot`, with the
+// stage's bins in set `set`.
+void rhs_launch(fm_flow* h, int nf, int slot, int set) {
     const unsigned ch = h->cfg.channels;
     if (h->direct) {
         timed(h, T_WTABLE, [&] { launch_wtable(h->stream, h->g, h->b, nf); });
@@ -272,13 +304,16 @@ void rhs_launch(fm_flow* h, int nf, int slot) {
         return;
     }
     const int mma = mma_mode(h->cfg.precision);
-    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, h->b, nf, ch, mma, h->tpw); });
+    const Buffers bs = with_bin_set(h->b, h->g, h->dbl, set);
+    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, bs, nf, ch, mma, h->tpw); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
 
-void stage_launch(fm_flow* h, int nf, const StageCoef& sc, int write_new, const double* Vbase) {
-    timed(h, T_STAGE, [&] {
-        launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, write_new, Vbase);
+void stage_launch(fm_flow* h, int nf, const StageCoef& sc, const BinPlan& bp, int write_new,
+                  const double* Vbase) {
+    const BinPlan& p = h->direct ? kNoBins : bp;
+    timed(h, p.n > 0 ? T_STAGE : T_STAGE_ONLY, [&] {
+        launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, p, write_new, Vbase);
     });
 }
 
@@ -305,7 +340,7 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
         if (it != g_tune.end()) { h->tpw = it->second; h->tuned_nf = nf; return FM_OK; }
     }
     StageCoef sc{};
-    launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, 0, Vbase);
+    launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, kOneNode, 0, Vbase);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -341,18 +376,19 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
 // One integrator step of every running flow (no host interaction).  V is the state array.
 void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed, double v_max) {
     const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
+    const StepPlan plan = step_plan(rk45);
     if (!rk45) {
         for (int s = 0; s < 4; ++s) {
-            stage_launch(h, nf, rk4_stage(s), 0, V);
-            rhs_launch(h, nf, s);
+            stage_launch(h, nf, rk4_stage(s), s == plan.first ? plan.bp : kNoBins, 0, V);
+            rhs_launch(h, nf, s, plan.set[s]);
         }
         timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->N3, V); });
         timed(h, T_FINISH, [&] { launch_finish(h->stream, h->b, nf, 0, v_max, fixed_steps, h_fixed); });
         return;
     }
     for (int s = 1; s < 7; ++s) {
-        stage_launch(h, nf, dp_stage(s), s == 6, V);
-        rhs_launch(h, nf, s);
+        stage_launch(h, nf, dp_stage(s), s == plan.first ? plan.bp : kNoBins, s == 6, V);
+        rhs_launch(h, nf, s, plan.set[s]);
     }
     ErrWeights ew;
     std::memcpy(ew.e, kDPE, sizeof ew.e);
@@ -565,8 +601,8 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
     if (!h) return fail(FM_EINVAL, "null handle");
     if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
     if (reps < 1 || !avg_ms) return fail(FM_EINVAL, "need reps >= 1 and an output");
-    if (group < 0 || group > 2 || (h->direct && group == 1))
-        return fail(FM_EINVAL, "group: 0 stage and phase 1, 1 phase 2a, 2 phase 2b");
+    if (group < 0 || group > 3 || (h->direct && group == 1))
+        return fail(FM_EINVAL, "group: 0 stage and phase 1, 1 phase 2a, 2 phase 2b, 3 stage alone");
     // flows replayed as running at their current temperature; their status is restored
     std::vector<FlowState> saved(batch);
     HIPCHK(hipMemcpyAsync(saved.data(), h->b.fs, sizeof(FlowState) * batch, hipMemcpyDeviceToHost, h->stream));
@@ -575,10 +611,13 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
     for (auto& f : run) { f.status = FM_FLOW_RUNNING; f.ht = 0.0; }
     HIPCHK(hipMemcpyAsync(h->b.fs, run.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     const StageCoef sc{};
+    const BinPlan step_bins = h->direct ? kNoBins : step_plan(h->cfg.integrator == FM_RK45_DOPRI).bp;
     auto once = [&] {
         const int mma = mma_mode(h->cfg.precision);
         if (group == 0)
-            launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, 0, h->b.V);
+            launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, step_bins, 0, h->b.V);
+        else if (group == 3)
+            launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, kNoBins, 0, h->b.V);
         else if (group == 1)
             launch_y(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, mma, h->tpw);
         else if (h->direct)
@@ -587,7 +626,8 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
             launch_contract(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, 0);
     };
     // inputs of the later groups: one stage and phase 1 first
-    launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, 0, h->b.V);
+    launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, h->direct ? kNoBins : kOneNode, 0,
+                 h->b.V);
     if (h->direct) launch_wtable(h->stream, h->g, h->b, batch);
     once();
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -625,8 +665,8 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
     if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
     untimed(h);
     StageCoef sc{};
-    stage_launch(h, batch, sc, 0, V_dev);
-    rhs_launch(h, batch, 0);
+    stage_launch(h, batch, sc, kOneNode, 0, V_dev);
+    rhs_launch(h, batch, 0, 0);
     launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);
     HIPCHK(hipGetLastError());
     return FM_OK;
@@ -654,8 +694,8 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     untimed(h);
     const double inf = std::numeric_limits<double>::infinity();
     if (rk45) {
-        stage_launch(h, batch, dp_stage(0), 0, V_dev);
-        rhs_launch(h, batch, 0);
+        stage_launch(h, batch, dp_stage(0), kOneNode, 0, V_dev);
+        rhs_launch(h, batch, 0, 0);
     }
     step_launch(h, batch, V_dev, 0, 0.0, inf);
     HIPCHK(hipGetLastError());
@@ -713,8 +753,8 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     if (int rc = ensure_tuned(h, n, h->b.V)) return rc;
     untimed(h);
     if (rk45) {
-        stage_launch(h, n, dp_stage(0), 0, h->b.V);
-        rhs_launch(h, n, 0);
+        stage_launch(h, n, dp_stage(0), kOneNode, 0, h->b.V);
+        rhs_launch(h, n, 0, 0);
     }
     HIPCHK(hipGetLastError());
     // fixed steps: flow f advances on its own grid ln T0_f + k (ln T_end - ln T0_f)/n_steps

@@ -111,6 +111,13 @@ struct StageCoef {
     int ns;                // number of previous stages used
 };
 
+// Stage nodes whose phase-1 bins one stage launch computes: every distinct node of an
+// integrator step (bins depend on the stage temperature only, not on V), one bin set each.
+struct BinPlan {
+    int n;                 // sets (0: the launch forms the stage argument only)
+    double c[6];           // node of each set
+};
+
 // Device buffers carved out of the caller's workspace.
 struct Buffers {
     // geometry
@@ -124,8 +131,9 @@ struct Buffers {
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0; int* item_rec;
-    void* bins;                        // [B][nRp + nRd][NN] real, representative transfers
-    void* binsT;                       // [B][nRd][NN] real, particle-hole bins transposed
+    void* bins;                        // [S][B][nRp + nRd][NN] real, representative transfers
+    void* binsT;                       // [S][B][nRd][NN] real, particle-hole bins transposed
+    int nbset;                         // S: bin sets (stage nodes of one step)
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
     void* v0; void* va; void* vc;      // operands [B][N^3] real
     void* k;                           // [7][B][3][N^3] real: per stage, flow and channel
@@ -145,8 +153,12 @@ struct ErrWeights {
 // Launchers (kernels.hip).  `dbl` selects the double-precision instantiation, nf is the
 // number of flows launched; buffers are strided by b.bstride flows.
 // Stage argument and operand layouts; with bins, phase 1 of the stage in the same launch.
+// bp.n > 0: phase 1 of every node of bp in the same launch, into bin sets 0 .. bp.n-1.
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
-                  int nf, const StageCoef& sc, int write_new, const double* Vbase);
+                  int nf, const StageCoef& sc, const BinPlan& bp, int write_new,
+                  const double* Vbase);
+// The buffers with bin set `set` in place of set 0 (phase 2a reads the bins of its stage).
+Buffers with_bin_set(const Buffers& b, const DevGeom& g, bool dbl, int set);
 // mma: 0 VALU, 1 f32 matrix cores, 2 bf16 matrix cores, 3 split-bf16 matrix cores (single
 // precision only, N <= 128);
 // tpw: row tiles per wavefront on matrix cores (1, 2, 4; 0 = by size)

@@ -412,26 +412,34 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     }
 }
 
-// One launch per stage: blocks [0, nRb) bin the representatives (phase 1, which needs only
-// T), the remaining blocks form the stage argument and its operand layouts.  Grid (nRb +
-// stage blocks, flows).
+// One launch per stage: blocks [0, nRb bp.n) bin the representatives (phase 1, which needs
+// only T) at every node of the plan -- the first stage of an integrator step bins all the
+// step's distinct nodes at once, the later stages none -- and the remaining blocks form the
+// stage argument and its operand layouts.  Grid (nRb bp.n + stage blocks, flows).
 template <typename R, int kMode, int BT>
 __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
-                                                            StageCoef sc, int write_new,
-                                                            const double* Vbase, const R* K,
-                                                            double* Vnew, R* v0, R* va, R* vc,
-                                                            double* T_stage, double* Z_stage,
-                                                            R* bins, R* binsT, int nRb, int B) {
+                                                            StageCoef sc, BinPlan bp,
+                                                            int write_new, const double* Vbase,
+                                                            const R* K, double* Vnew, R* v0,
+                                                            R* va, R* vc, double* T_stage,
+                                                            double* Z_stage, R* bins, R* binsT,
+                                                            int nRb, int B) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;                      // uniform over the block
     const FlowState st = fs[f];
-    if (static_cast<int>(blockIdx.x) < nRb) {
-        const double T = exp(st.lnT + sc.c * st.ht);
-        bins_part<R, kMode, BT>(g, f, blockIdx.x, T, bins, binsT, reinterpret_cast<R*>(smem_raw));
+    const int nbin = nRb * bp.n;
+    if (static_cast<int>(blockIdx.x) < nbin) {
+        const int set = static_cast<int>(blockIdx.x) / nRb;
+        const int r = static_cast<int>(blockIdx.x) - set * nRb;
+        const double T = exp(st.lnT + bp.c[set] * st.ht);
+        const size_t NN = static_cast<size_t>(g.NN);
+        bins_part<R, kMode, BT>(g, f, r, T, bins + static_cast<size_t>(set) * B * nRb * NN,
+                                binsT + static_cast<size_t>(set) * B * g.nRd * NN,
+                                reinterpret_cast<R*>(smem_raw));
     } else {
         stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
-                      B, blockIdx.x - nRb, gridDim.x - nRb);
+                      B, blockIdx.x - nbin, gridDim.x - nbin);
     }
 }
 
@@ -1231,41 +1239,43 @@ int bins_mode(const DevGeom& g) {
     return static_cast<size_t>(g.NN) * sizeof(R) <= 65536 ? 0 : 1;
 }
 
-// Stage argument plus, when bins exist, phase 1 of the same stage in one launch.
+// Stage argument plus, when the plan has nodes, their phase 1 in one launch.
 template <typename R, int BT>
 void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
-              const StageCoef& sc, int write_new, const double* Vbase, int nRb, int ept) {
+              const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase,
+              int nRb, int ept) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
     size_t ns = (N3 + static_cast<size_t>(BT) * ept - 1) / (static_cast<size_t>(BT) * ept);
     ns = ns > 1024 ? 1024 : ns;
-    const dim3 grid(static_cast<unsigned>(nRb + ns), nf);
-    const bool lds = nRb > 0 && bins_mode<R>(g) == 0;
+    const int nbin = nRb * bp.n;
+    const dim3 grid(static_cast<unsigned>(nbin + ns), nf);
+    const bool lds = nbin > 0 && bins_mode<R>(g) == 0;
     const size_t shm = lds ? static_cast<size_t>(g.NN) * sizeof(R) : 0;
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
-    if (nRb == 0 || lds)
-        hipLaunchKernelGGL((k_stage_bins<R, 0, BT>), grid, dim3(BT), shm, s, g, z, b.fs, sc,
+    if (nbin == 0 || lds)
+        hipLaunchKernelGGL((k_stage_bins<R, 0, BT>), grid, dim3(BT), shm, s, g, z, b.fs, sc, bp,
                            write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
     else
-        hipLaunchKernelGGL((k_stage_bins<R, 1, BT>), grid, dim3(BT), 0, s, g, z, b.fs, sc,
+        hipLaunchKernelGGL((k_stage_bins<R, 1, BT>), grid, dim3(BT), 0, s, g, z, b.fs, sc, bp,
                            write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
 }
 
-// Stage argument plus, when bins exist, phase 1 of the same stage in one launch.  Few
-// (flow, representative) pairs (at most one per CU): 1024-thread blocks, one stage element
-// per thread; many: 256-thread blocks, four stage elements per thread.
+// Stage argument plus the plan's phase 1 in one launch.  Few (flow, node, representative)
+// triples (at most one per CU): 1024-thread blocks, one stage element per thread; many:
+// 256-thread blocks, four stage elements per thread.
 template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
-             const StageCoef& sc, int write_new, const double* Vbase) {
+             const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
     const int nRb = b.bins ? g.nRp + g.nRd : 0;
-    if (static_cast<long>(nRb) * nf <= 256)
-        stage_go<R, 1024>(s, g, z, b, nf, sc, write_new, Vbase, nRb, 1);
+    if (static_cast<long>(nRb) * bp.n * nf <= 256)
+        stage_go<R, 1024>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
     else
-        stage_go<R, 256>(s, g, z, b, nf, sc, write_new, Vbase, nRb, 4);
+        stage_go<R, 256>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
@@ -1353,9 +1363,21 @@ void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsig
 }  // namespace
 
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
-                  int nf, const StageCoef& sc, int write_new, const double* Vbase) {
-    if (dbl) stage_t<double>(s, g, z, b, nf, sc, write_new, Vbase);
-    else stage_t<float>(s, g, z, b, nf, sc, write_new, Vbase);
+                  int nf, const StageCoef& sc, const BinPlan& bp, int write_new,
+                  const double* Vbase) {
+    if (dbl) stage_t<double>(s, g, z, b, nf, sc, bp, write_new, Vbase);
+    else stage_t<float>(s, g, z, b, nf, sc, bp, write_new, Vbase);
+}
+
+Buffers with_bin_set(const Buffers& b, const DevGeom& g, bool dbl, int set) {
+    Buffers o = b;
+    if (b.bins && set > 0) {
+        const size_t rs = dbl ? sizeof(double) : sizeof(float);
+        const size_t NN = static_cast<size_t>(g.NN), B = static_cast<size_t>(b.bstride);
+        o.bins = static_cast<char*>(b.bins) + set * B * (g.nRp + g.nRd) * NN * rs;
+        o.binsT = static_cast<char*>(b.binsT) + set * B * g.nRd * NN * rs;
+    }
+    return o;
 }
 
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,

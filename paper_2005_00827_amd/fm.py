@@ -245,8 +245,9 @@ class Flow:
         _check(load().fm_flow_set_timing(self.h, int(bool(on))))
 
     def kernel_time(self, group, batch=1, reps=50):
-        """Average launch duration (ms) of kernel group 0 (stage + phase 1), 1 (phase 2a) or
-        2 (phase 2b), replayed back to back on the handle's current state."""
+        """Average launch duration (ms) of kernel group 0 (stage + phase 1 of a step's stage
+        nodes), 1 (phase 2a), 2 (phase 2b) or 3 (stage alone), replayed back to back on the
+        handle's current state."""
         out = c_double(0.0)
         _check(load().fm_flow_kernel_time(self.h, int(group), int(batch), int(reps),
                                           ctypes.byref(out)))

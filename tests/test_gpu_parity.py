@@ -312,11 +312,11 @@ def test_kernel_time_replay_leaves_the_flow_state(torch_dev):
     f = fm.Flow(N=16, L=32, U=2.5, precision="fp64", integrator="rk45", max_batch=2, device=dev)
     try:
         r1 = f.run_batch([2.5, 2.0], [1.0, 0.8])
-        for g in (0, 1, 2):
+        for g in (0, 1, 2, 3):
             assert f.kernel_time(g, batch=2, reps=3) > 0.0
         r2 = f.run_batch([2.5, 2.0], [1.0, 0.8])
         with pytest.raises(fm.FmError):
-            f.kernel_time(3, batch=1, reps=1)
+            f.kernel_time(4, batch=1, reps=1)
     finally:
         f.close()
     for x, y in zip(r1, r2):
