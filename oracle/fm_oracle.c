@@ -20,7 +20,11 @@
  *     the particle-particle, crossed and direct particle-hole terms, in a temperature flow
  *     with scale s = ln T, each internal line weighted by the Z of its patch;
  *   - fixed-step RK4 and Dormand-Prince 5(4) integration in ln T, with the stop rule
- *     "largest |V| above a threshold" (Sec. 3.2, definition of U*(T)).
+ *     "largest |V| above a threshold" (Sec. 3.2, definition of U*(T));
+ *   - the paper's own interaction flow (Sec. 2.2; App. A, Steps 1 and 2): the same channel
+ *     formula at fixed T with flow parameter g, internal lines G_g = g Z G0 and
+ *     S_g = Z^2 G0, integrated from g = 0, giving the crossover coupling U* = g*^2 U where
+ *     the stop rule fires.
  * The paper states the vertex flow only in shorthand and for the interaction flow; the
  * explicit channel formula and the temperature-flow weight used here are readings that
  * the tests pin against second-order perturbation theory, closed forms and a generic
@@ -55,19 +59,23 @@ typedef struct {
 } orc_model;
 
 typedef struct {
-    double T0, T_end;
-    int integrator;     /* 0: classical RK4, fixed steps in ln T; 1: Dormand-Prince 5(4) */
+    double T0, T_end;   /* temperature flow: from T0 down to T_end; interaction flow: T0 is
+                           the fixed temperature, T_end unused */
+    int integrator;     /* 0: classical RK4, fixed steps in s; 1: Dormand-Prince 5(4) */
     int n_steps;        /* RK4 step count */
     double rtol, atol, h0, h_min;
     double v_max;       /* stop when max |V| exceeds this */
     int n_z;            /* 0: Z = 1 on every line */
-    const double *z_lnT; /* [n_z] ascending ln T nodes */
+    const double *z_lnT; /* [n_z] ascending nodes in the flow parameter (ln T, or g) */
     const double *z_tab; /* [n_z][N] */
+    int gflow;          /* 0: temperature flow, s = ln T; 1: interaction flow, s = g */
+    double g_end;       /* interaction flow: from g = 0 to g_end */
 } orc_flowcfg;
 
 typedef struct {
     double T_c, T_final, max_abs_V;
     int status, n_accepted, n_rejected, n_rhs;
+    double g_c, U_star, g_final;   /* interaction flow: crossing g*, U* = g*^2 U, last g */
 } orc_result;
 
 enum { ORC_RUNNING = 0, ORC_DIVERGED = 1, ORC_NONFINITE = 2, ORC_REACHED_TEND = 3,
@@ -326,15 +334,29 @@ int orc_transfer_counts(const orc_model *m, int *n_pp, int *n_ph)
 
 #define VIX(N, a, b, c) ((((size_t)(a)) * (N) + (b)) * (N) + (c))
 
-static void fill_weights(const geom *g, double T, const double *Z, int pp, int q, double *w)
+/* Weight of the internal line pair (j, j') with Z_x = Z of the patch of line x:
+ *   temperature flow, d/d ln T of the bubble with Z on both lines:
+ *     W = Z_j Z_j' T d/dT chi_X(xi_j, xi_j');
+ *   interaction flow (App. A, Step 2, Eqs. both_propagators_Z, vertex_flow_feedback_Z):
+ *   the line pair S_g G_g + G_g S_g with G_g = g Z G0, S_g = Z^2 G0, i.e.
+ *     W = g Z_j Z_j' (Z_j + Z_j') chi_X(xi_j, xi_j')   (2 g chi_X without Z, Step 1). */
+typedef struct { int gflow; double T, g; } wkind;
+
+static void fill_weights(const geom *g, wkind wk, const double *Z, int pp, int q, double *w)
 {
     int L = g->L;
     for (int j = 0; j < g->np; ++j) {
         int jp = pp ? partner_pp(L, q, j) : partner_ph(L, q, j);
-        double chid = pp ? orc_chidot_pp(g->xi[j], g->xi[jp], T)
-                         : orc_chidot_ph(g->xi[j], g->xi[jp], T);
-        double z = Z ? Z[g->patch[j]] * Z[g->patch[jp]] : 1.0;
-        w[j] = z * chid;
+        double za = Z ? Z[g->patch[j]] : 1.0, zb = Z ? Z[g->patch[jp]] : 1.0;
+        if (wk.gflow) {
+            double chi = pp ? orc_chi_pp(g->xi[j], g->xi[jp], wk.T)
+                            : orc_chi_ph(g->xi[j], g->xi[jp], wk.T);
+            w[j] = wk.g * za * zb * (za + zb) * chi;
+        } else {
+            double chid = pp ? orc_chidot_pp(g->xi[j], g->xi[jp], wk.T)
+                             : orc_chidot_ph(g->xi[j], g->xi[jp], wk.T);
+            w[j] = za * zb * chid;
+        }
     }
 }
 
@@ -376,7 +398,7 @@ static void set_threads(int nthreads)
 /* Weight tables for every transfer that occurs, keyed by the flat transfer index. */
 typedef struct { double **pp, **ph; } wcache;
 
-static void wcache_build(const geom *g, unsigned ch, double T, const double *Z, wcache *wc)
+static void wcache_build(const geom *g, unsigned ch, wkind wk, const double *Z, wcache *wc)
 {
     int np = g->np, N = g->N;
     wc->pp = (double **)calloc(np, sizeof(double *));
@@ -397,7 +419,7 @@ static void wcache_build(const geom *g, unsigned ch, double T, const double *Z, 
     for (int i = 0; i < n; ++i) {
         int q = list[i] >= 0 ? list[i] : -1 - list[i];
         int pp = list[i] >= 0;
-        fill_weights(g, T, Z, pp, q, pp ? wc->pp[q] : wc->ph[q]);
+        fill_weights(g, wk, Z, pp, q, pp ? wc->pp[q] : wc->ph[q]);
     }
     free(list); free(need_pp); free(need_ph);
 }
@@ -408,12 +430,12 @@ static void wcache_free(const geom *g, wcache *wc)
     free(wc->pp); free(wc->ph);
 }
 
-static void rhs_geom(const geom *g, unsigned ch, double T, const double *Z, const double *V,
+static void rhs_geom(const geom *g, unsigned ch, wkind wk, const double *Z, const double *V,
                      double *dV)
 {
     int N = g->N;
     wcache wc;
-    wcache_build(g, ch, T, Z, &wc);
+    wcache_build(g, ch, wk, Z, &wc);
 #pragma omp parallel for collapse(2) schedule(dynamic)
     for (int a = 0; a < N; ++a)
         for (int b = 0; b < N; ++b)
@@ -431,17 +453,31 @@ int orc_rhs(const orc_model *m, double T, const double *Z, const double *V, doub
     geom g;
     if (!(T > 0.0) || geom_build(m, &g)) return -1;
     set_threads(nthreads);
-    rhs_geom(&g, m->channels, T, Z, V, dV);
+    wkind wk = {0, T, 0.0};
+    rhs_geom(&g, m->channels, wk, Z, V, dV);
+    geom_free(&g);
+    return 0;
+}
+
+/* Interaction flow: dV/dg at temperature T and scale g. */
+int orc_rhs_g(const orc_model *m, double T, double gval, const double *Z, const double *V,
+              double *dV, int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    wkind wk = {1, T, gval};
+    rhs_geom(&g, m->channels, wk, Z, V, dV);
     geom_free(&g);
     return 0;
 }
 
 /* Sampled outputs: weights computed per output, nothing cached. */
-int orc_rhs_points(const orc_model *m, double T, const double *Z, const double *V, int n,
-                   const int *abc, double *out, int nthreads)
+static int rhs_points_wk(const orc_model *m, wkind wk, const double *Z, const double *V, int n,
+                         const int *abc, double *out, int nthreads)
 {
     geom g;
-    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    if (!(wk.T > 0.0) || geom_build(m, &g)) return -1;
     set_threads(nthreads);
 #pragma omp parallel
     {
@@ -452,15 +488,29 @@ int orc_rhs_points(const orc_model *m, double T, const double *Z, const double *
         for (int i = 0; i < n; ++i) {
             int a = abc[3 * i], b = abc[3 * i + 1], c = abc[3 * i + 2];
             int qpp = q_pp(&g, a, b), qcr = q_diff(&g, c, b), qd = q_diff(&g, a, c);
-            fill_weights(&g, T, Z, 1, qpp, wpp);
-            fill_weights(&g, T, Z, 0, qcr, wcr);
-            fill_weights(&g, T, Z, 0, qd, wd);
+            fill_weights(&g, wk, Z, 1, qpp, wpp);
+            fill_weights(&g, wk, Z, 0, qcr, wcr);
+            fill_weights(&g, wk, Z, 0, qd, wd);
             out[i] = rhs_one(&g, m->channels, V, a, b, c, wpp, qpp, wcr, qcr, wd, qd);
         }
         free(wpp); free(wcr); free(wd);
     }
     geom_free(&g);
     return 0;
+}
+
+int orc_rhs_points(const orc_model *m, double T, const double *Z, const double *V, int n,
+                   const int *abc, double *out, int nthreads)
+{
+    wkind wk = {0, T, 0.0};
+    return rhs_points_wk(m, wk, Z, V, n, abc, out, nthreads);
+}
+
+int orc_rhs_points_g(const orc_model *m, double T, double gval, const double *Z,
+                     const double *V, int n, const int *abc, double *out, int nthreads)
+{
+    wkind wk = {1, T, gval};
+    return rhs_points_wk(m, wk, Z, V, n, abc, out, nthreads);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -527,23 +577,24 @@ int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* Quasi-particle weights along the flow: a table Z_a(T_i), linear in ln T, clamped.       */
+/* Quasi-particle weights along the flow: a table Z_a(s_i) in the flow parameter (ln T, or  */
+/* g for the interaction flow), linear in s between nodes, clamped outside.               */
 /* ------------------------------------------------------------------------------------ */
-static void z_at(const orc_flowcfg *f, int N, double lnT, double *Z)
+static void z_at(const orc_flowcfg *f, int N, double s, double *Z)
 {
     if (f->n_z <= 0) { for (int a = 0; a < N; ++a) Z[a] = 1.0; return; }
     int n = f->n_z;
-    if (n == 1 || lnT <= f->z_lnT[0]) { memcpy(Z, f->z_tab, sizeof(double) * N); return; }
-    if (lnT >= f->z_lnT[n - 1]) { memcpy(Z, f->z_tab + (size_t)(n - 1) * N, sizeof(double) * N); return; }
+    if (n == 1 || s <= f->z_lnT[0]) { memcpy(Z, f->z_tab, sizeof(double) * N); return; }
+    if (s >= f->z_lnT[n - 1]) { memcpy(Z, f->z_tab + (size_t)(n - 1) * N, sizeof(double) * N); return; }
     int i = 0;
-    while (i + 1 < n - 1 && f->z_lnT[i + 1] <= lnT) ++i;
-    double w = (lnT - f->z_lnT[i]) / (f->z_lnT[i + 1] - f->z_lnT[i]);
+    while (i + 1 < n - 1 && f->z_lnT[i + 1] <= s) ++i;
+    double w = (s - f->z_lnT[i]) / (f->z_lnT[i + 1] - f->z_lnT[i]);
     for (int a = 0; a < N; ++a)
         Z[a] = (1.0 - w) * f->z_tab[(size_t)i * N + a] + w * f->z_tab[(size_t)(i + 1) * N + a];
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* Integrators in s = ln T.                                                             */
+/* Integrators in s = ln T (temperature flow) or s = g (interaction flow).              */
 /* ------------------------------------------------------------------------------------ */
 typedef struct {
     const geom *g;
@@ -556,7 +607,8 @@ typedef struct {
 static void eval_f(flowctx *cx, double s, const double *V, double *k)
 {
     z_at(cx->f, cx->g->N, s, cx->Z);
-    rhs_geom(cx->g, cx->m->channels, exp(s), cx->f->n_z > 0 ? cx->Z : NULL, V, k);
+    wkind wk = {cx->f->gflow != 0, cx->f->gflow ? cx->f->T0 : exp(s), cx->f->gflow ? s : 0.0};
+    rhs_geom(cx->g, cx->m->channels, wk, cx->f->n_z > 0 ? cx->Z : NULL, V, k);
     cx->n_rhs++;
 }
 
@@ -631,35 +683,41 @@ static double step_factor(double err)
 }
 
 /* Stop rule (Sec. 3.2: the flow is followed until the coupling grows beyond a threshold):
- * the largest |V| above v_max (or a non-finite value) ends the flow.  T_c is where
- * max|V| = v_max, found by interpolating 1/max|V| linearly in ln T across the last accepted
- * step: near an instability the one-loop flow grows like a simple pole in the scale
- * (for one patch 1/v = 1/U - [c(T) - c(T0)] exactly), so 1/max|V| is nearly linear and the
- * crossing does not depend on where the step boundaries fall. */
+ * the largest |V| above v_max (or a non-finite value) ends the flow.  The crossing
+ * max|V| = v_max is found by interpolating 1/max|V| linearly across the last accepted step,
+ * in ln T for the temperature flow and in g^2 for the interaction flow: near an instability
+ * the one-loop flow grows like a simple pole in that variable (for one patch
+ * 1/v = 1/U - [c(T) - c(T0)], resp. 1/v = 1/U - g^2 c, exactly), so 1/max|V| is nearly
+ * linear and the crossing does not depend on where the step boundaries fall. */
 static int stop_test(const orc_flowcfg *f, double s_prev, double m_prev, double s_new,
-                     double m_new, int finite, double *lnTc)
+                     double m_new, int finite, double *sc)
 {
-    if (!finite) { *lnTc = s_new; return ORC_NONFINITE; }
+    if (!finite) { *sc = s_new; return ORC_NONFINITE; }
     if (m_new > f->v_max) {
+        double u0 = f->gflow ? s_prev * s_prev : s_prev, u1 = f->gflow ? s_new * s_new : s_new;
+        double u = u1;
         if (m_prev > 0.0 && m_new != m_prev)
-            *lnTc = s_prev + (1.0 / m_prev - 1.0 / f->v_max) * (s_new - s_prev) /
-                                 (1.0 / m_prev - 1.0 / m_new);
-        else
-            *lnTc = s_new;
+            u = u0 + (1.0 / m_prev - 1.0 / f->v_max) * (u1 - u0) / (1.0 / m_prev - 1.0 / m_new);
+        *sc = f->gflow ? sqrt(u) : u;
         return ORC_DIVERGED;
     }
     return ORC_RUNNING;
 }
 
 /*
- * Full flow from V = U at T0.  trace (optional) receives (ln T, max|V|) after every accepted
- * step, starting with the initial point; *n_trace is its length (capped at max_trace).
+ * Full flow from V = U: temperature flow from T0 down to T_end, or interaction flow at
+ * T = T0 from g = 0 up to g_end.  trace (optional) receives (s, max|V|) after every
+ * accepted step, starting with the initial point; *n_trace is its length (capped at
+ * max_trace).
  */
 int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
              orc_result *res, double *trace, int max_trace, int *n_trace, int nthreads)
 {
     geom g;
-    if (!(f->T0 > f->T_end) || !(f->T_end > 0.0) || geom_build(m, &g)) return -1;
+    if (f->gflow ? !(f->T0 > 0.0 && f->g_end > 0.0)
+                 : (!(f->T0 > f->T_end) || !(f->T_end > 0.0)))
+        return -1;
+    if (geom_build(m, &g)) return -1;
     set_threads(nthreads);
     size_t n = (size_t)g.N * g.N * g.N;
     double *V = (double *)malloc(sizeof(double) * n);
@@ -672,7 +730,8 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
     flowctx cx = {&g, m, f, Z, 0};
     for (size_t i = 0; i < n; ++i) V[i] = U;
 
-    double s0 = log(f->T0), s_end = log(f->T_end), s = s0;
+    double s0 = f->gflow ? 0.0 : log(f->T0), s_end = f->gflow ? f->g_end : log(f->T_end);
+    double s = s0, dir = s_end > s0 ? 1.0 : -1.0;   /* direction of the flow parameter */
     int finite, status = ORC_RUNNING, nacc = 0, nrej = 0, ntr = 0;
     double mV = max_abs(V, n, &finite), lnTc = NAN;
     if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
@@ -706,8 +765,8 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
         double hmin = f->h_min > 0.0 ? f->h_min : 1e-8 * span;
         eval_f(&cx, s, V, k[0]);
         while (status == ORC_RUNNING) {
-            if (s <= s_end) { status = ORC_REACHED_TEND; break; }
-            int last = (s + h <= s_end);
+            if (dir * (s - s_end) >= 0.0) { status = ORC_REACHED_TEND; break; }
+            int last = (dir * (s + h - s_end) >= 0.0);
             double ht = last ? (s_end - s) : h;
             double err = dopri_attempt(&cx, s, ht, V, k, Vn, tmp, n);
             if (err <= 1.0) {
@@ -728,9 +787,13 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
         }
     }
     if (res) {
+        int stopped = status == ORC_DIVERGED || status == ORC_NONFINITE;
         res->status = status;
-        res->T_c = (status == ORC_DIVERGED || status == ORC_NONFINITE) ? exp(lnTc) : NAN;
-        res->T_final = exp(s);
+        res->T_c = (stopped && !f->gflow) ? exp(lnTc) : NAN;
+        res->T_final = f->gflow ? f->T0 : exp(s);
+        res->g_c = (stopped && f->gflow) ? lnTc : NAN;
+        res->U_star = (stopped && f->gflow) ? lnTc * lnTc * U : NAN;
+        res->g_final = f->gflow ? s : NAN;
         res->max_abs_V = mV;
         res->n_accepted = nacc;
         res->n_rejected = nrej;
@@ -744,9 +807,10 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
 }
 
 /*
- * One step from (lnT, V) with step *h, for step-by-step comparison.  RK4: always accepted,
- * *h unchanged.  Dormand-Prince: k1 evaluated here (no carry-over between calls); on
- * acceptance V and lnT advance; *h becomes the proposed next step either way.
+ * One step from (s, V) with step *h, for step-by-step comparison; s = ln T, or g for the
+ * interaction flow (at T = f->T0).  RK4: always accepted, *h unchanged.  Dormand-Prince: k1
+ * evaluated here (no carry-over between calls); on acceptance V and s advance; *h becomes
+ * the proposed next step either way.
  */
 int orc_step(const orc_model *m, const orc_flowcfg *f, double *lnT, double *h, double *V,
              int *accepted, double *err_out, int nthreads)

@@ -13,7 +13,9 @@ Functions mirror the definitions written out in ``fm_oracle.c``:
 * the one-loop flow right-hand side dV/d ln T (App. A, Eqs. vertex_flow_general and
   vertex_flow_feedback_Z, written out per channel), direct and binned;
 * RK4 / Dormand-Prince flows in ln T with the stop rule of Sec. 3.2 (largest |V| above a
-  threshold).
+  threshold);
+* the interaction flow in g at fixed T (Sec. 2.2; App. A, Steps 1-2: lines G_g = g Z G0,
+  S_g = Z^2 G0), with the crossover coupling U* = g*^2 U.
 """
 from __future__ import annotations
 
@@ -42,13 +44,15 @@ class FlowCfg(ctypes.Structure):
     _fields_ = [("T0", c_double), ("T_end", c_double), ("integrator", c_int),
                 ("n_steps", c_int), ("rtol", c_double), ("atol", c_double),
                 ("h0", c_double), ("h_min", c_double), ("v_max", c_double),
-                ("n_z", c_int), ("z_lnT", POINTER(c_double)), ("z_tab", POINTER(c_double))]
+                ("n_z", c_int), ("z_lnT", POINTER(c_double)), ("z_tab", POINTER(c_double)),
+                ("gflow", c_int), ("g_end", c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("T_c", c_double), ("T_final", c_double), ("max_abs_V", c_double),
                 ("status", c_int), ("n_accepted", c_int), ("n_rejected", c_int),
-                ("n_rhs", c_int)]
+                ("n_rhs", c_int), ("g_c", c_double), ("U_star", c_double),
+                ("g_final", c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -82,6 +86,8 @@ def lib():
             "orc_geometry": (i, [pm, pd, pi, pi, pd]),
             "orc_transfer_counts": (i, [pm, pi, pi]),
             "orc_rhs": (i, [pm, d, pd, pd, pd, i]),
+            "orc_rhs_g": (i, [pm, d, d, pd, pd, pd, i]),
+            "orc_rhs_points_g": (i, [pm, d, d, pd, pd, i, pi, pd, i]),
             "orc_rhs_binned": (i, [pm, d, pd, pd, pd, i]),
             "orc_rhs_points": (i, [pm, d, pd, pd, i, pi, pd, i]),
             "orc_flow": (i, [pm, pf, d, pd, pr, pd, i, pi, i]),
@@ -182,6 +188,30 @@ def rhs(m: Model, T, V, Z=None, nthreads=0, binned=False):
     return out.reshape(N, N, N)
 
 
+def rhs_g(m: Model, T, g, V, Z=None, nthreads=0):
+    """Interaction flow: dV/dg at temperature T and scale g."""
+    N = m.N
+    V = np.ascontiguousarray(V, np.float64).reshape(N * N * N)
+    Z = _zarg(Z, N)
+    out = np.zeros_like(V)
+    if lib().orc_rhs_g(ctypes.byref(m), float(T), float(g), _pd(Z), _pd(V), _pd(out),
+                       int(nthreads)):
+        raise ValueError("oracle rhs_g rejected its arguments")
+    return out.reshape(N, N, N)
+
+
+def rhs_points_g(m: Model, T, g, V, abc, Z=None, nthreads=0):
+    N = m.N
+    V = np.ascontiguousarray(V, np.float64).reshape(N * N * N)
+    Z = _zarg(Z, N)
+    abc = np.ascontiguousarray(abc, np.int32).reshape(-1, 3)
+    out = np.zeros(abc.shape[0], np.float64)
+    if lib().orc_rhs_points_g(ctypes.byref(m), float(T), float(g), _pd(Z), _pd(V),
+                              abc.shape[0], _pi(abc), _pd(out), int(nthreads)):
+        raise ValueError("oracle rhs_points_g rejected its arguments")
+    return out
+
+
 def rhs_points(m: Model, T, V, abc, Z=None, nthreads=0):
     N = m.N
     V = np.ascontiguousarray(V, np.float64).reshape(N * N * N)
@@ -198,12 +228,14 @@ def rhs_points(m: Model, T, V, abc, Z=None, nthreads=0):
 # flows
 # --------------------------------------------------------------------------------------
 def flowcfg(T0=1.0, T_end=0.01, integrator=0, n_steps=200, rtol=1e-6, atol=None, U=1.0,
-            h0=0.0, h_min=0.0, v_max=20.0, z_lnT=None, z_tab=None):
-    """Build a FlowCfg; keeps references to the Z arrays on the returned object."""
+            h0=0.0, h_min=0.0, v_max=20.0, z_lnT=None, z_tab=None, gflow=False, g_end=1.0):
+    """Build a FlowCfg; keeps references to the Z arrays on the returned object.  gflow:
+    interaction flow at the fixed temperature T0 from g = 0 to g_end (Z nodes in g)."""
     if atol is None:
         atol = 1e-9 * max(1.0, abs(U))
     cfg = FlowCfg(float(T0), float(T_end), int(integrator), int(n_steps), float(rtol),
-                  float(atol), float(h0), float(h_min), float(v_max), 0, None, None)
+                  float(atol), float(h0), float(h_min), float(v_max), 0, None, None,
+                  int(bool(gflow)), float(g_end))
     if z_tab is not None:
         z_lnT = np.ascontiguousarray(z_lnT, np.float64)
         z_tab = np.ascontiguousarray(z_tab, np.float64)
@@ -250,3 +282,10 @@ def tc_interp(s_prev, m_prev, s_new, m_new, v_max):
     """The stop rule's crossing point, for tests: 1/max|V| linear in ln T."""
     return s_prev + (1.0 / m_prev - 1.0 / v_max) * (s_new - s_prev) / (
         1.0 / m_prev - 1.0 / m_new)
+
+
+def gc_interp(g_prev, m_prev, g_new, m_new, v_max):
+    """The interaction flow's crossing point, for tests: 1/max|V| linear in g^2."""
+    u = g_prev ** 2 + (1.0 / m_prev - 1.0 / v_max) * (g_new ** 2 - g_prev ** 2) / (
+        1.0 / m_prev - 1.0 / m_new)
+    return math.sqrt(u)
