@@ -14,9 +14,15 @@
  *     total), the whole Brillouin zone as loop support (App. A, Comment 1);
  *   - stop rule: the flow ends when the largest |V| has grown beyond a threshold (Sec. 3.2,
  *     definition of U*(T)).
- * The flow parameter is the temperature, s = ln T; every internal pair of lines carries the
- * weight Z_a' Z_b' T d/dT chi(xi, xi') with chi the bare static particle-hole (or
- * particle-particle) bubble of the two lines.
+ * Two flows of the same one-loop vertex equation (FM_FLOW_*):
+ *   - temperature flow, s = ln T from T0 down to T_end: every internal pair of lines carries
+ *     the weight Z_a' Z_b' T d/dT chi(xi, xi') with chi the bare static particle-hole (or
+ *     particle-particle) bubble of the two lines;
+ *   - interaction flow, the paper's own scheme (Sec. 2.2; App. A, Steps 1 and 2): at fixed
+ *     T the propagator scale g runs from 0 to g_end, lines G_g = g Z G0 and S_g = Z^2 G0, so
+ *     the pair carries g Z_a' Z_b' (Z_a' + Z_b') chi (2 g chi without Z).  The stop rule
+ *     gives g* and the crossover coupling U*(T) = g*^2 U (Sec. 3.2); fm_flow_tstar inverts
+ *     it to T*(U).
  *
  * Conventions
  *   - Loop grid: L x L points k = -pi + 2 pi (j + 1/2)/L per axis, point index j = jx + L*jy.
@@ -73,6 +79,9 @@ enum { FM_RK4_FIXED = 0, FM_RK45_DOPRI = 1 };
  *                    per product, close to single precision at bf16 matrix-core rates) */
 enum { FM_FP64 = 0, FM_FP32 = 1, FM_FP32_BF16MFMA = 2, FM_FP64_DIRECT = 3, FM_FP32_BF16X3 = 4 };
 
+/* Flow parameter. */
+enum { FM_FLOW_TEMPERATURE = 0, FM_FLOW_INTERACTION = 1 };
+
 /* Channel mask (for ablations of the flow equation). */
 enum { FM_CH_PP = 1, FM_CH_CR = 2, FM_CH_D = 4, FM_CH_ALL = 7 };
 
@@ -86,37 +95,47 @@ typedef struct {
     int geometry;             /* FM_GEOM_* */
     int N, L;                 /* patches; loop grid side.  Angular: N == 1 or N % 4 == 0
                                  with N % 8 in {0, 4}; L % 4 == 0.  Identity: N == L*L. */
-    double T0, T_end;         /* temperature window, T0 > T_end > 0 (finite T only) */
+    double T0, T_end;         /* temperature flow: window, T0 > T_end > 0 (finite T only);
+                                 interaction flow: T0 > 0 is the temperature of
+                                 fm_flow_step (run_batch takes one per flow), T_end unused */
     int integrator, n_steps;  /* FM_RK4_FIXED uses n_steps */
     double rtol, atol;        /* Dormand-Prince: error norm max_i |E_i|/(atol + rtol max(|V|,|Vnew|));
                                  0 selects rtol 1e-6 (1e-4 for FM_FP32_BF16MFMA, whose
                                  right-hand side resolves about 3 digits) and atol
                                  1e-9 max(1, |U|) */
-    double h0, h_min;         /* first step and smallest |step| in ln T; 0 selects
-                                 ln(T_end/T0)/200 and 1e-8 |ln(T_end/T0)| */
+    double h0, h_min;         /* first step and smallest |step| in the flow parameter; 0
+                                 selects span/200 and 1e-8 |span|, span = ln(T_end/T0) or
+                                 g_end (h0 < 0 for the temperature flow, > 0 in g) */
     double v_max;             /* stop when max|V| > v_max (0 selects 20) */
     unsigned channels;        /* FM_CH_* mask (0 selects FM_CH_ALL) */
     int precision;            /* FM_FP64 | FM_FP32 | FM_FP32_BF16MFMA | FM_FP64_DIRECT |
                                  FM_FP32_BF16X3 */
     int n_zT;                 /* 0: no quasi-particle feedback (Z = 1) */
-    const double *z_lnT;      /* host [n_zT], ascending ln T nodes; copied */
-    const double *z_table;    /* host [n_zT][N], 0 < Z <= 1, linear in ln T between nodes,
-                                 clamped outside; copied */
+    const double *z_lnT;      /* host [n_zT], ascending nodes in the flow parameter (ln T, or
+                                 g in [0, g_end] for the interaction flow); copied */
+    const double *z_table;    /* host [n_zT][N], 0 < Z <= 1, linear between nodes, clamped
+                                 outside; copied */
     void *stream;             /* hipStream_t or NULL */
     int max_batch;            /* capacity (flows) for every batched call; >= 1 */
     int tile_rows;            /* single-precision phase 2a: 16-row transfer tiles per
                                  wavefront (>= 1, values past all tiles of a group are
                                  clamped); 0 = chosen by timing 1, 2, 4, ... and all on the
                                  first call (kept per shape for the process) */
+    int flow;                 /* FM_FLOW_TEMPERATURE (0) | FM_FLOW_INTERACTION */
+    double g_end;             /* interaction flow: last g (0 selects 1) */
 } fm_config;
 
 typedef struct {
-    double T_c;        /* interpolated crossing of max|V| = v_max in (ln T, ln max|V|);
-                          NaN unless status is DIVERGED or NONFINITE */
-    double T_final;    /* temperature of the last accepted step */
-    double max_abs_V;  /* max|V| at T_final */
-    int status;        /* FM_FLOW_* */
+    double T_c;        /* temperature flow: crossing of max|V| = v_max, 1/max|V| interpolated
+                          linearly in ln T over the last step; NaN unless status is DIVERGED
+                          or NONFINITE, and for the interaction flow */
+    double T_final;    /* temperature of the last accepted step (the flow's T in g) */
+    double max_abs_V;  /* max|V| at the last accepted step */
+    int status;        /* FM_FLOW_* (REACHED_TEND: T_end, or g_end, reached) */
     int n_accepted, n_rejected, n_rhs;
+    double g_c;        /* interaction flow: crossing g*, 1/max|V| linear in g^2; else NaN */
+    double U_star;     /* interaction flow: g*^2 U (Sec. 3.2, U*(T)); else NaN */
+    double g_final;    /* interaction flow: g of the last accepted step; else NaN */
 } fm_result;
 
 /* Bytes of device workspace needed for cfg (all buffers for cfg->max_batch flows). */
@@ -129,10 +148,19 @@ int fm_flow_init(const fm_config *cfg, void *workspace_dev, size_t bytes, fm_flo
 
 /* dV/d ln T for `batch` independent states at temperatures T[batch] (host array):
  * V_dev and dV_dev are device arrays of batch*N^3 doubles (dV_dev may not alias V_dev).
- * Z (if configured) is taken from the table at ln T.  Asynchronous on cfg.stream. */
+ * Z (if configured) is taken from the table at ln T.  Asynchronous on cfg.stream.
+ * Temperature-flow handles only (FM_EINVAL otherwise). */
 int fm_flow_rhs(fm_flow *h, int batch, const double *T, const double *V_dev, double *dV_dev);
 
-/* One integrator step for `batch` states.  lnT[batch], h[batch] are host in/out arrays,
+/* Interaction flow (App. A, Eq. vertex_flow_feedback_Z): dV/dg for `batch` states at
+ * temperatures T[batch] and scales g[batch] (host arrays, T > 0, g finite); Z (if
+ * configured) from the table at g.  Layout, aliasing and streams as fm_flow_rhs.
+ * Interaction-flow handles only (FM_EINVAL otherwise). */
+int fm_flow_rhs_g(fm_flow *h, int batch, const double *T, const double *g, const double *V_dev,
+                  double *dV_dev);
+
+/* One integrator step for `batch` states.  lnT[batch], h[batch] are host in/out arrays
+ * (ln T and its step; for the interaction flow g and its step, at T = cfg.T0),
  * V_dev (device, batch*N^3 doubles) in/out, accepted[batch] host out.
  * RK4: always accepted, lnT += h, h unchanged.  Dormand-Prince: the step is accepted when
  * the error norm is <= 1; then V and lnT advance; h returns the proposed next step
@@ -140,8 +168,9 @@ int fm_flow_rhs(fm_flow *h, int batch, const double *T, const double *V_dev, dou
 int fm_flow_step(fm_flow *h, int batch, double *lnT, double *hstep, double *V_dev,
                  int *accepted);
 
-/* Runs n_flows independent flows from V = U[f] at T0[f] down to cfg.T_end or until the stop
- * rule fires, all on the device: one integrator step of every running flow per replay of a
+/* Runs n_flows independent flows from V = U[f] at T0[f] down to cfg.T_end (interaction
+ * flow: at the fixed temperature T0[f] > 0 from g = 0 to cfg.g_end) or until the stop rule
+ * fires, all on the device: one integrator step of every running flow per replay of a
  * captured graph; finished flows are masked.  z_lnT / z_tables: NULL (use cfg's table for
  * every flow, or none) or per-flow host arrays [n_flows][n_zT] and [n_flows][n_zT][N].
  * V_final_dev: NULL or a device array of n_flows*N^3 doubles receiving the final states.
@@ -149,6 +178,17 @@ int fm_flow_step(fm_flow *h, int batch, double *lnT, double *hstep, double *V_de
 int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0,
                       const double *z_lnT, const double *z_tables, double *V_final_dev,
                       fm_result *res);
+
+/* Interaction flow: T*(U) for n_flows couplings U[f] (n_flows <= max_batch), the
+ * temperature below which the flow of bare U diverges before g = cfg.g_end, i.e. the root
+ * of U*(T) = U (Sec. 3.2).  Bisection in ln T inside [T_lo, T_hi] on the outcome of batched
+ * interaction flows (diverged, or not, by g_end) until hi/lo - 1 <= rtol; T_star[f] is the
+ * geometric midpoint of the final bracket.  status[f]: 0 found, 1 the flow diverges already
+ * at T_hi (T* >= T_hi), 2 it does not at T_lo (T* <= T_lo), T_star[f] = NaN for 1 and 2.
+ * Uses cfg's Z table for every flow.  FM_EINVAL for a temperature-flow handle or a bad
+ * bracket. */
+int fm_flow_tstar(fm_flow *h, int n_flows, const double *U, double T_lo, double T_hi,
+                  double rtol, double *T_star, int *status);
 
 /* Host-only geometry query (no device needed): xi[L*L], patch[L*L], anchor[N][2] (snapped
  * Fermi-point transfer indices, or loop indices in identity mode), the numbers of distinct

@@ -109,7 +109,15 @@ struct Layout {
 int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (!in) { why = "null config"; return FM_EINVAL; }
     c = *in;
-    if (!(c.T0 > c.T_end) || !(c.T_end > 0.0)) { why = "need T0 > T_end > 0"; return FM_EINVAL; }
+    if (c.flow != FM_FLOW_TEMPERATURE && c.flow != FM_FLOW_INTERACTION) { why = "bad flow"; return FM_EINVAL; }
+    if (c.flow == FM_FLOW_INTERACTION) {
+        if (!(c.T0 > 0.0) || !std::isfinite(c.T0)) { why = "interaction flow needs T0 > 0"; return FM_EINVAL; }
+        if (c.g_end == 0.0) c.g_end = 1.0;
+        if (!(c.g_end > 0.0) || !std::isfinite(c.g_end)) { why = "g_end must be positive"; return FM_EINVAL; }
+    } else if (!(c.T0 > c.T_end) || !(c.T_end > 0.0)) {
+        why = "need T0 > T_end > 0";
+        return FM_EINVAL;
+    }
     if (c.integrator != FM_RK4_FIXED && c.integrator != FM_RK45_DOPRI) { why = "bad integrator"; return FM_EINVAL; }
     if (c.integrator == FM_RK4_FIXED && c.n_steps < 1) { why = "RK4 needs n_steps >= 1"; return FM_EINVAL; }
     if (c.precision < FM_FP64 || c.precision > FM_FP32_BF16X3) { why = "bad precision"; return FM_EINVAL; }
@@ -205,12 +213,15 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.z_tab = L.take<double>(static_cast<size_t>(B) * nz * N);
     b.T_stage = L.take<double>(B);
     b.Z_stage = L.take<double>(static_cast<size_t>(B) * N);
+    b.zw_stage = L.take<double>(2 * static_cast<size_t>(B));
     b.U = L.take<double>(B);
     b.nblk = static_cast<int>(std::min<size_t>((N3 + 255) / 256, 512));
     b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
     b.bstride = B;
     if (!direct) {
-        const size_t S = static_cast<size_t>(step_plan(c.integrator == FM_RK45_DOPRI).bp.n);
+        // the interaction flow bins once per flow (T is fixed): one set
+        const size_t S = c.flow == FM_FLOW_INTERACTION
+                             ? 1 : static_cast<size_t>(step_plan(c.integrator == FM_RK45_DOPRI).bp.n);
         b.nbset = static_cast<int>(S);
         b.bins = L.take<char>(S * B * (nRp + nRd) * NN * rs);
         b.binsT = L.take<char>(S * B * nRd * NN * rs);
@@ -376,7 +387,11 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
 // One integrator step of every running flow (no host interaction).  V is the state array.
 void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed, double v_max) {
     const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
-    const StepPlan plan = step_plan(rk45);
+    StepPlan plan = step_plan(rk45);
+    if (h->g.gflow) {          // bins of the flow's fixed T, computed when the flow starts
+        plan.bp = kNoBins;
+        for (int& s : plan.set) s = 0;
+    }
     if (!rk45) {
         for (int s = 0; s < 4; ++s) {
             stage_launch(h, nf, rk4_stage(s), s == plan.first ? plan.bp : kNoBins, 0, V);
@@ -407,6 +422,14 @@ int upload_z(fm_flow* h, int nf, const double* zl, const double* zt) {
     for (int f = 0; f < nf; ++f) {
         const double* sl = zl ? zl + static_cast<size_t>(f) * nz : h->zlnT.data();
         const double* st = zt ? zt + static_cast<size_t>(f) * nz * N : h->ztab.data();
+        if (h->g.gflow) {      // nodes in s = -g: negated, in reversed (ascending) order
+            for (int i = 0; i < nz; ++i) {
+                l[static_cast<size_t>(f) * nz + i] = -sl[nz - 1 - i];
+                std::memcpy(&t[(static_cast<size_t>(f) * nz + i) * N],
+                            st + static_cast<size_t>(nz - 1 - i) * N, sizeof(double) * N);
+            }
+            continue;
+        }
         std::memcpy(&l[static_cast<size_t>(f) * nz], sl, sizeof(double) * nz);
         std::memcpy(&t[static_cast<size_t>(f) * nz * N], st, sizeof(double) * nz * N);
     }
@@ -493,6 +516,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.pinv = h->b.pinv;
     g.pI = h->b.pI;
     g.inv_ok = hg.inv_ok ? 1 : 0;
+    g.gflow = c.flow == FM_FLOW_INTERACTION ? 1 : 0;
     g.inv_rot = 0;
     if (hg.inv_ok && N % 2 == 0) {
         g.inv_rot = 1;
@@ -611,7 +635,9 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
     for (auto& f : run) { f.status = FM_FLOW_RUNNING; f.ht = 0.0; }
     HIPCHK(hipMemcpyAsync(h->b.fs, run.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     const StageCoef sc{};
-    const BinPlan step_bins = h->direct ? kNoBins : step_plan(h->cfg.integrator == FM_RK45_DOPRI).bp;
+    const BinPlan step_bins = h->direct ? kNoBins
+                              : h->g.gflow ? kOneNode
+                                           : step_plan(h->cfg.integrator == FM_RK45_DOPRI).bp;
     auto once = [&] {
         const int mma = mma_mode(h->cfg.precision);
         if (group == 0)
@@ -654,6 +680,7 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
     if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
     if (!T || !V_dev || !dV_dev) return fail(FM_EINVAL, "null argument");
     if (V_dev == dV_dev) return fail(FM_EINVAL, "dV_dev must not alias V_dev");
+    if (h->g.gflow) return fail(FM_EINVAL, "interaction-flow handle: use fm_flow_rhs_g");
     for (int f = 0; f < batch; ++f) {
         if (!(T[f] > 0.0) || !std::isfinite(T[f])) return fail(FM_EINVAL, "T must be positive and finite");
         FlowState s{};
@@ -677,12 +704,15 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
     if (!lnT || !hstep || !V_dev || !accepted) return fail(FM_EINVAL, "null argument");
     const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
+    const bool gf = h->g.gflow != 0;   // lnT holds g, and s = -g internally
     for (int f = 0; f < batch; ++f) {
         if (!std::isfinite(lnT[f]) || !std::isfinite(hstep[f]) || hstep[f] == 0.0)
             return fail(FM_EINVAL, "lnT and h must be finite, h nonzero");
         FlowState s{};
-        s.lnT = lnT[f];
-        s.h = s.ht = hstep[f];
+        s.lnT = gf ? -lnT[f] : lnT[f];
+        s.h = s.ht = gf ? -hstep[f] : hstep[f];
+        s.gflow = gf ? 1 : 0;
+        s.Tfix = gf ? h->cfg.T0 : 0.0;
         s.lnT_end = -std::numeric_limits<double>::infinity();
         s.hmin = 0.0;
         s.atol = h->cfg.atol > 0.0 ? h->cfg.atol : 1e-9 * std::max(1.0, std::fabs(h->cfg.U));
@@ -696,6 +726,8 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     if (rk45) {
         stage_launch(h, batch, dp_stage(0), kOneNode, 0, V_dev);
         rhs_launch(h, batch, 0, 0);
+    } else if (gf) {        // the interaction flow's bins, at its fixed temperature
+        stage_launch(h, batch, rk4_stage(0), kOneNode, 0, V_dev);
     }
     step_launch(h, batch, V_dev, 0, 0.0, inf);
     HIPCHK(hipGetLastError());
@@ -704,9 +736,37 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     for (int f = 0; f < batch; ++f) {
         const FlowState& s = h->hfs[f];
         accepted[f] = s.accepted;
-        if (s.accepted) lnT[f] = s.lnT;
-        if (rk45) hstep[f] = s.h;
+        if (s.accepted) lnT[f] = gf ? -s.lnT : s.lnT;
+        if (rk45) hstep[f] = gf ? -s.h : s.h;
     }
+    return FM_OK;
+}
+
+int fm_flow_rhs_g(fm_flow* h, int batch, const double* T, const double* g, const double* V_dev,
+                  double* dV_dev) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (batch < 1 || batch > h->cfg.max_batch) return fail(FM_EINVAL, "batch outside [1, max_batch]");
+    if (!T || !g || !V_dev || !dV_dev) return fail(FM_EINVAL, "null argument");
+    if (V_dev == dV_dev) return fail(FM_EINVAL, "dV_dev must not alias V_dev");
+    if (!h->g.gflow) return fail(FM_EINVAL, "temperature-flow handle: use fm_flow_rhs");
+    for (int f = 0; f < batch; ++f) {
+        if (!(T[f] > 0.0) || !std::isfinite(T[f])) return fail(FM_EINVAL, "T must be positive and finite");
+        if (!std::isfinite(g[f])) return fail(FM_EINVAL, "g must be finite");
+        FlowState s{};
+        s.lnT = -g[f];
+        s.Tfix = T[f];
+        s.gflow = 1;
+        s.status = FM_FLOW_RUNNING;
+        h->hfs[f] = s;
+    }
+    HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
+    if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
+    untimed(h);
+    StageCoef sc{};
+    stage_launch(h, batch, sc, kOneNode, 0, V_dev);
+    rhs_launch(h, batch, 0, 0);
+    launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);   // -dV/ds = dV/dg
+    HIPCHK(hipGetLastError());
     return FM_OK;
 }
 
@@ -719,15 +779,22 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     if (z_tables && h->cfg.n_zT == 0) return fail(FM_EINVAL, "per-flow Z tables need cfg.n_zT > 0");
     const fm_config& c = h->cfg;
     const bool rk45 = c.integrator == FM_RK45_DOPRI;
-    const double lnTe = std::log(c.T_end);
+    const bool gf = h->g.gflow != 0;
+    // temperature flow: s = ln T from ln T0 down to ln T_end; interaction flow: s = -g from 0
+    // down to -g_end at the fixed T0[f]
+    const double lnTe = gf ? -c.g_end : std::log(c.T_end);
     for (int f = 0; f < n; ++f) {
-        if (!(T0[f] > c.T_end) || !std::isfinite(U[f])) return fail(FM_EINVAL, "need T0[f] > T_end and finite U");
+        if (gf ? !(T0[f] > 0.0 && std::isfinite(T0[f])) : !(T0[f] > c.T_end))
+            return fail(FM_EINVAL, gf ? "need T0[f] > 0" : "need T0[f] > T_end");
+        if (!std::isfinite(U[f])) return fail(FM_EINVAL, "need a finite U");
         FlowState s{};
-        s.s0 = s.lnT = std::log(T0[f]);
+        s.s0 = s.lnT = gf ? 0.0 : std::log(T0[f]);
         s.lnT_end = lnTe;
+        s.gflow = gf ? 1 : 0;
+        s.Tfix = gf ? T0[f] : 0.0;
         const double span = lnTe - s.s0;
         if (rk45) {
-            s.h = c.h0 != 0.0 ? c.h0 : span / 200.0;
+            s.h = c.h0 != 0.0 ? (gf ? -c.h0 : c.h0) : span / 200.0;
             s.ht = (s.lnT + s.h <= lnTe) ? lnTe - s.lnT : s.h;
             s.hmin = c.h_min > 0.0 ? c.h_min : 1e-8 * std::fabs(span);
         } else {
@@ -755,6 +822,8 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     if (rk45) {
         stage_launch(h, n, dp_stage(0), kOneNode, 0, h->b.V);
         rhs_launch(h, n, 0, 0);
+    } else if (gf) {        // the interaction flow's bins, at its fixed temperature
+        stage_launch(h, n, rk4_stage(0), kOneNode, 0, h->b.V);
     }
     HIPCHK(hipGetLastError());
     // fixed steps: flow f advances on its own grid ln T0_f + k (ln T_end - ln T0_f)/n_steps
@@ -820,14 +889,64 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         const FlowState& s = h->hfs[f];
         fm_result& r = res[f];
         r.status = s.status == FM_FLOW_RUNNING ? FM_FLOW_STEPFAIL : s.status;
-        r.T_c = (s.status == FM_FLOW_DIVERGED || s.status == FM_FLOW_NONFINITE)
-                    ? std::exp(s.lnTc) : std::numeric_limits<double>::quiet_NaN();
-        r.T_final = std::exp(s.lnT);
+        const bool stopped = s.status == FM_FLOW_DIVERGED || s.status == FM_FLOW_NONFINITE;
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        r.T_c = (stopped && !gf) ? std::exp(s.lnTc) : nan;
+        r.T_final = gf ? s.Tfix : std::exp(s.lnT);
+        r.g_c = (stopped && gf) ? 0.0 - s.lnTc : nan;
+        r.U_star = (stopped && gf) ? s.lnTc * s.lnTc * U[f] : nan;
+        r.g_final = gf ? 0.0 - s.lnT : nan;
         r.max_abs_V = s.m;
         r.n_accepted = s.n_acc;
         r.n_rejected = s.n_rej;
         r.n_rhs = s.n_rhs;
     }
+    return FM_OK;
+}
+
+int fm_flow_tstar(fm_flow* h, int n, const double* U, double T_lo, double T_hi, double rtol,
+                  double* T_star, int* status) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (!h->g.gflow) return fail(FM_EINVAL, "T*(U) needs an interaction-flow handle");
+    if (n < 1 || n > h->cfg.max_batch) return fail(FM_EINVAL, "n_flows outside [1, max_batch]");
+    if (!U || !T_star || !status) return fail(FM_EINVAL, "null argument");
+    if (!(T_lo > 0.0) || !(T_hi > T_lo) || !std::isfinite(T_hi) || !(rtol > 0.0))
+        return fail(FM_EINVAL, "need 0 < T_lo < T_hi and rtol > 0");
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    std::vector<double> lo(n, std::log(T_lo)), hi(n, std::log(T_hi));
+    std::vector<double> Ua, Ta;
+    std::vector<int> idx;
+    std::vector<fm_result> r(n);
+    auto diverged = [](const fm_result& x) {
+        return x.status == FM_FLOW_DIVERGED || x.status == FM_FLOW_NONFINITE;
+    };
+    // the bracket: below T* the flow diverges before g_end, above it does not
+    std::vector<double> Tv(n, T_hi);
+    if (int rc = fm_flow_run_batch(h, n, U, Tv.data(), nullptr, nullptr, nullptr, r.data())) return rc;
+    for (int f = 0; f < n; ++f) status[f] = diverged(r[f]) ? 1 : 0;
+    std::fill(Tv.begin(), Tv.end(), T_lo);
+    if (int rc = fm_flow_run_batch(h, n, U, Tv.data(), nullptr, nullptr, nullptr, r.data())) return rc;
+    for (int f = 0; f < n; ++f)
+        if (status[f] == 0 && !diverged(r[f])) status[f] = 2;
+    const double width = std::log1p(rtol);
+    for (;;) {
+        idx.clear(); Ua.clear(); Ta.clear();
+        for (int f = 0; f < n; ++f)
+            if (status[f] == 0 && hi[f] - lo[f] > width) {
+                idx.push_back(f);
+                Ua.push_back(U[f]);
+                Ta.push_back(std::exp(0.5 * (lo[f] + hi[f])));
+            }
+        if (idx.empty()) break;
+        const int m = static_cast<int>(idx.size());
+        if (int rc = fm_flow_run_batch(h, m, Ua.data(), Ta.data(), nullptr, nullptr, nullptr, r.data()))
+            return rc;
+        for (int i = 0; i < m; ++i) {
+            const int f = idx[i];
+            (diverged(r[i]) ? lo[f] : hi[f]) = std::log(Ta[i]);
+        }
+    }
+    for (int f = 0; f < n; ++f) T_star[f] = status[f] == 0 ? std::exp(0.5 * (lo[f] + hi[f])) : nan;
     return FM_OK;
 }
 

@@ -50,8 +50,10 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err);
 // ------------------------------------------------------------------------------------
 // Device-side per-flow integrator state (double precision throughout).
 // ------------------------------------------------------------------------------------
+// s is ln T for the temperature flow and -g for the interaction flow, so that both run
+// towards smaller s; dV/ds = -dV/dg in the latter.
 struct FlowState {
-    double lnT;      // accepted ln T
+    double lnT;      // accepted s (ln T, or -g)
     double h;        // proposed next step
     double ht;       // step being attempted (h, or clamped to reach ln T_end)
     double lnT_end;  // -inf for free stepping
@@ -61,10 +63,11 @@ struct FlowState {
     double hmin;     // smallest allowed |h|
     double s0;       // ln T0 (fixed-step grid origin)
     double atol;     // absolute error tolerance of this flow
+    double Tfix;     // interaction flow: the flow's temperature
     int status;      // FM_FLOW_*
     int accepted;    // outcome of the last attempt
     int n_acc, n_rej, n_rhs;
-    int pad;
+    int gflow;       // 1: interaction flow
 };
 
 // Geometry as the kernels see it.
@@ -81,6 +84,7 @@ struct DevGeom {
     const int* pI;         // [N] patch permutation of k -> -k
     int inv_ok;            // pI is valid (k -> -k maps patches and dispersion onto themselves)
     int inv_rot;           // pI[a] = (a + N/2) mod N
+    int gflow;             // interaction flow: bins of chi instead of T d/dT chi
     const int* pp_off; const int* pp_pairs;
     const int* cr_off; const int* cr_pairs;
     const int* d_off;  const int* d_pairs;
@@ -127,6 +131,7 @@ struct Buffers {
     double* z_lnT; double* z_tab;      // [B][nz], [B][nz][N]
     double* T_stage;                   // [B]
     double* Z_stage;                   // [B][N]
+    double* zw_stage;                  // [B][2]: line-pair factor Z_a Z_b (al + be (Z_a + Z_b))
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;

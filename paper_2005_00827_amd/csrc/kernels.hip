@@ -119,19 +119,29 @@ __device__ inline R kval(const R* K, int l, int B, int f, size_t N3, size_t i) {
 
 // ------------------------------------------------------------------------------------
 // Stage argument V_s = V + h sum_l a_l k_l (double), Z and T of the stage, operand layouts
-//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z).
+//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z),
+// and the factor of the internal line pair (a', b') applied in phase 2a,
+//   Z_a' Z_b' (al + be (Z_a' + Z_b')):
+//   temperature flow (s = ln T): al = 1, be = 0, with bins of T d/dT chi;
+//   interaction flow (s = -g, lines G_g = g Z G0 and S_g = Z^2 G0, App. A, Step 2):
+//   al = 0, be = s = -g, with bins of chi, so that the product is dV/ds = -dV/dg.
 // ------------------------------------------------------------------------------------
 template <typename R>
 __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowState& st, int f,
                                   const StageCoef& sc, int write_new, const double* Vbase,
                                   const R* K, double* Vnew, R* v0, R* va, R* vc,
-                                  double* T_stage, double* Z_stage, int B, int blk, int nblk) {
+                                  double* T_stage, double* Z_stage, double* zw, int B, int blk,
+                                  int nblk) {
     const int N = g.N, NN = g.NN;
     const size_t N3 = static_cast<size_t>(NN) * N;
     const double ht = st.ht;
     const double lnTs = st.lnT + sc.c * ht;
     if (blk == 0) {
-        if (threadIdx.x == 0) T_stage[f] = exp(lnTs);
+        if (threadIdx.x == 0) {
+            T_stage[f] = st.gflow ? st.Tfix : exp(lnTs);
+            zw[2 * f] = st.gflow ? 0.0 : 1.0;
+            zw[2 * f + 1] = st.gflow ? lnTs : 0.0;
+        }
         for (int a = threadIdx.x; a < N; a += blockDim.x)
             Z_stage[static_cast<size_t>(f) * N + a] = z_interp(z, f, N, a, lnTs);
     }
@@ -224,6 +234,64 @@ __device__ inline double pair_weight(double xu, double xv, double twoT, bool pp)
     return phi_dd_pt(u, pp ? flip(v) : v);
 }
 
+// Interaction-flow weight of one loop-point pair: the divided difference
+// tanh[a,b] = (tanh a - tanh b)/(a - b), a = xi/2T (b negated for particle-particle), so
+// that chi = tanh[a,b] / 4T.  With e = exp(-2|x|), tanh|x| = (1 - e)/(1 + e) and, for a and
+// b of one sign, tanh a - tanh b = sgn(a) 2 (e_b/(1 + e_b) - e_a/(1 + e_a)) without
+// cancellation.
+// Near the diagonal (|a - b| < 0.05) the trapezoid value with its end correction,
+//   tanh[a,b] = (s_a + s_b)/2 - (a-b)^2 (s_a (6 t_a^2 - 2) + s_b (6 t_b^2 - 2))/24 + O((a-b)^4),
+// with s = sech^2, t = tanh (the third derivative of tanh is sech^2 (6 tanh^2 - 2)), taken
+// only when a lane of the wave needs it.
+__device__ inline float pair_chi(float xu, float xv, float inv2T, bool pp) {
+    const float a = xu * inv2T;
+    const float b0 = xv * inv2T;
+    const float b = pp ? -b0 : b0;
+    const float ea = __expf(-2.0f * fabsf(a)), eb = __expf(-2.0f * fabsf(b));
+    const float ra = __builtin_amdgcn_rcpf(1.0f + ea), rb = __builtin_amdgcn_rcpf(1.0f + eb);
+    const float ta = copysignf((1.0f - ea) * ra, a), tb = copysignf((1.0f - eb) * rb, b);
+    const bool same = (a >= 0.0f) == (b >= 0.0f);
+    const float diff = same ? (a >= 0.0f ? 2.0f : -2.0f) * (eb * rb - ea * ra) : ta - tb;
+    const float d = a - b;
+    float w = diff * __builtin_amdgcn_rcpf(d);
+    const bool near = fabsf(d) < 0.05f;
+    if (__ballot(near)) {
+        if (near) {
+            const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;
+            const float c3 = sa * (6.0f * ta * ta - 2.0f) + sb * (6.0f * tb * tb - 2.0f);
+            w = 0.5f * (sa + sb) - (d * d) * c3 * (1.0f / 24.0f);
+        }
+    }
+    return w;
+}
+// Double precision: the quotient away from the diagonal; within |a - b| < 0.01 the series
+// about the midpoint m, tanh[a,b] = s (1 + (6 t^2 - 2) d^2/24 + (16 - 120 t^2 + 120 t^4) d^4/1920)
+// + O(d^6), s = sech^2 m, t = tanh m, d = a - b.
+__device__ inline double tanh_abs(double x, double& e) {
+    e = exp(-2.0 * fabs(x));
+    return (1.0 - e) / (1.0 + e);
+}
+__device__ inline double pair_chi(double xu, double xv, double twoT, bool pp) {
+    const double a = xu / twoT;
+    const double b = pp ? -(xv / twoT) : xv / twoT;
+    const double d = a - b;
+    if (fabs(d) >= 0.01) {
+        double ea, eb;
+        const double ta = copysign(tanh_abs(a, ea), a), tb = copysign(tanh_abs(b, eb), b);
+        const bool same = (a >= 0.0) == (b >= 0.0);
+        const double diff = same ? (a >= 0.0 ? 2.0 : -2.0) * (eb / (1.0 + eb) - ea / (1.0 + ea))
+                                 : ta - tb;
+        return diff / d;
+    }
+    const double m = 0.5 * (a + b);
+    double e;
+    const double t = copysign(tanh_abs(m, e), m);
+    const double s = 4.0 * e / ((1.0 + e) * (1.0 + e));
+    const double t2 = t * t, d2 = d * d;
+    return s * (1.0 + (6.0 * t2 - 2.0) * d2 * (1.0 / 24.0) +
+                (16.0 - 120.0 * t2 + 120.0 * t2 * t2) * d2 * d2 * (1.0 / 1920.0));
+}
+
 // ------------------------------------------------------------------------------------
 // Phase 1: bins of the representative transfers.  One 1024-thread block per
 // (representative, flow) accumulates the N x N bin matrix in LDS and stores it scaled by
@@ -312,7 +380,8 @@ __device__ inline int inv_patch(const DevGeom& g, int a) {
     return g.pI[a];
 }
 
-template <typename R, int kMode, int BT>
+// kG = 1: interaction-flow bins, chi = tanh[a,b]/4T, stored scaled by +1/(4 T L^2).
+template <typename R, int kMode, int BT, int kG>
 __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bins, R* binsT,
                                  R* lb) {
     using PT = typename PtT<R>::T;
@@ -322,7 +391,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int m = pp ? g.rep_pp[r] : g.rep_ph[r - g.nRp];
     const int mx = m % L, my = m / L;
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
-    const R scale = static_cast<R>(-1.0 / (4.0 * T * np));
+    const R scale = static_cast<R>((kG ? 1.0 : -1.0) / (4.0 * T * np));
     const R tp = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * T) : 2.0 * T);   // 1/2T or 2T
     constexpr int kBinBatch = BinBatch<R>::v;
     const bool half = (pp || g.inv_ok) && L % 2 == 0;
@@ -367,7 +436,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
             const bool ok = u0 + i < u_end && (u0 + i) * 16 + s < npt;
-            const R w = pair_weight(xu[i], xv[i], tp, pp);
+            const R w = kG ? pair_chi(xu[i], xv[i], tp, pp) : pair_weight(xu[i], xv[i], tp, pp);
             R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
             const int key = pa[i] * N + pq[i];
             const int key2 = pp ? pq[i] * N + pa[i] : inv_patch(g, pq[i]) * N + inv_patch(g, pa[i]);
@@ -395,7 +464,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
         int qa, qb;
         xi_patch(g, jy * L + jx, xa, qa);
         xi_patch(g, py * L + px, xb, qb);
-        const R w = pair_weight(xa, xb, tp, pp);
+        const R w = kG ? pair_chi(xa, xb, tp, pp) : pair_weight(xa, xb, tp, pp);
         atomicAdd(&acc[qa * N + qb], kMode == 0 ? w : w * scale);
     }
     if (kMode == 1) __threadfence();
@@ -416,14 +485,14 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
 // only T) at every node of the plan -- the first stage of an integrator step bins all the
 // step's distinct nodes at once, the later stages none -- and the remaining blocks form the
 // stage argument and its operand layouts.  Grid (nRb bp.n + stage blocks, flows).
-template <typename R, int kMode, int BT>
+template <typename R, int kMode, int BT, int kG>
 __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
                                                             StageCoef sc, BinPlan bp,
                                                             int write_new, const double* Vbase,
                                                             const R* K, double* Vnew, R* v0,
                                                             R* va, R* vc, double* T_stage,
-                                                            double* Z_stage, R* bins, R* binsT,
-                                                            int nRb, int B) {
+                                                            double* Z_stage, double* zw,
+                                                            R* bins, R* binsT, int nRb, int B) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;                      // uniform over the block
@@ -432,14 +501,14 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
     if (static_cast<int>(blockIdx.x) < nbin) {
         const int set = static_cast<int>(blockIdx.x) / nRb;
         const int r = static_cast<int>(blockIdx.x) - set * nRb;
-        const double T = exp(st.lnT + bp.c[set] * st.ht);
+        const double T = kG ? st.Tfix : exp(st.lnT + bp.c[set] * st.ht);
         const size_t NN = static_cast<size_t>(g.NN);
-        bins_part<R, kMode, BT>(g, f, r, T, bins + static_cast<size_t>(set) * B * nRb * NN,
+        bins_part<R, kMode, BT, kG>(g, f, r, T, bins + static_cast<size_t>(set) * B * nRb * NN,
                                 binsT + static_cast<size_t>(set) * B * g.nRd * NN,
                                 reinterpret_cast<R*>(smem_raw));
     } else {
         stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
-                      B, blockIdx.x - nbin, gridDim.x - nbin);
+                      zw, B, blockIdx.x - nbin, gridDim.x - nbin);
     }
 }
 
@@ -463,8 +532,8 @@ struct YArgs {
 
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
-                                                const double* Z_stage, const R* bins,
-                                                const R* binsT, YArgs<R> args) {
+                                                const double* Z_stage, const double* zw,
+                                                const R* bins, const R* binsT, YArgs<R> args) {
     constexpr int TM = 64, TN = 64, TK = 16;
     __shared__ R As[TK][TM + 4];
     __shared__ R Bs[TK][TN + 4];
@@ -488,6 +557,7 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     const R* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
     const double* Zf = Z_stage + static_cast<size_t>(f) * N;
     const R zg = static_cast<R>(Zf[grp]);
+    const R al = static_cast<R>(zw[2 * f]), be = static_cast<R>(zw[2 * f + 1]);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     __shared__ int pis[8 * 256];
     for (int i = threadIdx.x; i < 8 * N && i < 8 * 256; i += blockDim.x) pis[i] = g.pinv[i];
@@ -516,7 +586,8 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     }
     for (int k0 = 0; k0 < N; k0 += TK) {
         const int k = k0 + kk_t;
-        const R zk = k < N ? zg * static_cast<R>(Zf[k]) : R(0);
+        const R zkk = k < N ? static_cast<R>(Zf[k]) : R(0);
+        const R zk = k < N ? zg * zkk * (al + be * (zg + zkk)) : R(0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rr = threadIdx.x / TK + 16 * i;
@@ -654,7 +725,7 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
 template <int kM, int KE>
 __device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, int grp,
                                 int rep, int op, const int* pis, const float* zs, float zg,
-                                int lane) {
+                                float al, float be, int lane) {
     const int* pi = pis + op * N;
     const float* row = Bf + static_cast<size_t>(rep) * NN + pi[grp] * N;
 #pragma unroll
@@ -662,7 +733,8 @@ __device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, 
         const int k = mfma_k<kM>(e, lane);
         const int kc = min(k, N - 1);
         const float x = row[pi[kc]];
-        a[e] = k < N ? x * (zg * zs[kc]) : 0.f;
+        const float zk = zs[kc];
+        a[e] = k < N ? x * (zg * zk * (al + be * (zg + zk))) : 0.f;
     }
 }
 
@@ -680,18 +752,19 @@ __device__ inline void tile_rep(const int* qrep, const int* qg, int M, int tile,
 template <int kM, int KE, int NT, bool kTwo>
 __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, int NN, int N,
                                int M, int grp, int n0, int t_begin, int t_end, const int* pis,
-                               const float* zs, const void* Bs0, const void* Bs1, float* Y0,
-                               float* Y1, int lane, int r0, int o0, int r1, int o1) {
+                               const float* zs, float al, float be, const void* Bs0,
+                               const void* Bs1, float* Y0, float* Y1, int lane, int r0, int o0,
+                               int r1, int o1) {
     const int col = lane & 15;
     const float zg = zs[grp];
     float a0[KE], a1[KE];
-    gather_a<kM, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, lane);
+    gather_a<kM, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, al, be, lane);
     for (int tile = t_begin; tile < t_end; ++tile) {
         // B fragments are re-read from LDS every tile instead of being kept in registers
         asm volatile("" ::: "memory");
         int r2, o2;
         tile_rep(qrep, qg, M, tile + 2, col, r2, o2);
-        if (tile + 1 < t_end) gather_a<kM, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, lane);
+        if (tile + 1 < t_end) gather_a<kM, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, al, be, lane);
         fm_f4 c0[NT], c1[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u) c0[u] = c1[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
@@ -725,9 +798,10 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
 // every wave gathers its tiles' A operands straight into MFMA layout.
 template <int kM, int KE, int NT>
 __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
-                                                     const double* Z_stage, const float* bins,
-                                                     const float* binsT, YArgs<float> args,
-                                                     int nchunk, int tpw, int bx, int nwork) {
+                                                     const double* Z_stage, const double* zw,
+                                                     const float* bins, const float* binsT,
+                                                     YArgs<float> args, int nchunk, int tpw,
+                                                     int bx, int nwork) {
     constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
     constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
     __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
@@ -792,13 +866,15 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     const void* B0 = Braw;
     const void* B1 = Braw + kBytes;
+    const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
     if (two)
         y_tiles<kM, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                     B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane, r0, o0,
-                                     r1, o1);
+                                     al, be, B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane,
+                                     r0, o0, r1, o1);
     else
         y_tiles<kM, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                      B0, B1, args.Y[ch] + yoff, nullptr, lane, r0, o0, r1, o1);
+                                      al, be, B0, B1, args.Y[ch] + yoff, nullptr, lane, r0, o0,
+                                      r1, o1);
 }
 
 // ------------------------------------------------------------------------------------
@@ -957,7 +1033,8 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_wtable(DevGeom g, const FlowState* fs,
                                                      const double* T_stage,
-                                                     const double* Z_stage, double* W) {
+                                                     const double* Z_stage, const double* zw,
+                                                     double* W) {
     const int f = blockIdx.z;
     if (!running(fs, f)) return;
     const int q = blockIdx.y;
@@ -967,12 +1044,19 @@ __global__ void __launch_bounds__(kThreads) k_wtable(DevGeom g, const FlowState*
     const int m = pp ? g.q_pp[q] : g.q_ph[q - g.nP];
     const int jp = pp ? partner_pp(m, j, g.L) : partner_ph(m, j, g.L);
     const double T = T_stage[f];
-    const double a = g.xi[j] / (2.0 * T);
-    double b = g.xi[jp] / (2.0 * T);
-    if (pp) b = -b;
-    const double w = -phi_dd<double>(a, phi_d(a), b, phi_d(b)) / (4.0 * T * g.np);
+    double w;
+    if (g.gflow) {
+        w = pair_chi(g.xi[j], g.xi[jp], 2.0 * T, pp) / (4.0 * T * g.np);
+    } else {
+        const double a = g.xi[j] / (2.0 * T);
+        double b = g.xi[jp] / (2.0 * T);
+        if (pp) b = -b;
+        w = -phi_dd<double>(a, phi_d(a), b, phi_d(b)) / (4.0 * T * g.np);
+    }
     const double* Z = Z_stage + static_cast<size_t>(f) * g.N;
-    W[(static_cast<size_t>(f) * (g.nP + g.nD) + q) * g.np + j] = Z[g.patch[j]] * Z[g.patch[jp]] * w;
+    const double za = Z[g.patch[j]], zb = Z[g.patch[jp]];
+    W[(static_cast<size_t>(f) * (g.nP + g.nD) + q) * g.np + j] =
+        za * zb * (zw[2 * f] + zw[2 * f + 1] * (za + zb)) * w;
 }
 
 __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState* fs,
@@ -1027,7 +1111,8 @@ __global__ void __launch_bounds__(kThreads) k_to_f64(const FlowState* fs, const 
     if (!running(fs, f)) return;
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
          i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        out[f * N3 + i] = static_cast<double>(kval(K, 0, 0, f, N3, i));
+        out[f * N3 + i] = fs[f].gflow ? -static_cast<double>(kval(K, 0, 0, f, N3, i))
+                                      : static_cast<double>(kval(K, 0, 0, f, N3, i));
 }
 
 __global__ void __launch_bounds__(kThreads) k_fill_u(double* V, const double* U, size_t N3) {
@@ -1119,6 +1204,12 @@ __device__ inline double crossing(double s, double m, double s_new, double mv, d
     if (!(m > 0.0) || mv == m) return s_new;
     return s + (1.0 / m - 1.0 / v_max) * (s_new - s) / (1.0 / m - 1.0 / mv);
 }
+// Interaction flow (s = -g): 1/max|V| interpolated linearly in g^2 (exact for one patch,
+// where 1/v = 1/U - g^2 c).
+__device__ inline double crossing_at(const FlowState& st, double s_new, double mv, double v_max) {
+    if (!st.gflow) return crossing(st.lnT, st.m, s_new, mv, v_max);
+    return -sqrt(crossing(st.lnT * st.lnT, st.m, s_new * s_new, mv, v_max));
+}
 
 __device__ inline double step_factor(double err) {
     if (err == 0.0) return 5.0;
@@ -1157,7 +1248,7 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
         if (!finite) { st.status = FM_FLOW_NONFINITE; st.lnTc = s_new; }
         else if (mv > v_max) {
             st.status = FM_FLOW_DIVERGED;
-            st.lnTc = crossing(s, st.m, s_new, mv, v_max);
+            st.lnTc = crossing_at(st, s_new, mv, v_max);
         }
         st.lnT = s_new;
         st.m = mv;
@@ -1172,7 +1263,7 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
             st.n_acc += 1;
             if (mv > v_max) {
                 st.status = FM_FLOW_DIVERGED;
-                st.lnTc = crossing(s, st.m, s_new, mv, v_max);
+                st.lnTc = crossing_at(st, s_new, mv, v_max);
             }
             st.lnT = s_new;
             st.m = mv;
@@ -1240,7 +1331,7 @@ int bins_mode(const DevGeom& g) {
 }
 
 // Stage argument plus, when the plan has nodes, their phase 1 in one launch.
-template <typename R, int BT>
+template <typename R, int BT, int kG>
 void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
               const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase,
               int nRb, int ept) {
@@ -1254,15 +1345,15 @@ void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, 
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
     if (nbin == 0 || lds)
-        hipLaunchKernelGGL((k_stage_bins<R, 0, BT>), grid, dim3(BT), shm, s, g, z, b.fs, sc, bp,
-                           write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+        hipLaunchKernelGGL((k_stage_bins<R, 0, BT, kG>), grid, dim3(BT), shm, s, g, z, b.fs, sc,
+                           bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
-                           b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
+                           b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride);
     else
-        hipLaunchKernelGGL((k_stage_bins<R, 1, BT>), grid, dim3(BT), 0, s, g, z, b.fs, sc, bp,
-                           write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+        hipLaunchKernelGGL((k_stage_bins<R, 1, BT, kG>), grid, dim3(BT), 0, s, g, z, b.fs, sc,
+                           bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
-                           b.T_stage, b.Z_stage, bins, binsT, nRb, b.bstride);
+                           b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride);
 }
 
 // Stage argument plus the plan's phase 1 in one launch.  Few (flow, node, representative)
@@ -1272,10 +1363,14 @@ template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
              const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
     const int nRb = b.bins ? g.nRp + g.nRd : 0;
-    if (static_cast<long>(nRb) * bp.n * nf <= 256)
-        stage_go<R, 1024>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
-    else
-        stage_go<R, 256>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
+    const bool wide = static_cast<long>(nRb) * bp.n * nf <= 256;
+    if (g.gflow && bp.n > 0) {
+        if (wide) stage_go<R, 1024, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
+        else stage_go<R, 256, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
+    } else {
+        if (wide) stage_go<R, 1024, 0>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
+        else stage_go<R, 256, 0>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
+    }
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
@@ -1292,7 +1387,8 @@ void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
     const long nwork = static_cast<long>(bx) * g.N * 3 * nf;
     const long nblocks = (nwork + 7) / 8 * 8 * nchunk;
     hipLaunchKernelGGL((k_y_mfma<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
-                       dim3(kThreads), 0, s, g, b.fs, b.Z_stage, static_cast<const float*>(b.bins),
+                       dim3(kThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
+                       static_cast<const float*>(b.bins),
                        static_cast<const float*>(b.binsT), a, nchunk, tpw, bx,
                        static_cast<int>(nwork));
 }
@@ -1346,7 +1442,8 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
     }
     const int tiles = ((mmax + 63) / 64) * ((g.N + 63) / 64);
     hipLaunchKernelGGL(k_y<R>, dim3(tiles, g.N, 4 * nf), dim3(kThreads), 0, s, g, b.fs,
-                       b.Z_stage, static_cast<const R*>(b.bins), static_cast<const R*>(b.binsT), a);
+                       b.Z_stage, b.zw_stage, static_cast<const R*>(b.bins),
+                       static_cast<const R*>(b.binsT), a);
 }
 
 template <typename R>
@@ -1394,7 +1491,7 @@ void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b
 
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {
     hipLaunchKernelGGL(k_wtable, dim3((g.np + kThreads - 1) / kThreads, g.nP + g.nD, nf),
-                       dim3(kThreads), 0, s, g, b.fs, b.T_stage, b.Z_stage, b.wtab);
+                       dim3(kThreads), 0, s, g, b.fs, b.T_stage, b.Z_stage, b.zw_stage, b.wtab);
 }
 
 void launch_direct(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,

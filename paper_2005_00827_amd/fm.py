@@ -28,9 +28,11 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": FP32_BF16MFMA, "fp64_direct": 
 INTEGRATORS = {"rk4": RK4_FIXED, "rk45": RK45_DOPRI}
 
 # every entry point declared in include/fm_flow.h
-EXPORTS = ("fm_flow_workspace_bytes", "fm_flow_init", "fm_flow_rhs", "fm_flow_step",
-           "fm_flow_run_batch", "fm_geometry_query", "fm_flow_set_timing", "fm_flow_timings",
-           "fm_flow_kernel_time", "fm_flow_destroy", "fm_last_error")
+EXPORTS = ("fm_flow_workspace_bytes", "fm_flow_init", "fm_flow_rhs", "fm_flow_rhs_g",
+           "fm_flow_step", "fm_flow_run_batch", "fm_flow_tstar", "fm_geometry_query",
+           "fm_flow_set_timing", "fm_flow_timings", "fm_flow_kernel_time", "fm_flow_destroy",
+           "fm_last_error")
+FLOWS = {"temperature": 0, "interaction": 1}
 
 
 class Config(ctypes.Structure):
@@ -41,13 +43,15 @@ class Config(ctypes.Structure):
                 ("rtol", c_double), ("atol", c_double), ("h0", c_double), ("h_min", c_double),
                 ("v_max", c_double), ("channels", c_uint), ("precision", c_int),
                 ("n_zT", c_int), ("z_lnT", POINTER(c_double)), ("z_table", POINTER(c_double)),
-                ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int)]
+                ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int),
+                ("flow", c_int), ("g_end", c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("T_c", c_double), ("T_final", c_double), ("max_abs_V", c_double),
                 ("status", c_int), ("n_accepted", c_int), ("n_rejected", c_int),
-                ("n_rhs", c_int)]
+                ("n_rhs", c_int), ("g_c", c_double), ("U_star", c_double),
+                ("g_final", c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -77,6 +81,8 @@ def load():
         "fm_flow_workspace_bytes": (c_int, [pc, POINTER(c_size_t)]),
         "fm_flow_init": (c_int, [pc, c_void_p, c_size_t, POINTER(c_void_p)]),
         "fm_flow_rhs": (c_int, [c_void_p, c_int, pd, c_void_p, c_void_p]),
+        "fm_flow_rhs_g": (c_int, [c_void_p, c_int, pd, pd, c_void_p, c_void_p]),
+        "fm_flow_tstar": (c_int, [c_void_p, c_int, pd, c_double, c_double, c_double, pd, pi]),
         "fm_flow_step": (c_int, [c_void_p, c_int, pd, pd, c_void_p, pi]),
         "fm_flow_run_batch": (c_int, [c_void_p, c_int, pd, pd, pd, pd, c_void_p, pr]),
         "fm_geometry_query": (c_int, [pc, pd, pi, pi, pi, pi, pd, pi]),
@@ -109,7 +115,7 @@ def _pi(a):
 def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, T_end=0.01,
                 integrator="rk4", n_steps=200, rtol=0.0, atol=0.0, h0=0.0, h_min=0.0,
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
-                stream=None, max_batch=1, tile_rows=0):
+                stream=None, max_batch=1, tile_rows=0, flow="temperature", g_end=0.0):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
     cfg.geometry = GEOM_IDENTITY if geometry == "identity" else GEOM_ANGULAR
@@ -133,6 +139,8 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
     cfg.stream = stream
     cfg.max_batch = int(max_batch)
     cfg.tile_rows = int(tile_rows)
+    cfg.flow = FLOWS[flow] if isinstance(flow, str) else int(flow)
+    cfg.g_end = float(g_end)
     cfg._keep = keep
     return cfg
 
@@ -214,8 +222,31 @@ class Flow:
                                   c_void_p(out.data_ptr())))
         return out
 
+    def rhs_g(self, T, g, V, out=None):
+        """Interaction flow: dV/dg at temperatures T[batch] and scales g[batch]."""
+        b = self._state(V)
+        T = np.ascontiguousarray(np.atleast_1d(T), np.float64)
+        g = np.ascontiguousarray(np.atleast_1d(g), np.float64)
+        if T.shape[0] != b or g.shape[0] != b:
+            raise ValueError("one temperature and one g per state")
+        if out is None:
+            out = self.torch.empty_like(V)
+        _check(load().fm_flow_rhs_g(self.h, b, _pd(T), _pd(g), c_void_p(V.data_ptr()),
+                                    c_void_p(out.data_ptr())))
+        return out
+
+    def tstar(self, U, T_lo, T_hi, rtol=1e-4):
+        """Interaction flow: T*(U) per coupling by bisection in ln T; returns (T*, status)."""
+        U = np.ascontiguousarray(np.atleast_1d(U), np.float64)
+        out = np.zeros(U.shape[0], np.float64)
+        st = np.zeros(U.shape[0], np.int32)
+        _check(load().fm_flow_tstar(self.h, U.shape[0], _pd(U), float(T_lo), float(T_hi),
+                                    float(rtol), _pd(out), _pi(st)))
+        return out, st
+
     def step(self, lnT, h, V):
-        """One integrator step in place on V; returns (lnT, h, accepted) arrays."""
+        """One integrator step in place on V; returns (lnT, h, accepted) arrays (for the
+        interaction flow: g, its step, accepted)."""
         b = self._state(V)
         lnT = np.ascontiguousarray(np.atleast_1d(lnT), np.float64).copy()
         hh = np.ascontiguousarray(np.atleast_1d(h), np.float64).copy()

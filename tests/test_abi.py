@@ -76,6 +76,9 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=17, L=4, geometry="identity"), "identity"),
     (dict(N=16, L=32, channels=9), "channel"),
     (dict(N=16, L=32, tile_rows=-1), "tile_rows"),
+    (dict(N=16, L=32, flow=2), "bad flow"),
+    (dict(N=16, L=32, flow="interaction", T0=0.0), "T0 > 0"),
+    (dict(N=16, L=32, flow="interaction", T0=0.2, g_end=-1.0), "g_end"),
 ])
 def test_invalid_configs_rejected(kw, msg):
     cfg = fm.make_config(**kw)
@@ -92,3 +95,14 @@ def test_workspace_scales_with_batch():
     a = fm.workspace_bytes(fm.make_config(48, 128, precision="fp32", max_batch=1))
     b = fm.workspace_bytes(fm.make_config(48, 128, precision="fp32", max_batch=4))
     assert 3.5 * a < b < 4.5 * a
+
+
+def test_interaction_flow_config_and_workspace():
+    """The interaction flow ignores T_end and bins one temperature per flow (one bin set),
+    the temperature flow's Dormand-Prince steps five stage nodes."""
+    g = fm.make_config(48, 128, precision="fp32", flow="interaction", T0=0.1, T_end=0.0,
+                       integrator="rk45")
+    t = fm.make_config(48, 128, precision="fp32", integrator="rk45")
+    nRp, nRd = fm.representative_counts(t)
+    bin_set = (nRp + 2 * nRd) * 48 * 48 * 4
+    assert fm.workspace_bytes(t) - fm.workspace_bytes(g) >= 4 * bin_set
