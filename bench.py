@@ -116,6 +116,46 @@ def batched_sweep(fm, inputs, torch, dev):
     return out
 
 
+def interaction_flow(fm, inputs, torch, dev):
+    """The paper's own interaction flow at N=48, L=128 (no Z): the crossover curve U*(T) at
+    16 temperatures log-spaced in [0.03, 0.3] from one batched launch of flows with bare
+    U = 8 (U* = g*^2 U, so one flow per temperature gives U*(T)), in single and double
+    precision, and T*(U) for U = 2, 3, 4 by bisection in ln T to 1e-4."""
+    import numpy as np
+    N, L, Ub = 48, 128, 8.0
+    T = np.geomspace(0.03, 0.3, 16)
+    out, ustar = {}, {}
+    for prec in ("fp32", "fp64"):
+        f = fm.Flow(N=N, L=L, U=Ub, T0=0.1, integrator="rk45", precision=prec,
+                    flow="interaction", max_batch=len(T), device=dev)
+        if prec == "fp32":
+            f.run_batch([Ub] * len(T), T)   # first call picks the tile shape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = f.run_batch([Ub] * len(T), T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ustar[prec] = [r["U_star"] for r in res]
+        out["seconds_" + prec] = dt
+        out["flows_per_hour_" + prec] = len(T) / dt * 3600.0
+        out["rhs_" + prec] = int(sum(r["n_rhs"] for r in res))
+        out["updates_per_s_" + prec] = out["rhs_" + prec] * 3.0 * N ** 3 * L ** 2 / dt
+        if prec == "fp32":
+            t0 = time.perf_counter()
+            ts, st = f.tstar([2.0, 3.0, 4.0], 0.005, 1.0, rtol=1e-4)
+            torch.cuda.synchronize()
+            out["tstar_seconds_fp32"] = time.perf_counter() - t0
+            out["T_star_fp32"] = {str(u): (float(t) if s == 0 else None)
+                                  for u, t, s in zip((2.0, 3.0, 4.0), ts, st)}
+        f.close()
+    out["T"] = [float(t) for t in T]
+    out["U_star_fp64"] = [float(u) for u in ustar["fp64"]]
+    d = [abs(a / b - 1.0) for a, b in zip(ustar["fp32"], ustar["fp64"])
+         if math.isfinite(a) and math.isfinite(b)]
+    out["U_star_max_rel_diff"] = max(d) if d else None
+    return out
+
+
 def large_batch(fm, inputs, torch, dev):
     """16 flows, U = 1 + 3i/15, N=128, L=512, synthetic Z per flow, T 1 -> 0.01: flows/hour for
     the bf16, split-bf16 and fp32 right-hand sides against the plain FP64 path, T_c agreement,
@@ -168,6 +208,7 @@ def main():
                     help="skip the batched U x T0 sweep (64 flows) in the extra section")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large batch (16 flows, N=128, L=512) in the extra section")
+    ap.add_argument("--no-gflow", action="store_true", help="skip the interaction-flow runs")
     ap.add_argument("--cpu-rhs", type=int, default=6, help="oracle RHS evaluations timed")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB three times "
@@ -286,6 +327,8 @@ def main():
 
     if not args.no_sweep:
         extra["sweep_64_flows"] = batched_sweep(fm, inputs, torch, dev)
+    if not args.no_gflow:
+        extra["interaction_flow"] = interaction_flow(fm, inputs, torch, dev)
     if not args.no_large:
         extra["large_16_flows"] = large_batch(fm, inputs, torch, dev)
 

@@ -106,7 +106,7 @@ typedef struct {
     double h0, h_min;         /* first step and smallest |step| in the flow parameter; 0
                                  selects span/200 and 1e-8 |span|, span = ln(T_end/T0) or
                                  g_end (h0 < 0 for the temperature flow, > 0 in g) */
-    double v_max;             /* stop when max|V| > v_max (0 selects 20) */
+    double v_max;             /* temperature flow: stop when max|V| > v_max (0 selects 20) */
     unsigned channels;        /* FM_CH_* mask (0 selects FM_CH_ALL) */
     int precision;            /* FM_FP64 | FM_FP32 | FM_FP32_BF16MFMA | FM_FP64_DIRECT |
                                  FM_FP32_BF16X3 */
@@ -123,6 +123,9 @@ typedef struct {
                                  first call (kept per shape for the process) */
     int flow;                 /* FM_FLOW_TEMPERATURE (0) | FM_FLOW_INTERACTION */
     double g_end;             /* interaction flow: last g (0 selects 1) */
+    double v_rel;             /* interaction flow: stop when max|V| > v_rel |U|, the paper's
+                                 criterion relative to the bare coupling (Sec. 3.2); with it
+                                 U* = g*^2 U depends on T alone without Z (0 selects 100) */
 } fm_config;
 
 typedef struct {

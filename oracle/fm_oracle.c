@@ -70,6 +70,7 @@ typedef struct {
     const double *z_tab; /* [n_z][N] */
     int gflow;          /* 0: temperature flow, s = ln T; 1: interaction flow, s = g */
     double g_end;       /* interaction flow: from g = 0 to g_end */
+    double v_rel;       /* interaction flow: stop when max |V| exceeds v_rel |U| (0: 100) */
 } orc_flowcfg;
 
 typedef struct {
@@ -683,21 +684,24 @@ static double step_factor(double err)
 }
 
 /* Stop rule (Sec. 3.2: the flow is followed until the coupling grows beyond a threshold):
- * the largest |V| above v_max (or a non-finite value) ends the flow.  The crossing
+ * the largest |V| above the threshold vth (or a non-finite value) ends the flow.  The
+ * temperature flow uses an absolute threshold v_max; the interaction flow the paper's own
+ * criterion, relative to the bare coupling, vth = v_rel |U|: since g^2 V_g depends on g^2 U
+ * only (without Z), the crossing U* = g*^2 U is then a function of T alone.  The crossing
  * max|V| = v_max is found by interpolating 1/max|V| linearly across the last accepted step,
  * in ln T for the temperature flow and in g^2 for the interaction flow: near an instability
  * the one-loop flow grows like a simple pole in that variable (for one patch
  * 1/v = 1/U - [c(T) - c(T0)], resp. 1/v = 1/U - g^2 c, exactly), so 1/max|V| is nearly
  * linear and the crossing does not depend on where the step boundaries fall. */
-static int stop_test(const orc_flowcfg *f, double s_prev, double m_prev, double s_new,
-                     double m_new, int finite, double *sc)
+static int stop_test(const orc_flowcfg *f, double vth, double s_prev, double m_prev,
+                     double s_new, double m_new, int finite, double *sc)
 {
     if (!finite) { *sc = s_new; return ORC_NONFINITE; }
-    if (m_new > f->v_max) {
+    if (m_new > vth) {
         double u0 = f->gflow ? s_prev * s_prev : s_prev, u1 = f->gflow ? s_new * s_new : s_new;
         double u = u1;
         if (m_prev > 0.0 && m_new != m_prev)
-            u = u0 + (1.0 / m_prev - 1.0 / f->v_max) * (u1 - u0) / (1.0 / m_prev - 1.0 / m_new);
+            u = u0 + (1.0 / m_prev - 1.0 / vth) * (u1 - u0) / (1.0 / m_prev - 1.0 / m_new);
         *sc = f->gflow ? sqrt(u) : u;
         return ORC_DIVERGED;
     }
@@ -732,11 +736,12 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
 
     double s0 = f->gflow ? 0.0 : log(f->T0), s_end = f->gflow ? f->g_end : log(f->T_end);
     double s = s0, dir = s_end > s0 ? 1.0 : -1.0;   /* direction of the flow parameter */
+    double vth = f->gflow ? (f->v_rel > 0.0 ? f->v_rel : 100.0) * fabs(U) : f->v_max;
     int finite, status = ORC_RUNNING, nacc = 0, nrej = 0, ntr = 0;
     double mV = max_abs(V, n, &finite), lnTc = NAN;
     if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
     if (!finite) { status = ORC_NONFINITE; lnTc = s; }
-    else if (mV > f->v_max) { status = ORC_DIVERGED; lnTc = s; }
+    else if (mV > vth) { status = ORC_DIVERGED; lnTc = s; }
 
     if (status == ORC_RUNNING && f->integrator == 0) {
         double h = (s_end - s0) / f->n_steps;
@@ -754,7 +759,7 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
             double s_new = (st + 1 == f->n_steps) ? s_end : s0 + (st + 1) * h;
             double m_new = max_abs(V, n, &finite);
             ++nacc;
-            status = stop_test(f, s, mV, s_new, m_new, finite, &lnTc);
+            status = stop_test(f, vth, s, mV, s_new, m_new, finite, &lnTc);
             s = s_new; mV = m_new;
             if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
         }
@@ -775,7 +780,7 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
                 memcpy(V, Vn, sizeof(double) * n);
                 memcpy(k[0], k[6], sizeof(double) * n);
                 ++nacc;
-                status = stop_test(f, s, mV, s_new, m_new, finite, &lnTc);
+                status = stop_test(f, vth, s, mV, s_new, m_new, finite, &lnTc);
                 s = s_new; mV = m_new;
                 if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
                 h = ht * step_factor(err);

@@ -129,6 +129,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     // bf16 operands carry about 3 significant digits, so their default is 1e-4
     if (c.rtol <= 0.0) c.rtol = c.precision == FM_FP32_BF16MFMA ? 1e-4 : 1e-6;
     if (c.v_max <= 0.0) c.v_max = 20.0;
+    if (c.v_rel <= 0.0) c.v_rel = 100.0;
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
     if (c.tile_rows < 0) { why = "tile_rows must be >= 0"; return FM_EINVAL; }
@@ -385,7 +386,7 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
 }
 
 // One integrator step of every running flow (no host interaction).  V is the state array.
-void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed, double v_max) {
+void step_launch(fm_flow* h, int nf, double* V, int fixed_steps) {
     const bool rk45 = h->cfg.integrator == FM_RK45_DOPRI;
     StepPlan plan = step_plan(rk45);
     if (h->g.gflow) {          // bins of the flow's fixed T, computed when the flow starts
@@ -398,7 +399,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed,
             rhs_launch(h, nf, s, plan.set[s]);
         }
         timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->N3, V); });
-        timed(h, T_FINISH, [&] { launch_finish(h->stream, h->b, nf, 0, v_max, fixed_steps, h_fixed); });
+        timed(h, T_FINISH, [&] { launch_finish(h->stream, h->b, nf, 0, fixed_steps); });
         return;
     }
     for (int s = 1; s < 7; ++s) {
@@ -409,7 +410,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps, double h_fixed,
     std::memcpy(ew.e, kDPE, sizeof ew.e);
     timed(h, T_UPDATE, [&] { launch_dopri_err(h->stream, h->dbl, h->b, nf, h->N3, V, h->cfg.rtol, ew); });
     timed(h, T_FINISH, [&] {
-        launch_finish(h->stream, h->b, nf, 1, v_max, 0, 0.0);
+        launch_finish(h->stream, h->b, nf, 1, 0);
         launch_commit(h->stream, h->dbl, h->b, nf, h->N3, V);
     });
 }
@@ -713,6 +714,7 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
         s.h = s.ht = gf ? -hstep[f] : hstep[f];
         s.gflow = gf ? 1 : 0;
         s.Tfix = gf ? h->cfg.T0 : 0.0;
+        s.vmax = std::numeric_limits<double>::infinity();   // no stop test in a lone step
         s.lnT_end = -std::numeric_limits<double>::infinity();
         s.hmin = 0.0;
         s.atol = h->cfg.atol > 0.0 ? h->cfg.atol : 1e-9 * std::max(1.0, std::fabs(h->cfg.U));
@@ -722,14 +724,13 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
     untimed(h);
-    const double inf = std::numeric_limits<double>::infinity();
     if (rk45) {
         stage_launch(h, batch, dp_stage(0), kOneNode, 0, V_dev);
         rhs_launch(h, batch, 0, 0);
     } else if (gf) {        // the interaction flow's bins, at its fixed temperature
         stage_launch(h, batch, rk4_stage(0), kOneNode, 0, V_dev);
     }
-    step_launch(h, batch, V_dev, 0, 0.0, inf);
+    step_launch(h, batch, V_dev, 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->hfs.data(), h->b.fs, sizeof(FlowState) * batch, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -803,7 +804,10 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         s.atol = c.atol > 0.0 ? c.atol : 1e-9 * std::max(1.0, std::fabs(U[f]));
         s.m = std::fabs(U[f]);
         s.status = FM_FLOW_RUNNING;
-        if (s.m > c.v_max) { s.status = FM_FLOW_DIVERGED; s.lnTc = s.lnT; }
+        // the paper's threshold is relative to the bare coupling (Sec. 3.2); the temperature
+        // flow uses an absolute one
+        s.vmax = gf ? c.v_rel * std::fabs(U[f]) : c.v_max;
+        if (s.m > s.vmax) { s.status = FM_FLOW_DIVERGED; s.lnTc = s.lnT; }
         s.n_rhs = (rk45 && s.status == FM_FLOW_RUNNING) ? 1 : 0;
         h->hfs[f] = s;
     }
@@ -845,7 +849,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            step_launch(h, n, h->b.V, fixed, 0.0, c.v_max);
+            step_launch(h, n, h->b.V, fixed);
             e = hipStreamEndCapture(cap, &graph);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&h->step_exec, graph, nullptr, nullptr, 0);
@@ -865,7 +869,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
             if (use_graph) {
                 HIPCHK(hipGraphLaunch(h->step_exec, cap));
             } else {
-                step_launch(h, n, h->b.V, fixed, 0.0, c.v_max);
+                step_launch(h, n, h->b.V, fixed);
             }
         }
         done_steps += k;

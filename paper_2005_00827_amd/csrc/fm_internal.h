@@ -64,6 +64,7 @@ struct FlowState {
     double s0;       // ln T0 (fixed-step grid origin)
     double atol;     // absolute error tolerance of this flow
     double Tfix;     // interaction flow: the flow's temperature
+    double vmax;     // stop threshold on max|V| (v_max, or v_rel |U| in the interaction flow)
     int status;      // FM_FLOW_*
     int accepted;    // outcome of the last attempt
     int n_acc, n_rej, n_rhs;
@@ -180,8 +181,8 @@ void launch_fill_u(hipStream_t s, const Buffers& b, int nf, size_t N3, const dou
 void launch_rk4_update(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
 void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3,
                       const double* V, double rtol, const ErrWeights& ew);
-void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, double v_max,
-                   int fixed_steps, double h_fixed);
+// Accept/reject and the stop test against each flow's own threshold (FlowState::vmax).
+void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, int fixed_steps);
 void launch_commit(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
 void launch_copy(hipStream_t s, const double* from, double* to, size_t n);
 

@@ -1218,7 +1218,7 @@ __device__ inline double step_factor(double err) {
 
 // Accept/reject, stop rule and the next attempted step, one workgroup per flow.
 __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double* part, int nblk,
-                                                     int rk45, double v_max, int fixed_steps) {
+                                                     int rk45, int fixed_steps) {
     const int f = blockIdx.x;
     const bool run = fs[f].status == FM_FLOW_RUNNING;
     double e = 0.0, mv = 0.0;
@@ -1232,7 +1232,7 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
     if (threadIdx.x != 0) return;
     FlowState st = fs[f];
     if (!run) { st.accepted = 0; fs[f] = st; return; }
-    const double s = st.lnT, ht = st.ht;
+    const double s = st.lnT, ht = st.ht, v_max = st.vmax;
     const bool last = ht != st.h;
     if (!rk45) {
         st.err = 0.0;
@@ -1539,11 +1539,9 @@ void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t 
                            N3, b.bstride);
 }
 
-void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, double v_max,
-                   int fixed_steps, double h_fixed) {
-    (void)h_fixed;
+void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, int fixed_steps) {
     hipLaunchKernelGGL(k_finish, dim3(nf), dim3(kThreads), 0, s, b.fs, b.part, b.nblk, rk45,
-                       v_max, fixed_steps);
+                       fixed_steps);
 }
 
 void launch_commit(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V) {

@@ -1,6 +1,7 @@
 """GPU parity of the interaction flow (Sec. 2.2; App. A, Steps 1 and 2) through the C ABI
 against the double-precision CPU oracle: dV/dg, single steps in g, batched ragged flows
-with the crossover coupling U* = g*^2 U, Z tables in g, and the T*(U) search.
+with the crossover coupling U* = g*^2 U (stop when max|V| > v_rel |U|, v_rel = 100), Z
+tables in g, and the T*(U) search.
 
 Tolerances (relative to max|reference|) as for the temperature flow: 1e-10 double
 precision, 1e-4 single precision and split bf16, 1e-2 bf16; g* and U* to 1e-8 (double)
@@ -245,7 +246,7 @@ def test_flow_kind_errors_and_stop_at_start(torch_dev):
     torch, dev = torch_dev
     N, L = 8, 16
     V = torch.from_numpy(inputs.noisy_state(N, 2.0).reshape(1, N, N, N)).to(dev)
-    fg = fm.Flow(N=N, L=L, T0=0.2, precision="fp64", flow="interaction", device=dev)
+    fg = fm.Flow(N=N, L=L, T0=0.2, precision="fp64", flow="interaction", v_rel=0.5, device=dev)
     ft = fm.Flow(N=N, L=L, precision="fp64", device=dev)
     try:
         with pytest.raises(fm.FmError):
@@ -256,8 +257,26 @@ def test_flow_kind_errors_and_stop_at_start(torch_dev):
             ft.tstar([2.0], 0.05, 1.0)
         with pytest.raises(fm.FmError):
             fg.run_batch([2.0], [0.0])
-        r = fg.run_batch([25.0], [0.2])[0]
+        r = fg.run_batch([25.0], [0.2])[0]          # max|V| = U > 0.5 U at g = 0
         assert r["status"] == fm.DIVERGED and r["g_c"] == 0.0 and r["U_star"] == 0.0
     finally:
         fg.close()
         ft.close()
+
+
+def test_ustar_is_a_function_of_t_and_tstar_inverts_it(torch_dev):
+    """With the threshold relative to the bare coupling, flows of bare U = 6 and 9 at one T
+    cross at the same U* = g*^2 U, and T*(U*(T)) returns T."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L, T = 16, 32, 0.1
+    f = fm.Flow(N=N, L=L, U=6.0, T0=T, precision="fp64", integrator="rk45", rtol=1e-9,
+                flow="interaction", max_batch=2, device=dev)
+    try:
+        r = f.run_batch([6.0, 9.0], [T, T])
+        us = [x["U_star"] for x in r]
+        ts, st = f.tstar([us[0]], 0.02, 1.0, rtol=1e-6)
+    finally:
+        f.close()
+    assert abs(us[0] / us[1] - 1) <= 1e-6
+    assert st[0] == 0 and abs(ts[0] / T - 1) <= 1e-4

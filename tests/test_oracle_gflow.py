@@ -12,6 +12,8 @@ the internal line pair carries g Z_a Z_b (Z_a + Z_b) chi (2 g chi without Z).
   U^2 [chi_ph(k3 - k2) - chi_pp(k1 + k2)] (the right-hand side at the start of the flow is
   second-order perturbation theory up to a factor, Sec. 3.1), residual ~ U^3.  Fixes the
   factor 2 and the signs.
+* stop rule: relative to the bare coupling, max|V| > v_rel |U| (Sec. 3.2), so that the
+  crossover coupling U* = g*^2 U is the same for every bare U above it (without Z).
 * Z: Z = 1 tables bitwise equal no feedback; constant Z = z gives
   V_z(g; U) = V_1(g; z^3 U) / z^3; a g- and patch-dependent table gives the O(U^2) term
   int_0^1 g Z_a Z_b (Z_a + Z_b) chi dg, by quadrature of oracle-independent bubble sums.
@@ -56,7 +58,7 @@ def loop_sum(L, m, T, pp):
 
 
 def gcfg(T, U, **kw):
-    kw.setdefault("v_max", 1e300)
+    kw.setdefault("v_rel", 1e300)
     return O.flowcfg(T0=T, U=U, gflow=True, **kw)
 
 
@@ -99,7 +101,7 @@ def test_n1_attractive_crossing(integrator, n):
     # |v| = v_max with v < 0: 1/U - g^2 c = -1/v_max
     g2 = (1.0 / U + 1.0 / vmax) / c
     assert 0.05 < g2 < 0.9, (c, g2)
-    cfg = gcfg(T, U, integrator=integrator, n_steps=n, v_max=vmax, rtol=1e-10)
+    cfg = gcfg(T, U, integrator=integrator, n_steps=n, v_rel=vmax / abs(U), rtol=1e-10)
     V, res, tr = O.flow(O.model(1, L1), cfg, U)
     assert res["status"] == O.DIVERGED
     assert res["g_c"] == pytest.approx(math.sqrt(g2), rel=1e-7)
@@ -110,8 +112,25 @@ def test_n1_attractive_crossing(integrator, n):
 
 
 def test_stop_at_start():
-    _, res, _ = O.flow(O.model(1, L1), gcfg(0.2, 3.0, v_max=1.0), 3.0)
+    _, res, _ = O.flow(O.model(1, L1), gcfg(0.2, 3.0, v_rel=0.5), 3.0)
     assert res["status"] == O.DIVERGED and res["g_c"] == 0.0 and res["U_star"] == 0.0
+
+
+def test_relative_threshold_makes_ustar_independent_of_bare_u():
+    """With max|V| > v_rel |U|, the flows of two bare couplings above U*(T) cross at the same
+    g*^2 U; an absolute threshold would not."""
+    N, L, T = 8, 16, 0.1
+    us = []
+    for U in (6.0, 9.0):
+        _, r, _ = O.flow(O.model(N, L), gcfg(T, U, integrator=1, rtol=1e-10, v_rel=100.0), U)
+        assert r["status"] == O.DIVERGED and 0.0 < r["g_c"] < 1.0
+        us.append(r["U_star"])
+    assert us[0] == pytest.approx(us[1], rel=1e-7)
+    ab = []
+    for U in (6.0, 9.0):
+        _, r, _ = O.flow(O.model(N, L), gcfg(T, U, integrator=1, rtol=1e-10, v_rel=20.0 / U), U)
+        ab.append(r["U_star"])
+    assert abs(ab[0] / ab[1] - 1.0) > 1e-3
 
 
 # --------------------------------------------------------------------------------------
@@ -228,7 +247,7 @@ def test_tabulated_z_second_order():
 def test_step_matches_flow():
     """One oracle step in g from 0 reproduces the first accepted step of the flow."""
     N, L, T, U = 4, 8, 0.2, 2.0
-    cfg = gcfg(T, U, integrator=1, v_max=20.0)
+    cfg = gcfg(T, U, integrator=1, v_rel=10.0)
     V, res, tr = O.flow(O.model(N, L), cfg, U)
     g1 = tr[1][0]
     gn, hn, Vs, acc, err = O.step(O.model(N, L), cfg, 0.0, g1, np.full((N, N, N), U))
