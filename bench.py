@@ -159,10 +159,16 @@ def interaction_flow(fm, inputs, torch, dev):
 def large_batch(fm, inputs, torch, dev):
     """16 flows, U = 1 + 3i/15, N=128, L=512, synthetic Z per flow, T 1 -> 0.01: flows/hour for
     the bf16, split-bf16 and fp32 right-hand sides against the plain FP64 path, T_c agreement,
-    and the per-kernel timings (HIP events, eager replay) of the bf16 run."""
+    the per-kernel timings (HIP events, eager replay) of the bf16 run, and for bf16 and fp32
+    the roofline of each kernel group with all 16 flows running (10 back-to-back launches on
+    the final state, HIP events on the library stream)."""
     import numpy as np
     w = inputs.workload("C5")
     N, L, U, T0 = w["N"], w["L"], w["U"], w["T0"]
+    cfg = fm.make_config(N, L)
+    _, _, _, nP, nD, _ = fm.geometry_query(cfg)
+    nRp, nRd = fm.representative_counts(cfg)
+    nf = len(U)
     tabs = [inputs.synthetic_z_table(N, u, 1.0, w["T_end"]) for u in U]
     zl = np.stack([t[0] for t in tabs])
     zt = np.stack([t[1] for t in tabs])
@@ -181,6 +187,19 @@ def large_batch(fm, inputs, torch, dev):
             out["kernels_bf16"] = {k: {"launches": n, "avg_us": ms / n * 1e3}
                                    for k, (ms, n) in f.timings().items()}
             f.set_timing(False)
+        if prec in ("bf16", "fp32"):
+            roof = {}
+            for name, gid in (("stage_bins", 0), ("y", 1), ("contract", 2), ("stage", 3)):
+                us = f.kernel_time(gid, nf, 10) * 1e3
+                wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd)
+                r = {"avg_us": us}
+                if wk["bound"] == "hbm":
+                    r.update(bound="hbm", achieved_GBs=nf * wk["bytes"] / (us * 1e-6) / 1e9)
+                    r["frac"] = r["achieved_GBs"] / PEAK["hbm_GBs"]
+                else:
+                    r.update(bound="alu", pair_evals_per_s=nf * wk["flops"] / 6.0 / 2.0 / (us * 1e-6))
+                roof[name] = r
+            out["roofline_16_flows_" + prec] = roof
         f.close()
         rhs = int(sum(r["n_rhs"] for r in res))
         tc[prec] = [r["T_c"] for r in res]

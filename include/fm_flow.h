@@ -126,6 +126,10 @@ typedef struct {
     double v_rel;             /* interaction flow: stop when max|V| > v_rel |U|, the paper's
                                  criterion relative to the bare coupling (Sec. 3.2); with it
                                  U* = g*^2 U depends on T alone without Z (0 selects 100) */
+    int y_kernel;             /* single-precision phase 2a on matrix cores: 1 gathers each
+                                 transfer's permuted bins, 2 stages the operand permuted once
+                                 per point-group operation class; 0 = chosen by timing with
+                                 tile_rows on the first call */
 } fm_config;
 
 typedef struct {

@@ -133,6 +133,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
     if (c.tile_rows < 0) { why = "tile_rows must be >= 0"; return FM_EINVAL; }
+    if (c.y_kernel < 0 || c.y_kernel > 2) { why = "y_kernel must be 0, 1 or 2"; return FM_EINVAL; }
     return FM_OK;
 }
 
@@ -150,8 +151,9 @@ struct fm_flow {
     size_t N3 = 0;
     std::vector<double> zlnT, ztab;    // configured table (host copy)
     std::vector<FlowState> hfs;
-    // phase-2a row tiles per wavefront (cfg.tile_rows, or tuned for tuned_nf flows)
-    int tpw = 0, tuned_nf = -1;
+    // phase-2a kernel variant and row tiles per wavefront (cfg.y_kernel, cfg.tile_rows, or
+    // tuned for tuned_nf flows)
+    int tpw = 0, yvar = 1, tuned_nf = -1;
     // graphs of one integrator step, keyed by the number of flows captured
     hipGraphExec_t step_exec = nullptr;
     int step_nf = -1;
@@ -199,6 +201,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.qrep_ph = L.take<int>(nD);
     b.qg_ph = L.take<int>(nD);
     b.pinv = L.take<int>(8 * static_cast<size_t>(N));
+    b.perm = L.take<int>(8 * static_cast<size_t>(N));
     b.pI = L.take<int>(N);
     b.pp_off = L.take<int>(nP + 1);
     b.pp_pairs = L.take<int>(NN);
@@ -224,8 +227,11 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         const size_t S = c.flow == FM_FLOW_INTERACTION
                              ? 1 : static_cast<size_t>(step_plan(c.integrator == FM_RK45_DOPRI).bp.n);
         b.nbset = static_cast<int>(S);
-        b.bins = L.take<char>(S * B * (nRp + nRd) * NN * rs);
-        b.binsT = L.take<char>(S * B * nRd * NN * rs);
+        // padding: phase-2a row reads run up to kBinPad values past a row's end
+        b.bins = L.take<char>((S * B * (nRp + nRd) * NN + kBinPad) * rs);
+        b.binsT = L.take<char>((S * B * nRd * NN + kBinPad) * rs);
+        b.bins_bytes = (S * B * (nRp + nRd) * NN + kBinPad) * rs;
+        b.binsT_bytes = (S * B * nRd * NN + kBinPad) * rs;
         b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
         b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
         b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
@@ -233,6 +239,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         b.wtab = nullptr;
     } else {
         b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.bins_bytes = b.binsT_bytes = 0;
         b.nbset = 0;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
     }
@@ -317,7 +324,7 @@ void rhs_launch(fm_flow* h, int nf, int slot, int set) {
     }
     const int mma = mma_mode(h->cfg.precision);
     const Buffers bs = with_bin_set(h->b, h->g, h->dbl, set);
-    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, bs, nf, ch, mma, h->tpw); });
+    timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, bs, nf, ch, mma, h->tpw, h->yvar); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
 
@@ -329,56 +336,70 @@ void stage_launch(fm_flow* h, int nf, const StageCoef& sc, const BinPlan& bp, in
     });
 }
 
-// Phase-2a tile choice: cfg.tile_rows when set, else the fastest of 1, 2, 4, ... row tiles
-// per wavefront up to all of a group's tiles in one block (few blocks, each staging its B
-// chunk once, against many blocks with more parallelism), timed with events on the operands
-// of a stage at the flows' current state.
+// Phase-2a choice: the kernel variant (cfg.y_kernel, or both) and row tiles per wavefront
+// (cfg.tile_rows, or 1, 2, 4, ... up to all of a group's or a class's tiles in one block:
+// few blocks, each staging its B chunk once, against many blocks with more parallelism);
+// the fastest candidate, timed with events on the operands of a stage at the flows' current
+// state.  The per-row kernel gathers permuted bins; the operation-class kernel reads plain
+// bin rows and stages a permuted operand once per class, which pays where the gathers
+// dominate (large N, bf16) and costs where blocks are few.
 // Every later stage recomputes these products, so the timing runs change no result.
-// Choices are kept for the process, per shape and number of flows.
-using TuneKey = std::tuple<int, int, int, int, int, double, double, double>;
+// Choices are kept for the process, per shape, settings and number of flows.
+using TuneKey = std::tuple<int, int, int, int, int, double, double, double, int, int>;
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, std::pair<int, int>> g_tune;
 
 int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     const fm_config& c = h->cfg;
     const int mma = mma_mode(c.precision);
     if (h->dbl || h->direct || mma == 0 || c.N > 128) return FM_OK;
-    if (c.tile_rows > 0) { h->tpw = c.tile_rows; return FM_OK; }
+    std::vector<std::pair<int, int>> cand;    // (variant, tiles per wavefront)
+    for (int var = 1; var <= 2; ++var) {
+        if (c.y_kernel != 0 && var != c.y_kernel) continue;
+        if (c.tile_rows > 0) { cand.emplace_back(var, c.tile_rows); continue; }
+        const int maxt = var == 2 ? y_max_tpw(h->g) : y_rows_max_tpw(h->g);
+        for (int t = 1; t < maxt; t *= 2) cand.emplace_back(var, t);
+        cand.emplace_back(var, maxt);
+    }
+    if (cand.size() == 1) { h->yvar = cand[0].first; h->tpw = cand[0].second; return FM_OK; }
     if (h->tuned_nf == nf) return FM_OK;
-    const TuneKey key{c.N, c.L, c.precision, nf, c.geometry, c.t, c.tp, c.mu};
+    const TuneKey key{c.N, c.L, c.precision, nf, c.geometry, c.t, c.tp, c.mu, c.y_kernel,
+                      c.tile_rows};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) { h->tpw = it->second; h->tuned_nf = nf; return FM_OK; }
+        if (it != g_tune.end()) {
+            h->yvar = it->second.first;
+            h->tpw = it->second.second;
+            h->tuned_nf = nf;
+            return FM_OK;
+        }
     }
     StageCoef sc{};
     launch_stage(h->stream, h->dbl, h->g, h->z, h->b, nf, sc, kOneNode, 0, Vbase);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    int best = 1;
+    std::pair<int, int> best = cand[0];
     float best_ms = std::numeric_limits<float>::infinity();
-    const int ntiles = (std::max(h->g.nP, h->g.nD) + 15) / 16;
-    const int maxt = (ntiles + 3) / 4;
-    std::vector<int> cand;
-    for (int t = 1; t < maxt; t *= 2) cand.push_back(t);
-    cand.push_back(maxt);
-    for (int tpw : cand) {
-        launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, tpw);
+    for (const auto& cv : cand) {
+        launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, cv.second, cv.first);
         (void)hipEventRecord(e0, h->stream);
-        for (int r = 0; r < 5; ++r) launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, tpw);
+        for (int r = 0; r < 5; ++r)
+            launch_y(h->stream, false, h->g, h->b, nf, c.channels, mma, cv.second, cv.first);
         (void)hipEventRecord(e1, h->stream);
         float ms = 0.f;
         if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
             ms < best_ms) {
             best_ms = ms;
-            best = tpw;
+            best = cv;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipGetLastError());
-    h->tpw = best;
+    h->yvar = best.first;
+    h->tpw = best.second;
     h->tuned_nf = nf;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
@@ -515,6 +536,11 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.qrep_pp = h->b.qrep_pp; g.qg_pp = h->b.qg_pp;
     g.qrep_ph = h->b.qrep_ph; g.qg_ph = h->b.qg_ph;
     g.pinv = h->b.pinv;
+    g.perm = h->b.perm;
+    for (int o = 0; o < 9; ++o) {
+        g.cls[0][o] = hg.cls_pp[o];
+        g.cls[1][o] = hg.cls_ph[o];
+    }
     g.pI = h->b.pI;
     g.inv_ok = hg.inv_ok ? 1 : 0;
     g.gflow = c.flow == FM_FLOW_INTERACTION ? 1 : 0;
@@ -557,6 +583,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.qrep_ph, hg.qrep_ph);
     if (e == hipSuccess) e = upv(h->b.qg_ph, hg.qg_ph);
     if (e == hipSuccess) e = upv(h->b.pinv, hg.pinv);
+    if (e == hipSuccess) e = upv(h->b.perm, hg.perm);
     if (e == hipSuccess) e = upv(h->b.pI, hg.inv_perm);
     if (e == hipSuccess) e = upv(h->b.pp_off, hg.pp_off);
     if (e == hipSuccess) e = upv(h->b.pp_pairs, hg.pp_pairs);
@@ -567,6 +594,10 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.item_q, hg.item_q);
     if (e == hipSuccess) e = upv(h->b.item_p0, hg.item_p0);
     if (e == hipSuccess) e = upv(h->b.item_rec, hg.item_rec);
+    // bins start zeroed (with their padding): phase 2a may read past a row's end, and only
+    // finite values may meet the zero operand there
+    if (e == hipSuccess && h->b.bins) e = hipMemsetAsync(h->b.bins, 0, h->b.bins_bytes, h->stream);
+    if (e == hipSuccess && h->b.binsT) e = hipMemsetAsync(h->b.binsT, 0, h->b.binsT_bytes, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -646,7 +677,7 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
         else if (group == 3)
             launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, kNoBins, 0, h->b.V);
         else if (group == 1)
-            launch_y(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, mma, h->tpw);
+            launch_y(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, mma, h->tpw, h->yvar);
         else if (h->direct)
             launch_direct(h->stream, h->g, h->b, batch, h->cfg.channels, 0);
         else

@@ -36,6 +36,10 @@ struct HostGeometry {
     std::vector<int> rep_pp, rep_ph; // representative transfers (flat index)
     std::vector<int> qrep_pp, qg_pp; // [nP] representative index and operation
     std::vector<int> qrep_ph, qg_ph; // [nD]
+    std::vector<int> perm;           // [8][N] patch permutation of o (pinv is its inverse)
+    // Transfers are ordered by (operation, representative); cls_*[o] .. cls_*[o+1] are the
+    // transfers obtained with operation o.
+    std::vector<int> cls_pp, cls_ph; // [9]
     // Output pairs grouped by transfer (CSR): pp pairs (a,b), crossed (b,c), direct (a,c),
     // each packed as x*N + y.
     std::vector<int> pp_off, pp_pairs, cr_off, cr_pairs, d_off, d_pairs;
@@ -82,6 +86,8 @@ struct DevGeom {
     const int* qrep_ph;    // [nD]
     const int* qg_ph;      // [nD]
     const int* pinv;       // [8][N]
+    const int* perm;       // [8][N], inverse of pinv
+    int cls[2][9];         // transfer classes by operation: particle-particle, particle-hole
     const int* pI;         // [N] patch permutation of k -> -k
     int inv_ok;            // pI is valid (k -> -k maps patches and dispersion onto themselves)
     int inv_rot;           // pI[a] = (a + N/2) mod N
@@ -123,6 +129,9 @@ struct BinPlan {
     double c[6];           // node of each set
 };
 
+// Values of padding after each bin buffer: phase 2a reads a row up to 4 KE <= 128 values.
+constexpr size_t kBinPad = 256;
+
 // Device buffers carved out of the caller's workspace.
 struct Buffers {
     // geometry
@@ -134,12 +143,14 @@ struct Buffers {
     double* Z_stage;                   // [B][N]
     double* zw_stage;                  // [B][2]: line-pair factor Z_a Z_b (al + be (Z_a + Z_b))
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
+    int* perm;
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0; int* item_rec;
     void* bins;                        // [S][B][nRp + nRd][NN] real, representative transfers
     void* binsT;                       // [S][B][nRd][NN] real, particle-hole bins transposed
     int nbset;                         // S: bin sets (stage nodes of one step)
+    size_t bins_bytes, binsT_bytes;    // with kBinPad values of zeroed padding each
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
     void* v0; void* va; void* vc;      // operands [B][N^3] real
     void* k;                           // [7][B][3][N^3] real: per stage, flow and channel
@@ -163,13 +174,20 @@ struct ErrWeights {
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
                   int nf, const StageCoef& sc, const BinPlan& bp, int write_new,
                   const double* Vbase);
+// Largest useful tiles per wavefront of the operation-class kernel: all tiles of the
+// largest class in the 4 waves of one block.
+int y_max_tpw(const DevGeom& g);
 // The buffers with bin set `set` in place of set 0 (phase 2a reads the bins of its stage).
 Buffers with_bin_set(const Buffers& b, const DevGeom& g, bool dbl, int set);
 // mma: 0 VALU, 1 f32 matrix cores, 2 bf16 matrix cores, 3 split-bf16 matrix cores (single
 // precision only, N <= 128);
-// tpw: row tiles per wavefront on matrix cores (1, 2, 4; 0 = by size)
+// tpw: row tiles per wavefront on matrix cores (1, 2, 4; 0 = by size);
+// yvar: matrix-core kernel, 1 per-row gather of permuted bins, 2 operation classes (the
+// permutation applied to the staged operand)
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
-              int mma, int tpw);
+              int mma, int tpw, int yvar);
+// Largest useful tiles per wavefront of the per-row kernel.
+int y_rows_max_tpw(const DevGeom& g);
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,
                      unsigned ch, int slot);
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf);

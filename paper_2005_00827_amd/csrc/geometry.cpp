@@ -12,6 +12,7 @@
 // snapped to the transfer grid 2 pi m / L so that all transfer bookkeeping is integer.
 //
 // Dispersion: Sec. 2.1, Eq. free_dispersion_xi.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -163,6 +164,40 @@ void build_symmetry(HostGeometry& g) {
     };
     reduce(g.q_pp, g.rep_pp, g.qrep_pp, g.qg_pp);
     reduce(g.q_ph, g.rep_ph, g.qrep_ph, g.qg_ph);
+    g.perm.assign(8 * static_cast<size_t>(N), 0);
+    for (int o = 0; o < 8; ++o)
+        for (int a = 0; a < N; ++a)
+            g.perm[o * static_cast<size_t>(N) + a] = ok ? perm[o * static_cast<size_t>(N) + a] : a;
+    // Transfers ordered by (operation, representative): the rows of a phase-2a tile then
+    // share one point-group operation, whose patch permutation the kernel applies to the
+    // operand it stages once instead of to every bin it reads.  The transfer index is only
+    // a label; the maps are renumbered with it.
+    auto order = [](std::vector<int>& q, std::vector<int>& qrep, std::vector<int>& qg,
+                    std::vector<std::vector<int>*> maps, std::vector<int>& cls) {
+        const size_t n = q.size();
+        std::vector<int> idx(n);
+        for (size_t i = 0; i < n; ++i) idx[i] = static_cast<int>(i);
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+            return qg[x] != qg[y] ? qg[x] < qg[y] : qrep[x] < qrep[y];
+        });
+        std::vector<int> pos(n), q2(n), r2(n), g2(n);
+        for (size_t i = 0; i < n; ++i) {
+            pos[idx[i]] = static_cast<int>(i);
+            q2[i] = q[idx[i]];
+            r2[i] = qrep[idx[i]];
+            g2[i] = qg[idx[i]];
+        }
+        q.swap(q2);
+        qrep.swap(r2);
+        qg.swap(g2);
+        for (auto* m : maps)
+            for (int& v : *m) v = pos[v];
+        cls.assign(9, 0);
+        for (size_t i = 0; i < n; ++i) cls[qg[i] + 1]++;
+        for (int o = 0; o < 8; ++o) cls[o + 1] += cls[o];
+    };
+    order(g.q_pp, g.qrep_pp, g.qg_pp, {&g.map_pp}, g.cls_pp);
+    order(g.q_ph, g.qrep_ph, g.qg_ph, {&g.map_cr, &g.map_d}, g.cls_ph);
 }
 
 void csr(const std::vector<int>& map, int nq, std::vector<int>& off, std::vector<int>& pairs) {

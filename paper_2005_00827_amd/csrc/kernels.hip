@@ -632,12 +632,11 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
 
 // Phase 2a on matrix cores (single-precision storage, N <= 128).  Same products as k_y.
 // One wave computes, for one group g, a column chunk of NT 16-wide tiles and a run of
-// 16-row tiles of transfers.  Both operands go straight from memory into the MFMA register
-// layout (no LDS staging):
-//   B[k][n] = Vsrc[g][k][n] is loaded once per wave (KE values per lane and tile; for
-//     the direct channel two such operands, va and vc, share one A);
-//   A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k) is gathered per row tile, the patch
-//     permutations and Z read from LDS.
+// 16-row tiles of transfers of one operation class:
+//   B'[k'][n] = Z_g Z_k (al + be (Z_g + Z_k)) Vsrc[g][k][n], k = perm_o k', is staged in
+//     LDS once per block (for the direct channel two such operands, va and vc, share one A);
+//   A[q][k'] = Brep_r(pinv_o g, k') is read straight from a representative's bin row into
+//     the MFMA register layout.
 // kM = 0: v_mfma_f32_16x16x4_f32, lane holds k = 4 e + lane / 16 (e < KE);
 // kM = 1: v_mfma_f32_16x16x32_bf16, k = 32 (e / 8) + 8 (lane / 16) + e % 8, operands rounded
 //         to bf16;
@@ -723,7 +722,7 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
 // A operand of one row tile: lane row q = 16 tile + lane % 16 (rep r, operation o), k-values
 // of the lane: A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k), zero for k >= N.
 template <int kM, int KE>
-__device__ inline void gather_a(float (&a)[KE], const float* Bf, int NN, int N, int grp,
+__device__ inline void gather_rows(float (&a)[KE], const float* Bf, int NN, int N, int grp,
                                 int rep, int op, const int* pis, const float* zs, float zg,
                                 float al, float be, int lane) {
     const int* pi = pis + op * N;
@@ -750,7 +749,7 @@ __device__ inline void tile_rep(const int* qrep, const int* qg, int M, int tile,
 // Row tiles [t_begin, t_end) of one wavefront: the A gather of tile t+1 and the table
 // entries of tile t+2 are in flight while tile t runs on the matrix cores and is stored.
 template <int kM, int KE, int NT, bool kTwo>
-__device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, int NN, int N,
+__device__ inline void y_tiles_rows(const float* Bf, const int* qrep, const int* qg, int NN, int N,
                                int M, int grp, int n0, int t_begin, int t_end, const int* pis,
                                const float* zs, float al, float be, const void* Bs0,
                                const void* Bs1, float* Y0, float* Y1, int lane, int r0, int o0,
@@ -758,13 +757,13 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
     const int col = lane & 15;
     const float zg = zs[grp];
     float a0[KE], a1[KE];
-    gather_a<kM, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, al, be, lane);
+    gather_rows<kM, KE>(a0, Bf, NN, N, grp, r0, o0, pis, zs, zg, al, be, lane);
     for (int tile = t_begin; tile < t_end; ++tile) {
         // B fragments are re-read from LDS every tile instead of being kept in registers
         asm volatile("" ::: "memory");
         int r2, o2;
         tile_rep(qrep, qg, M, tile + 2, col, r2, o2);
-        if (tile + 1 < t_end) gather_a<kM, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, al, be, lane);
+        if (tile + 1 < t_end) gather_rows<kM, KE>(a1, Bf, NN, N, grp, r1, o1, pis, zs, zg, al, be, lane);
         fm_f4 c0[NT], c1[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u) c0[u] = c1[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
@@ -789,7 +788,8 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
     }
 }
 
-// 1D grid.  A work group is (row-tile run x, group g, channel, flow), numbered
+// Per-row variant (any transfer order).  1D grid.  A work group is (row-tile run x, group g,
+// channel, flow), numbered
 // w = ((flow * 3 + channel) * N + g) * bx + x; its nchunk column chunks read the same A rows.
 // Workgroups are dealt to the 8 XCDs round-robin, so the chunks of one work group get
 // block ids 8 apart (same XCD, launched together) and its A rows come from one L2:
@@ -797,7 +797,7 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, const int* qg, 
 // The block stages its B chunk(s) in LDS once and reuses them for all 4 tpw row tiles;
 // every wave gathers its tiles' A operands straight into MFMA layout.
 template <int kM, int KE, int NT>
-__global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
+__global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowState* fs,
                                                      const double* Z_stage, const double* zw,
                                                      const float* bins, const float* binsT,
                                                      YArgs<float> args, int nchunk, int tpw,
@@ -868,13 +868,204 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState*
     const void* B1 = Braw + kBytes;
     const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
     if (two)
-        y_tiles<kM, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
+        y_tiles_rows<kM, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
                                      al, be, B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane,
                                      r0, o0, r1, o1);
     else
-        y_tiles<kM, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
+        y_tiles_rows<kM, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
                                       al, be, B0, B1, args.Y[ch] + yoff, nullptr, lane, r0, o0,
                                       r1, o1);
+}
+
+// Row tiles of one operation class.  Transfers are ordered by (operation o, representative),
+// so a 16-row tile shares o and its A rows are plain rows of representatives' bins:
+//   A[q][k'] = Brep_r(pinv_o g, k')   (k' = pinv_o k; the permutation moves to B, below).
+// Rows past the class end are clamped to its last transfer (valid reads; never stored).
+// A lane's k-values: kM = 0, k' = 4 e + lane / 16 (the four lane groups of a row read 16
+// contiguous bytes); kM > 0, eight consecutive k' per 32-wide step, two 16-byte loads
+// (N % 4 == 0; else one value at a time).  Every address is the lane's base plus a
+// constant.  k' in [N, 4 KE) reads past the row's end, into the next row or the zeroed
+// padding that follows the bin buffers (finite values either way); the staged B is zero
+// there.
+template <int kM, int KE>
+__device__ inline void gather_a(float (&a)[KE], const float* row, int N, int lane) {
+    if constexpr (kM == 0) {
+        const float* r = row + (lane >> 4);
+#pragma unroll
+        for (int e = 0; e < KE; ++e) a[e] = r[4 * e];
+    } else {
+        const float* r = row + 8 * (lane >> 4);
+        if ((N & 3) == 0) {
+#pragma unroll
+            for (int s = 0; s < KE / 8; ++s) {
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const float4 v = *reinterpret_cast<const float4*>(r + 32 * s + 4 * hh);
+                    a[8 * s + 4 * hh] = v.x;
+                    a[8 * s + 4 * hh + 1] = v.y;
+                    a[8 * s + 4 * hh + 2] = v.z;
+                    a[8 * s + 4 * hh + 3] = v.w;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < KE; ++e) a[e] = r[32 * (e >> 3) + (e & 7)];
+        }
+    }
+}
+
+// Row tiles [t_begin, t_end) of one wavefront within class [q0, q1): the A rows of tile t+1
+// are loaded while tile t runs on the matrix cores and is stored, and the representative
+// of tile t+2 is in flight.
+template <int kM, int KE, int NT, bool kTwo>
+__device__ inline void y_tiles(const float* Bf, const int* qrep, int NN, int N, int q0,
+                               int q1, int prow, int grp, int n0, int t_begin, int t_end,
+                               const void* Bs0, const void* Bs1, float* Y0, float* Y1,
+                               int lane, int r0, int r1) {
+    const int col = lane & 15;
+    const size_t roff = static_cast<size_t>(prow) * N;
+    float a0[KE], a1[KE];
+    gather_a<kM, KE>(a0, Bf + static_cast<size_t>(r0) * NN + roff, N, lane);
+#pragma unroll 1
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        // B fragments are re-read from LDS every tile instead of being kept in registers
+        asm volatile("" ::: "memory");
+        const int r2 = qrep[min(q0 + 16 * (tile + 2) + col, q1 - 1)];
+        if (tile + 1 < t_end) gather_a<kM, KE>(a1, Bf + static_cast<size_t>(r1) * NN + roff, N, lane);
+        fm_f4 c0[NT], c1[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) c0[u] = c1[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+        mfma_tile<kM, KE, NT, kTwo>(a0, Bs0, Bs1, c0, c1, lane);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int n = n0 + 16 * u + col;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int qq = q0 + tile * 16 + 4 * (lane >> 4) + r;
+                if (qq < q1 && n < N) {
+                    const size_t o = static_cast<size_t>(qq) * NN + grp * N + n;
+                    Y0[o] = c0[u][r];
+                    if constexpr (kTwo) Y1[o] = c1[u][r];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < KE; ++e) a0[e] = a1[e];
+        r1 = r2;
+    }
+}
+
+// Row-tile runs of the operation classes for one launch: run count of class o per channel
+// kind (0 particle-particle, 1 particle-hole) and in total, for `tpw` tiles per wavefront.
+struct YRuns {
+    int nr[2][8];
+    int tot[2];
+};
+
+// 1D grid.  A work group is (class run x, group g, channel, flow), numbered
+// w = ((flow * 3 + channel) * N + g) * bx + x; its nchunk column chunks read the same A rows.
+// Workgroups are dealt to the 8 XCDs round-robin, so the chunks of one work group get
+// block ids 8 apart (same XCD, launched together) and its A rows come from one L2:
+//   id = (w / 8) * 8 nchunk + chunk * 8 + w % 8.
+// Run x of channel kind c is run r of class o; the block stages its B chunk once, for that
+// operation:
+//   B'[k'][n] = Z_g Z_k (al + be (Z_g + Z_k)) Vsrc[g][k][n],  k = perm_o k',
+// so that sum_k' A[q][k'] B'[k'][n] is the product of the gathered, permuted and Z-weighted
+// bins with the slab.  The 4 waves take tpw consecutive row tiles each.
+template <int kM, int KE, int NT>
+__global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
+                                                     const double* Z_stage, const double* zw,
+                                                     const float* bins, const float* binsT,
+                                                     YArgs<float> args, YRuns runs, int nchunk,
+                                                     int tpw, int bx, int nwork) {
+    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
+    constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
+    __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks
+    __shared__ int kperm[4 * KE];                     // perm_o k' (k' < N)
+    __shared__ float kfac[4 * KE];                    // Z_g Z_k (al + be (Z_g + Z_k)), k = perm_o k' 
+    const int id = blockIdx.x;
+    const int rem = id % (8 * nchunk);
+    const int work = (id / (8 * nchunk)) * 8 + rem % 8;
+    const int chunk = rem / 8;
+    if (work >= nwork) return;                        // padding of the last 8 work groups
+    const int N = g.N, NN = g.NN;
+    int x = work % bx;
+    const int grp = (work / bx) % N;
+    const int ch = (work / (bx * N)) % 3;
+    const int f = work / (bx * N * 3);
+    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
+    const int cc = ch == 0 ? 0 : 1;
+    int o = 0;
+    for (; o < 8; ++o) {
+        if (x < runs.nr[cc][o]) break;
+        x -= runs.nr[cc][o];
+    }
+    if (o == 8) return;                               // past this kind's runs (uniform)
+    const int q0 = g.cls[cc][o], q1 = g.cls[cc][o + 1];
+    const int M = ch == 0 ? g.nP : g.nD;
+    const int n0 = chunk * W;
+    const int ntiles = (q1 - q0 + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int t_begin = (x * 4 + wv) * tpw;
+    const int t_end = min(t_begin + tpw, ntiles);
+    const bool two = ch == 2;
+    const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
+    // the first two tiles' representatives: in flight across the barrier
+    const int col = lane & 15;
+    const int r0 = qrep[min(q0 + 16 * t_begin + col, q1 - 1)];
+    const int r1 = qrep[min(q0 + 16 * (t_begin + 1) + col, q1 - 1)];
+    const int prow = g.pinv[o * N + grp];
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    const size_t slab = f * N3 + static_cast<size_t>(grp) * NN;
+    const float* V0 = args.Vs[two ? 2 : ch] + slab;
+    const float* V1 = args.Vs[3] + slab;
+    if (threadIdx.x < KP) {                           // per-k' permutation and factor
+        const double* Zf = Z_stage + static_cast<size_t>(f) * N;
+        const float zg = static_cast<float>(Zf[grp]);
+        const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
+        const int kp = g.perm[o * N + min(static_cast<int>(threadIdx.x), N - 1)];
+        const float zk = static_cast<float>(Zf[kp]);
+        kperm[threadIdx.x] = kp;
+        kfac[threadIdx.x] = zg * zk * (al + be * (zg + zk));
+    }
+    __syncthreads();                                   // every thread of the block
+    for (int e = threadIdx.x; e < KP * W; e += kThreads) {
+        const int k = e / W, n = e - k * W;            // W is a compile-time constant
+        const bool ok = k < N && n0 + n < N;
+        const int kp = kperm[k];
+        const float fac = kfac[k];
+        const size_t ia = static_cast<size_t>(kp) * N + min(n0 + n, N - 1);
+        const float x0 = ok ? fac * V0[ia] : 0.f;
+        const float x1 = (two && ok) ? fac * V1[ia] : 0.f;
+        if constexpr (kM > 0) {
+            __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
+            const __bf16 h0 = static_cast<__bf16>(x0), h1 = static_cast<__bf16>(x1);
+            Bh[n * KBS + k] = h0;
+            if (two) Bh[kBytes / 2 + n * KBS + k] = h1;
+            if constexpr (kM == 2) {                   // low parts: the second plane
+                Bh[W * KBS + n * KBS + k] = static_cast<__bf16>(x0 - static_cast<float>(h0));
+                if (two) Bh[kBytes / 2 + W * KBS + n * KBS + k] = static_cast<__bf16>(x1 - static_cast<float>(h1));
+            }
+        } else {
+            float* Bf32 = reinterpret_cast<float*>(Braw);
+            Bf32[k * S + n] = x0;
+            if (two) Bf32[KP * S + k * S + n] = x1;
+        }
+    }
+    __syncthreads();                                   // every thread of the block
+    if (t_begin >= t_end) return;
+    const int nR = g.nRp + g.nRd;
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
+                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const size_t yoff = static_cast<size_t>(f) * M * NN;
+    const void* B0 = Braw;
+    const void* B1 = Braw + kBytes;
+    if (two)
+        y_tiles<kM, KE, NT, true>(Bf, qrep, NN, N, q0, q1, prow, grp, n0, t_begin, t_end, B0,
+                                     B1, args.Y[2] + yoff, args.Y[3] + yoff, lane, r0, r1);
+    else
+        y_tiles<kM, KE, NT, false>(Bf, qrep, NN, N, q0, q1, prow, grp, n0, t_begin, t_end, B0,
+                                      B1, args.Y[ch] + yoff, nullptr, lane, r0, r1);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1376,7 +1567,7 @@ void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, i
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
 // tiles per wave); row tiles per wavefront `tpw` is a tuning choice (0: one).
 template <int kM, int KE, int NT>
-void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+void y_mfma_rows(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                 const YArgs<float>& a, int tpw) {
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     const int ntiles = (mmax + 15) / 16;
@@ -1386,43 +1577,75 @@ void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
     const int bx = (ntiles + 4 * tpw - 1) / (4 * tpw);
     const long nwork = static_cast<long>(bx) * g.N * 3 * nf;
     const long nblocks = (nwork + 7) / 8 * 8 * nchunk;
-    hipLaunchKernelGGL((k_y_mfma<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+    hipLaunchKernelGGL((k_y_mfma_rows<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
                        dim3(kThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
                        static_cast<const float*>(b.bins),
                        static_cast<const float*>(b.binsT), a, nchunk, tpw, bx,
                        static_cast<int>(nwork));
 }
 
+template <int kM, int KE, int NT>
+void y_mfma_cls(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+                const YArgs<float>& a, int tpw) {
+    const int maxt = y_max_tpw(g);
+    tpw = tpw <= 0 ? 1 : (tpw > maxt ? maxt : tpw);
+    YRuns runs{};
+    for (int c = 0; c < 2; ++c)
+        for (int o = 0; o < 8; ++o) {
+            const int nt = (g.cls[c][o + 1] - g.cls[c][o] + 15) / 16;
+            runs.nr[c][o] = (nt + 4 * tpw - 1) / (4 * tpw);
+            runs.tot[c] += runs.nr[c][o];
+        }
+    const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
+    const int bx = runs.tot[0] > runs.tot[1] ? runs.tot[0] : runs.tot[1];
+    const long nwork = static_cast<long>(bx) * g.N * 3 * nf;
+    const long nblocks = (nwork + 7) / 8 * 8 * nchunk;
+    if (nblocks == 0) return;
+    hipLaunchKernelGGL((k_y_mfma<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+                       dim3(kThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
+                       static_cast<const float*>(b.bins),
+                       static_cast<const float*>(b.binsT), a, runs, nchunk, tpw, bx,
+                       static_cast<int>(nwork));
+}
+
+// yvar 2: the operation-class kernel, else the per-row one.
+template <int kM, int KE, int NT>
+void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+                const YArgs<float>& a, int tpw, int yvar) {
+    if (yvar == 2) y_mfma_cls<kM, KE, NT>(s, g, b, nf, a, tpw);
+    else y_mfma_rows<kM, KE, NT>(s, g, b, nf, a, tpw);
+}
+
 inline void y_mfma_launch(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
-                          const YArgs<float>& a, int mode, int tpw) {
+                          const YArgs<float>& a, int mode, int tpw, int yvar) {
     const int N = g.N;
     if (mode == 2) {         // bf16 operands
-        if (N <= 16) y_mfma_tpw<1, 8, 1>(s, g, b, nf, a, tpw);
-        else if (N <= 32) y_mfma_tpw<1, 8, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 48) y_mfma_tpw<1, 16, 3>(s, g, b, nf, a, tpw);
-        else if (N <= 64) y_mfma_tpw<1, 16, 4>(s, g, b, nf, a, tpw);
-        else if (N <= 96) y_mfma_tpw<1, 24, 3>(s, g, b, nf, a, tpw);
-        else y_mfma_tpw<1, 32, 4>(s, g, b, nf, a, tpw);
+        if (N <= 16) y_mfma_tpw<1, 8, 1>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 32) y_mfma_tpw<1, 8, 2>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 48) y_mfma_tpw<1, 16, 3>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 64) y_mfma_tpw<1, 16, 4>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 96) y_mfma_tpw<1, 24, 3>(s, g, b, nf, a, tpw, yvar);
+        else y_mfma_tpw<1, 32, 4>(s, g, b, nf, a, tpw, yvar);
     } else if (mode == 3) {  // split bf16 operands (two planes in LDS)
-        if (N <= 16) y_mfma_tpw<2, 8, 1>(s, g, b, nf, a, tpw);
-        else if (N <= 32) y_mfma_tpw<2, 8, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 48) y_mfma_tpw<2, 16, 3>(s, g, b, nf, a, tpw);
-        else if (N <= 64) y_mfma_tpw<2, 16, 4>(s, g, b, nf, a, tpw);
-        else if (N <= 96) y_mfma_tpw<2, 24, 3>(s, g, b, nf, a, tpw);
-        else y_mfma_tpw<2, 32, 2>(s, g, b, nf, a, tpw);
+        if (N <= 16) y_mfma_tpw<2, 8, 1>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 32) y_mfma_tpw<2, 8, 2>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 48) y_mfma_tpw<2, 16, 3>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 64) y_mfma_tpw<2, 16, 4>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 96) y_mfma_tpw<2, 24, 3>(s, g, b, nf, a, tpw, yvar);
+        else y_mfma_tpw<2, 32, 2>(s, g, b, nf, a, tpw, yvar);
     } else {
-        if (N <= 16) y_mfma_tpw<0, 4, 1>(s, g, b, nf, a, tpw);
-        else if (N <= 32) y_mfma_tpw<0, 8, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 48) y_mfma_tpw<0, 12, 3>(s, g, b, nf, a, tpw);
-        else if (N <= 64) y_mfma_tpw<0, 16, 2>(s, g, b, nf, a, tpw);
-        else if (N <= 96) y_mfma_tpw<0, 24, 2>(s, g, b, nf, a, tpw);
-        else y_mfma_tpw<0, 32, 2>(s, g, b, nf, a, tpw);
+        if (N <= 16) y_mfma_tpw<0, 4, 1>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 32) y_mfma_tpw<0, 8, 2>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 48) y_mfma_tpw<0, 12, 3>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 64) y_mfma_tpw<0, 16, 2>(s, g, b, nf, a, tpw, yvar);
+        else if (N <= 96) y_mfma_tpw<0, 24, 2>(s, g, b, nf, a, tpw, yvar);
+        else y_mfma_tpw<0, 32, 2>(s, g, b, nf, a, tpw, yvar);
     }
 }
 
 template <typename R>
 void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int mma,
-         int tpw) {
+         int tpw, int yvar) {
     YArgs<R> a;
     a.Vs[0] = static_cast<const R*>(b.v0);
     a.Vs[1] = static_cast<const R*>(b.vc);
@@ -1436,7 +1659,7 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     if constexpr (sizeof(R) == 4) {
         if (mma > 0 && g.N <= 128) {
-            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma, tpw);
+            y_mfma_launch(s, g, b, nf, reinterpret_cast<const YArgs<float>&>(a), mma, tpw, yvar);
             return;
         }
     }
@@ -1459,6 +1682,16 @@ void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsig
 
 }  // namespace
 
+int y_max_tpw(const DevGeom& g) {
+    int most = 1;
+    for (int c = 0; c < 2; ++c)
+        for (int o = 0; o < 8; ++o) {
+            const int nt = (g.cls[c][o + 1] - g.cls[c][o] + 15) / 16;
+            most = nt > most ? nt : most;
+        }
+    return (most + 3) / 4;
+}
+
 void launch_stage(hipStream_t s, bool dbl, const DevGeom& g, const DevZ& z, const Buffers& b,
                   int nf, const StageCoef& sc, const BinPlan& bp, int write_new,
                   const double* Vbase) {
@@ -1478,9 +1711,14 @@ Buffers with_bin_set(const Buffers& b, const DevGeom& g, bool dbl, int set) {
 }
 
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
-              int mma, int tpw) {
-    if (dbl) y_t<double>(s, g, b, nf, ch, 0, 0);
-    else y_t<float>(s, g, b, nf, ch, mma, tpw);
+              int mma, int tpw, int yvar) {
+    if (dbl) y_t<double>(s, g, b, nf, ch, 0, 0, 0);
+    else y_t<float>(s, g, b, nf, ch, mma, tpw, yvar);
+}
+
+int y_rows_max_tpw(const DevGeom& g) {
+    const int mmax = g.nP > g.nD ? g.nP : g.nD;
+    return ((mmax + 15) / 16 + 3) / 4;
 }
 
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,

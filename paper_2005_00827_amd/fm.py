@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
                 ("v_max", c_double), ("channels", c_uint), ("precision", c_int),
                 ("n_zT", c_int), ("z_lnT", POINTER(c_double)), ("z_table", POINTER(c_double)),
                 ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int),
-                ("flow", c_int), ("g_end", c_double), ("v_rel", c_double)]
+                ("flow", c_int), ("g_end", c_double), ("v_rel", c_double), ("y_kernel", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -116,7 +116,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
                 integrator="rk4", n_steps=200, rtol=0.0, atol=0.0, h0=0.0, h_min=0.0,
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
                 stream=None, max_batch=1, tile_rows=0, flow="temperature", g_end=0.0,
-                v_rel=0.0):
+                v_rel=0.0, y_kernel=0):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
     cfg.geometry = GEOM_IDENTITY if geometry == "identity" else GEOM_ANGULAR
@@ -143,6 +143,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
     cfg.flow = FLOWS[flow] if isinstance(flow, str) else int(flow)
     cfg.g_end = float(g_end)
     cfg.v_rel = float(v_rel)
+    cfg.y_kernel = int(y_kernel)
     cfg._keep = keep
     return cfg
 
