@@ -27,6 +27,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "fm_internal.h"
 
@@ -315,8 +316,11 @@ template <> struct BinBatch<float> { static constexpr int v = 8; };
 template <> struct BinBatch<double> { static constexpr int v = 4; };
 
 // xi and patch of loop point j: single precision reads the packed (float xi, patch) table.
+// The byte offset is formed in 32 bits (L <= 2048: under 32 MiB), so a load is the table's
+// base plus one 32-bit offset.
 __device__ inline void xi_patch(const DevGeom& g, int j, float& x, int& p) {
-    const int2 v = g.xp[j];
+    const unsigned off = static_cast<unsigned>(j) * 8u;
+    const int2 v = *reinterpret_cast<const int2*>(reinterpret_cast<const char*>(g.xp) + off);
     x = __int_as_float(v.x);
     p = v.y;
 }
@@ -410,34 +414,15 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = lane & 15;
     const int band = (lane >> 4) * (BT / 64) + wv;
-    const int nunits = (npt + 15) / 16;
-    const int per_band = (nunits + kBands - 1) / kBands;
-    const int u_begin = band * per_band;
-    const int u_end = min(u_begin + per_band, nunits);
-    for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
-        R xu[kBinBatch], xv[kBinBatch];
-        int pa[kBinBatch], pq[kBinBatch];
+    // Weights of one batch (kBinBatch points per lane), the segmented scan of equal keys
+    // within each 16-lane row, and one atomic per run of equal keys (two under the pairing).
+    auto add_batch = [&](const R (&xu)[kBinBatch], const R (&xv)[kBinBatch],
+                         const int (&pa)[kBinBatch], const int (&pq)[kBinBatch],
+                         const bool (&ok)[kBinBatch]) {
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
-            const int p = min((u0 + i) * 16 + s, npt - 1);
-            // p < nrow L: row rr of the visited rows; else column of a row fixed by s
-            const int rr = static_cast<int>((p + 0.5f) * invL);       // p / L (L <= 2048)
-            const int q2 = p - nrow * L, fr = q2 >= ncol ? 1 : 0;
-            const bool mainpart = q2 < 0;
-            const int jx = mainpart ? p - rr * L : half_map(hx, q2 - fr * ncol);
-            const int jy = mainpart ? (half ? half_map(hy, rr) : rr) : half_fix(hy, fr, L);
-            int px = pp ? mx - jx - 1 : jx + mx;
-            int py = pp ? my - jy - 1 : jy + my;
-            px += px < 0 ? L : (px >= L ? -L : 0);
-            py += py < 0 ? L : (py >= L ? -L : 0);
-            xi_patch(g, jy * L + jx, xu[i], pa[i]);
-            xi_patch(g, py * L + px, xv[i], pq[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < kBinBatch; ++i) {
-            const bool ok = u0 + i < u_end && (u0 + i) * 16 + s < npt;
             const R w = kG ? pair_chi(xu[i], xv[i], tp, pp) : pair_weight(xu[i], xv[i], tp, pp);
-            R x = ok ? (kMode == 0 ? w : w * scale) : R(0);
+            R x = ok[i] ? (kMode == 0 ? w : w * scale) : R(0);
             const int key = pa[i] * N + pq[i];
             const int key2 = pp ? pq[i] * N + pa[i] : inv_patch(g, pq[i]) * N + inv_patch(g, pa[i]);
             const int kprev = dpp_i<0x111>(key);   // row_shr:1
@@ -451,6 +436,98 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
                 atomicAdd(&acc[key], x);
                 if (half) atomicAdd(&acc[key2], x);
             }
+        }
+    };
+    auto partner = [&](int jx, int jy, int& px, int& py) {
+        px = pp ? mx - jx - 1 : jx + mx;
+        py = pp ? my - jy - 1 : jy + my;
+        px += px < 0 ? L : (px >= L ? -L : 0);
+        py += py < 0 ? L : (py >= L ? -L : 0);
+    };
+    if (L % 16 == 0) {
+        // The visited rows in full: a 16-point unit never crosses a grid row, so the row is
+        // found once per unit and the column is the lane's offset.  The loop is specialised
+        // per kind: a particle-particle partner coordinate m - j - 1 can only fall below 0,
+        // a particle-hole one j + m only reach L.
+        const int upr = L >> 4;                                   // units per row
+        const float invu = 1.0f / static_cast<float>(upr);
+        const int nmain = nrow * upr;
+        const int per_band = (nmain + kBands - 1) / kBands;
+        const int u_begin = band * per_band;
+        const int u_end = min(u_begin + per_band, nmain);
+        auto main_rows = [&](auto kind) {
+            constexpr bool kPP = decltype(kind)::value;
+            for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
+                R xu[kBinBatch], xv[kBinBatch];
+                int pa[kBinBatch], pq[kBinBatch];
+                bool ok[kBinBatch];
+#pragma unroll
+                for (int i = 0; i < kBinBatch; ++i) {
+                    const int u = min(u0 + i, nmain - 1);
+                    const int rr = static_cast<int>((u + 0.5f) * invu);   // u / upr (exact, L <= 2048)
+                    const int jx = ((u - rr * upr) << 4) + s;
+                    const int jy = half ? half_map(hy, rr) : rr;
+                    int px = kPP ? mx - jx - 1 : jx + mx;
+                    int py = kPP ? my - jy - 1 : jy + my;
+                    if constexpr (kPP) {
+                        px += px < 0 ? L : 0;
+                        py += py < 0 ? L : 0;
+                    } else {
+                        px -= px >= L ? L : 0;
+                        py -= py >= L ? L : 0;
+                    }
+                    xi_patch(g, jy * L + jx, xu[i], pa[i]);
+                    xi_patch(g, py * L + px, xv[i], pq[i]);
+                    ok[i] = u0 + i < u_end;
+                }
+                add_batch(xu, xv, pa, pq, ok);
+            }
+        };
+        if (pp) main_rows(std::true_type{});
+        else main_rows(std::false_type{});
+        // the rows the pairing fixes (at most two): one column of each column pair, few
+        // points, one atomic per key
+        if (half)
+            for (int t = threadIdx.x; t < hy.nfix * ncol; t += BT) {
+                const int fr = t >= ncol ? 1 : 0;
+                const int jx = half_map(hx, t - fr * ncol), jy = half_fix(hy, fr, L);
+                int px, py;
+                partner(jx, jy, px, py);
+                R xa, xb;
+                int qa, qb;
+                xi_patch(g, jy * L + jx, xa, qa);
+                xi_patch(g, py * L + px, xb, qb);
+                const R w = kG ? pair_chi(xa, xb, tp, pp) : pair_weight(xa, xb, tp, pp);
+                const R x = kMode == 0 ? w : w * scale;
+                atomicAdd(&acc[qa * N + qb], x);
+                atomicAdd(&acc[pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa)], x);
+            }
+    } else {
+        // any L: visited rows and fixed rows as one numbered list of points
+        const int nunits = (npt + 15) / 16;
+        const int per_band = (nunits + kBands - 1) / kBands;
+        const int u_begin = band * per_band;
+        const int u_end = min(u_begin + per_band, nunits);
+        for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
+            R xu[kBinBatch], xv[kBinBatch];
+            int pa[kBinBatch], pq[kBinBatch];
+            bool ok[kBinBatch];
+#pragma unroll
+            for (int i = 0; i < kBinBatch; ++i) {
+                const int p = min((u0 + i) * 16 + s, npt - 1);
+                // p < nrow L: row rr of the visited rows; else column of a row fixed by s
+                const int rr = static_cast<int>((p + 0.5f) * invL);       // p / L (L <= 2048)
+                const int q2 = p - nrow * L, fr = q2 >= ncol ? 1 : 0;
+                const bool mainpart = q2 < 0;
+                const int jx = mainpart ? p - rr * L : half_map(hx, q2 - fr * ncol);
+                const int jy = mainpart ? (half ? half_map(hy, rr) : rr) : half_fix(hy, fr, L);
+                int px, py;
+                partner(jx, jy, px, py);
+                xi_patch(g, jy * L + jx, xu[i], pa[i]);
+                xi_patch(g, py * L + px, xv[i], pq[i]);
+                ok[i] = u0 + i < u_end && (u0 + i) * 16 + s < npt;
+            }
+            add_batch(xu, xv, pa, pq, ok);
         }
     }
     // points fixed by s: their own pair, added once
