@@ -228,14 +228,16 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large batch (16 flows, N=128, L=512) in the extra section")
     ap.add_argument("--no-gflow", action="store_true", help="skip the interaction-flow runs")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the 16-flow N=128, L=512 batch (for profiling); prints its record")
     ap.add_argument("--cpu-rhs", type=int, default=6, help="oracle RHS evaluations timed")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB three times "
                          "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the flow batch and the transfer groups would shard).",
+        print("bench.py runs on one GPU only: there is no multi-GPU path; independent flows "
+              "and the per-transfer work would be the units to shard over GPUs.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -243,6 +245,9 @@ def main():
     import torch
     from paper_2005_00827_amd import fm, inputs
 
+    if args.large_only:
+        print(json.dumps({"large_16_flows": large_batch(fm, inputs, torch, torch.device("cuda:0"))}))
+        return
     w = inputs.workload("C2")
     N, L, U, T0, Te = w["N"], w["L"], w["U"][0], w["T0"][0], w["T_end"]
     zl, zt = inputs.synthetic_z_table(N, U, T0, Te)

@@ -17,7 +17,8 @@
 //   and in the same grid the bubble-weight derivatives, evaluated on the fly for every loop
 //   point j and every representative transfer q (one per orbit of the lattice point group),
 //   summed into per-transfer bin matrices held in LDS.
-// Phase 2a (k_y_mfma on matrix cores, k_y on vector units): per-transfer grouped products
+// Phase 2a (k_y_mfma_rows / k_y_mfma_cls on matrix cores, k_y on vector units): per-transfer
+//   grouped products
 //   Y_q = B_q x V-slab, four kinds.
 // Phase 2b (k_contract): the remaining contraction over one patch index per channel,
 //   written straight into the stage's k slot, one part per channel.
@@ -1050,7 +1051,7 @@ struct YRuns {
 // so that sum_k' A[q][k'] B'[k'][n] is the product of the gathered, permuted and Z-weighted
 // bins with the slab.  The 4 waves take tpw consecutive row tiles each.
 template <int kM, int KE, int NT>
-__global__ void __launch_bounds__(kThreads) k_y_mfma(DevGeom g, const FlowState* fs,
+__global__ void __launch_bounds__(kThreads) k_y_mfma_cls(DevGeom g, const FlowState* fs,
                                                      const double* Z_stage, const double* zw,
                                                      const float* bins, const float* binsT,
                                                      YArgs<float> args, YRuns runs, int nchunk,
@@ -1678,7 +1679,7 @@ void y_mfma_cls(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
     const long nwork = static_cast<long>(bx) * g.N * 3 * nf;
     const long nblocks = (nwork + 7) / 8 * 8 * nchunk;
     if (nblocks == 0) return;
-    hipLaunchKernelGGL((k_y_mfma<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+    hipLaunchKernelGGL((k_y_mfma_cls<kM, KE, NT>), dim3(static_cast<unsigned>(nblocks)),
                        dim3(kThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
                        static_cast<const float*>(b.bins),
                        static_cast<const float*>(b.binsT), a, runs, nchunk, tpw, bx,
