@@ -131,14 +131,16 @@ def test_rhs_c2_full(torch_dev, prec):
 
 
 @pytest.mark.parametrize("N,L", [(96, 256), (128, 512)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3"])
-def test_rhs_large_sampled(torch_dev, N, L, prec):
-    """Full-size grids: sampled outputs against the oracle's per-element sums."""
+@pytest.mark.parametrize("prec,y_kernel", [("fp64", 0), ("fp32", 1), ("fp32", 2), ("bf16", 1),
+                                           ("bf16", 2), ("bf16x3", 1), ("bf16x3", 2)])
+def test_rhs_large_sampled(torch_dev, N, L, prec, y_kernel):
+    """Full-size grids: sampled outputs against the oracle's per-element sums, with each
+    matrix-core phase-2a kernel."""
     V = inputs.noisy_state(N, 3.0)
     T = 0.08
     abc = inputs.sample_indices(N, 48)
     ref = O.rhs_points(O.model(N, L), T, V, abc)
-    got = gpu_rhs(torch_dev, N, L, T, V, prec)[0]
+    got = gpu_rhs(torch_dev, N, L, T, V, prec, y_kernel=y_kernel)[0]
     g = got[abc[:, 0], abc[:, 1], abc[:, 2]]
     # relative to the largest sampled reference value
     assert rel(g, ref) <= TOL[prec]
