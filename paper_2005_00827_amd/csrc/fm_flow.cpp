@@ -133,7 +133,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
     if (c.tile_rows < 0) { why = "tile_rows must be >= 0"; return FM_EINVAL; }
-    if (c.y_kernel < 0 || c.y_kernel > 2) { why = "y_kernel must be 0, 1 or 2"; return FM_EINVAL; }
+    if (c.y_kernel < 0 || c.y_kernel > 3) { why = "y_kernel must be 0, 1, 2 or 3"; return FM_EINVAL; }
     return FM_OK;
 }
 
@@ -202,6 +202,10 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.qg_ph = L.take<int>(nD);
     b.pinv = L.take<int>(8 * static_cast<size_t>(N));
     b.perm = L.take<int>(8 * static_cast<size_t>(N));
+    b.orb_rows = L.take<int>(hg.orb_rows.size());
+    b.orb_q = L.take<int>(hg.orb_q.size());
+    b.orb_mask = L.take<int>(hg.orb_mask.size());
+    b.porder = L.take<int>(hg.porder.size());
     b.pI = L.take<int>(N);
     b.pp_off = L.take<int>(nP + 1);
     b.pp_pairs = L.take<int>(NN);
@@ -336,13 +340,15 @@ void stage_launch(fm_flow* h, int nf, const StageCoef& sc, const BinPlan& bp, in
     });
 }
 
-// Phase-2a choice: the kernel variant (cfg.y_kernel, or both) and row tiles per wavefront
-// (cfg.tile_rows, or 1, 2, 4, ... up to all of a group's or a class's tiles in one block:
-// few blocks, each staging its B chunk once, against many blocks with more parallelism);
-// the fastest candidate, timed with events on the operands of a stage at the flows' current
-// state.  The per-row kernel gathers permuted bins; the operation-class kernel reads plain
-// bin rows and stages a permuted operand once per class, which pays where the gathers
-// dominate (large N, bf16) and costs where blocks are few.
+// Phase-2a choice: the kernel variant (cfg.y_kernel, or all three) and row tiles per
+// wavefront (cfg.tile_rows, or 1, 2, 4, ... up to all of a group's or a class's tiles in one
+// block: few blocks, each staging its B chunk once, against many blocks with more
+// parallelism); the fastest candidate, timed with events on the operands of a stage at the
+// flows' current state.  The per-row kernel gathers permuted bins; the operation-class
+// kernel reads plain bin rows and stages a permuted operand once per class, which pays where
+// the gathers dominate (large N, bf16) and costs where blocks are few; the orbit kernel
+// reads each representative's bin row once and stages the operand once per operation,
+// which cuts the bins' re-reads where they dominate the traffic.
 // Every later stage recomputes these products, so the timing runs change no result.
 // Choices are kept for the process, per shape, settings and number of flows.
 using TuneKey = std::tuple<int, int, int, int, int, double, double, double, int, int>;
@@ -354,10 +360,11 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     const int mma = mma_mode(c.precision);
     if (h->dbl || h->direct || mma == 0 || c.N > 128) return FM_OK;
     std::vector<std::pair<int, int>> cand;    // (variant, tiles per wavefront)
-    for (int var = 1; var <= 2; ++var) {
+    for (int var = 1; var <= 3; ++var) {
         if (c.y_kernel != 0 && var != c.y_kernel) continue;
         if (c.tile_rows > 0) { cand.emplace_back(var, c.tile_rows); continue; }
-        const int maxt = var == 2 ? y_max_tpw(h->g) : y_rows_max_tpw(h->g);
+        const int maxt = var == 3 ? y_orb_max_tpw(h->g, mma)
+                         : var == 2 ? y_max_tpw(h->g) : y_rows_max_tpw(h->g);
         for (int t = 1; t < maxt; t *= 2) cand.emplace_back(var, t);
         cand.emplace_back(var, maxt);
     }
@@ -537,6 +544,11 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.qrep_ph = h->b.qrep_ph; g.qg_ph = h->b.qg_ph;
     g.pinv = h->b.pinv;
     g.perm = h->b.perm;
+    g.orb_rows = h->b.orb_rows; g.orb_q = h->b.orb_q; g.orb_mask = h->b.orb_mask;
+    g.orb_nt[0] = hg.orb_nt[0];
+    g.orb_nt[1] = hg.orb_nt[1];
+    g.porder = h->b.porder;
+    g.nG = static_cast<int>(hg.porder.size() / 8);
     for (int o = 0; o < 9; ++o) {
         g.cls[0][o] = hg.cls_pp[o];
         g.cls[1][o] = hg.cls_ph[o];
@@ -584,6 +596,10 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.qg_ph, hg.qg_ph);
     if (e == hipSuccess) e = upv(h->b.pinv, hg.pinv);
     if (e == hipSuccess) e = upv(h->b.perm, hg.perm);
+    if (e == hipSuccess) e = upv(h->b.orb_rows, hg.orb_rows);
+    if (e == hipSuccess) e = upv(h->b.orb_q, hg.orb_q);
+    if (e == hipSuccess) e = upv(h->b.orb_mask, hg.orb_mask);
+    if (e == hipSuccess) e = upv(h->b.porder, hg.porder);
     if (e == hipSuccess) e = upv(h->b.pI, hg.inv_perm);
     if (e == hipSuccess) e = upv(h->b.pp_off, hg.pp_off);
     if (e == hipSuccess) e = upv(h->b.pp_pairs, hg.pp_pairs);

@@ -40,6 +40,14 @@ struct HostGeometry {
     // Transfers are ordered by (operation, representative); cls_*[o] .. cls_*[o+1] are the
     // transfers obtained with operation o.
     std::vector<int> cls_pp, cls_ph; // [9]
+    // Orbit kernel: representatives in 16-row tiles per channel kind (pp tiles first), the
+    // transfer of each (tile, operation, row) and each tile's operation set; patches in
+    // groups of 8, orbit by orbit (-1 pads).
+    std::vector<int> orb_rows;       // [16 (nt0 + nt1)] representative or -1
+    std::vector<int> orb_q;          // [(nt0 + nt1) * 8 * 16] transfer or -1
+    std::vector<int> orb_mask;       // [nt0 + nt1] bit o: some row has a transfer by o
+    int orb_nt[2] = {0, 0};
+    std::vector<int> porder;         // [8 nG]
     // Output pairs grouped by transfer (CSR): pp pairs (a,b), crossed (b,c), direct (a,c),
     // each packed as x*N + y.
     std::vector<int> pp_off, pp_pairs, cr_off, cr_pairs, d_off, d_pairs;
@@ -88,6 +96,12 @@ struct DevGeom {
     const int* pinv;       // [8][N]
     const int* perm;       // [8][N], inverse of pinv
     int cls[2][9];         // transfer classes by operation: particle-particle, particle-hole
+    const int* orb_rows;   // orbit kernel tables (see HostGeometry)
+    const int* orb_q;
+    const int* orb_mask;
+    int orb_nt[2];
+    const int* porder;
+    int nG;                // patch groups of 8
     const int* pI;         // [N] patch permutation of k -> -k
     int inv_ok;            // pI is valid (k -> -k maps patches and dispersion onto themselves)
     int inv_rot;           // pI[a] = (a + N/2) mod N
@@ -144,6 +158,7 @@ struct Buffers {
     double* zw_stage;                  // [B][2]: line-pair factor Z_a Z_b (al + be (Z_a + Z_b))
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
     int* perm;
+    int* orb_rows; int* orb_q; int* orb_mask; int* porder;
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0; int* item_rec;
@@ -183,11 +198,14 @@ Buffers with_bin_set(const Buffers& b, const DevGeom& g, bool dbl, int set);
 // precision only, N <= 128);
 // tpw: row tiles per wavefront on matrix cores (1, 2, 4; 0 = by size);
 // yvar: matrix-core kernel, 1 per-row gather of permuted bins, 2 operation classes (the
-// permutation applied to the staged operand)
+// permutation applied to the staged operand), 3 orbits (each representative's bin row read
+// once, every operation applied to it in the block)
 void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
               int mma, int tpw, int yvar);
 // Largest useful tiles per wavefront of the per-row kernel.
 int y_rows_max_tpw(const DevGeom& g);
+// Largest useful tiles per wavefront of the orbit kernel (1, 2, or 4 with bf16 operands).
+int y_orb_max_tpw(const DevGeom& g, int mma);
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,
                      unsigned ch, int slot);
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf);

@@ -200,6 +200,72 @@ void build_symmetry(HostGeometry& g) {
     order(g.q_ph, g.qrep_ph, g.qg_ph, {&g.map_cr, &g.map_d}, g.cls_ph);
 }
 
+// Tables of the orbit phase-2a kernel, which reads each representative's bins once and
+// produces every transfer of the representative's orbit from them.
+//   Row tiles: per channel kind, the representatives in 16-row tiles, grouped by the set of
+//   operations that yield their transfers (a tile holds one set; rows past a set's end are
+//   -1), with the transfer index of each (tile, operation, row), -1 where none.
+//   Patch groups: patches listed orbit by orbit, orbits by decreasing size, in groups of 8
+//   (-1 padding).  Orbit sizes divide 8, so no orbit straddles two groups; the slabs of the
+//   operand that a group's blocks read are those of its orbits.
+void build_orbit_tables(HostGeometry& g) {
+    const int N = g.N;
+    g.orb_rows.clear();
+    g.orb_q.clear();
+    g.orb_mask.clear();
+    for (int cc = 0; cc < 2; ++cc) {
+        const std::vector<int>& qrep = cc == 0 ? g.qrep_pp : g.qrep_ph;
+        const std::vector<int>& qg = cc == 0 ? g.qg_pp : g.qg_ph;
+        const int nR = static_cast<int>(cc == 0 ? g.rep_pp.size() : g.rep_ph.size());
+        std::vector<int> mask(nR, 0), qof(8 * static_cast<size_t>(nR), -1);
+        for (size_t q = 0; q < qrep.size(); ++q) {
+            mask[qrep[q]] |= 1 << qg[q];
+            qof[static_cast<size_t>(qg[q]) * nR + qrep[q]] = static_cast<int>(q);
+        }
+        std::vector<int> idx(nR);
+        for (int r = 0; r < nR; ++r) idx[r] = r;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return mask[x] > mask[y]; });
+        std::vector<int> rows;
+        for (int i = 0; i < nR; ++i) {
+            if (i > 0 && mask[idx[i]] != mask[idx[i - 1]])
+                while (rows.size() % 16) rows.push_back(-1);
+            rows.push_back(idx[i]);
+        }
+        while (rows.size() % 16) rows.push_back(-1);
+        const int nt = static_cast<int>(rows.size() / 16);
+        g.orb_nt[cc] = nt;
+        for (int t = 0; t < nt; ++t) {
+            int m = 0;
+            for (int j = 0; j < 16; ++j)
+                if (rows[16 * t + j] >= 0) m |= mask[rows[16 * t + j]];
+            g.orb_mask.push_back(m);
+            for (int o = 0; o < 8; ++o)
+                for (int j = 0; j < 16; ++j) {
+                    const int r = rows[16 * t + j];
+                    g.orb_q.push_back(r < 0 ? -1 : qof[static_cast<size_t>(o) * nR + r]);
+                }
+        }
+        g.orb_rows.insert(g.orb_rows.end(), rows.begin(), rows.end());
+    }
+    std::vector<int> seen(N, 0);
+    std::vector<std::vector<int>> orbits;
+    for (int a = 0; a < N; ++a) {
+        if (seen[a]) continue;
+        std::vector<int> orb;
+        for (int o = 0; o < 8; ++o) {
+            const int b = g.perm[o * static_cast<size_t>(N) + a];
+            if (!seen[b]) { seen[b] = 1; orb.push_back(b); }
+        }
+        std::sort(orb.begin(), orb.end());
+        orbits.push_back(orb);
+    }
+    std::stable_sort(orbits.begin(), orbits.end(),
+                     [](const std::vector<int>& x, const std::vector<int>& y) { return x.size() > y.size(); });
+    g.porder.clear();
+    for (const auto& orb : orbits) g.porder.insert(g.porder.end(), orb.begin(), orb.end());
+    while (g.porder.size() % 8) g.porder.push_back(-1);
+}
+
 void csr(const std::vector<int>& map, int nq, std::vector<int>& off, std::vector<int>& pairs) {
     off.assign(nq + 1, 0);
     for (int v : map) off[v + 1]++;
@@ -329,6 +395,7 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
             g.map_cr[b * N + c] = intern(iph, g.q_ph, flat(ac[0] - ab[0], ac[1] - ab[1]));
         }
     build_symmetry(g);
+    build_orbit_tables(g);
     build_pairs(g);
     return true;
 }

@@ -736,14 +736,44 @@ __device__ inline int mfma_k(int e, int lane) {
 template <int NT>
 constexpr int b_stride() { return (16 * NT) % 32 == 16 ? 16 * NT : 16 * NT + 16; }
 
+// A operand of one row tile as the matrix cores take it: kM > 0 packed bf16 (kM = 2 with the
+// low parts), kM = 0 the f32 values.
+template <int kM, int KE>
+struct AFrag {
+    fm_bf8 h[KE / 8];
+    fm_bf8 l[kM == 2 ? KE / 8 : 1];
+};
+template <int KE>
+struct AFrag<0, KE> {
+    float a[KE];
+};
+
+template <int kM, int KE>
+__device__ inline AFrag<kM, KE> make_afrag(const float (&a)[KE]) {
+    AFrag<kM, KE> r;
+    if constexpr (kM > 0) {
+#pragma unroll
+        for (int s = 0; s < KE / 8; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                r.h[s][e] = static_cast<__bf16>(a[8 * s + e]);
+                if constexpr (kM == 2) r.l[s][e] = static_cast<__bf16>(a[8 * s + e] - static_cast<float>(r.h[s][e]));
+            }
+    } else {
+#pragma unroll
+        for (int e = 0; e < KE; ++e) r.a[e] = a[e];
+    }
+    return r;
+}
+
 // One 16-row tile on the matrix cores: c0 += A B0 (and c1 += A B1 for the direct channel).
 // kM = 0: B fragments read from LDS as [k][n] floats (stride b_stride).  kM > 0: B staged as
 // bf16, transposed [n][k] with row stride 4 KE + 8, so a lane's 8 consecutive k of one column
 // are a single 16-byte read; kM = 2 keeps a second plane with the low parts right after the
 // first.  Both zero beyond N.
 template <int kM, int KE, int NT, bool kTwo>
-__device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const void* Bs1v,
-                                 fm_f4 (&c0)[NT], fm_f4 (&c1)[NT], int lane) {
+__device__ inline void mfma_tile_f(const AFrag<kM, KE>& A, const void* Bs0v, const void* Bs1v,
+                                   fm_f4 (&c0)[NT], fm_f4 (&c1)[NT], int lane) {
     const int col = lane & 15;
     if constexpr (kM > 0) {
         constexpr int KBS = 4 * KE + 8;
@@ -752,12 +782,7 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
         const __bf16* Bh1 = static_cast<const __bf16*>(Bs1v);
 #pragma unroll
         for (int s = 0; s < KE / 8; ++s) {
-            fm_bf8 ah, al;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                ah[e] = static_cast<__bf16>(a[8 * s + e]);
-                if constexpr (kM == 2) al[e] = static_cast<__bf16>(a[8 * s + e] - static_cast<float>(ah[e]));
-            }
+            const fm_bf8 ah = A.h[s];
             const int kb = 32 * s + 8 * (lane >> 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -765,7 +790,7 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
                 const fm_bf8 bh = *reinterpret_cast<const fm_bf8*>(Bh0 + o);
                 if constexpr (kM == 2) {
                     const fm_bf8 bl = *reinterpret_cast<const fm_bf8*>(Bh0 + PL + o);
-                    c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c0[t], 0, 0, 0);
+                    c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.l[s], bh, c0[t], 0, 0, 0);
                     c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c0[t], 0, 0, 0);
                 }
                 c0[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c0[t], 0, 0, 0);
@@ -773,7 +798,7 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
                     const fm_bf8 wh = *reinterpret_cast<const fm_bf8*>(Bh1 + o);
                     if constexpr (kM == 2) {
                         const fm_bf8 wl = *reinterpret_cast<const fm_bf8*>(Bh1 + PL + o);
-                        c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, c1[t], 0, 0, 0);
+                        c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.l[s], wh, c1[t], 0, 0, 0);
                         c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wl, c1[t], 0, 0, 0);
                     }
                     c1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wh, c1[t], 0, 0, 0);
@@ -789,12 +814,19 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
             const int k = 4 * e + (lane >> 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], Bs0[k * S + 16 * t + col], c0[t], 0, 0, 0);
+                c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[e], Bs0[k * S + 16 * t + col], c0[t], 0, 0, 0);
                 if constexpr (kTwo)
-                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], Bs1[k * S + 16 * t + col], c1[t], 0, 0, 0);
+                    c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[e], Bs1[k * S + 16 * t + col], c1[t], 0, 0, 0);
             }
         }
     }
+}
+
+// The same from the f32 values of the lane's k-values.
+template <int kM, int KE, int NT, bool kTwo>
+__device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const void* Bs1v,
+                                 fm_f4 (&c0)[NT], fm_f4 (&c1)[NT], int lane) {
+    mfma_tile_f<kM, KE, NT, kTwo>(make_afrag<kM, KE>(a), Bs0v, Bs1v, c0, c1, lane);
 }
 
 // A operand of one row tile: lane row q = 16 tile + lane % 16 (rep r, operation o), k-values
@@ -1144,6 +1176,265 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_cls(DevGeom g, const FlowSt
     else
         y_tiles<kM, KE, NT, false>(Bf, qrep, NN, N, q0, q1, prow, grp, n0, t_begin, t_end, B0,
                                       B1, args.Y[ch] + yoff, nullptr, lane, r0, r1);
+}
+
+// B operand of one wavefront's tiles in registers: the fragments of every k-step and column
+// tile, read from the staged chunk once and used by all of the wave's row tiles.
+template <int kM, int KE, int NT>
+struct BFrag {
+    fm_bf8 h[KE / 8][NT];
+    fm_bf8 l[kM == 2 ? KE / 8 : 1][NT];
+};
+template <int KE, int NT>
+struct BFrag<0, KE, NT> {
+    float b[KE][NT];
+};
+
+template <int kM, int KE, int NT>
+__device__ inline void load_bfrag(BFrag<kM, KE, NT>& B, const void* Bsv, int lane) {
+    const int col = lane & 15;
+    if constexpr (kM > 0) {
+        constexpr int KBS = 4 * KE + 8;
+        constexpr int PL = 16 * NT * KBS;
+        const __bf16* Bh = static_cast<const __bf16*>(Bsv);
+#pragma unroll
+        for (int s = 0; s < KE / 8; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int o = (16 * t + col) * KBS + 32 * s + 8 * (lane >> 4);
+                B.h[s][t] = *reinterpret_cast<const fm_bf8*>(Bh + o);
+                if constexpr (kM == 2) B.l[s][t] = *reinterpret_cast<const fm_bf8*>(Bh + PL + o);
+            }
+    } else {
+        constexpr int S = b_stride<NT>();
+        const float* Bs = static_cast<const float*>(Bsv);
+#pragma unroll
+        for (int e = 0; e < KE; ++e)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) B.b[e][t] = Bs[(4 * e + (lane >> 4)) * S + 16 * t + col];
+    }
+}
+
+// c += A B with both operands in registers (the fragment layouts of mfma_tile_f).
+template <int kM, int KE, int NT>
+__device__ inline void mfma_ab(const AFrag<kM, KE>& A, const BFrag<kM, KE, NT>& B, fm_f4 (&c)[NT]) {
+    if constexpr (kM > 0) {
+#pragma unroll
+        for (int s = 0; s < KE / 8; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (kM == 2) {
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.l[s], B.h[s][t], c[t], 0, 0, 0);
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h[s], B.l[s][t], c[t], 0, 0, 0);
+                }
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h[s], B.h[s][t], c[t], 0, 0, 0);
+            }
+    } else {
+#pragma unroll
+        for (int e = 0; e < KE; ++e)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[e], B.b[e][t], c[t], 0, 0, 0);
+    }
+}
+
+// Loads a thread keeps in flight while staging: the largest divisor of its count up to 16.
+constexpr int stage_group(int per) {
+    int gsz = per < 16 ? per : 16;
+    while (per % gsz) --gsz;
+    return gsz;
+}
+
+// Stages B'_o[k'][n] = fac(k) Vsrc[k][n0 + n], k = perm_o k' (fac from the stage's Z), for
+// one or two operand slabs into the block's chunk(s).  Loads are issued in groups before
+// any of them is used, so a thread has a group in flight instead of one.
+template <int kM, int KE, int NT, bool kTwo>
+__device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const float* V1,
+                                     const int* pm, const float* zs, float zg, float al,
+                                     float be, int N, int n0) {
+    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
+    constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;
+    constexpr int kPer = KP * W / kThreads;
+    static_assert(KP * W % kThreads == 0, "staging covers the chunk in whole rounds");
+    constexpr int kGrp = stage_group(kPer);
+#pragma unroll 1
+    for (int j0 = 0; j0 < kPer; j0 += kGrp) {
+        float v0[kGrp], v1[kGrp];
+        int kq[kGrp];
+#pragma unroll
+        for (int j = 0; j < kGrp; ++j) {
+            const int e = threadIdx.x + (j0 + j) * kThreads;
+            const int k = e / W, n = e - k * W;
+            const int kp = pm[min(k, N - 1)];
+            kq[j] = kp;
+            const size_t ia = static_cast<size_t>(kp) * N + min(n0 + n, N - 1);
+            v0[j] = V0[ia];
+            if constexpr (kTwo) v1[j] = V1[ia];
+        }
+#pragma unroll
+        for (int j = 0; j < kGrp; ++j) {
+            const int e = threadIdx.x + (j0 + j) * kThreads;
+            const int k = e / W, n = e - k * W;
+            const bool ok = k < N && n0 + n < N;
+            const float zk = zs[kq[j]];
+            const float fac = ok ? zg * zk * (al + be * (zg + zk)) : 0.f;
+            const float x0 = fac * v0[j];
+            const float x1 = kTwo ? fac * v1[j] : 0.f;
+            if constexpr (kM > 0) {
+                __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
+                const __bf16 h0 = static_cast<__bf16>(x0), h1 = static_cast<__bf16>(x1);
+                Bh[n * KBS + k] = h0;
+                if constexpr (kTwo) Bh[kBytes / 2 + n * KBS + k] = h1;
+                if constexpr (kM == 2) {               // low parts: the second plane
+                    Bh[W * KBS + n * KBS + k] = static_cast<__bf16>(x0 - static_cast<float>(h0));
+                    if constexpr (kTwo) Bh[kBytes / 2 + W * KBS + n * KBS + k] = static_cast<__bf16>(x1 - static_cast<float>(h1));
+                }
+            } else {
+                float* Bf32 = reinterpret_cast<float*>(Braw);
+                Bf32[k * S + n] = x0;
+                if constexpr (kTwo) Bf32[KP * S + k * S + n] = x1;
+            }
+        }
+    }
+}
+
+// Orbit kernel.  Transfer q = o(r) of representative r needs row pinv_o(g) of r's bins for
+// slab g; for fixed bin row p that is slab g = perm_o(p).  A block takes one bin row p, a run
+// of representative tiles (4 waves x TPW tiles of 16 representatives) and one column chunk;
+// it loads its A rows once, keeps them in registers, and for each operation o that yields
+// transfers of its tiles stages
+//   B'_o[k'][n] = Z_g Z_k (al + be (Z_g + Z_k)) Vsrc[g][k][n],  g = perm_o p,  k = perm_o k',
+// and stores the tile product into the rows of the transfers o(r) at slab g.  Every (q, g)
+// is produced once (q by its own (o, r), g by p = pinv_o g), and every bin row is read by
+// one block per column chunk instead of once per transfer of its orbit.  A wave reads B'_o
+// from LDS into registers once and applies it to all its tiles.
+// Grid: a work group is (patch group G of 8 bin rows, channel, flow), numbered
+// gw = (flow * 3 + channel) * nG + G; its 8 bx nchunk blocks (member i, run x, chunk) read
+// the operand slabs of G's orbits only and go to one XCD, launched together:
+//   id = (gw / 8) * 8 gsize + m * 8 + gw % 8,  m = (i * bx + x) * nchunk + chunk.
+template <int kM, int KE, int NT, int TPW, bool kTwo>
+__device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const float* Vs0,
+                                     const float* Vs1, float* Y0, float* Y1, int p, int tb,
+                                     int nt, int toff, int n0, float al, float be,
+                                     const double* Zf, unsigned char* Braw, int* pms,
+                                     float* zs, int* qs, int* msk) {
+    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
+    constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
+    const int N = g.N, NN = g.NN;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int col = lane & 15;
+    const int tn = min(tb + 4 * TPW, nt);
+    for (int e = threadIdx.x; e < 8 * N; e += kThreads) pms[e] = g.perm[e];
+    if (threadIdx.x < N) zs[threadIdx.x] = static_cast<float>(Zf[threadIdx.x]);
+    for (int e = threadIdx.x; e < (tn - tb) * 128; e += kThreads)
+        qs[e] = g.orb_q[static_cast<size_t>(toff + tb) * 128 + e];
+    if (threadIdx.x < tn - tb) msk[threadIdx.x] = g.orb_mask[toff + tb + threadIdx.x];
+    // A rows of the wave's tiles: row p of each representative's bins
+    const int tw0 = tb + wv * TPW;
+    AFrag<kM, KE> A[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int t = min(tw0 + j, nt - 1);
+        const int r = max(g.orb_rows[16 * (toff + t) + col], 0);
+        float a[KE];
+        gather_a<kM, KE>(a, Bf + static_cast<size_t>(r) * NN + static_cast<size_t>(p) * N, N, lane);
+        A[j] = make_afrag<kM, KE>(a);
+    }
+    __syncthreads();                                   // tables; every thread of the block
+    int bmask = 0;                                     // operations used by the block's tiles
+    for (int t = 0; t < tn - tb; ++t) bmask |= msk[t];
+#pragma unroll 1
+    for (int o = 0; o < 8; ++o) {
+        if (!((bmask >> o) & 1)) continue;             // uniform over the block
+        const int grp = pms[o * N + p];
+        stage_orbit_b<kM, KE, NT, kTwo>(Braw, Vs0 + static_cast<size_t>(grp) * NN,
+                                        Vs1 + static_cast<size_t>(grp) * NN, pms + o * N,
+                                        zs, zs[grp], al, be, N, n0);
+        __syncthreads();                               // B'_o staged; every thread
+#pragma unroll
+        for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
+            BFrag<kM, KE, NT> B;
+            load_bfrag<kM, KE, NT>(B, Braw + w * kBytes, lane);
+            float* Yw = w ? Y1 : Y0;
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int tl = tw0 + j - tb;           // tile within the block (wave-uniform)
+                if (tw0 + j >= nt || !((msk[tl] >> o) & 1)) continue;
+                const int* qt = qs + (tl * 8 + o) * 16 + 4 * (lane >> 4);
+                fm_f4 c[NT];
+#pragma unroll
+                for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+                mfma_ab<kM, KE, NT>(A[j], B, c);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = qt[r];
+                    if (q < 0) continue;
+                    float* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+#pragma unroll
+                    for (int u = 0; u < NT; ++u) {
+                        const int n = n0 + 16 * u + col;
+                        if (n < N) yrow[n] = c[u][r];
+                    }
+                }
+            }
+        }
+        __syncthreads();                               // B'_o consumed before the next stage
+    }
+}
+
+template <int kM, int KE, int NT, int TPW>
+__global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowState* fs,
+                                                     const double* Z_stage, const double* zw,
+                                                     const float* bins, const float* binsT,
+                                                     YArgs<float> args, int nchunk, int bx,
+                                                     int ngw) {
+    constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
+    constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
+    __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks (two for direct)
+    __shared__ int pms[8 * 128];                      // perm_o (N <= 128)
+    __shared__ float zs[128];                         // Z of the stage
+    __shared__ int qs[4 * TPW * 8 * 16];              // transfers of the block's (tile, o, row)
+    __shared__ int msk[4 * TPW];                      // operation sets of the block's tiles
+    const int gsize = 8 * bx * nchunk;
+    const int id = blockIdx.x;
+    const int gw = (id / (8 * gsize)) * 8 + id % 8;
+    if (gw >= ngw) return;                            // padding of the last 8 work groups
+    const int m = (id % (8 * gsize)) / 8;
+    const int chunk = m % nchunk;
+    const int x = (m / nchunk) % bx;
+    const int i = m / (nchunk * bx);
+    const int G = gw % g.nG;
+    const int ch = (gw / g.nG) % 3;
+    const int f = gw / (g.nG * 3);
+    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
+    const int p = g.porder[8 * G + i];
+    if (p < 0) return;                                // padding of the last patch group
+    const int cc = ch == 0 ? 0 : 1;
+    const int nt = g.orb_nt[cc];
+    const int tb = x * 4 * TPW;
+    if (tb >= nt) return;                             // past this kind's tiles
+    const int N = g.N, NN = g.NN;
+    const int M = ch == 0 ? g.nP : g.nD;
+    const int nR = g.nRp + g.nRd;
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
+                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    const size_t yoff = static_cast<size_t>(f) * M * NN;
+    const int toff = cc == 0 ? 0 : g.orb_nt[0];
+    if (ch == 2)
+        y_orbit_block<kM, KE, NT, TPW, true>(g, Bf, args.Vs[2] + f * N3, args.Vs[3] + f * N3,
+                                             args.Y[2] + yoff, args.Y[3] + yoff, p, tb, nt,
+                                             toff, chunk * 16 * NT, al, be,
+                                             Z_stage + static_cast<size_t>(f) * N, Braw, pms, zs, qs,
+                                             msk);
+    else
+        y_orbit_block<kM, KE, NT, TPW, false>(g, Bf, args.Vs[ch] + f * N3, args.Vs[ch] + f * N3,
+                                              args.Y[ch] + yoff, args.Y[ch] + yoff, p, tb, nt,
+                                              toff, chunk * 16 * NT, al, be,
+                                              Z_stage + static_cast<size_t>(f) * N, Braw, pms, zs,
+                                              qs, msk);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1686,11 +1977,40 @@ void y_mfma_cls(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                        static_cast<int>(nwork));
 }
 
-// yvar 2: the operation-class kernel, else the per-row one.
+template <int kM, int KE, int NT, int TPW>
+void y_mfma_orb_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+                   const YArgs<float>& a) {
+    const int ntmax = g.orb_nt[0] > g.orb_nt[1] ? g.orb_nt[0] : g.orb_nt[1];
+    const int bx = (ntmax + 4 * TPW - 1) / (4 * TPW);
+    const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
+    const long ngw = 3L * g.nG * nf;
+    const long nblocks = (ngw + 7) / 8 * 8 * (8L * bx * nchunk);
+    if (nblocks == 0) return;
+    hipLaunchKernelGGL((k_y_mfma_orb<kM, KE, NT, TPW>), dim3(static_cast<unsigned>(nblocks)),
+                       dim3(kThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
+                       static_cast<const float*>(b.bins),
+                       static_cast<const float*>(b.binsT), a, nchunk, bx,
+                       static_cast<int>(ngw));
+}
+
+// Orbit kernel: tiles per wavefront 1, 2 or (bf16 operands) 4; A stays in registers across
+// the operations.
+template <int kM, int KE, int NT>
+void y_mfma_orb(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
+                const YArgs<float>& a, int tpw) {
+    if constexpr (kM == 1) {
+        if (tpw >= 4) { y_mfma_orb_go<kM, KE, NT, 4>(s, g, b, nf, a); return; }
+    }
+    if (tpw >= 2) y_mfma_orb_go<kM, KE, NT, 2>(s, g, b, nf, a);
+    else y_mfma_orb_go<kM, KE, NT, 1>(s, g, b, nf, a);
+}
+
+// yvar 2: the operation-class kernel, 3: the orbit kernel, else the per-row one.
 template <int kM, int KE, int NT>
 void y_mfma_tpw(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                 const YArgs<float>& a, int tpw, int yvar) {
     if (yvar == 2) y_mfma_cls<kM, KE, NT>(s, g, b, nf, a, tpw);
+    else if (yvar == 3) y_mfma_orb<kM, KE, NT>(s, g, b, nf, a, tpw);
     else y_mfma_rows<kM, KE, NT>(s, g, b, nf, a, tpw);
 }
 
@@ -1797,6 +2117,14 @@ void launch_y(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int n
 int y_rows_max_tpw(const DevGeom& g) {
     const int mmax = g.nP > g.nD ? g.nP : g.nD;
     return ((mmax + 15) / 16 + 3) / 4;
+}
+
+int y_orb_max_tpw(const DevGeom& g, int mma) {
+    const int ntmax = g.orb_nt[0] > g.orb_nt[1] ? g.orb_nt[0] : g.orb_nt[1];
+    const int cap = mma == 2 ? 4 : 2;
+    int t = 1;
+    while (t < cap && 4 * t < ntmax) t *= 2;
+    return t;
 }
 
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,

@@ -77,7 +77,7 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=16, L=32, channels=9), "channel"),
     (dict(N=16, L=32, tile_rows=-1), "tile_rows"),
     (dict(N=16, L=32, flow=2), "bad flow"),
-    (dict(N=16, L=32, y_kernel=3), "y_kernel"),
+    (dict(N=16, L=32, y_kernel=4), "y_kernel"),
     (dict(N=16, L=32, flow="interaction", T0=0.0), "T0 > 0"),
     (dict(N=16, L=32, flow="interaction", T0=0.2, g_end=-1.0), "g_end"),
 ])

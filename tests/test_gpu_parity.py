@@ -88,15 +88,16 @@ def test_rhs_small(torch_dev, prec, N, L, T, state, kw):
     assert rel(got, ref) <= TOL[prec], (prec, N, L, T, state, kw, rel(got, ref))
 
 
-@pytest.mark.parametrize("y_kernel", [1, 2])
+@pytest.mark.parametrize("y_kernel", [1, 2, 3])
 @pytest.mark.parametrize("tile_rows", [1, 2, 3, 100])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("N,L", [(32, 64), (48, 64), (20, 16)])
 def test_rhs_every_phase2a_tile_choice(torch_dev, prec, tile_rows, y_kernel, N, L):
-    """Both matrix-core kernels (per-row gathers; operation classes) at every row-tile count
-    per wavefront, up to all of a group's or class's tiles (100 is clamped), give the
-    oracle's RHS: 12 and more transfer tiles, so runs of 2 and 3 tiles end ragged, classes
-    of uneven size, and N = 20 (not a multiple of 8) for the rows read past their end."""
+    """The three matrix-core kernels (per-row gathers; operation classes; orbits) at every
+    row-tile count per wavefront, up to all of a group's or class's tiles (100 is clamped),
+    give the oracle's RHS: 12 and more transfer tiles, so runs of 2 and 3 tiles end ragged,
+    classes of uneven size, representatives with fewer than eight operations, and N = 20
+    (not a multiple of 8) for the rows read past their end."""
     V = inputs.noisy_state(N, 2.5)
     ref = O.rhs(O.model(N, L), 0.09, V)
     got = gpu_rhs(torch_dev, N, L, 0.09, V, prec, tile_rows=tile_rows, y_kernel=y_kernel)[0]
@@ -131,8 +132,9 @@ def test_rhs_c2_full(torch_dev, prec):
 
 
 @pytest.mark.parametrize("N,L", [(96, 256), (128, 512)])
-@pytest.mark.parametrize("prec,y_kernel", [("fp64", 0), ("fp32", 1), ("fp32", 2), ("bf16", 1),
-                                           ("bf16", 2), ("bf16x3", 1), ("bf16x3", 2)])
+@pytest.mark.parametrize("prec,y_kernel", [("fp64", 0), ("fp32", 1), ("fp32", 2), ("fp32", 3),
+                                           ("bf16", 1), ("bf16", 2), ("bf16", 3), ("bf16x3", 1),
+                                           ("bf16x3", 2), ("bf16x3", 3)])
 def test_rhs_large_sampled(torch_dev, N, L, prec, y_kernel):
     """Full-size grids: sampled outputs against the oracle's per-element sums, with each
     matrix-core phase-2a kernel."""
