@@ -128,8 +128,10 @@ typedef struct {
                                  U* = g*^2 U depends on T alone without Z (0 selects 100) */
     int y_kernel;             /* single-precision phase 2a on matrix cores: 1 gathers each
                                  transfer's permuted bins, 2 stages the operand permuted once
-                                 per point-group operation class; 0 = chosen by timing with
-                                 tile_rows on the first call */
+                                 per point-group operation class, 3 reads each representative's
+                                 bin row once and applies every operation of its orbit to it
+                                 (tile_rows 1, 2, or 4 with bf16 operands); 0 = chosen by
+                                 timing with tile_rows on the first call */
 } fm_config;
 
 typedef struct {

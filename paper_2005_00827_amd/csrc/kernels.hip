@@ -309,8 +309,9 @@ __device__ inline double pair_chi(double xu, double xv, double twoT, bool pp) {
 //   representative's bins in global memory with atomics, after clearing them.
 // ------------------------------------------------------------------------------------
 // Block size of stage and phase 1: 1024 threads for few (flow, representative) pairs, so
-// one flow's bins spread over many waves; 256 when there are many, so several blocks share
-// a CU and one block's fill and drain overlap another's work.
+// one flow's bins spread over many waves, and wherever the LDS bins allow few blocks per
+// CU; otherwise 256, so several blocks share a CU and one block's fill and drain overlap
+// another's work.
 // 16-point units per row whose loads are in flight together
 template <typename R> struct BinBatch;
 template <> struct BinBatch<float> { static constexpr int v = 8; };
@@ -344,16 +345,24 @@ __device__ inline double dpp_f(double v) {
 template <int kCtrl>
 __device__ inline int dpp_i(int v) { return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xf, 0xf, false); }
 
-// One step of the segmented inclusive scan within a 16-lane row: lane s combines with lane
-// s - d (values from the same step), (v1, h1) + (v2, h2) = (h2 ? v2 : v1 + v2, h1 | h2).
+// One step of the segmented inclusive scan within a 16-lane row (Hillis-Steele): lane s adds
+// the partial sum of lane s - D when that lane lies in its own run, i.e. s - D >= st, st the
+// first lane of the run.
 template <int D, typename R>
-__device__ inline void seg_step(R& v, int& h, int s) {
+__device__ inline void seg_step(R& v, int st, int s) {
     const R vp = dpp_f<0x110 | D>(v);   // row_shr:D
-    const int hp = dpp_i<0x110 | D>(h);
-    if (s >= D) {
-        if (!h) v += vp;
-        h |= hp;
-    }
+    if (s - D >= st) v += vp;
+}
+// First lane of each lane's run of equal keys within its 16-lane row: the inclusive prefix
+// maximum of the run heads' lane numbers (row_shr reads 0 past the row's start).
+__device__ inline int run_start(int key, int s) {
+    const int kprev = dpp_i<0x111>(key);   // row_shr:1
+    int st = (s == 0 || kprev != key) ? s : 0;
+    st = max(st, dpp_i<0x111>(st));
+    st = max(st, dpp_i<0x112>(st));
+    st = max(st, dpp_i<0x114>(st));
+    st = max(st, dpp_i<0x118>(st));
+    return st;
 }
 
 // Pairing (exact, halves the weight evaluations): the particle-particle partner map
@@ -424,15 +433,16 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
         for (int i = 0; i < kBinBatch; ++i) {
             const R w = kG ? pair_chi(xu[i], xv[i], tp, pp) : pair_weight(xu[i], xv[i], tp, pp);
             R x = ok[i] ? (kMode == 0 ? w : w * scale) : R(0);
-            const int key = pa[i] * N + pq[i];
-            const int key2 = pp ? pq[i] * N + pa[i] : inv_patch(g, pq[i]) * N + inv_patch(g, pa[i]);
-            const int kprev = dpp_i<0x111>(key);   // row_shr:1
+            // keys < N^2 (24-bit products)
+            const int key = static_cast<int>(__umul24(pa[i], N)) + pq[i];
+            const int key2 = pp ? static_cast<int>(__umul24(pq[i], N)) + pa[i]
+                                : static_cast<int>(__umul24(inv_patch(g, pq[i]), N)) + inv_patch(g, pa[i]);
             const int knext = dpp_i<0x101>(key);   // row_shl:1
-            int h = (s == 0 || kprev != key) ? 1 : 0;
-            seg_step<1>(x, h, s);
-            seg_step<2>(x, h, s);
-            seg_step<4>(x, h, s);
-            seg_step<8>(x, h, s);
+            const int st = run_start(key, s);
+            seg_step<1>(x, st, s);
+            seg_step<2>(x, st, s);
+            seg_step<4>(x, st, s);
+            seg_step<8>(x, st, s);
             if (s == 15 || knext != key) {     // key2 is a bijective function of key
                 atomicAdd(&acc[key], x);
                 if (half) atomicAdd(&acc[key2], x);
@@ -458,6 +468,46 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
         const int u_end = min(u_begin + per_band, nmain);
         auto main_rows = [&](auto kind) {
             constexpr bool kPP = decltype(kind)::value;
+            auto wrap = [&](int v) {
+                if constexpr (kPP) return v + (v < 0 ? L : 0);
+                else return v - (v >= L ? L : 0);
+            };
+            if (upr >= kBinBatch) {
+                // A batch of consecutive units crosses at most one row end: unit u0 + i is
+                // column block cb0 + i of row rr0, or of row rr0 + 1 past the end; the two
+                // rows' offsets are formed once per batch (24-bit products).  Units past the
+                // band's end read the last row (valid addresses, never added).
+                int rr0 = u_begin / upr, cb0 = u_begin - rr0 * upr;
+                for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
+                    const int ra = min(rr0, nrow - 1), rb = min(rr0 + 1, nrow - 1);
+                    const int jya = half ? half_map(hy, ra) : ra;
+                    const int jyb = half ? half_map(hy, rb) : rb;
+                    const int pya = wrap(kPP ? my - jya - 1 : jya + my);
+                    const int pyb = wrap(kPP ? my - jyb - 1 : jyb + my);
+                    const int oa = static_cast<int>(__umul24(jya, L)), ob = static_cast<int>(__umul24(jyb, L));
+                    const int qa = static_cast<int>(__umul24(pya, L)), qb = static_cast<int>(__umul24(pyb, L));
+                    R xu[kBinBatch], xv[kBinBatch];
+                    int pa[kBinBatch], pq[kBinBatch];
+                    bool ok[kBinBatch];
+#pragma unroll
+                    for (int i = 0; i < kBinBatch; ++i) {
+                        const int c = cb0 + i;
+                        const bool nx = c >= upr;
+                        const int jx = ((nx ? c - upr : c) << 4) + s;
+                        const int px = wrap(kPP ? mx - jx - 1 : jx + mx);
+                        xi_patch(g, (nx ? ob : oa) + jx, xu[i], pa[i]);
+                        xi_patch(g, (nx ? qb : qa) + px, xv[i], pq[i]);
+                        ok[i] = u0 + i < u_end;
+                    }
+                    add_batch(xu, xv, pa, pq, ok);
+                    cb0 += kBinBatch;
+                    if (cb0 >= upr) {
+                        cb0 -= upr;
+                        ++rr0;
+                    }
+                }
+                return;
+            }
             for (int u0 = u_begin; u0 < u_begin + per_band; u0 += kBinBatch) {   // same trip count for all rows
                 R xu[kBinBatch], xv[kBinBatch];
                 int pa[kBinBatch], pq[kBinBatch];
@@ -1923,7 +1973,10 @@ template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
              const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
     const int nRb = b.bins ? g.nRp + g.nRd : 0;
-    const bool wide = static_cast<long>(nRb) * bp.n * nf <= 256;
+    // bins in LDS above 40 KB leave room for at most three blocks per CU: 256-thread blocks
+    // would keep three waves or fewer per SIMD to hide the scan's dependent steps
+    const bool big = nRb > 0 && bins_mode<R>(g) == 0 && static_cast<size_t>(g.NN) * sizeof(R) > 40960;
+    const bool wide = static_cast<long>(nRb) * bp.n * nf <= 256 || (big && bp.n > 0);
     if (g.gflow && bp.n > 0) {
         if (wide) stage_go<R, 1024, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
         else stage_go<R, 256, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
