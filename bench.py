@@ -28,7 +28,12 @@ PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6, "bf16_TFs": 2500
 METRIC = "coupling·loop-point updates/s per RHS (N³·L²·3); flows/hour, mixed vs FP64"
 
 
-def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5):
+# Matrix-core peak of each single-precision phase-2a mode (TFLOP/s): split bf16 issues three
+# bf16 products per product.
+MFMA_PEAK = {"fp32": PEAK["fp32_TFs"], "bf16": PEAK["bf16_TFs"], "bf16x3": PEAK["bf16_TFs"] / 3.0}
+
+
+def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5, prec="fp32"):
     """Algorithmic work of one launch of each timed kernel group for one flow.
 
     stage_bins: phase 1 of every stage node of a Dormand-Prince step (nsets = 5 distinct
@@ -38,8 +43,10 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5):
               the point quantities the kernel evaluates on the fly are not counted
     stage:    the stage argument alone: V read (f64), on average four earlier k slots of
               three channel parts read, three operand layouts written
-    y:        (nP + 3 nD) N^3 multiply-adds; bytes = representative bins read (plus the
-              transposed particle-hole bins) + 3 operand slabs read + Y written
+    y:        (nP + 3 nD) N^3 multiply-adds on the matrix cores; bytes = representative
+              bins read (plus the transposed particle-hole bins) + 3 operand slabs read + Y
+              written; bound by whichever roof takes longer at its peak: the matrix cores of
+              the mode `prec` (peak MFMA_PEAK[prec]) or HBM
     contract: 4 N^4 multiply-adds; bytes = Y read + operand read + k written
     """
     NN, N3 = N * N, N ** 3
@@ -50,8 +57,11 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5):
     if name == "stage":
         return {"bound": "hbm", "bytes": N3 * (8 + 4 * 3 * rsize + 3 * rsize)}
     if name == "y":
-        return {"bound": "hbm", "flops": 2.0 * (nP + 3 * nD) * N3,
-                "bytes": (nRp + 2 * nRd) * NN * rsize + 3 * N3 * rsize + (nP + 3 * nD) * NN * rsize}
+        flops = 2.0 * (nP + 3 * nD) * N3
+        nbytes = (nRp + 2 * nRd) * NN * rsize + 3 * N3 * rsize + (nP + 3 * nD) * NN * rsize
+        mma = flops / (MFMA_PEAK[prec] * 1e12) > nbytes / (PEAK["hbm_GBs"] * 1e9)
+        return {"bound": "mfma" if mma else "hbm", "flops": flops, "bytes": nbytes,
+                "peak_TFs": MFMA_PEAK[prec]}
     if name == "contract":
         return {"bound": "hbm", "flops": 8.0 * N ** 4,
                 "bytes": (nP + 3 * nD) * NN * rsize + 2 * N3 * rsize}
@@ -191,11 +201,15 @@ def large_batch(fm, inputs, torch, dev):
             roof = {}
             for name, gid in (("stage_bins", 0), ("y", 1), ("contract", 2), ("stage", 3)):
                 us = f.kernel_time(gid, nf, 10) * 1e3
-                wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd)
+                wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, prec=prec)
                 r = {"avg_us": us}
                 if wk["bound"] == "hbm":
                     r.update(bound="hbm", achieved_GBs=nf * wk["bytes"] / (us * 1e-6) / 1e9)
                     r["frac"] = r["achieved_GBs"] / PEAK["hbm_GBs"]
+                elif wk["bound"] == "mfma":
+                    r.update(bound="mfma", achieved_TFs=nf * wk["flops"] / (us * 1e-6) / 1e12,
+                             hbm_GBs=nf * wk["bytes"] / (us * 1e-6) / 1e9)
+                    r["frac"] = r["achieved_TFs"] / wk["peak_TFs"]
                 else:
                     r.update(bound="alu", pair_evals_per_s=nf * wk["flops"] / 6.0 / 2.0 / (us * 1e-6))
                 roof[name] = r
@@ -302,8 +316,8 @@ def main():
                 k.update(bound="hbm", achieved=wk["bytes"] / avg_s / 1e9, peak=PEAK["hbm_GBs"],
                          unit="GB/s")
             else:
-                k.update(bound="alu", achieved=wk["flops"] / avg_s / 1e12, peak=PEAK["fp32_TFs"],
-                         unit="TFLOP/s")
+                k.update(bound=wk["bound"], achieved=wk["flops"] / avg_s / 1e12,
+                         peak=wk.get("peak_TFs", PEAK["fp32_TFs"]), unit="TFLOP/s")
             k["frac"] = k["achieved"] / k["peak"]
         kernels[name] = k
     # Per-launch durations of the three RHS kernel groups: each launched 200 times back to
@@ -326,7 +340,7 @@ def main():
     if wk["bound"] == "hbm":
         ach, peak, unit = wk["bytes"] / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
     else:
-        ach, peak, unit = wk["flops"] / avg_s / 1e12, PEAK["fp32_TFs"], "TFLOP/s"
+        ach, peak, unit = wk["flops"] / avg_s / 1e12, wk.get("peak_TFs", PEAK["fp32_TFs"]), "TFLOP/s"
     roofline = {"kernel": dom, "bound": wk["bound"], "achieved": ach, "peak": peak, "unit": unit,
                 "frac": ach / peak, "traffic": measured_traffic(dom), "avg_us": replay[dom],
                 "launches_per_flow": kernels[dom].get("launches", 0) / args.steps,
