@@ -305,7 +305,7 @@ __device__ inline double pair_chi(double xu, double xv, double twoT, bool pp) {
 // share their patch pair, so a segmented scan over the row (DPP shifts 1, 2, 4, 8) sums
 // each run of equal keys and only the last lane of a run issues the atomic.  The four
 // rows of a wave work in bands a quarter of the grid apart, so their keys rarely collide.
-//   kMode 0: bins in LDS; kMode 1 (bin matrix above 64 KB): the block accumulates its own
+//   kMode 0: bins in LDS; kMode 1 (bin matrix above 128 KB): the block accumulates its own
 //   representative's bins in global memory with atomics, after clearing them.
 // ------------------------------------------------------------------------------------
 // Block size of stage and phase 1: 1024 threads for few (flow, representative) pairs, so
@@ -598,6 +598,19 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
     R* outT = pp ? nullptr : binsT + (static_cast<size_t>(f) * g.nRd + (r - g.nRp)) * NN;
+    if (kMode == 0 && outT && N % 16 == 0) {
+        // the transpose in chunks of 16 rows x 4 columns of outT per wave: LDS reads of 4 bin
+        // rows x 16 consecutive values (a column walk of stride N would put a whole wave on
+        // one bank when N is a multiple of 32), 16-byte or wider segments written
+        const int ng = N >> 2;
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+            out[i] = lb[i] * scale;
+            const int c = i >> 6, l = i & 63;
+            const int bg = c / ng, aa = ((c - bg * ng) << 2) + (l & 3), bb = (bg << 4) + (l >> 2);
+            outT[bb * N + aa] = lb[aa * N + bb] * scale;
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
         const int bb = i / N, aa = i - bb * N;
         if (kMode == 0) {
@@ -1937,7 +1950,8 @@ R* kslot_ptr(const Buffers& b, int slot, size_t N3) {   // slot base: [flow][cha
 
 template <typename R>
 int bins_mode(const DevGeom& g) {
-    return static_cast<size_t>(g.NN) * sizeof(R) <= 65536 ? 0 : 1;
+    // a gfx950 CU has 160 KB of LDS, and one work group may take up to 128 KB of it here
+    return static_cast<size_t>(g.NN) * sizeof(R) <= 131072 ? 0 : 1;
 }
 
 // Stage argument plus, when the plan has nodes, their phase 1 in one launch.
