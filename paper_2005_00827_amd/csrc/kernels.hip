@@ -1278,7 +1278,8 @@ __device__ inline void load_bfrag(BFrag<kM, KE, NT>& B, const void* Bsv, int lan
     }
 }
 
-// c += A B with both operands in registers (the fragment layouts of mfma_tile_f).
+// c += A B with both operands in registers (the fragment layouts of mfma_tile_f): lane holds
+// rows 4 (lane / 16) .. + 3 of column lane % 16 of each 16 x 16 tile c[t].
 template <int kM, int KE, int NT>
 __device__ inline void mfma_ab(const AFrag<kM, KE>& A, const BFrag<kM, KE, NT>& B, fm_f4 (&c)[NT]) {
     if constexpr (kM > 0) {
@@ -1298,6 +1299,33 @@ __device__ inline void mfma_ab(const AFrag<kM, KE>& A, const BFrag<kM, KE, NT>& 
 #pragma unroll
             for (int t = 0; t < NT; ++t)
                 c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[e], B.b[e][t], c[t], 0, 0, 0);
+    }
+}
+
+// c += (A B)^T with both operands in registers (the fragment layouts of mfma_tile_f).  The A
+// and B fragments of these shapes have the same lane layout (lane % 16 the row of A or the
+// column of B, lane / 16 the k group), so passing B first gives the transposed tile: lane
+// holds rows 4 (lane / 16) .. + 3 of column lane % 16 of c[t] = (A B)^T, i.e. four
+// consecutive n of row tile row lane % 16.
+template <int kM, int KE, int NT>
+__device__ inline void mfma_abt(const AFrag<kM, KE>& A, const BFrag<kM, KE, NT>& B, fm_f4 (&c)[NT]) {
+    if constexpr (kM > 0) {
+#pragma unroll
+        for (int s = 0; s < KE / 8; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (kM == 2) {
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.h[s][t], A.l[s], c[t], 0, 0, 0);
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.l[s][t], A.h[s], c[t], 0, 0, 0);
+                }
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.h[s][t], A.h[s], c[t], 0, 0, 0);
+            }
+    } else {
+#pragma unroll
+        for (int e = 0; e < KE; ++e)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(B.b[e][t], A.a[e], c[t], 0, 0, 0);
     }
 }
 
@@ -1424,20 +1452,44 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
             for (int j = 0; j < TPW; ++j) {
                 const int tl = tw0 + j - tb;           // tile within the block (wave-uniform)
                 if (tw0 + j >= nt || !((msk[tl] >> o) & 1)) continue;
-                const int* qt = qs + (tl * 8 + o) * 16 + 4 * (lane >> 4);
                 fm_f4 c[NT];
 #pragma unroll
                 for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
-                mfma_ab<kM, KE, NT>(A[j], B, c);
+                if constexpr (kM == 0) {
+                    // f32 operands: the untransposed tile (fewer registers live here), one
+                    // value per store
+                    mfma_ab<kM, KE, NT>(A[j], B, c);
+                    const int* qt = qs + (tl * 8 + o) * 16 + 4 * (lane >> 4);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = qt[r];
-                    if (q < 0) continue;
+                    for (int r = 0; r < 4; ++r) {
+                        const int q = qt[r];
+                        if (q < 0) continue;
+                        float* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+#pragma unroll
+                        for (int u = 0; u < NT; ++u) {
+                            const int n = n0 + 16 * u + col;
+                            if (n < N) yrow[n] = c[u][r];
+                        }
+                    }
+                    continue;
+                }
+                const int q = qs[(tl * 8 + o) * 16 + col];
+                mfma_abt<kM, KE, NT>(A[j], B, c);
+                // four consecutive n of transfer q per lane: one 16-byte store when N % 4 == 0
+                // (rows then start 16-byte aligned and a group of four lies wholly below N or
+                // at or above it), else one value at a time
+                if (q >= 0) {
                     float* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
 #pragma unroll
                     for (int u = 0; u < NT; ++u) {
-                        const int n = n0 + 16 * u + col;
-                        if (n < N) yrow[n] = c[u][r];
+                        const int n = n0 + 16 * u + 4 * (lane >> 4);
+                        if ((N & 3) == 0) {
+                            if (n < N) *reinterpret_cast<fm_f4*>(yrow + n) = c[u];
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (n + r < N) yrow[n + r] = c[u][r];
+                        }
                     }
                 }
             }

@@ -88,6 +88,20 @@ def test_rhs_small(torch_dev, prec, N, L, T, state, kw):
     assert rel(got, ref) <= TOL[prec], (prec, N, L, T, state, kw, rel(got, ref))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("N,L,T,state,kw", RHS_CASES)
+def test_rhs_small_orbit_kernel(torch_dev, prec, N, L, T, state, kw):
+    """The orbit phase-2a kernel forced on every small case: N = 1 (stores one value at a
+    time), identity geometries (every operation set trivial), channel subsets, ragged N."""
+    V = make_state(state, N)
+    ref = O.rhs(oracle_model(N, L, **kw), T, V)
+    got = gpu_rhs(torch_dev, N, L, T, V, prec, y_kernel=3, **kw)[0]
+    if np.abs(ref).max() < 1e-13:
+        assert np.abs(got).max() < 1e-12
+        return
+    assert rel(got, ref) <= TOL[prec], (prec, N, L, T, state, kw, rel(got, ref))
+
+
 @pytest.mark.parametrize("y_kernel", [1, 2, 3])
 @pytest.mark.parametrize("tile_rows", [1, 2, 3, 100])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
