@@ -128,14 +128,52 @@ __device__ inline R kval(const R* K, int l, int B, int f, size_t N3, size_t i) {
 //   interaction flow (s = -g, lines G_g = g Z G0 and S_g = Z^2 G0, App. A, Step 2):
 //   al = 0, be = s = -g, with bins of chi, so that the product is dV/ds = -dV/dg.
 // ------------------------------------------------------------------------------------
+// The stage elements of one thread with NS earlier stages: all 3 NS k loads and the V load of
+// an element are in flight together, then summed as kval and the l loop would.
+template <int NS, typename R>
+__device__ inline void stage_elems(const DevGeom& g, const StageCoef& sc, double ht, int f,
+                                   int write_new, const double* Vf, const R* K, double* Vnew,
+                                   R* v0, R* va, R* vc, int B, size_t i0, size_t stride) {
+    const int N = g.N, NN = g.NN;
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    for (size_t i = i0; i < N3; i += stride) {
+        R kv[NS > 0 ? NS : 1][3];
+#pragma unroll
+        for (int l = 0; l < NS; ++l) {
+            const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3 + i;
+            kv[l][0] = p[0];
+            kv[l][1] = p[N3];
+            kv[l][2] = p[2 * N3];
+        }
+        const double vb = Vf[i];
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < NS; ++l) {
+            R s3 = kv[l][0];
+            s3 += kv[l][1];
+            s3 += kv[l][2];
+            acc += sc.a[l] * static_cast<double>(s3);
+        }
+        const double v = vb + ht * acc;
+        if (write_new) Vnew[f * N3 + i] = v;
+        const int x = static_cast<int>(i / NN);
+        const int y = static_cast<int>((i / N) % N);
+        const int zz = static_cast<int>(i % N);
+        const R r = static_cast<R>(v);
+        v0[f * N3 + i] = r;
+        va[f * N3 + static_cast<size_t>(zz) * NN + x * N + y] = r;
+        vc[f * N3 + static_cast<size_t>(zz) * NN + y * N + x] = r;
+    }
+}
+
 template <typename R>
 __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowState& st, int f,
                                   const StageCoef& sc, int write_new, const double* Vbase,
                                   const R* K, double* Vnew, R* v0, R* va, R* vc,
                                   double* T_stage, double* Z_stage, double* zw, int B, int blk,
                                   int nblk) {
-    const int N = g.N, NN = g.NN;
-    const size_t N3 = static_cast<size_t>(NN) * N;
+    const int N = g.N;
+    const size_t N3 = static_cast<size_t>(g.NN) * N;
     const double ht = st.ht;
     const double lnTs = st.lnT + sc.c * ht;
     if (blk == 0) {
@@ -149,20 +187,18 @@ __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowSta
     }
     const double* Vf = Vbase + f * N3;
     const size_t stride = static_cast<size_t>(nblk) * blockDim.x;
-    for (size_t i = blk * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3; i += stride) {
-        double acc = 0.0;
-        for (int l = 0; l < sc.ns; ++l) acc += sc.a[l] * static_cast<double>(kval(K, l, B, f, N3, i));
-        const double v = Vf[i] + ht * acc;
-        if (write_new) Vnew[f * N3 + i] = v;
-        const int x = static_cast<int>(i / NN);
-        const int y = static_cast<int>((i / N) % N);
-        const int zz = static_cast<int>(i % N);
-        const R r = static_cast<R>(v);
-        v0[f * N3 + i] = r;
-        va[f * N3 + static_cast<size_t>(zz) * NN + x * N + y] = r;
-        vc[f * N3 + static_cast<size_t>(zz) * NN + y * N + x] = r;
+    const size_t i0 = blk * static_cast<size_t>(blockDim.x) + threadIdx.x;
+    switch (sc.ns) {                                   // uniform: earlier stages of this stage
+    case 0: stage_elems<0>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    case 1: stage_elems<1>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    case 2: stage_elems<2>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    case 3: stage_elems<3>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    case 4: stage_elems<4>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    case 5: stage_elems<5>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    default: stage_elems<6>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
     }
 }
+
 
 // Point quantities at the stage temperature, a = xi / 2T (single precision: xi rounded to
 // float times 1/2T rounded to float):
@@ -900,13 +936,17 @@ __device__ inline void gather_rows(float (&a)[KE], const float* Bf, int NN, int 
                                 float al, float be, int lane) {
     const int* pi = pis + op * N;
     const float* row = Bf + static_cast<size_t>(rep) * NN + pi[grp] * N;
+    // all permutation entries, then all loads in flight together, then the Z factors
+    int col[KE];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) col[e] = pi[min(mfma_k<kM>(e, lane), N - 1)];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) a[e] = row[col[e]];
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
         const int k = mfma_k<kM>(e, lane);
-        const int kc = min(k, N - 1);
-        const float x = row[pi[kc]];
-        const float zk = zs[kc];
-        a[e] = k < N ? x * (zg * zk * (al + be * (zg + zk))) : 0.f;
+        const float zk = zs[min(k, N - 1)];
+        a[e] = k < N ? a[e] * (zg * zk * (al + be * (zg + zk))) : 0.f;
     }
 }
 
@@ -1004,18 +1044,47 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     int r0, o0, r1, o1;
     tile_rep(qrep, qg, M, t_begin, lane & 15, r0, o0);
     tile_rep(qrep, qg, M, t_begin + 1, lane & 15, r1, o1);
-    for (int i = threadIdx.x; i < 8 * N; i += kThreads) pis[i] = g.pinv[i];
-    if (threadIdx.x < N) zs[threadIdx.x] = static_cast<float>(Z_stage[static_cast<size_t>(f) * N + threadIdx.x]);
+    const int nR = g.nRp + g.nRd;
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
+                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    // The permutation table, Z and the B chunk: every load in flight before any LDS store
+    // (one round trip instead of one per element).
+    int pv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pv[v] = g.pinv[min(static_cast<int>(threadIdx.x) + v * kThreads, 8 * N - 1)];
+    const float zv = static_cast<float>(Z_stage[static_cast<size_t>(f) * N + min(static_cast<int>(threadIdx.x), N - 1)]);
     const size_t N3 = static_cast<size_t>(NN) * N;
     const size_t slab = f * N3 + static_cast<size_t>(grp) * NN;
     const float* V0 = args.Vs[two ? 2 : ch] + slab;
     const float* V1 = args.Vs[3] + slab;
-    for (int e = threadIdx.x; e < KP * W; e += kThreads) {
+    // B chunk: every element's load in flight before any is stored
+    constexpr int kPer = KP * W / kThreads;
+    static_assert(KP * W % kThreads == 0, "staging covers the chunk in whole rounds");
+    float sv0[kPer], sv1[kPer];
+    auto stage_index = [&](int j) {
+        const int e = threadIdx.x + j * kThreads;
         const int k = e / W, n = e - k * W;            // W is a compile-time constant
+        return static_cast<size_t>(min(k, N - 1)) * N + min(n0 + n, N - 1);
+    };
+    // the second operand only for the direct channel; elsewhere the same loads repeat the
+    // first one's addresses (cache hits, no branch between the loads)
+    const float* V1s = two ? V1 : V0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        sv0[j] = V0[stage_index(j)];
+        sv1[j] = V1s[stage_index(j)];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)          // the permutation table (8 N <= 1024 entries)
+        if (static_cast<int>(threadIdx.x) + v * kThreads < 8 * N) pis[threadIdx.x + v * kThreads] = pv[v];
+    if (threadIdx.x < N) zs[threadIdx.x] = zv;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        const int k = e / W, n = e - k * W;
         const bool ok = k < N && n0 + n < N;
-        const size_t ia = static_cast<size_t>(min(k, N - 1)) * N + min(n0 + n, N - 1);
-        const float x0 = ok ? V0[ia] : 0.f;
-        const float x1 = (two && ok) ? V1[ia] : 0.f;
+        const float x0 = ok ? sv0[j] : 0.f;
+        const float x1 = (two && ok) ? sv1[j] : 0.f;
         if constexpr (kM > 0) {
             __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
             const __bf16 h0 = static_cast<__bf16>(x0), h1 = static_cast<__bf16>(x1);
@@ -1033,9 +1102,6 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     }
     __syncthreads();                                   // every thread of the block
     if (t_begin >= t_end) return;
-    const int nR = g.nRp + g.nRd;
-    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
-                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     const void* B0 = Braw;
     const void* B1 = Braw + kBytes;
@@ -1580,6 +1646,11 @@ __device__ __attribute__((always_inline)) inline void contract_item(
     const int* pairs, int cnt, R* vu, R* vw, R* Kf) {
     constexpr int G = KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v;
     const int N = g.N, NN = g.NN;
+    // the item's output pairs, read once with the first loads (the stores at the end would
+    // otherwise each wait for their pair's load)
+    int pr[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) pr[i] = pairs[min(i, cnt - 1)];
     for (int n0 = 0; n0 < N; n0 += 64) {
         const int n = min(n0 + static_cast<int>(threadIdx.x), N - 1);
         R acc[kChunk];
@@ -1649,7 +1720,7 @@ __device__ __attribute__((always_inline)) inline void contract_item(
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
             if (i >= cnt) break;
-            const int xy = pairs[i];
+            const int xy = pr[i];
             const int a = xy / N, c = xy - a * N;
             if (KIND == 0) Kf[static_cast<size_t>(xy) * N + n] = -acc[i];
             else if (KIND == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = acc[i];
