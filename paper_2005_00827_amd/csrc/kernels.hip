@@ -1030,7 +1030,6 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     const int grp = (work / bx) % N;
     const int ch = (work / (bx * N)) % 3;
     const int f = work / (bx * N * 3);
-    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
     const int M = ch == 0 ? g.nP : g.nD;
     const int n0 = chunk * W;
     const int ntiles = (M + 15) / 16;
@@ -1040,10 +1039,12 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     const bool two = ch == 2;
     const int* qrep = ch == 0 ? g.qrep_pp : g.qrep_ph;
     const int* qg = ch == 0 ? g.qg_pp : g.qg_ph;
-    // the first two tiles' transfer tables need no LDS: in flight across the barrier
+    // the first two tiles' transfer tables need no LDS: loaded with the flow's status and in
+    // flight across the barrier
     int r0, o0, r1, o1;
     tile_rep(qrep, qg, M, t_begin, lane & 15, r0, o0);
     tile_rep(qrep, qg, M, t_begin + 1, lane & 15, r1, o1);
+    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
     const int nR = g.nRp + g.nRd;
     const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
                               : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
@@ -1482,22 +1483,39 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int col = lane & 15;
     const int tn = min(tb + 4 * TPW, nt);
-    for (int e = threadIdx.x; e < 8 * N; e += kThreads) pms[e] = g.perm[e];
-    if (threadIdx.x < N) zs[threadIdx.x] = static_cast<float>(Zf[threadIdx.x]);
-    for (int e = threadIdx.x; e < (tn - tb) * 128; e += kThreads)
-        qs[e] = g.orb_q[static_cast<size_t>(toff + tb) * 128 + e];
-    if (threadIdx.x < tn - tb) msk[threadIdx.x] = g.orb_mask[toff + tb + threadIdx.x];
-    // A rows of the wave's tiles: row p of each representative's bins
     const int tw0 = tb + wv * TPW;
+    // Loads in dependency order, each group in flight together: the representatives of the
+    // wave's tiles, the block's tables (permutations, transfers, operation sets, Z), then the
+    // A rows (row p of each representative's bins), which need the representatives.
+    int rr[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) rr[j] = g.orb_rows[16 * (toff + min(tw0 + j, nt - 1)) + col];
+    int pv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pv[v] = g.perm[min(static_cast<int>(threadIdx.x) + v * kThreads, 8 * N - 1)];
+    constexpr int kQ = 4 * TPW * 128 / kThreads;
+    const int nq = (tn - tb) * 128;
+    const int* qsrc = g.orb_q + static_cast<size_t>(toff + tb) * 128;
+    int qv[kQ];
+#pragma unroll
+    for (int v = 0; v < kQ; ++v) qv[v] = qsrc[min(static_cast<int>(threadIdx.x) + v * kThreads, nq - 1)];
+    const int mv = g.orb_mask[toff + tb + min(static_cast<int>(threadIdx.x), tn - tb - 1)];
+    const float zv = static_cast<float>(Zf[min(static_cast<int>(threadIdx.x), N - 1)]);
+    float a[TPW][KE];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+        gather_a<kM, KE>(a[j], Bf + static_cast<size_t>(max(rr[j], 0)) * NN + static_cast<size_t>(p) * N, N, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        if (static_cast<int>(threadIdx.x) + v * kThreads < 8 * N) pms[threadIdx.x + v * kThreads] = pv[v];
+#pragma unroll
+    for (int v = 0; v < kQ; ++v)
+        if (static_cast<int>(threadIdx.x) + v * kThreads < nq) qs[threadIdx.x + v * kThreads] = qv[v];
+    if (static_cast<int>(threadIdx.x) < tn - tb) msk[threadIdx.x] = mv;
+    if (static_cast<int>(threadIdx.x) < N) zs[threadIdx.x] = zv;
     AFrag<kM, KE> A[TPW];
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-        const int t = min(tw0 + j, nt - 1);
-        const int r = max(g.orb_rows[16 * (toff + t) + col], 0);
-        float a[KE];
-        gather_a<kM, KE>(a, Bf + static_cast<size_t>(r) * NN + static_cast<size_t>(p) * N, N, lane);
-        A[j] = make_afrag<kM, KE>(a);
-    }
+    for (int j = 0; j < TPW; ++j) A[j] = make_afrag<kM, KE>(a[j]);
     __syncthreads();                                   // tables; every thread of the block
     int bmask = 0;                                     // operations used by the block's tiles
     for (int t = 0; t < tn - tb; ++t) bmask |= msk[t];
@@ -1588,8 +1606,8 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
     const int G = gw % g.nG;
     const int ch = (gw / g.nG) % 3;
     const int f = gw / (g.nG * 3);
+    const int p = g.porder[8 * G + i];                // loaded with the flow's status
     if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
-    const int p = g.porder[8 * G + i];
     if (p < 0) return;                                // padding of the last patch group
     const int cc = ch == 0 ? 0 : 1;
     const int nt = g.orb_nt[cc];
