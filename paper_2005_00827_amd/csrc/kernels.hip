@@ -206,9 +206,6 @@ __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowSta
 // where phi(u) = u sech^2 u, phi' = s (1 - 2 a tau) and the third derivative
 //   phi3 = s (-6 (1 - 3 tau^2) + 8 a tau (2 - 3 tau^2)),  s = sech^2 a, tau = tanh a,
 // with s and tau from e = exp(-2|a|) <= 1 (no overflow): s = 4e/(1+e)^2, |tau| = (1-e)/(1+e).
-template <typename R> struct PtT;
-template <> struct PtT<float> { using T = float4; };
-template <> struct PtT<double> { using T = double2; };
 
 __device__ inline float4 point_q(float xi, float inv2T) {
     const float a = xi * inv2T;
@@ -431,18 +428,29 @@ __device__ inline int inv_patch(const DevGeom& g, int a) {
 }
 
 // kG = 1: interaction-flow bins, chi = tanh[a,b]/4T, stored scaled by +1/(4 T L^2).
-template <typename R, int kMode, int BT, int kG>
-__device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bins, R* binsT,
+// NODES > 1 (bins in LDS): the block bins one representative at nn <= NODES stage
+// temperatures T[0..nn) at once, one LDS bin matrix each: the loads, indices, keys and run
+// starts of a pair serve every node, only the weights, scans and atomics are per node.
+// bins / binsT point to the first node's set; consecutive nodes' sets are set_bins /
+// set_binsT values apart.
+template <typename R, int kMode, int BT, int kG, int NODES>
+__device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&T)[NODES],
+                                 int nn, R* bins, R* binsT, size_t set_bins, size_t set_binsT,
                                  R* lb) {
-    using PT = typename PtT<R>::T;
+    static_assert(kMode == 0 || NODES == 1, "several nodes per block need the LDS bins");
     const int N = g.N, NN = g.NN, L = g.L, np = g.np;
     const int nR = g.nRp + g.nRd;
     const bool pp = r < g.nRp;
     const int m = pp ? g.rep_pp[r] : g.rep_ph[r - g.nRp];
     const int mx = m % L, my = m / L;
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
-    const R scale = static_cast<R>((kG ? 1.0 : -1.0) / (4.0 * T * np));
-    const R tp = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * T) : 2.0 * T);   // 1/2T or 2T
+    R scale[NODES], tp[NODES];
+#pragma unroll
+    for (int j = 0; j < NODES; ++j) {
+        const double Tj = T[j];
+        scale[j] = static_cast<R>((kG ? 1.0 : -1.0) / (4.0 * Tj * np));
+        tp[j] = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * Tj) : 2.0 * Tj);   // 1/2T or 2T
+    }
     constexpr int kBinBatch = BinBatch<R>::v;
     const bool half = (pp || g.inv_ok) && L % 2 == 0;
     const Half hy = half_of(pp ? my : L - my, L), hx = half_of(pp ? mx : L - mx, L);
@@ -450,8 +458,8 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int ncol = hx.h1 + hx.h2;                        // columns visited in a fixed row
     const int npt = nrow * L + (half ? hy.nfix * ncol : 0);
     const float invL = 1.0f / static_cast<float>(L);
-    R* acc = kMode == 0 ? lb : out;
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) acc[i] = R(0);
+    R* acc = kMode == 0 ? lb : out;                   // node j: acc + j NN (LDS)
+    for (int i = threadIdx.x; i < nn * NN; i += blockDim.x) acc[i] = R(0);
     if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
     // BT/16 rows of 16 lanes per block; row rr works on band rr of BT/16 contiguous bands of
@@ -462,26 +470,35 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
     const int band = (lane >> 4) * (BT / 64) + wv;
     // Weights of one batch (kBinBatch points per lane), the segmented scan of equal keys
     // within each 16-lane row, and one atomic per run of equal keys (two under the pairing).
+    auto weight = [&](R xa, R xb, int j) -> R {
+        return kG ? pair_chi(xa, xb, tp[j], pp) : pair_weight(xa, xb, tp[j], pp);
+    };
     auto add_batch = [&](const R (&xu)[kBinBatch], const R (&xv)[kBinBatch],
                          const int (&pa)[kBinBatch], const int (&pq)[kBinBatch],
                          const bool (&ok)[kBinBatch]) {
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
-            const R w = kG ? pair_chi(xu[i], xv[i], tp, pp) : pair_weight(xu[i], xv[i], tp, pp);
-            R x = ok[i] ? (kMode == 0 ? w : w * scale) : R(0);
             // keys < N^2 (24-bit products)
             const int key = static_cast<int>(__umul24(pa[i], N)) + pq[i];
             const int key2 = pp ? static_cast<int>(__umul24(pq[i], N)) + pa[i]
                                 : static_cast<int>(__umul24(inv_patch(g, pq[i]), N)) + inv_patch(g, pa[i]);
             const int knext = dpp_i<0x101>(key);   // row_shl:1
             const int st = run_start(key, s);
-            seg_step<1>(x, st, s);
-            seg_step<2>(x, st, s);
-            seg_step<4>(x, st, s);
-            seg_step<8>(x, st, s);
-            if (s == 15 || knext != key) {     // key2 is a bijective function of key
-                atomicAdd(&acc[key], x);
-                if (half) atomicAdd(&acc[key2], x);
+            const bool end = s == 15 || knext != key;   // key2 is a bijective function of key
+#pragma unroll
+            for (int j = 0; j < NODES; ++j) {
+                if (j >= nn) break;                    // uniform over the block
+                const R w = weight(xu[i], xv[i], j);
+                R x = ok[i] ? (kMode == 0 ? w : w * scale[j]) : R(0);
+                seg_step<1>(x, st, s);
+                seg_step<2>(x, st, s);
+                seg_step<4>(x, st, s);
+                seg_step<8>(x, st, s);
+                if (end) {
+                    R* aj = acc + j * NN;
+                    atomicAdd(&aj[key], x);
+                    if (half) atomicAdd(&aj[key2], x);
+                }
             }
         }
     };
@@ -584,10 +601,15 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
                 int qa, qb;
                 xi_patch(g, jy * L + jx, xa, qa);
                 xi_patch(g, py * L + px, xb, qb);
-                const R w = kG ? pair_chi(xa, xb, tp, pp) : pair_weight(xa, xb, tp, pp);
-                const R x = kMode == 0 ? w : w * scale;
-                atomicAdd(&acc[qa * N + qb], x);
-                atomicAdd(&acc[pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa)], x);
+                const int k1 = qa * N + qb, k2 = pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa);
+#pragma unroll
+                for (int j = 0; j < NODES; ++j) {
+                    if (j >= nn) break;                // uniform over the block
+                    const R w = weight(xa, xb, j);
+                    const R x = kMode == 0 ? w : w * scale[j];
+                    atomicAdd(&acc[j * NN + k1], x);
+                    atomicAdd(&acc[j * NN + k2], x);
+                }
             }
     } else {
         // any L: visited rows and fixed rows as one numbered list of points
@@ -628,41 +650,53 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, double T, R* bi
         int qa, qb;
         xi_patch(g, jy * L + jx, xa, qa);
         xi_patch(g, py * L + px, xb, qb);
-        const R w = kG ? pair_chi(xa, xb, tp, pp) : pair_weight(xa, xb, tp, pp);
-        atomicAdd(&acc[qa * N + qb], kMode == 0 ? w : w * scale);
+#pragma unroll
+        for (int j = 0; j < NODES; ++j) {
+            if (j >= nn) break;                        // uniform over the block
+            const R w = weight(xa, xb, j);
+            atomicAdd(&acc[j * NN + qa * N + qb], kMode == 0 ? w : w * scale[j]);
+        }
     }
     if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
     R* outT = pp ? nullptr : binsT + (static_cast<size_t>(f) * g.nRd + (r - g.nRp)) * NN;
-    if (kMode == 0 && outT && N % 16 == 0) {
-        // the transpose in chunks of 16 rows x 4 columns of outT per wave: LDS reads of 4 bin
-        // rows x 16 consecutive values (a column walk of stride N would put a whole wave on
-        // one bank when N is a multiple of 32), 16-byte or wider segments written
-        const int ng = N >> 2;
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            out[i] = lb[i] * scale;
-            const int c = i >> 6, l = i & 63;
-            const int bg = c / ng, aa = ((c - bg * ng) << 2) + (l & 3), bb = (bg << 4) + (l >> 2);
-            outT[bb * N + aa] = lb[aa * N + bb] * scale;
+#pragma unroll
+    for (int j = 0; j < NODES; ++j) {
+        if (j >= nn) break;                            // uniform over the block
+        R* oj = out + j * set_bins;
+        R* oTj = outT ? outT + j * set_binsT : nullptr;
+        const R* lj = lb + j * NN;
+        if (kMode == 0 && oTj && N % 16 == 0) {
+            // the transpose in chunks of 16 rows x 4 columns of outT per wave: LDS reads of 4
+            // bin rows x 16 consecutive values (a column walk of stride N would put a whole
+            // wave on one bank when N is a multiple of 32), 16-byte or wider segments written
+            const int ng = N >> 2;
+            for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+                oj[i] = lj[i] * scale[j];
+                const int c = i >> 6, l = i & 63;
+                const int bg = c / ng, aa = ((c - bg * ng) << 2) + (l & 3), bb = (bg << 4) + (l >> 2);
+                oTj[bb * N + aa] = lj[aa * N + bb] * scale[j];
+            }
+            continue;
         }
-        return;
-    }
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        const int bb = i / N, aa = i - bb * N;
-        if (kMode == 0) {
-            out[i] = lb[i] * scale;
-            if (outT) outT[i] = lb[aa * N + bb] * scale;
-        } else if (outT) {
-            outT[i] = out[aa * N + bb];
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+            const int bb = i / N, aa = i - bb * N;
+            if (kMode == 0) {
+                oj[i] = lj[i] * scale[j];
+                if (oTj) oTj[i] = lj[aa * N + bb] * scale[j];
+            } else if (oTj) {
+                oTj[i] = oj[aa * N + bb];
+            }
         }
     }
 }
 
-// One launch per stage: blocks [0, nRb bp.n) bin the representatives (phase 1, which needs
-// only T) at every node of the plan -- the first stage of an integrator step bins all the
-// step's distinct nodes at once, the later stages none -- and the remaining blocks form the
-// stage argument and its operand layouts.  Grid (nRb bp.n + stage blocks, flows).
-template <typename R, int kMode, int BT, int kG>
+// One launch per stage: blocks [0, nRb ceil(bp.n / NODES)) bin the representatives (phase
+// 1, which needs only T) at every node of the plan, NODES consecutive nodes per block -- the
+// first stage of an integrator step bins all the step's distinct nodes at once, the later
+// stages none -- and the remaining blocks form the stage argument and its operand layouts.
+// Grid (nRb ceil(bp.n / NODES) + stage blocks, flows).
+template <typename R, int kMode, int BT, int kG, int NODES>
 __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
                                                             StageCoef sc, BinPlan bp,
                                                             int write_new, const double* Vbase,
@@ -674,15 +708,20 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
     const int f = blockIdx.y;
     if (!running(fs, f)) return;                      // uniform over the block
     const FlowState st = fs[f];
-    const int nbin = nRb * bp.n;
+    const int nbin = nRb * ((bp.n + NODES - 1) / NODES);
     if (static_cast<int>(blockIdx.x) < nbin) {
-        const int set = static_cast<int>(blockIdx.x) / nRb;
-        const int r = static_cast<int>(blockIdx.x) - set * nRb;
-        const double T = kG ? st.Tfix : exp(st.lnT + bp.c[set] * st.ht);
+        const int grp = static_cast<int>(blockIdx.x) / nRb;
+        const int r = static_cast<int>(blockIdx.x) - grp * nRb;
+        const int set0 = grp * NODES;
+        const int nn = min(NODES, bp.n - set0);
+        double T[NODES];
+#pragma unroll
+        for (int j = 0; j < NODES; ++j)
+            T[j] = kG ? st.Tfix : exp(st.lnT + bp.c[min(set0 + j, bp.n - 1)] * st.ht);
         const size_t NN = static_cast<size_t>(g.NN);
-        bins_part<R, kMode, BT, kG>(g, f, r, T, bins + static_cast<size_t>(set) * B * nRb * NN,
-                                binsT + static_cast<size_t>(set) * B * g.nRd * NN,
-                                reinterpret_cast<R*>(smem_raw));
+        const size_t sb = static_cast<size_t>(B) * nRb * NN, sbT = static_cast<size_t>(B) * g.nRd * NN;
+        bins_part<R, kMode, BT, kG, NODES>(g, f, r, T, nn, bins + set0 * sb, binsT + set0 * sbT,
+                                           sb, sbT, reinterpret_cast<R*>(smem_raw));
     } else {
         stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
                       zw, B, blockIdx.x - nbin, gridDim.x - nbin);
@@ -2096,49 +2135,73 @@ int bins_mode(const DevGeom& g) {
 }
 
 // Stage argument plus, when the plan has nodes, their phase 1 in one launch.
-template <typename R, int BT, int kG>
+template <typename R, int BT, int kG, int NODES>
 void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
               const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase,
               int nRb, int ept) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
     size_t ns = (N3 + static_cast<size_t>(BT) * ept - 1) / (static_cast<size_t>(BT) * ept);
     ns = ns > 1024 ? 1024 : ns;
-    const int nbin = nRb * bp.n;
+    const int nbin = nRb * ((bp.n + NODES - 1) / NODES);
     const dim3 grid(static_cast<unsigned>(nbin + ns), nf);
     const bool lds = nbin > 0 && bins_mode<R>(g) == 0;
-    const size_t shm = lds ? static_cast<size_t>(g.NN) * sizeof(R) : 0;
+    const int per_block = bp.n < NODES ? bp.n : NODES;   // bin matrices a block holds
+    const size_t shm = lds ? static_cast<size_t>(per_block) * g.NN * sizeof(R) : 0;
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
     if (nbin == 0 || lds)
-        hipLaunchKernelGGL((k_stage_bins<R, 0, BT, kG>), grid, dim3(BT), shm, s, g, z, b.fs, sc,
-                           bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+        hipLaunchKernelGGL((k_stage_bins<R, 0, BT, kG, NODES>), grid, dim3(BT), shm, s, g, z, b.fs,
+                           sc, bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride);
-    else
-        hipLaunchKernelGGL((k_stage_bins<R, 1, BT, kG>), grid, dim3(BT), 0, s, g, z, b.fs, sc,
+    else if constexpr (NODES == 1)
+        hipLaunchKernelGGL((k_stage_bins<R, 1, BT, kG, 1>), grid, dim3(BT), 0, s, g, z, b.fs, sc,
                            bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride);
 }
 
+// Stage nodes one phase-1 block bins together: two where a node's LDS bins exceed 40 KB
+// (single-node blocks are then limited by LDS to two per CU anyway) and two fit in 128 KB,
+// given many (representative, flow) pairs; else one.  Measured: two nodes per block at
+// N = 128 save 5% of phase 1; five per block at N = 48 (more blocks per CU without them)
+// cost 27-33%.
+template <typename R>
+int nodes_per_block(const DevGeom& g, const BinPlan& bp, int nRb, int nf) {
+    const size_t per = static_cast<size_t>(g.NN) * sizeof(R);
+    if (g.gflow || bp.n <= 1 || bins_mode<R>(g) != 0) return 1;
+    if (static_cast<long>(nRb) * nf < 4096) return 1;
+    return per > 40960 && 2 * per <= 131072 ? 2 : 1;
+}
+
 // Stage argument plus the plan's phase 1 in one launch.  Few (flow, node, representative)
 // triples (at most one per CU): 1024-thread blocks, one stage element per thread; many:
 // 256-thread blocks, four stage elements per thread.
+template <typename R, int kG, int NODES>
+void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
+                 const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
+    const int nRb = b.bins ? g.nRp + g.nRd : 0;
+    const int per_block = bp.n < NODES ? bp.n : NODES;
+    // bins in LDS above 40 KB leave room for at most three blocks per CU: 256-thread blocks
+    // would keep three waves or fewer per SIMD to hide the scan's dependent steps
+    const bool big = nRb > 0 && bins_mode<R>(g) == 0 &&
+                     static_cast<size_t>(per_block) * g.NN * sizeof(R) > 40960;
+    const long nblk = static_cast<long>(nRb) * ((bp.n + NODES - 1) / NODES) * nf;
+    const bool wide = nblk <= 256 || (big && bp.n > 0);
+    if (wide) stage_go<R, 1024, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
+    else stage_go<R, 256, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
+}
+
 template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
              const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
-    const int nRb = b.bins ? g.nRp + g.nRd : 0;
-    // bins in LDS above 40 KB leave room for at most three blocks per CU: 256-thread blocks
-    // would keep three waves or fewer per SIMD to hide the scan's dependent steps
-    const bool big = nRb > 0 && bins_mode<R>(g) == 0 && static_cast<size_t>(g.NN) * sizeof(R) > 40960;
-    const bool wide = static_cast<long>(nRb) * bp.n * nf <= 256 || (big && bp.n > 0);
     if (g.gflow && bp.n > 0) {
-        if (wide) stage_go<R, 1024, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
-        else stage_go<R, 256, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
-    } else {
-        if (wide) stage_go<R, 1024, 0>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
-        else stage_go<R, 256, 0>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
+        stage_nodes<R, 1, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase);
+        return;
     }
+    const int nodes = b.bins ? nodes_per_block<R>(g, bp, g.nRp + g.nRd, nf) : 1;
+    if (nodes == 2) stage_nodes<R, 0, 2>(s, g, z, b, nf, sc, bp, write_new, Vbase);
+    else stage_nodes<R, 0, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase);
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column
