@@ -26,6 +26,7 @@
 // Direct path (k_wtable, k_direct): the same sums over every loop point, no bins.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -128,50 +129,101 @@ __device__ inline R kval(const R* K, int l, int B, int f, size_t N3, size_t i) {
 //   interaction flow (s = -g, lines G_g = g Z G0 and S_g = Z^2 G0, App. A, Step 2):
 //   al = 0, be = s = -g, with bins of chi, so that the product is dV/ds = -dV/dg.
 // ------------------------------------------------------------------------------------
-// The stage elements of one thread with NS earlier stages: all 3 NS k loads and the V load of
-// an element are in flight together, then summed as kval and the l loop would.
-template <int NS, typename R>
+// The stage argument is formed in tiles of w (x) x w (y) x 16 (z) elements, w = 2^tl = 8 or
+// 16 (chosen per launch).  Each element's 3 NS k loads and V load are in flight together, then
+// summed as kval and the l loop would; V_s and v0 are written along z, and the tile goes
+// through LDS (padded strides) so that va is written along y and vc along x, w consecutive
+// elements per run.
+constexpr int kTZ = 16, kTSY = kTZ + 1;
+
+__host__ __device__ inline int stage_tiles(int N, int tl) {
+    const int w = 1 << tl, nx = (N + w - 1) / w;
+    return nx * nx * ((N + kTZ - 1) / kTZ);
+}
+__host__ __device__ inline int stage_tile_lds(int tl) {     // elements of the LDS tile
+    const int w = 1 << tl;
+    return w * (w * kTSY + 1);
+}
+
+template <int NS, int TL, typename R>
 __device__ inline void stage_elems(const DevGeom& g, const StageCoef& sc, double ht, int f,
                                    int write_new, const double* Vf, const R* K, double* Vnew,
-                                   R* v0, R* va, R* vc, int B, size_t i0, size_t stride) {
+                                   R* v0, R* va, R* vc, int B, R* tile, int blk, int nblk) {
     const int N = g.N, NN = g.NN;
     const size_t N3 = static_cast<size_t>(NN) * N;
-    for (size_t i = i0; i < N3; i += stride) {
-        R kv[NS > 0 ? NS : 1][3];
+    constexpr int tl = TL, w = 1 << tl, m = w - 1, tsx = w * kTSY + 1, tile_n = kTZ * w * w;
+    const int nx = (N + m) >> tl, nz = (N + kTZ - 1) / kTZ;
+    const int ntile = nx * nx * nz;
+    R* v0f = v0 + f * N3;
+    R* vaf = va + f * N3;
+    R* vcf = vc + f * N3;
+    for (int t = blk; t < ntile; t += nblk) {          // uniform over the block
+        const int tz = t % nz, txy = t / nz;
+        const int x0 = (txy / nx) << tl, y0 = (txy % nx) << tl, z0 = tz * kTZ;
+        for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+            const int lz = e & (kTZ - 1), ly = (e >> 4) & m, lx = e >> (4 + tl);
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            if (x >= N || y >= N || zz >= N) continue;
+            const size_t i = (static_cast<size_t>(x) * N + y) * N + zz;
+            R kv[NS > 0 ? NS : 1][3];
 #pragma unroll
-        for (int l = 0; l < NS; ++l) {
-            const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3 + i;
-            kv[l][0] = p[0];
-            kv[l][1] = p[N3];
-            kv[l][2] = p[2 * N3];
-        }
-        const double vb = Vf[i];
-        double acc = 0.0;
+            for (int l = 0; l < NS; ++l) {
+                const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3 + i;
+                kv[l][0] = p[0];
+                kv[l][1] = p[N3];
+                kv[l][2] = p[2 * N3];
+            }
+            const double vb = Vf[i];
+            double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < NS; ++l) {
-            R s3 = kv[l][0];
-            s3 += kv[l][1];
-            s3 += kv[l][2];
-            acc += sc.a[l] * static_cast<double>(s3);
+            for (int l = 0; l < NS; ++l) {
+                R s3 = kv[l][0];
+                s3 += kv[l][1];
+                s3 += kv[l][2];
+                acc += sc.a[l] * static_cast<double>(s3);
+            }
+            const double v = vb + ht * acc;
+            if (write_new) Vnew[f * N3 + i] = v;
+            const R r = static_cast<R>(v);
+            v0f[i] = r;
+            tile[lx * tsx + ly * kTSY + lz] = r;
         }
-        const double v = vb + ht * acc;
-        if (write_new) Vnew[f * N3 + i] = v;
-        const int x = static_cast<int>(i / NN);
-        const int y = static_cast<int>((i / N) % N);
-        const int zz = static_cast<int>(i % N);
-        const R r = static_cast<R>(v);
-        v0[f * N3 + i] = r;
-        va[f * N3 + static_cast<size_t>(zz) * NN + x * N + y] = r;
-        vc[f * N3 + static_cast<size_t>(zz) * NN + y * N + x] = r;
+        __syncthreads();
+        // va[z][x][y]: runs along y
+        for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+            const int ly = e & m, lx = (e >> tl) & m, lz = e >> (2 * tl);
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            if (x < N && y < N && zz < N)
+                vaf[static_cast<size_t>(zz) * NN + x * N + y] = tile[lx * tsx + ly * kTSY + lz];
+        }
+        // vc[z][y][x]: runs along x
+        for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+            const int lx = e & m, ly = (e >> tl) & m, lz = e >> (2 * tl);
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            if (x < N && y < N && zz < N)
+                vcf[static_cast<size_t>(zz) * NN + y * N + x] = tile[lx * tsx + ly * kTSY + lz];
+        }
+        __syncthreads();                                // the tile is rewritten next round
     }
+}
+
+// The tile width as a compile-time constant (a run-time width costs 17% at 16 wide).
+template <int NS, typename R>
+__device__ inline void stage_ns(const DevGeom& g, const StageCoef& sc, double ht, int f,
+                                int write_new, const double* Vf, const R* K, double* Vnew, R* v0,
+                                R* va, R* vc, int B, R* tile, int tl, int blk, int nblk) {
+    if (tl == 4)
+        stage_elems<NS, 4>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, blk, nblk);
+    else
+        stage_elems<NS, 3>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, blk, nblk);
 }
 
 template <typename R>
 __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowState& st, int f,
                                   const StageCoef& sc, int write_new, const double* Vbase,
                                   const R* K, double* Vnew, R* v0, R* va, R* vc,
-                                  double* T_stage, double* Z_stage, double* zw, int B, int blk,
-                                  int nblk) {
+                                  double* T_stage, double* Z_stage, double* zw, int B, R* tile,
+                                  int tl, int blk, int nblk) {
     const int N = g.N;
     const size_t N3 = static_cast<size_t>(g.NN) * N;
     const double ht = st.ht;
@@ -186,16 +238,14 @@ __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowSta
             Z_stage[static_cast<size_t>(f) * N + a] = z_interp(z, f, N, a, lnTs);
     }
     const double* Vf = Vbase + f * N3;
-    const size_t stride = static_cast<size_t>(nblk) * blockDim.x;
-    const size_t i0 = blk * static_cast<size_t>(blockDim.x) + threadIdx.x;
     switch (sc.ns) {                                   // uniform: earlier stages of this stage
-    case 0: stage_elems<0>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
-    case 1: stage_elems<1>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
-    case 2: stage_elems<2>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
-    case 3: stage_elems<3>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
-    case 4: stage_elems<4>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
-    case 5: stage_elems<5>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
-    default: stage_elems<6>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, i0, stride); break;
+    case 0: stage_ns<0>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    case 1: stage_ns<1>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    case 2: stage_ns<2>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    case 3: stage_ns<3>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    case 4: stage_ns<4>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    case 5: stage_ns<5>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    default: stage_ns<6>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
     }
 }
 
@@ -703,7 +753,8 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
                                                             const R* K, double* Vnew, R* v0,
                                                             R* va, R* vc, double* T_stage,
                                                             double* Z_stage, double* zw,
-                                                            R* bins, R* binsT, int nRb, int B) {
+                                                            R* bins, R* binsT, int nRb, int B,
+                                                            int tl) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;                      // uniform over the block
@@ -724,7 +775,8 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
                                            sb, sbT, reinterpret_cast<R*>(smem_raw));
     } else {
         stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
-                      zw, B, blockIdx.x - nbin, gridDim.x - nbin);
+                      zw, B, reinterpret_cast<R*>(smem_raw), tl, blockIdx.x - nbin,
+                      gridDim.x - nbin);
     }
 }
 
@@ -2138,27 +2190,34 @@ int bins_mode(const DevGeom& g) {
 template <typename R, int BT, int kG, int NODES>
 void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
               const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase,
-              int nRb, int ept) {
-    const size_t N3 = static_cast<size_t>(g.NN) * g.N;
-    size_t ns = (N3 + static_cast<size_t>(BT) * ept - 1) / (static_cast<size_t>(BT) * ept);
-    ns = ns > 1024 ? 1024 : ns;
+              int nRb) {
+    static_assert(BT <= 1024, "a stage block covers one tile (at least 1024 elements) at a time");
     const int nbin = nRb * ((bp.n + NODES - 1) / NODES);
-    const dim3 grid(static_cast<unsigned>(nbin + ns), nf);
     const bool lds = nbin > 0 && bins_mode<R>(g) == 0;
     const int per_block = bp.n < NODES ? bp.n : NODES;   // bin matrices a block holds
-    const size_t shm = lds ? static_cast<size_t>(per_block) * g.NN * sizeof(R) : 0;
+    const size_t shm_bins = lds ? static_cast<size_t>(per_block) * g.NN * sizeof(R) : 0;
+    // stage tiles 16 x 16 x 16 (64-byte runs in all three layouts) where they give about one
+    // block per CU or more and do not raise the LDS of phase-1 blocks, else 8 x 8 x 16
+    // (measured: 16 wide at N = 48 and 4 flows, 108 tiles, is 25% slower than 8 wide)
+    const size_t lds16 = static_cast<size_t>(stage_tile_lds(4)) * sizeof(R);
+    const int tl = static_cast<long>(stage_tiles(g.N, 4)) * nf >= 192 &&
+                           (nbin == 0 || shm_bins >= lds16) ? 4 : 3;
+    const int ns = std::min(stage_tiles(g.N, tl), 1024);  // one stage tile per block round
+    // LDS: the block's bin matrices, or one stage tile
+    const size_t shm = std::max(shm_bins, static_cast<size_t>(stage_tile_lds(tl)) * sizeof(R));
+    const dim3 grid(static_cast<unsigned>(nbin + ns), nf);
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
     if (nbin == 0 || lds)
         hipLaunchKernelGGL((k_stage_bins<R, 0, BT, kG, NODES>), grid, dim3(BT), shm, s, g, z, b.fs,
                            sc, bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
-                           b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride);
+                           b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride, tl);
     else if constexpr (NODES == 1)
-        hipLaunchKernelGGL((k_stage_bins<R, 1, BT, kG, 1>), grid, dim3(BT), 0, s, g, z, b.fs, sc,
+        hipLaunchKernelGGL((k_stage_bins<R, 1, BT, kG, 1>), grid, dim3(BT), shm, s, g, z, b.fs, sc,
                            bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
-                           b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride);
+                           b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride, tl);
 }
 
 // Stage nodes one phase-1 block bins together: two where a node's LDS bins exceed 40 KB
@@ -2175,8 +2234,8 @@ int nodes_per_block(const DevGeom& g, const BinPlan& bp, int nRb, int nf) {
 }
 
 // Stage argument plus the plan's phase 1 in one launch.  Few (flow, node, representative)
-// triples (at most one per CU): 1024-thread blocks, one stage element per thread; many:
-// 256-thread blocks, four stage elements per thread.
+// triples (at most one per CU): 1024-thread blocks, one element of a stage tile per thread;
+// many: 256-thread blocks, four per thread.
 template <typename R, int kG, int NODES>
 void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
                  const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
@@ -2188,8 +2247,8 @@ void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& 
                      static_cast<size_t>(per_block) * g.NN * sizeof(R) > 40960;
     const long nblk = static_cast<long>(nRb) * ((bp.n + NODES - 1) / NODES) * nf;
     const bool wide = nblk <= 256 || (big && bp.n > 0);
-    if (wide) stage_go<R, 1024, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 1);
-    else stage_go<R, 256, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb, 4);
+    if (wide) stage_go<R, 1024, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb);
+    else stage_go<R, 256, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb);
 }
 
 template <typename R>
