@@ -41,8 +41,9 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5, prec="fp
               weight derivatives (orbit representatives), each counted as 6 flops (two
               differences, one division, the 1/(4 T L^2) scale and the bin accumulation) --
               the point quantities the kernel evaluates on the fly are not counted
-    stage:    the stage argument alone: V read (f64), on average four earlier k slots of
-              three channel parts read, three operand layouts written
+    stage:    the stage argument alone, timed as a middle stage of a step: V read (f64),
+              four earlier k slots of three channel parts read, three operand layouts
+              written
     y:        (nP + 3 nD) N^3 multiply-adds on the matrix cores; bytes = representative
               bins read (plus the transposed particle-hole bins) + 3 operand slabs read + Y
               written; bound by whichever roof takes longer at its peak: the matrix cores of

@@ -214,8 +214,8 @@ int fm_geometry_query(const fm_config *cfg, double *xi, int *patch, int *anchor,
  * current temperature; their status is restored): group 0 stage argument and phase 1 of
  * every stage node of an integrator step (the first stage launch of a step), 1 phase-2a
  * products, 2 phase-2b contraction (the direct kernel in FM_FP64_DIRECT), 3 stage argument
- * alone (the later stages of a step).  The
- * group is launched `reps` times back to back on cfg->stream between two HIP events; every
+ * alone as a later stage of a step forms it (four earlier k slots read).  The group is
+ * launched `reps` times back to back on cfg->stream between two HIP events; every
  * launch recomputes the same products from the same inputs.  It overwrites the stage
  * operands, bins, products and k slot 0, all of which the next integrator step recomputes.
  * Synchronous.  FM_EINVAL for a bad group, batch or reps. */
