@@ -41,8 +41,9 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5, prec="fp
               weight derivatives (orbit representatives), each counted as 6 flops (two
               differences, one division, the 1/(4 T L^2) scale and the bin accumulation) --
               the point quantities the kernel evaluates on the fly are not counted
-    stage:    the stage argument alone, timed as a middle stage of a step: V read (f64),
-              four earlier k slots of three channel parts read, three operand layouts
+    stage:    the stage argument alone, timed as a middle stage of a step (four earlier k
+              slots): V read (f64), the newest slot's three channel parts and the three
+              earlier slots' sums read, the newest slot's sum and three operand layouts
               written
     y:        (nP + 3 nD) N^3 multiply-adds on the matrix cores; bytes = representative
               bins read (plus the transposed particle-hole bins) + 3 operand slabs read + Y
@@ -56,7 +57,7 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5, prec="fp
     if name == "stage_bins":
         return {"bound": "alu", "flops": 6.0 * nsets * (nRp + nRd) * L * L}
     if name == "stage":
-        return {"bound": "hbm", "bytes": N3 * (8 + 4 * 3 * rsize + 3 * rsize)}
+        return {"bound": "hbm", "bytes": N3 * (8 + (3 + 3) * rsize + (1 + 3) * rsize)}
     if name == "y":
         flops = 2.0 * (nP + 3 * nD) * N3
         nbytes = (nRp + 2 * nRd) * NN * rsize + 3 * N3 * rsize + (nP + 3 * nD) * NN * rsize

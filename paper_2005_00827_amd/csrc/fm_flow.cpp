@@ -223,7 +223,11 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.Z_stage = L.take<double>(static_cast<size_t>(B) * N);
     b.zw_stage = L.take<double>(2 * static_cast<size_t>(B));
     b.U = L.take<double>(B);
-    b.nblk = static_cast<int>(std::min<size_t>((N3 + 255) / 256, 512));
+    // integrator reduction blocks per flow: one per 8 x 8 x 16 element tile, at most 512
+    {
+        const size_t nx = (static_cast<size_t>(N) + 7) / 8, nz = (static_cast<size_t>(N) + 15) / 16;
+        b.nblk = static_cast<int>(std::min<size_t>(nx * nx * nz, 512));
+    }
     b.part = L.take<double>(static_cast<size_t>(B) * b.nblk * 2);
     b.bstride = B;
     if (!direct) {
@@ -251,6 +255,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.va = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.vc = L.take<char>(static_cast<size_t>(B) * N3 * rs);
     b.k = L.take<char>(7 * 3 * static_cast<size_t>(B) * N3 * rs);
+    b.ksum = L.take<char>(7 * static_cast<size_t>(B) * N3 * rs);
     b.V = L.take<double>(static_cast<size_t>(B) * N3);
     b.Vnew = L.take<double>(static_cast<size_t>(B) * N3);
     *bytes = L.off + 256;
@@ -426,7 +431,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps) {
             stage_launch(h, nf, rk4_stage(s), s == plan.first ? plan.bp : kNoBins, 0, V);
             rhs_launch(h, nf, s, plan.set[s]);
         }
-        timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->N3, V); });
+        timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->g.N, V); });
         timed(h, T_FINISH, [&] { launch_finish(h->stream, h->b, nf, 0, fixed_steps); });
         return;
     }
@@ -436,7 +441,7 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps) {
     }
     ErrWeights ew;
     std::memcpy(ew.e, kDPE, sizeof ew.e);
-    timed(h, T_UPDATE, [&] { launch_dopri_err(h->stream, h->dbl, h->b, nf, h->N3, V, h->cfg.rtol, ew); });
+    timed(h, T_UPDATE, [&] { launch_dopri_err(h->stream, h->dbl, h->b, nf, h->g.N, V, h->cfg.rtol, ew); });
     timed(h, T_FINISH, [&] {
         launch_finish(h->stream, h->b, nf, 1, 0);
         launch_commit(h->stream, h->dbl, h->b, nf, h->N3, V);
@@ -746,7 +751,7 @@ int fm_flow_rhs(fm_flow* h, int batch, const double* T, const double* V_dev, dou
     StageCoef sc{};
     stage_launch(h, batch, sc, kOneNode, 0, V_dev);
     rhs_launch(h, batch, 0, 0);
-    launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);
+    launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->g.N, 0, dV_dev);
     HIPCHK(hipGetLastError());
     return FM_OK;
 }
@@ -817,7 +822,7 @@ int fm_flow_rhs_g(fm_flow* h, int batch, const double* T, const double* g, const
     StageCoef sc{};
     stage_launch(h, batch, sc, kOneNode, 0, V_dev);
     rhs_launch(h, batch, 0, 0);
-    launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->N3, 0, dV_dev);   // -dV/ds = dV/dg
+    launch_k_to_f64(h->stream, h->dbl, h->b, batch, h->g.N, 0, dV_dev);   // -dV/ds = dV/dg
     HIPCHK(hipGetLastError());
     return FM_OK;
 }

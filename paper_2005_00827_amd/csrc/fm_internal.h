@@ -168,7 +168,8 @@ struct Buffers {
     size_t bins_bytes, binsT_bytes;    // with kBinPad values of zeroed padding each
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real
     void* v0; void* va; void* vc;      // operands [B][N^3] real
-    void* k;                           // [7][B][3][N^3] real: per stage, flow and channel
+    void* k;                           // [7][B][3][N^3] real: per stage, flow and channel (parts in phase-2b order)
+    void* ksum;                        // [7][B][N^3] real: a slot's three parts summed, V order
     double* V; double* Vnew;           // [B][N^3] state, candidate
     double* part;                      // [B][nblk][2] reduction partials
     double* wtab;                      // direct mode: [B][nP+nD][np]
@@ -211,11 +212,11 @@ void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf);
 void launch_direct(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
                    int slot);
-void launch_k_to_f64(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, int slot,
+void launch_k_to_f64(hipStream_t s, bool dbl, const Buffers& b, int nf, int N, int slot,
                      double* out);
 void launch_fill_u(hipStream_t s, const Buffers& b, int nf, size_t N3, const double* U);
-void launch_rk4_update(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
-void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3,
+void launch_rk4_update(hipStream_t s, bool dbl, const Buffers& b, int nf, int N, double* V);
+void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, int N,
                       const double* V, double rtol, const ErrWeights& ew);
 // Accept/reject and the stop test against each flow's own threshold (FlowState::vmax).
 void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, int fixed_steps);

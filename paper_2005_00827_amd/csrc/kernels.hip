@@ -37,6 +37,7 @@ namespace fm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kStepThreads = 1024;   // integrator kernels: one 8 x 8 x 16 tile per block round
 
 __device__ inline int wrapi(int v, int L) {
     int r = v % L;
@@ -109,121 +110,210 @@ __device__ inline double z_interp(const DevZ& z, int f, int N, int a, double lnT
 
 __device__ inline bool running(const FlowState* fs, int f) { return fs[f].status == FM_FLOW_RUNNING; }
 
-// k of stage l, flow f, element i.  A k slot holds the three channel right-hand sides
-// [slot][flow][pp, crossed, direct][N^3]; their sum is taken in that order.
+// k slots [slot][flow][pp, crossed, direct][N^3] (R).  Each channel part is stored in the
+// order phase 2b writes it: a phase-2b lane owns the free index n of an output pair's row,
+//   pp part       V(x,y,z) at (x N + y) N + z   (n = z)
+//   crossed part  V(x,y,z) at (y N + z) N + x   (n = x)
+//   direct part   V(x,y,z) at (x N + z) N + y   (n = y)
+// so each of its stores is contiguous over the wave.  The first kernel after phase 2b that
+// needs a slot (the next stage argument, or the step's update or error norm for the last slot)
+// tiles the cube, brings the crossed and direct parts to V order through LDS (tile_parts, each
+// read along its own contiguous index), and writes the slot's sum (pp + crossed) + direct,
+// rounded to R as each addition is, to ksum[slot][flow][N^3] in V order; later readers in the
+// same step read that sum.
+__host__ __device__ inline size_t kpos(int ch, int N, int x, int y, int z) {
+    const size_t n = static_cast<size_t>(N);
+    return ch == 0 ? (x * n + y) * n + z : (ch == 1 ? (y * n + z) * n + x : (x * n + z) * n + y);
+}
+
+// k of stage l, flow f, element (x, y, z): the three parts summed in that order.
 template <typename R>
-__device__ inline R kval(const R* K, int l, int B, int f, size_t N3, size_t i) {
-    const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3 + i;
-    R v = p[0];
-    v += p[N3];
-    v += p[2 * N3];
+__device__ inline R kval_at(const R* K, int l, int B, int f, size_t N3, int N, int x, int y,
+                            int z) {
+    const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3;
+    R v = p[kpos(0, N, x, y, z)];
+    v += p[N3 + kpos(1, N, x, y, z)];
+    v += p[2 * N3 + kpos(2, N, x, y, z)];
     return v;
 }
 
-// ------------------------------------------------------------------------------------
-// Stage argument V_s = V + h sum_l a_l k_l (double), Z and T of the stage, operand layouts
-//   v0[x][y][z] = V(x,y,z),  va[z][x][y] = V(x,y,z),  vc[z][y][x] = V(x,y,z),
-// and the factor of the internal line pair (a', b') applied in phase 2a,
-//   Z_a' Z_b' (al + be (Z_a' + Z_b')):
-//   temperature flow (s = ln T): al = 1, be = 0, with bins of T d/dT chi;
-//   interaction flow (s = -g, lines G_g = g Z G0 and S_g = Z^2 G0, App. A, Step 2):
-//   al = 0, be = s = -g, with bins of chi, so that the product is dV/ds = -dV/dg.
-// ------------------------------------------------------------------------------------
-// The stage argument is formed in tiles of w (x) x w (y) x 16 (z) elements, w = 2^tl = 8 or
-// 16 (chosen per launch).  Each element's 3 NS k loads and V load are in flight together, then
-// summed as kval and the l loop would; V_s and v0 are written along z, and the tile goes
-// through LDS (padded strides) so that va is written along y and vc along x, w consecutive
-// elements per run.
+// Element tiles of w (x) x w (y) x 16 (z), w = 2^TL, with padded LDS strides; tile t of a
+// flow starts at (x0, y0, z0), z fastest over t.
 constexpr int kTZ = 16, kTSY = kTZ + 1;
 
 __host__ __device__ inline int stage_tiles(int N, int tl) {
     const int w = 1 << tl, nx = (N + w - 1) / w;
     return nx * nx * ((N + kTZ - 1) / kTZ);
 }
-__host__ __device__ inline int stage_tile_lds(int tl) {     // elements of the LDS tile
-    const int w = 1 << tl;
-    return w * (w * kTSY + 1);
+__host__ __device__ constexpr int stage_tile_lds(int tl) {  // elements of one LDS tile
+    return (1 << tl) * ((1 << tl) * kTSY + 1);
+}
+__device__ inline void tile_origin(int t, int N, int tl, int& x0, int& y0, int& z0) {
+    const int nx = (N + (1 << tl) - 1) >> tl, nz = (N + kTZ - 1) / kTZ;
+    const int txy = t / nz;
+    x0 = (txy / nx) << tl;
+    y0 = (txy % nx) << tl;
+    z0 = (t - txy * nz) * kTZ;
 }
 
-template <int NS, int TL, typename R>
+// The crossed and direct parts of one k slot (Kp: the slot's flow base) at one tile's
+// elements, read along x and along y respectively, left in LDS (exactly, as double) at the
+// element's tile position; the caller synchronises before use.
+template <int TL, typename R>
+__device__ inline void tile_parts(const R* Kp, size_t N3, int N, int x0, int y0, int z0,
+                                  double* p1, double* p2) {
+    constexpr int w = 1 << TL, m = w - 1, tsx = w * kTSY + 1, tile_n = kTZ * w * w;
+    for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+        const int u = e & m, v = (e >> TL) & m, lz = e >> (2 * TL);
+        const int zz = z0 + lz;
+        // crossed: (lx, ly) = (u, v); direct: (lx, ly) = (v, u)
+        const bool ok1 = x0 + u < N && y0 + v < N && zz < N;
+        const bool ok2 = x0 + v < N && y0 + u < N && zz < N;
+        const R k1 = Kp[N3 + (ok1 ? kpos(1, N, x0 + u, y0 + v, zz) : 0)];
+        const R k2 = Kp[2 * N3 + (ok2 ? kpos(2, N, x0 + v, y0 + u, zz) : 0)];
+        if (ok1) p1[u * tsx + v * kTSY + lz] = static_cast<double>(k1);
+        if (ok2) p2[v * tsx + u * kTSY + lz] = static_cast<double>(k2);
+    }
+}
+
+// Sum of the three parts of a slot at one element, in the order and precision kval_at uses.
+template <typename R>
+__device__ inline R part_sum(R pp, double cr, double d) {
+    R v = pp;
+    v += static_cast<R>(cr);
+    v += static_cast<R>(d);
+    return v;
+}
+
+// The stage argument is formed in element tiles, w = 8 or 16 (chosen per launch).  The newest
+// slot's crossed and direct parts go to LDS first (tile_parts); then each element's loads
+// (the newest slot's pp part, the earlier slots' sums, V) are summed as the slots' order
+// gives, V_s = V + h sum_l a_l k_l, the newest slot's sum is written to ksum, V_s and v0 are
+// written along z, and V_s in operand precision takes the element's crossed-part slot (read
+// only by the same thread), from which va is written along y and vc along x, w consecutive
+// elements per run.  LDS: two double tiles.
+template <int NS, int TL, int BT, bool PRE, typename R>
 __device__ inline void stage_elems(const DevGeom& g, const StageCoef& sc, double ht, int f,
-                                   int write_new, const double* Vf, const R* K, double* Vnew,
-                                   R* v0, R* va, R* vc, int B, R* tile, int blk, int nblk) {
+                                   int write_new, const double* Vf, const R* K, R* KS,
+                                   double* Vnew, R* v0, R* va, R* vc, int B, double* tile,
+                                   int blk, int nblk) {
     const int N = g.N, NN = g.NN;
     const size_t N3 = static_cast<size_t>(NN) * N;
     constexpr int tl = TL, w = 1 << tl, m = w - 1, tsx = w * kTSY + 1, tile_n = kTZ * w * w;
-    const int nx = (N + m) >> tl, nz = (N + kTZ - 1) / kTZ;
-    const int ntile = nx * nx * nz;
+    constexpr int NL = NS > 0 ? NS : 1;
+    // with PRE (and at most 96 bytes of them per thread) this thread's element loads are
+    // issued before the LDS parts and held in registers across the barrier: one memory round
+    // trip per tile instead of two
+    constexpr int EPT = tile_n / BT;
+    constexpr bool kPre = PRE && EPT * NS * sizeof(R) <= 96;
+    double* p1 = tile;
+    double* p2 = tile + stage_tile_lds(TL);
+    const int ntile = stage_tiles(N, tl);
     R* v0f = v0 + f * N3;
     R* vaf = va + f * N3;
     R* vcf = vc + f * N3;
+    const size_t ks = static_cast<size_t>(B) * N3;               // ksum slot stride
+    const R* Kn = K + ((static_cast<size_t>(NL - 1) * B + f) * 3) * N3;   // newest slot, flow f
+    const R* KSf = KS + static_cast<size_t>(f) * N3;
+    R* KSn = KS + (static_cast<size_t>(NL - 1) * B + f) * N3;
     for (int t = blk; t < ntile; t += nblk) {          // uniform over the block
-        const int tz = t % nz, txy = t / nz;
-        const int x0 = (txy / nx) << tl, y0 = (txy % nx) << tl, z0 = tz * kTZ;
-        for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+        int x0, y0, z0;
+        tile_origin(t, N, tl, x0, y0, z0);
+        R kp[kPre ? EPT : 1][NL];
+        double vp[kPre ? EPT : 1];
+        if constexpr (kPre) {
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                const int e = threadIdx.x + r * BT;
+                const int lz = e & (kTZ - 1), ly = (e >> 4) & m, lx = e >> (4 + tl);
+                const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+                const size_t i =
+                    x < N && y < N && zz < N ? (static_cast<size_t>(x) * N + y) * N + zz : 0;
+#pragma unroll
+                for (int l = 0; l + 1 < NS; ++l) kp[r][l] = KSf[l * ks + i];
+                if constexpr (NS > 0) kp[r][NS - 1] = Kn[i];
+                vp[r] = Vf[i];
+            }
+        }
+        if constexpr (NS > 0) {
+            tile_parts<TL>(Kn, N3, N, x0, y0, z0, p1, p2);
+            __syncthreads();
+        }
+        // unrolled only with the preload (else one element's loads at a time)
+#pragma unroll (kPre ? EPT : 1)
+        for (int r = 0; r < EPT; ++r) {
+            const int e = threadIdx.x + r * BT;
             const int lz = e & (kTZ - 1), ly = (e >> 4) & m, lx = e >> (4 + tl);
             const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
             if (x >= N || y >= N || zz >= N) continue;
             const size_t i = (static_cast<size_t>(x) * N + y) * N + zz;
-            R kv[NS > 0 ? NS : 1][3];
+            const int j = lx * tsx + ly * kTSY + lz;
+            R kv[NL];
+            double vb;
+            if constexpr (kPre) {
 #pragma unroll
-            for (int l = 0; l < NS; ++l) {
-                const R* p = K + (static_cast<size_t>(l) * B + f) * 3 * N3 + i;
-                kv[l][0] = p[0];
-                kv[l][1] = p[N3];
-                kv[l][2] = p[2 * N3];
+                for (int l = 0; l < NS; ++l) kv[l] = kp[r][l];
+                vb = vp[r];
+            } else {
+#pragma unroll
+                for (int l = 0; l + 1 < NS; ++l) kv[l] = KSf[l * ks + i];
+                if constexpr (NS > 0) kv[NS - 1] = Kn[i];
+                vb = Vf[i];
             }
-            const double vb = Vf[i];
             double acc = 0.0;
-#pragma unroll
-            for (int l = 0; l < NS; ++l) {
-                R s3 = kv[l][0];
-                s3 += kv[l][1];
-                s3 += kv[l][2];
-                acc += sc.a[l] * static_cast<double>(s3);
+            if constexpr (NS > 0) {
+                kv[NS - 1] = part_sum(kv[NS - 1], p1[j], p2[j]);
+                KSn[i] = kv[NS - 1];
             }
+#pragma unroll
+            for (int l = 0; l < NS; ++l) acc += sc.a[l] * static_cast<double>(kv[l]);
             const double v = vb + ht * acc;
             if (write_new) Vnew[f * N3 + i] = v;
-            const R r = static_cast<R>(v);
-            v0f[i] = r;
-            tile[lx * tsx + ly * kTSY + lz] = r;
+            const R rv = static_cast<R>(v);
+            v0f[i] = rv;
+            p1[j] = static_cast<double>(rv);
         }
         __syncthreads();
         // va[z][x][y]: runs along y
-        for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+        for (int e = threadIdx.x; e < tile_n; e += BT) {
             const int ly = e & m, lx = (e >> tl) & m, lz = e >> (2 * tl);
             const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
             if (x < N && y < N && zz < N)
-                vaf[static_cast<size_t>(zz) * NN + x * N + y] = tile[lx * tsx + ly * kTSY + lz];
+                vaf[static_cast<size_t>(zz) * NN + x * N + y] =
+                    static_cast<R>(p1[lx * tsx + ly * kTSY + lz]);
         }
         // vc[z][y][x]: runs along x
-        for (int e = threadIdx.x; e < tile_n; e += blockDim.x) {
+        for (int e = threadIdx.x; e < tile_n; e += BT) {
             const int lx = e & m, ly = (e >> tl) & m, lz = e >> (2 * tl);
             const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
             if (x < N && y < N && zz < N)
-                vcf[static_cast<size_t>(zz) * NN + y * N + x] = tile[lx * tsx + ly * kTSY + lz];
+                vcf[static_cast<size_t>(zz) * NN + y * N + x] =
+                    static_cast<R>(p1[lx * tsx + ly * kTSY + lz]);
         }
-        __syncthreads();                                // the tile is rewritten next round
+        __syncthreads();                                // the tiles are rewritten next round
     }
 }
 
 // The tile width as a compile-time constant (a run-time width costs 17% at 16 wide).
-template <int NS, typename R>
+template <int NS, int BT, bool PRE, typename R>
 __device__ inline void stage_ns(const DevGeom& g, const StageCoef& sc, double ht, int f,
-                                int write_new, const double* Vf, const R* K, double* Vnew, R* v0,
-                                R* va, R* vc, int B, R* tile, int tl, int blk, int nblk) {
+                                int write_new, const double* Vf, const R* K, R* KS,
+                                double* Vnew, R* v0, R* va, R* vc, int B, double* tile, int tl,
+                                int blk, int nblk) {
     if (tl == 4)
-        stage_elems<NS, 4>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, blk, nblk);
+        stage_elems<NS, 4, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile,
+                                    blk, nblk);
     else
-        stage_elems<NS, 3>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, blk, nblk);
+        stage_elems<NS, 3, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile,
+                                    blk, nblk);
 }
 
-template <typename R>
+template <typename R, int BT, bool PRE>
 __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowState& st, int f,
                                   const StageCoef& sc, int write_new, const double* Vbase,
-                                  const R* K, double* Vnew, R* v0, R* va, R* vc,
-                                  double* T_stage, double* Z_stage, double* zw, int B, R* tile,
-                                  int tl, int blk, int nblk) {
+                                  const R* K, R* KS, double* Vnew, R* v0, R* va, R* vc,
+                                  double* T_stage, double* Z_stage, double* zw, int B,
+                                  double* tile, int tl, int blk, int nblk) {
     const int N = g.N;
     const size_t N3 = static_cast<size_t>(g.NN) * N;
     const double ht = st.ht;
@@ -239,13 +329,34 @@ __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowSta
     }
     const double* Vf = Vbase + f * N3;
     switch (sc.ns) {                                   // uniform: earlier stages of this stage
-    case 0: stage_ns<0>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
-    case 1: stage_ns<1>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
-    case 2: stage_ns<2>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
-    case 3: stage_ns<3>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
-    case 4: stage_ns<4>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
-    case 5: stage_ns<5>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
-    default: stage_ns<6>(g, sc, ht, f, write_new, Vf, K, Vnew, v0, va, vc, B, tile, tl, blk, nblk); break;
+    case 0:
+        stage_ns<0, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
+    case 1:
+        stage_ns<1, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
+    case 2:
+        stage_ns<2, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
+    case 3:
+        stage_ns<3, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
+    case 4:
+        stage_ns<4, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
+    case 5:
+        stage_ns<5, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
+    default:
+        stage_ns<6, BT, PRE>(g, sc, ht, f, write_new, Vf, K, KS, Vnew, v0, va, vc, B, tile, tl, blk,
+                             nblk);
+        break;
     }
 }
 
@@ -750,8 +861,8 @@ template <typename R, int kMode, int BT, int kG, int NODES>
 __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const FlowState* fs,
                                                             StageCoef sc, BinPlan bp,
                                                             int write_new, const double* Vbase,
-                                                            const R* K, double* Vnew, R* v0,
-                                                            R* va, R* vc, double* T_stage,
+                                                            const R* K, R* KS, double* Vnew,
+                                                            R* v0, R* va, R* vc, double* T_stage,
                                                             double* Z_stage, double* zw,
                                                             R* bins, R* binsT, int nRb, int B,
                                                             int tl) {
@@ -774,10 +885,28 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
         bins_part<R, kMode, BT, kG, NODES>(g, f, r, T, nn, bins + set0 * sb, binsT + set0 * sbT,
                                            sb, sbT, reinterpret_cast<R*>(smem_raw));
     } else {
-        stage_part<R>(g, z, st, f, sc, write_new, Vbase, K, Vnew, v0, va, vc, T_stage, Z_stage,
-                      zw, B, reinterpret_cast<R*>(smem_raw), tl, blockIdx.x - nbin,
-                      gridDim.x - nbin);
+        stage_part<R, BT, false>(g, z, st, f, sc, write_new, Vbase, K, KS, Vnew, v0, va, vc,
+                                 T_stage, Z_stage, zw, B, reinterpret_cast<double*>(smem_raw),
+                                 tl, blockIdx.x - nbin, gridDim.x - nbin);
     }
+}
+
+// The stage argument alone (the later stages of a step): 1024-thread blocks, one element tile
+// per block round, the pp-part and V loads held across the tile's barrier.  Grid (tiles, flows).
+template <typename R>
+__global__ void __launch_bounds__(1024) k_stage(DevGeom g, DevZ z, const FlowState* fs,
+                                                StageCoef sc, int write_new, const double* Vbase,
+                                                const R* K, R* KS, double* Vnew, R* v0, R* va,
+                                                R* vc,
+                                                double* T_stage, double* Z_stage, double* zw,
+                                                int B, int tl) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int f = blockIdx.y;
+    if (!running(fs, f)) return;                      // uniform over the block
+    const FlowState st = fs[f];
+    stage_part<R, 1024, true>(g, z, st, f, sc, write_new, Vbase, K, KS, Vnew, v0, va, vc,
+                              T_stage, Z_stage, zw, B, reinterpret_cast<double*>(smem_raw), tl,
+                              blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1827,13 +1956,9 @@ __device__ __attribute__((always_inline)) inline void contract_item(
         }
         if (n0 + static_cast<int>(threadIdx.x) >= N) continue;
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
+        for (int i = 0; i < kChunk; ++i) {   // every part at (pair) N + n: contiguous in n
             if (i >= cnt) break;
-            const int xy = pr[i];
-            const int a = xy / N, c = xy - a * N;
-            if (KIND == 0) Kf[static_cast<size_t>(xy) * N + n] = -acc[i];
-            else if (KIND == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = acc[i];
-            else Kf[static_cast<size_t>(a) * NN + n * N + c] = acc[i];
+            Kf[static_cast<size_t>(pr[i]) * N + n] = KIND == 0 ? -acc[i] : acc[i];
         }
     }
 }
@@ -1863,11 +1988,7 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     if (!(ch & bit)) {   // a channel that is switched off contributes zero
         for (int e = threadIdx.x; e < cnt * N; e += blockDim.x) {
             const int i = e / N, n = e - i * N;
-            const int xy = pairs[i];
-            const int a = xy / N, c = xy - a * N;
-            if (kind == 0) Kf[static_cast<size_t>(xy) * N + n] = R(0);
-            else if (kind == 1) Kf[static_cast<size_t>(n) * NN + a * N + c] = R(0);
-            else Kf[static_cast<size_t>(a) * NN + n * N + c] = R(0);
+            Kf[static_cast<size_t>(pairs[i]) * N + n] = R(0);
         }
         return;
     }
@@ -1950,10 +2071,10 @@ __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState*
                            + vajc * V[static_cast<size_t>(b) * NN + pq * N + pj]);
         }
     }
-    const size_t o = f * 3 * N3 + static_cast<size_t>(a) * NN + b * N + c;   // slot parts
-    K[o] = -s1;
-    K[o + N3] = s2;
-    K[o + 2 * N3] = s3;
+    double* Kf = K + f * 3 * N3;                       // slot parts, phase-2b order
+    Kf[kpos(0, N, a, b, c)] = -s1;
+    Kf[N3 + kpos(1, N, a, b, c)] = s2;
+    Kf[2 * N3 + kpos(2, N, a, b, c)] = s3;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1961,13 +2082,17 @@ __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState*
 // ------------------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_to_f64(const FlowState* fs, const R* K, double* out,
-                                                     size_t N3) {
+                                                     int N) {
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
+    const size_t N3 = static_cast<size_t>(N) * N * N;
+    const double sg = fs[f].gflow ? -1.0 : 1.0;
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        out[f * N3 + i] = fs[f].gflow ? -static_cast<double>(kval(K, 0, 0, f, N3, i))
-                                      : static_cast<double>(kval(K, 0, 0, f, N3, i));
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(i / (static_cast<size_t>(N) * N));
+        const int y = static_cast<int>((i / N) % N), z = static_cast<int>(i % N);
+        out[f * N3 + i] = sg * static_cast<double>(kval_at(K, 0, 0, f, N3, N, x, y, z));
+    }
 }
 
 __global__ void __launch_bounds__(kThreads) k_fill_u(double* V, const double* U, size_t N3) {
@@ -1978,7 +2103,7 @@ __global__ void __launch_bounds__(kThreads) k_fill_u(double* V, const double* U,
 }
 
 __device__ inline double block_max(double v) {
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[1024 / 64];
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     const int w = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -1996,22 +2121,58 @@ __device__ inline double block_max(double v) {
 
 // V += h/6 (k0 + 2 k1 + 2 k2 + k3); partial max|V| (inf if non-finite).
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_rk4_update(const FlowState* fs, const R* K,
-                                                         double* V, double* part, int nblk,
-                                                         size_t N3, int B) {
+__global__ void __launch_bounds__(kStepThreads) k_rk4_update(const FlowState* fs, const R* K,
+                                                             const R* KS, double* V,
+                                                             double* part, int nblk, int N,
+                                                             int B) {
+    __shared__ double p1[stage_tile_lds(3)], p2[stage_tile_lds(3)];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const double h = fs[f].ht;
+    const size_t N3 = static_cast<size_t>(N) * N * N;
+    const size_t ks = static_cast<size_t>(B) * N3;
+    const R* K3 = K + ((3 * static_cast<size_t>(B) + f) * 3) * N3;   // slot 3 (parts)
+    const R* KSf = KS + static_cast<size_t>(f) * N3;                 // sums of slots 0..2
+    constexpr int tsx = 8 * kTSY + 1, tile_n = kTZ * 64, EPT = tile_n / kStepThreads;
     double mx = 0.0;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const double k0 = kval(K, 0, B, f, N3, i);
-        const double k1 = kval(K, 1, B, f, N3, i);
-        const double k2 = kval(K, 2, B, f, N3, i);
-        const double k3 = kval(K, 3, B, f, N3, i);
-        const double v = V[f * N3 + i] + h / 6.0 * (k0 + 2.0 * k1 + 2.0 * k2 + k3);
-        V[f * N3 + i] = v;
-        mx = fmax(mx, isfinite(v) ? fabs(v) : INFINITY);
+    const int ntile = stage_tiles(N, 3);
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {   // uniform over the block
+        int x0, y0, z0;
+        tile_origin(t, N, 3, x0, y0, z0);
+        // this thread's slot sums, slot-3 pp parts and V first (in registers across the barrier)
+        R kv[EPT][4];
+        double vo[EPT];
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int e = threadIdx.x + r * kStepThreads;
+            const int lz = e & (kTZ - 1), ly = (e >> 4) & 7, lx = e >> 7;
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            const size_t i =
+                x < N && y < N && zz < N ? (static_cast<size_t>(x) * N + y) * N + zz : 0;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) kv[r][l] = KSf[l * ks + i];
+            kv[r][3] = K3[i];
+            vo[r] = V[f * N3 + i];
+        }
+        tile_parts<3>(K3, N3, N, x0, y0, z0, p1, p2);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int e = threadIdx.x + r * kStepThreads;
+            const int lz = e & (kTZ - 1), ly = (e >> 4) & 7, lx = e >> 7;
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            if (x >= N || y >= N || zz >= N) continue;
+            const size_t i = (static_cast<size_t>(x) * N + y) * N + zz;
+            const int j = lx * tsx + ly * kTSY + lz;
+            const double k0 = static_cast<double>(kv[r][0]);
+            const double k1 = static_cast<double>(kv[r][1]);
+            const double k2 = static_cast<double>(kv[r][2]);
+            const double k3 = static_cast<double>(part_sum(kv[r][3], p1[j], p2[j]));
+            const double v = vo[r] + h / 6.0 * (k0 + 2.0 * k1 + 2.0 * k2 + k3);
+            V[f * N3 + i] = v;
+            mx = fmax(mx, isfinite(v) ? fabs(v) : INFINITY);
+        }
+        __syncthreads();
     }
     mx = block_max(mx);
     if (threadIdx.x == 0) {
@@ -2019,30 +2180,64 @@ __global__ void __launch_bounds__(kThreads) k_rk4_update(const FlowState* fs, co
         part[(static_cast<size_t>(f) * nblk + blockIdx.x) * 2 + 1] = mx;
     }
 }
-
-// Dormand-Prince error norm max_i |h sum_l e_l k_l| / (atol + rtol max(|V|, |Vnew|)) and
-// max|Vnew|; inf when anything is non-finite.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_dopri_err(const FlowState* fs, const R* K,
-                                                        const double* V, const double* Vnew,
-                                                        double rtol, ErrWeights ew,
-                                                        double* part, int nblk, size_t N3,
-                                                        int B) {
+__global__ void __launch_bounds__(kStepThreads) k_dopri_err(const FlowState* fs, const R* K,
+                                                            const R* KS, const double* V,
+                                                            const double* Vnew, double rtol,
+                                                            ErrWeights ew, double* part, int nblk,
+                                                            int N, int B) {
+    __shared__ double p1[stage_tile_lds(3)], p2[stage_tile_lds(3)];
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const double h = fs[f].ht;
     const double at = fs[f].atol;
+    const size_t N3 = static_cast<size_t>(N) * N * N;
+    const size_t ks = static_cast<size_t>(B) * N3;
+    const R* K6 = K + ((6 * static_cast<size_t>(B) + f) * 3) * N3;   // slot 6 (parts)
+    const R* KSf = KS + static_cast<size_t>(f) * N3;                 // sums of slots 0..5
+    constexpr int tsx = 8 * kTSY + 1, tile_n = kTZ * 64, EPT = tile_n / kStepThreads;
     double emax = 0.0, vmax = 0.0;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < N3;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        double e = 0.0;
-        for (int l = 0; l < 7; ++l) e += ew.e[l] * static_cast<double>(kval(K, l, B, f, N3, i));
-        e = fabs(h * e);
-        const double vn = Vnew[f * N3 + i];
-        const double sc = at + rtol * fmax(fabs(V[f * N3 + i]), fabs(vn));
-        const double r = e / sc;
-        if (!isfinite(r) || !isfinite(vn)) { emax = INFINITY; vmax = INFINITY; }
-        else { emax = fmax(emax, r); vmax = fmax(vmax, fabs(vn)); }
+    const int ntile = stage_tiles(N, 3);
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {   // uniform over the block
+        int x0, y0, z0;
+        tile_origin(t, N, 3, x0, y0, z0);
+        // this thread's slot sums, slot-6 pp parts, V and Vnew first (held across the barrier)
+        R kv[EPT][7];
+        double vop[EPT], vnp[EPT];
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int e = threadIdx.x + r * kStepThreads;
+            const int lz = e & (kTZ - 1), ly = (e >> 4) & 7, lx = e >> 7;
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            const size_t i =
+                x < N && y < N && zz < N ? (static_cast<size_t>(x) * N + y) * N + zz : 0;
+#pragma unroll
+            for (int l = 0; l < 6; ++l) kv[r][l] = KSf[l * ks + i];
+            kv[r][6] = K6[i];
+            vop[r] = V[f * N3 + i];
+            vnp[r] = Vnew[f * N3 + i];
+        }
+        tile_parts<3>(K6, N3, N, x0, y0, z0, p1, p2);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int e = threadIdx.x + r * kStepThreads;
+            const int lz = e & (kTZ - 1), ly = (e >> 4) & 7, lx = e >> 7;
+            const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+            if (x >= N || y >= N || zz >= N) continue;
+            const int j = lx * tsx + ly * kTSY + lz;
+            const double vo = vop[r], vn = vnp[r];
+            kv[r][6] = part_sum(kv[r][6], p1[j], p2[j]);
+            double es = 0.0;
+#pragma unroll
+            for (int l = 0; l < 7; ++l) es += ew.e[l] * static_cast<double>(kv[r][l]);
+            es = fabs(h * es);
+            const double sc = at + rtol * fmax(fabs(vo), fabs(vn));
+            const double q = es / sc;
+            if (!isfinite(q) || !isfinite(vn)) { emax = INFINITY; vmax = INFINITY; }
+            else { emax = fmax(emax, q); vmax = fmax(vmax, fabs(vn)); }
+        }
+        __syncthreads();
     }
     emax = block_max(emax);
     vmax = block_max(vmax);
@@ -2199,23 +2394,32 @@ void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, 
     // stage tiles 16 x 16 x 16 (64-byte runs in all three layouts) where they give about one
     // block per CU or more and do not raise the LDS of phase-1 blocks, else 8 x 8 x 16
     // (measured: 16 wide at N = 48 and 4 flows, 108 tiles, is 25% slower than 8 wide)
-    const size_t lds16 = static_cast<size_t>(stage_tile_lds(4)) * sizeof(R);
+    const size_t lds16 = 2 * static_cast<size_t>(stage_tile_lds(4)) * sizeof(double);
     const int tl = static_cast<long>(stage_tiles(g.N, 4)) * nf >= 192 &&
                            (nbin == 0 || shm_bins >= lds16) ? 4 : 3;
     const int ns = std::min(stage_tiles(g.N, tl), 1024);  // one stage tile per block round
-    // LDS: the block's bin matrices, or one stage tile
-    const size_t shm = std::max(shm_bins, static_cast<size_t>(stage_tile_lds(tl)) * sizeof(R));
+    // LDS: the block's bin matrices, or the two double tiles of a stage block
+    const size_t shm =
+        std::max(shm_bins, 2 * static_cast<size_t>(stage_tile_lds(tl)) * sizeof(double));
     const dim3 grid(static_cast<unsigned>(nbin + ns), nf);
     R* bins = static_cast<R*>(b.bins);
     R* binsT = static_cast<R*>(b.binsT);
-    if (nbin == 0 || lds)
+    if (nbin == 0)
+        hipLaunchKernelGGL(k_stage<R>, dim3(static_cast<unsigned>(ns), nf), dim3(1024), shm, s,
+                           g, z, b.fs, sc, write_new, Vbase, static_cast<const R*>(b.k),
+                           static_cast<R*>(b.ksum), b.Vnew,
+                           static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
+                           b.T_stage, b.Z_stage, b.zw_stage, b.bstride, tl);
+    else if (lds)
         hipLaunchKernelGGL((k_stage_bins<R, 0, BT, kG, NODES>), grid, dim3(BT), shm, s, g, z, b.fs,
-                           sc, bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+                           sc, bp, write_new, Vbase, static_cast<const R*>(b.k),
+                           static_cast<R*>(b.ksum), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride, tl);
     else if constexpr (NODES == 1)
         hipLaunchKernelGGL((k_stage_bins<R, 1, BT, kG, 1>), grid, dim3(BT), shm, s, g, z, b.fs, sc,
-                           bp, write_new, Vbase, static_cast<const R*>(b.k), b.Vnew,
+                           bp, write_new, Vbase, static_cast<const R*>(b.k),
+                           static_cast<R*>(b.ksum), b.Vnew,
                            static_cast<R*>(b.v0), static_cast<R*>(b.va), static_cast<R*>(b.vc),
                            b.T_stage, b.Z_stage, b.zw_stage, bins, binsT, nRb, b.bstride, tl);
 }
@@ -2476,41 +2680,47 @@ void launch_direct(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, un
                        static_cast<const double*>(b.v0), kslot_ptr<double>(b, slot, N3), ch);
 }
 
-void launch_k_to_f64(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, int slot,
+void launch_k_to_f64(hipStream_t s, bool dbl, const Buffers& b, int nf, int N, int slot,
                      double* out) {
+    const size_t N3 = static_cast<size_t>(N) * N * N;
     if (dbl)
         hipLaunchKernelGGL(k_to_f64<double>, grid_for(N3, nf), dim3(kThreads), 0, s, b.fs,
-                           kslot_ptr<double>(b, slot, N3), out, N3);
+                           kslot_ptr<double>(b, slot, N3), out, N);
     else
         hipLaunchKernelGGL(k_to_f64<float>, grid_for(N3, nf), dim3(kThreads), 0, s, b.fs,
-                           kslot_ptr<float>(b, slot, N3), out, N3);
+                           kslot_ptr<float>(b, slot, N3), out, N);
 }
 
 void launch_fill_u(hipStream_t s, const Buffers& b, int nf, size_t N3, const double* U) {
     hipLaunchKernelGGL(k_fill_u, grid_for(N3, nf), dim3(kThreads), 0, s, b.V, U, N3);
 }
 
-void launch_rk4_update(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V) {
+// (b.nblk blocks per flow, one per tile up to 512, each writing its partial maxima)
+void launch_rk4_update(hipStream_t s, bool dbl, const Buffers& b, int nf, int N, double* V) {
     const dim3 grid(b.nblk, nf);
     if (dbl)
-        hipLaunchKernelGGL(k_rk4_update<double>, grid, dim3(kThreads), 0, s, b.fs,
-                           static_cast<const double*>(b.k), V, b.part, b.nblk, N3, b.bstride);
+        hipLaunchKernelGGL(k_rk4_update<double>, grid, dim3(kStepThreads), 0, s, b.fs,
+                           static_cast<const double*>(b.k),
+                           static_cast<const double*>(b.ksum), V, b.part, b.nblk, N, b.bstride);
     else
-        hipLaunchKernelGGL(k_rk4_update<float>, grid, dim3(kThreads), 0, s, b.fs,
-                           static_cast<const float*>(b.k), V, b.part, b.nblk, N3, b.bstride);
+        hipLaunchKernelGGL(k_rk4_update<float>, grid, dim3(kStepThreads), 0, s, b.fs,
+                           static_cast<const float*>(b.k),
+                           static_cast<const float*>(b.ksum), V, b.part, b.nblk, N, b.bstride);
 }
 
-void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3,
+void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, int N,
                       const double* V, double rtol, const ErrWeights& ew) {
     const dim3 grid(b.nblk, nf);
     if (dbl)
-        hipLaunchKernelGGL(k_dopri_err<double>, grid, dim3(kThreads), 0, s, b.fs,
-                           static_cast<const double*>(b.k), V, b.Vnew, rtol, ew, b.part, b.nblk,
-                           N3, b.bstride);
+        hipLaunchKernelGGL(k_dopri_err<double>, grid, dim3(kStepThreads), 0, s, b.fs,
+                           static_cast<const double*>(b.k),
+                           static_cast<const double*>(b.ksum), V, b.Vnew, rtol, ew, b.part, b.nblk,
+                           N, b.bstride);
     else
-        hipLaunchKernelGGL(k_dopri_err<float>, grid, dim3(kThreads), 0, s, b.fs,
-                           static_cast<const float*>(b.k), V, b.Vnew, rtol, ew, b.part, b.nblk,
-                           N3, b.bstride);
+        hipLaunchKernelGGL(k_dopri_err<float>, grid, dim3(kStepThreads), 0, s, b.fs,
+                           static_cast<const float*>(b.k),
+                           static_cast<const float*>(b.ksum), V, b.Vnew, rtol, ew, b.part, b.nblk,
+                           N, b.bstride);
 }
 
 void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, int fixed_steps) {
