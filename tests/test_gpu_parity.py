@@ -227,29 +227,35 @@ def test_phase1_two_nodes_per_block_matches_one(torch_dev):
         f1.close()
 
 
-def test_stage_wide_tiles_ragged_batch(torch_dev):
+@pytest.mark.parametrize("prec,integ,check", [("fp64", "rk45", "all"), ("fp32", "rk45", "ends"),
+                                              ("fp64", "rk4", "ends")])
+def test_stage_wide_tiles_ragged_batch(torch_dev, prec, integ, check):
     """Eight flows at N = 36 have 216 stage tiles of 16 x 16 x 16 between them, so the later
     stages of a step form the stage argument and its transposed layouts in 16-wide tiles, with
-    ragged edges (36 = 2 * 16 + 4) in all three directions.  A double-precision Dormand-Prince
-    step of the batch must match the oracle's step for every flow."""
+    ragged edges (36 = 2 * 16 + 4) in all three directions; the k slots' crossed and direct
+    parts reach V order through the same tiles in the stage, RK4 update and error-norm
+    kernels.  Each checked flow's step must match the oracle's (FP64: 1e-10, FP32: 1e-4);
+    "ends" checks the first and last flow of the batch."""
     torch, dev = torch_dev
     fm = _fm()
     N, L = 36, 32
     Us = [1.0 + 0.25 * i for i in range(8)]
     V = np.stack([inputs.noisy_state(N, u, seed=31 + i) for i, u in enumerate(Us)])
     lnT, h = math.log(0.2), -0.02
-    f = fm.Flow(N=N, L=L, U=Us[0], precision="fp64", integrator="rk45", max_batch=len(Us),
+    f = fm.Flow(N=N, L=L, U=Us[0], precision=prec, integrator=integ, max_batch=len(Us),
                 device=dev)
     m = O.model(N, L)
     try:
         Vb = torch.from_numpy(V.copy()).to(dev)
         lb, hb, ab = f.step([lnT] * len(Us), [h] * len(Us), Vb)
         got = Vb.cpu().numpy()
-        for i, u in enumerate(Us):
-            ol, oh, oV, oacc, _ = O.step(m, O.flowcfg(U=u, integrator=1), lnT, h, V[i])
+        for i in (range(len(Us)) if check == "all" else (0, len(Us) - 1)):
+            cfg = O.flowcfg(U=Us[i], integrator=1 if integ == "rk45" else 0)
+            ol, oh, oV, oacc, _ = O.step(m, cfg, lnT, h, V[i])
             assert bool(ab[i]) == bool(oacc)
-            assert hb[i] == pytest.approx(oh, rel=1e-9)
-            assert rel(got[i], oV) <= 1e-10, (i, rel(got[i], oV))
+            if prec == "fp64":
+                assert hb[i] == pytest.approx(oh, rel=1e-9)
+            assert rel(got[i], oV) <= TOL[prec], (i, rel(got[i], oV))
     finally:
         f.close()
 
