@@ -892,7 +892,8 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
 }
 
 // The stage argument alone (the later stages of a step): 1024-thread blocks, one element tile
-// per block round, the pp-part and V loads held across the tile's barrier.  Grid (tiles, flows).
+// per block round, each element's loads (newest slot's pp part, earlier slots' sums, V) held
+// across the tile's barrier.  Grid (tiles, flows).
 template <typename R>
 __global__ void __launch_bounds__(1024) k_stage(DevGeom g, DevZ z, const FlowState* fs,
                                                 StageCoef sc, int write_new, const double* Vbase,
@@ -2393,7 +2394,7 @@ void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, 
     const size_t shm_bins = lds ? static_cast<size_t>(per_block) * g.NN * sizeof(R) : 0;
     // stage tiles 16 x 16 x 16 (64-byte runs in all three layouts) where they give about one
     // block per CU or more and do not raise the LDS of phase-1 blocks, else 8 x 8 x 16
-    // (measured: 16 wide at N = 48 and 4 flows, 108 tiles, is 25% slower than 8 wide)
+    // (measured: 16 wide for one flow at N = 48, 27 tiles, is 25% slower than 8 wide)
     const size_t lds16 = 2 * static_cast<size_t>(stage_tile_lds(4)) * sizeof(double);
     const int tl = static_cast<long>(stage_tiles(g.N, 4)) * nf >= 192 &&
                            (nbin == 0 || shm_bins >= lds16) ? 4 : 3;
@@ -2437,9 +2438,9 @@ int nodes_per_block(const DevGeom& g, const BinPlan& bp, int nRb, int nf) {
     return per > 40960 && 2 * per <= 131072 ? 2 : 1;
 }
 
-// Stage argument plus the plan's phase 1 in one launch.  Few (flow, node, representative)
-// triples (at most one per CU): 1024-thread blocks, one element of a stage tile per thread;
-// many: 256-thread blocks, four per thread.
+// Stage argument plus the plan's phase 1 in one launch (without phase 1: k_stage).  Few
+// (flow, node, representative) triples (at most one per CU): 1024-thread blocks; many:
+// 256-thread blocks.
 template <typename R, int kG, int NODES>
 void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
                  const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
