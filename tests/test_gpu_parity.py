@@ -324,6 +324,38 @@ def test_rk45_batch_ragged(torch_dev, prec, tol):
     assert res[2]["status"] == O.REACHED_TEND
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rk45_rejections_in_a_batch(torch_dev, prec):
+    """A first step of -1 in ln T makes the Dormand-Prince control reject many attempts (16
+    for U = 2 in the oracle).  A rejected attempt keeps the step's first k slot (first same
+    as last) and its retry forms that slot's sum again; two flows in one batch must follow
+    the oracle's accept/reject sequence exactly in FP64 and reach its T_c.  The final state
+    (at the divergence, after some 35 attempts near the instability, which amplifies the
+    RHS's rounding-order differences) is held to 1e-8, as in the other adaptive batch test."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L, h0 = 16, 32, -1.0
+    U = [2.0, 1.5]
+    f = fm.Flow(N=N, L=L, U=2.0, precision=prec, integrator="rk45", h0=h0, max_batch=2,
+                device=dev)
+    try:
+        res, Vg = f.run_batch(U, [1.0, 1.0], return_V=True)
+    finally:
+        f.close()
+    Vg = Vg.cpu().numpy()
+    for i in range(2):
+        cfg = O.flowcfg(T0=1.0, U=U[i], integrator=1, h0=h0)
+        Vo, ores, _ = O.flow(O.model(N, L), cfg, U[i])
+        assert ores["n_rejected"] > 0
+        assert res[i]["status"] == ores["status"], (i, res[i], ores)
+        if ores["status"] == O.DIVERGED:
+            assert res[i]["T_c"] == pytest.approx(ores["T_c"], rel=1e-3)
+        if prec == "fp64":
+            assert (res[i]["n_accepted"], res[i]["n_rejected"]) == \
+                (ores["n_accepted"], ores["n_rejected"])
+            assert rel(Vg[i], Vo) <= 1e-8
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2), ("bf16x3", 1e-4)])
 def test_mixed_precision_along_the_fp64_schedule(torch_dev, prec, tol):
     """N = 96, L = 256, U = 3 (the mixed-precision workload's size): the FP64 GPU path (its
