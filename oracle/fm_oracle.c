@@ -71,6 +71,9 @@ typedef struct {
     int gflow;          /* 0: temperature flow, s = ln T; 1: interaction flow, s = g */
     double g_end;       /* interaction flow: from g = 0 to g_end */
     double v_rel;       /* interaction flow: stop when max |V| exceeds v_rel |U| (0: 100) */
+    int rhs_binned;     /* evaluate every right-hand side in the binned form (the same sums
+                           in another order; measures how a flow amplifies rounding-order
+                           differences) */
 } orc_flowcfg;
 
 typedef struct {
@@ -516,17 +519,17 @@ int orc_rhs_points_g(const orc_model *m, double T, double gval, const double *Z,
 
 /* ------------------------------------------------------------------------------------ */
 /* Right-hand side, binned form: the same sums regrouped by the patch pair (a',b') of the  */
-/* two internal lines, B_q(a',b') = sum over j with pi(j)=a', pi(j')=b' of T d/dT chi.    */
-/* Exists only to check that regrouping against the direct form.                          */
+/* two internal lines, B_q(a',b') = sum over j with pi(j)=a', pi(j')=b' of T d/dT chi     */
+/* (chi itself for the interaction flow, whose Z factor depends on the pair's patches     */
+/* only).  Exists to check that regrouping against the direct form, and to measure how a   */
+/* flow amplifies a change of summation order.                                            */
 /* ------------------------------------------------------------------------------------ */
-int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *V, double *dV,
-                   int nthreads)
+static void rhs_binned_geom(const geom *gp, unsigned ch, wkind wk, const double *Z,
+                            const double *V, double *dV)
 {
-    geom g;
-    if (!(T > 0.0) || geom_build(m, &g)) return -1;
-    set_threads(nthreads);
+    const double T = wk.T;
+    const geom g = *gp;
     int N = g.N, L = g.L, np = g.np;
-    unsigned ch = m->channels;
     size_t NN = (size_t)N * N;
     double **bpp = (double **)calloc(np, sizeof(double *));
     double **bph = (double **)calloc(np, sizeof(double *));
@@ -542,11 +545,13 @@ int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *
         for (int j = 0; j < np; ++j) {
             if (bpp[q]) {
                 int jp = partner_pp(L, q, j);
-                bpp[q][(size_t)g.patch[j] * N + g.patch[jp]] += orc_chidot_pp(g.xi[j], g.xi[jp], T);
+                bpp[q][(size_t)g.patch[j] * N + g.patch[jp]] +=
+                    wk.gflow ? orc_chi_pp(g.xi[j], g.xi[jp], T) : orc_chidot_pp(g.xi[j], g.xi[jp], T);
             }
             if (bph[q]) {
                 int jp = partner_ph(L, q, j);
-                bph[q][(size_t)g.patch[j] * N + g.patch[jp]] += orc_chidot_ph(g.xi[j], g.xi[jp], T);
+                bph[q][(size_t)g.patch[j] * N + g.patch[jp]] +=
+                    wk.gflow ? orc_chi_ph(g.xi[j], g.xi[jp], T) : orc_chidot_ph(g.xi[j], g.xi[jp], T);
             }
         }
     }
@@ -560,7 +565,8 @@ int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *
                 double s = 0.0;
                 for (int x = 0; x < N; ++x)
                     for (int y = 0; y < N; ++y) {
-                        double zz = Z ? Z[x] * Z[y] : 1.0;
+                        double zx = Z ? Z[x] : 1.0, zy = Z ? Z[y] : 1.0;
+                        double zz = wk.gflow ? wk.g * zx * zy * (zx + zy) : zx * zy;
                         size_t xy = (size_t)x * N + y;
                         if (ch & 1u) s -= zz * Bp[xy] * V[VIX(N, a, b, x)] * V[VIX(N, x, y, c)];
                         if (ch & 2u) s += zz * Bc[xy] * V[VIX(N, a, x, y)] * V[VIX(N, y, b, c)];
@@ -573,6 +579,16 @@ int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *
             }
     for (int q = 0; q < np; ++q) { free(bpp[q]); free(bph[q]); }
     free(bpp); free(bph);
+}
+
+int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *V, double *dV,
+                   int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    wkind wk = {0, T, 0.0};
+    rhs_binned_geom(&g, m->channels, wk, Z, V, dV);
     geom_free(&g);
     return 0;
 }
@@ -609,7 +625,10 @@ static void eval_f(flowctx *cx, double s, const double *V, double *k)
 {
     z_at(cx->f, cx->g->N, s, cx->Z);
     wkind wk = {cx->f->gflow != 0, cx->f->gflow ? cx->f->T0 : exp(s), cx->f->gflow ? s : 0.0};
-    rhs_geom(cx->g, cx->m->channels, wk, cx->f->n_z > 0 ? cx->Z : NULL, V, k);
+    if (cx->f->rhs_binned)
+        rhs_binned_geom(cx->g, cx->m->channels, wk, cx->f->n_z > 0 ? cx->Z : NULL, V, k);
+    else
+        rhs_geom(cx->g, cx->m->channels, wk, cx->f->n_z > 0 ? cx->Z : NULL, V, k);
     cx->n_rhs++;
 }
 

@@ -45,7 +45,8 @@ class FlowCfg(ctypes.Structure):
                 ("n_steps", c_int), ("rtol", c_double), ("atol", c_double),
                 ("h0", c_double), ("h_min", c_double), ("v_max", c_double),
                 ("n_z", c_int), ("z_lnT", POINTER(c_double)), ("z_tab", POINTER(c_double)),
-                ("gflow", c_int), ("g_end", c_double), ("v_rel", c_double)]
+                ("gflow", c_int), ("g_end", c_double), ("v_rel", c_double),
+                ("rhs_binned", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -229,15 +230,16 @@ def rhs_points(m: Model, T, V, abc, Z=None, nthreads=0):
 # --------------------------------------------------------------------------------------
 def flowcfg(T0=1.0, T_end=0.01, integrator=0, n_steps=200, rtol=1e-6, atol=None, U=1.0,
             h0=0.0, h_min=0.0, v_max=20.0, z_lnT=None, z_tab=None, gflow=False, g_end=1.0,
-            v_rel=100.0):
+            v_rel=100.0, binned=False):
     """Build a FlowCfg; keeps references to the Z arrays on the returned object.  gflow:
     interaction flow at the fixed temperature T0 from g = 0 to g_end (Z nodes in g), stopped
-    when max|V| exceeds v_rel |U|."""
+    when max|V| exceeds v_rel |U|.  binned: every right-hand side in the binned form (the
+    same sums in another order)."""
     if atol is None:
         atol = 1e-9 * max(1.0, abs(U))
     cfg = FlowCfg(float(T0), float(T_end), int(integrator), int(n_steps), float(rtol),
                   float(atol), float(h0), float(h_min), float(v_max), 0, None, None,
-                  int(bool(gflow)), float(g_end), float(v_rel))
+                  int(bool(gflow)), float(g_end), float(v_rel), int(bool(binned)))
     if z_tab is not None:
         z_lnT = np.ascontiguousarray(z_lnT, np.float64)
         z_tab = np.ascontiguousarray(z_tab, np.float64)

@@ -160,7 +160,10 @@ def test_step_g_matches_oracle(torch_dev, integrator, prec):
         f.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3", 1e-3)])
+# Final states of independently adaptive FP64 interaction flows: summed in another order,
+# the oracle's own flows end up to 1.6e-10 apart (U = 3, T = 0.1; tests/test_oracle_dopri.py,
+# test_rounding_order_amplification_of_adaptive_flows), so the final state is held to 1e-9.
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-3), ("bf16x3", 1e-3)])
 def test_gflow_batch_ragged(torch_dev, prec, tol):
     """Four interaction flows in one launch at different temperatures: three diverge at
     different g*, one reaches g = 1."""
