@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the one-loop temperature-flow right-hand side on one MI355X.
 
-Workload (the quasi-particle configuration): square lattice t = 1, t' = 0, mu = 0, U = 3t,
-N = 48 angular Fermi-surface patches, L = 128 loop grid, T from 1.0t towards 0.01t with
-Dormand-Prince steps in ln T, synthetic Z table on the internal lines, single-precision
-right-hand side, double-precision state / error estimate / stop test (stop at max|V| > 20t).
+Workload (the large batch): 16 flows with U_i = 1 + 3i/15, square lattice t = 1, t' = 0,
+mu = 0, N = 128 angular Fermi-surface patches, L = 512 loop grid, T from 1.0t towards 0.01t
+with Dormand-Prince steps in ln T, a synthetic Z table per flow on the internal lines,
+single-precision loop sums with the grouped contractions on bf16 matrix cores, double-
+precision state / error estimate / stop test (stop at max|V| > 20t).
 
-One benchmark step is one complete flow (every right-hand side, stage, error estimate and
-stop test until the flow stops) with its inputs already on the device.  The metric counts
-3 N^3 L^2 coupling-loop-point updates per right-hand side (the direct form's nominal work).
+One benchmark step is the whole 16-flow batch (every right-hand side, stage, error estimate
+and stop test until every flow has stopped) with its inputs already on the device.  The
+metric counts 3 N^3 L^2 coupling-loop-point updates per right-hand side of each flow (the
+direct form's nominal work).
 
 Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
 """
@@ -24,53 +26,99 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6, "bf16_TFs": 2500.0}
+PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6, "bf16_TFs": 2500.0,
+        # plain (non-packed) vector issue: 256 CUs x 64 lanes x 2.4 GHz; packed FP32 is
+        # disabled in these kernels, so a lane-op is one VALU instruction on one lane and an
+        # FP32 FMA is 2 flops of a 78.6 TFLOP/s rate
+        "valu_TOPs": 256 * 64 * 2.4e9 / 1e12, "fp32_fma_TFs": 256 * 64 * 2 * 2.4e9 / 1e12}
 METRIC = "coupling·loop-point updates/s per RHS (N³·L²·3); flows/hour, mixed vs FP64"
-
 
 # Matrix-core peak of each single-precision phase-2a mode (TFLOP/s): split bf16 issues three
 # bf16 products per product.
 MFMA_PEAK = {"fp32": PEAK["fp32_TFs"], "bf16": PEAK["bf16_TFs"], "bf16x3": PEAK["bf16_TFs"] / 3.0}
 
+# Lane-ops priced per bubble-weight evaluation in phase 1 (two exponentials, one reciprocal,
+# about 25 FMA-class operations and the bin update)
+OPS_PER_WEIGHT = 40.0
 
-def kernel_work(name, N, L, nP, nD, rsize, nRp=None, nRd=None, nsets=5, prec="fp32"):
-    """Algorithmic work of one launch of each timed kernel group for one flow.
+
+def bin_density(fm, N, L, stride=16):
+    """Fraction of the N x N patch pairs (a', b') that a transfer's bin actually holds (a loop
+    point of patch a' whose partner lies in patch b'), averaged over every stride-th distinct
+    transfer of each channel kind (the point group maps transfers onto each other with equal
+    density).  Returns (rho_pp, rho_ph)."""
+    import numpy as np
+    cfg = fm.make_config(N, L)
+    _, patch, anchor, npp, nph, _ = fm.geometry_query(cfg)
+    ax, ay = anchor[:, 0].astype(np.int64), anchor[:, 1].astype(np.int64)
+    qpp = np.unique(((ax[:, None] + ax[None, :]) % L) + L * ((ay[:, None] + ay[None, :]) % L))
+    qph = np.unique(((ax[:, None] - ax[None, :]) % L) + L * ((ay[:, None] - ay[None, :]) % L))
+    j = np.arange(L * L)
+    jx, jy = j % L, j // L
+    pj = patch.astype(np.int64)
+    out = []
+    for qs, pp in ((qpp, True), (qph, False)):
+        nnz, sel = 0, qs[::stride]
+        for q in sel:
+            mx, my = q % L, q // L
+            if pp:       # partner of k_j in q - k_j on the half-shifted grid
+                px, py = (mx - jx - 1) % L, (my - jy - 1) % L
+            else:        # partner k_j + q
+                px, py = (mx + jx) % L, (my + jy) % L
+            nnz += np.unique(pj * N + pj[px + L * py]).size
+        out.append(nnz / (len(sel) * N * N))
+    return out[0], out[1]
+
+
+def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", nbin_flows=1):
+    """Algorithmic work of one launch of each timed kernel group for one flow (phase 1: for
+    nbin_flows flows that bin, one per step-sharing group).
 
     stage_bins: phase 1 of every stage node of a Dormand-Prince step (nsets = 5 distinct
-              nodes; the stage argument in the same launch is minor): nsets (nRp + nRd) L^2
-              weight derivatives (orbit representatives), each counted as 6 flops (two
-              differences, one division, the 1/(4 T L^2) scale and the bin accumulation) --
-              the point quantities the kernel evaluates on the fly are not counted
+              nodes) for the orbit representatives, each unordered pair of a transfer's
+              involution once: nsets (nRp + nRd) L^2 / 2 weight evaluations at OPS_PER_WEIGHT
+              lane-ops each, against the plain vector issue rate (bound "alu")
+    y:        the contraction over the bins, weighted by their density rho = (rho_pp, rho_ph):
+              2 (nP rho_pp + 3 nD rho_ph) N^3 flops on the matrix cores of the mode; bytes =
+              representative bins (plus the transposed particle-hole bins) + 3 operand slabs
+              (the products Y that this build stores between phase 2a and 2b are not the
+              method's work and are not counted)
+    contract: 4 N^4 multiply-adds (8 N^4 flops) on the vector units (bound "alu" at the plain
+              FP32 FMA rate)
     stage:    the stage argument alone, timed as a middle stage of a step (four earlier k
               slots): V read (f64), the newest slot's three channel parts and the three
               earlier slots' sums read, the newest slot's sum and three operand layouts
-              written
-    y:        (nP + 3 nD) N^3 multiply-adds on the matrix cores; bytes = representative
-              bins read (plus the transposed particle-hole bins) + 3 operand slabs read + Y
-              written; bound by whichever roof takes longer at its peak: the matrix cores of
-              the mode `prec` (peak MFMA_PEAK[prec]) or HBM
-    contract: 4 N^4 multiply-adds; bytes = Y read + operand read + k written
+              written (bound "hbm")
     """
     NN, N3 = N * N, N ** 3
-    nRp = nP if nRp is None else nRp
-    nRd = nD if nRd is None else nRd
+    opsz = 2 if prec == "bf16" else 4
     if name == "stage_bins":
-        return {"bound": "alu", "flops": 6.0 * nsets * (nRp + nRd) * L * L}
+        return {"bound": "alu", "ops": OPS_PER_WEIGHT * nsets * (nRp + nRd) * L * L / 2.0
+                * nbin_flows, "peak": PEAK["valu_TOPs"], "unit": "TOP/s (lane-ops)"}
     if name == "stage":
-        return {"bound": "hbm", "bytes": N3 * (8 + (3 + 3) * rsize + (1 + 3) * rsize)}
+        return {"bound": "hbm", "bytes": N3 * (8 + (3 + 3) * rsize + (1 + 3) * rsize),
+                "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
     if name == "y":
-        flops = 2.0 * (nP + 3 * nD) * N3
-        nbytes = (nRp + 2 * nRd) * NN * rsize + 3 * N3 * rsize + (nP + 3 * nD) * NN * rsize
-        mma = flops / (MFMA_PEAK[prec] * 1e12) > nbytes / (PEAK["hbm_GBs"] * 1e9)
-        return {"bound": "mfma" if mma else "hbm", "flops": flops, "bytes": nbytes,
-                "peak_TFs": MFMA_PEAK[prec]}
+        flops = 2.0 * (nP * rho[0] + 3 * nD * rho[1]) * N3
+        nbytes = (nRp + 2 * nRd) * NN * rsize + 3 * N3 * opsz
+        return {"bound": "mfma", "flops": flops, "bytes": nbytes, "peak": MFMA_PEAK[prec],
+                "unit": "TFLOP/s"}
     if name == "contract":
-        return {"bound": "hbm", "flops": 8.0 * N ** 4,
-                "bytes": (nP + 3 * nD) * NN * rsize + 2 * N3 * rsize}
+        return {"bound": "alu", "flops": 8.0 * N ** 4, "peak": PEAK["fp32_fma_TFs"],
+                "unit": "TFLOP/s"}
     return None
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2.txt")
+def achieved(wk, avg_s, nflows):
+    """Achieved rate of one launch in the unit of its roof (per-flow work x flows)."""
+    if wk["bound"] == "hbm":
+        return wk["bytes"] * nflows / avg_s / 1e9
+    if "ops" in wk:
+        return wk["ops"] / avg_s / 1e12          # phase 1: already counted for the binning flows
+    return wk["flops"] * nflows / avg_s / 1e12
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c5_16flows.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2005_00827_amd", "csrc", "kernels.hip")
 
 
@@ -168,85 +216,102 @@ def interaction_flow(fm, inputs, torch, dev):
     return out
 
 
-def large_batch(fm, inputs, torch, dev):
-    """16 flows, U = 1 + 3i/15, N=128, L=512, synthetic Z per flow, T 1 -> 0.01: flows/hour for
-    the bf16, split-bf16 and fp32 right-hand sides against the plain FP64 path, T_c agreement,
-    the per-kernel timings (HIP events, eager replay) of the bf16 run, and for bf16 and fp32
-    the roofline of each kernel group with all 16 flows running (10 back-to-back launches on
-    the final state, HIP events on the library stream)."""
+def c5_tables(inputs, w):
     import numpy as np
-    w = inputs.workload("C5")
-    N, L, U, T0 = w["N"], w["L"], w["U"], w["T0"]
-    cfg = fm.make_config(N, L)
-    _, _, _, nP, nD, _ = fm.geometry_query(cfg)
-    nRp, nRd = fm.representative_counts(cfg)
-    nf = len(U)
-    tabs = [inputs.synthetic_z_table(N, u, 1.0, w["T_end"]) for u in U]
-    zl = np.stack([t[0] for t in tabs])
-    zt = np.stack([t[1] for t in tabs])
-    out, tc = {}, {}
-    for prec in ("bf16", "bf16x3", "fp32", "fp64"):
-        f = fm.Flow(N=N, L=L, U=U[0], T0=1.0, T_end=w["T_end"], integrator="rk45", precision=prec,
-                    z_lnT=zl[0], z_table=zt[0], max_batch=len(U), device=dev)
+    tabs = [inputs.synthetic_z_table(w["N"], u, 1.0, w["T_end"]) for u in w["U"]]
+    return np.stack([t[0] for t in tabs]), np.stack([t[1] for t in tabs])
+
+
+def c5_flow(fm, w, zl, zt, dev, prec, rtol=0.0, sync=False):
+    return fm.Flow(N=w["N"], L=w["L"], U=w["U"][0], T0=1.0, T_end=w["T_end"], integrator="rk45",
+                   precision=prec, rtol=rtol, z_lnT=zl[0], z_table=zt[0], max_batch=len(w["U"]),
+                   sync_batch=sync, device=dev)
+
+
+def timed_batch(f, torch, w, zl, zt):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = f.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t0
+
+
+def tc_diff(res, ref):
+    d = [abs(r["T_c"] / q - 1.0) for r, q in zip(res, ref)
+         if math.isfinite(r["T_c"]) and math.isfinite(q)]
+    return max(d) if d else None
+
+
+def c5_other_modes(fm, inputs, torch, dev, w, zl, zt, ref_tc):
+    """The 16-flow batch in the other precisions (each at its default rtol) and in the
+    step-sharing mode: flows/hour, RHS count and the largest T_c difference from the
+    converged FP64 reference."""
+    out = {}
+    for key, prec, sync in (("bf16x3", "bf16x3", False), ("fp32", "fp32", False),
+                            ("fp64", "fp64", False), ("bf16_sync", "bf16", True)):
+        f = c5_flow(fm, w, zl, zt, dev, prec, sync=sync)
+        if prec != "fp64":
+            f.run_batch(w["U"][:2], w["T0"][:2], z_lnT=zl[:2], z_tables=zt[:2])  # tuning
+        res, dt = timed_batch(f, torch, w, zl, zt)
+        r = {"seconds": dt, "flows_per_hour": len(w["U"]) / dt * 3600.0,
+             "rhs": int(sum(x["n_rhs"] for x in res)), "Tc_max_rel_diff": tc_diff(res, ref_tc)}
+        if sync:
+            r["phase1_launch_us"] = f.kernel_time(0, len(w["U"]), 3) * 1e3
+        f.close()
+        out[key] = r
+    return out
+
+
+def c2_single_flow(fm, inputs, torch, dev, steps=5):
+    """The quasi-particle workload of one flow (N=48, L=128, U=3, Z table, f32): updates/s and
+    flows/hour, and its T_c against the FP64 path."""
+    w = inputs.workload("C2")
+    N, L, U, Te = w["N"], w["L"], w["U"][0], w["T_end"]
+    zl, zt = inputs.synthetic_z_table(N, U, 1.0, Te)
+    out = {}
+    tc = {}
+    for prec in ("fp32", "fp64"):
+        f = fm.Flow(N=N, L=L, U=U, T0=1.0, T_end=Te, integrator="rk45", precision=prec,
+                    z_lnT=zl, z_table=zt, device=dev)
+        f.run_batch([U], [1.0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = f.run_batch(U, T0, z_lnT=zl, z_tables=zt)
+        res = [f.run_batch([U], [1.0])[0] for _ in range(steps)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        if prec == "bf16":
-            f.set_timing(True)
-            f.run_batch(U, T0, z_lnT=zl, z_tables=zt)
-            out["kernels_bf16"] = {k: {"launches": n, "avg_us": ms / n * 1e3}
-                                   for k, (ms, n) in f.timings().items()}
-            f.set_timing(False)
-        if prec in ("bf16", "fp32"):
-            roof = {}
-            for name, gid in (("stage_bins", 0), ("y", 1), ("contract", 2), ("stage", 3)):
-                us = f.kernel_time(gid, nf, 10) * 1e3
-                wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, prec=prec)
-                r = {"avg_us": us}
-                if wk["bound"] == "hbm":
-                    r.update(bound="hbm", achieved_GBs=nf * wk["bytes"] / (us * 1e-6) / 1e9)
-                    r["frac"] = r["achieved_GBs"] / PEAK["hbm_GBs"]
-                elif wk["bound"] == "mfma":
-                    r.update(bound="mfma", achieved_TFs=nf * wk["flops"] / (us * 1e-6) / 1e12,
-                             hbm_GBs=nf * wk["bytes"] / (us * 1e-6) / 1e9)
-                    r["frac"] = r["achieved_TFs"] / wk["peak_TFs"]
-                else:
-                    r.update(bound="alu", pair_evals_per_s=nf * wk["flops"] / 6.0 / 2.0 / (us * 1e-6))
-                roof[name] = r
-            out["roofline_16_flows_" + prec] = roof
         f.close()
-        rhs = int(sum(r["n_rhs"] for r in res))
-        tc[prec] = [r["T_c"] for r in res]
-        out["flows_per_hour_" + prec] = len(U) / dt * 3600.0
-        out["seconds_" + prec] = dt
-        out["rhs_" + prec] = rhs
+        rhs = sum(r["n_rhs"] for r in res)
+        tc[prec] = res[0]["T_c"]
         out["updates_per_s_" + prec] = rhs * 3.0 * N ** 3 * L ** 2 / dt
-    for prec in ("bf16", "bf16x3", "fp32"):
-        d = [abs(a / b - 1.0) for a, b in zip(tc[prec], tc["fp64"])
-             if math.isfinite(a) and math.isfinite(b)]
-        out["Tc_max_rel_diff_" + prec] = max(d) if d else None
-    out["note"] = ("first call of each single-precision mode includes the phase-2a tile tuning; "
-                   "bf16 runs at its default rtol 1e-4, the others at 1e-6")
+        out["ms_per_flow_" + prec] = dt / steps * 1e3
+        out["rhs_per_flow_" + prec] = rhs / steps
+    out["Tc_rel_diff_fp32_fp64"] = abs(tc["fp32"] / tc["fp64"] - 1.0)
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="bf16", choices=("bf16", "bf16x3", "fp32"),
+                    help="precision of the headline right-hand side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the batched U x T0 sweep (64 flows) in the extra section")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the large batch (16 flows, N=128, L=512) in the extra section")
-    ap.add_argument("--no-gflow", action="store_true", help="skip the interaction-flow runs")
-    ap.add_argument("--large-only", action="store_true",
-                    help="only the 16-flow N=128, L=512 batch (for profiling); prints its record")
-    ap.add_argument("--cpu-rhs", type=int, default=6, help="oracle RHS evaluations timed")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline batch (for profiling)")
+    ap.add_argument("--cpu-outputs", type=int, default=256,
+                    help="outputs of the 16-flow workload the oracle evaluates for the CPU baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -261,20 +326,12 @@ def main():
     import torch
     from paper_2005_00827_amd import fm, inputs
 
-    if args.large_only:
-        print(json.dumps({"large_16_flows": large_batch(fm, inputs, torch, torch.device("cuda:0"))}))
-        return
-    w = inputs.workload("C2")
-    N, L, U, T0, Te = w["N"], w["L"], w["U"][0], w["T0"][0], w["T_end"]
-    zl, zt = inputs.synthetic_z_table(N, U, T0, Te)
     dev = torch.device("cuda:0")
-    print("bench: C2 N=%d L=%d U=%g fp32 rhs, rk45, Z table; steps=%d warmup=%d"
-          % (N, L, U, args.steps, args.warmup), file=sys.stderr, flush=True)
-
-    def make(prec):
-        return fm.Flow(N=N, L=L, U=U, T0=T0, T_end=Te, integrator="rk45", precision=prec,
-                       z_lnT=zl, z_table=zt, max_batch=1, device=dev)
-
+    w = inputs.workload("C5")
+    N, L, nf = w["N"], w["L"], len(w["U"])
+    zl, zt = c5_tables(inputs, w)
+    print("bench: 16 flows N=%d L=%d U=1..4, Z per flow, %s rhs, rk45; steps=%d warmup=%d"
+          % (N, L, args.prec, args.steps, args.warmup), file=sys.stderr, flush=True)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -283,122 +340,104 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    flow = make("fp32")
-    for _ in range(args.warmup):
-        flow.run_batch([U], [T0])
+    flow = c5_flow(fm, w, zl, zt, dev, args.prec)
+    for _ in range(args.warmup):          # the first call also times the phase-2a variants
+        flow.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [flow.run_batch([U], [T0])[0] for _ in range(args.steps)]
+    runs = [flow.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt) for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    n_rhs = sum(r["n_rhs"] for r in res)
+    n_rhs = sum(r["n_rhs"] for res in runs for r in res)
     upd = 3.0 * N ** 3 * L ** 2
     value = n_rhs * upd / wall
-    print("bench: timed %d flows in %.3f s, %d rhs, T_c %.6f" % (args.steps, wall, n_rhs, res[0]["T_c"]),
+    print("bench: timed %d batches in %.3f s, %d rhs" % (args.steps, wall, n_rhs),
           file=sys.stderr, flush=True)
 
-    # Kernel durations: HIP events on the library's stream around every launch group, over the
-    # same flows replayed eagerly (same kernels, same inputs) -- these include host launch
-    # gaps; the roofline uses the replay measurement below.
+    # launches per batch of each kernel group (HIP events around each launch of one eager
+    # batch), then each group's average launch duration: 10 back-to-back launches with all 16
+    # flows running on the batch's final state, between HIP events on the library's stream
     flow.set_timing(True)
-    for _ in range(args.steps):
-        flow.run_batch([U], [T0])
+    flow.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
     tm = flow.timings()
     flow.set_timing(False)
     cfg = fm.make_config(N, L)
     _, _, _, nP, nD, _ = fm.geometry_query(cfg)
     nRp, nRd = fm.representative_counts(cfg)
-    kernels = {}
-    for name, (ms, n) in tm.items():
-        avg_s = ms / n * 1e-3
-        k = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6}
-        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd)
-        if wk:
-            if wk["bound"] == "hbm":
-                k.update(bound="hbm", achieved=wk["bytes"] / avg_s / 1e9, peak=PEAK["hbm_GBs"],
-                         unit="GB/s")
-            else:
-                k.update(bound=wk["bound"], achieved=wk["flops"] / avg_s / 1e12,
-                         peak=wk.get("peak_TFs", PEAK["fp32_TFs"]), unit="TFLOP/s")
-            k["frac"] = k["achieved"] / k["peak"]
-        kernels[name] = k
-    # Per-launch durations of the three RHS kernel groups: each launched 200 times back to
-    # back on the flow's final state between two HIP events on the library's stream (the
-    # serialized-launch cost is included, host gaps are not).
+    rho = bin_density(fm, N, L)
     groups = {"stage_bins": 0, "y": 1, "contract": 2, "stage": 3}
-    replay = {name: flow.kernel_time(gid, 1, 200) * 1e3 for name, gid in groups.items()}
-    for name, us in replay.items():
-        k = kernels.setdefault(name, {})
-        k["replay_avg_us"] = us
-        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd)
-        if wk and wk["bound"] == "hbm":
-            k["replay_achieved_GBs"] = wk["bytes"] / (us * 1e-6) / 1e9
-        elif wk:
-            k["replay_achieved_TFs"] = wk["flops"] / (us * 1e-6) / 1e12
-    # dominant: the largest share of a flow's time (per-launch duration x launches per flow)
-    dom = max(groups, key=lambda n: replay[n] * kernels[n].get("launches", 0))
-    wk = kernel_work(dom, N, L, nP, nD, 4, nRp, nRd)
-    avg_s = replay[dom] * 1e-6
-    if wk["bound"] == "hbm":
-        ach, peak, unit = wk["bytes"] / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
-    else:
-        ach, peak, unit = wk["flops"] / avg_s / 1e12, wk.get("peak_TFs", PEAK["fp32_TFs"]), "TFLOP/s"
-    roofline = {"kernel": dom, "bound": wk["bound"], "achieved": ach, "peak": peak, "unit": unit,
-                "frac": ach / peak, "traffic": measured_traffic(dom), "avg_us": replay[dom],
-                "launches_per_flow": kernels[dom].get("launches", 0) / args.steps,
-                "timing": "200 back-to-back launches on the flow's final state, HIP events on "
+    kernels = {}
+    for name, gid in groups.items():
+        us = flow.kernel_time(gid, nf, 10) * 1e3
+        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, rho, prec=args.prec, nbin_flows=nf)
+        ach = achieved(wk, us * 1e-6, nf)
+        launches = tm.get(name, (0.0, 0))[1]
+        kernels[name] = {"avg_us": us, "launches_per_batch": launches,
+                         "share_ms_per_batch": us * launches / 1e3, "bound": wk["bound"],
+                         "achieved": ach, "peak": wk["peak"], "unit": wk["unit"],
+                         "frac": ach / wk["peak"]}
+        if name == "y":
+            kernels[name]["achieved_method_GBs"] = wk["bytes"] * nf / (us * 1e-6) / 1e9
+    dom = max(kernels, key=lambda k: kernels[k]["share_ms_per_batch"])
+    kd = kernels[dom]
+    roofline = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+                "unit": kd["unit"], "frac": kd["frac"], "traffic": measured_traffic(dom),
+                "avg_us": kd["avg_us"], "launches_per_batch": kd["launches_per_batch"],
+                "timing": "10 back-to-back launches with all 16 flows running, HIP events on "
                           "the library stream"}
+    flow.close()
 
-    extra = {"flows": args.steps, "rhs_per_flow": n_rhs / args.steps,
-             "T_c_fp32": res[0]["T_c"], "flows_per_hour_fp32": args.steps / wall * 3600.0,
-             "kernels": kernels}
-    if not args.no_fp64:
-        f64 = make("fp64")
-        f64.run_batch([U], [T0])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        r64 = f64.run_batch([U], [T0])[0]
-        torch.cuda.synchronize()
-        w64 = time.perf_counter() - t1
-        extra.update(T_c_fp64=r64["T_c"], flows_per_hour_fp64=3600.0 / w64,
-                     Tc_rel_diff=abs(res[0]["T_c"] / r64["T_c"] - 1.0),
-                     updates_per_s_fp64=r64["n_rhs"] * upd / w64)
-        f64.close()
-
-    if not args.no_sweep:
+    # the converged FP64 reference of the same batch (rtol 1e-8) for the T_c agreement
+    f64 = c5_flow(fm, w, zl, zt, dev, "fp64", rtol=1e-8)
+    ref, ref_dt = timed_batch(f64, torch, w, zl, zt)
+    f64.close()
+    ref_tc = [r["T_c"] for r in ref]
+    extra = {"batches": args.steps, "rhs_per_batch": n_rhs / args.steps,
+             "flows_per_hour": args.steps * nf / wall * 3600.0,
+             "Tc_max_rel_diff_vs_fp64": tc_diff(runs[0], ref_tc),
+             "fp64_reference": {"rtol": 1e-8, "seconds": ref_dt, "T_c": ref_tc},
+             "T_c": [r["T_c"] for r in runs[0]], "status": [r["status"] for r in runs[0]],
+             "bin_density": rho, "kernels": kernels}
+    if not args.no_extra:
+        extra["c5_other_modes"] = c5_other_modes(fm, inputs, torch, dev, w, zl, zt, ref_tc)
+        extra["c2_single_flow"] = c2_single_flow(fm, inputs, torch, dev)
         extra["sweep_64_flows"] = batched_sweep(fm, inputs, torch, dev)
-    if not args.no_gflow:
         extra["interaction_flow"] = interaction_flow(fm, inputs, torch, dev)
-    if not args.no_large:
-        extra["large_16_flows"] = large_batch(fm, inputs, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O   # the checker, timed as the CPU baseline only
         m = O.model(N, L)
-        V = inputs.noisy_state(N, U)
-        Z = np.array([np.interp(math.log(0.2), zl, zt[:, a]) for a in range(N)])
-        O.rhs(O.model(16, 32), 0.2, inputs.noisy_state(16, U))   # load + warm
-        tc = time.perf_counter()
-        for _ in range(args.cpu_rhs):
-            O.rhs(m, 0.2, V, Z=Z)
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": args.cpu_rhs * upd / tcpu, "unit": "coupling·loop-point updates/s",
-               "cores": O.n_threads(), "kind": "oracle",
-               "sample": "%d direct-form RHS evaluations of the same workload (N=48, L=128, "
-                         "Z on, T=0.2) in %.1f s" % (args.cpu_rhs, tcpu)}
+        V = inputs.noisy_state(N, w["U"][8])
+        T = 0.2
+        Z = np.array([np.interp(math.log(T), zl[8], zt[8][:, a]) for a in range(N)])
+        abc = inputs.sample_indices(N, args.cpu_outputs)
+        O.rhs_points(m, T, V, abc[:2], Z=Z)                   # load + warm
+        tc0 = time.perf_counter()
+        O.rhs_points(m, T, V, abc, Z=Z)
+        tcpu = time.perf_counter() - tc0
+        cpu = {"value": args.cpu_outputs * 3.0 * L * L / tcpu,
+               "unit": "coupling·loop-point updates/s", "cores": O.n_threads(), "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": "%d outputs (a,b,c) of one flow's direct-form RHS at N=128, L=512, "
+                         "T=0.2, Z on, each 3 L^2 nominal updates, in %.1f s"
+                         % (args.cpu_outputs, tcpu)}
 
     line = {"metric": METRIC, "value": value, "unit": "coupling·loop-point updates/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "C2 quasi-particle flow: N=48 patches, L=128 loop grid, "
-                                   "U=3t, t'=0, mu=0, T 1.0t->0.01t, Dormand-Prince in ln T, "
-                                   "synthetic Z table, f32 RHS, f64 state, stop at max|V|>20t",
-                       "N": N, "L": L, "U": U, "flows_per_step": 1},
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": {"bf16": "bf16 contraction, f32 loop sums, f64 state",
+                      "bf16x3": "split-bf16 contraction, f32 loop sums, f64 state",
+                      "fp32": "f32, f64 state"}[args.prec],
+            "data": "synthetic",
+            "config": {"workload": "16 flows, U_i = 1 + 3i/15, N=128 patches, L=512 loop grid, "
+                                   "t'=0, mu=0, T 1.0t->0.01t, Dormand-Prince in ln T, synthetic "
+                                   "Z table per flow, %s contraction, f64 state, stop at "
+                                   "max|V|>20t; one step = the whole 16-flow batch" % args.prec,
+                       "N": N, "L": L, "flows_per_step": nf},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line))
-    flow.close()
 
 
 if __name__ == "__main__":

@@ -85,6 +85,11 @@ enum { FM_FLOW_TEMPERATURE = 0, FM_FLOW_INTERACTION = 1 };
 /* Channel mask (for ablations of the flow equation). */
 enum { FM_CH_PP = 1, FM_CH_CR = 2, FM_CH_D = 4, FM_CH_ALL = 7 };
 
+/* Sizes: FM_FP32_BF16MFMA and FM_FP32_BF16X3 need N <= 128 (FM_EINVAL above; their
+ * contractions run on bf16 matrix cores only up to that width); FM_FP32 runs its contractions
+ * on fp32 matrix cores up to N = 128 and on the vector units above; FM_FP64 and
+ * FM_FP64_DIRECT have no bound on N beyond memory. */
+
 /* fm_result.status */
 enum { FM_FLOW_RUNNING = 0, FM_FLOW_DIVERGED = 1, FM_FLOW_NONFINITE = 2,
        FM_FLOW_REACHED_TEND = 3, FM_FLOW_STEPFAIL = 4 };
@@ -132,6 +137,13 @@ typedef struct {
                                  bin row once and applies every operation of its orbit to it
                                  (tile_rows 1, 2, or 4 with bf16 operands); 0 = chosen by
                                  timing with tile_rows on the first call */
+    int sync_batch;           /* fm_flow_run_batch: 1 = flows with equal T0 form a group that
+                                 advances on one step schedule (Dormand-Prince: a step is
+                                 accepted only when every running member accepts it, and the
+                                 next step is the smallest any member proposes), so that every
+                                 stage temperature is shared and the group's phase-1 bins are
+                                 computed once, by its first running member; each flow keeps
+                                 its own stop rule and T_c.  0 = every flow steps on its own */
 } fm_config;
 
 typedef struct {
@@ -155,10 +167,15 @@ int fm_flow_workspace_bytes(const fm_config *cfg, size_t *bytes);
  * point lies within 1e-9 sector widths of a patch boundary. */
 int fm_flow_init(const fm_config *cfg, void *workspace_dev, size_t bytes, fm_flow **out);
 
-/* dV/d ln T for `batch` independent states at temperatures T[batch] (host array):
+/* The right-hand side of the one-loop flow of the static vertex (App. A, Eq.
+ * vertex_flow_general; Z on the internal lines as in Eq. vertex_flow_feedback_Z, projected
+ * onto each line's patch), in the temperature flow: dV/d ln T with the particle-particle,
+ * crossed and direct particle-hole loop sums over the L x L grid, each pair of lines carrying
+ * Z_a' Z_b' T d/dT chi.
+ * `batch` independent states at temperatures T[batch] (host array, T > 0):
  * V_dev and dV_dev are device arrays of batch*N^3 doubles (dV_dev may not alias V_dev).
  * Z (if configured) is taken from the table at ln T.  Asynchronous on cfg.stream.
- * Temperature-flow handles only (FM_EINVAL otherwise). */
+ * Temperature-flow handles only; FM_EINVAL for a bad batch, T or pointer. */
 int fm_flow_rhs(fm_flow *h, int batch, const double *T, const double *V_dev, double *dV_dev);
 
 /* Interaction flow (App. A, Eq. vertex_flow_feedback_Z): dV/dg for `batch` states at
@@ -168,7 +185,10 @@ int fm_flow_rhs(fm_flow *h, int batch, const double *T, const double *V_dev, dou
 int fm_flow_rhs_g(fm_flow *h, int batch, const double *T, const double *g, const double *V_dev,
                   double *dV_dev);
 
-/* One integrator step for `batch` states.  lnT[batch], h[batch] are host in/out arrays
+/* One step of the flow integrated as an ordinary differential equation in the flow
+ * parameter (Sec. 3.2; the scheme is not given in the paper: classical RK4, or
+ * Dormand-Prince 5(4) with the error control below), right-hand sides as fm_flow_rhs.
+ * `batch` states.  lnT[batch], h[batch] are host in/out arrays
  * (ln T and its step; for the interaction flow g and its step, at T = cfg.T0),
  * V_dev (device, batch*N^3 doubles) in/out, accepted[batch] host out.
  * RK4: always accepted, lnT += h, h unchanged.  Dormand-Prince: the step is accepted when
@@ -177,11 +197,16 @@ int fm_flow_rhs_g(fm_flow *h, int batch, const double *T, const double *g, const
 int fm_flow_step(fm_flow *h, int batch, double *lnT, double *hstep, double *V_dev,
                  int *accepted);
 
-/* Runs n_flows independent flows from V = U[f] at T0[f] down to cfg.T_end (interaction
+/* Whole flows with the stop rule of Sec. 3.2 (the largest coupling beyond a threshold
+ * marks the instability; here max|V| > cfg.v_max, crossing T_c interpolated), for a sweep
+ * of bare couplings and start temperatures such as the paper's U-T plane of crossover scales.
+ * Runs n_flows independent flows from V = U[f] at T0[f] down to cfg.T_end (interaction
  * flow: at the fixed temperature T0[f] > 0 from g = 0 to cfg.g_end) or until the stop rule
  * fires, all on the device: one integrator step of every running flow per replay of a
  * captured graph; finished flows are masked.  z_lnT / z_tables: NULL (use cfg's table for
- * every flow, or none) or per-flow host arrays [n_flows][n_zT] and [n_flows][n_zT][N].
+ * every flow, or none) or per-flow host arrays [n_flows][n_zT] and [n_flows][n_zT][N],
+ * checked as fm_flow_init checks the configured table (FM_EINVAL unless every flow's nodes
+ * ascend and every Z lies in (0, 1]).
  * V_final_dev: NULL or a device array of n_flows*N^3 doubles receiving the final states.
  * res[n_flows] (host) receives the outcomes. */
 int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0,

@@ -706,22 +706,54 @@ static double step_factor(double err)
  * the largest |V| above the threshold vth (or a non-finite value) ends the flow.  The
  * temperature flow uses an absolute threshold v_max; the interaction flow the paper's own
  * criterion, relative to the bare coupling, vth = v_rel |U|: since g^2 V_g depends on g^2 U
- * only (without Z), the crossing U* = g*^2 U is then a function of T alone.  The crossing
- * max|V| = v_max is found by interpolating 1/max|V| linearly across the last accepted step,
- * in ln T for the temperature flow and in g^2 for the interaction flow: near an instability
- * the one-loop flow grows like a simple pole in that variable (for one patch
- * 1/v = 1/U - [c(T) - c(T0)], resp. 1/v = 1/U - g^2 c, exactly), so 1/max|V| is nearly
- * linear and the crossing does not depend on where the step boundaries fall. */
-static int stop_test(const orc_flowcfg *f, double vth, double s_prev, double m_prev,
-                     double s_new, double m_new, int finite, double *sc)
+ * only (without Z), the crossing U* = g*^2 U is then a function of T alone.
+ * The crossing max|V| = vth is located on 1/max|V| as a function of x = ln T (temperature
+ * flow) or x = g^2 (interaction flow): near an instability the one-loop flow grows like a
+ * simple pole in that variable (for one patch 1/v = 1/U - [c(T) - c(T0)], resp.
+ * 1/v = 1/U - g^2 c, exactly), so 1/max|V| is smooth and nearly linear.  Its curvature over
+ * a long last step still shifts a straight-line crossing (by ~5e-4 in T_c for the N = 128
+ * workloads at rtol 1e-6), so the crossing is the root of the parabola through the last
+ * three accepted points (x_prev2, x_prev, x_new), inside the last step; with only two points,
+ * or no root inside the step, the straight line through the last two. */
+static double crossing_x(double x0, double m0, double x1, double m1, double x2, double m2,
+                         double vth)
+{
+    if (!(m1 > 0.0) || m2 == m1) return x2;
+    double y1 = 1.0 / m1, y2 = 1.0 / m2, ys = 1.0 / vth;
+    double lin = x1 + (ys - y1) * (x2 - x1) / (y2 - y1);
+    if (!(m0 > 0.0) || x0 == x1) return lin;
+    /* Newton form: y(x) = y1 + (x - x1) d1 + (x - x1)(x - x2) d2 */
+    double d0 = (y1 - 1.0 / m0) / (x1 - x0);
+    double d1 = (y2 - y1) / (x2 - x1);
+    double d2 = (d1 - d0) / (x2 - x0);
+    if (d2 == 0.0) return lin;
+    /* in t = x - x1: d2 t^2 + (d1 - d2 (x2 - x1)) t + (y1 - ys) = 0 */
+    double A = d2, B = d1 - d2 * (x2 - x1), C = y1 - ys;
+    double disc = B * B - 4.0 * A * C;
+    if (!(disc >= 0.0)) return lin;
+    double q = -0.5 * (B + copysign(sqrt(disc), B));
+    double lo = fmin(0.0, x2 - x1), hi = fmax(0.0, x2 - x1);
+    double best = lin, dist = INFINITY;
+    double r[2] = {q != 0.0 ? q / A : NAN, q != 0.0 ? C / q : NAN};
+    for (int i = 0; i < 2; ++i) {
+        if (!(r[i] >= lo && r[i] <= hi)) continue;
+        double x = x1 + r[i];
+        if (fabs(x - lin) < dist) { dist = fabs(x - lin); best = x; }
+    }
+    return best;
+}
+
+/* (s_pp, m_pp): the accepted point before (s_prev, m_prev); m_pp = 0 when there is none. */
+static int stop_test(const orc_flowcfg *f, double vth, double s_pp, double m_pp, double s_prev,
+                     double m_prev, double s_new, double m_new, int finite, double *sc)
 {
     if (!finite) { *sc = s_new; return ORC_NONFINITE; }
     if (m_new > vth) {
-        double u0 = f->gflow ? s_prev * s_prev : s_prev, u1 = f->gflow ? s_new * s_new : s_new;
-        double u = u1;
-        if (m_prev > 0.0 && m_new != m_prev)
-            u = u0 + (1.0 / m_prev - 1.0 / vth) * (u1 - u0) / (1.0 / m_prev - 1.0 / m_new);
-        *sc = f->gflow ? sqrt(u) : u;
+        if (f->gflow)
+            *sc = sqrt(crossing_x(s_pp * s_pp, m_pp, s_prev * s_prev, m_prev, s_new * s_new,
+                                  m_new, vth));
+        else
+            *sc = crossing_x(s_pp, m_pp, s_prev, m_prev, s_new, m_new, vth);
         return ORC_DIVERGED;
     }
     return ORC_RUNNING;
@@ -758,6 +790,7 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
     double vth = f->gflow ? (f->v_rel > 0.0 ? f->v_rel : 100.0) * fabs(U) : f->v_max;
     int finite, status = ORC_RUNNING, nacc = 0, nrej = 0, ntr = 0;
     double mV = max_abs(V, n, &finite), lnTc = NAN;
+    double sp = s, mp = 0.0;      /* the accepted point before (s, mV); none yet */
     if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
     if (!finite) { status = ORC_NONFINITE; lnTc = s; }
     else if (mV > vth) { status = ORC_DIVERGED; lnTc = s; }
@@ -778,7 +811,8 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
             double s_new = (st + 1 == f->n_steps) ? s_end : s0 + (st + 1) * h;
             double m_new = max_abs(V, n, &finite);
             ++nacc;
-            status = stop_test(f, vth, s, mV, s_new, m_new, finite, &lnTc);
+            status = stop_test(f, vth, sp, mp, s, mV, s_new, m_new, finite, &lnTc);
+            sp = s; mp = mV;
             s = s_new; mV = m_new;
             if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
         }
@@ -799,7 +833,8 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
                 memcpy(V, Vn, sizeof(double) * n);
                 memcpy(k[0], k[6], sizeof(double) * n);
                 ++nacc;
-                status = stop_test(f, vth, s, mV, s_new, m_new, finite, &lnTc);
+                status = stop_test(f, vth, sp, mp, s, mV, s_new, m_new, finite, &lnTc);
+                sp = s; mp = mV;
                 s = s_new; mV = m_new;
                 if (trace && ntr < max_trace) { trace[2 * ntr] = s; trace[2 * ntr + 1] = mV; ++ntr; }
                 h = ht * step_factor(err);
@@ -826,6 +861,130 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
     if (V_out) memcpy(V_out, V, sizeof(double) * n);
     if (n_trace) *n_trace = ntr;
     free(V); free(Vn); free(tmp); free(kb); free(Z);
+    geom_free(&g);
+    return 0;
+}
+
+/*
+ * Flows on one step schedule: nf flows from V = U[i], all from the same start (T0, or g = 0
+ * at T = T0), Dormand-Prince only.  Every attempt is made by every running flow with the
+ * same step; it is accepted only if each flow's error norm is <= 1, and the next step follows
+ * from the largest norm of the running flows (the smallest step any of them proposes).  Each
+ * flow keeps its own stop rule and crossing.  Sharing one schedule makes every stage
+ * temperature common to the flows, which is what lets their bubble sums be shared.  atol <= 0
+ * selects 1e-9 max(1, |U_i|) per flow.  V_out: [nf][N^3] or NULL; res: [nf].
+ */
+int orc_flow_sync(const orc_model *m, const orc_flowcfg *f, int nf, const double *U,
+                  double *V_out, orc_result *res, int nthreads)
+{
+    geom g;
+    if (nf < 1 || f->integrator != 1) return -1;
+    if (f->gflow ? !(f->T0 > 0.0 && f->g_end > 0.0) : (!(f->T0 > f->T_end) || !(f->T_end > 0.0)))
+        return -1;
+    if (geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    size_t n = (size_t)g.N * g.N * g.N;
+    double *V = (double *)malloc(sizeof(double) * n * nf);
+    double *Vn = (double *)malloc(sizeof(double) * n * nf);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    double *kb = (double *)malloc(sizeof(double) * n * 7 * nf);
+    double *Z = (double *)malloc(sizeof(double) * g.N);
+    double *err = (double *)malloc(sizeof(double) * nf);
+    double *mV = (double *)malloc(sizeof(double) * nf);
+    double *lnTc = (double *)malloc(sizeof(double) * nf);
+    double *sl = (double *)malloc(sizeof(double) * nf);    /* each flow's last accepted s */
+    double *spp = (double *)malloc(sizeof(double) * nf);   /* and the accepted point before */
+    double *mpp = (double *)calloc(nf, sizeof(double));
+    int *status = (int *)malloc(sizeof(int) * nf);
+    int *nacc = (int *)calloc(nf, sizeof(int));
+    int *nrej = (int *)calloc(nf, sizeof(int));
+    long *nrhs = (long *)calloc(nf, sizeof(long));
+    orc_flowcfg fi = *f;
+    flowctx cx = {&g, m, &fi, Z, 0};
+    double s0 = f->gflow ? 0.0 : log(f->T0), s_end = f->gflow ? f->g_end : log(f->T_end);
+    double s = s0, dir = s_end > s0 ? 1.0 : -1.0;
+    double h = f->h0 != 0.0 ? f->h0 : (s_end - s0) / 200.0;
+    double hmin = f->h_min > 0.0 ? f->h_min : 1e-8 * fabs(s_end - s0);
+    for (int i = 0; i < nf; ++i) {
+        double *Vi = V + (size_t)i * n, *k0 = kb + (size_t)i * 7 * n;
+        for (size_t e = 0; e < n; ++e) Vi[e] = U[i];
+        double vth = f->gflow ? (f->v_rel > 0.0 ? f->v_rel : 100.0) * fabs(U[i]) : f->v_max;
+        int finite;
+        mV[i] = max_abs(Vi, n, &finite);
+        lnTc[i] = NAN;
+        sl[i] = s;
+        spp[i] = s;
+        status[i] = ORC_RUNNING;
+        if (!finite) { status[i] = ORC_NONFINITE; lnTc[i] = s; }
+        else if (mV[i] > vth) { status[i] = ORC_DIVERGED; lnTc[i] = s; }
+        if (status[i] == ORC_RUNNING) { cx.n_rhs = 0; eval_f(&cx, s, Vi, k0); nrhs[i] += cx.n_rhs; }
+    }
+    for (;;) {
+        int any = 0;
+        for (int i = 0; i < nf; ++i) any |= status[i] == ORC_RUNNING;
+        if (!any) break;
+        if (dir * (s - s_end) >= 0.0) {
+            for (int i = 0; i < nf; ++i) if (status[i] == ORC_RUNNING) status[i] = ORC_REACHED_TEND;
+            break;
+        }
+        int last = (dir * (s + h - s_end) >= 0.0);
+        double ht = last ? (s_end - s) : h;
+        double eg = 0.0;
+        for (int i = 0; i < nf; ++i) {
+            if (status[i] != ORC_RUNNING) continue;
+            double *k[7];
+            for (int l = 0; l < 7; ++l) k[l] = kb + ((size_t)i * 7 + l) * n;
+            fi.atol = f->atol > 0.0 ? f->atol : 1e-9 * fmax(1.0, fabs(U[i]));
+            cx.n_rhs = 0;
+            err[i] = dopri_attempt(&cx, s, ht, V + (size_t)i * n, k, Vn + (size_t)i * n, tmp, n);
+            nrhs[i] += cx.n_rhs;
+            if (!(err[i] <= eg)) eg = err[i];          /* a non-finite norm is the largest */
+        }
+        if (eg <= 1.0) {
+            double s_new = last ? s_end : s + ht;
+            for (int i = 0; i < nf; ++i) {
+                if (status[i] != ORC_RUNNING) continue;
+                double *Vi = V + (size_t)i * n, *k0 = kb + (size_t)i * 7 * n;
+                int finite;
+                double m_new = max_abs(Vn + (size_t)i * n, n, &finite);
+                memcpy(Vi, Vn + (size_t)i * n, sizeof(double) * n);
+                memcpy(k0, k0 + 6 * n, sizeof(double) * n);
+                ++nacc[i];
+                double vth = f->gflow ? (f->v_rel > 0.0 ? f->v_rel : 100.0) * fabs(U[i]) : f->v_max;
+                status[i] = stop_test(f, vth, spp[i], mpp[i], s, mV[i], s_new, m_new, finite,
+                                      &lnTc[i]);
+                spp[i] = s; mpp[i] = mV[i];
+                mV[i] = m_new;
+                sl[i] = s_new;
+            }
+            s = s_new;
+            h = ht * step_factor(eg);
+        } else {
+            for (int i = 0; i < nf; ++i) if (status[i] == ORC_RUNNING) ++nrej[i];
+            h = isfinite(eg) ? ht * step_factor(eg) : 0.5 * ht;
+        }
+        if (fabs(h) < hmin)
+            for (int i = 0; i < nf; ++i) if (status[i] == ORC_RUNNING) status[i] = ORC_STEPFAIL;
+    }
+    for (int i = 0; i < nf; ++i) {
+        if (res) {
+            orc_result *r = res + i;
+            int stopped = status[i] == ORC_DIVERGED || status[i] == ORC_NONFINITE;
+            r->status = status[i];
+            r->T_c = (stopped && !f->gflow) ? exp(lnTc[i]) : NAN;
+            r->T_final = f->gflow ? f->T0 : exp(sl[i]);
+            r->g_c = (stopped && f->gflow) ? lnTc[i] : NAN;
+            r->U_star = (stopped && f->gflow) ? lnTc[i] * lnTc[i] * U[i] : NAN;
+            r->g_final = f->gflow ? sl[i] : NAN;
+            r->max_abs_V = mV[i];
+            r->n_accepted = nacc[i];
+            r->n_rejected = nrej[i];
+            r->n_rhs = (int)nrhs[i];
+        }
+        if (V_out) memcpy(V_out + (size_t)i * n, V + (size_t)i * n, sizeof(double) * n);
+    }
+    free(V); free(Vn); free(tmp); free(kb); free(Z); free(err); free(mV); free(lnTc); free(sl);
+    free(spp); free(mpp); free(status); free(nacc); free(nrej); free(nrhs);
     geom_free(&g);
     return 0;
 }

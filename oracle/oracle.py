@@ -93,6 +93,7 @@ def lib():
             "orc_rhs_points": (i, [pm, d, pd, pd, i, pi, pd, i]),
             "orc_flow": (i, [pm, pf, d, pd, pr, pd, i, pi, i]),
             "orc_step": (i, [pm, pf, pd, pd, pd, pi, pd, i]),
+            "orc_flow_sync": (i, [pm, pf, i, pd, pd, pr, i]),
             "orc_dopri_tableau": (i, [pd, pd, pd]),
             "orc_num_threads": (i, []),
         }
@@ -261,6 +262,22 @@ def flow(m: Model, cfg: FlowCfg, U, nthreads=0, max_trace=100000):
                       _pd(trace), max_trace, ctypes.byref(ntr), int(nthreads)):
         raise ValueError("oracle flow rejected its arguments")
     return V.reshape(N, N, N), res.as_dict(), trace[: ntr.value].copy()
+
+
+def flow_sync(m: Model, cfg: FlowCfg, U, nthreads=0):
+    """Dormand-Prince flows from V = U[i] on one shared step schedule (an attempt is accepted
+    only if every running flow accepts it; the next step follows from the largest error
+    norm); cfg.atol <= 0 gives each flow 1e-9 max(1, |U_i|).  Returns (V [nf, N, N, N],
+    [result dicts])."""
+    N = m.N
+    U = np.ascontiguousarray(np.atleast_1d(U), np.float64)
+    nf = U.shape[0]
+    V = np.zeros(nf * N ** 3, np.float64)
+    res = (Result * nf)()
+    if lib().orc_flow_sync(ctypes.byref(m), ctypes.byref(cfg), nf, _pd(U), _pd(V), res,
+                           int(nthreads)):
+        raise ValueError("oracle flow_sync rejected its arguments")
+    return V.reshape(nf, N, N, N), [r.as_dict() for r in res]
 
 
 def step(m: Model, cfg: FlowCfg, lnT, h, V, nthreads=0):

@@ -133,7 +133,14 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.channels == 0) c.channels = FM_CH_ALL;
     if (c.channels & ~7u) { why = "bad channel mask"; return FM_EINVAL; }
     if (c.tile_rows < 0) { why = "tile_rows must be >= 0"; return FM_EINVAL; }
+    // the bf16 matrix-core products stage a whole operand row (N values) per lane group;
+    // there is no bf16 path beyond that width (FP32 runs phase 2a on the vector units there)
+    if ((c.precision == FM_FP32_BF16MFMA || c.precision == FM_FP32_BF16X3) && c.N > 128) {
+        why = "bf16 and split-bf16 precisions support N <= 128";
+        return FM_EINVAL;
+    }
     if (c.y_kernel < 0 || c.y_kernel > 3) { why = "y_kernel must be 0, 1, 2 or 3"; return FM_EINVAL; }
+    if (c.sync_batch != 0 && c.sync_batch != 1) { why = "sync_batch must be 0 or 1"; return FM_EINVAL; }
     return FM_OK;
 }
 
@@ -154,9 +161,12 @@ struct fm_flow {
     // phase-2a kernel variant and row tiles per wavefront (cfg.y_kernel, cfg.tile_rows, or
     // tuned for tuned_nf flows)
     int tpw = 0, yvar = 1, tuned_nf = -1;
-    // graphs of one integrator step, keyed by the number of flows captured
+    // graphs of one integrator step, keyed by the number of flows captured and the
+    // step-sharing groups (count, largest)
     hipGraphExec_t step_exec = nullptr;
-    int step_nf = -1;
+    int step_nf = -1, step_ng = -1, step_gmax = -1;
+    // run_batch's step-sharing groups (0: every flow steps on its own)
+    int ngroups = 0, gmax = 0;
     // timings
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -223,6 +233,8 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.Z_stage = L.take<double>(static_cast<size_t>(B) * N);
     b.zw_stage = L.take<double>(2 * static_cast<size_t>(B));
     b.U = L.take<double>(B);
+    b.grp_members = L.take<int>(B);
+    b.grp_off = L.take<int>(static_cast<size_t>(B) + 1);
     // integrator reduction blocks per flow: one per 8 x 8 x 16 element tile, at most 512
     {
         const size_t nx = (static_cast<size_t>(N) + 7) / 8, nz = (static_cast<size_t>(N) + 15) / 16;
@@ -432,7 +444,12 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps) {
             rhs_launch(h, nf, s, plan.set[s]);
         }
         timed(h, T_UPDATE, [&] { launch_rk4_update(h->stream, h->dbl, h->b, nf, h->g.N, V); });
-        timed(h, T_FINISH, [&] { launch_finish(h->stream, h->b, nf, 0, fixed_steps); });
+        timed(h, T_FINISH, [&] {
+            if (h->ngroups > 0)
+                launch_finish_sync(h->stream, h->b, h->ngroups, h->gmax, 0, fixed_steps, !h->g.gflow);
+            else
+                launch_finish(h->stream, h->b, nf, 0, fixed_steps);
+        });
         return;
     }
     for (int s = 1; s < 7; ++s) {
@@ -443,7 +460,10 @@ void step_launch(fm_flow* h, int nf, double* V, int fixed_steps) {
     std::memcpy(ew.e, kDPE, sizeof ew.e);
     timed(h, T_UPDATE, [&] { launch_dopri_err(h->stream, h->dbl, h->b, nf, h->g.N, V, h->cfg.rtol, ew); });
     timed(h, T_FINISH, [&] {
-        launch_finish(h->stream, h->b, nf, 1, 0);
+        if (h->ngroups > 0)
+            launch_finish_sync(h->stream, h->b, h->ngroups, h->gmax, 1, 0, !h->g.gflow);
+        else
+            launch_finish(h->stream, h->b, nf, 1, 0);
         launch_commit(h->stream, h->dbl, h->b, nf, h->N3, V);
     });
 }
@@ -474,6 +494,8 @@ int upload_z(fm_flow* h, int nf, const double* zl, const double* zt) {
 }
 
 }  // namespace
+
+void fm::set_last_error(const std::string& msg) { g_err = msg; }
 
 extern "C" {
 
@@ -780,6 +802,7 @@ int fm_flow_step(fm_flow* h, int batch, double* lnT, double* hstep, double* V_de
     HIPCHK(hipMemcpyAsync(h->b.fs, h->hfs.data(), sizeof(FlowState) * batch, hipMemcpyHostToDevice, h->stream));
     if (int rc = ensure_tuned(h, batch, V_dev)) return rc;
     untimed(h);
+    h->ngroups = h->gmax = 0;      // a lone step: every state on its own step
     if (rk45) {
         stage_launch(h, batch, dp_stage(0), kOneNode, 0, V_dev);
         rhs_launch(h, batch, 0, 0);
@@ -834,6 +857,17 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     if (!U || !T0 || !res) return fail(FM_EINVAL, "null argument");
     if ((z_lnT == nullptr) != (z_tables == nullptr)) return fail(FM_EINVAL, "give both Z arrays or neither");
     if (z_tables && h->cfg.n_zT == 0) return fail(FM_EINVAL, "per-flow Z tables need cfg.n_zT > 0");
+    if (z_tables) {   // each flow's table as fm_flow_init checks the configured one
+        const int nz = h->cfg.n_zT, N = h->cfg.N;
+        for (int f = 0; f < n; ++f) {
+            const double* l = z_lnT + static_cast<size_t>(f) * nz;
+            const double* t = z_tables + static_cast<size_t>(f) * nz * N;
+            for (int i = 1; i < nz; ++i)
+                if (!(l[i] > l[i - 1])) return fail(FM_EINVAL, "per-flow Z nodes must ascend");
+            for (size_t i = 0; i < static_cast<size_t>(nz) * N; ++i)
+                if (!(t[i] > 0.0 && t[i] <= 1.0)) return fail(FM_EINVAL, "per-flow Z must lie in (0, 1]");
+        }
+    }
     const fm_config& c = h->cfg;
     const bool rk45 = c.integrator == FM_RK45_DOPRI;
     const bool gf = h->g.gflow != 0;
@@ -867,6 +901,33 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         s.n_rhs = (rk45 && s.status == FM_FLOW_RUNNING) ? 1 : 0;
         h->hfs[f] = s;
     }
+    // step-sharing groups: flows with equal T0, in order of first appearance; the first
+    // running member bins for the group
+    h->ngroups = h->gmax = 0;
+    if (c.sync_batch) {
+        std::vector<int> members, off{0};
+        std::vector<char> done(n, 0);
+        for (int f = 0; f < n; ++f) {
+            if (done[f]) continue;
+            int lead = -1;
+            for (int k = f; k < n; ++k) {
+                if (done[k] || T0[k] != T0[f]) continue;
+                done[k] = 1;
+                members.push_back(k);
+                if (lead < 0 && h->hfs[k].status == FM_FLOW_RUNNING) lead = k;
+            }
+            for (size_t i = off.back(); i < members.size(); ++i)
+                h->hfs[members[i]].bshare = lead >= 0 ? lead + 1 : 0;
+            h->gmax = std::max(h->gmax, static_cast<int>(members.size()) - off.back());
+            off.push_back(static_cast<int>(members.size()));
+        }
+        h->ngroups = static_cast<int>(off.size()) - 1;
+        HIPCHK(hipMemcpyAsync(h->b.grp_members, members.data(), sizeof(int) * members.size(),
+                              hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->b.grp_off, off.data(), sizeof(int) * off.size(),
+                              hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
     if (z_tables) {
         int rc = upload_z(h, n, z_lnT, z_tables);
         if (rc) return rc;
@@ -899,7 +960,7 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         HIPCHK(hipStreamSynchronize(h->stream));
     }
     hipStream_t saved = h->stream;
-    if (use_graph && h->step_nf != n) {
+    if (use_graph && (h->step_nf != n || h->step_ng != h->ngroups || h->step_gmax != h->gmax)) {
         if (h->step_exec) { (void)hipGraphExecDestroy(h->step_exec); h->step_exec = nullptr; }
         h->stream = cap;
         hipGraph_t graph = nullptr;
@@ -912,11 +973,15 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         if (graph) (void)hipGraphDestroy(graph);
         h->stream = saved;
         if (e != hipSuccess) {
+            // eager steps on the caller's stream, and every readback on the same stream
             (void)hipGetLastError();
             h->step_exec = nullptr;
             use_graph = false;
+            cap = h->stream;
         } else {
             h->step_nf = n;
+            h->step_ng = h->ngroups;
+            h->step_gmax = h->gmax;
         }
     }
     while (done_steps < max_steps) {

@@ -59,6 +59,9 @@ struct HostGeometry {
 
 bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err);
 
+// The message fm_last_error() returns on the calling thread.
+void set_last_error(const std::string& msg);
+
 // ------------------------------------------------------------------------------------
 // Device-side per-flow integrator state (double precision throughout).
 // ------------------------------------------------------------------------------------
@@ -77,10 +80,13 @@ struct FlowState {
     double atol;     // absolute error tolerance of this flow
     double Tfix;     // interaction flow: the flow's temperature
     double vmax;     // stop threshold on max|V| (v_max, or v_rel |U| in the interaction flow)
+    double sp, mp;   // the accepted point before (lnT, m): s and max|V| (mp = 0: none yet)
     int status;      // FM_FLOW_*
     int accepted;    // outcome of the last attempt
     int n_acc, n_rej, n_rhs;
     int gflow;       // 1: interaction flow
+    int bshare;      // 0: phase 1 bins this flow's own temperatures; else 1 + the flow whose
+                     // bins it reads (flows on one step schedule share every stage temperature)
 };
 
 // Geometry as the kernels see it.
@@ -174,6 +180,8 @@ struct Buffers {
     double* part;                      // [B][nblk][2] reduction partials
     double* wtab;                      // direct mode: [B][nP+nD][np]
     double* U;                         // [B] bare couplings of run_batch
+    int* grp_members;                  // [B] flows of run_batch's step-sharing groups, by group
+    int* grp_off;                      // [B + 1] group g: members grp_off[g] .. grp_off[g+1]
     int nblk;                          // reduction blocks per flow
     int bstride;                       // flows per buffer (max_batch)
 };
@@ -220,6 +228,12 @@ void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, int N,
                       const double* V, double rtol, const ErrWeights& ew);
 // Accept/reject and the stop test against each flow's own threshold (FlowState::vmax).
 void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, int fixed_steps);
+// The same for groups of flows on one step schedule (members[off[g] .. off[g+1]) of group g):
+// a step is accepted when every running member accepts it, and the group's next step is the
+// smallest any member proposes; the first running member bins for the group (its bins are
+// recomputed every step unless `rebind` is 0, as for the interaction flow's fixed bins).
+void launch_finish_sync(hipStream_t s, const Buffers& b, int ngroups, int max_members, int rk45,
+                        int fixed_steps, int rebind);
 void launch_commit(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
 void launch_copy(hipStream_t s, const double* from, double* to, size_t n);
 

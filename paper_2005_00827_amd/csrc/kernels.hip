@@ -110,6 +110,13 @@ __device__ inline double z_interp(const DevZ& z, int f, int N, int a, double lnT
 
 __device__ inline bool running(const FlowState* fs, int f) { return fs[f].status == FM_FLOW_RUNNING; }
 
+// The flow whose phase-1 bins flow f reads: its own, or, for flows that share one step
+// schedule (and so every stage temperature), the group's first running flow.
+__device__ inline int bin_flow(const FlowState* fs, int f) {
+    const int b = fs[f].bshare;
+    return b ? b - 1 : f;
+}
+
 // k slots [slot][flow][pp, crossed, direct][N^3] (R).  Each channel part is stored in the
 // order phase 2b writes it: a phase-2b lane owns the free index n of an output pair's row,
 //   pp part       V(x,y,z) at (x N + y) N + z   (n = z)
@@ -872,6 +879,7 @@ __global__ void __launch_bounds__(BT, 4) k_stage_bins(DevGeom g, DevZ z, const F
     const FlowState st = fs[f];
     const int nbin = nRb * ((bp.n + NODES - 1) / NODES);
     if (static_cast<int>(blockIdx.x) < nbin) {
+        if (bin_flow(fs, f) != f) return;             // another flow bins this temperature
         const int grp = static_cast<int>(blockIdx.x) / nRb;
         const int r = static_cast<int>(blockIdx.x) - grp * nRb;
         const int set0 = grp * NODES;
@@ -948,8 +956,9 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     const size_t N3 = static_cast<size_t>(NN) * N;
     const int nR = g.nRp + g.nRd;
     // kind 1 reads the transposed particle-hole bins, so every kind reads a contiguous row
-    const R* Bf = kind == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
-                            : bins + static_cast<size_t>(f) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int fb = bin_flow(fs, f);
+    const R* Bf = kind == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
+                            : bins + static_cast<size_t>(fb) * nR * NN + (ppk ? 0 : static_cast<size_t>(g.nRp) * NN);
     const int* qrep = ppk ? g.qrep_pp : g.qrep_ph;
     const int* qg = ppk ? g.qg_pp : g.qg_ph;
     const R* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
@@ -1267,8 +1276,9 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     tile_rep(qrep, qg, M, t_begin + 1, lane & 15, r1, o1);
     if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
     const int nR = g.nRp + g.nRd;
-    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
-                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int fb = bin_flow(fs, f);
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
+                              : bins + static_cast<size_t>(fb) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
     // The permutation table, Z and the B chunk: every load in flight before any LDS store
     // (one round trip instead of one per element).
     int pv[4];
@@ -1516,8 +1526,9 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_cls(DevGeom g, const FlowSt
     __syncthreads();                                   // every thread of the block
     if (t_begin >= t_end) return;
     const int nR = g.nRp + g.nRd;
-    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
-                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int fb = bin_flow(fs, f);
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
+                              : bins + static_cast<size_t>(fb) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     const void* B0 = Braw;
     const void* B1 = Braw + kBytes;
@@ -1837,8 +1848,9 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
     const int N = g.N, NN = g.NN;
     const int M = ch == 0 ? g.nP : g.nD;
     const int nR = g.nRp + g.nRd;
-    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(f) * g.nRd * NN
-                              : bins + static_cast<size_t>(f) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int fb = bin_flow(fs, f);
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
+                              : bins + static_cast<size_t>(fb) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
     const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
     const size_t N3 = static_cast<size_t>(NN) * N;
     const size_t yoff = static_cast<size_t>(f) * M * NN;
@@ -1904,13 +1916,15 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                 if (KIND == 2) yb[j] = Yb[static_cast<size_t>(x) * N + n];
             }
             if (n0 == 0 && xg == 0) {
-                // gather the pair vectors while the first Y rows are in flight (at most
-                // kChunk * 128 values, kVec per lane, loaded to registers before any store)
+                // gather the pair vectors while the first Y rows are in flight (kChunk * 128
+                // values per round, kVec per lane, loaded to registers before any store; one
+                // round for N <= 128)
                 constexpr int kVec = kChunk * 128 / 64;
+                for (int e0 = 0; e0 < kChunk * N; e0 += 64 * kVec) {
                 R av[kVec], bv[kVec];
 #pragma unroll
                 for (int v = 0; v < kVec; ++v) {
-                    const int e = min(static_cast<int>(threadIdx.x) + 64 * v, kChunk * N - 1);
+                    const int e = min(e0 + static_cast<int>(threadIdx.x) + 64 * v, kChunk * N - 1);
                     const int i = e / N, x = e - i * N;
                     const int xy = pairs[min(i, cnt - 1)];
                     const int u = xy / N, w = xy - u * N;
@@ -1923,7 +1937,7 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                 }
 #pragma unroll
                 for (int v = 0; v < kVec; ++v) {
-                    const int e = threadIdx.x + 64 * v;
+                    const int e = e0 + threadIdx.x + 64 * v;
                     const int ec = min(e, kChunk * N - 1);
                     const int i = ec / N, x = ec - i * N;
                     const bool ok = e < kChunk * N;
@@ -1937,6 +1951,7 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                             vu[x * kChunk + i] = a;
                         }
                     }
+                }
                 }
                 __syncthreads();
             }
@@ -2043,9 +2058,8 @@ __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState*
     if (!running(fs, f)) return;
     const int N = g.N, NN = g.NN, L = g.L, np = g.np;
     const int a = blockIdx.x / N, b = blockIdx.x - (blockIdx.x / N) * N;
-    const int c = threadIdx.x;
-    if (c >= N) return;
     const size_t N3 = static_cast<size_t>(NN) * N;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
     const double* V = v0 + f * N3;
     const double* Wf = W + static_cast<size_t>(f) * (g.nP + g.nD) * np;
     const int q1 = g.map_pp[a * N + b], q2 = g.map_cr[b * N + c], q3 = g.map_d[a * N + c];
@@ -2076,6 +2090,7 @@ __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState*
     Kf[kpos(0, N, a, b, c)] = -s1;
     Kf[N3 + kpos(1, N, a, b, c)] = s2;
     Kf[2 * N3 + kpos(2, N, a, b, c)] = s3;
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -2248,18 +2263,34 @@ __global__ void __launch_bounds__(kStepThreads) k_dopri_err(const FlowState* fs,
     }
 }
 
-// ln T where max|V| = v_max within the last accepted step [s, s_new] (max|V| from m to
-// mv > v_max): 1/max|V| interpolated linearly in ln T, exact for the pole-like growth of the
-// coupling near an instability.
-__device__ inline double crossing(double s, double m, double s_new, double mv, double v_max) {
-    if (!(m > 0.0) || mv == m) return s_new;
-    return s + (1.0 / m - 1.0 / v_max) * (s_new - s) / (1.0 / m - 1.0 / mv);
+// The crossing max|V| = v_max inside the last accepted step, on 1/max|V| as a function of
+// x = ln T (temperature flow) or x = g^2 (interaction flow), where the coupling grows like a
+// simple pole (1/max|V| smooth and nearly linear): the root of the parabola through the
+// last three accepted points (x0, m0), (x1, m1), (x2, m2) that lies in [x1, x2], found by
+// Newton's method from the straight line through the last two; the straight line itself
+// when there is no earlier point (m0 = 0) or the parabola has no root in the step.
+__device__ inline double crossing(double x0, double m0, double x1, double m1, double x2,
+                                  double m2, double v_max) {
+    if (!(m1 > 0.0) || m2 == m1) return x2;
+    const double y1 = 1.0 / m1, y2 = 1.0 / m2, ys = 1.0 / v_max;
+    const double d1 = (y2 - y1) / (x2 - x1);
+    const double lin = x1 + (ys - y1) / d1;
+    if (!(m0 > 0.0) || x0 == x1) return lin;
+    const double d2 = (d1 - (y1 - 1.0 / m0) / (x1 - x0)) / (x2 - x0);
+    double x = lin;
+    for (int it = 0; it < 8; ++it) {
+        const double r = (x - x1) * d1 + (x - x1) * (x - x2) * d2 - (ys - y1);
+        const double d = d1 + (2.0 * x - x1 - x2) * d2;
+        x -= r / d;
+    }
+    const bool inside = x1 < x2 ? (x >= x1 && x <= x2) : (x >= x2 && x <= x1);
+    return isfinite(x) && inside ? x : lin;
 }
-// Interaction flow (s = -g): 1/max|V| interpolated linearly in g^2 (exact for one patch,
-// where 1/v = 1/U - g^2 c).
+// Interaction flow (s = -g): in g^2, since 1/v = 1/U - g^2 c for one patch.
 __device__ inline double crossing_at(const FlowState& st, double s_new, double mv, double v_max) {
-    if (!st.gflow) return crossing(st.lnT, st.m, s_new, mv, v_max);
-    return -sqrt(crossing(st.lnT * st.lnT, st.m, s_new * s_new, mv, v_max));
+    if (!st.gflow) return crossing(st.sp, st.mp, st.lnT, st.m, s_new, mv, v_max);
+    return -sqrt(crossing(st.sp * st.sp, st.mp, st.lnT * st.lnT, st.m, s_new * s_new, mv,
+                          v_max));
 }
 
 __device__ inline double step_factor(double err) {
@@ -2267,22 +2298,11 @@ __device__ inline double step_factor(double err) {
     return fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.2)));
 }
 
-// Accept/reject, stop rule and the next attempted step, one workgroup per flow.
-__global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double* part, int nblk,
-                                                     int rk45, int fixed_steps) {
-    const int f = blockIdx.x;
-    const bool run = fs[f].status == FM_FLOW_RUNNING;
-    double e = 0.0, mv = 0.0;
-    if (run)
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-            e = fmax(e, part[(static_cast<size_t>(f) * nblk + i) * 2]);
-            mv = fmax(mv, part[(static_cast<size_t>(f) * nblk + i) * 2 + 1]);
-        }
-    e = block_max(e);
-    mv = block_max(mv);
-    if (threadIdx.x != 0) return;
-    FlowState st = fs[f];
-    if (!run) { st.accepted = 0; fs[f] = st; return; }
+// Accept/reject, stop rule and the next attempted step of one flow: e is its own error norm
+// (kept in st.err), ed the norm that decides acceptance and the next step (its own, or the
+// largest of its step-sharing group), mv its max|V| after the attempt.
+__device__ inline void finish_flow(FlowState& st, double e, double ed, double mv, int rk45,
+                                   int fixed_steps) {
     const double s = st.lnT, ht = st.ht, v_max = st.vmax;
     const bool last = ht != st.h;
     if (!rk45) {
@@ -2301,6 +2321,8 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
             st.status = FM_FLOW_DIVERGED;
             st.lnTc = crossing_at(st, s_new, mv, v_max);
         }
+        st.sp = st.lnT;
+        st.mp = st.m;
         st.lnT = s_new;
         st.m = mv;
         if (st.status == FM_FLOW_RUNNING && fixed_steps > 0 && st.n_acc >= fixed_steps)
@@ -2308,7 +2330,7 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
     } else {
         st.err = e;
         st.n_rhs += 6;
-        if (e <= 1.0) {
+        if (ed <= 1.0) {
             const double s_new = last ? st.lnT_end : s + ht;
             st.accepted = 1;
             st.n_acc += 1;
@@ -2316,19 +2338,88 @@ __global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double
                 st.status = FM_FLOW_DIVERGED;
                 st.lnTc = crossing_at(st, s_new, mv, v_max);
             }
+            st.sp = st.lnT;
+            st.mp = st.m;
             st.lnT = s_new;
             st.m = mv;
-            st.h = ht * step_factor(e);
+            st.h = ht * step_factor(ed);
         } else {
             st.accepted = 0;
             st.n_rej += 1;
-            st.h = isfinite(e) ? ht * step_factor(e) : 0.5 * ht;
+            st.h = isfinite(ed) ? ht * step_factor(ed) : 0.5 * ht;
         }
         if (st.status == FM_FLOW_RUNNING && st.lnT <= st.lnT_end) st.status = FM_FLOW_REACHED_TEND;
         if (st.status == FM_FLOW_RUNNING && fabs(st.h) < st.hmin) st.status = FM_FLOW_STEPFAIL;
         st.ht = (st.lnT + st.h <= st.lnT_end) ? st.lnT_end - st.lnT : st.h;
     }
+}
+
+// Largest error norm and max|V| of flow f's partials (every thread returns both).
+__device__ inline void flow_partials(const FlowState* fs, const double* part, int nblk, int f,
+                                     double& e, double& mv) {
+    e = 0.0;
+    mv = 0.0;
+    if (fs[f].status == FM_FLOW_RUNNING)
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+            e = fmax(e, part[(static_cast<size_t>(f) * nblk + i) * 2]);
+            mv = fmax(mv, part[(static_cast<size_t>(f) * nblk + i) * 2 + 1]);
+        }
+    e = block_max(e);
+    mv = block_max(mv);
+}
+
+// One workgroup per flow.
+__global__ void __launch_bounds__(kThreads) k_finish(FlowState* fs, const double* part, int nblk,
+                                                     int rk45, int fixed_steps) {
+    const int f = blockIdx.x;
+    double e, mv;
+    flow_partials(fs, part, nblk, f, e, mv);
+    if (threadIdx.x != 0) return;
+    FlowState st = fs[f];
+    if (st.status != FM_FLOW_RUNNING) { st.accepted = 0; fs[f] = st; return; }
+    finish_flow(st, e, e, mv, rk45, fixed_steps);
     fs[f] = st;
+}
+
+// Flows on one step schedule, one workgroup per group (members[off[g] .. off[g+1]), which
+// all hold the same ln T, h and attempted step): the group's step is decided on the largest
+// error norm of its running members (accepted only if every member accepts; the next step is
+// the smallest any member proposes), each member keeps its own stop rule, T_c and counters.
+// The first member still running then bins for the group.  Shared memory: 2 doubles per member.
+__global__ void __launch_bounds__(kThreads) k_finish_sync(FlowState* fs, const double* part,
+                                                          int nblk, const int* members,
+                                                          const int* off, int rk45,
+                                                          int fixed_steps, int rebind) {
+    extern __shared__ double sm[];
+    const int i0 = off[blockIdx.x], n = off[blockIdx.x + 1] - i0;
+    double* se = sm;
+    double* sv = sm + n;
+    for (int i = 0; i < n; ++i) {      // uniform over the block
+        double e, mv;
+        flow_partials(fs, part, nblk, members[i0 + i], e, mv);
+        if (threadIdx.x == 0) { se[i] = e; sv[i] = mv; }
+    }
+    if (threadIdx.x != 0) return;
+    double eg = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (fs[members[i0 + i]].status == FM_FLOW_RUNNING) eg = fmax(eg, se[i]);
+    int lead = -1;
+    for (int i = 0; i < n; ++i) {
+        const int f = members[i0 + i];
+        FlowState st = fs[f];
+        if (st.status != FM_FLOW_RUNNING) {
+            st.accepted = 0;
+        } else {
+            finish_flow(st, se[i], eg, sv[i], rk45, fixed_steps);
+            if (st.status == FM_FLOW_RUNNING && lead < 0) lead = f;
+        }
+        fs[f] = st;
+    }
+    if (!rebind || lead < 0) return;
+    for (int i = 0; i < n; ++i) {
+        const int f = members[i0 + i];
+        if (fs[f].status == FM_FLOW_RUNNING) fs[f].bshare = lead + 1;
+    }
 }
 
 // After an accepted Dormand-Prince step: V = Vnew and k0 = k6 (first same as last), all
@@ -2676,7 +2767,7 @@ void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {
 void launch_direct(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
                    int slot) {
     const size_t N3 = static_cast<size_t>(g.NN) * g.N;
-    const int threads = ((g.N + 63) / 64) * 64;
+    const int threads = std::min(((g.N + 63) / 64) * 64, kThreads);   // a thread per c, looped
     hipLaunchKernelGGL(k_direct, dim3(g.NN, nf), dim3(threads), 0, s, g, b.fs, b.wtab,
                        static_cast<const double*>(b.v0), kslot_ptr<double>(b, slot, N3), ch);
 }
@@ -2727,6 +2818,13 @@ void launch_dopri_err(hipStream_t s, bool dbl, const Buffers& b, int nf, int N,
 void launch_finish(hipStream_t s, const Buffers& b, int nf, int rk45, int fixed_steps) {
     hipLaunchKernelGGL(k_finish, dim3(nf), dim3(kThreads), 0, s, b.fs, b.part, b.nblk, rk45,
                        fixed_steps);
+}
+
+void launch_finish_sync(hipStream_t s, const Buffers& b, int ngroups, int max_members, int rk45,
+                        int fixed_steps, int rebind) {
+    hipLaunchKernelGGL(k_finish_sync, dim3(ngroups), dim3(kThreads),
+                       2 * static_cast<size_t>(max_members) * sizeof(double), s, b.fs, b.part,
+                       b.nblk, b.grp_members, b.grp_off, rk45, fixed_steps, rebind);
 }
 
 void launch_commit(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V) {

@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
                 ("v_max", c_double), ("channels", c_uint), ("precision", c_int),
                 ("n_zT", c_int), ("z_lnT", POINTER(c_double)), ("z_table", POINTER(c_double)),
                 ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int),
-                ("flow", c_int), ("g_end", c_double), ("v_rel", c_double), ("y_kernel", c_int)]
+                ("flow", c_int), ("g_end", c_double), ("v_rel", c_double), ("y_kernel", c_int),
+                ("sync_batch", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -116,7 +117,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
                 integrator="rk4", n_steps=200, rtol=0.0, atol=0.0, h0=0.0, h_min=0.0,
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
                 stream=None, max_batch=1, tile_rows=0, flow="temperature", g_end=0.0,
-                v_rel=0.0, y_kernel=0):
+                v_rel=0.0, y_kernel=0, sync_batch=False):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
     cfg.geometry = GEOM_IDENTITY if geometry == "identity" else GEOM_ANGULAR
@@ -144,6 +145,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
     cfg.g_end = float(g_end)
     cfg.v_rel = float(v_rel)
     cfg.y_kernel = int(y_kernel)
+    cfg.sync_batch = int(bool(sync_batch))
     cfg._keep = keep
     return cfg
 
@@ -264,6 +266,13 @@ class Flow:
         n = U.shape[0]
         zl = None if z_lnT is None else np.ascontiguousarray(z_lnT, np.float64)
         zt = None if z_tables is None else np.ascontiguousarray(z_tables, np.float64)
+        if (zl is None) != (zt is None):
+            raise ValueError("give both per-flow Z arrays or neither")
+        if zt is not None:
+            nz = self.cfg.n_zT
+            if zl.shape != (n, nz) or zt.shape != (n, nz, self.N):
+                raise ValueError("per-flow Z arrays must be [n_flows, n_zT] and "
+                                 "[n_flows, n_zT, N] with the configured n_zT = %d" % nz)
         res = (Result * n)()
         Vout = None
         if return_V:

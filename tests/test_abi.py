@@ -80,6 +80,8 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=16, L=32, y_kernel=4), "y_kernel"),
     (dict(N=16, L=32, flow="interaction", T0=0.0), "T0 > 0"),
     (dict(N=16, L=32, flow="interaction", T0=0.2, g_end=-1.0), "g_end"),
+    (dict(N=136, L=128, precision="bf16"), "N <= 128"),
+    (dict(N=136, L=128, precision="bf16x3"), "N <= 128"),
 ])
 def test_invalid_configs_rejected(kw, msg):
     cfg = fm.make_config(**kw)

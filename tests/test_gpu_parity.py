@@ -169,6 +169,24 @@ def test_rhs_large_sampled(torch_dev, N, L, prec, y_kernel):
         assert rel(d[np.ix_(r, r, r)], d) <= 1e-12
 
 
+@pytest.mark.parametrize("N,L,prec", [(136, 128, "fp64"), (136, 128, "fp32"),
+                                      (264, 64, "fp64_direct")])
+def test_rhs_above_128_patches_sampled(torch_dev, N, L, prec):
+    """More than 128 patches: phase 2b gathers its pair vectors in several rounds, FP32
+    phase 2a runs on the vector units, and the direct kernel loops its threads over the
+    outgoing patch (264 > 256 threads per block).  Sampled outputs against the oracle; bf16
+    modes reject this size."""
+    fm = _fm()
+    V = inputs.noisy_state(N, 3.0)
+    T = 0.08
+    abc = inputs.sample_indices(N, 48)
+    ref = O.rhs_points(O.model(N, L), T, V, abc)
+    got = gpu_rhs(torch_dev, N, L, T, V, prec)[0]
+    assert rel(got[abc[:, 0], abc[:, 1], abc[:, 2]], ref) <= TOL[prec]
+    with pytest.raises(fm.FmError):
+        fm.Flow(N=N, L=L, precision="bf16", device=torch_dev[1])
+
+
 @pytest.mark.parametrize("integrator", ["rk4", "rk45"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_step_matches_oracle(torch_dev, integrator, prec):
@@ -429,6 +447,83 @@ def test_flow_with_z_feedback_fp64(torch_dev):
     assert res[0]["status"] == ores["status"]
     assert res[0]["T_c"] == pytest.approx(ores["T_c"], rel=1e-6)
     assert rel(Vg.cpu().numpy()[0], Vo) <= ADAPTIVE_FINAL_FP64
+
+
+def test_run_batch_per_flow_z_tables(torch_dev):
+    """Three flows in one batch, each with its own Z table (the synthetic table of its own
+    U, one of them with fewer nodes' worth of variation), against the oracle's flows with the
+    same tables; then a table that is not ascending, or has a Z outside (0, 1], is refused."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L = 16, 32
+    U = [3.0, 2.5, 3.5]
+    tabs = [inputs.synthetic_z_table(N, u, 1.0, 0.01) for u in U]
+    zl = np.stack([t[0] for t in tabs])
+    zt = np.stack([t[1] for t in tabs])
+    zt[1] = np.sqrt(zt[1])          # a different table shape for the second flow
+    f = fm.Flow(N=N, L=L, U=U[0], precision="fp64", integrator="rk45", z_lnT=zl[0],
+                z_table=zt[0], max_batch=3, device=dev)
+    try:
+        res, Vg = f.run_batch(U, [1.0] * 3, z_lnT=zl, z_tables=zt, return_V=True)
+        Vg = Vg.cpu().numpy()
+        for i in range(3):
+            Vo, ores, _ = O.flow(O.model(N, L), O.flowcfg(U=U[i], integrator=1, z_lnT=zl[i],
+                                                         z_tab=zt[i]), U[i])
+            assert res[i]["status"] == ores["status"] == O.DIVERGED
+            assert res[i]["T_c"] == pytest.approx(ores["T_c"], rel=1e-6)
+            assert rel(Vg[i], Vo) <= ADAPTIVE_FINAL_FP64
+        bad = zl.copy()
+        bad[2, 5] = bad[2, 4]
+        with pytest.raises(fm.FmError):
+            f.run_batch(U, [1.0] * 3, z_lnT=bad, z_tables=zt)
+        bad = zt.copy()
+        bad[0, 3, 7] = 1.5
+        with pytest.raises(fm.FmError):
+            f.run_batch(U, [1.0] * 3, z_lnT=zl, z_tables=bad)
+        with pytest.raises(ValueError):
+            f.run_batch(U, [1.0] * 3, z_lnT=zl[:, :-1], z_tables=zt)
+    finally:
+        f.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("flow", ["temperature", "interaction"])
+def test_sync_batch_against_oracle(torch_dev, prec, flow):
+    """sync_batch: flows with equal T0 (for the interaction flow: equal temperature) step on
+    one schedule, and each group's bins are computed once, by its first running flow (the
+    one diverging first hands that over).  Six flows in two interleaved groups against the
+    oracle's shared-schedule flows of each group: FP64 with the oracle's exact accept/reject
+    counts, T_c (g*) to 1e-9 and V to ADAPTIVE_FINAL_FP64; FP32 status and T_c (g*) to
+    1e-3."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L = 16, 32
+    gf = flow == "interaction"
+    U = [2.5, 2.2, 2.0, 1.5, 1.8, 0.4] if not gf else [3.0, 2.6, 2.5, 0.5, 3.5, 4.0]
+    T0 = [1.0, 0.7, 1.0, 1.0, 0.7, 1.0] if not gf else [0.1, 0.05, 0.1, 0.1, 0.05, 0.1]
+    f = fm.Flow(N=N, L=L, U=U[0], T0=T0[0], precision=prec, integrator="rk45",
+                flow=flow, max_batch=6, sync_batch=True, device=dev)
+    try:
+        res, Vg = f.run_batch(U, T0, return_V=True)
+    finally:
+        f.close()
+    Vg = Vg.cpu().numpy()
+    m = O.model(N, L)
+    key = "g_c" if gf else "T_c"
+    for t0 in sorted(set(T0)):
+        idx = [i for i in range(6) if T0[i] == t0]
+        Vo, ro = O.flow_sync(m, O.flowcfg(T0=t0, integrator=1, atol=0.0, gflow=gf),
+                             [U[i] for i in idx])
+        assert any(r["status"] == O.DIVERGED for r in ro)
+        for j, i in enumerate(idx):
+            assert res[i]["status"] == ro[j]["status"], (i, res[i], ro[j])
+            if ro[j]["status"] == O.DIVERGED:
+                tol = 1e-9 if prec == "fp64" else 1e-3
+                assert abs(res[i][key] / ro[j][key] - 1.0) <= tol, (i, res[i][key], ro[j][key])
+            if prec == "fp64":
+                assert (res[i]["n_accepted"], res[i]["n_rejected"], res[i]["n_rhs"]) == \
+                    (ro[j]["n_accepted"], ro[j]["n_rejected"], ro[j]["n_rhs"]), (i, res[i], ro[j])
+                assert rel(Vg[i], Vo[j]) <= ADAPTIVE_FINAL_FP64, (i, rel(Vg[i], Vo[j]))
 
 
 @pytest.mark.parametrize("case", ["U2.5", "U2_h0-1", "U3_Z"])

@@ -109,10 +109,30 @@ def test_n1_attractive_tc(integrator, n):
     V, res, tr = O.flow(O.model(1, L1), cfg, U)
     assert res["status"] == O.DIVERGED
     assert res["T_c"] == pytest.approx(tc, rel=1e-3)
-    # the stop rule: the crossing of 1/max|V| = 1/v_max, linear in ln T over the last step
+    # the stop rule: the crossing of 1/max|V| = 1/v_max on the parabola in ln T through the
+    # last three accepted points, inside the last step
     (s0, m0), (s1, m1) = tr[-2], tr[-1]
     assert m0 <= vmax < m1
-    assert math.log(res["T_c"]) == pytest.approx(O.tc_interp(s0, m0, s1, m1, vmax), abs=1e-14)
+    coef = np.polyfit(tr[-3:, 0], 1.0 / tr[-3:, 1], 2)
+    coef[-1] -= 1.0 / vmax
+    roots = [r.real for r in np.roots(coef) if abs(r.imag) < 1e-12 and s1 <= r.real <= s0]
+    assert len(roots) == 1
+    assert math.log(res["T_c"]) == pytest.approx(roots[0], abs=1e-10)
+
+
+@pytest.mark.parametrize("rtol", [1e-4, 1e-6])
+def test_n1_crossing_through_three_points_tracks_the_closed_form(rtol):
+    """With long steps near the instability (loose rtol), the crossing on the parabola
+    through the last three points stays within 1e-4 of the closed-form T_c; the straight line
+    through the last two is what the curvature of 1/max|V| over the step moves."""
+    U, vmax = -2.0, 20.0
+    tc = _tc_exact(U, vmax)
+    cfg = O.flowcfg(T0=1.0, T_end=0.01, integrator=1, rtol=rtol, v_max=vmax, U=U)
+    _, res, tr = O.flow(O.model(1, L1), cfg, U)
+    assert res["status"] == O.DIVERGED
+    assert abs(res["T_c"] / tc - 1.0) < 1e-4, (res["T_c"], tc)
+    lin = math.exp(O.tc_interp(tr[-2, 0], tr[-2, 1], tr[-1, 0], tr[-1, 1], vmax))
+    assert abs(res["T_c"] / tc - 1.0) <= abs(lin / tc - 1.0)
 
 
 def test_stop_at_start_and_stepfail():
@@ -274,3 +294,36 @@ def test_step_matches_flow():
             assert np.abs(V2).max() == pytest.approx(tr[k][1], rel=1e-15)
             lnT, V, k = lnT2, V2, k + 1
         h = h2
+
+
+# --------------------------------------------------------------------------------------
+# flows on one shared step schedule
+# --------------------------------------------------------------------------------------
+def test_sync_batch_of_one_is_the_plain_flow():
+    """One flow on a 'shared' schedule takes exactly the plain Dormand-Prince flow's steps."""
+    m = O.model(16, 32)
+    V1, r1, _ = O.flow(m, O.flowcfg(U=2.5, integrator=1), 2.5)
+    Vs, rs = O.flow_sync(m, O.flowcfg(integrator=1, atol=0.0), [2.5])
+    assert np.array_equal(V1, Vs[0])
+    for k in ("status", "T_c", "T_final", "n_accepted", "n_rejected", "n_rhs", "max_abs_V"):
+        assert rs[0][k] == r1[k], k
+
+
+def test_sync_batch_closed_form_and_shared_steps():
+    """Attractive one-patch flows of different U on one schedule: each reaches its own
+    closed-form T_c (the stop rule stays per flow), every running flow makes every attempt
+    (equal counts while both run), and the group takes at least as many steps as either
+    flow alone (its step is the smallest either proposes)."""
+    m = O.model(1, L1)
+    Us = [-3.0, -2.0]
+    _, rs = O.flow_sync(m, O.flowcfg(T0=1.0, T_end=0.01, integrator=1, atol=0.0), Us)
+    for U, r in zip(Us, rs):
+        assert r["status"] == O.DIVERGED
+        assert r["T_c"] == pytest.approx(_tc_exact(U, 20.0), rel=1e-3)
+        _, r1, _ = O.flow(m, O.flowcfg(T0=1.0, T_end=0.01, integrator=1, U=U), U)
+        assert r["n_accepted"] + r["n_rejected"] >= r1["n_accepted"] + r1["n_rejected"]
+        assert r["T_c"] == pytest.approx(r1["T_c"], rel=1e-4)
+    # -3 diverges first; until then the two flows share every attempt
+    assert rs[0]["T_c"] > rs[1]["T_c"]
+    assert rs[1]["n_accepted"] >= rs[0]["n_accepted"]
+    assert rs[0]["n_rhs"] == 1 + 6 * (rs[0]["n_accepted"] + rs[0]["n_rejected"])
