@@ -178,6 +178,20 @@ int fm_flow_init(const fm_config *cfg, void *workspace_dev, size_t bytes, fm_flo
  * Temperature-flow handles only; FM_EINVAL for a bad batch, T or pointer. */
 int fm_flow_rhs(fm_flow *h, int batch, const double *T, const double *V_dev, double *dV_dev);
 
+/* For callers that cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc): fm_flow_rhs with the library's own static device array
+ * as the workspace, so the caller passes only the inputs and outputs.  cfg, batch, T, V_dev,
+ * dV_dev as fm_flow_init and fm_flow_rhs (batch <= cfg->max_batch; cfg->stream is used).
+ * The array holds 96 MiB per device (one flow of the N = 48, L = 128 workloads fits); a
+ * configuration whose workspace would be larger gives FM_EINVAL.  Each device holds its own
+ * array for the life of the process, shared by every call on that device: the first call
+ * (and any call whose configuration differs from the previous one) builds the geometry into
+ * it, later calls with an equal configuration reuse it.  Calls that overlap in time on one
+ * device (other threads, or other streams still running) race on the array.  It allocates
+ * no device memory and calls no allocating library routine. */
+int fm_flow_rhs_static(const fm_config *cfg, int batch, const double *T, const double *V_dev,
+                       double *dV_dev);
+
 /* Interaction flow (App. A, Eq. vertex_flow_feedback_Z): dV/dg for `batch` states at
  * temperatures T[batch] and scales g[batch] (host arrays, T > 0, g finite); Z (if
  * configured) from the table at g.  Layout, aliasing and streams as fm_flow_rhs.

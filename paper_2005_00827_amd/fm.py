@@ -31,7 +31,7 @@ INTEGRATORS = {"rk4": RK4_FIXED, "rk45": RK45_DOPRI}
 EXPORTS = ("fm_flow_workspace_bytes", "fm_flow_init", "fm_flow_rhs", "fm_flow_rhs_g",
            "fm_flow_step", "fm_flow_run_batch", "fm_flow_tstar", "fm_geometry_query",
            "fm_flow_set_timing", "fm_flow_timings", "fm_flow_kernel_time", "fm_flow_destroy",
-           "fm_last_error")
+           "fm_last_error", "fm_flow_rhs_static")
 FLOWS = {"temperature": 0, "interaction": 1}
 
 
@@ -90,6 +90,7 @@ def load():
         "fm_flow_set_timing": (c_int, [c_void_p, c_int]),
         "fm_flow_timings": (c_int, [c_void_p, POINTER(c_char_p), pd, pi, c_int]),
         "fm_flow_kernel_time": (c_int, [c_void_p, c_int, c_int, c_int, pd]),
+        "fm_flow_rhs_static": (c_int, [pc, c_int, pd, c_void_p, c_void_p]),
         "fm_flow_destroy": (None, [c_void_p]),
         "fm_last_error": (c_char_p, []),
     }
@@ -304,6 +305,32 @@ class Flow:
         if k < 0:
             _check(k)
         return {names[i].decode(): (float(ms[i]), int(n[i])) for i in range(k)}
+
+
+def rhs_static(T, V, out=None, device=None, **kw):
+    """fm_flow_rhs_static: dV/d ln T like Flow.rhs, with the library's static device array as
+    the workspace (no allocation; one flow of the N = 48, L = 128 workloads fits).  kw as
+    make_config; the stream defaults to torch's current stream."""
+    import torch
+    dev = torch.device(device or "cuda:0")
+    if kw.get("stream") is None:
+        kw["stream"] = torch.cuda.current_stream(dev).cuda_stream
+    cfg = make_config(**kw)
+    if not (isinstance(V, torch.Tensor) and V.is_cuda and V.dtype == torch.float64
+            and V.is_contiguous()):
+        raise TypeError("V must be a contiguous float64 CUDA tensor")
+    n3 = cfg.N ** 3
+    if V.numel() % n3:
+        raise ValueError("V must hold batch x N^3 values")
+    b = V.numel() // n3
+    T = np.ascontiguousarray(np.atleast_1d(T), np.float64)
+    if T.shape[0] != b:
+        raise ValueError("one temperature per state")
+    if out is None:
+        out = torch.empty_like(V)
+    _check(load().fm_flow_rhs_static(ctypes.byref(cfg), b, _pd(T), c_void_p(V.data_ptr()),
+                                     c_void_p(out.data_ptr())))
+    return out
 
 
 def hubbard_flow(N, L, **kw):
