@@ -82,7 +82,8 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", 
               2 (nP rho_pp + 3 nD rho_ph) N^3 flops on the matrix cores of the mode; bytes =
               representative bins (plus the transposed particle-hole bins) + 3 operand slabs
               (the products Y that this build stores between phase 2a and 2b are not the
-              method's work and are not counted)
+              method's work and are not counted); bound by HBM or the matrix cores, whichever
+              takes longer at its peak
     contract: 4 N^4 multiply-adds (8 N^4 flops) on the vector units (bound "alu" at the plain
               FP32 FMA rate)
     stage:    the stage argument alone, timed as a middle stage of a step (four earlier k
@@ -101,6 +102,10 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", 
     if name == "y":
         flops = 2.0 * (nP * rho[0] + 3 * nD * rho[1]) * N3
         nbytes = (nRp + 2 * nRd) * NN * rsize + 3 * N3 * opsz
+        # the binding roof: whichever takes longer at its peak for this work
+        if nbytes / (PEAK["hbm_GBs"] * 1e9) > flops / (MFMA_PEAK[prec] * 1e12):
+            return {"bound": "hbm", "flops": flops, "bytes": nbytes, "peak": PEAK["hbm_GBs"],
+                    "unit": "GB/s"}
         return {"bound": "mfma", "flops": flops, "bytes": nbytes, "peak": MFMA_PEAK[prec],
                 "unit": "TFLOP/s"}
     if name == "contract":
@@ -222,7 +227,7 @@ def c5_tables(inputs, w):
     return np.stack([t[0] for t in tabs]), np.stack([t[1] for t in tabs])
 
 
-def c5_flow(fm, w, zl, zt, dev, prec, rtol=0.0, sync=False):
+def c5_flow(fm, w, zl, zt, dev, prec, rtol=0.0, sync=0):
     return fm.Flow(N=w["N"], L=w["L"], U=w["U"][0], T0=1.0, T_end=w["T_end"], integrator="rk45",
                    precision=prec, rtol=rtol, z_lnT=zl[0], z_table=zt[0], max_batch=len(w["U"]),
                    sync_batch=sync, device=dev)
@@ -243,20 +248,20 @@ def tc_diff(res, ref):
 
 
 def c5_other_modes(fm, inputs, torch, dev, w, zl, zt, ref_tc):
-    """The 16-flow batch in the other precisions (each at its default rtol) and in the
-    step-sharing mode: flows/hour, RHS count and the largest T_c difference from the
-    converged FP64 reference."""
+    """The 16-flow batch with every flow stepping on its own, in step-sharing groups of 2 and
+    of all 16, and in the other precisions (each at its default rtol): flows/hour, RHS count,
+    the largest T_c difference from the converged FP64 reference, and the phase-1 launch."""
     out = {}
-    for key, prec, sync in (("bf16x3", "bf16x3", False), ("fp32", "fp32", False),
-                            ("fp64", "fp64", False), ("bf16_sync", "bf16", True)):
+    for key, prec, sync in (("bf16_independent", "bf16", 0), ("bf16_sync2", "bf16", 2),
+                            ("bf16_sync16", "bf16", 1), ("bf16x3_sync2", "bf16x3", 2),
+                            ("fp32_sync2", "fp32", 2), ("fp64", "fp64", 0)):
         f = c5_flow(fm, w, zl, zt, dev, prec, sync=sync)
-        if prec != "fp64":
-            f.run_batch(w["U"][:2], w["T0"][:2], z_lnT=zl[:2], z_tables=zt[:2])  # tuning
+        if prec != "fp64":    # tuning and the batch's step graph, outside the timed run
+            f.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
         res, dt = timed_batch(f, torch, w, zl, zt)
         r = {"seconds": dt, "flows_per_hour": len(w["U"]) / dt * 3600.0,
              "rhs": int(sum(x["n_rhs"] for x in res)), "Tc_max_rel_diff": tc_diff(res, ref_tc)}
-        if sync:
-            r["phase1_launch_us"] = f.kernel_time(0, len(w["U"]), 3) * 1e3
+        r["phase1_launch_us"] = f.kernel_time(0, len(w["U"]), 3) * 1e3
         f.close()
         out[key] = r
     return out
@@ -307,10 +312,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="bf16", choices=("bf16", "bf16x3", "fp32"),
                     help="precision of the headline right-hand side")
+    ap.add_argument("--sync", type=int, default=2,
+                    help="step-sharing groups of at most this many flows (0: every flow steps "
+                         "on its own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline batch (for profiling)")
-    ap.add_argument("--cpu-outputs", type=int, default=256,
+    ap.add_argument("--cpu-outputs", type=int, default=4096,
                     help="outputs of the 16-flow workload the oracle evaluates for the CPU baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB three times "
@@ -340,7 +348,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    flow = c5_flow(fm, w, zl, zt, dev, args.prec)
+    flow = c5_flow(fm, w, zl, zt, dev, args.prec, sync=args.sync)
     for _ in range(args.warmup):          # the first call also times the phase-2a variants
         flow.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
     torch.cuda.synchronize()
@@ -369,7 +377,10 @@ def main():
     kernels = {}
     for name, gid in groups.items():
         us = flow.kernel_time(gid, nf, 10) * 1e3
-        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, rho, prec=args.prec, nbin_flows=nf)
+        # flows that bin in phase 1: one per step-sharing group
+        nbin = nf if args.sync == 0 else (nf + (args.sync if args.sync > 1 else nf) - 1) // \
+            (args.sync if args.sync > 1 else nf)
+        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, rho, prec=args.prec, nbin_flows=nbin)
         ach = achieved(wk, us * 1e-6, nf)
         launches = tm.get(name, (0.0, 0))[1]
         kernels[name] = {"avg_us": us, "launches_per_batch": launches,
@@ -435,7 +446,8 @@ def main():
                                    "t'=0, mu=0, T 1.0t->0.01t, Dormand-Prince in ln T, synthetic "
                                    "Z table per flow, %s contraction, f64 state, stop at "
                                    "max|V|>20t; one step = the whole 16-flow batch" % args.prec,
-                       "N": N, "L": L, "flows_per_step": nf},
+                       "N": N, "L": L, "flows_per_step": nf,
+                       "step_sharing_groups": args.sync},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line))
 

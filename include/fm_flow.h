@@ -143,7 +143,9 @@ typedef struct {
                                  next step is the smallest any member proposes), so that every
                                  stage temperature is shared and the group's phase-1 bins are
                                  computed once, by its first running member; each flow keeps
-                                 its own stop rule and T_c.  0 = every flow steps on its own */
+                                 its own stop rule and T_c.  k > 1: the same with groups of at
+                                 most k such flows, consecutive in the batch.  0 = every flow
+                                 steps on its own */
 } fm_config;
 
 typedef struct {

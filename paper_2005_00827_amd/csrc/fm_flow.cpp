@@ -140,7 +140,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
         return FM_EINVAL;
     }
     if (c.y_kernel < 0 || c.y_kernel > 3) { why = "y_kernel must be 0, 1, 2 or 3"; return FM_EINVAL; }
-    if (c.sync_batch != 0 && c.sync_batch != 1) { why = "sync_batch must be 0 or 1"; return FM_EINVAL; }
+    if (c.sync_batch < 0) { why = "sync_batch must be >= 0"; return FM_EINVAL; }
     return FM_OK;
 }
 
@@ -252,13 +252,17 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         b.binsT = L.take<char>((S * B * nRd * NN + kBinPad) * rs);
         b.bins_bytes = (S * B * (nRp + nRd) * NN + kBinPad) * rs;
         b.binsT_bytes = (S * B * nRd * NN + kBinPad) * rs;
-        b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * rs);
-        b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
-        b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
-        b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * rs);
+        // the products of bf16 operands are stored as bf16 (the same 8-bit significand)
+        b.y_bf16 = c.precision == FM_FP32_BF16MFMA ? 1 : 0;
+        const size_t ys = b.y_bf16 ? 2 : rs;
+        b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * ys);
+        b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
+        b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
+        b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
         b.wtab = nullptr;
     } else {
         b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
+        b.y_bf16 = 0;
         b.bins_bytes = b.binsT_bytes = 0;
         b.nbset = 0;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);
@@ -901,16 +905,18 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         s.n_rhs = (rk45 && s.status == FM_FLOW_RUNNING) ? 1 : 0;
         h->hfs[f] = s;
     }
-    // step-sharing groups: flows with equal T0, in order of first appearance; the first
-    // running member bins for the group
+    // step-sharing groups: flows with equal T0, in order of first appearance, at most
+    // cfg.sync_batch of them per group (1 = no limit); the first running member bins for
+    // the group
     h->ngroups = h->gmax = 0;
     if (c.sync_batch) {
+        const int cap = c.sync_batch == 1 ? n : c.sync_batch;
         std::vector<int> members, off{0};
         std::vector<char> done(n, 0);
         for (int f = 0; f < n; ++f) {
             if (done[f]) continue;
             int lead = -1;
-            for (int k = f; k < n; ++k) {
+            for (int k = f; k < n && static_cast<int>(members.size()) - off.back() < cap; ++k) {
                 if (done[k] || T0[k] != T0[f]) continue;
                 done[k] = 1;
                 members.push_back(k);

@@ -1054,6 +1054,13 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
 // k >= N (and n >= N) are zero in both operands.
 typedef float fm_f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 fm_bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 fm_bf4 __attribute__((ext_vector_type(4)));
+
+// Storage of the products Y: bf16 operands (kM = 1) leave about 3 significant digits in a
+// product, so Y is stored rounded to bf16 (half the bytes phase 2a writes and phase 2b
+// reads); the f32 and split-bf16 modes keep f32.
+template <int kM> struct YStore { using T = float; };
+template <> struct YStore<1> { using T = __bf16; };
 
 template <int kM>
 __device__ inline int mfma_k(int e, int lane) {
@@ -1195,8 +1202,10 @@ template <int kM, int KE, int NT, bool kTwo>
 __device__ inline void y_tiles_rows(const float* Bf, const int* qrep, const int* qg, int NN, int N,
                                int M, int grp, int n0, int t_begin, int t_end, const int* pis,
                                const float* zs, float al, float be, const void* Bs0,
-                               const void* Bs1, float* Y0, float* Y1, int lane, int r0, int o0,
+                               const void* Bs1, typename YStore<kM>::T* Y0,
+                               typename YStore<kM>::T* Y1, int lane, int r0, int o0,
                                int r1, int o1) {
+    using YT = typename YStore<kM>::T;
     const int col = lane & 15;
     const float zg = zs[grp];
     float a0[KE], a1[KE];
@@ -1219,8 +1228,8 @@ __device__ inline void y_tiles_rows(const float* Bf, const int* qrep, const int*
                 const int qq = tile * 16 + 4 * (lane >> 4) + r;
                 if (qq < M && n < N) {
                     const size_t o = static_cast<size_t>(qq) * NN + grp * N + n;
-                    Y0[o] = c0[u][r];
-                    if constexpr (kTwo) Y1[o] = c1[u][r];
+                    Y0[o] = static_cast<YT>(c0[u][r]);
+                    if constexpr (kTwo) Y1[o] = static_cast<YT>(c1[u][r]);
                 }
             }
         }
@@ -1334,18 +1343,20 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     }
     __syncthreads();                                   // every thread of the block
     if (t_begin >= t_end) return;
+    using YT = typename YStore<kM>::T;
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     const void* B0 = Braw;
     const void* B1 = Braw + kBytes;
     const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
     if (two)
         y_tiles_rows<kM, KE, NT, true>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                     al, be, B0, B1, args.Y[2] + yoff, args.Y[3] + yoff, lane,
-                                     r0, o0, r1, o1);
+                                     al, be, B0, B1, reinterpret_cast<YT*>(args.Y[2]) + yoff,
+                                     reinterpret_cast<YT*>(args.Y[3]) + yoff, lane, r0, o0, r1,
+                                     o1);
     else
         y_tiles_rows<kM, KE, NT, false>(Bf, qrep, qg, NN, N, M, grp, n0, t_begin, t_end, pis, zs,
-                                      al, be, B0, B1, args.Y[ch] + yoff, nullptr, lane, r0, o0,
-                                      r1, o1);
+                                      al, be, B0, B1, reinterpret_cast<YT*>(args.Y[ch]) + yoff,
+                                      nullptr, lane, r0, o0, r1, o1);
 }
 
 // Row tiles of one operation class.  Transfers are ordered by (operation o, representative),
@@ -1391,8 +1402,9 @@ __device__ inline void gather_a(float (&a)[KE], const float* row, int N, int lan
 template <int kM, int KE, int NT, bool kTwo>
 __device__ inline void y_tiles(const float* Bf, const int* qrep, int NN, int N, int q0,
                                int q1, int prow, int grp, int n0, int t_begin, int t_end,
-                               const void* Bs0, const void* Bs1, float* Y0, float* Y1,
-                               int lane, int r0, int r1) {
+                               const void* Bs0, const void* Bs1, typename YStore<kM>::T* Y0,
+                               typename YStore<kM>::T* Y1, int lane, int r0, int r1) {
+    using YT = typename YStore<kM>::T;
     const int col = lane & 15;
     const size_t roff = static_cast<size_t>(prow) * N;
     float a0[KE], a1[KE];
@@ -1415,8 +1427,8 @@ __device__ inline void y_tiles(const float* Bf, const int* qrep, int NN, int N, 
                 const int qq = q0 + tile * 16 + 4 * (lane >> 4) + r;
                 if (qq < q1 && n < N) {
                     const size_t o = static_cast<size_t>(qq) * NN + grp * N + n;
-                    Y0[o] = c0[u][r];
-                    if constexpr (kTwo) Y1[o] = c1[u][r];
+                    Y0[o] = static_cast<YT>(c0[u][r]);
+                    if constexpr (kTwo) Y1[o] = static_cast<YT>(c1[u][r]);
                 }
             }
         }
@@ -1529,15 +1541,18 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_cls(DevGeom g, const FlowSt
     const int fb = bin_flow(fs, f);
     const float* Bf = ch == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
                               : bins + static_cast<size_t>(fb) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    using YT = typename YStore<kM>::T;
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     const void* B0 = Braw;
     const void* B1 = Braw + kBytes;
     if (two)
         y_tiles<kM, KE, NT, true>(Bf, qrep, NN, N, q0, q1, prow, grp, n0, t_begin, t_end, B0,
-                                     B1, args.Y[2] + yoff, args.Y[3] + yoff, lane, r0, r1);
+                                  B1, reinterpret_cast<YT*>(args.Y[2]) + yoff,
+                                  reinterpret_cast<YT*>(args.Y[3]) + yoff, lane, r0, r1);
     else
         y_tiles<kM, KE, NT, false>(Bf, qrep, NN, N, q0, q1, prow, grp, n0, t_begin, t_end, B0,
-                                      B1, args.Y[ch] + yoff, nullptr, lane, r0, r1);
+                                   B1, reinterpret_cast<YT*>(args.Y[ch]) + yoff, nullptr, lane,
+                                   r0, r1);
 }
 
 // B operand of one wavefront's tiles in registers: the fragments of every k-step and column
@@ -1704,7 +1719,8 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
 //   id = (gw / 8) * 8 gsize + m * 8 + gw % 8,  m = (i * bx + x) * nchunk + chunk.
 template <int kM, int KE, int NT, int TPW, bool kTwo>
 __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const float* Vs0,
-                                     const float* Vs1, float* Y0, float* Y1, int p, int tb,
+                                     const float* Vs1, typename YStore<kM>::T* Y0,
+                                     typename YStore<kM>::T* Y1, int p, int tb,
                                      int nt, int toff, int n0, float al, float be,
                                      const double* Zf, unsigned char* Braw, int* pms,
                                      float* zs, int* qs, int* msk) {
@@ -1763,7 +1779,7 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
         for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
             BFrag<kM, KE, NT> B;
             load_bfrag<kM, KE, NT>(B, Braw + w * kBytes, lane);
-            float* Yw = w ? Y1 : Y0;
+            typename YStore<kM>::T* Yw = w ? Y1 : Y0;
 #pragma unroll
             for (int j = 0; j < TPW; ++j) {
                 const int tl = tw0 + j - tb;           // tile within the block (wave-uniform)
@@ -1780,7 +1796,7 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
                     for (int r = 0; r < 4; ++r) {
                         const int q = qt[r];
                         if (q < 0) continue;
-                        float* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+                        auto* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
 #pragma unroll
                         for (int u = 0; u < NT; ++u) {
                             const int n = n0 + 16 * u + col;
@@ -1795,16 +1811,21 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
                 // (rows then start 16-byte aligned and a group of four lies wholly below N or
                 // at or above it), else one value at a time
                 if (q >= 0) {
-                    float* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+                    auto* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
 #pragma unroll
                     for (int u = 0; u < NT; ++u) {
                         const int n = n0 + 16 * u + 4 * (lane >> 4);
                         if ((N & 3) == 0) {
-                            if (n < N) *reinterpret_cast<fm_f4*>(yrow + n) = c[u];
+                            if (n < N) {
+                                if constexpr (kM == 1)   // bf16 products: one 8-byte store
+                                    *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
+                                else
+                                    *reinterpret_cast<fm_f4*>(yrow + n) = c[u];
+                            }
                         } else {
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                if (n + r < N) yrow[n + r] = c[u][r];
+                                if (n + r < N) yrow[n + r] = static_cast<typename YStore<kM>::T>(c[u][r]);
                         }
                     }
                 }
@@ -1855,15 +1876,18 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
     const size_t N3 = static_cast<size_t>(NN) * N;
     const size_t yoff = static_cast<size_t>(f) * M * NN;
     const int toff = cc == 0 ? 0 : g.orb_nt[0];
+    using YT = typename YStore<kM>::T;
     if (ch == 2)
         y_orbit_block<kM, KE, NT, TPW, true>(g, Bf, args.Vs[2] + f * N3, args.Vs[3] + f * N3,
-                                             args.Y[2] + yoff, args.Y[3] + yoff, p, tb, nt,
+                                             reinterpret_cast<YT*>(args.Y[2]) + yoff,
+                                             reinterpret_cast<YT*>(args.Y[3]) + yoff, p, tb, nt,
                                              toff, chunk * 16 * NT, al, be,
                                              Z_stage + static_cast<size_t>(f) * N, Braw, pms, zs, qs,
                                              msk);
     else
         y_orbit_block<kM, KE, NT, TPW, false>(g, Bf, args.Vs[ch] + f * N3, args.Vs[ch] + f * N3,
-                                              args.Y[ch] + yoff, args.Y[ch] + yoff, p, tb, nt,
+                                              reinterpret_cast<YT*>(args.Y[ch]) + yoff,
+                                              reinterpret_cast<YT*>(args.Y[ch]) + yoff, p, tb, nt,
                                               toff, chunk * 16 * NT, al, be,
                                               Z_stage + static_cast<size_t>(f) * N, Braw, pms, zs,
                                               qs, msk);
@@ -1891,9 +1915,9 @@ template <> struct YGroup<double> { static constexpr int v = 24; };
 // index n: its column of Y (a group of rows at a time) is loaded into registers while the
 // item's pair vectors are gathered into LDS (zero-padded to kChunk, laid out [x][pair] so
 // one x is a 128-bit broadcast read), so every group costs one memory round trip.
-template <typename R, int KIND>
+template <typename R, typename YT, int KIND>
 __device__ __attribute__((always_inline)) inline void contract_item(
-    const DevGeom& g, const R* V, const R* VA, const R* VC, const R* Ya, const R* Yb,
+    const DevGeom& g, const R* V, const R* VA, const R* VC, const YT* Ya, const YT* Yb,
     const int* pairs, int cnt, R* vu, R* vw, R* Kf) {
     constexpr int G = KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v;
     const int N = g.N, NN = g.NN;
@@ -1912,8 +1936,8 @@ __device__ __attribute__((always_inline)) inline void contract_item(
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 const int x = min(xg + j, N - 1);
-                ya[j] = Ya[static_cast<size_t>(x) * N + n];
-                if (KIND == 2) yb[j] = Yb[static_cast<size_t>(x) * N + n];
+                ya[j] = static_cast<R>(Ya[static_cast<size_t>(x) * N + n]);
+                if (KIND == 2) yb[j] = static_cast<R>(Yb[static_cast<size_t>(x) * N + n]);
             }
             if (n0 == 0 && xg == 0) {
                 // gather the pair vectors while the first Y rows are in flight (kChunk * 128
@@ -1979,11 +2003,11 @@ __device__ __attribute__((always_inline)) inline void contract_item(
     }
 }
 
-template <typename R>
+template <typename R, typename YT>
 __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
                                                  const R* v0, const R* va, const R* vc,
-                                                 const R* y1, const R* y2, const R* y3,
-                                                 const R* y4, R* K, unsigned ch, int slot,
+                                                 const YT* y1, const YT* y2, const YT* y3,
+                                                 const YT* y4, R* K, unsigned ch, int slot,
                                                  int B) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int f = blockIdx.y;
@@ -2011,13 +2035,13 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     const R* V = v0 + f * N3;
     const R* VA = va + f * N3;
     const R* VC = vc + f * N3;
-    const R* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
-    const R* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
+    const YT* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
+    const YT* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
     R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
     R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
-    if (kind == 0) contract_item<R, 0>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-    else if (kind == 1) contract_item<R, 1>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-    else contract_item<R, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    if (kind == 0) contract_item<R, YT, 0>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    else if (kind == 1) contract_item<R, YT, 1>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    else contract_item<R, YT, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
 }
 
 // ------------------------------------------------------------------------------------
@@ -2693,15 +2717,23 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
                        static_cast<const R*>(b.binsT), a);
 }
 
-template <typename R>
-void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
+template <typename R, typename YT>
+void contract_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
     const size_t lds = 2 * static_cast<size_t>(kChunk) * g.N * sizeof(R);
     const int items = g.n_items[0] + g.n_items[1] + g.n_items[2];
-    hipLaunchKernelGGL(k_contract<R>, dim3(items, nf), dim3(64), lds, s, g, b.fs,
+    hipLaunchKernelGGL((k_contract<R, YT>), dim3(items, nf), dim3(64), lds, s, g, b.fs,
                        static_cast<const R*>(b.v0), static_cast<const R*>(b.va),
-                       static_cast<const R*>(b.vc), static_cast<const R*>(b.y1),
-                       static_cast<const R*>(b.y2), static_cast<const R*>(b.y3),
-                       static_cast<const R*>(b.y4), static_cast<R*>(b.k), ch, slot, b.bstride);
+                       static_cast<const R*>(b.vc), static_cast<const YT*>(b.y1),
+                       static_cast<const YT*>(b.y2), static_cast<const YT*>(b.y3),
+                       static_cast<const YT*>(b.y4), static_cast<R*>(b.k), ch, slot, b.bstride);
+}
+
+template <typename R>
+void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
+    if constexpr (sizeof(R) == 4) {
+        if (b.y_bf16) { contract_go<float, __bf16>(s, g, b, nf, ch, slot); return; }
+    }
+    contract_go<R, R>(s, g, b, nf, ch, slot);
 }
 
 }  // namespace

@@ -146,7 +146,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
     cfg.g_end = float(g_end)
     cfg.v_rel = float(v_rel)
     cfg.y_kernel = int(y_kernel)
-    cfg.sync_batch = int(bool(sync_batch))
+    cfg.sync_batch = int(sync_batch)
     cfg._keep = keep
     return cfg
 

@@ -214,37 +214,6 @@ def test_step_matches_oracle(torch_dev, integrator, prec):
         f.close()
 
 
-def test_phase1_two_nodes_per_block_matches_one(torch_dev):
-    """At N = 128 with many (representative, flow) pairs, the first stage launch of a step
-    bins two stage nodes per phase-1 block.  A Dormand-Prince step of five C5-size flows
-    (that path) must match the same flows stepped one at a time (one node per block, the
-    path the oracle tests pin): the same sums, up to the order of the LDS atomics."""
-    torch, dev = torch_dev
-    fm = _fm()
-    N, L = 128, 512
-    Us = [1.5, 2.0, 2.5, 3.0, 3.5]
-    V = np.stack([inputs.noisy_state(N, u, seed=11 + i) for i, u in enumerate(Us)])
-    lnT, h = math.log(0.2), -0.02
-    fb = fm.Flow(N=N, L=L, U=Us[0], precision="fp32", integrator="rk45", max_batch=len(Us),
-                 device=dev)
-    f1 = fm.Flow(N=N, L=L, U=Us[0], precision="fp32", integrator="rk45", device=dev)
-    try:
-        Vb = torch.from_numpy(V.copy()).to(dev)
-        lb, hb, ab = fb.step([lnT] * len(Us), [h] * len(Us), Vb)
-        got = Vb.cpu().numpy()
-        for i in range(len(Us)):
-            V1 = torch.from_numpy(V[i:i + 1].copy()).to(dev)
-            l1, h1, a1 = f1.step([lnT], [h], V1)
-            assert bool(ab[i]) and bool(a1[0])
-            # the single-precision error estimate is set by rounding, so the proposed steps
-            # agree only within the step-size rule's bounds
-            assert 0.2 * abs(h) - 1e-15 <= abs(hb[i]) <= 5 * abs(h) + 1e-15
-            assert rel(got[i], V1.cpu().numpy()[0]) <= 1e-6, (i, rel(got[i], V1.cpu().numpy()[0]))
-    finally:
-        fb.close()
-        f1.close()
-
-
 @pytest.mark.parametrize("prec,integ,check", [("fp64", "rk45", "all"), ("fp32", "rk45", "ends"),
                                               ("fp64", "rk4", "ends")])
 def test_stage_wide_tiles_ragged_batch(torch_dev, prec, integ, check):
