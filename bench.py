@@ -294,6 +294,33 @@ def c2_single_flow(fm, inputs, torch, dev, steps=5):
     return out
 
 
+def shell_flow(fm, inputs, torch, dev):
+    """Energy-shell patching at the paper's 224 patches (7 shells x 32 sectors), L=128, U=3,
+    one FP32 flow (phase 2a on the vector units above 128 patches) and the FP64 flow of the
+    same workload: seconds, RHS, updates/s and the T_c difference."""
+    w = inputs.workload("shells")
+    N, L, U = w["N"], w["L"], w["U"][0]
+    out, tc = {}, {}
+    for prec in ("fp32", "fp64"):
+        f = fm.Flow(N=N, L=L, U=U, T0=1.0, T_end=w["T_end"], geometry="shells",
+                    n_shells=w["n_shells"], integrator="rk45", precision=prec, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f.run_batch([U], [1.0])[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["rhs_ms_" + prec] = f.kernel_time(1, 1, 3) + f.kernel_time(2, 1, 3)
+        f.close()
+        tc[prec] = r["T_c"]
+        out["seconds_" + prec] = dt
+        out["rhs_" + prec] = r["n_rhs"]
+        out["updates_per_s_" + prec] = r["n_rhs"] * 3.0 * N ** 3 * L ** 2 / dt
+    out["T_c_fp64"] = tc["fp64"]
+    out["Tc_rel_diff_fp32_fp64"] = abs(tc["fp32"] / tc["fp64"] - 1.0)
+    out["note"] = "rhs_ms_*: phase 2a + phase 2b launch of one flow (first call includes tuning)"
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -414,6 +441,7 @@ def main():
         extra["c2_single_flow"] = c2_single_flow(fm, inputs, torch, dev)
         extra["sweep_64_flows"] = batched_sweep(fm, inputs, torch, dev)
         extra["interaction_flow"] = interaction_flow(fm, inputs, torch, dev)
+        extra["shells_224"] = shell_flow(fm, inputs, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

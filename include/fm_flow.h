@@ -60,8 +60,10 @@ typedef struct fm_flow fm_flow;
 
 enum { FM_OK = 0, FM_EINVAL = -1, FM_ENOMEM = -2, FM_EDEVICE = -3, FM_ESTATE = -4 };
 
-/* Patch geometry. */
-enum { FM_GEOM_ANGULAR = 0, FM_GEOM_IDENTITY = 1 };
+/* Patch geometry.  FM_GEOM_SHELLS: energy-shell patching (Sec. 3.2: the angular sectors
+ * subdivided in energy, 7 shells x 32 sectors = 224 patches); patch a = e * (N / n_shells) +
+ * s for shell e (0 = most negative xi) and angular sector s. */
+enum { FM_GEOM_ANGULAR = 0, FM_GEOM_IDENTITY = 1, FM_GEOM_SHELLS = 2 };
 
 /* Integrator in s = ln T: classical RK4 with n_steps fixed steps from T0 to T_end, or
  * Dormand-Prince 5(4) with error control (rtol, atol, h0, h_min). */
@@ -146,6 +148,20 @@ typedef struct {
                                  its own stop rule and T_c.  k > 1: the same with groups of at
                                  most k such flows, consecutive in the batch.  0 = every flow
                                  steps on its own */
+    int n_shells;             /* FM_GEOM_SHELLS: odd number of energy shells (N % n_shells == 0,
+                                 N / n_shells a valid angular patch count); other geometries: 0
+                                 or 1 */
+    const double *shell_edges;/* FM_GEOM_SHELLS: host [(n_shells - 1) / 2], ascending positive
+                                 |xi| at which the shells meet (symmetric about the Fermi
+                                 surface xi = 0); NULL selects 2|t| (2^k - 1)/(2^m - 1),
+                                 k = 1..m = (n_shells - 1)/2, finest at the Fermi surface.  The
+                                 patch of a loop point is its angular sector and the shell of
+                                 its xi; a patch is represented by the point of its sector's
+                                 centre ray where xi equals the shell's representative energy
+                                 (0 for the Fermi-surface shell, the middle of the shell's
+                                 range otherwise, the outermost shell's inner edge plus half
+                                 the width of the shell below it), snapped to the transfer grid.
+                                 FM_EINVAL when a loop point lies within 1e-9 of an edge. */
 } fm_config;
 
 typedef struct {

@@ -56,6 +56,8 @@ typedef struct {
     int N, L;           /* patch count, loop grid side */
     int identity;       /* 1: patch = loop point (N = L*L), exact momenta */
     unsigned channels;  /* bit 1: particle-particle, bit 2: crossed ph, bit 4: direct ph */
+    int n_shells;       /* > 1 (odd): energy shells, N = n_shells x angular sectors */
+    const double *shell_edges; /* [(n_shells-1)/2] ascending |xi| edges, or NULL (default) */
 } orc_model;
 
 typedef struct {
@@ -118,27 +120,32 @@ static int patch_of(double kx, double ky, int N, double *margin)
     return (int)p;
 }
 
-/* Fermi-surface point on the ray at angle th: the first sign change of xi between Gamma and
- * the zone edge, found by a 4096-sample scan and bisection; no sign change means the sample
- * of smallest |xi| is used. */
-static void fs_point(const orc_model *m, double th, double *kx, double *ky)
+/* Point on the ray at angle th where xi equals `level` (0: the Fermi surface): the first
+ * sign change of xi - level between Gamma and the zone edge, found by a 4096-sample scan and
+ * bisection; no sign change means the sample of smallest |xi - level| is used. */
+static double disp_at(const orc_model *m, double kx, double ky, double level)
+{
+    return disp(m, kx, ky) - level;
+}
+
+static void fs_point(const orc_model *m, double th, double level, double *kx, double *ky)
 {
     const int ns = 4096;
     double c = cos(th), s = sin(th);
     double rmax = M_PI / fmax(fabs(c), fabs(s));
-    double f0 = disp(m, 0.0, 0.0);
+    double f0 = disp_at(m, 0.0, 0.0, level);
     double r_best = 0.0, f_best = fabs(f0);
     if (f0 == 0.0) { *kx = 0.0; *ky = 0.0; return; }
     double r_prev = 0.0, f_prev = f0;
     for (int i = 1; i <= ns; ++i) {
         double r = rmax * i / ns;
-        double f = disp(m, r * c, r * s);
+        double f = disp_at(m, r * c, r * s, level);
         if ((f_prev < 0.0 && f >= 0.0) || (f_prev > 0.0 && f <= 0.0)) {
             double lo = r_prev, hi = r;
             for (int it = 0; it < 200; ++it) {
                 double mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
-                double fm = disp(m, mid * c, mid * s);
+                double fm = disp_at(m, mid * c, mid * s, level);
                 if ((f_prev < 0.0 && fm < 0.0) || (f_prev > 0.0 && fm > 0.0)) lo = mid;
                 else hi = mid;
             }
@@ -168,13 +175,50 @@ static void geom_free(geom *g)
     memset(g, 0, sizeof(*g));
 }
 
+/* Energy shells (Sec. 3.2: the angular patches subdivided in energy, 7 shells x 32 sectors =
+ * 224 patches).  With S = n_shells (odd) and M = (S - 1)/2, the shells meet at the energies
+ * +-E_1 < ... < +-E_M (given, or by default E_k = 2|t| (2^k - 1)/(2^M - 1), finest at the
+ * Fermi surface).  A loop point of energy x lies in shell M - k below the Fermi surface and
+ * M + k above it, k being the number of edges below |x|; patch = shell * (N/S) + sector.
+ * A patch is represented by the point of its sector's centre ray at the shell's energy: 0 for
+ * the Fermi-surface shell, the middle of an inner shell, and for the outermost shell its edge
+ * plus half the width of the shell inside it. */
+static double shell_edge(const orc_model *m, int k)
+{
+    int M = (m->n_shells - 1) / 2;
+    if (m->shell_edges) return m->shell_edges[k - 1];
+    return 2.0 * fabs(m->t) * (pow(2.0, k) - 1.0) / (pow(2.0, M) - 1.0);
+}
+
+static int n_shells_of(const orc_model *m) { return m->n_shells > 1 ? m->n_shells : 1; }
+
+static int shell_of(const orc_model *m, double x)
+{
+    int M = (n_shells_of(m) - 1) / 2, k = 0;
+    while (k < M && fabs(x) > shell_edge(m, k + 1)) ++k;
+    return x < 0.0 ? M - k : M + k;
+}
+
+static double shell_energy(const orc_model *m, int e)
+{
+    int M = (n_shells_of(m) - 1) / 2, k = abs(e - M);
+    if (k == 0) return 0.0;
+    double lo = shell_edge(m, k);
+    double mag = k < M ? 0.5 * (lo + shell_edge(m, k + 1))
+                       : lo + 0.5 * (lo - (k > 1 ? shell_edge(m, k - 1) : 0.0));
+    return e < M ? -mag : mag;
+}
+
 static int geom_build(const orc_model *m, geom *g)
 {
     memset(g, 0, sizeof(*g));
     int L = m->L, N = m->N;
+    int S = n_shells_of(m), Ns = N / (S > 0 ? S : 1);
     if (L < 2 || (L & 1)) return -1;
     if (m->identity) { if (N != L * L) return -1; }
-    else if (N < 1 || isnan(theta_off(N)) || (L % 4)) return -1;
+    else if (S % 2 == 0 || N % S || Ns < 1 || isnan(theta_off(Ns)) || (L % 4)) return -1;
+    for (int k = 1; k <= (S - 1) / 2; ++k)
+        if (!(shell_edge(m, k) > (k > 1 ? shell_edge(m, k - 1) : 0.0))) return -1;
     g->N = N; g->L = L; g->np = L * L; g->identity = m->identity;
     g->xi = (double *)malloc(sizeof(double) * g->np);
     g->patch = (int *)malloc(sizeof(int) * g->np);
@@ -189,8 +233,10 @@ static int geom_build(const orc_model *m, geom *g)
                 g->patch[j] = j;
             } else {
                 double mg;
-                g->patch[j] = patch_of(kx, ky, N, &mg);
+                g->patch[j] = shell_of(m, g->xi[j]) * Ns + patch_of(kx, ky, Ns, &mg);
                 if (mg < g->margin) g->margin = mg;
+                for (int k = 1; k <= (S - 1) / 2; ++k)     /* no point on a shell edge */
+                    if (fabs(fabs(g->xi[j]) - shell_edge(m, k)) < 1e-9) { geom_free(g); return -1; }
             }
         }
     if (m->identity) {
@@ -199,7 +245,8 @@ static int geom_build(const orc_model *m, geom *g)
     } else {
         for (int a = 0; a < N; ++a) {
             double kx, ky;
-            fs_point(m, theta_off(N) + 2.0 * M_PI * a / N, &kx, &ky);
+            fs_point(m, theta_off(Ns) + 2.0 * M_PI * (a % Ns) / Ns, shell_energy(m, a / Ns),
+                     &kx, &ky);
             g->anchor[2 * a] = mod_l(lround(kx * L / (2.0 * M_PI)), L);
             g->anchor[2 * a + 1] = mod_l(lround(ky * L / (2.0 * M_PI)), L);
         }

@@ -37,7 +37,8 @@ RUNNING, DIVERGED, NONFINITE, REACHED_TEND, STEPFAIL = 0, 1, 2, 3, 4
 
 class Model(ctypes.Structure):
     _fields_ = [("t", c_double), ("tp", c_double), ("mu", c_double), ("N", c_int),
-                ("L", c_int), ("identity", c_int), ("channels", c_uint)]
+                ("L", c_int), ("identity", c_int), ("channels", c_uint), ("n_shells", c_int),
+                ("shell_edges", POINTER(c_double))]
 
 
 class FlowCfg(ctypes.Structure):
@@ -112,9 +113,17 @@ def _pi(a):
     return a.ctypes.data_as(POINTER(c_int)) if a is not None else None
 
 
-def model(N, L, t=1.0, tp=0.0, mu=0.0, identity=False, channels=CH_ALL) -> Model:
-    return Model(float(t), float(tp), float(mu), int(N), int(L), int(bool(identity)),
-                 int(channels))
+def model(N, L, t=1.0, tp=0.0, mu=0.0, identity=False, channels=CH_ALL, n_shells=0,
+          shell_edges=None) -> Model:
+    """n_shells > 1: energy-shell patching, N = n_shells x angular sectors; shell_edges:
+    (n_shells - 1)/2 ascending |xi| edges, or None for the default."""
+    m = Model(float(t), float(tp), float(mu), int(N), int(L), int(bool(identity)),
+              int(channels), int(n_shells), None)
+    if shell_edges is not None:
+        se = np.ascontiguousarray(shell_edges, np.float64)
+        m.shell_edges = _pd(se)
+        m._keep = se
+    return m
 
 
 def n_threads() -> int:

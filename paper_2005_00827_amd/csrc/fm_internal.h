@@ -17,6 +17,7 @@ namespace fm {
 // ------------------------------------------------------------------------------------
 struct HostGeometry {
     int N = 0, L = 0, np = 0, identity = 0, pp_shift = 0;
+    int nsec = 0;                    // angular sectors (N / n_shells; N for identity patches)
     std::vector<double> xi;          // [np] dispersion at each loop point
     std::vector<int> patch;          // [np] patch of each loop point
     std::vector<int> anchor;         // [N][2] transfer-grid index of each patch's Fermi point

@@ -41,13 +41,15 @@ double sector_offset(int N) {
     return std::nan("");
 }
 
-// Radius of the first zero of xi along the ray (cos th, sin th) inside the zone: scan 4096
-// equal steps from Gamma to the zone edge for the first sign change and bisect it; without
-// a sign change take the scanned radius of smallest |xi|.
-double fermi_radius(const Disp& xi, double th) {
+// Radius of the first point along the ray (cos th, sin th) inside the zone where xi equals
+// `level` (0: the Fermi surface): scan 4096 equal steps from Gamma to the zone edge for the
+// first sign change of xi - level and bisect it; without a sign change take the scanned
+// radius of smallest |xi - level|.
+double fermi_radius(const Disp& disp, double th, double level = 0.0) {
     const int n_scan = 4096;
     const double c = std::cos(th), s = std::sin(th);
     const double r_edge = M_PI / std::max(std::fabs(c), std::fabs(s));
+    auto xi = [&](double kx, double ky) { return disp(kx, ky) - level; };
     double f_prev = xi(0.0, 0.0);
     if (f_prev == 0.0) return 0.0;
     double r_prev = 0.0, r_min = 0.0, f_min = std::fabs(f_prev);
@@ -90,9 +92,33 @@ inline int op_transfer(int o, int L, int m) {
     return x + L * y;
 }
 
+// Fills the permutation of patches that no loop point lies in (energy shells of a sector the
+// band does not reach): within their shell, by the permutation of their sector learned from a
+// patch of the same sector that has points.  False if that is impossible or the result is not
+// a permutation mapping empty patches onto empty ones.
+bool fill_empty(const HostGeometry& g, const std::vector<char>& used, int* p) {
+    const int N = g.N, ns = g.nsec;
+    for (int a = 0; a < N; ++a) {
+        if (p[a] >= 0) continue;
+        int s = -1;
+        for (int b = a % ns; b < N && s < 0; b += ns)
+            if (p[b] >= 0) s = p[b] % ns;
+        if (s < 0) return false;
+        p[a] = (a / ns) * ns + s;
+    }
+    std::vector<char> seen(N, 0);
+    for (int a = 0; a < N; ++a) {
+        if (seen[p[a]] || used[a] != used[p[a]]) return false;
+        seen[p[a]] = 1;
+    }
+    return true;
+}
+
 void build_symmetry(HostGeometry& g) {
     const int N = g.N, L = g.L;
     std::vector<int> perm(8 * static_cast<size_t>(N), -1);
+    std::vector<char> used(N, 0);
+    for (int j = 0; j < g.np; ++j) used[g.patch[j]] = 1;
     bool ok = true;
     for (int o = 0; o < 8 && ok; ++o) {
         for (int jy = 0; jy < L && ok; ++jy)
@@ -106,8 +132,7 @@ void build_symmetry(HostGeometry& g) {
                 if (p < 0) p = g.patch[oj];
                 else if (p != g.patch[oj]) ok = false;
             }
-        for (int a = 0; a < N && ok; ++a)
-            if (perm[o * static_cast<size_t>(N) + a] < 0) ok = false;
+        if (ok) ok = fill_empty(g, used, &perm[o * static_cast<size_t>(N)]);
     }
     g.sym = ok;
     // inversion k -> -k alone (operation 3), used to pair the particle-hole loop points of
@@ -124,11 +149,7 @@ void build_symmetry(HostGeometry& g) {
                 else if (p[g.patch[j]] < 0) p[g.patch[j]] = g.patch[oj];
                 else if (p[g.patch[j]] != g.patch[oj]) iok = false;
             }
-        std::vector<int> seen(N, 0);
-        for (int a = 0; a < N && iok; ++a) {
-            if (p[a] < 0 || seen[p[a]]) iok = false;
-            else seen[p[a]] = 1;
-        }
+        if (iok) iok = fill_empty(g, used, p.data());
         g.inv_ok = iok;
         g.inv_perm.resize(N);
         for (int a = 0; a < N; ++a) g.inv_perm[a] = iok ? p[a] : a;
@@ -311,14 +332,33 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
     char buf[256];
     if (L < 2 || (L % 2) != 0) { err = "L must be even and >= 2"; return false; }
     if (L > 2048) { err = "L must be <= 2048"; return false; }
+    // energy shells: ns shells, m = (ns - 1)/2 edges E_1 < ... < E_m on each side of xi = 0
+    const bool shells = cfg.geometry == FM_GEOM_SHELLS;
+    const int ns = shells ? cfg.n_shells : 1;
+    std::vector<double> edge;
     if (cfg.geometry == FM_GEOM_IDENTITY) {
         if (N != L * L) { err = "identity geometry needs N == L*L"; return false; }
-    } else if (cfg.geometry == FM_GEOM_ANGULAR) {
-        if (N < 1 || std::isnan(sector_offset(N))) {
-            err = "angular geometry needs N == 1 or N % 8 in {0, 4}";
+    } else if (cfg.geometry == FM_GEOM_ANGULAR || shells) {
+        if (shells && (ns < 1 || ns % 2 == 0 || N % ns != 0)) {
+            err = "shell geometry needs an odd n_shells dividing N";
+            return false;
+        }
+        const int Na = N / ns;
+        if (Na < 1 || std::isnan(sector_offset(Na))) {
+            err = "angular geometry needs N == 1 or N % 8 in {0, 4} (per shell)";
             return false;
         }
         if (L % 4 != 0) { err = "angular geometry needs L % 4 == 0"; return false; }
+        const int m = (ns - 1) / 2;
+        for (int k = 1; k <= m; ++k)
+            edge.push_back(cfg.shell_edges ? cfg.shell_edges[k - 1]
+                                           : 2.0 * std::fabs(cfg.t) * (std::ldexp(1.0, k) - 1.0) /
+                                                 (std::ldexp(1.0, m) - 1.0));
+        for (int k = 0; k < m; ++k)
+            if (!(edge[k] > (k ? edge[k - 1] : 0.0)) || !std::isfinite(edge[k])) {
+                err = "shell edges must be positive and ascending";
+                return false;
+            }
     } else {
         err = "unknown geometry";
         return false;
@@ -327,22 +367,33 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
     g = HostGeometry{};
     g.N = N; g.L = L; g.np = L * L;
     g.identity = cfg.geometry == FM_GEOM_IDENTITY;
+    const int Nsec = g.identity ? N : N / ns;
+    g.nsec = Nsec;
+    // shell of an energy: m - k below the Fermi surface, m + k above, k = edges below |x|
+    const int m = (ns - 1) / 2;
+    auto shell_of = [&](double x) {
+        int k = 0;
+        while (k < m && std::fabs(x) > edge[k]) ++k;
+        return x < 0.0 ? m - k : m + k;
+    };
+    double emargin = INFINITY;   // smallest distance of a loop point's |xi| to an edge
     g.xi.resize(g.np);
     g.patch.resize(g.np);
     g.anchor.resize(2 * N);
     std::vector<double> kg(L);
     for (int j = 0; j < L; ++j) kg[j] = -M_PI + 2.0 * M_PI * (j + 0.5) / L;
-    const double off = g.identity ? 0.0 : sector_offset(N);
+    const double off = g.identity ? 0.0 : sector_offset(Nsec);
     g.margin = 0.5;
     for (int jy = 0; jy < L; ++jy) {
         for (int jx = 0; jx < L; ++jx) {
             const int j = jx + L * jy;
             g.xi[j] = xi(kg[jx], kg[jy]);
             if (g.identity) { g.patch[j] = j; continue; }
-            const double u = (std::atan2(kg[jy], kg[jx]) - off) * N / (2.0 * M_PI);
+            const double u = (std::atan2(kg[jy], kg[jx]) - off) * Nsec / (2.0 * M_PI);
             const double r = std::round(u);   // nearest centre (ties cannot pass the margin test)
             g.margin = std::min(g.margin, 0.5 - std::fabs(u - r));
-            g.patch[j] = wrap(static_cast<long>(r), N);
+            g.patch[j] = shell_of(g.xi[j]) * Nsec + wrap(static_cast<long>(r), Nsec);
+            for (double e : edge) emargin = std::min(emargin, std::fabs(std::fabs(g.xi[j]) - e));
         }
     }
     if (!g.identity && g.margin < 1e-9) {
@@ -351,13 +402,27 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
         err = buf;
         return false;
     }
+    if (emargin < 1e-9) {
+        std::snprintf(buf, sizeof buf, "a loop point lies %.3g from a shell edge", emargin);
+        err = buf;
+        return false;
+    }
     if (g.identity) {
         for (int a = 0; a < N; ++a) { g.anchor[2 * a] = a % L; g.anchor[2 * a + 1] = a / L; }
         g.pp_shift = 1;   // k_a + k_b of two half-shifted points has index ja + jb + 1
     } else {
         for (int a = 0; a < N; ++a) {
-            const double th = off + 2.0 * M_PI * a / N;
-            const double r = fermi_radius(xi, th);
+            // representative energy of the patch's shell: 0 on the Fermi surface, the middle
+            // of an inner shell, the outermost shell's edge plus half the width below it
+            const int e = a / Nsec, k = std::abs(e - m);
+            double level = 0.0;
+            if (k > 0) {
+                const double lo = edge[k - 1], below = k > 1 ? edge[k - 2] : 0.0;
+                level = k < m ? 0.5 * (lo + edge[k]) : lo + 0.5 * (lo - below);
+                if (e < m) level = -level;
+            }
+            const double th = off + 2.0 * M_PI * (a % Nsec) / Nsec;
+            const double r = fermi_radius(xi, th, level);
             const double kx = r * std::cos(th), ky = r * std::sin(th);
             g.anchor[2 * a] = wrap(std::lround(kx * L / (2.0 * M_PI)), L);
             g.anchor[2 * a + 1] = wrap(std::lround(ky * L / (2.0 * M_PI)), L);

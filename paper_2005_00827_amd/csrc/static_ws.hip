@@ -48,7 +48,9 @@ bool same_config(const Slot& s, const fm_config& c) {
                       a.channels == c.channels && a.precision == c.precision &&
                       a.n_zT == c.n_zT && a.stream == c.stream && a.max_batch == c.max_batch &&
                       a.tile_rows == c.tile_rows && a.flow == c.flow && a.g_end == c.g_end &&
-                      a.v_rel == c.v_rel && a.y_kernel == c.y_kernel;
+                      a.v_rel == c.v_rel && a.y_kernel == c.y_kernel &&
+                      a.sync_batch == c.sync_batch && a.n_shells == c.n_shells &&
+                      a.shell_edges == nullptr && c.shell_edges == nullptr;
     if (!same) return false;
     if (c.n_zT <= 0) return true;
     const size_t nz = static_cast<size_t>(c.n_zT), nt = nz * static_cast<size_t>(c.N);

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmflow.so")
 
 FM_OK, FM_EINVAL, FM_ENOMEM, FM_EDEVICE, FM_ESTATE = 0, -1, -2, -3, -4
-GEOM_ANGULAR, GEOM_IDENTITY = 0, 1
+GEOM_ANGULAR, GEOM_IDENTITY, GEOM_SHELLS = 0, 1, 2
+GEOMETRIES = {"angular": GEOM_ANGULAR, "identity": GEOM_IDENTITY, "shells": GEOM_SHELLS}
 RK4_FIXED, RK45_DOPRI = 0, 1
 FP64, FP32, FP32_BF16MFMA, FP64_DIRECT, FP32_BF16X3 = 0, 1, 2, 3, 4
 CH_PP, CH_CR, CH_D, CH_ALL = 1, 2, 4, 7
@@ -45,7 +46,7 @@ class Config(ctypes.Structure):
                 ("n_zT", c_int), ("z_lnT", POINTER(c_double)), ("z_table", POINTER(c_double)),
                 ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int),
                 ("flow", c_int), ("g_end", c_double), ("v_rel", c_double), ("y_kernel", c_int),
-                ("sync_batch", c_int)]
+                ("sync_batch", c_int), ("n_shells", c_int), ("shell_edges", POINTER(c_double))]
 
 
 class Result(ctypes.Structure):
@@ -118,10 +119,10 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
                 integrator="rk4", n_steps=200, rtol=0.0, atol=0.0, h0=0.0, h_min=0.0,
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
                 stream=None, max_batch=1, tile_rows=0, flow="temperature", g_end=0.0,
-                v_rel=0.0, y_kernel=0, sync_batch=False):
+                v_rel=0.0, y_kernel=0, sync_batch=False, n_shells=0, shell_edges=None):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
-    cfg.geometry = GEOM_IDENTITY if geometry == "identity" else GEOM_ANGULAR
+    cfg.geometry = GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry)
     cfg.N, cfg.L = int(N), int(L)
     cfg.T0, cfg.T_end = float(T0), float(T_end)
     cfg.integrator = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
@@ -147,6 +148,13 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
     cfg.v_rel = float(v_rel)
     cfg.y_kernel = int(y_kernel)
     cfg.sync_batch = int(sync_batch)
+    cfg.n_shells = int(n_shells)
+    if shell_edges is not None:
+        se = np.ascontiguousarray(shell_edges, np.float64)
+        if se.shape != ((int(n_shells) - 1) // 2,):
+            raise ValueError("shell_edges must hold (n_shells - 1) / 2 values")
+        cfg.shell_edges = _pd(se)
+        keep = keep + [se]
     cfg._keep = keep
     return cfg
 

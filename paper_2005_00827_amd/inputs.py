@@ -13,6 +13,8 @@ in Sec. 3 of the paper; initial condition V = U; stop when max|V| > 20 t; T_end 
   C3  N=96,  L=256, U=3,   Dormand-Prince, no Z, BF16 operands with FP32 accumulation
   C4  64 flows, U in {1.0,1.5,...,4.5} x T0_i = 0.5*4^(i/7), N=48, L=128, FP32, ragged
   C5  16 flows, U_i = 1 + 3i/15, N=128, L=512, synthetic Z (per-flow U), BF16 contraction
+  shells  energy-shell patching as in the paper's 224-patch runs: 7 shells x 32 sectors,
+      L=128, U=3, Dormand-Prince, no Z, FP32
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ WORKLOADS = {
                T_end=0.01, integrator="rk45", n_steps=200, z=False, precision="fp32"),
     "C5": dict(N=128, L=512, U=[1.0 + 3.0 * i / 15.0 for i in range(16)], T0=[1.0] * 16,
                T_end=0.01, integrator="rk45", n_steps=200, z=True, precision="bf16"),
+    "shells": dict(N=224, n_shells=7, L=128, U=[3.0], T0=[1.0], T_end=0.01, integrator="rk45",
+                   n_steps=200, z=False, precision="fp32"),
 }
 
 

@@ -38,6 +38,26 @@ def test_geometry_matches_oracle(N, L, identity, tp, mu):
         assert margin == pytest.approx(omargin, rel=1e-9)
 
 
+@pytest.mark.parametrize("N,L,S,edges,tp,mu", [(24, 32, 3, None, 0, 0), (40, 32, 5, [0.3, 1.1], 0, 0),
+                                               (224, 128, 7, None, 0, 0),
+                                               (24, 32, 3, None, -0.3, -0.4)])
+def test_shell_geometry_matches_oracle(N, L, S, edges, tp, mu):
+    """Energy shells: the library's host geometry (written independently) equals the
+    oracle's bit for bit; the point group still reduces the transfers (empty patches of a
+    sector the band does not reach permute with their sector)."""
+    cfg = fm.make_config(N, L, tp=tp, mu=mu, geometry="shells", n_shells=S, shell_edges=edges)
+    xi, patch, anchor, npp, nph, margin = fm.geometry_query(cfg)
+    m = O.model(N, L, tp=tp, mu=mu, n_shells=S, shell_edges=edges)
+    oxi, opatch, oanchor, omargin = O.geometry(m)
+    assert np.array_equal(patch, opatch)
+    assert np.array_equal(anchor, oanchor)
+    assert np.abs(xi - oxi).max() <= 1e-15
+    assert (npp, nph) == O.transfer_counts(m)
+    nrp, nrd = fm.representative_counts(cfg)
+    if tp == 0 and mu == 0:
+        assert nrp < npp / 4 and nrd < nph / 4
+
+
 def test_transfer_counts_of_the_workloads():
     for (N, L), n in {(16, 32): 48, (48, 128): 424, (96, 256): 1520, (128, 512): 2856}.items():
         _, _, _, npp, nph, _ = fm.geometry_query(fm.make_config(N, L))
@@ -81,6 +101,9 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=16, L=32, flow="interaction", T0=0.0), "T0 > 0"),
     (dict(N=16, L=32, flow="interaction", T0=0.2, g_end=-1.0), "g_end"),
     (dict(N=136, L=128, precision="bf16"), "N <= 128"),
+    (dict(N=24, L=32, geometry="shells", n_shells=2), "odd n_shells"),
+    (dict(N=24, L=32, geometry="shells", n_shells=5), "odd n_shells"),
+    (dict(N=24, L=32, geometry="shells", n_shells=3, shell_edges=[-0.5]), "shell edges"),
     (dict(N=136, L=128, precision="bf16x3"), "N <= 128"),
 ])
 def test_invalid_configs_rejected(kw, msg):
