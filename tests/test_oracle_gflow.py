@@ -108,7 +108,15 @@ def test_n1_attractive_crossing(integrator, n):
     assert res["U_star"] == pytest.approx(g2 * U, rel=1e-7)
     (g0, m0), (g1, m1) = tr[-2], tr[-1]
     assert m0 <= vmax < m1
-    assert res["g_c"] == pytest.approx(O.gc_interp(g0, m0, g1, m1, vmax), abs=1e-14)
+    # the crossing of 1/max|V| = 1/v_max on the parabola in g^2 through the last three
+    # accepted points, inside the last step (exactly linear for N = 1 up to the integrator's
+    # own error, so the straight line through the last two agrees closely)
+    coef = np.polyfit(tr[-3:, 0] ** 2, 1.0 / tr[-3:, 1], 2)
+    roots = [r.real for r in np.roots(coef - np.array([0.0, 0.0, 1.0 / vmax]))
+             if abs(r.imag) < 1e-12 and g0 ** 2 <= r.real <= g1 ** 2]
+    assert len(roots) == 1
+    assert res["g_c"] == pytest.approx(math.sqrt(roots[0]), abs=1e-10)
+    assert res["g_c"] == pytest.approx(O.gc_interp(g0, m0, g1, m1, vmax), abs=1e-8)
 
 
 def test_stop_at_start():
