@@ -120,8 +120,9 @@ typedef struct {
     int n_zT;                 /* 0: no quasi-particle feedback (Z = 1) */
     const double *z_lnT;      /* host [n_zT], ascending nodes in the flow parameter (ln T, or
                                  g in [0, g_end] for the interaction flow); copied */
-    const double *z_table;    /* host [n_zT][N], 0 < Z <= 1, linear between nodes, clamped
-                                 outside; copied */
+    const double *z_table;    /* host [n_zT][N], every Z positive and finite (Z passes 1
+                                 where Re Sigma slopes upward, as its definition allows),
+                                 linear between nodes, clamped outside; copied */
     void *stream;             /* hipStream_t or NULL */
     int max_batch;            /* capacity (flows) for every batched call; >= 1 */
     int tile_rows;            /* single-precision phase 2a: 16-row transfer tiles per
@@ -238,7 +239,7 @@ int fm_flow_step(fm_flow *h, int batch, double *lnT, double *hstep, double *V_de
  * captured graph; finished flows are masked.  z_lnT / z_tables: NULL (use cfg's table for
  * every flow, or none) or per-flow host arrays [n_flows][n_zT] and [n_flows][n_zT][N],
  * checked as fm_flow_init checks the configured table (FM_EINVAL unless every flow's nodes
- * ascend and every Z lies in (0, 1]).
+ * ascend and every Z is positive and finite).
  * V_final_dev: NULL or a device array of n_flows*N^3 doubles receiving the final states.
  * res[n_flows] (host) receives the outcomes. */
 int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0,
@@ -255,6 +256,30 @@ int fm_flow_run_batch(fm_flow *h, int n_flows, const double *U, const double *T0
  * bracket. */
 int fm_flow_tstar(fm_flow *h, int n_flows, const double *U, double T_lo, double T_hi,
                   double rtol, double *T_star, int *status);
+
+/* Quasi-particle weights from the self-energy on the real axis (Sec. 3.1: Im Sigma as raw
+ * data on a frequency grid, Re Sigma by Kramers-Kronig, Z from the slope of Re Sigma taken
+ * outside the window of inverted slope; App. A, Eq. definition_Z, Z = (1 - d Re Sigma/dw)^-1,
+ * projected onto each patch's representative point k).  Im Sigma is the second-order
+ * (two-loop) diagram of a static vertex,
+ *   Im Sigma(w, k) = -pi L^-4 sum_{p1,p3} W [f1 (1-f2)(1-f3) + (1-f1) f2 f3]
+ *                    delta(w + xi1 - xi2 - xi3),   p2 = k + p1 - p3 (its energy exact),
+ * with W = U^2 when V_dev is NULL (second-order perturbation theory in the bare U), else
+ * W = V(a,b,c)^2 + (V(a,b,c) - V(b,a,c))^2 / 2 for the flowing vertex V_dev (device,
+ * [N][N][N] doubles; a, b, c the patches of k, p1, p3), which is U^2 for V = U.  The delta
+ * function is shared linearly between the two nearest of FM_SIGMA_NW frequency nodes
+ * w_i = -W0 + 2 W0 i / (FM_SIGMA_NW - 1), W0 = fm_sigma_wmax(cfg); Re Sigma is the
+ * principal-value integral of the piecewise-linear Im Sigma; Z = 1 / (1 - s) with s the
+ * least-squares slope of Re Sigma over the nodes with 2T <= |w| <= 4T, NaN when fewer than
+ * 8 nodes fall there (T below about 4 W0 / (FM_SIGMA_NW - 1): the slope is not resolved).
+ * The slope may pass zero far from low T (Z > 1 where the window reaches the band's flank, as
+ * the definition allows) and, on a loop grid too coarse for T, pass 1 (Z < 0).
+ * Z: host [N]; im_sigma, re_sigma: NULL or host [N][FM_SIGMA_NW].  Synchronous on cfg.stream.
+ * FM_EINVAL for T <= 0 or a null Z. */
+enum { FM_SIGMA_NW = 2048 };
+int fm_flow_z(fm_flow *h, double T, double U, const double *V_dev, double *Z, double *im_sigma,
+              double *re_sigma);
+double fm_sigma_wmax(const fm_config *cfg);
 
 /* Host-only geometry query (no device needed): xi[L*L], patch[L*L], anchor[N][2] (snapped
  * Fermi-point transfer indices, or loop indices in identity mode), the numbers of distinct

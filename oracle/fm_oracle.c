@@ -40,6 +40,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <stdint.h>
+#include <stdio.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -76,6 +77,7 @@ typedef struct {
     int rhs_binned;     /* evaluate every right-hand side in the binned form (the same sums
                            in another order; measures how a flow amplifies rounding-order
                            differences) */
+    int progress;       /* 1: one line per step attempt on stderr (long flows) */
 } orc_flowcfg;
 
 typedef struct {
@@ -641,6 +643,121 @@ int orc_rhs_binned(const orc_model *m, double T, const double *Z, const double *
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* The quasi-particle weight from the self-energy on the real axis (Sec. 3.1: Im Sigma as   */
+/* raw data on a frequency grid, Re Sigma by Kramers-Kronig, Z from the slope of Re Sigma  */
+/* taken outside the window of inverted slope; App. A, Eq. definition_Z).                  */
+/*                                                                                      */
+/* The self-energy is the two-loop (second-order) diagram of a static vertex: for an      */
+/* external point k (the patch's representative point, not snapped) and loop points p1   */
+/* (hole), p3 (particle), with p2 = k + p1 - p3 (particle) taken off the grid exactly,     */
+/*   Im Sigma(w, k) = -pi (1/L^4) sum_{p1,p3} W F delta(w + xi1 - xi2 - xi3),              */
+/*   F = f1 (1 - f2)(1 - f3) + (1 - f1) f2 f3,                                            */
+/* and W the squared vertex summed over spins: U^2 for the bare coupling (second-order    */
+/* perturbation theory), else with V at the patches a of k, b of p1, c of p3,             */
+/*   W = V(a,b,c)^2 + (V(a,b,c) - V(b,a,c))^2 / 2                                         */
+/* (the opposite-spin pair with both assignments of its outgoing lines, and the            */
+/* antisymmetrised same-spin pair), which is U^2 for V = U.  The delta function is spread  */
+/* over the two nearest nodes of a uniform grid of n_w frequencies on [-W0, W0],          */
+/* W0 = 3.0001 (4|t| + 4|t'| + |mu|), linearly (every term's weight kept exactly).         */
+/* Re Sigma(w) = -(1/pi) P int Im Sigma(w') / (w - w') dw' with Im Sigma linear between    */
+/* nodes, integrated in closed form per interval.                                          */
+/* Z = 1 / (1 - s), s the least-squares slope of Re Sigma over the nodes with              */
+/* 2T <= |w| <= 4T (a margin of 2T around the Fermi level, where the slope inverts); NaN  */
+/* when fewer than 8 nodes fall there, a slope the frequency grid does not resolve.       */
+/* ------------------------------------------------------------------------------------ */
+static double fermi(double x, double T) { return 0.5 * (1.0 - tanh(0.5 * x / T)); }
+
+/* Representative point of patch a: the loop point itself under identity patching, else  */
+/* the unsnapped point on the patch's centre ray at its shell's representative energy.    */
+static void patch_point(const orc_model *m, int a, double *kx, double *ky)
+{
+    if (m->identity) { *kx = grid_k(a % m->L, m->L); *ky = grid_k(a / m->L, m->L); return; }
+    int S = n_shells_of(m), Ns = m->N / S;
+    fs_point(m, theta_off(Ns) + 2.0 * M_PI * (a % Ns) / Ns, shell_energy(m, a / Ns), kx, ky);
+}
+
+double orc_sigma_wmax(const orc_model *m)
+{
+    return 3.0001 * (4.0 * fabs(m->t) + 4.0 * fabs(m->tp) + fabs(m->mu));
+}
+
+/* Principal-value Kramers-Kronig of a piecewise-linear Im on a uniform grid (re = Re). */
+void orc_kramers_kronig(int n_w, double w0, double dw, const double *im, double *re)
+{
+    for (int i = 0; i < n_w; ++i) {
+        double w = w0 + dw * i, acc = 0.0;
+        for (int j = 0; j + 1 < n_w; ++j) {
+            double x0 = w0 + dw * j, x1 = x0 + dw;
+            double slope = (im[j + 1] - im[j]) / dw;
+            double at_w = im[j] + slope * (w - x0);      /* the interval's line at w */
+            acc -= slope * dw;
+            if (j != i && j + 1 != i)                     /* the two touching w cancel */
+                acc += at_w * log(fabs((w - x0) / (w - x1)));
+        }
+        re[i] = -acc / M_PI;
+    }
+}
+
+int orc_sigma2(const orc_model *m, double T, double U, const double *V, int n_w, double *w_out,
+               double *im_out, double *re_out, double *Z_out, int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || n_w < 16 || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    int N = g.N, L = g.L, np = g.np;
+    double W0 = orc_sigma_wmax(m), dw = 2.0 * W0 / (n_w - 1);
+    if (!(W0 > 0.0)) { geom_free(&g); return -1; }
+    double *f = (double *)malloc(sizeof(double) * np);
+    for (int j = 0; j < np; ++j) f[j] = fermi(g.xi[j], T);
+    for (int i = 0; i < n_w; ++i) if (w_out) w_out[i] = -W0 + dw * i;
+#pragma omp parallel for schedule(dynamic)
+    for (int a = 0; a < N; ++a) {
+        double kx, ky;
+        patch_point(m, a, &kx, &ky);
+        double *h = (double *)calloc(n_w, sizeof(double));
+        for (int j1 = 0; j1 < np; ++j1) {
+            double k1x = grid_k(j1 % L, L), k1y = grid_k(j1 / L, L);
+            for (int j3 = 0; j3 < np; ++j3) {
+                double k3x = grid_k(j3 % L, L), k3y = grid_k(j3 / L, L);
+                double x2 = disp(m, kx + k1x - k3x, ky + k1y - k3y);
+                double f2 = fermi(x2, T);
+                double F = f[j1] * (1.0 - f2) * (1.0 - f[j3]) + (1.0 - f[j1]) * f2 * f[j3];
+                double W = U * U;
+                if (V) {
+                    int b = g.patch[j1], c = g.patch[j3];
+                    double v = V[VIX(N, a, b, c)], vx = V[VIX(N, b, a, c)];
+                    W = v * v + 0.5 * (v - vx) * (v - vx);
+                }
+                double E = x2 + g.xi[j3] - g.xi[j1];
+                double x = (E + W0) / dw;
+                int i = (int)floor(x);
+                double fr = x - i;
+                h[i] += (1.0 - fr) * W * F;
+                h[i + 1] += fr * W * F;
+            }
+        }
+        double *im = im_out + (size_t)a * n_w;
+        for (int i = 0; i < n_w; ++i) im[i] = -M_PI * h[i] / ((double)np * np * dw);
+        double *re = (double *)malloc(sizeof(double) * n_w);
+        orc_kramers_kronig(n_w, -W0, dw, im, re);
+        if (re_out) memcpy(re_out + (size_t)a * n_w, re, sizeof(double) * n_w);
+        double sx = 0, sy = 0, sxx = 0, sxy = 0;
+        int cnt = 0;
+        for (int i = 0; i < n_w; ++i) {
+            double w = -W0 + dw * i;
+            if (fabs(w) < 2.0 * T || fabs(w) > 4.0 * T) continue;
+            sx += w; sy += re[i]; sxx += w * w; sxy += w * re[i]; ++cnt;
+        }
+        double slope = (cnt * sxy - sx * sy) / (cnt * sxx - sx * sx);
+        if (Z_out) Z_out[a] = cnt >= 8 ? 1.0 / (1.0 - slope) : NAN;
+        free(re); free(h);
+    }
+    free(f);
+    geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Quasi-particle weights along the flow: a table Z_a(s_i) in the flow parameter (ln T, or  */
 /* g for the interaction flow), linear in s between nodes, clamped outside.               */
 /* ------------------------------------------------------------------------------------ */
@@ -874,6 +991,11 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
             int last = (dir * (s + h - s_end) >= 0.0);
             double ht = last ? (s_end - s) : h;
             double err = dopri_attempt(&cx, s, ht, V, k, Vn, tmp, n);
+            if (f->progress) {
+                fprintf(stderr, "oracle flow: s %.6f h %.3e err %.3g max|V| %.4g\n", s, ht, err,
+                        mV);
+                fflush(stderr);
+            }
             if (err <= 1.0) {
                 double s_new = last ? s_end : s + ht;
                 double m_new = max_abs(Vn, n, &finite);

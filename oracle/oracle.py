@@ -47,7 +47,7 @@ class FlowCfg(ctypes.Structure):
                 ("h0", c_double), ("h_min", c_double), ("v_max", c_double),
                 ("n_z", c_int), ("z_lnT", POINTER(c_double)), ("z_tab", POINTER(c_double)),
                 ("gflow", c_int), ("g_end", c_double), ("v_rel", c_double),
-                ("rhs_binned", c_int)]
+                ("rhs_binned", c_int), ("progress", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -95,6 +95,9 @@ def lib():
             "orc_flow": (i, [pm, pf, d, pd, pr, pd, i, pi, i]),
             "orc_step": (i, [pm, pf, pd, pd, pd, pi, pd, i]),
             "orc_flow_sync": (i, [pm, pf, i, pd, pd, pr, i]),
+            "orc_sigma2": (i, [pm, d, d, pd, i, pd, pd, pd, pd, i]),
+            "orc_kramers_kronig": (None, [i, d, d, pd, pd]),
+            "orc_sigma_wmax": (d, [pm]),
             "orc_dopri_tableau": (i, [pd, pd, pd]),
             "orc_num_threads": (i, []),
         }
@@ -240,16 +243,18 @@ def rhs_points(m: Model, T, V, abc, Z=None, nthreads=0):
 # --------------------------------------------------------------------------------------
 def flowcfg(T0=1.0, T_end=0.01, integrator=0, n_steps=200, rtol=1e-6, atol=None, U=1.0,
             h0=0.0, h_min=0.0, v_max=20.0, z_lnT=None, z_tab=None, gflow=False, g_end=1.0,
-            v_rel=100.0, binned=False):
+            v_rel=100.0, binned=False, progress=False):
     """Build a FlowCfg; keeps references to the Z arrays on the returned object.  gflow:
     interaction flow at the fixed temperature T0 from g = 0 to g_end (Z nodes in g), stopped
     when max|V| exceeds v_rel |U|.  binned: every right-hand side in the binned form (the
-    same sums in another order)."""
+    same sums in another order).  progress: one line per Dormand-Prince step attempt on
+    stderr."""
     if atol is None:
         atol = 1e-9 * max(1.0, abs(U))
     cfg = FlowCfg(float(T0), float(T_end), int(integrator), int(n_steps), float(rtol),
                   float(atol), float(h0), float(h_min), float(v_max), 0, None, None,
-                  int(bool(gflow)), float(g_end), float(v_rel), int(bool(binned)))
+                  int(bool(gflow)), float(g_end), float(v_rel), int(bool(binned)),
+                  int(bool(progress)))
     if z_tab is not None:
         z_lnT = np.ascontiguousarray(z_lnT, np.float64)
         z_tab = np.ascontiguousarray(z_tab, np.float64)
@@ -287,6 +292,35 @@ def flow_sync(m: Model, cfg: FlowCfg, U, nthreads=0):
                            int(nthreads)):
         raise ValueError("oracle flow_sync rejected its arguments")
     return V.reshape(nf, N, N, N), [r.as_dict() for r in res]
+
+
+def sigma2(m: Model, T, U, V=None, n_w=2048, nthreads=0):
+    """Second-order self-energy on the real axis at each patch's representative point, bare
+    (V None: U^2) or with the static vertex V; returns (w [n_w], Im [N, n_w], Re [N, n_w],
+    Z [N])."""
+    N = m.N
+    w = np.zeros(n_w)
+    im = np.zeros((N, n_w))
+    re = np.zeros((N, n_w))
+    Z = np.zeros(N)
+    Vp = None
+    if V is not None:
+        Vp = np.ascontiguousarray(V, np.float64).reshape(N ** 3)
+    if lib().orc_sigma2(ctypes.byref(m), float(T), float(U), _pd(Vp), int(n_w), _pd(w), _pd(im),
+                        _pd(re), _pd(Z), int(nthreads)):
+        raise ValueError("oracle sigma2 rejected its arguments")
+    return w, im, re, Z
+
+
+def kramers_kronig(w0, dw, im):
+    im = np.ascontiguousarray(im, np.float64)
+    re = np.zeros_like(im)
+    lib().orc_kramers_kronig(im.shape[0], float(w0), float(dw), _pd(im), _pd(re))
+    return re
+
+
+def sigma_wmax(m: Model):
+    return lib().orc_sigma_wmax(ctypes.byref(m))
 
 
 def step(m: Model, cfg: FlowCfg, lnT, h, V, nthreads=0):

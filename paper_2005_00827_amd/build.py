@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmflow.so")
-SOURCES = ["kernels.hip", "fm_flow.cpp", "geometry.cpp", "static_ws.hip"]
+SOURCES = ["kernels.hip", "fm_flow.cpp", "geometry.cpp", "static_ws.hip", "sigma.hip"]
 ARCH = os.environ.get("FM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

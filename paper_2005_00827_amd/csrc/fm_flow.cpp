@@ -233,6 +233,12 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.Z_stage = L.take<double>(static_cast<size_t>(B) * N);
     b.zw_stage = L.take<double>(2 * static_cast<size_t>(B));
     b.U = L.take<double>(B);
+    b.kpt = L.take<double>(2 * static_cast<size_t>(N));
+    b.sig_f = L.take<double>(np);
+    b.sig_hist = L.take<double>(static_cast<size_t>(N) * kSigmaW);
+    b.sig_im = L.take<double>(static_cast<size_t>(N) * kSigmaW);
+    b.sig_re = L.take<double>(static_cast<size_t>(N) * kSigmaW);
+    b.sig_Z = L.take<double>(N);
     b.grp_members = L.take<int>(B);
     b.grp_off = L.take<int>(static_cast<size_t>(B) + 1);
     // integrator reduction blocks per flow: one per 8 x 8 x 16 element tile, at most 512
@@ -641,6 +647,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.item_q, hg.item_q);
     if (e == hipSuccess) e = upv(h->b.item_p0, hg.item_p0);
     if (e == hipSuccess) e = upv(h->b.item_rec, hg.item_rec);
+    if (e == hipSuccess) e = up(h->b.kpt, hg.kpt.data(), sizeof(double) * hg.kpt.size());
     // bins start zeroed (with their padding): phase 2a may read past a row's end, and only
     // finite values may meet the zero operand there
     if (e == hipSuccess && h->b.bins) e = hipMemsetAsync(h->b.bins, 0, h->b.bins_bytes, h->stream);
@@ -654,7 +661,10 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
         h->zlnT.assign(c.z_lnT, c.z_lnT + c.n_zT);
         h->ztab.assign(c.z_table, c.z_table + static_cast<size_t>(c.n_zT) * N);
         for (double z : h->ztab)
-            if (!(z > 0.0 && z <= 1.0)) { delete h; return fail(FM_EINVAL, "Z must lie in (0, 1]"); }
+            if (!(z > 0.0 && std::isfinite(z))) {
+                delete h;
+                return fail(FM_EINVAL, "Z must be positive and finite");
+            }
         rc = upload_z(h, c.max_batch, nullptr, nullptr);
         if (rc) { delete h; return rc; }
     }
@@ -869,7 +879,8 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
             for (int i = 1; i < nz; ++i)
                 if (!(l[i] > l[i - 1])) return fail(FM_EINVAL, "per-flow Z nodes must ascend");
             for (size_t i = 0; i < static_cast<size_t>(nz) * N; ++i)
-                if (!(t[i] > 0.0 && t[i] <= 1.0)) return fail(FM_EINVAL, "per-flow Z must lie in (0, 1]");
+                if (!(t[i] > 0.0 && std::isfinite(t[i])))
+                    return fail(FM_EINVAL, "per-flow Z must be positive and finite");
         }
     }
     const fm_config& c = h->cfg;
@@ -1033,6 +1044,40 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
         r.n_rhs = s.n_rhs;
     }
     return FM_OK;
+}
+
+int fm_flow_z(fm_flow* h, double T, double U, const double* V_dev, double* Z, double* im_sigma,
+              double* re_sigma) {
+    if (!h) return fail(FM_EINVAL, "null handle");
+    if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(U)) return fail(FM_EINVAL, "need T > 0, finite U");
+    if (!Z) return fail(FM_EINVAL, "null Z");
+    const fm_config& c = h->cfg;
+    SigmaArgs s{};
+    s.N = c.N;
+    s.L = c.L;
+    s.t = c.t; s.tp = c.tp; s.mu = c.mu; s.T = T; s.U = U;
+    s.w0 = fm_sigma_wmax(&c);
+    s.dw = 2.0 * s.w0 / (kSigmaW - 1);
+    if (!(s.w0 > 0.0) || !std::isfinite(s.w0)) return fail(FM_EINVAL, "the band has no width (t, t', mu)");
+    s.xi = h->b.xi;
+    s.patch = h->b.patch;
+    s.kpt = h->b.kpt;
+    s.f = h->b.sig_f;
+    launch_sigma(h->stream, s, V_dev, h->b.sig_hist, h->b.sig_im, h->b.sig_re, h->b.sig_Z);
+    HIPCHK(hipGetLastError());
+    const size_t nw = static_cast<size_t>(c.N) * kSigmaW;
+    HIPCHK(hipMemcpyAsync(Z, h->b.sig_Z, sizeof(double) * c.N, hipMemcpyDeviceToHost, h->stream));
+    if (im_sigma)
+        HIPCHK(hipMemcpyAsync(im_sigma, h->b.sig_im, sizeof(double) * nw, hipMemcpyDeviceToHost, h->stream));
+    if (re_sigma)
+        HIPCHK(hipMemcpyAsync(re_sigma, h->b.sig_re, sizeof(double) * nw, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return FM_OK;
+}
+
+double fm_sigma_wmax(const fm_config* cfg) {
+    if (!cfg) return 0.0;
+    return 3.0001 * (4.0 * std::fabs(cfg->t) + 4.0 * std::fabs(cfg->tp) + std::fabs(cfg->mu));
 }
 
 int fm_flow_tstar(fm_flow* h, int n, const double* U, double T_lo, double T_hi, double rtol,

@@ -21,6 +21,7 @@ struct HostGeometry {
     std::vector<double> xi;          // [np] dispersion at each loop point
     std::vector<int> patch;          // [np] patch of each loop point
     std::vector<int> anchor;         // [N][2] transfer-grid index of each patch's Fermi point
+    std::vector<double> kpt;         // [N][2] each patch's representative point (not snapped)
     std::vector<int> q_pp, q_ph;     // distinct transfers, flat index mx + L*my
     std::vector<int> map_pp;         // [a*N+b] -> index into q_pp of k_a + k_b
     std::vector<int> map_cr;         // [b*N+c] -> index into q_ph of k_c - k_b
@@ -182,6 +183,10 @@ struct Buffers {
     double* part;                      // [B][nblk][2] reduction partials
     double* wtab;                      // direct mode: [B][nP+nD][np]
     double* U;                         // [B] bare couplings of run_batch
+    double* kpt;                       // [N][2] patch representative points (self-energy)
+    double* sig_f;                     // [L^2] Fermi factors of the self-energy's temperature
+    double* sig_hist; double* sig_im; double* sig_re;   // [N][kSigmaW]
+    double* sig_Z;                     // [N]
     int* grp_members;                  // [B] flows of run_batch's step-sharing groups, by group
     int* grp_off;                      // [B + 1] group g: members grp_off[g] .. grp_off[g+1]
     int nblk;                          // reduction blocks per flow
@@ -238,5 +243,20 @@ void launch_finish_sync(hipStream_t s, const Buffers& b, int ngroups, int max_me
                         int fixed_steps, int rebind);
 void launch_commit(hipStream_t s, bool dbl, const Buffers& b, int nf, size_t N3, double* V);
 void launch_copy(hipStream_t s, const double* from, double* to, size_t n);
+
+// Quasi-particle weight provider (sigma.hip): frequency nodes of the real-axis self-energy.
+constexpr int kSigmaW = 2048;
+struct SigmaArgs {
+    int N, L;
+    double t, tp, mu, T, U;
+    double w0, dw;            // nodes -w0 + dw i, i < kSigmaW
+    const double* xi;         // [L^2]
+    const int* patch;         // [L^2]
+    const double* kpt;        // [N][2] representative points
+    double* f;                // [L^2] Fermi factors at T (filled by the launch)
+};
+// Im Sigma, Re Sigma [N][kSigmaW] and Z [N] at temperature s.T; V = null: bare U^2 weights.
+void launch_sigma(hipStream_t st, const SigmaArgs& s, const double* V, double* hist, double* im,
+                  double* re, double* Z);
 
 }  // namespace fm

@@ -407,8 +407,12 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
         err = buf;
         return false;
     }
+    g.kpt.resize(2 * static_cast<size_t>(N));
     if (g.identity) {
-        for (int a = 0; a < N; ++a) { g.anchor[2 * a] = a % L; g.anchor[2 * a + 1] = a / L; }
+        for (int a = 0; a < N; ++a) {
+            g.anchor[2 * a] = a % L; g.anchor[2 * a + 1] = a / L;
+            g.kpt[2 * a] = kg[a % L]; g.kpt[2 * a + 1] = kg[a / L];
+        }
         g.pp_shift = 1;   // k_a + k_b of two half-shifted points has index ja + jb + 1
     } else {
         for (int a = 0; a < N; ++a) {
@@ -424,6 +428,8 @@ bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err) {
             const double th = off + 2.0 * M_PI * (a % Nsec) / Nsec;
             const double r = fermi_radius(xi, th, level);
             const double kx = r * std::cos(th), ky = r * std::sin(th);
+            g.kpt[2 * a] = kx;
+            g.kpt[2 * a + 1] = ky;
             g.anchor[2 * a] = wrap(std::lround(kx * L / (2.0 * M_PI)), L);
             g.anchor[2 * a + 1] = wrap(std::lround(ky * L / (2.0 * M_PI)), L);
         }

@@ -32,7 +32,8 @@ INTEGRATORS = {"rk4": RK4_FIXED, "rk45": RK45_DOPRI}
 EXPORTS = ("fm_flow_workspace_bytes", "fm_flow_init", "fm_flow_rhs", "fm_flow_rhs_g",
            "fm_flow_step", "fm_flow_run_batch", "fm_flow_tstar", "fm_geometry_query",
            "fm_flow_set_timing", "fm_flow_timings", "fm_flow_kernel_time", "fm_flow_destroy",
-           "fm_last_error", "fm_flow_rhs_static")
+           "fm_last_error", "fm_flow_rhs_static", "fm_flow_z", "fm_sigma_wmax")
+SIGMA_NW = 2048
 FLOWS = {"temperature": 0, "interaction": 1}
 
 
@@ -92,6 +93,8 @@ def load():
         "fm_flow_timings": (c_int, [c_void_p, POINTER(c_char_p), pd, pi, c_int]),
         "fm_flow_kernel_time": (c_int, [c_void_p, c_int, c_int, c_int, pd]),
         "fm_flow_rhs_static": (c_int, [pc, c_int, pd, c_void_p, c_void_p]),
+        "fm_flow_z": (c_int, [c_void_p, c_double, c_double, c_void_p, pd, pd, pd]),
+        "fm_sigma_wmax": (c_double, [pc]),
         "fm_flow_destroy": (None, [c_void_p]),
         "fm_last_error": (c_char_p, []),
     }
@@ -257,6 +260,28 @@ class Flow:
         _check(load().fm_flow_tstar(self.h, U.shape[0], _pd(U), float(T_lo), float(T_hi),
                                     float(rtol), _pd(out), _pi(st)))
         return out, st
+
+    def z(self, T, U, V=None, spectra=False):
+        """Quasi-particle weights Z[N] from the second-order self-energy on the real axis at
+        temperature T (bare U when V is None, else the static vertex V [N, N, N] float64 CUDA);
+        with spectra, also (w [SIGMA_NW], Im Sigma [N, SIGMA_NW], Re Sigma [N, SIGMA_NW])."""
+        N = self.N
+        Z = np.zeros(N, np.float64)
+        im = re = None
+        if spectra:
+            im = np.zeros((N, SIGMA_NW), np.float64)
+            re = np.zeros((N, SIGMA_NW), np.float64)
+        vp = None
+        if V is not None:
+            if self._state(V) != 1:
+                raise ValueError("one vertex V")
+            vp = c_void_p(V.data_ptr())
+        _check(load().fm_flow_z(self.h, float(T), float(U), vp, _pd(Z), _pd(im), _pd(re)))
+        if not spectra:
+            return Z
+        w0 = load().fm_sigma_wmax(ctypes.byref(self.cfg))
+        w = -w0 + 2.0 * w0 * np.arange(SIGMA_NW) / (SIGMA_NW - 1)
+        return Z, w, im, re
 
     def step(self, lnT, h, V):
         """One integrator step in place on V; returns (lnT, h, accepted) arrays (for the

@@ -421,7 +421,8 @@ def test_flow_with_z_feedback_fp64(torch_dev):
 def test_run_batch_per_flow_z_tables(torch_dev):
     """Three flows in one batch, each with its own Z table (the synthetic table of its own
     U, one of them with fewer nodes' worth of variation), against the oracle's flows with the
-    same tables; then a table that is not ascending, or has a Z outside (0, 1], is refused."""
+    same tables; then a table that is not ascending, or has a Z that is not positive and
+    finite, is refused."""
     fm = _fm()
     torch, dev = torch_dev
     N, L = 16, 32
@@ -445,10 +446,11 @@ def test_run_batch_per_flow_z_tables(torch_dev):
         bad[2, 5] = bad[2, 4]
         with pytest.raises(fm.FmError):
             f.run_batch(U, [1.0] * 3, z_lnT=bad, z_tables=zt)
-        bad = zt.copy()
-        bad[0, 3, 7] = 1.5
-        with pytest.raises(fm.FmError):
-            f.run_batch(U, [1.0] * 3, z_lnT=zl, z_tables=bad)
+        for z in (0.0, -0.2, np.inf, np.nan):
+            bad = zt.copy()
+            bad[0, 3, 7] = z
+            with pytest.raises(fm.FmError):
+                f.run_batch(U, [1.0] * 3, z_lnT=zl, z_tables=bad)
         with pytest.raises(ValueError):
             f.run_batch(U, [1.0] * 3, z_lnT=zl[:, :-1], z_tables=zt)
     finally:
