@@ -423,9 +423,11 @@ def main():
     print("bench: timed %d batches in %.3f s, %d rhs" % (args.steps, wall, n_rhs),
           file=sys.stderr, flush=True)
 
-    # launches per batch of each kernel group (HIP events around each launch of one eager
-    # batch), then each group's average launch duration: 10 back-to-back launches with all 16
-    # flows running on the batch's final state, between HIP events on the library's stream
+    # launches and time per batch of each kernel group (HIP events around each launch of one
+    # eager batch, whose launches shrink as flows stop; the dominant group is the one with the
+    # most time there), then each group's average launch duration: 10 back-to-back launches
+    # with all 16 flows running on the batch's final state, between HIP events on the
+    # library's stream
     flow.set_timing(True)
     flow.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
     tm = flow.timings()
@@ -443,9 +445,9 @@ def main():
             (args.sync if args.sync > 1 else nf)
         wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, rho, prec=args.prec, nbin_flows=nbin)
         ach = achieved(wk, us * 1e-6, nf)
-        launches = tm.get(name, (0.0, 0))[1]
+        batch_ms, launches = tm.get(name, (0.0, 0))
         kernels[name] = {"avg_us": us, "launches_per_batch": launches,
-                         "share_ms_per_batch": us * launches / 1e3, "bound": wk["bound"],
+                         "share_ms_per_batch": batch_ms, "bound": wk["bound"],
                          "achieved": ach, "peak": wk["peak"], "unit": wk["unit"],
                          "frac": ach / wk["peak"]}
         if name == "y":
