@@ -163,6 +163,14 @@ typedef struct {
                                  range otherwise, the outermost shell's inner edge plus half
                                  the width of the shell below it), snapped to the transfer grid.
                                  FM_EINVAL when a loop point lies within 1e-9 of an edge. */
+    const double *k_table;    /* interaction flow with a Z table only: host [n_zT][N] Katanin
+                                 factors K on the Z table's nodes (App. A, Step 3), or NULL
+                                 (K = 1).  The single-scale line Z^2 G0 becomes K Z^2 G0
+                                 (Eq. vertex_flow_feedback_Z_with_Katanin), so a line pair
+                                 carries g Z_a Z_b (K_a Z_a + K_b Z_b) chi; K is linear between
+                                 nodes, clamped outside, any finite sign (it may change sign
+                                 along the flow); copied.  Every flow of the handle uses it:
+                                 fm_flow_run_batch then takes no per-flow Z tables. */
 } fm_config;
 
 typedef struct {
@@ -272,7 +280,7 @@ int fm_flow_tstar(fm_flow *h, int n_flows, const double *U, double T_lo, double 
  * principal-value integral of the piecewise-linear Im Sigma; Z = 1 / (1 - s) with s the
  * least-squares slope of Re Sigma over the nodes with 2T <= |w| <= 4T, NaN when fewer than
  * 8 nodes fall there (T below about 4 W0 / (FM_SIGMA_NW - 1): the slope is not resolved).
- * The slope may pass zero far from low T (Z > 1 where the window reaches the band's flank, as
+ * The slope may turn positive at high T (Z > 1 where the window reaches the band's flank, as
  * the definition allows) and, on a loop grid too coarse for T, pass 1 (Z < 0).
  * Z: host [N]; im_sigma, re_sigma: NULL or host [N][FM_SIGMA_NW].  Synchronous on cfg.stream.
  * FM_EINVAL for T <= 0 or a null Z. */
@@ -280,6 +288,20 @@ enum { FM_SIGMA_NW = 2048 };
 int fm_flow_z(fm_flow *h, double T, double U, const double *V_dev, double *Z, double *im_sigma,
               double *re_sigma);
 double fm_sigma_wmax(const fm_config *cfg);
+
+/* Host-only (no device): the Katanin factors and A_g of the interaction flow (App. A,
+ * Eqs. K_definition and A_g_simple) from quasi-particle weights Z tabulated on n >= 3
+ * ascending scales g[n] (host), z_tab [n][N] (positive, finite).  With s = 1 - 1/Z the slope
+ * of Re(g Sigma_g) at the Fermi level (Eq. definition_Z), so that d_w Re Sigma_g = s/g,
+ *   K = 1 + g^2 d_w Re(d Sigma_g/dg) = 1 - s + g ds/dg,
+ *   A = -(2/g)(1 - Z K)  (= 2 (dZ/dg)/Z; this form at g = 0),
+ * ds/dg the derivative of the parabola through each node and its two neighbours (the first
+ * or last three nodes at the ends).  k_tab [n][N] receives K (for cfg.k_table), a_tab
+ * [n][N] (or NULL) A; a_minmax (or NULL) [n][2] the smallest and largest A over the patches
+ * at each node, the bounds between which A_g's patch dependence is followed.  FM_EINVAL for
+ * n < 3, nodes that do not ascend, or a Z that is not positive and finite. */
+int fm_katanin_table(int n, const double *g, int N, const double *z_tab, double *k_tab,
+                     double *a_tab, double *a_minmax);
 
 /* Host-only geometry query (no device needed): xi[L*L], patch[L*L], anchor[N][2] (snapped
  * Fermi-point transfer indices, or loop indices in identity mode), the numbers of distinct

@@ -44,6 +44,18 @@ def chidot_pp(x, y, T):
     return chidot_ph(x, -y, T)
 
 
+def chi_ph(x, y, T):
+    """Static bubble -(f(x) - f(y))/(x - y), -f'(x) = f(1 - f)/T on the diagonal."""
+    if abs(x - y) <= 1e-9 * T:
+        f = _fermi(0.5 * (x + y), T)
+        return f * (1.0 - f) / T
+    return -(_fermi(x, T) - _fermi(y, T)) / (x - y)
+
+
+def chi_pp(x, y, T):
+    return chi_ph(x, -y, T)
+
+
 def _disp(kx, ky, t, tp, mu):
     return -2.0 * t * (math.cos(kx) + math.cos(ky)) - 4.0 * tp * math.cos(kx) * math.cos(ky) - mu
 
@@ -131,11 +143,21 @@ def _fermi_index(a, N, L, t, tp, mu, S=1, E=()):
     return rnd(kx * L / (2.0 * math.pi)) % L, rnd(ky * L / (2.0 * math.pi)) % L
 
 
-def rhs(V, N, L, T, t=1.0, tp=0.0, mu=0.0, channels=7, Z=None, n_shells=1, shell_edges=None):
+def rhs(V, N, L, T, t=1.0, tp=0.0, mu=0.0, channels=7, Z=None, n_shells=1, shell_edges=None,
+        g=None, K=None):
     """V: nested list or array indexable as V[a][b][c]; returns a dict (a,b,c) -> dV/dlnT.
-    n_shells > 1: energy-shell patches (N = n_shells x angular sectors)."""
+    n_shells > 1: energy-shell patches (N = n_shells x angular sectors).
+    g: the interaction flow's dV/dg at scale g instead, each line pair (j, j') weighted by
+    g Z_j Z_j' (K_j Z_j + K_j' Z_j') times the static bubble (K: Katanin factors, default 1)."""
     out = {}
     z = (lambda a: 1.0) if Z is None else (lambda a: Z[a])
+    kat = (lambda a: 1.0) if K is None else (lambda a: K[a])
+
+    def weight(pj, pu, x, y, pp):
+        if g is None:
+            return z(pj) * z(pu) * (chidot_pp(x, y, T) if pp else chidot_ph(x, y, T))
+        b = chi_pp(x, y, T) if pp else chi_ph(x, y, T)
+        return g * z(pj) * z(pu) * (kat(pj) * z(pj) + kat(pu) * z(pu)) * b
     n = L * L
     S = n_shells if n_shells > 1 else 1
     E = _edges(S, t, shell_edges) if S > 1 else []
@@ -160,19 +182,19 @@ def rhs(V, N, L, T, t=1.0, tp=0.0, mu=0.0, channels=7, Z=None, n_shells=1, shell
                             ux, uy = (qpp[0] - jx - 1) % L, (qpp[1] - jy - 1) % L
                             y = _disp(_k(ux, L), _k(uy, L), t, tp, mu)
                             pu = _patch(ux, uy, L, N)
-                            w = z(pj) * z(pu) * chidot_pp(x, y, T)
+                            w = weight(pj, pu, x, y, True)
                             s -= w * V[a][b][pj] * V[pj][pu][c]
                         if channels & 2:
                             ux, uy = (jx + qcr[0]) % L, (jy + qcr[1]) % L
                             y = _disp(_k(ux, L), _k(uy, L), t, tp, mu)
                             pu = _patch(ux, uy, L, N)
-                            w = z(pj) * z(pu) * chidot_ph(x, y, T)
+                            w = weight(pj, pu, x, y, False)
                             s += w * V[a][pj][pu] * V[pu][b][c]
                         if channels & 4:
                             ux, uy = (jx + qd[0]) % L, (jy + qd[1]) % L
                             y = _disp(_k(ux, L), _k(uy, L), t, tp, mu)
                             pu = _patch(ux, uy, L, N)
-                            w = z(pj) * z(pu) * chidot_ph(x, y, T)
+                            w = weight(pj, pu, x, y, False)
                             s += w * (-2.0 * V[a][pj][c] * V[pu][b][pj]
                                       + V[pj][a][c] * V[pu][b][pj]
                                       + V[a][pj][c] * V[b][pu][pj])

@@ -78,6 +78,8 @@ typedef struct {
                            in another order; measures how a flow amplifies rounding-order
                            differences) */
     int progress;       /* 1: one line per step attempt on stderr (long flows) */
+    const double *k_tab; /* interaction flow only: [n_z][N] Katanin factors K on the same
+                           nodes as z_tab (NULL: K = 1, no Katanin correction) */
 } orc_flowcfg;
 
 typedef struct {
@@ -393,7 +395,10 @@ int orc_transfer_counts(const orc_model *m, int *n_pp, int *n_ph)
  *   interaction flow (App. A, Step 2, Eqs. both_propagators_Z, vertex_flow_feedback_Z):
  *   the line pair S_g G_g + G_g S_g with G_g = g Z G0, S_g = Z^2 G0, i.e.
  *     W = g Z_j Z_j' (Z_j + Z_j') chi_X(xi_j, xi_j')   (2 g chi_X without Z, Step 1). */
-typedef struct { int gflow; double T, g; } wkind;
+/* K: interaction flow with the Katanin correction (App. A, Step 3): the single-scale line
+ * S_g = Z^2 G0 becomes dG_g/dg = K Z^2 G0, so the line pair (j, j') carries
+ * g Z_j Z_j' (K_j Z_j + K_j' Z_j') chi (Eq. vertex_flow_feedback_Z_with_Katanin); NULL: K = 1. */
+typedef struct { int gflow; double T, g; const double *K; } wkind;
 
 static void fill_weights(const geom *g, wkind wk, const double *Z, int pp, int q, double *w)
 {
@@ -404,7 +409,8 @@ static void fill_weights(const geom *g, wkind wk, const double *Z, int pp, int q
         if (wk.gflow) {
             double chi = pp ? orc_chi_pp(g->xi[j], g->xi[jp], wk.T)
                             : orc_chi_ph(g->xi[j], g->xi[jp], wk.T);
-            w[j] = wk.g * za * zb * (za + zb) * chi;
+            double ka = wk.K ? wk.K[g->patch[j]] : 1.0, kb = wk.K ? wk.K[g->patch[jp]] : 1.0;
+            w[j] = wk.g * za * zb * (ka * za + kb * zb) * chi;
         } else {
             double chid = pp ? orc_chidot_pp(g->xi[j], g->xi[jp], wk.T)
                              : orc_chidot_ph(g->xi[j], g->xi[jp], wk.T);
@@ -519,7 +525,20 @@ int orc_rhs_g(const orc_model *m, double T, double gval, const double *Z, const 
     geom g;
     if (!(T > 0.0) || geom_build(m, &g)) return -1;
     set_threads(nthreads);
-    wkind wk = {1, T, gval};
+    wkind wk = {1, T, gval, NULL};
+    rhs_geom(&g, m->channels, wk, Z, V, dV);
+    geom_free(&g);
+    return 0;
+}
+
+/* The same with the Katanin factors K[N] on the single-scale line (K NULL: K = 1). */
+int orc_rhs_gk(const orc_model *m, double T, double gval, const double *Z, const double *K,
+               const double *V, double *dV, int nthreads)
+{
+    geom g;
+    if (!(T > 0.0) || geom_build(m, &g)) return -1;
+    set_threads(nthreads);
+    wkind wk = {1, T, gval, K};
     rhs_geom(&g, m->channels, wk, Z, V, dV);
     geom_free(&g);
     return 0;
@@ -615,7 +634,8 @@ static void rhs_binned_geom(const geom *gp, unsigned ch, wkind wk, const double 
                 for (int x = 0; x < N; ++x)
                     for (int y = 0; y < N; ++y) {
                         double zx = Z ? Z[x] : 1.0, zy = Z ? Z[y] : 1.0;
-                        double zz = wk.gflow ? wk.g * zx * zy * (zx + zy) : zx * zy;
+                        double kx = wk.K ? wk.K[x] : 1.0, ky = wk.K ? wk.K[y] : 1.0;
+                        double zz = wk.gflow ? wk.g * zx * zy * (kx * zx + ky * zy) : zx * zy;
                         size_t xy = (size_t)x * N + y;
                         if (ch & 1u) s -= zz * Bp[xy] * V[VIX(N, a, b, x)] * V[VIX(N, x, y, c)];
                         if (ch & 2u) s += zz * Bc[xy] * V[VIX(N, a, x, y)] * V[VIX(N, y, b, c)];
@@ -758,21 +778,63 @@ int orc_sigma2(const orc_model *m, double T, double U, const double *V, int n_w,
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Katanin factor and A_g of the interaction flow (App. A, Steps 2 and 3) from Z tabulated */
+/* on n >= 3 nodes g_0 < ... < g_{n-1} (Z_g from the self-energy at scale g, so that      */
+/* s_g = 1 - 1/Z_g is the slope of Re(g Sigma_g) at the Fermi level, Eq. definition_Z):   */
+/*   K_g = 1 + g^2 d_w Re(d Sigma_g/dg) = 1 - s_g + g ds_g/dg   (Eq. K_definition, with     */
+/*         d_w Re Sigma_g = s_g / g),                                                      */
+/*   A_g = -(2/g)(1 - Z_g K_g)                                  (Eq. A_g_simple),          */
+/* which equals 2 (dZ_g/dg)/Z_g = 2 s_g'/(1 - s_g), the form used at g = 0.  ds/dg is the  */
+/* derivative of the parabola through three neighbouring nodes (one-sided at the ends).    */
+/* z_tab, k_tab, a_tab: [n][N]; a_tab may be NULL.                                          */
+/* ------------------------------------------------------------------------------------ */
+int orc_katanin(int n, const double *g, int N, const double *z_tab, double *k_tab,
+                double *a_tab)
+{
+    if (n < 3 || N < 1 || !g || !z_tab || !k_tab) return -1;
+    for (int i = 1; i < n; ++i) if (!(g[i] > g[i - 1])) return -1;
+    for (int i = 0; i < n; ++i) {
+        /* three nodes i0, i0+1, i0+2 around i, and the derivative weights at g_i */
+        int i0 = i == 0 ? 0 : (i == n - 1 ? n - 3 : i - 1);
+        double x0 = g[i0], x1 = g[i0 + 1], x2 = g[i0 + 2], x = g[i];
+        /* d/dx of the Lagrange basis polynomials at x */
+        double w0 = ((x - x1) + (x - x2)) / ((x0 - x1) * (x0 - x2));
+        double w1 = ((x - x0) + (x - x2)) / ((x1 - x0) * (x1 - x2));
+        double w2 = ((x - x0) + (x - x1)) / ((x2 - x0) * (x2 - x1));
+        for (int a = 0; a < N; ++a) {
+            double s0 = 1.0 - 1.0 / z_tab[(size_t)i0 * N + a];
+            double s1 = 1.0 - 1.0 / z_tab[(size_t)(i0 + 1) * N + a];
+            double s2 = 1.0 - 1.0 / z_tab[(size_t)(i0 + 2) * N + a];
+            double z = z_tab[(size_t)i * N + a], s = 1.0 - 1.0 / z;
+            double ds = w0 * s0 + w1 * s1 + w2 * s2;
+            double K = 1.0 - s + x * ds;
+            k_tab[(size_t)i * N + a] = K;
+            if (a_tab)
+                a_tab[(size_t)i * N + a] = x > 0.0 ? -(2.0 / x) * (1.0 - z * K)
+                                                   : 2.0 * ds / (1.0 - s);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Quasi-particle weights along the flow: a table Z_a(s_i) in the flow parameter (ln T, or  */
 /* g for the interaction flow), linear in s between nodes, clamped outside.               */
 /* ------------------------------------------------------------------------------------ */
-static void z_at(const orc_flowcfg *f, int N, double s, double *Z)
+static void table_at(const orc_flowcfg *f, const double *tab, int N, double s, double *Z)
 {
-    if (f->n_z <= 0) { for (int a = 0; a < N; ++a) Z[a] = 1.0; return; }
+    if (f->n_z <= 0 || !tab) { for (int a = 0; a < N; ++a) Z[a] = 1.0; return; }
     int n = f->n_z;
-    if (n == 1 || s <= f->z_lnT[0]) { memcpy(Z, f->z_tab, sizeof(double) * N); return; }
-    if (s >= f->z_lnT[n - 1]) { memcpy(Z, f->z_tab + (size_t)(n - 1) * N, sizeof(double) * N); return; }
+    if (n == 1 || s <= f->z_lnT[0]) { memcpy(Z, tab, sizeof(double) * N); return; }
+    if (s >= f->z_lnT[n - 1]) { memcpy(Z, tab + (size_t)(n - 1) * N, sizeof(double) * N); return; }
     int i = 0;
     while (i + 1 < n - 1 && f->z_lnT[i + 1] <= s) ++i;
     double w = (s - f->z_lnT[i]) / (f->z_lnT[i + 1] - f->z_lnT[i]);
     for (int a = 0; a < N; ++a)
-        Z[a] = (1.0 - w) * f->z_tab[(size_t)i * N + a] + w * f->z_tab[(size_t)(i + 1) * N + a];
+        Z[a] = (1.0 - w) * tab[(size_t)i * N + a] + w * tab[(size_t)(i + 1) * N + a];
 }
+
+static void z_at(const orc_flowcfg *f, int N, double s, double *Z) { table_at(f, f->z_tab, N, s, Z); }
 
 /* ------------------------------------------------------------------------------------ */
 /* Integrators in s = ln T (temperature flow) or s = g (interaction flow).              */
@@ -783,12 +845,15 @@ typedef struct {
     const orc_flowcfg *f;
     double *Z;
     long n_rhs;
+    double *K;           /* Katanin factors at the current s (k_tab set) */
 } flowctx;
 
 static void eval_f(flowctx *cx, double s, const double *V, double *k)
 {
     z_at(cx->f, cx->g->N, s, cx->Z);
-    wkind wk = {cx->f->gflow != 0, cx->f->gflow ? cx->f->T0 : exp(s), cx->f->gflow ? s : 0.0};
+    if (cx->f->k_tab) table_at(cx->f, cx->f->k_tab, cx->g->N, s, cx->K);
+    wkind wk = {cx->f->gflow != 0, cx->f->gflow ? cx->f->T0 : exp(s), cx->f->gflow ? s : 0.0,
+                cx->f->k_tab ? cx->K : NULL};
     if (cx->f->rhs_binned)
         rhs_binned_geom(cx->g, cx->m->channels, wk, cx->f->n_z > 0 ? cx->Z : NULL, V, k);
     else
@@ -923,6 +988,9 @@ static int stop_test(const orc_flowcfg *f, double vth, double s_pp, double m_pp,
     return ORC_RUNNING;
 }
 
+/* A Katanin table needs the interaction flow and a Z table's nodes. */
+static int katanin_ok(const orc_flowcfg *f) { return !f->k_tab || (f->gflow && f->n_z > 0); }
+
 /*
  * Full flow from V = U: temperature flow from T0 down to T_end, or interaction flow at
  * T = T0 from g = 0 up to g_end.  trace (optional) receives (s, max|V|) after every
@@ -936,7 +1004,7 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
     if (f->gflow ? !(f->T0 > 0.0 && f->g_end > 0.0)
                  : (!(f->T0 > f->T_end) || !(f->T_end > 0.0)))
         return -1;
-    if (geom_build(m, &g)) return -1;
+    if (!katanin_ok(f) || geom_build(m, &g)) return -1;
     set_threads(nthreads);
     size_t n = (size_t)g.N * g.N * g.N;
     double *V = (double *)malloc(sizeof(double) * n);
@@ -946,7 +1014,8 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
     double *k[7];
     for (int i = 0; i < 7; ++i) k[i] = kb + (size_t)i * n;
     double *Z = (double *)malloc(sizeof(double) * g.N);
-    flowctx cx = {&g, m, f, Z, 0};
+    double *Kz = (double *)malloc(sizeof(double) * g.N);
+    flowctx cx = {&g, m, f, Z, 0, Kz};
     for (size_t i = 0; i < n; ++i) V[i] = U;
 
     double s0 = f->gflow ? 0.0 : log(f->T0), s_end = f->gflow ? f->g_end : log(f->T_end);
@@ -1029,7 +1098,7 @@ int orc_flow(const orc_model *m, const orc_flowcfg *f, double U, double *V_out,
     }
     if (V_out) memcpy(V_out, V, sizeof(double) * n);
     if (n_trace) *n_trace = ntr;
-    free(V); free(Vn); free(tmp); free(kb); free(Z);
+    free(V); free(Vn); free(tmp); free(kb); free(Z); free(Kz);
     geom_free(&g);
     return 0;
 }
@@ -1050,7 +1119,7 @@ int orc_flow_sync(const orc_model *m, const orc_flowcfg *f, int nf, const double
     if (nf < 1 || f->integrator != 1) return -1;
     if (f->gflow ? !(f->T0 > 0.0 && f->g_end > 0.0) : (!(f->T0 > f->T_end) || !(f->T_end > 0.0)))
         return -1;
-    if (geom_build(m, &g)) return -1;
+    if (!katanin_ok(f) || geom_build(m, &g)) return -1;
     set_threads(nthreads);
     size_t n = (size_t)g.N * g.N * g.N;
     double *V = (double *)malloc(sizeof(double) * n * nf);
@@ -1069,7 +1138,8 @@ int orc_flow_sync(const orc_model *m, const orc_flowcfg *f, int nf, const double
     int *nrej = (int *)calloc(nf, sizeof(int));
     long *nrhs = (long *)calloc(nf, sizeof(long));
     orc_flowcfg fi = *f;
-    flowctx cx = {&g, m, &fi, Z, 0};
+    double *Kz = (double *)malloc(sizeof(double) * g.N);
+    flowctx cx = {&g, m, &fi, Z, 0, Kz};
     double s0 = f->gflow ? 0.0 : log(f->T0), s_end = f->gflow ? f->g_end : log(f->T_end);
     double s = s0, dir = s_end > s0 ? 1.0 : -1.0;
     double h = f->h0 != 0.0 ? f->h0 : (s_end - s0) / 200.0;
@@ -1152,7 +1222,7 @@ int orc_flow_sync(const orc_model *m, const orc_flowcfg *f, int nf, const double
         }
         if (V_out) memcpy(V_out + (size_t)i * n, V + (size_t)i * n, sizeof(double) * n);
     }
-    free(V); free(Vn); free(tmp); free(kb); free(Z); free(err); free(mV); free(lnTc); free(sl);
+    free(V); free(Vn); free(tmp); free(kb); free(Z); free(Kz); free(err); free(mV); free(lnTc); free(sl);
     free(spp); free(mpp); free(status); free(nacc); free(nrej); free(nrhs);
     geom_free(&g);
     return 0;
@@ -1168,7 +1238,7 @@ int orc_step(const orc_model *m, const orc_flowcfg *f, double *lnT, double *h, d
              int *accepted, double *err_out, int nthreads)
 {
     geom g;
-    if (geom_build(m, &g)) return -1;
+    if (!katanin_ok(f) || geom_build(m, &g)) return -1;
     set_threads(nthreads);
     size_t n = (size_t)g.N * g.N * g.N;
     double *Vn = (double *)malloc(sizeof(double) * n);
@@ -1177,7 +1247,8 @@ int orc_step(const orc_model *m, const orc_flowcfg *f, double *lnT, double *h, d
     double *k[7];
     for (int i = 0; i < 7; ++i) k[i] = kb + (size_t)i * n;
     double *Z = (double *)malloc(sizeof(double) * g.N);
-    flowctx cx = {&g, m, f, Z, 0};
+    double *Kz = (double *)malloc(sizeof(double) * g.N);
+    flowctx cx = {&g, m, f, Z, 0, Kz};
     double s = *lnT, hh = *h;
     eval_f(&cx, s, V, k[0]);
     if (f->integrator == 0) {
@@ -1205,7 +1276,7 @@ int orc_step(const orc_model *m, const orc_flowcfg *f, double *lnT, double *h, d
             *h = isfinite(err) ? hh * step_factor(err) : 0.5 * hh;
         }
     }
-    free(Vn); free(tmp); free(kb); free(Z);
+    free(Vn); free(tmp); free(kb); free(Z); free(Kz);
     geom_free(&g);
     return 0;
 }

@@ -47,7 +47,7 @@ class FlowCfg(ctypes.Structure):
                 ("h0", c_double), ("h_min", c_double), ("v_max", c_double),
                 ("n_z", c_int), ("z_lnT", POINTER(c_double)), ("z_tab", POINTER(c_double)),
                 ("gflow", c_int), ("g_end", c_double), ("v_rel", c_double),
-                ("rhs_binned", c_int), ("progress", c_int)]
+                ("rhs_binned", c_int), ("progress", c_int), ("k_tab", POINTER(c_double))]
 
 
 class Result(ctypes.Structure):
@@ -89,6 +89,8 @@ def lib():
             "orc_transfer_counts": (i, [pm, pi, pi]),
             "orc_rhs": (i, [pm, d, pd, pd, pd, i]),
             "orc_rhs_g": (i, [pm, d, d, pd, pd, pd, i]),
+            "orc_rhs_gk": (i, [pm, d, d, pd, pd, pd, pd, i]),
+            "orc_katanin": (i, [i, pd, i, pd, pd, pd]),
             "orc_rhs_points_g": (i, [pm, d, d, pd, pd, i, pi, pd, i]),
             "orc_rhs_binned": (i, [pm, d, pd, pd, pd, i]),
             "orc_rhs_points": (i, [pm, d, pd, pd, i, pi, pd, i]),
@@ -202,16 +204,36 @@ def rhs(m: Model, T, V, Z=None, nthreads=0, binned=False):
     return out.reshape(N, N, N)
 
 
-def rhs_g(m: Model, T, g, V, Z=None, nthreads=0):
-    """Interaction flow: dV/dg at temperature T and scale g."""
+def rhs_g(m: Model, T, g, V, Z=None, K=None, nthreads=0):
+    """Interaction flow: dV/dg at temperature T and scale g (K: Katanin factors [N] on the
+    single-scale line, App. A Step 3)."""
     N = m.N
     V = np.ascontiguousarray(V, np.float64).reshape(N * N * N)
     Z = _zarg(Z, N)
     out = np.zeros_like(V)
-    if lib().orc_rhs_g(ctypes.byref(m), float(T), float(g), _pd(Z), _pd(V), _pd(out),
-                       int(nthreads)):
+    if K is None:
+        rc = lib().orc_rhs_g(ctypes.byref(m), float(T), float(g), _pd(Z), _pd(V), _pd(out),
+                             int(nthreads))
+    else:
+        K = _zarg(K, N)
+        rc = lib().orc_rhs_gk(ctypes.byref(m), float(T), float(g), _pd(Z), _pd(K), _pd(V),
+                              _pd(out), int(nthreads))
+    if rc:
         raise ValueError("oracle rhs_g rejected its arguments")
     return out.reshape(N, N, N)
+
+
+def katanin(g, z_tab):
+    """Katanin factors K and A_g on the nodes g of a Z table [n][N] (App. A, Eqs. K_definition
+    and A_g_simple); returns (K [n][N], A [n][N])."""
+    g = np.ascontiguousarray(g, np.float64)
+    z = np.ascontiguousarray(z_tab, np.float64)
+    n, N = z.shape
+    K = np.zeros_like(z)
+    A = np.zeros_like(z)
+    if lib().orc_katanin(int(n), _pd(g), int(N), _pd(z), _pd(K), _pd(A)):
+        raise ValueError("oracle katanin rejected its arguments")
+    return K, A
 
 
 def rhs_points_g(m: Model, T, g, V, abc, Z=None, nthreads=0):
@@ -243,18 +265,18 @@ def rhs_points(m: Model, T, V, abc, Z=None, nthreads=0):
 # --------------------------------------------------------------------------------------
 def flowcfg(T0=1.0, T_end=0.01, integrator=0, n_steps=200, rtol=1e-6, atol=None, U=1.0,
             h0=0.0, h_min=0.0, v_max=20.0, z_lnT=None, z_tab=None, gflow=False, g_end=1.0,
-            v_rel=100.0, binned=False, progress=False):
+            v_rel=100.0, binned=False, progress=False, k_tab=None):
     """Build a FlowCfg; keeps references to the Z arrays on the returned object.  gflow:
     interaction flow at the fixed temperature T0 from g = 0 to g_end (Z nodes in g), stopped
     when max|V| exceeds v_rel |U|.  binned: every right-hand side in the binned form (the
     same sums in another order).  progress: one line per Dormand-Prince step attempt on
-    stderr."""
+    stderr.  k_tab: interaction flow only, Katanin factors [n_z][N] on the Z table's nodes."""
     if atol is None:
         atol = 1e-9 * max(1.0, abs(U))
     cfg = FlowCfg(float(T0), float(T_end), int(integrator), int(n_steps), float(rtol),
                   float(atol), float(h0), float(h_min), float(v_max), 0, None, None,
                   int(bool(gflow)), float(g_end), float(v_rel), int(bool(binned)),
-                  int(bool(progress)))
+                  int(bool(progress)), None)
     if z_tab is not None:
         z_lnT = np.ascontiguousarray(z_lnT, np.float64)
         z_tab = np.ascontiguousarray(z_tab, np.float64)
@@ -263,6 +285,10 @@ def flowcfg(T0=1.0, T_end=0.01, integrator=0, n_steps=200, rtol=1e-6, atol=None,
         cfg.z_lnT = _pd(z_lnT)
         cfg.z_tab = _pd(z_tab)
         cfg._keep = (z_lnT, z_tab)
+    if k_tab is not None:
+        k_tab = np.ascontiguousarray(k_tab, np.float64)
+        cfg.k_tab = _pd(k_tab)
+        cfg._keep_k = k_tab
     return cfg
 
 

@@ -123,6 +123,13 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (c.precision < FM_FP64 || c.precision > FM_FP32_BF16X3) { why = "bad precision"; return FM_EINVAL; }
     if (c.max_batch < 1) { why = "max_batch must be >= 1"; return FM_EINVAL; }
     if (c.n_zT < 0 || (c.n_zT > 0 && (!c.z_lnT || !c.z_table))) { why = "bad Z table"; return FM_EINVAL; }
+    if (c.k_table && (c.flow != FM_FLOW_INTERACTION || c.n_zT < 1)) {
+        why = "a Katanin table needs the interaction flow and a Z table's nodes";
+        return FM_EINVAL;
+    }
+    if (c.k_table)
+        for (size_t i = 0; i < static_cast<size_t>(c.n_zT) * c.N; ++i)
+            if (!std::isfinite(c.k_table[i])) { why = "Katanin factors must be finite"; return FM_EINVAL; }
     for (int i = 1; i < c.n_zT; ++i)
         if (!(c.z_lnT[i] > c.z_lnT[i - 1])) { why = "Z nodes must ascend"; return FM_EINVAL; }
     // the relative tolerance must not ask for more than the right-hand side resolves:
@@ -157,6 +164,7 @@ struct fm_flow {
     bool dbl = false, direct = false;
     size_t N3 = 0;
     std::vector<double> zlnT, ztab;    // configured table (host copy)
+    std::vector<double> ktab;          // configured Katanin factors on the same nodes, or empty
     std::vector<FlowState> hfs;
     // phase-2a kernel variant and row tiles per wavefront (cfg.y_kernel, cfg.tile_rows, or
     // tuned for tuned_nf flows)
@@ -229,8 +237,9 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.fs = L.take<FlowState>(B);
     b.z_lnT = L.take<double>(static_cast<size_t>(B) * nz);
     b.z_tab = L.take<double>(static_cast<size_t>(B) * nz * N);
+    b.k_tab = c.k_table ? L.take<double>(static_cast<size_t>(B) * nz * N) : nullptr;
     b.T_stage = L.take<double>(B);
-    b.Z_stage = L.take<double>(static_cast<size_t>(B) * N);
+    b.Z_stage = L.take<double>(static_cast<size_t>(B) * 2 * N);
     b.zw_stage = L.take<double>(2 * static_cast<size_t>(B));
     b.U = L.take<double>(B);
     b.kpt = L.take<double>(2 * static_cast<size_t>(N));
@@ -482,23 +491,27 @@ int upload_z(fm_flow* h, int nf, const double* zl, const double* zt) {
     const int nz = h->cfg.n_zT;
     if (nz == 0) return FM_OK;
     const int N = h->cfg.N;
+    const bool kat = !h->ktab.empty();   // the configured K table, for every flow
     std::vector<double> l(static_cast<size_t>(nf) * nz), t(static_cast<size_t>(nf) * nz * N);
+    std::vector<double> k(kat ? t.size() : 0);
     for (int f = 0; f < nf; ++f) {
         const double* sl = zl ? zl + static_cast<size_t>(f) * nz : h->zlnT.data();
         const double* st = zt ? zt + static_cast<size_t>(f) * nz * N : h->ztab.data();
-        if (h->g.gflow) {      // nodes in s = -g: negated, in reversed (ascending) order
-            for (int i = 0; i < nz; ++i) {
-                l[static_cast<size_t>(f) * nz + i] = -sl[nz - 1 - i];
-                std::memcpy(&t[(static_cast<size_t>(f) * nz + i) * N],
-                            st + static_cast<size_t>(nz - 1 - i) * N, sizeof(double) * N);
-            }
-            continue;
+        for (int i = 0; i < nz; ++i) {
+            // interaction flow: nodes in s = -g, negated, in reversed (ascending) order
+            const int src = h->g.gflow ? nz - 1 - i : i;
+            l[static_cast<size_t>(f) * nz + i] = h->g.gflow ? -sl[src] : sl[src];
+            std::memcpy(&t[(static_cast<size_t>(f) * nz + i) * N], st + static_cast<size_t>(src) * N,
+                        sizeof(double) * N);
+            if (kat)
+                std::memcpy(&k[(static_cast<size_t>(f) * nz + i) * N],
+                            h->ktab.data() + static_cast<size_t>(src) * N, sizeof(double) * N);
         }
-        std::memcpy(&l[static_cast<size_t>(f) * nz], sl, sizeof(double) * nz);
-        std::memcpy(&t[static_cast<size_t>(f) * nz * N], st, sizeof(double) * nz * N);
     }
     HIPCHK(hipMemcpyAsync(h->b.z_lnT, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->b.z_tab, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (kat)
+        HIPCHK(hipMemcpyAsync(h->b.k_tab, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return FM_OK;
 }
@@ -660,6 +673,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (c.n_zT > 0) {
         h->zlnT.assign(c.z_lnT, c.z_lnT + c.n_zT);
         h->ztab.assign(c.z_table, c.z_table + static_cast<size_t>(c.n_zT) * N);
+        if (c.k_table) h->ktab.assign(c.k_table, c.k_table + static_cast<size_t>(c.n_zT) * N);
         for (double z : h->ztab)
             if (!(z > 0.0 && std::isfinite(z))) {
                 delete h;
@@ -671,6 +685,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     h->z.n = c.n_zT;
     h->z.lnT = h->b.z_lnT;
     h->z.tab = h->b.z_tab;
+    h->z.ktab = c.k_table ? h->b.k_tab : nullptr;
     h->hfs.resize(c.max_batch);
     *out = h;
     return FM_OK;
@@ -871,6 +886,8 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
     if (!U || !T0 || !res) return fail(FM_EINVAL, "null argument");
     if ((z_lnT == nullptr) != (z_tables == nullptr)) return fail(FM_EINVAL, "give both Z arrays or neither");
     if (z_tables && h->cfg.n_zT == 0) return fail(FM_EINVAL, "per-flow Z tables need cfg.n_zT > 0");
+    if (z_tables && !h->ktab.empty())
+        return fail(FM_EINVAL, "per-flow Z tables cannot be combined with a configured Katanin table");
     if (z_tables) {   // each flow's table as fm_flow_init checks the configured one
         const int nz = h->cfg.n_zT, N = h->cfg.N;
         for (int f = 0; f < n; ++f) {
@@ -1078,6 +1095,41 @@ int fm_flow_z(fm_flow* h, double T, double U, const double* V_dev, double* Z, do
 double fm_sigma_wmax(const fm_config* cfg) {
     if (!cfg) return 0.0;
     return 3.0001 * (4.0 * std::fabs(cfg->t) + 4.0 * std::fabs(cfg->tp) + std::fabs(cfg->mu));
+}
+
+int fm_katanin_table(int n, const double* g, int N, const double* z_tab, double* k_tab,
+                     double* a_tab, double* a_minmax) {
+    if (n < 3 || N < 1 || !g || !z_tab || !k_tab) return fail(FM_EINVAL, "need n >= 3 nodes, N >= 1 and the tables");
+    for (int i = 1; i < n; ++i)
+        if (!(g[i] > g[i - 1])) return fail(FM_EINVAL, "Katanin table: nodes must ascend");
+    for (size_t i = 0; i < static_cast<size_t>(n) * N; ++i)
+        if (!(z_tab[i] > 0.0 && std::isfinite(z_tab[i]))) return fail(FM_EINVAL, "Katanin table: Z must be positive and finite");
+    for (int i = 0; i < n; ++i) {
+        // the three nodes whose parabola gives ds/dg at g_i
+        const int c = std::min(std::max(i, 1), n - 2);
+        const double xm = g[c - 1], x0 = g[c], xp = g[c + 1], x = g[i];
+        // derivative of the Lagrange basis polynomials of (xm, x0, xp) at x
+        const double dm = (2.0 * x - x0 - xp) / ((xm - x0) * (xm - xp));
+        const double d0 = (2.0 * x - xm - xp) / ((x0 - xm) * (x0 - xp));
+        const double dp = (2.0 * x - xm - x0) / ((xp - xm) * (xp - x0));
+        double amin = std::numeric_limits<double>::infinity(), amax = -amin;
+        for (int a = 0; a < N; ++a) {
+            auto s_at = [&](int j) { return 1.0 - 1.0 / z_tab[static_cast<size_t>(j) * N + a]; };
+            const double ds = dm * s_at(c - 1) + d0 * s_at(c) + dp * s_at(c + 1);
+            const double z = z_tab[static_cast<size_t>(i) * N + a], s = s_at(i);
+            const double K = 1.0 - s + x * ds;
+            const double A = x > 0.0 ? -2.0 / x * (1.0 - z * K) : 2.0 * ds / (1.0 - s);
+            k_tab[static_cast<size_t>(i) * N + a] = K;
+            if (a_tab) a_tab[static_cast<size_t>(i) * N + a] = A;
+            amin = std::min(amin, A);
+            amax = std::max(amax, A);
+        }
+        if (a_minmax) {
+            a_minmax[2 * i] = amin;
+            a_minmax[2 * i + 1] = amax;
+        }
+    }
+    return FM_OK;
 }
 
 int fm_flow_tstar(fm_flow* h, int n, const double* U, double T_lo, double T_hi, double rtol,

@@ -130,11 +130,12 @@ struct DevGeom {
     const int* map_d;      // [NN]
 };
 
-// Per-flow Z tables.
+// Per-flow Z tables, and the Katanin factors on the same nodes (interaction flow).
 struct DevZ {
     int n;                 // nodes (0: Z = 1)
     const double* lnT;     // [B][n]
     const double* tab;     // [B][n][N]
+    const double* ktab;    // [B][n][N] K, or nullptr (K = 1)
 };
 
 // Integrator constants for one stage.
@@ -161,9 +162,10 @@ struct Buffers {
     // per flow
     FlowState* fs;
     double* z_lnT; double* z_tab;      // [B][nz], [B][nz][N]
+    double* k_tab;                     // [B][nz][N] Katanin factors, or nullptr
     double* T_stage;                   // [B]
-    double* Z_stage;                   // [B][N]
-    double* zw_stage;                  // [B][2]: line-pair factor Z_a Z_b (al + be (Z_a + Z_b))
+    double* Z_stage;                   // [B][2][N]: Z, then W = K Z (W = Z without K)
+    double* zw_stage;                  // [B][2]: line-pair factor Z_a Z_b (al + be (W_a + W_b))
     int* rep_pp; int* rep_ph; int* qrep_pp; int* qg_pp; int* qrep_ph; int* qg_ph; int* pinv;
     int* perm;
     int* orb_rows; int* orb_q; int* orb_mask; int* porder;

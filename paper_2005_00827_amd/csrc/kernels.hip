@@ -23,6 +23,11 @@
 // Phase 2b (k_contract): the remaining contraction over one patch index per channel,
 //   written straight into the stage's k slot, one part per channel.
 // Integrator (k_rk4_update, k_dopri_err, k_finish, k_commit): double precision.
+// Z weights: a line pair (a', b') carries Z_a' Z_b' (al + be (W_a' + W_b')) per flow, with
+// (al, be) = (1, 0) for the temperature flow and (0, g) for the interaction flow, where W = Z,
+// or W = K Z with the Katanin factors K on the single-scale line (App. A, Step 3: dG/dg =
+// K Z^2 G0 replaces S = Z^2 G0, Eq. vertex_flow_feedback_Z_with_Katanin).  The stage writes Z
+// and W per flow, [flow][2][N].
 // Direct path (k_wtable, k_direct): the same sums over every loop point, no bins.
 #include <hip/hip_runtime.h>
 
@@ -106,6 +111,13 @@ __device__ inline double z_interp(const DevZ& z, int f, int N, int a, double lnT
     while (i + 1 < z.n - 1 && x[i + 1] <= lnT) ++i;
     const double w = (lnT - x[i]) / (x[i + 1] - x[i]);
     return (1.0 - w) * t[static_cast<size_t>(i) * N + a] + w * t[static_cast<size_t>(i + 1) * N + a];
+}
+
+// Katanin factor K of patch a (the K table shares the Z table's nodes); 1 without one.
+__device__ inline double k_interp(const DevZ& z, int f, int N, int a, double lnT) {
+    if (!z.ktab) return 1.0;
+    const DevZ zk{z.n, z.lnT, z.ktab, nullptr};
+    return z_interp(zk, f, N, a, lnT);
 }
 
 __device__ inline bool running(const FlowState* fs, int f) { return fs[f].status == FM_FLOW_RUNNING; }
@@ -331,8 +343,11 @@ __device__ inline void stage_part(const DevGeom& g, const DevZ& z, const FlowSta
             zw[2 * f] = st.gflow ? 0.0 : 1.0;
             zw[2 * f + 1] = st.gflow ? lnTs : 0.0;
         }
-        for (int a = threadIdx.x; a < N; a += blockDim.x)
-            Z_stage[static_cast<size_t>(f) * N + a] = z_interp(z, f, N, a, lnTs);
+        for (int a = threadIdx.x; a < N; a += blockDim.x) {
+            const double za = z_interp(z, f, N, a, lnTs);
+            Z_stage[static_cast<size_t>(f) * 2 * N + a] = za;
+            Z_stage[static_cast<size_t>(f) * 2 * N + N + a] = z.ktab ? za * k_interp(z, f, N, a, lnTs) : za;
+        }
     }
     const double* Vf = Vbase + f * N3;
     switch (sc.ns) {                                   // uniform: earlier stages of this stage
@@ -962,8 +977,9 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     const int* qrep = ppk ? g.qrep_pp : g.qrep_ph;
     const int* qg = ppk ? g.qg_pp : g.qg_ph;
     const R* Vg = args.Vs[kind] + f * N3 + static_cast<size_t>(grp) * NN;
-    const double* Zf = Z_stage + static_cast<size_t>(f) * N;
-    const R zg = static_cast<R>(Zf[grp]);
+    const double* Zf = Z_stage + static_cast<size_t>(f) * 2 * N;
+    const double* Wf = Zf + N;
+    const R zg = static_cast<R>(Zf[grp]), wg = static_cast<R>(Wf[grp]);
     const R al = static_cast<R>(zw[2 * f]), be = static_cast<R>(zw[2 * f + 1]);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     __shared__ int pis[8 * 256];
@@ -994,7 +1010,8 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     for (int k0 = 0; k0 < N; k0 += TK) {
         const int k = k0 + kk_t;
         const R zkk = k < N ? static_cast<R>(Zf[k]) : R(0);
-        const R zk = k < N ? zg * zkk * (al + be * (zg + zkk)) : R(0);
+        const R wkk = k < N ? static_cast<R>(Wf[k]) : R(0);
+        const R zk = k < N ? zg * zkk * (al + be * (wg + wkk)) : R(0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rr = threadIdx.x / TK + 16 * i;
@@ -1040,7 +1057,7 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
 // Phase 2a on matrix cores (single-precision storage, N <= 128).  Same products as k_y.
 // One wave computes, for one group g, a column chunk of NT 16-wide tiles and a run of
 // 16-row tiles of transfers of one operation class:
-//   B'[k'][n] = Z_g Z_k (al + be (Z_g + Z_k)) Vsrc[g][k][n], k = perm_o k', is staged in
+//   B'[k'][n] = Z_g Z_k (al + be (W_g + W_k)) Vsrc[g][k][n], k = perm_o k', is staged in
 //     LDS once per block (for the direct channel two such operands, va and vc, share one A);
 //   A[q][k'] = Brep_r(pinv_o g, k') is read straight from a representative's bin row into
 //     the MFMA register layout.
@@ -1166,7 +1183,8 @@ __device__ inline void mfma_tile(const float (&a)[KE], const void* Bs0v, const v
 }
 
 // A operand of one row tile: lane row q = 16 tile + lane % 16 (rep r, operation o), k-values
-// of the lane: A[q][k] = Z_g Z_k Brep_r(pinv_o g, pinv_o k), zero for k >= N.
+// of the lane: A[q][k] = Z_g Z_k (al + be (W_g + W_k)) Brep_r(pinv_o g, pinv_o k), zero for
+// k >= N; zs holds Z in [0, N) and W = K Z in [N, 2N).
 template <int kM, int KE>
 __device__ inline void gather_rows(float (&a)[KE], const float* Bf, int NN, int N, int grp,
                                 int rep, int op, const int* pis, const float* zs, float zg,
@@ -1179,11 +1197,12 @@ __device__ inline void gather_rows(float (&a)[KE], const float* Bf, int NN, int 
     for (int e = 0; e < KE; ++e) col[e] = pi[min(mfma_k<kM>(e, lane), N - 1)];
 #pragma unroll
     for (int e = 0; e < KE; ++e) a[e] = row[col[e]];
+    const float wg = zs[N + grp];
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
         const int k = mfma_k<kM>(e, lane);
-        const float zk = zs[min(k, N - 1)];
-        a[e] = k < N ? a[e] * (zg * zk * (al + be * (zg + zk))) : 0.f;
+        const float zk = zs[min(k, N - 1)], wk = zs[N + min(k, N - 1)];
+        a[e] = k < N ? a[e] * (zg * zk * (al + be * (wg + wk))) : 0.f;
     }
 }
 
@@ -1257,7 +1276,7 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
     constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
     __shared__ int pis[8 * 128];                      // patch permutations (N <= 128)
-    __shared__ float zs[128];                         // Z of the stage
+    __shared__ float zs[256];                         // Z and W = K Z of the stage
     __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks
     const int id = blockIdx.x;
     const int rem = id % (8 * nchunk);
@@ -1293,7 +1312,9 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
     int pv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) pv[v] = g.pinv[min(static_cast<int>(threadIdx.x) + v * kThreads, 8 * N - 1)];
-    const float zv = static_cast<float>(Z_stage[static_cast<size_t>(f) * N + min(static_cast<int>(threadIdx.x), N - 1)]);
+    const double* Zf = Z_stage + static_cast<size_t>(f) * 2 * N;
+    const float zv = static_cast<float>(Zf[min(static_cast<int>(threadIdx.x), N - 1)]);
+    const float kzv = static_cast<float>(Zf[N + min(static_cast<int>(threadIdx.x), N - 1)]);
     const size_t N3 = static_cast<size_t>(NN) * N;
     const size_t slab = f * N3 + static_cast<size_t>(grp) * NN;
     const float* V0 = args.Vs[two ? 2 : ch] + slab;
@@ -1318,7 +1339,10 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_rows(DevGeom g, const FlowS
 #pragma unroll
     for (int v = 0; v < 4; ++v)          // the permutation table (8 N <= 1024 entries)
         if (static_cast<int>(threadIdx.x) + v * kThreads < 8 * N) pis[threadIdx.x + v * kThreads] = pv[v];
-    if (threadIdx.x < N) zs[threadIdx.x] = zv;
+    if (threadIdx.x < N) {
+        zs[threadIdx.x] = zv;
+        zs[N + threadIdx.x] = kzv;
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int e = threadIdx.x + j * kThreads;
@@ -1452,7 +1476,7 @@ struct YRuns {
 //   id = (w / 8) * 8 nchunk + chunk * 8 + w % 8.
 // Run x of channel kind c is run r of class o; the block stages its B chunk once, for that
 // operation:
-//   B'[k'][n] = Z_g Z_k (al + be (Z_g + Z_k)) Vsrc[g][k][n],  k = perm_o k',
+//   B'[k'][n] = Z_g Z_k (al + be (W_g + W_k)) Vsrc[g][k][n],  k = perm_o k',
 // so that sum_k' A[q][k'] B'[k'][n] is the product of the gathered, permuted and Z-weighted
 // bins with the slab.  The 4 waves take tpw consecutive row tiles each.
 template <int kM, int KE, int NT>
@@ -1465,7 +1489,7 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_cls(DevGeom g, const FlowSt
     constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
     __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks
     __shared__ int kperm[4 * KE];                     // perm_o k' (k' < N)
-    __shared__ float kfac[4 * KE];                    // Z_g Z_k (al + be (Z_g + Z_k)), k = perm_o k' 
+    __shared__ float kfac[4 * KE];                    // Z_g Z_k (al + be (W_g + W_k)), k = perm_o k' 
     const int id = blockIdx.x;
     const int rem = id % (8 * nchunk);
     const int work = (id / (8 * nchunk)) * 8 + rem % 8;
@@ -1503,13 +1527,13 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_cls(DevGeom g, const FlowSt
     const float* V0 = args.Vs[two ? 2 : ch] + slab;
     const float* V1 = args.Vs[3] + slab;
     if (threadIdx.x < KP) {                           // per-k' permutation and factor
-        const double* Zf = Z_stage + static_cast<size_t>(f) * N;
-        const float zg = static_cast<float>(Zf[grp]);
+        const double* Zf = Z_stage + static_cast<size_t>(f) * 2 * N;
+        const float zg = static_cast<float>(Zf[grp]), wg = static_cast<float>(Zf[N + grp]);
         const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
         const int kp = g.perm[o * N + min(static_cast<int>(threadIdx.x), N - 1)];
-        const float zk = static_cast<float>(Zf[kp]);
+        const float zk = static_cast<float>(Zf[kp]), wk = static_cast<float>(Zf[N + kp]);
         kperm[threadIdx.x] = kp;
-        kfac[threadIdx.x] = zg * zk * (al + be * (zg + zk));
+        kfac[threadIdx.x] = zg * zk * (al + be * (wg + wk));
     }
     __syncthreads();                                   // every thread of the block
     for (int e = threadIdx.x; e < KP * W; e += kThreads) {
@@ -1655,8 +1679,8 @@ constexpr int stage_group(int per) {
 // any of them is used, so a thread has a group in flight instead of one.
 template <int kM, int KE, int NT, bool kTwo>
 __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const float* V1,
-                                     const int* pm, const float* zs, float zg, float al,
-                                     float be, int N, int n0) {
+                                     const int* pm, const float* zs, float zg, float wg,
+                                     float al, float be, int N, int n0) {
     constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
     constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;
     constexpr int kPer = KP * W / kThreads;
@@ -1681,8 +1705,8 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
             const int e = threadIdx.x + (j0 + j) * kThreads;
             const int k = e / W, n = e - k * W;
             const bool ok = k < N && n0 + n < N;
-            const float zk = zs[kq[j]];
-            const float fac = ok ? zg * zk * (al + be * (zg + zk)) : 0.f;
+            const float zk = zs[kq[j]], wk = zs[N + kq[j]];
+            const float fac = ok ? zg * zk * (al + be * (wg + wk)) : 0.f;
             const float x0 = fac * v0[j];
             const float x1 = kTwo ? fac * v1[j] : 0.f;
             if constexpr (kM > 0) {
@@ -1708,7 +1732,7 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
 // of representative tiles (4 waves x TPW tiles of 16 representatives) and one column chunk;
 // it loads its A rows once, keeps them in registers, and for each operation o that yields
 // transfers of its tiles stages
-//   B'_o[k'][n] = Z_g Z_k (al + be (Z_g + Z_k)) Vsrc[g][k][n],  g = perm_o p,  k = perm_o k',
+//   B'_o[k'][n] = Z_g Z_k (al + be (W_g + W_k)) Vsrc[g][k][n],  g = perm_o p,  k = perm_o k',
 // and stores the tile product into the rows of the transfers o(r) at slab g.  Every (q, g)
 // is produced once (q by its own (o, r), g by p = pinv_o g), and every bin row is read by
 // one block per column chunk instead of once per transfer of its orbit.  A wave reads B'_o
@@ -1749,6 +1773,7 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
     for (int v = 0; v < kQ; ++v) qv[v] = qsrc[min(static_cast<int>(threadIdx.x) + v * kThreads, nq - 1)];
     const int mv = g.orb_mask[toff + tb + min(static_cast<int>(threadIdx.x), tn - tb - 1)];
     const float zv = static_cast<float>(Zf[min(static_cast<int>(threadIdx.x), N - 1)]);
+    const float kzv = static_cast<float>(Zf[N + min(static_cast<int>(threadIdx.x), N - 1)]);
     float a[TPW][KE];
 #pragma unroll
     for (int j = 0; j < TPW; ++j)
@@ -1760,7 +1785,10 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
     for (int v = 0; v < kQ; ++v)
         if (static_cast<int>(threadIdx.x) + v * kThreads < nq) qs[threadIdx.x + v * kThreads] = qv[v];
     if (static_cast<int>(threadIdx.x) < tn - tb) msk[threadIdx.x] = mv;
-    if (static_cast<int>(threadIdx.x) < N) zs[threadIdx.x] = zv;
+    if (static_cast<int>(threadIdx.x) < N) {
+        zs[threadIdx.x] = zv;
+        zs[N + threadIdx.x] = kzv;
+    }
     AFrag<kM, KE> A[TPW];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) A[j] = make_afrag<kM, KE>(a[j]);
@@ -1773,7 +1801,7 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
         const int grp = pms[o * N + p];
         stage_orbit_b<kM, KE, NT, kTwo>(Braw, Vs0 + static_cast<size_t>(grp) * NN,
                                         Vs1 + static_cast<size_t>(grp) * NN, pms + o * N,
-                                        zs, zs[grp], al, be, N, n0);
+                                        zs, zs[grp], zs[N + grp], al, be, N, n0);
         __syncthreads();                               // B'_o staged; every thread
 #pragma unroll
         for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
@@ -1845,7 +1873,7 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
     constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;   // one B chunk (kM planes)
     __shared__ __align__(16) unsigned char Braw[2 * kBytes];   // B chunks (two for direct)
     __shared__ int pms[8 * 128];                      // perm_o (N <= 128)
-    __shared__ float zs[128];                         // Z of the stage
+    __shared__ float zs[256];                         // Z and W = K Z of the stage
     __shared__ int qs[4 * TPW * 8 * 16];              // transfers of the block's (tile, o, row)
     __shared__ int msk[4 * TPW];                      // operation sets of the block's tiles
     const int gsize = 8 * bx * nchunk;
@@ -1882,14 +1910,14 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
                                              reinterpret_cast<YT*>(args.Y[2]) + yoff,
                                              reinterpret_cast<YT*>(args.Y[3]) + yoff, p, tb, nt,
                                              toff, chunk * 16 * NT, al, be,
-                                             Z_stage + static_cast<size_t>(f) * N, Braw, pms, zs, qs,
+                                             Z_stage + static_cast<size_t>(f) * 2 * N, Braw, pms, zs, qs,
                                              msk);
     else
         y_orbit_block<kM, KE, NT, TPW, false>(g, Bf, args.Vs[ch] + f * N3, args.Vs[ch] + f * N3,
                                               reinterpret_cast<YT*>(args.Y[ch]) + yoff,
                                               reinterpret_cast<YT*>(args.Y[ch]) + yoff, p, tb, nt,
                                               toff, chunk * 16 * NT, al, be,
-                                              Z_stage + static_cast<size_t>(f) * N, Braw, pms, zs,
+                                              Z_stage + static_cast<size_t>(f) * 2 * N, Braw, pms, zs,
                                               qs, msk);
 }
 
@@ -2102,10 +2130,11 @@ __global__ void __launch_bounds__(kThreads) k_wtable(DevGeom g, const FlowState*
         if (pp) b = -b;
         w = -phi_dd<double>(a, phi_d(a), b, phi_d(b)) / (4.0 * T * g.np);
     }
-    const double* Z = Z_stage + static_cast<size_t>(f) * g.N;
+    const double* Z = Z_stage + static_cast<size_t>(f) * 2 * g.N;
     const double za = Z[g.patch[j]], zb = Z[g.patch[jp]];
+    const double wa = Z[g.N + g.patch[j]], wb = Z[g.N + g.patch[jp]];
     W[(static_cast<size_t>(f) * (g.nP + g.nD) + q) * g.np + j] =
-        za * zb * (zw[2 * f] + zw[2 * f + 1] * (za + zb)) * w;
+        za * zb * (zw[2 * f] + zw[2 * f + 1] * (wa + wb)) * w;
 }
 
 __global__ void __launch_bounds__(kThreads) k_direct(DevGeom g, const FlowState* fs,

@@ -32,7 +32,8 @@ INTEGRATORS = {"rk4": RK4_FIXED, "rk45": RK45_DOPRI}
 EXPORTS = ("fm_flow_workspace_bytes", "fm_flow_init", "fm_flow_rhs", "fm_flow_rhs_g",
            "fm_flow_step", "fm_flow_run_batch", "fm_flow_tstar", "fm_geometry_query",
            "fm_flow_set_timing", "fm_flow_timings", "fm_flow_kernel_time", "fm_flow_destroy",
-           "fm_last_error", "fm_flow_rhs_static", "fm_flow_z", "fm_sigma_wmax")
+           "fm_last_error", "fm_flow_rhs_static", "fm_flow_z", "fm_sigma_wmax",
+           "fm_katanin_table")
 SIGMA_NW = 2048
 FLOWS = {"temperature": 0, "interaction": 1}
 
@@ -47,7 +48,8 @@ class Config(ctypes.Structure):
                 ("n_zT", c_int), ("z_lnT", POINTER(c_double)), ("z_table", POINTER(c_double)),
                 ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int),
                 ("flow", c_int), ("g_end", c_double), ("v_rel", c_double), ("y_kernel", c_int),
-                ("sync_batch", c_int), ("n_shells", c_int), ("shell_edges", POINTER(c_double))]
+                ("sync_batch", c_int), ("n_shells", c_int), ("shell_edges", POINTER(c_double)),
+                ("k_table", POINTER(c_double))]
 
 
 class Result(ctypes.Structure):
@@ -95,6 +97,7 @@ def load():
         "fm_flow_rhs_static": (c_int, [pc, c_int, pd, c_void_p, c_void_p]),
         "fm_flow_z": (c_int, [c_void_p, c_double, c_double, c_void_p, pd, pd, pd]),
         "fm_sigma_wmax": (c_double, [pc]),
+        "fm_katanin_table": (c_int, [c_int, pd, c_int, pd, pd, pd, pd]),
         "fm_flow_destroy": (None, [c_void_p]),
         "fm_last_error": (c_char_p, []),
     }
@@ -122,7 +125,8 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
                 integrator="rk4", n_steps=200, rtol=0.0, atol=0.0, h0=0.0, h_min=0.0,
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
                 stream=None, max_batch=1, tile_rows=0, flow="temperature", g_end=0.0,
-                v_rel=0.0, y_kernel=0, sync_batch=False, n_shells=0, shell_edges=None):
+                v_rel=0.0, y_kernel=0, sync_batch=False, n_shells=0, shell_edges=None,
+                k_table=None):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
     cfg.geometry = GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry)
@@ -158,8 +162,27 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
             raise ValueError("shell_edges must hold (n_shells - 1) / 2 values")
         cfg.shell_edges = _pd(se)
         keep = keep + [se]
+    if k_table is not None:
+        kt = np.ascontiguousarray(k_table, np.float64)
+        if z_table is None or kt.shape != (cfg.n_zT, int(N)):
+            raise ValueError("k_table must be [n_zT, N], on the Z table's nodes")
+        cfg.k_table = _pd(kt)
+        keep = keep + [kt]
     cfg._keep = keep
     return cfg
+
+
+def katanin_table(g, z_table):
+    """fm_katanin_table: Katanin factors K, A_g and its per-node bounds from Z on the scales
+    g (host-only); returns (K [n, N], A [n, N], A_minmax [n, 2])."""
+    g = np.ascontiguousarray(g, np.float64)
+    z = np.ascontiguousarray(z_table, np.float64)
+    n, N = z.shape
+    if g.shape != (n,):
+        raise ValueError("g must hold one scale per table row")
+    K, A, mm = np.zeros_like(z), np.zeros_like(z), np.zeros((n, 2))
+    _check(load().fm_katanin_table(int(n), _pd(g), int(N), _pd(z), _pd(K), _pd(A), _pd(mm)))
+    return K, A, mm
 
 
 def geometry_query(cfg: Config):

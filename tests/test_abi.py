@@ -132,3 +132,34 @@ def test_interaction_flow_config_and_workspace():
     nRp, nRd = fm.representative_counts(t)
     bin_set = (nRp + 2 * nRd) * 48 * 48 * 4
     assert fm.workspace_bytes(t) - fm.workspace_bytes(g) >= 4 * bin_set
+
+
+def test_katanin_table_matches_the_oracle():
+    """fm_katanin_table is host code: K, A_g and the per-node bounds of A against the
+    oracle's table on non-uniform nodes (App. A, Eqs. K_definition and A_g_simple)."""
+    rng = np.random.default_rng(8)
+    g = np.array([0.0, 0.07, 0.2, 0.33, 0.5, 0.61, 0.8, 1.0])
+    z = rng.uniform(0.5, 1.3, (g.size, 12))
+    K, A, mm = fm.katanin_table(g, z)
+    oK, oA = O.katanin(g, z)
+    assert np.abs(K - oK).max() <= 1e-13 * np.abs(oK).max()
+    assert np.abs(A - oA).max() <= 1e-12 * np.abs(oA).max()
+    assert np.array_equal(mm[:, 0], A.min(axis=1)) and np.array_equal(mm[:, 1], A.max(axis=1))
+    for bad in (dict(g=g[:2], z=z[:2]), dict(g=g[::-1], z=z),
+                dict(g=g, z=np.where(np.arange(12) == 3, 0.0, z))):
+        with pytest.raises(fm.FmError):
+            fm.katanin_table(bad["g"], bad["z"])
+
+
+def test_katanin_table_needs_the_interaction_flow():
+    gs = np.linspace(0.0, 1.0, 4)
+    z = np.full((4, 8), 0.9)
+    ok = fm.make_config(8, 16, flow="interaction", T0=0.2, z_lnT=gs, z_table=z,
+                        k_table=np.full((4, 8), 0.7))
+    assert fm.workspace_bytes(ok) > 0
+    for cfg in (fm.make_config(8, 16, z_lnT=np.log([0.01, 0.1, 0.5, 1.0]), z_table=z,
+                               k_table=np.full((4, 8), 0.7)),
+                fm.make_config(8, 16, flow="interaction", T0=0.2, z_lnT=gs, z_table=z,
+                               k_table=np.full((4, 8), np.inf))):
+        with pytest.raises(fm.FmError):
+            fm.workspace_bytes(cfg)
