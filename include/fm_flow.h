@@ -138,8 +138,11 @@ typedef struct {
                                  transfer's permuted bins, 2 stages the operand permuted once
                                  per point-group operation class, 3 reads each representative's
                                  bin row once and applies every operation of its orbit to it
-                                 (tile_rows 1, 2, or 4 with bf16 operands); 0 = chosen by
-                                 timing with tile_rows on the first call */
+                                 (tile_rows 1, 2, or 4 with bf16 operands); 4 (bf16 and split
+                                 bf16 products, N <= 128) runs phase 2 as one fused kernel that
+                                 contracts the products in registers, so the workspace holds
+                                 no product buffers; 0 = chosen by timing with tile_rows on the
+                                 first call, the fused kernel included where it applies */
     int sync_batch;           /* fm_flow_run_batch: 1 = flows with equal T0 form a group that
                                  advances on one step schedule (Dormand-Prince: a step is
                                  accepted only when every running member accepts it, and the

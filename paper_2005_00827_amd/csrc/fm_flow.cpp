@@ -106,6 +106,14 @@ struct Layout {
     }
 };
 
+// Phase 2 as one fused kernel is possible for bf16 or split-bf16 products at N <= 128;
+// y_kernel 4 asks for it alone (and the workspace then holds no product buffers), y_kernel 0
+// lets the tuner choose between it and the two-kernel path by timing.
+bool fusable(const fm_config& c) {
+    return (c.precision == FM_FP32_BF16MFMA || c.precision == FM_FP32_BF16X3) && c.N <= 128;
+}
+bool fused_phase2(const fm_config& c) { return fusable(c) && c.y_kernel == 4; }
+
 int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (!in) { why = "null config"; return FM_EINVAL; }
     c = *in;
@@ -146,7 +154,11 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
         why = "bf16 and split-bf16 precisions support N <= 128";
         return FM_EINVAL;
     }
-    if (c.y_kernel < 0 || c.y_kernel > 3) { why = "y_kernel must be 0, 1, 2 or 3"; return FM_EINVAL; }
+    if (c.y_kernel < 0 || c.y_kernel > 4) { why = "y_kernel must be 0 .. 4"; return FM_EINVAL; }
+    if (c.y_kernel == 4 && !fused_phase2(c)) {
+        why = "y_kernel 4 (fused phase 2) needs bf16 or split-bf16 products and N <= 128";
+        return FM_EINVAL;
+    }
     if (c.sync_batch < 0) { why = "sync_batch must be >= 0"; return FM_EINVAL; }
     return FM_OK;
 }
@@ -161,7 +173,7 @@ struct fm_flow {
     Buffers b{};
     hipStream_t stream = nullptr;      // caller's stream (may be null)
     hipStream_t own = nullptr;         // capture stream for graphs when the caller's is null
-    bool dbl = false, direct = false;
+    bool dbl = false, direct = false, fused = false;
     size_t N3 = 0;
     std::vector<double> zlnT, ztab;    // configured table (host copy)
     std::vector<double> ktab;          // configured Katanin factors on the same nodes, or empty
@@ -234,6 +246,9 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.item_q = L.take<int>(hg.item_q.size());
     b.item_p0 = L.take<int>(hg.item_p0.size());
     b.item_rec = L.take<int>(hg.item_rec.size());
+    b.fz_row = L.take<int>(hg.fz_row.size());
+    b.fz_pair = L.take<int>(hg.fz_pair.size());
+    b.fz_blk = L.take<int>(hg.fz_blk.size());
     b.fs = L.take<FlowState>(B);
     b.z_lnT = L.take<double>(static_cast<size_t>(B) * nz);
     b.z_tab = L.take<double>(static_cast<size_t>(B) * nz * N);
@@ -267,13 +282,15 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         b.binsT = L.take<char>((S * B * nRd * NN + kBinPad) * rs);
         b.bins_bytes = (S * B * (nRp + nRd) * NN + kBinPad) * rs;
         b.binsT_bytes = (S * B * nRd * NN + kBinPad) * rs;
-        // the products of bf16 operands are stored as bf16 (the same 8-bit significand)
+        // the products of bf16 operands are stored as bf16 (the same 8-bit significand); the
+        // fused phase 2 keeps them in registers and needs no buffers for them
         b.y_bf16 = c.precision == FM_FP32_BF16MFMA ? 1 : 0;
         const size_t ys = b.y_bf16 ? 2 : rs;
-        b.y1 = L.take<char>(static_cast<size_t>(B) * nP * NN * ys);
-        b.y2 = L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
-        b.y3 = L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
-        b.y4 = L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
+        const bool fz = fused_phase2(c);
+        b.y1 = fz ? nullptr : L.take<char>(static_cast<size_t>(B) * nP * NN * ys);
+        b.y2 = fz ? nullptr : L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
+        b.y3 = fz ? nullptr : L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
+        b.y4 = fz ? nullptr : L.take<char>(static_cast<size_t>(B) * nD * NN * ys);
         b.wtab = nullptr;
     } else {
         b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
@@ -364,6 +381,10 @@ void rhs_launch(fm_flow* h, int nf, int slot, int set) {
     }
     const int mma = mma_mode(h->cfg.precision);
     const Buffers bs = with_bin_set(h->b, h->g, h->dbl, set);
+    if (h->fused) {
+        timed(h, T_Y, [&] { launch_fused(h->stream, h->g, bs, nf, ch, slot, mma); });
+        return;
+    }
     timed(h, T_Y, [&] { launch_y(h->stream, h->dbl, h->g, bs, nf, ch, mma, h->tpw, h->yvar); });
     timed(h, T_CONTRACT, [&] { launch_contract(h->stream, h->dbl, h->g, h->b, nf, ch, slot); });
 }
@@ -394,7 +415,7 @@ std::map<TuneKey, std::pair<int, int>> g_tune;
 int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     const fm_config& c = h->cfg;
     const int mma = mma_mode(c.precision);
-    if (h->dbl || h->direct || mma == 0 || c.N > 128) return FM_OK;
+    if (h->dbl || h->direct || fused_phase2(c) || mma == 0 || c.N > 128) return FM_OK;
     std::vector<std::pair<int, int>> cand;    // (variant, tiles per wavefront)
     for (int var = 1; var <= 3; ++var) {
         if (c.y_kernel != 0 && var != c.y_kernel) continue;
@@ -414,6 +435,7 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
         if (it != g_tune.end()) {
             h->yvar = it->second.first;
             h->tpw = it->second.second;
+            h->fused = h->yvar == 4;
             h->tuned_nf = nf;
             return FM_OK;
         }
@@ -438,11 +460,28 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
             best = cv;
         }
     }
+    // the fused phase 2 against the best phase 2a plus phase 2b
+    if (fusable(c) && c.y_kernel == 0) {
+        auto time5 = [&](auto&& launch) {
+            launch();
+            (void)hipEventRecord(e0, h->stream);
+            for (int r = 0; r < 5; ++r) launch();
+            (void)hipEventRecord(e1, h->stream);
+            float ms = std::numeric_limits<float>::infinity();
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                ms = std::numeric_limits<float>::infinity();
+            return ms;
+        };
+        const float c_ms = time5([&] { launch_contract(h->stream, false, h->g, h->b, nf, c.channels, 0); });
+        const float f_ms = time5([&] { launch_fused(h->stream, h->g, h->b, nf, c.channels, 0, mma); });
+        if (f_ms < best_ms + c_ms) best = {4, 0};
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipGetLastError());
     h->yvar = best.first;
     h->tpw = best.second;
+    h->fused = best.first == 4;
     h->tuned_nf = nf;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
@@ -577,6 +616,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     h->stream = static_cast<hipStream_t>(c.stream);
     h->dbl = c.precision == FM_FP64 || c.precision == FM_FP64_DIRECT;
     h->direct = c.precision == FM_FP64_DIRECT;
+    h->fused = fused_phase2(c);
     const HostGeometry& hg = h->hg;
     const int N = c.N;
     h->N3 = static_cast<size_t>(N) * N * N;
@@ -617,6 +657,8 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.d_off = h->b.d_off; g.d_pairs = h->b.d_pairs;
     g.item_q = h->b.item_q; g.item_p0 = h->b.item_p0; g.item_rec = h->b.item_rec;
     for (int k = 0; k < 3; ++k) g.n_items[k] = hg.n_items[k];
+    g.fz_row = h->b.fz_row; g.fz_pair = h->b.fz_pair; g.fz_blk = h->b.fz_blk;
+    for (int k = 0; k < 3; ++k) g.fz_nblk[k] = hg.fz_nblk[k];
     auto up = [&](void* dst, const void* src, size_t n) {
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, h->stream);
     };
@@ -660,6 +702,9 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.item_q, hg.item_q);
     if (e == hipSuccess) e = upv(h->b.item_p0, hg.item_p0);
     if (e == hipSuccess) e = upv(h->b.item_rec, hg.item_rec);
+    if (e == hipSuccess) e = upv(h->b.fz_row, hg.fz_row);
+    if (e == hipSuccess) e = upv(h->b.fz_pair, hg.fz_pair);
+    if (e == hipSuccess) e = upv(h->b.fz_blk, hg.fz_blk);
     if (e == hipSuccess) e = up(h->b.kpt, hg.kpt.data(), sizeof(double) * hg.kpt.size());
     // bins start zeroed (with their padding): phase 2a may read past a row's end, and only
     // finite values may meet the zero operand there
@@ -731,6 +776,8 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
     if (reps < 1 || !avg_ms) return fail(FM_EINVAL, "need reps >= 1 and an output");
     if (group < 0 || group > 3 || (h->direct && group == 1))
         return fail(FM_EINVAL, "group: 0 stage and phase 1, 1 phase 2a, 2 phase 2b, 3 stage alone");
+    if (h->fused && group == 2)
+        return fail(FM_EINVAL, "phase 2 is one fused launch here: time group 1");
     // flows replayed as running at their current temperature; their status is restored
     std::vector<FlowState> saved(batch);
     HIPCHK(hipMemcpyAsync(saved.data(), h->b.fs, sizeof(FlowState) * batch, hipMemcpyDeviceToHost, h->stream));
@@ -752,6 +799,8 @@ int fm_flow_kernel_time(fm_flow* h, int group, int batch, int reps, double* avg_
             launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, sc, step_bins, 0, h->b.V);
         else if (group == 3)
             launch_stage(h->stream, h->dbl, h->g, h->z, h->b, batch, mid, kNoBins, 0, h->b.V);
+        else if (group == 1 && h->fused)
+            launch_fused(h->stream, h->g, h->b, batch, h->cfg.channels, 0, mma);
         else if (group == 1)
             launch_y(h->stream, h->dbl, h->g, h->b, batch, h->cfg.channels, mma, h->tpw, h->yvar);
         else if (h->direct)

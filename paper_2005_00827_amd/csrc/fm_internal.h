@@ -57,7 +57,19 @@ struct HostGeometry {
     std::vector<int> item_q, item_p0;
     std::vector<int> item_rec;       // [items][16]: transfer, pair count, channel, first pair, 8 pairs
     int n_items[3] = {0, 0, 0};
+    // Fused phase 2: rows (transfer, up to kFusedPairs of its output pairs) per channel kind,
+    // ordered by (operation, representative) like the transfers, each operation class padded
+    // to whole blocks of kFusedRows rows (padding rows: transfer -1, no pairs); per block its
+    // operation and first row.
+    std::vector<int> fz_row;         // [rows] transfer or -1
+    std::vector<int> fz_pair;        // [rows][kFusedPairs] packed pair or -1
+    std::vector<int> fz_blk;         // [blocks][2] operation, first row
+    int fz_nblk[3] = {0, 0, 0};      // blocks of the pp, crossed and direct kinds, in order
 };
+
+// Fused phase 2: output pairs per row and rows per block (16-row tiles, one per wavefront).
+constexpr int kFusedPairs = 4;
+constexpr int kFusedRows = 128;
 
 bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err);
 
@@ -120,6 +132,10 @@ struct DevGeom {
     const int* item_q; const int* item_p0;
     const int* item_rec;   // [items][16] (one 64-byte record per phase-2b work item)
     int n_items[3];
+    const int* fz_row;     // fused phase 2 tables (see HostGeometry)
+    const int* fz_pair;
+    const int* fz_blk;
+    int fz_nblk[3];
     const double* xi;      // [np]
     const int* patch;      // [np]
     const int2* xp;        // [np] (xi as float bits, patch): single-precision phase 1
@@ -172,6 +188,7 @@ struct Buffers {
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
     int* item_q; int* item_p0; int* item_rec;
+    int* fz_row; int* fz_pair; int* fz_blk;
     void* bins;                        // [S][B][nRp + nRd][NN] real, representative transfers
     void* binsT;                       // [S][B][nRd][NN] real, particle-hole bins transposed
     int nbset;                         // S: bin sets (stage nodes of one step)
@@ -226,6 +243,10 @@ int y_rows_max_tpw(const DevGeom& g);
 int y_orb_max_tpw(const DevGeom& g, int mma);
 void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b, int nf,
                      unsigned ch, int slot);
+// Fused phase 2 (FM_FP32_BF16MFMA, FM_FP32_BF16X3 with N <= 128): products and contraction
+// in one launch into k slot `slot`, with the bins of b's set.
+void launch_fused(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
+                  int slot, int mma);
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf);
 void launch_direct(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
                    int slot);

@@ -323,6 +323,37 @@ void build_pairs(HostGeometry& g) {
             }
         g.n_items[k] = n;
     }
+    // fused phase 2: each transfer's pairs in rows of at most kFusedPairs, rows of one
+    // operation class in whole blocks
+    g.fz_row.clear();
+    g.fz_pair.clear();
+    g.fz_blk.clear();
+    for (int k = 0; k < 3; ++k) {
+        const std::vector<int>& off = *offs[k];
+        const std::vector<int>& pr = *prs[k];
+        const std::vector<int>& cls = k == 0 ? g.cls_pp : g.cls_ph;
+        int nb = 0;
+        for (int o = 0; o < 8; ++o) {
+            const size_t r0 = g.fz_row.size();
+            for (int q = cls[o]; q < cls[o + 1]; ++q)
+                for (int p = off[q]; p < off[q + 1]; p += kFusedPairs) {
+                    g.fz_row.push_back(q);
+                    for (int i = 0; i < kFusedPairs; ++i)
+                        g.fz_pair.push_back(p + i < off[q + 1] ? pr[p + i] : -1);
+                }
+            if (g.fz_row.size() == r0) continue;
+            while ((g.fz_row.size() - r0) % kFusedRows) {
+                g.fz_row.push_back(-1);
+                for (int i = 0; i < kFusedPairs; ++i) g.fz_pair.push_back(-1);
+            }
+            for (size_t r = r0; r < g.fz_row.size(); r += kFusedRows) {
+                g.fz_blk.push_back(o);
+                g.fz_blk.push_back(static_cast<int>(r));
+                ++nb;
+            }
+        }
+        g.fz_nblk[k] = nb;
+    }
 }
 
 }  // namespace

@@ -2106,6 +2106,280 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
 }
 
 // ------------------------------------------------------------------------------------
+// Fused phase 2 (bf16 and split-bf16 operands, N <= 128): the grouped products and the
+// contraction they feed in one kernel, so the products never leave registers (no Y buffers).
+// A block takes kFusedRows rows of one channel kind, all from transfers q = o(r) of one
+// operation o, and one chunk of W = 16 NT output columns n; a row is (q, up to kFusedPairs of
+// the output pairs that use q), held by lane % 16 of its wavefront's 16-row tile.  For every
+// bin row p of the representatives (slab g = perm_o p):
+//   Y_q[g][n] = sum_k' Brep_r(p, k') B'[k'][n],
+//   B'[k'][n] = Z_g Z_k (al + be (W_g + W_k)) Vsrc[g][k][n],  k = perm_o k'
+// (the products of the operation-class kernel), on the matrix cores with the staged operand
+// first, so that a lane holds four consecutive n of its own row; then on the vector units
+//   acc[pair][n] += L(pair, g) Y_q[g][n]
+// with the pair vectors of phase 2b (V(a,b,g); V(g,b,c); for the direct channel
+// V(g,a,c) - 2 V(a,g,c) against the va products plus V(a,g,c) against the vc products).
+// After the last p the accumulators are the channel's part of the k slot (-acc for pp).  The
+// staged operand is double-buffered (single with split bf16, whose two planes fill the LDS),
+// so the next slab's staging overlaps this slab's products; the next bin row and pair values
+// are loaded while the current ones are used.
+// ------------------------------------------------------------------------------------
+template <int kM, int KE, int NT>
+__device__ inline void mfma_bt(const AFrag<kM, KE>& A, const __bf16* Bh, fm_f4 (&c)[NT],
+                               int lane) {
+    constexpr int KBS = 4 * KE + 8, PL = 16 * NT * KBS;
+    const int col = lane & 15;
+#pragma unroll
+    for (int s = 0; s < KE / 8; ++s) {
+        const int kb = 32 * s + 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int o = (16 * t + col) * KBS + kb;
+            const fm_bf8 bh = *reinterpret_cast<const fm_bf8*>(Bh + o);
+            if constexpr (kM == 2) {
+                const fm_bf8 bl = *reinterpret_cast<const fm_bf8*>(Bh + PL + o);
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, A.h[s], c[t], 0, 0, 0);
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, A.l[s], c[t], 0, 0, 0);
+            }
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, A.h[s], c[t], 0, 0, 0);
+        }
+    }
+}
+
+template <int kM, int KE, int NT>
+__global__ void __launch_bounds__(4 * kFusedRows) k_fused(
+        DevGeom g, const FlowState* fs, const double* Z_stage, const double* zw,
+        const float* bins, const float* binsT, const float* v0, const float* va,
+        const float* vc, float* K, unsigned ch, int slot, int B, int nchunk, int nf) {
+    constexpr int kT = 4 * kFusedRows;            // 16 rows per wavefront
+    constexpr int KP = 4 * KE;                    // staged k' (zero from N on)
+    constexpr int W = 16 * NT;
+    constexpr int KBS = KP + 8;
+    constexpr int PL = W * KBS;                   // bf16 per plane
+    constexpr int kOp = PL * (kM == 2 ? 2 : 1);   // bf16 per staged operand
+    constexpr int kBuf = kM == 2 ? 1 : 2;
+    constexpr int kTasks = KP / 8 * W;            // staging: 8 consecutive k' of one column
+    constexpr int kTPT = (kTasks + kT - 1) / kT;  // staging tasks per thread
+    constexpr int kP = kFusedPairs;
+    __shared__ __align__(16) __bf16 Bs[kBuf][2][kOp];
+    __shared__ float zs[256];                     // Z and W = K Z of the stage
+    __shared__ int pms[128];                      // perm_o
+    __shared__ float za[128], zb[128];            // fac(g, k') = Z_g (za[k'] + zb[k'] W_g)
+    __shared__ int ko[128];                       // k = perm_o k' times N (row of a slab)
+    const int N = g.N, NN = g.NN;
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    // 1D grid.  The blocks that read the same bin rows -- both column chunks, and the two
+    // flows of a pair (which share bins when they step together) -- are one work group of
+    // M = 2 nchunk members; work groups are dealt to the 8 XCDs round-robin and a group's
+    // members get block ids 8 apart, so they run on one XCD at about the same time and read
+    // the rows through its L2:
+    //   id = (key / 8) 8 M + member 8 + key % 8,  key = (flow / 2) nblk + row block.
+    const int nblk = g.fz_nblk[0] + g.fz_nblk[1] + g.fz_nblk[2];
+    const int M = 2 * nchunk;
+    const int id = blockIdx.x;
+    const int key = (id / (8 * M)) * 8 + id % 8;
+    const int member = (id % (8 * M)) / 8;
+    if (key >= nblk * ((nf + 1) / 2)) return;     // padding of the last 8 work groups
+    const int b = key % nblk;
+    const int f = 2 * (key / nblk) + member / nchunk;
+    const int chunk = member % nchunk;
+    if (f >= nf || !running(fs, f)) return;       // uniform over the block
+    const int kind = b < g.fz_nblk[0] ? 0 : (b < g.fz_nblk[0] + g.fz_nblk[1] ? 1 : 2);
+    const int o = g.fz_blk[2 * b], row0 = g.fz_blk[2 * b + 1];
+    const int lane = threadIdx.x & 63;
+    const int row = row0 + 16 * static_cast<int>(threadIdx.x >> 6) + (lane & 15);
+    const int q = g.fz_row[row];
+    int pr[kP];
+#pragma unroll
+    for (int i = 0; i < kP; ++i) pr[i] = g.fz_pair[row * kP + i];
+    const int n0 = chunk * W;
+    const int nl = n0 + 4 * (lane >> 4);          // the lane's first n in tile 0
+    float* Kf = K + ((static_cast<size_t>(slot) * B + f) * 3 + kind) * N3;
+    const unsigned bit = kind == 0 ? FM_CH_PP : (kind == 1 ? FM_CH_CR : FM_CH_D);
+    if (!(ch & bit)) {                            // a channel that is off contributes zero
+#pragma unroll
+        for (int i = 0; i < kP; ++i)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = nl + 16 * t + r;
+                    if (pr[i] >= 0 && n < N) Kf[static_cast<size_t>(pr[i]) * N + n] = 0.f;
+                }
+        return;
+    }
+    const bool two = kind == 2;                   // uniform over the block
+    const int nR = g.nRp + g.nRd;
+    const int fb = bin_flow(fs, f);
+    const float* Bf = kind == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
+                                : bins + static_cast<size_t>(fb) * nR * NN + (kind == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const int rep = q >= 0 ? (kind == 0 ? g.qrep_pp[q] : g.qrep_ph[q]) : 0;
+    const float* Arow = Bf + static_cast<size_t>(rep) * NN;
+    const float* S0 = (kind == 0 ? v0 : (kind == 1 ? vc : va)) + f * N3;
+    const float* S1 = vc + f * N3;
+    const float* L0 = (kind == 0 ? v0 : vc) + f * N3;
+    const float* L1 = va + f * N3;
+    size_t lb[kP];
+#pragma unroll
+    for (int i = 0; i < kP; ++i) {
+        // pair vectors, contiguous in g: V(u,w,g) = v0[u][w][g]; V(g,u,w) = vc[w][u][g],
+        // V(u,g,w) = va[w][u][g]
+        const int xy = max(pr[i], 0), u = xy / N, w = xy - u * N;
+        lb[i] = kind == 0 ? static_cast<size_t>(xy) * N : static_cast<size_t>(w) * NN + static_cast<size_t>(u) * N;
+    }
+    const double* Zf = Z_stage + static_cast<size_t>(f) * 2 * N;
+    for (int k = threadIdx.x; k < 2 * N; k += kT) zs[k] = static_cast<float>(Zf[k]);
+    for (int k = threadIdx.x; k < N; k += kT) pms[k] = g.perm[o * N + k];
+    const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
+    __syncthreads();
+    // Z_g Z_k (al + be (W_g + W_k)) = Z_g (Z_k (al + be W_k) + be Z_k W_g), k = perm_o k';
+    // zero for k' >= N
+    for (int kk = threadIdx.x; kk < KP; kk += kT) {
+        const int k = pms[min(kk, N - 1)];
+        const float zk = zs[k], wk = zs[N + k];
+        za[kk] = kk < N ? zk * (al + be * wk) : 0.f;
+        zb[kk] = kk < N ? be * zk : 0.f;
+        ko[kk] = k * N;
+    }
+    __syncthreads();
+
+    // B'[k'][n] of slab perm_o p for both operands (the second only for the direct channel),
+    // bf16 transposed [n][k'] (split bf16: the low parts in a second plane).  A task is 8
+    // consecutive k' of one column n: its 8 loads are coalesced over the wave's columns, and
+    // its values go to LDS as one 16-byte store per plane.  The loads of a slab are issued
+    // one slab ahead of its stores, so their latency is spent on the current products.
+    float sx0[kTPT][8], sx1[kTPT][8];
+    auto stage_load = [&](int p) {
+        const int gs = pms[p];
+        const float* s0 = S0 + static_cast<size_t>(gs) * NN;
+        const float* s1 = S1 + static_cast<size_t>(gs) * NN;
+#pragma unroll
+        for (int j = 0; j < kTPT; ++j) {
+            const int task = min(static_cast<int>(threadIdx.x) + j * kT, kTasks - 1);
+            const int n = task % W, kb = 8 * (task / W);
+            const int nc = min(n0 + n, N - 1);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sx0[j][i] = s0[ko[kb + i] + nc];
+                sx1[j][i] = two ? s1[ko[kb + i] + nc] : 0.f;
+            }
+        }
+    };
+    auto stage_store = [&](int p, int buf) {
+        const int gs = pms[p];
+        const float zg = zs[gs], wg = zs[N + gs];
+#pragma unroll
+        for (int j = 0; j < kTPT; ++j) {
+            const int task = static_cast<int>(threadIdx.x) + j * kT;
+            if (task >= kTasks) break;
+            const int n = task % W, kb = 8 * (task / W);
+            const float nok = n0 + n < N ? zg : 0.f;
+            fm_bf8 h0, h1, l0, l1;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float fac = nok * (za[kb + i] + zb[kb + i] * wg);
+                const float y0 = fac * sx0[j][i], y1 = fac * sx1[j][i];
+                h0[i] = static_cast<__bf16>(y0);
+                h1[i] = static_cast<__bf16>(y1);
+                if constexpr (kM == 2) {
+                    l0[i] = static_cast<__bf16>(y0 - static_cast<float>(h0[i]));
+                    l1[i] = static_cast<__bf16>(y1 - static_cast<float>(h1[i]));
+                }
+            }
+            *reinterpret_cast<fm_bf8*>(&Bs[buf][0][n * KBS + kb]) = h0;
+            if constexpr (kM == 2) *reinterpret_cast<fm_bf8*>(&Bs[buf][0][PL + n * KBS + kb]) = l0;
+            if (two) {
+                *reinterpret_cast<fm_bf8*>(&Bs[buf][1][n * KBS + kb]) = h1;
+                if constexpr (kM == 2) *reinterpret_cast<fm_bf8*>(&Bs[buf][1][PL + n * KBS + kb]) = l1;
+            }
+        }
+    };
+    // pair values at slab perm_o p (0 for the padding pairs)
+    auto load_l = [&](int p, float (&x)[kP], float (&y)[kP]) {
+        const int gs = pms[p];
+#pragma unroll
+        for (int i = 0; i < kP; ++i) {
+            x[i] = pr[i] >= 0 ? L0[lb[i] + gs] : 0.f;
+            y[i] = (two && pr[i] >= 0) ? L1[lb[i] + gs] : 0.f;
+        }
+    };
+
+    fm_f4 acc[kP][NT];
+#pragma unroll
+    for (int i = 0; i < kP; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[i][t] = fm_f4{0.f, 0.f, 0.f, 0.f};
+    float a[KE], lc[kP], wc[kP];
+    stage_load(0);
+    stage_store(0, 0);
+    if (N > 1) stage_load(1);
+    gather_a<kM, KE>(a, Arow, N, lane);
+    load_l(0, lc, wc);
+    __syncthreads();                              // slab 0 staged; every thread
+    for (int p = 0; p < N; ++p) {
+        const int cur = kBuf == 2 ? (p & 1) : 0;
+        if constexpr (kBuf == 2) {
+            if (p + 1 < N) stage_store(p + 1, cur ^ 1);   // loaded during the last slab
+            if (p + 2 < N) stage_load(p + 2);
+        } else {
+            if (p + 1 < N && p > 0) stage_load(p + 1);
+        }
+        const AFrag<kM, KE> A = make_afrag<kM, KE>(a);
+        float ln[kP], wn[kP];
+        if (p + 1 < N) {
+            gather_a<kM, KE>(a, Arow + static_cast<size_t>(p + 1) * N, N, lane);
+            load_l(p + 1, ln, wn);
+        }
+        {
+            fm_f4 c[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) c[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
+            mfma_bt<kM, KE, NT>(A, Bs[cur][0], c, lane);
+#pragma unroll
+            for (int i = 0; i < kP; ++i) {
+                const float s = two ? lc[i] - 2.f * wc[i] : lc[i];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[i][t] += s * c[t];
+            }
+        }
+        if (two) {
+            fm_f4 c[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) c[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
+            mfma_bt<kM, KE, NT>(A, Bs[cur][1], c, lane);
+#pragma unroll
+            for (int i = 0; i < kP; ++i)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[i][t] += wc[i] * c[t];
+        }
+        if (p + 1 < N) {
+#pragma unroll
+            for (int i = 0; i < kP; ++i) { lc[i] = ln[i]; wc[i] = wn[i]; }
+        }
+        if constexpr (kBuf == 1) {
+            if (p + 1 < N) {
+                __syncthreads();                  // every wave is done with the buffer
+                stage_store(p + 1, 0);
+            }
+        }
+        __syncthreads();                          // next slab staged; every thread
+    }
+    const float sg = kind == 0 ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < kP; ++i) {
+        if (pr[i] < 0) continue;
+        float* dst = Kf + static_cast<size_t>(pr[i]) * N;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = nl + 16 * t + r;
+                if (n < N) dst[n] = sg * acc[i][t][r];
+            }
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // Direct double-precision path.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_wtable(DevGeom g, const FlowState* fs,
@@ -2798,6 +3072,30 @@ void contract_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsig
     contract_go<R, R>(s, g, b, nf, ch, slot);
 }
 
+template <int kM, int KE, int NT>
+void fused_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
+    const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
+    const int nblk = g.fz_nblk[0] + g.fz_nblk[1] + g.fz_nblk[2];
+    const int keys = nblk * ((nf + 1) / 2);
+    const int blocks = (keys + 7) / 8 * 8 * 2 * nchunk;
+    hipLaunchKernelGGL((k_fused<kM, KE, NT>), dim3(blocks), dim3(4 * kFusedRows), 0, s, g,
+                       b.fs, b.Z_stage, b.zw_stage, static_cast<const float*>(b.bins),
+                       static_cast<const float*>(b.binsT), static_cast<const float*>(b.v0),
+                       static_cast<const float*>(b.va), static_cast<const float*>(b.vc),
+                       static_cast<float*>(b.k), ch, slot, b.bstride, nchunk, nf);
+}
+
+template <int kM>
+void fused_m(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
+    // k padded to whole 32-wide steps; columns in chunks of at most 64
+    if (g.N <= 16) fused_go<kM, 8, 1>(s, g, b, nf, ch, slot);
+    else if (g.N <= 32) fused_go<kM, 8, 2>(s, g, b, nf, ch, slot);
+    else if (g.N <= 48) fused_go<kM, 16, 3>(s, g, b, nf, ch, slot);
+    else if (g.N <= 64) fused_go<kM, 16, 4>(s, g, b, nf, ch, slot);
+    else if (g.N <= 96) fused_go<kM, 24, 4>(s, g, b, nf, ch, slot);
+    else fused_go<kM, 32, 4>(s, g, b, nf, ch, slot);
+}
+
 }  // namespace
 
 int y_max_tpw(const DevGeom& g) {
@@ -2851,6 +3149,12 @@ void launch_contract(hipStream_t s, bool dbl, const DevGeom& g, const Buffers& b
                      unsigned ch, int slot) {
     if (dbl) contract_t<double>(s, g, b, nf, ch, slot);
     else contract_t<float>(s, g, b, nf, ch, slot);
+}
+
+void launch_fused(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
+                  int slot, int mma) {
+    if (mma == 3) fused_m<2>(s, g, b, nf, ch, slot);
+    else fused_m<1>(s, g, b, nf, ch, slot);
 }
 
 void launch_wtable(hipStream_t s, const DevGeom& g, const Buffers& b, int nf) {

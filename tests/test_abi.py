@@ -97,7 +97,9 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=16, L=32, channels=9), "channel"),
     (dict(N=16, L=32, tile_rows=-1), "tile_rows"),
     (dict(N=16, L=32, flow=2), "bad flow"),
-    (dict(N=16, L=32, y_kernel=4), "y_kernel"),
+    (dict(N=16, L=32, y_kernel=5), "y_kernel"),
+    (dict(N=16, L=32, y_kernel=4), "fused phase 2"),          # needs bf16 products
+    (dict(N=136, L=128, precision="bf16x3", y_kernel=4), "N <= 128"),
     (dict(N=16, L=32, flow="interaction", T0=0.0), "T0 > 0"),
     (dict(N=16, L=32, flow="interaction", T0=0.2, g_end=-1.0), "g_end"),
     (dict(N=136, L=128, precision="bf16"), "N <= 128"),
@@ -163,3 +165,15 @@ def test_katanin_table_needs_the_interaction_flow():
                                k_table=np.full((4, 8), np.inf))):
         with pytest.raises(fm.FmError):
             fm.workspace_bytes(cfg)
+
+
+def test_fused_phase2_workspace_holds_no_products():
+    """y_kernel 4 runs phase 2 as one fused kernel: the workspace drops the product buffers,
+    (nP + 3 nD) N^2 values per flow, stored as bf16 for bf16 products and f32 otherwise."""
+    for prec, ys in (("bf16", 2), ("bf16x3", 4)):
+        two = fm.make_config(48, 64, precision=prec, y_kernel=3, max_batch=2)
+        one = fm.make_config(48, 64, precision=prec, y_kernel=4, max_batch=2)
+        _, _, _, nP, nD, _ = fm.geometry_query(two)
+        saved = fm.workspace_bytes(two) - fm.workspace_bytes(one)
+        want = 2 * (nP + 3 * nD) * 48 * 48 * ys
+        assert want <= saved <= want + 4 * 256

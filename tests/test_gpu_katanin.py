@@ -38,8 +38,10 @@ def interp(g, gs, tab):
     return np.array([np.interp(g, gs, tab[:, a]) for a in range(tab.shape[1])])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp64_direct", "fp32", "bf16", "bf16x3"])
-def test_rhs_g_with_katanin_table(torch_dev, prec):
+@pytest.mark.parametrize("prec,y_kernel", [("fp64", 0), ("fp64_direct", 0), ("fp32", 0),
+                                           ("bf16", 3), ("bf16x3", 3), ("bf16", 4), ("bf16x3", 4)])
+def test_rhs_g_with_katanin_table(torch_dev, prec, y_kernel):
+    """y_kernel 3: phase 2 on the orbit kernel and phase 2b; 4: the fused phase 2."""
     from paper_2005_00827_amd import fm
     torch, dev = torch_dev
     N, L, U = 16, 32, 2.5
@@ -47,7 +49,7 @@ def test_rhs_g_with_katanin_table(torch_dev, prec):
     V = np.stack([inputs.noisy_state(N, U, seed=1), inputs.noisy_state(N, U, seed=2)])
     T, g = [0.3, 0.05], [0.35, 0.9]
     f = fm.Flow(N=N, L=L, precision=prec, flow="interaction", T0=0.3, max_batch=2,
-                z_lnT=gs, z_table=z, k_table=k, device=dev)
+                z_lnT=gs, z_table=z, k_table=k, y_kernel=y_kernel, device=dev)
     try:
         got = f.rhs_g(T, g, torch.from_numpy(V).to(dev)).cpu().numpy()
     finally:

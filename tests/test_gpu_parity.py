@@ -118,6 +118,26 @@ def test_rhs_every_phase2a_tile_choice(torch_dev, prec, tile_rows, y_kernel, N, 
     assert rel(got, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("N,L,channels", [(16, 32, 7), (20, 16, 7), (32, 64, 7), (48, 64, 7),
+                                          (64, 64, 7), (96, 32, 7), (32, 64, 1), (32, 64, 2),
+                                          (32, 64, 4), (32, 64, 6)])
+def test_rhs_fused_phase2(torch_dev, prec, N, L, channels):
+    """Phase 2 as one fused launch (products and contraction, no product buffers), forced
+    with y_kernel 4: every N from one 16-column tile to 96 (every column-tile and k-step
+    count of the kernel), every channel alone and together (channels switched off write
+    zeros), two states at two temperatures with a Z table."""
+    lnT, tab = inputs.synthetic_z_table(N, 2.5, 1.0, 0.01)
+    V = np.stack([inputs.noisy_state(N, 2.5, seed=5), inputs.noisy_state(N, 2.0, seed=6)])
+    T = [0.3, 0.06]
+    got = gpu_rhs(torch_dev, N, L, T, V, prec, y_kernel=4, channels=channels, z_lnT=lnT,
+                  z_table=tab)
+    for i in range(2):
+        Z = np.array([np.interp(math.log(T[i]), lnT, tab[:, a]) for a in range(N)])
+        ref = O.rhs(O.model(N, L, channels=channels), T[i], V[i], Z=Z)
+        assert rel(got[i], ref) <= TOL[prec], (i, rel(got[i], ref))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_rhs_with_z_table_and_batch(torch_dev, prec):
     """Two states at two temperatures in one batch, Z interpolated from a table."""
@@ -147,8 +167,9 @@ def test_rhs_c2_full(torch_dev, prec):
 
 @pytest.mark.parametrize("N,L", [(96, 256), (128, 512)])
 @pytest.mark.parametrize("prec,y_kernel", [("fp64", 0), ("fp32", 1), ("fp32", 2), ("fp32", 3),
-                                           ("bf16", 1), ("bf16", 2), ("bf16", 3), ("bf16x3", 1),
-                                           ("bf16x3", 2), ("bf16x3", 3)])
+                                           ("bf16", 1), ("bf16", 2), ("bf16", 3), ("bf16", 4),
+                                           ("bf16x3", 1), ("bf16x3", 2), ("bf16x3", 3),
+                                           ("bf16x3", 4)])
 def test_rhs_large_sampled(torch_dev, N, L, prec, y_kernel):
     """Full-size grids: sampled outputs against the oracle's per-element sums, with each
     matrix-core phase-2a kernel."""
