@@ -1,0 +1,215 @@
+"""The named workloads as whole flows on the GPU, through the C ABI:
+
+* the 16-flow batch (N = 128, L = 512, U = 1..4, Z per flow): T_c of the bf16, split-bf16
+  and FP32 right-hand sides against a converged FP64 run of the same batch (rtol 1e-8) to
+  1e-3 (the oracle would need hours per right-hand side here);
+* the quasi-particle flow (N = 48, L = 128, U = 3, Z table) against the oracle's flow stored
+  in tests/golden/c2_flow.txt, in FP64 and FP32, and the FP32 path replayed on the FP64
+  path's schedule (every accepted step to 1e-4);
+* three early-diverging flows of the 64-flow sweep against the oracle's flows stored in
+  tests/golden/c4_flows.txt, inside the full 64-flow batch, and every flow's T_c in FP32
+  against FP64;
+* phase 1 with two stage nodes per block (the path of the 16-flow batch) against the
+  oracle: a Dormand-Prince step with h = -1e-6 moves V by h times the right-hand side at the
+  step's start to within 1e-6 relative, which is compared with the oracle's sums at sampled
+  outputs.
+
+Goldens come from tests/golden/make_flow_goldens.py, which calls only the oracle.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2005_00827_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    return torch, torch.device("cuda:0")
+
+
+def _fm():
+    from paper_2005_00827_amd import fm
+    return fm
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def c2_golden():
+    out = {"trace": []}
+    for ln in open(os.path.join(GOLD, "c2_flow.txt")):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        k, *v = ln.split()
+        if k == "trace":
+            out["trace"].append((float(v[0]), float(v[1])))
+        elif k == "T_c":
+            out[k] = float(v[0])
+        else:
+            out[k] = int(v[0])
+    out["trace"] = np.array(out["trace"])
+    return out
+
+
+def c4_golden():
+    rows = []
+    for ln in open(os.path.join(GOLD, "c4_flows.txt")):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        U, T0, st, tc, na, nr, nh = ln.split()
+        rows.append(dict(U=float(U), T0=float(T0), status=int(st), T_c=float(tc),
+                         n_accepted=int(na), n_rejected=int(nr), n_rhs=int(nh)))
+    return rows
+
+
+def test_c5_batch_tc_against_converged_fp64(torch_dev):
+    fm = _fm()
+    torch, dev = torch_dev
+    w = inputs.workload("C5")
+    N, L, U, T0 = w["N"], w["L"], w["U"], w["T0"]
+    tabs = [inputs.synthetic_z_table(N, u, 1.0, w["T_end"]) for u in U]
+    zl = np.stack([t[0] for t in tabs])
+    zt = np.stack([t[1] for t in tabs])
+
+    def run(prec, rtol=0.0):
+        f = fm.Flow(N=N, L=L, U=U[0], T0=1.0, T_end=w["T_end"], integrator="rk45",
+                    precision=prec, rtol=rtol, z_lnT=zl[0], z_table=zt[0], max_batch=len(U),
+                    device=dev)
+        try:
+            return f.run_batch(U, T0, z_lnT=zl, z_tables=zt)
+        finally:
+            f.close()
+
+    ref = run("fp64", 1e-8)
+    assert sum(r["status"] == fm.DIVERGED for r in ref) >= 12
+    for prec in ("bf16", "bf16x3", "fp32"):
+        res = run(prec)
+        for i, (r, q) in enumerate(zip(res, ref)):
+            assert r["status"] == q["status"], (prec, i, r, q)
+            if q["status"] == fm.DIVERGED:
+                assert abs(r["T_c"] / q["T_c"] - 1.0) <= 1e-3, (prec, i, r["T_c"], q["T_c"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_flow_against_oracle_golden(torch_dev, prec):
+    fm = _fm()
+    torch, dev = torch_dev
+    gold = c2_golden()
+    w = inputs.workload("C2")
+    N, L, U = w["N"], w["L"], w["U"][0]
+    zl, zt = inputs.synthetic_z_table(N, U, 1.0, w["T_end"])
+    f = fm.Flow(N=N, L=L, U=U, T0=1.0, T_end=w["T_end"], integrator="rk45", precision=prec,
+                z_lnT=zl, z_table=zt, device=dev)
+    try:
+        res = f.run_batch([U], [1.0])[0]
+    finally:
+        f.close()
+    assert res["status"] == gold["status"] == fm.DIVERGED
+    if prec == "fp64":
+        assert (res["n_accepted"], res["n_rejected"], res["n_rhs"]) == \
+            (gold["n_accepted"], gold["n_rejected"], gold["n_rhs"])
+        assert abs(res["T_c"] / gold["T_c"] - 1.0) <= 1e-9
+        assert res["max_abs_V"] == pytest.approx(gold["trace"][-1, 1], rel=1e-9)
+    else:
+        assert abs(res["T_c"] / gold["T_c"] - 1.0) <= 1e-3
+
+
+def test_c2_fp32_on_the_fp64_schedule(torch_dev):
+    """The FP64 path's accepted steps (its RHS matches the oracle to 1e-10) replayed in FP32,
+    every attempt accepted: the state after each step to 1e-4 of max|V|."""
+    fm = _fm()
+    torch, dev = torch_dev
+    w = inputs.workload("C2")
+    N, L, U = w["N"], w["L"], w["U"][0]
+    zl, zt = inputs.synthetic_z_table(N, U, 1.0, w["T_end"])
+    kw = dict(N=N, L=L, U=U, integrator="rk45", z_lnT=zl, z_table=zt, device=dev)
+    f64 = fm.Flow(precision="fp64", **kw)
+    f32 = fm.Flow(precision="fp32", rtol=1e30, **kw)
+    try:
+        V = torch.full((1, N, N, N), U, dtype=torch.float64, device=dev)
+        Vm = V.clone()
+        lnT, h, lnTe = 0.0, math.log(0.01) / 200, math.log(0.01)
+        n = 0
+        for _ in range(400):
+            l1, h1, acc = f64.step([lnT], [h], V)
+            if acc[0]:
+                _, _, acc32 = f32.step([lnT], [l1[0] - lnT], Vm)
+                assert acc32[0]
+                err = ((Vm - V).abs().max() / V.abs().max()).item()
+                assert err <= 1e-4, (lnT, err)
+                n += 1
+                lnT = l1[0]
+                if V.abs().max().item() > 20.0 or lnT <= lnTe:
+                    break
+            h = max(h1[0], lnTe - lnT)
+        assert n >= 10 and V.abs().max().item() > 20.0
+    finally:
+        f64.close()
+        f32.close()
+
+
+def test_c4_sweep_subset_against_oracle_goldens(torch_dev):
+    fm = _fm()
+    torch, dev = torch_dev
+    w = inputs.workload("C4")
+    U, T0 = w["U"], w["T0"]
+    res = {}
+    for prec in ("fp64", "fp32"):
+        f = fm.Flow(N=w["N"], L=w["L"], U=U[0], T0=max(T0), T_end=w["T_end"], integrator="rk45",
+                    precision=prec, max_batch=len(U), device=dev)
+        try:
+            res[prec] = f.run_batch(U, T0)
+        finally:
+            f.close()
+    for g in c4_golden():
+        i = min(range(len(U)), key=lambda k: abs(U[k] - g["U"]) + abs(T0[k] - g["T0"]))
+        assert abs(U[i] - g["U"]) < 1e-12 and abs(T0[i] - g["T0"]) < 1e-12
+        r = res["fp64"][i]
+        assert r["status"] == g["status"] == fm.DIVERGED
+        assert (r["n_accepted"], r["n_rejected"], r["n_rhs"]) == \
+            (g["n_accepted"], g["n_rejected"], g["n_rhs"])
+        assert abs(r["T_c"] / g["T_c"] - 1.0) <= 1e-9
+        assert abs(res["fp32"][i]["T_c"] / g["T_c"] - 1.0) <= 1e-3
+    for r32, r64 in zip(res["fp32"], res["fp64"]):
+        assert r32["status"] == r64["status"]
+        if r64["status"] == fm.DIVERGED:
+            assert abs(r32["T_c"] / r64["T_c"] - 1.0) <= 1e-3
+
+
+def test_two_nodes_per_phase1_block_against_oracle(torch_dev):
+    """Five flows at N = 128, L = 512 take a Dormand-Prince step of h = -1e-6 in FP32: the
+    step's first stage launch bins the five stage nodes two per block (the path of the
+    16-flow batch).  (V_new - V)/h is the weighted sum of the six stage derivatives, which
+    differ from the derivative at the step's start by O(h) (1e-6 relative), and is compared
+    with the oracle's sums at 40 sampled outputs per flow, to the FP32 tolerance 1e-4."""
+    fm = _fm()
+    torch, dev = torch_dev
+    N, L = 128, 512
+    Us = [1.5, 2.0, 2.5, 3.0, 3.5]
+    V = np.stack([inputs.noisy_state(N, u, seed=11 + i) for i, u in enumerate(Us)])
+    T, h = 0.2, -1e-6
+    f = fm.Flow(N=N, L=L, U=Us[0], precision="fp32", integrator="rk45", max_batch=len(Us),
+                device=dev)
+    try:
+        Vb = torch.from_numpy(V.copy()).to(dev)
+        _, _, acc = f.step([math.log(T)] * len(Us), [h] * len(Us), Vb)
+        assert all(acc)
+        D = (Vb.cpu().numpy() - V) / h
+    finally:
+        f.close()
+    m = O.model(N, L)
+    for i in range(len(Us)):
+        abc = inputs.sample_indices(N, 40, seed=100 + i)
+        ref = O.rhs_points(m, T, V[i], abc)
+        got = D[i][abc[:, 0], abc[:, 1], abc[:, 2]]
+        assert rel(got, ref) <= 1e-4, (i, rel(got, ref))
