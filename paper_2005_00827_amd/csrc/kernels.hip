@@ -1686,6 +1686,62 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
     constexpr int kPer = KP * W / kThreads;
     static_assert(KP * W % kThreads == 0, "staging covers the chunk in whole rounds");
     constexpr int kGrp = stage_group(kPer);
+    if constexpr (kM > 0) {
+        // bf16 planes [n][k']: a task is 8 consecutive k' of one column n, loaded together
+        // (each load coalesced over the wave's columns) and stored as one 16-byte row
+        // segment per plane
+        constexpr int kTasks = KP / 8 * W;
+        constexpr int kTPT = (kTasks + kThreads - 1) / kThreads;
+        constexpr int R = kTPT < 2 ? kTPT : 2;          // tasks whose loads are in flight
+        __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
+#pragma unroll 1
+        for (int j0 = 0; j0 < kTPT; j0 += R) {
+            float x0[R][8], x1[R][8];
+            int kq[R][8];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int task = min(static_cast<int>(threadIdx.x) + (j0 + j) * kThreads, kTasks - 1);
+                const int n = task % W, kb = 8 * (task / W);
+                const int nc = min(n0 + n, N - 1);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int kp = pm[min(kb + i, N - 1)];
+                    kq[j][i] = kp;
+                    x0[j][i] = V0[static_cast<size_t>(kp) * N + nc];
+                    if constexpr (kTwo) x1[j][i] = V1[static_cast<size_t>(kp) * N + nc];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int task = static_cast<int>(threadIdx.x) + (j0 + j) * kThreads;
+                if (task >= kTasks) continue;
+                const int n = task % W, kb = 8 * (task / W);
+                const bool nok = n0 + n < N;
+                fm_bf8 h0, h1, l0, l1;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int kp = kq[j][i];
+                    const float fac = (nok && kb + i < N) ? zg * zs[kp] * (al + be * (wg + zs[N + kp])) : 0.f;
+                    const float y0 = fac * x0[j][i];
+                    h0[i] = static_cast<__bf16>(y0);
+                    if constexpr (kM == 2) l0[i] = static_cast<__bf16>(y0 - static_cast<float>(h0[i]));
+                    if constexpr (kTwo) {
+                        const float y1 = fac * x1[j][i];
+                        h1[i] = static_cast<__bf16>(y1);
+                        if constexpr (kM == 2) l1[i] = static_cast<__bf16>(y1 - static_cast<float>(h1[i]));
+                    }
+                }
+                const int o = n * KBS + kb;
+                *reinterpret_cast<fm_bf8*>(Bh + o) = h0;
+                if constexpr (kM == 2) *reinterpret_cast<fm_bf8*>(Bh + W * KBS + o) = l0;
+                if constexpr (kTwo) {
+                    *reinterpret_cast<fm_bf8*>(Bh + kBytes / 2 + o) = h1;
+                    if constexpr (kM == 2) *reinterpret_cast<fm_bf8*>(Bh + kBytes / 2 + W * KBS + o) = l1;
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll 1
     for (int j0 = 0; j0 < kPer; j0 += kGrp) {
         float v0[kGrp], v1[kGrp];
