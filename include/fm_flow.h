@@ -174,6 +174,11 @@ typedef struct {
                                  nodes, clamped outside, any finite sign (it may change sign
                                  along the flow); copied.  Every flow of the handle uses it:
                                  fm_flow_run_batch then takes no per-flow Z tables. */
+    int phase1_variant;       /* launch shape of the step's phase-1 launch: 1 / 2 one stage
+                                 node per block with 256 / 1024 threads, 3 / 4 two nodes per
+                                 block (where the bins fit in LDS; else one); 0 = chosen by
+                                 timing all four on the first call (kept per shape for the
+                                 process) */
 } fm_config;
 
 typedef struct {

@@ -155,6 +155,7 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
         return FM_EINVAL;
     }
     if (c.y_kernel < 0 || c.y_kernel > 4) { why = "y_kernel must be 0 .. 4"; return FM_EINVAL; }
+    if (c.phase1_variant < 0 || c.phase1_variant > 4) { why = "phase1_variant must be 0 .. 4"; return FM_EINVAL; }
     if (c.y_kernel == 4 && !fused_phase2(c)) {
         why = "y_kernel 4 (fused phase 2) needs bf16 or split-bf16 products and N <= 128";
         return FM_EINVAL;
@@ -181,6 +182,7 @@ struct fm_flow {
     // phase-2a kernel variant and row tiles per wavefront (cfg.y_kernel, cfg.tile_rows, or
     // tuned for tuned_nf flows)
     int tpw = 0, yvar = 1, tuned_nf = -1;
+    int ph1_nf = -1;                   // flows the phase-1 launch shape was timed for
     // graphs of one integrator step, keyed by the number of flows captured and the
     // step-sharing groups (count, largest)
     hipGraphExec_t step_exec = nullptr;
@@ -412,7 +414,65 @@ using TuneKey = std::tuple<int, int, int, int, int, double, double, double, int,
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
 
+// Phase-1 launch shape (cfg.phase1_variant, or timed): the step's first stage launch, which
+// bins every node of the step, with 256- or 1024-thread blocks and one or two nodes per
+// block; the fastest of the applicable shapes on the flows' current state.  Kept for the
+// process per shape, settings, flows and step-sharing groups.
+using Tune1Key = std::tuple<int, int, int, int, int, double, double, double, int, int, int>;
+std::map<Tune1Key, int> g_tune1;
+
+int tune_phase1(fm_flow* h, int nf, const double* Vbase) {
+    const fm_config& c = h->cfg;
+    if (h->direct || !h->b.bins || h->g.gflow) return FM_OK;
+    if (c.phase1_variant != 0) { h->b.ph1var = c.phase1_variant; return FM_OK; }
+    if (h->ph1_nf == nf) return FM_OK;
+    const Tune1Key key{c.N, c.L, c.precision, nf, c.geometry, c.t, c.tp, c.mu, c.sync_batch,
+                       c.integrator, c.n_shells};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune1.find(key);
+        if (it != g_tune1.end()) {
+            h->b.ph1var = it->second;
+            h->ph1_nf = nf;
+            return FM_OK;
+        }
+    }
+    const BinPlan bp = step_plan(c.integrator == FM_RK45_DOPRI).bp;
+    const size_t rs = h->dbl ? sizeof(double) : sizeof(float);
+    const bool two = bp.n > 1 && 2 * static_cast<size_t>(h->g.NN) * rs <= 131072;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    StageCoef sc{};
+    int best = 0;
+    float best_ms = std::numeric_limits<float>::infinity();
+    for (int v = 1; v <= (two ? 4 : 2); ++v) {
+        Buffers bb = h->b;
+        bb.ph1var = v;
+        launch_stage(h->stream, h->dbl, h->g, h->z, bb, nf, sc, bp, 0, Vbase);
+        (void)hipEventRecord(e0, h->stream);
+        for (int r = 0; r < 3; ++r) launch_stage(h->stream, h->dbl, h->g, h->z, bb, nf, sc, bp, 0, Vbase);
+        (void)hipEventRecord(e1, h->stream);
+        float ms = 0.f;
+        const bool ok = hipGetLastError() == hipSuccess;   // a shape that cannot launch is skipped
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ok && ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    h->b.ph1var = best;
+    h->ph1_nf = nf;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune1[key] = best;
+    return FM_OK;
+}
+
 int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
+    if (int rc = tune_phase1(h, nf, Vbase)) return rc;
     const fm_config& c = h->cfg;
     const int mma = mma_mode(c.precision);
     if (h->dbl || h->direct || fused_phase2(c) || mma == 0 || c.N > 128) return FM_OK;

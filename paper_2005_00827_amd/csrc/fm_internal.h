@@ -210,6 +210,8 @@ struct Buffers {
     int* grp_off;                      // [B + 1] group g: members grp_off[g] .. grp_off[g+1]
     int nblk;                          // reduction blocks per flow
     int bstride;                       // flows per buffer (max_batch)
+    int ph1var;                        // phase-1 launch shape: 0 by rule, 1..4 fixed (threads
+                                       // 256 or 1024, one or two stage nodes per block)
 };
 
 // Dormand-Prince error weights (5th minus embedded 4th order).

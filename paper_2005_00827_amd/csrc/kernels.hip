@@ -2950,7 +2950,8 @@ int nodes_per_block(const DevGeom& g, const BinPlan& bp, int nRb, int nf) {
 // 256-thread blocks.
 template <typename R, int kG, int NODES>
 void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
-                 const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
+                 const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase,
+                 int wide_force) {
     const int nRb = b.bins ? g.nRp + g.nRd : 0;
     const int per_block = bp.n < NODES ? bp.n : NODES;
     // bins in LDS above 40 KB leave room for at most three blocks per CU: 256-thread blocks
@@ -2959,6 +2960,11 @@ void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& 
                      static_cast<size_t>(per_block) * g.NN * sizeof(R) > 40960;
     const long nblk = static_cast<long>(nRb) * ((bp.n + NODES - 1) / NODES) * nf;
     const bool wide = nblk <= 256 || (big && bp.n > 0);
+    if (wide_force >= 0 && bp.n > 0) {       // a fixed launch shape (timing, or the caller's)
+        if (wide_force) stage_go<R, 1024, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb);
+        else stage_go<R, 256, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb);
+        return;
+    }
     if (wide) stage_go<R, 1024, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb);
     else stage_go<R, 256, kG, NODES>(s, g, z, b, nf, sc, bp, write_new, Vbase, nRb);
 }
@@ -2967,12 +2973,21 @@ template <typename R>
 void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, int nf,
              const StageCoef& sc, const BinPlan& bp, int write_new, const double* Vbase) {
     if (g.gflow && bp.n > 0) {
-        stage_nodes<R, 1, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase);
+        stage_nodes<R, 1, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, -1);
         return;
     }
-    const int nodes = b.bins ? nodes_per_block<R>(g, bp, g.nRp + g.nRd, nf) : 1;
-    if (nodes == 2) stage_nodes<R, 0, 2>(s, g, z, b, nf, sc, bp, write_new, Vbase);
-    else stage_nodes<R, 0, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase);
+    // a fixed shape (b.ph1var 1..4: 256 or 1024 threads, one or two nodes per block) where
+    // it applies (two nodes need several nodes and two bin matrices within 128 KB of LDS),
+    // else the rule
+    const int v = b.ph1var;
+    int nodes = b.bins ? nodes_per_block<R>(g, bp, g.nRp + g.nRd, nf) : 1;
+    int wide = -1;
+    if (v >= 1 && v <= 4 && b.bins && bp.n > 0) {
+        wide = (v - 1) % 2;
+        nodes = (v >= 3 && bp.n > 1 && 2 * static_cast<size_t>(g.NN) * sizeof(R) <= 131072) ? 2 : 1;
+    }
+    if (nodes == 2) stage_nodes<R, 0, 2>(s, g, z, b, nf, sc, bp, write_new, Vbase, wide);
+    else stage_nodes<R, 0, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, wide);
 }
 
 // Matrix-core phase 2a: operand widths by patch count (KE k-values per lane, NT column

@@ -98,6 +98,7 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=16, L=32, tile_rows=-1), "tile_rows"),
     (dict(N=16, L=32, flow=2), "bad flow"),
     (dict(N=16, L=32, y_kernel=5), "y_kernel"),
+    (dict(N=16, L=32, phase1_variant=5), "phase1_variant"),
     (dict(N=16, L=32, y_kernel=4), "fused phase 2"),          # needs bf16 products
     (dict(N=136, L=128, precision="bf16x3", y_kernel=4), "N <= 128"),
     (dict(N=16, L=32, flow="interaction", T0=0.0), "T0 > 0"),

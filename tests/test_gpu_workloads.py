@@ -186,12 +186,15 @@ def test_c4_sweep_subset_against_oracle_goldens(torch_dev):
             assert abs(r32["T_c"] / r64["T_c"] - 1.0) <= 1e-3
 
 
-def test_two_nodes_per_phase1_block_against_oracle(torch_dev):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_two_nodes_per_phase1_block_against_oracle(torch_dev, variant):
     """Five flows at N = 128, L = 512 take a Dormand-Prince step of h = -1e-6 in FP32: the
     step's first stage launch bins the five stage nodes two per block (the path of the
     16-flow batch).  (V_new - V)/h is the weighted sum of the six stage derivatives, which
     differ from the derivative at the step's start by O(h) (1e-6 relative), and is compared
-    with the oracle's sums at 40 sampled outputs per flow, to the FP32 tolerance 1e-4."""
+    with the oracle's sums at 40 sampled outputs per flow, to the FP32 tolerance 1e-4.  Every
+    phase-1 launch shape (variant 1..4: 256 or 1024 threads, one or two nodes per block) and
+    the timed choice (0)."""
     fm = _fm()
     torch, dev = torch_dev
     N, L = 128, 512
@@ -199,7 +202,7 @@ def test_two_nodes_per_phase1_block_against_oracle(torch_dev):
     V = np.stack([inputs.noisy_state(N, u, seed=11 + i) for i, u in enumerate(Us)])
     T, h = 0.2, -1e-6
     f = fm.Flow(N=N, L=L, U=Us[0], precision="fp32", integrator="rk45", max_batch=len(Us),
-                device=dev)
+                phase1_variant=variant, device=dev)
     try:
         Vb = torch.from_numpy(V.copy()).to(dev)
         _, _, acc = f.step([math.log(T)] * len(Us), [h] * len(Us), Vb)
