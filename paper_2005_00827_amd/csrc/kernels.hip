@@ -2009,14 +2009,15 @@ __device__ inline void load_cols(const YT* p, R* out) {
     }
 }
 
-// One wave per work item (kind, q, first pair, count <= kChunk).  Each lane owns CW
+// One wave per work item (kind, q, first pair, count <= kChunk), with KC = 4 accumulators per
+// column for items of at most four pairs and KC = kChunk otherwise.  Each lane owns CW
 // consecutive free indices n (CW = 2 for single precision and even N > 64: one wider load per
 // Y row, and each pair value read from LDS serves two columns; at N = 128 with bf16 products
 // 2.63 -> 1.90 ms for 16 flows): its columns of Y (a group of
 // rows at a time) are loaded into registers while the item's pair vectors are gathered into
-// LDS (zero-padded to kChunk, laid out [x][pair] so one x is a 128-bit broadcast read), so
+// LDS (zero-padded to KC, laid out [x][pair] so one x is a 128-bit broadcast read), so
 // every group costs one memory round trip.
-template <typename R, typename YT, int KIND, int CW>
+template <typename R, typename YT, int KIND, int CW, int KC>
 __device__ __attribute__((always_inline)) inline void contract_item(
     const DevGeom& g, const R* V, const R* VA, const R* VC, const YT* Ya, const YT* Yb,
     const int* pairs, int cnt, R* vu, R* vw, R* Kf) {
@@ -2024,14 +2025,14 @@ __device__ __attribute__((always_inline)) inline void contract_item(
     const int N = g.N, NN = g.NN;
     // the item's output pairs, read once with the first loads (the stores at the end would
     // otherwise each wait for their pair's load)
-    int pr[kChunk];
+    int pr[KC];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) pr[i] = pairs[min(i, cnt - 1)];
+    for (int i = 0; i < KC; ++i) pr[i] = pairs[min(i, cnt - 1)];
     for (int n0 = 0; n0 < N; n0 += 64 * CW) {
         const int n = min(n0 + CW * static_cast<int>(threadIdx.x), N - CW);
-        R acc[kChunk][CW];
+        R acc[KC][CW];
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i)
+        for (int i = 0; i < KC; ++i)
 #pragma unroll
             for (int c = 0; c < CW; ++c) acc[i][c] = R(0);
         for (int xg = 0; xg < N; xg += G) {
@@ -2043,15 +2044,15 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                 if (KIND == 2) load_cols<R, YT, CW>(Yb + static_cast<size_t>(x) * N + n, yb[j]);
             }
             if (n0 == 0 && xg == 0) {
-                // gather the pair vectors while the first Y rows are in flight (kChunk * 128
+                // gather the pair vectors while the first Y rows are in flight (KC * 128
                 // values per round, kVec per lane, loaded to registers before any store; one
                 // round for N <= 128)
-                constexpr int kVec = kChunk * 128 / 64;
-                for (int e0 = 0; e0 < kChunk * N; e0 += 64 * kVec) {
+                constexpr int kVec = KC * 128 / 64;
+                for (int e0 = 0; e0 < KC * N; e0 += 64 * kVec) {
                 R av[kVec], bv[kVec];
 #pragma unroll
                 for (int v = 0; v < kVec; ++v) {
-                    const int e = min(e0 + static_cast<int>(threadIdx.x) + 64 * v, kChunk * N - 1);
+                    const int e = min(e0 + static_cast<int>(threadIdx.x) + 64 * v, KC * N - 1);
                     const int i = e / N, x = e - i * N;
                     const int xy = pairs[min(i, cnt - 1)];
                     const int u = xy / N, w = xy - u * N;
@@ -2065,17 +2066,17 @@ __device__ __attribute__((always_inline)) inline void contract_item(
 #pragma unroll
                 for (int v = 0; v < kVec; ++v) {
                     const int e = e0 + threadIdx.x + 64 * v;
-                    const int ec = min(e, kChunk * N - 1);
+                    const int ec = min(e, KC * N - 1);
                     const int i = ec / N, x = ec - i * N;
-                    const bool ok = e < kChunk * N;
+                    const bool ok = e < KC * N;
                     const bool live = i < cnt;          // padding pairs contribute zero
                     const R a = live ? av[v] : R(0), b = live ? bv[v] : R(0);
                     if (ok) {
                         if (KIND == 2) {
-                            vu[x * kChunk + i] = a - R(2) * b;
-                            vw[x * kChunk + i] = b;
+                            vu[x * KC + i] = a - R(2) * b;
+                            vw[x * KC + i] = b;
                         } else {
-                            vu[x * kChunk + i] = a;
+                            vu[x * KC + i] = a;
                         }
                     }
                 }
@@ -2087,15 +2088,15 @@ __device__ __attribute__((always_inline)) inline void contract_item(
             for (int j = 0; j < G; ++j) {
                 const int x = min(xg + j, N - 1);
                 const R mask = xg + j < N ? R(1) : R(0);
-                const R* u = vu + x * kChunk;
+                const R* u = vu + x * KC;
 #pragma unroll
-                for (int i = 0; i < kChunk; ++i)
+                for (int i = 0; i < KC; ++i)
 #pragma unroll
                     for (int c = 0; c < CW; ++c) acc[i][c] += u[i] * (mask * ya[j][c]);
                 if (KIND == 2) {
-                    const R* w = vw + x * kChunk;
+                    const R* w = vw + x * KC;
 #pragma unroll
-                    for (int i = 0; i < kChunk; ++i)
+                    for (int i = 0; i < KC; ++i)
 #pragma unroll
                         for (int c = 0; c < CW; ++c) acc[i][c] += w[i] * (mask * yb[j][c]);
                 }
@@ -2103,7 +2104,7 @@ __device__ __attribute__((always_inline)) inline void contract_item(
         }
         if (n0 + CW * static_cast<int>(threadIdx.x) >= N) continue;
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) {   // every part at (pair) N + n: contiguous in n
+        for (int i = 0; i < KC; ++i) {   // every part at (pair) N + n: contiguous in n
             if (i >= cnt) break;
 #pragma unroll
             for (int c = 0; c < CW; ++c)
@@ -2150,15 +2151,29 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
     // two columns per lane where one per lane would take more than one pass over the row
     // (N > 64; at N = 48 two per lane leave 40 of 64 lanes idle: 11.6 -> 13.5 us measured)
+    // items of at most four pairs (most transfers have four) carry four accumulators per
+    // column instead of eight, half of them padding
     if (sizeof(R) == 4 && (N & 1) == 0 && N > 64) {
-        if (kind == 0) contract_item<R, YT, 0, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-        else if (kind == 1) contract_item<R, YT, 1, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-        else contract_item<R, YT, 2, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        if (cnt <= 4) {
+            if (kind == 0) contract_item<R, YT, 0, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+            else if (kind == 1) contract_item<R, YT, 1, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+            else contract_item<R, YT, 2, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+            return;
+        }
+        if (kind == 0) contract_item<R, YT, 0, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        else if (kind == 1) contract_item<R, YT, 1, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        else contract_item<R, YT, 2, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
         return;
     }
-    if (kind == 0) contract_item<R, YT, 0, 1>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-    else if (kind == 1) contract_item<R, YT, 1, 1>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-    else contract_item<R, YT, 2, 1>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    if (cnt <= 4) {
+        if (kind == 0) contract_item<R, YT, 0, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        else if (kind == 1) contract_item<R, YT, 1, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        else contract_item<R, YT, 2, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        return;
+    }
+    if (kind == 0) contract_item<R, YT, 0, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    else if (kind == 1) contract_item<R, YT, 1, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    else contract_item<R, YT, 2, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
 }
 
 // ------------------------------------------------------------------------------------
