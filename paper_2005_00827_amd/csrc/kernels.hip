@@ -2083,22 +2083,41 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                 }
                 __syncthreads();
             }
-            // rows past N repeat row N-1 (clamped loads) and are weighted by zero
+            // rows past N repeat row N-1 (clamped loads) and are weighted by zero; a group
+            // wholly below N needs no weights
+            if (xg + G <= N) {
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int x = min(xg + j, N - 1);
-                const R mask = xg + j < N ? R(1) : R(0);
-                const R* u = vu + x * KC;
-#pragma unroll
-                for (int i = 0; i < KC; ++i)
-#pragma unroll
-                    for (int c = 0; c < CW; ++c) acc[i][c] += u[i] * (mask * ya[j][c]);
-                if (KIND == 2) {
-                    const R* w = vw + x * KC;
+                for (int j = 0; j < G; ++j) {
+                    const R* u = vu + (xg + j) * KC;
 #pragma unroll
                     for (int i = 0; i < KC; ++i)
 #pragma unroll
-                        for (int c = 0; c < CW; ++c) acc[i][c] += w[i] * (mask * yb[j][c]);
+                        for (int c = 0; c < CW; ++c) acc[i][c] += u[i] * ya[j][c];
+                    if (KIND == 2) {
+                        const R* w = vw + (xg + j) * KC;
+#pragma unroll
+                        for (int i = 0; i < KC; ++i)
+#pragma unroll
+                            for (int c = 0; c < CW; ++c) acc[i][c] += w[i] * yb[j][c];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int x = min(xg + j, N - 1);
+                    const R mask = xg + j < N ? R(1) : R(0);
+                    const R* u = vu + x * KC;
+#pragma unroll
+                    for (int i = 0; i < KC; ++i)
+#pragma unroll
+                        for (int c = 0; c < CW; ++c) acc[i][c] += u[i] * (mask * ya[j][c]);
+                    if (KIND == 2) {
+                        const R* w = vw + x * KC;
+#pragma unroll
+                        for (int i = 0; i < KC; ++i)
+#pragma unroll
+                            for (int c = 0; c < CW; ++c) acc[i][c] += w[i] * (mask * yb[j][c]);
+                    }
                 }
             }
         }
