@@ -439,7 +439,7 @@ int tune_phase1(fm_flow* h, int nf, const double* Vbase) {
     }
     const BinPlan bp = step_plan(c.integrator == FM_RK45_DOPRI).bp;
     const size_t rs = h->dbl ? sizeof(double) : sizeof(float);
-    const bool two = bp.n > 1 && 2 * static_cast<size_t>(h->g.NN) * rs <= 131072;
+    const bool two = bp.n > 1 && 2 * bins_lds_bytes(h->g.N, rs) <= static_cast<size_t>(h->g.lds_max);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -706,6 +706,16 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.pI = h->b.pI;
     g.inv_ok = hg.inv_ok ? 1 : 0;
     g.gflow = c.flow == FM_FLOW_INTERACTION ? 1 : 0;
+    {
+        int dev = 0, lds = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(FM_EDEVICE, std::string("device query: ") + hipGetErrorString(e));
+        }
+        g.lds_max = lds;
+    }
     g.inv_rot = 0;
     if (hg.inv_ok && N % 2 == 0) {
         g.inv_rot = 1;

@@ -126,6 +126,7 @@ struct DevGeom {
     int inv_ok;            // pI is valid (k -> -k maps patches and dispersion onto themselves)
     int inv_rot;           // pI[a] = (a + N/2) mod N
     int gflow;             // interaction flow: bins of chi instead of T d/dT chi
+    int lds_max;           // LDS bytes one work group may allocate on the device
     const int* pp_off; const int* pp_pairs;
     const int* cr_off; const int* cr_pairs;
     const int* d_off;  const int* d_pairs;
@@ -145,6 +146,9 @@ struct DevGeom {
     const int* map_cr;     // [NN]
     const int* map_d;      // [NN]
 };
+
+// LDS bytes of one phase-1 bin matrix held by a work group: N rows of stride N + 1 (R values).
+inline size_t bins_lds_bytes(int N, size_t rs) { return static_cast<size_t>(N) * (N + 1) * rs; }
 
 // Per-flow Z tables, and the Katanin factors on the same nodes (interaction flow).
 struct DevZ {

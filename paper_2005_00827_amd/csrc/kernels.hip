@@ -421,24 +421,29 @@ __device__ inline float4 flip(float4 v) { return make_float4(-v.x, -v.y, v.z, v.
 __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 
 // Single-precision weight of one loop-point pair for phase 1, straight from xi: the same
-// values as phi_dd_pt(point_q(.), point_q(.)), with tanh entering only as |a| tanh|a| and
-// tanh^2 (no sign), and phi', phi3 and the trapezoid evaluated only when a lane of the
-// wave has |a - b| < 0.05 (the branch is uniform over the wave).
-__device__ inline float pair_weight(float xu, float xv, float inv2T, bool pp) {
-    const float a = xu * inv2T;
-    const float b0 = xv * inv2T;
-    const float b = pp ? -b0 : b0;
-    const float aa = fabsf(a), ab = fabsf(b);
-    const float ea = __expf(-2.0f * aa), eb = __expf(-2.0f * ab);
-    const float ra = __builtin_amdgcn_rcpf(1.0f + ea), rb = __builtin_amdgcn_rcpf(1.0f + eb);
-    const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;   // sech^2
+// quantity as phi_dd_pt(point_q(.), point_q(.)).  With e = exp(-2|x|), p = 1 + e and
+// sech^2 x = 4e/p^2, the quotient away from the diagonal is
+//   phi[a,b] = (a s_a - b s_b)/(a - b) = 4 (a e_a p_b^2 - b e_b p_a^2) / ((a - b) p_a^2 p_b^2)
+// (p in [1, 2]: one reciprocal instead of three).  Arguments: tp = 1/2T, tq = 1/2T, or -1/2T
+// for particle-particle (b = -xv/2T), and ce = -log2(e)/T, so that e_a = exp2(ce |xu|).
+// phi', phi3 and the trapezoid are evaluated only when a lane of the wave has |a - b| < 0.05
+// (the branch is uniform over the wave), with tanh entering only as |a| tanh|a| and tanh^2.
+__device__ inline float pair_weight(float xu, float xv, float tp, float tq, float ce) {
+    const float a = xu * tp, b = xv * tq;
+    const float ea = __builtin_amdgcn_exp2f(ce * fabsf(xu));
+    const float eb = __builtin_amdgcn_exp2f(ce * fabsf(xv));
+    const float pa = 1.0f + ea, pb = 1.0f + eb;
+    const float pa2 = pa * pa, pb2 = pb * pb;
     const float d = a - b;
-    float w = (a * sa - b * sb) * __builtin_amdgcn_rcpf(d);
+    const float num = (a * ea) * pb2 - (b * eb) * pa2;
+    float w = 4.0f * num * __builtin_amdgcn_rcpf(d * pa2 * pb2);
     const bool near = fabsf(d) < 0.05f;
     if (__ballot(near)) {
         if (near) {
-            const float ta = (1.0f - ea) * ra, tb = (1.0f - eb) * rb;     // tanh|a|, tanh|b|
-            const float xa = aa * ta, xb = ab * tb, qa = ta * ta, qb = tb * tb;
+            const float ra = __builtin_amdgcn_rcpf(pa), rb = __builtin_amdgcn_rcpf(pb);
+            const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;   // sech^2
+            const float ta = (1.0f - ea) * ra, tb = (1.0f - eb) * rb;         // tanh|a|, tanh|b|
+            const float xa = fabsf(a) * ta, xb = fabsf(b) * tb, qa = ta * ta, qb = tb * tb;
             const float d1 = sa * (1.0f - 2.0f * xa) + sb * (1.0f - 2.0f * xb);
             const float d3 = sa * (-6.0f * (1.0f - 3.0f * qa) + 8.0f * xa * (2.0f - 3.0f * qa)) +
                              sb * (-6.0f * (1.0f - 3.0f * qb) + 8.0f * xb * (2.0f - 3.0f * qb));
@@ -590,7 +595,11 @@ __device__ inline int run_start(int key, int s) {
 // pair is visited in full; in a row that s fixes (two when c - 1 is even) the columns pair
 // up the same way and one column of each pair is visited; the at most four points that s
 // fixes are their own pair and are added once, at the end.  Without the inversion symmetry
-// the particle-hole sum visits every point once.
+// the particle-hole sum visits every point once.  With the bins in LDS a pair is added under
+// its first key only, and the second key's share is taken when the block stores its bins:
+// the map of keys k = (a, b) -> k' = (b, a) (particle-particle) or (P b, P a) (particle-hole)
+// is an involution, so bin k is the LDS sum at k plus that at k'; a point that s fixes has
+// k' = k and adds half its weight.
 struct Half {
     int h1, h2, nfix, c;   // [0, h1) and [c + 1, c + 1 + h2) are one side; fixed c/2, c/2 + L/2
 };
@@ -622,17 +631,22 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
                                  R* lb) {
     static_assert(kMode == 0 || NODES == 1, "several nodes per block need the LDS bins");
     const int N = g.N, NN = g.NN, L = g.L, np = g.np;
+    // LDS bin rows have stride N + 1, so the column walks of the store fall on distinct banks
+    const int S = kMode == 0 ? N + 1 : N, NS = kMode == 0 ? N * (N + 1) : NN;
     const int nR = g.nRp + g.nRd;
     const bool pp = r < g.nRp;
     const int m = pp ? g.rep_pp[r] : g.rep_ph[r - g.nRp];
     const int mx = m % L, my = m / L;
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
     R scale[NODES], tp[NODES];
+    float tq[NODES], ce[NODES];                        // single-precision weight: +-1/2T, -log2(e)/T
 #pragma unroll
     for (int j = 0; j < NODES; ++j) {
         const double Tj = T[j];
         scale[j] = static_cast<R>((kG ? 1.0 : -1.0) / (4.0 * Tj * np));
         tp[j] = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * Tj) : 2.0 * Tj);   // 1/2T or 2T
+        tq[j] = static_cast<float>((pp ? -1.0 : 1.0) / (2.0 * Tj));
+        ce[j] = static_cast<float>(-1.4426950408889634 / Tj);
     }
     constexpr int kBinBatch = BinBatch<R>::v;
     const bool half = (pp || g.inv_ok) && L % 2 == 0;
@@ -641,8 +655,8 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
     const int ncol = hx.h1 + hx.h2;                        // columns visited in a fixed row
     const int npt = nrow * L + (half ? hy.nfix * ncol : 0);
     const float invL = 1.0f / static_cast<float>(L);
-    R* acc = kMode == 0 ? lb : out;                   // node j: acc + j NN (LDS)
-    for (int i = threadIdx.x; i < nn * NN; i += blockDim.x) acc[i] = R(0);
+    R* acc = kMode == 0 ? lb : out;                   // node j: acc + j NS
+    for (int i = threadIdx.x; i < nn * NS; i += blockDim.x) acc[i] = R(0);
     if (kMode == 1) __threadfence();
     __syncthreads();                                   // every thread of the block
     // BT/16 rows of 16 lanes per block; row rr works on band rr of BT/16 contiguous bands of
@@ -652,22 +666,23 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
     const int s = lane & 15;
     const int band = (lane >> 4) * (BT / 64) + wv;
     // Weights of one batch (kBinBatch points per lane), the segmented scan of equal keys
-    // within each 16-lane row, and one atomic per run of equal keys (two under the pairing).
+    // within each 16-lane row, and one atomic per run of equal keys (global bins: two under
+    // the pairing).
     auto weight = [&](R xa, R xb, int j) -> R {
-        return kG ? pair_chi(xa, xb, tp[j], pp) : pair_weight(xa, xb, tp[j], pp);
+        if constexpr (kG) return pair_chi(xa, xb, tp[j], pp);
+        else if constexpr (sizeof(R) == 4) return pair_weight(xa, xb, tp[j], tq[j], ce[j]);
+        else return pair_weight(xa, xb, tp[j], pp);
     };
     auto add_batch = [&](const R (&xu)[kBinBatch], const R (&xv)[kBinBatch],
                          const int (&pa)[kBinBatch], const int (&pq)[kBinBatch],
                          const bool (&ok)[kBinBatch]) {
 #pragma unroll
         for (int i = 0; i < kBinBatch; ++i) {
-            // keys < N^2 (24-bit products)
-            const int key = static_cast<int>(__umul24(pa[i], N)) + pq[i];
-            const int key2 = pp ? static_cast<int>(__umul24(pq[i], N)) + pa[i]
-                                : static_cast<int>(__umul24(inv_patch(g, pq[i]), N)) + inv_patch(g, pa[i]);
+            // keys < N (N + 1) (24-bit products)
+            const int key = static_cast<int>(__umul24(pa[i], S)) + pq[i];
             const int knext = dpp_i<0x101>(key);   // row_shl:1
             const int st = run_start(key, s);
-            const bool end = s == 15 || knext != key;   // key2 is a bijective function of key
+            const bool end = s == 15 || knext != key;
 #pragma unroll
             for (int j = 0; j < NODES; ++j) {
                 if (j >= nn) break;                    // uniform over the block
@@ -678,9 +693,16 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
                 seg_step<4>(x, st, s);
                 seg_step<8>(x, st, s);
                 if (end) {
-                    R* aj = acc + j * NN;
+                    R* aj = acc + j * NS;
                     atomicAdd(&aj[key], x);
-                    if (half) atomicAdd(&aj[key2], x);
+                    if constexpr (kMode == 1) {        // the second key (bijective in the first)
+                        if (half) {
+                            const int key2 = pp ? static_cast<int>(__umul24(pq[i], N)) + pa[i]
+                                                : static_cast<int>(__umul24(inv_patch(g, pq[i]), N)) +
+                                                      inv_patch(g, pa[i]);
+                            atomicAdd(&aj[key2], x);
+                        }
+                    }
                 }
             }
         }
@@ -784,14 +806,14 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
                 int qa, qb;
                 xi_patch(g, jy * L + jx, xa, qa);
                 xi_patch(g, py * L + px, xb, qb);
-                const int k1 = qa * N + qb, k2 = pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa);
+                const int k1 = qa * S + qb, k2 = pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa);
 #pragma unroll
                 for (int j = 0; j < NODES; ++j) {
                     if (j >= nn) break;                // uniform over the block
                     const R w = weight(xa, xb, j);
                     const R x = kMode == 0 ? w : w * scale[j];
-                    atomicAdd(&acc[j * NN + k1], x);
-                    atomicAdd(&acc[j * NN + k2], x);
+                    atomicAdd(&acc[j * NS + k1], x);
+                    if constexpr (kMode == 1) atomicAdd(&acc[k2], x);
                 }
             }
     } else {
@@ -822,7 +844,8 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
             add_batch(xu, xv, pa, pq, ok);
         }
     }
-    // points fixed by s: their own pair, added once
+    // points fixed by s: their own pair, added once (in LDS half of it, at a key that is its
+    // own second key)
     if (half && static_cast<int>(threadIdx.x) < hy.nfix * hx.nfix) {
         const int jy = half_fix(hy, threadIdx.x >> 1, L), jx = half_fix(hx, threadIdx.x & 1, L);
         int px = pp ? mx - jx - 1 : jx + mx;
@@ -837,7 +860,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
         for (int j = 0; j < NODES; ++j) {
             if (j >= nn) break;                        // uniform over the block
             const R w = weight(xa, xb, j);
-            atomicAdd(&acc[j * NN + qa * N + qb], kMode == 0 ? w : w * scale[j]);
+            atomicAdd(&acc[j * NS + qa * S + qb], kMode == 0 ? R(0.5) * w : w * scale[j]);
         }
     }
     if (kMode == 1) __threadfence();
@@ -848,26 +871,20 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
         if (j >= nn) break;                            // uniform over the block
         R* oj = out + j * set_bins;
         R* oTj = outT ? outT + j * set_binsT : nullptr;
-        const R* lj = lb + j * NN;
-        if (kMode == 0 && oTj && N % 16 == 0) {
-            // the transpose in chunks of 16 rows x 4 columns of outT per wave: LDS reads of 4
-            // bin rows x 16 consecutive values (a column walk of stride N would put a whole
-            // wave on one bank when N is a multiple of 32), 16-byte or wider segments written
-            const int ng = N >> 2;
+        if constexpr (kMode == 0) {
+            // bin (a, b) = L(a, b) + L(k'(a, b)) under the pairing, with k'(a, b) = (b, a) or
+            // (P b, P a), and the particle-hole transpose T(a, b) = bin (b, a); every LDS
+            // read walks a row or a column (stride N + 1), every store a row
+            const R* lj = lb + j * NS;
             for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-                oj[i] = lj[i] * scale[j];
-                const int c = i >> 6, l = i & 63;
-                const int bg = c / ng, aa = ((c - bg * ng) << 2) + (l & 3), bb = (bg << 4) + (l >> 2);
-                oTj[bb * N + aa] = lj[aa * N + bb] * scale[j];
+                const int a = i / N, b = i - a * N;
+                const int pa = pp ? a : inv_patch(g, a), pb = pp ? b : inv_patch(g, b);
+                oj[i] = (lj[a * S + b] + (half ? lj[pb * S + pa] : R(0))) * scale[j];
+                if (oTj) oTj[i] = (lj[b * S + a] + (half ? lj[pa * S + pb] : R(0))) * scale[j];
             }
-            continue;
-        }
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            const int bb = i / N, aa = i - bb * N;
-            if (kMode == 0) {
-                oj[i] = lj[i] * scale[j];
-                if (oTj) oTj[i] = lj[aa * N + bb] * scale[j];
-            } else if (oTj) {
+        } else if (oTj) {
+            for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+                const int bb = i / N, aa = i - bb * N;
                 oTj[i] = oj[aa * N + bb];
             }
         }
@@ -2919,8 +2936,8 @@ R* kslot_ptr(const Buffers& b, int slot, size_t N3) {   // slot base: [flow][cha
 
 template <typename R>
 int bins_mode(const DevGeom& g) {
-    // a gfx950 CU has 160 KB of LDS, and one work group may take up to 128 KB of it here
-    return static_cast<size_t>(g.NN) * sizeof(R) <= 131072 ? 0 : 1;
+    // LDS bins where one padded bin matrix fits in a work group's LDS (160 KB on gfx950)
+    return bins_lds_bytes(g.N, sizeof(R)) <= static_cast<size_t>(g.lds_max) ? 0 : 1;
 }
 
 // Stage argument plus, when the plan has nodes, their phase 1 in one launch.
@@ -2932,7 +2949,7 @@ void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, 
     const int nbin = nRb * ((bp.n + NODES - 1) / NODES);
     const bool lds = nbin > 0 && bins_mode<R>(g) == 0;
     const int per_block = bp.n < NODES ? bp.n : NODES;   // bin matrices a block holds
-    const size_t shm_bins = lds ? static_cast<size_t>(per_block) * g.NN * sizeof(R) : 0;
+    const size_t shm_bins = lds ? per_block * bins_lds_bytes(g.N, sizeof(R)) : 0;
     // stage tiles 16 x 16 x 16 (64-byte runs in all three layouts) where they give about one
     // block per CU or more and do not raise the LDS of phase-1 blocks, else 8 x 8 x 16
     // (measured: 16 wide for one flow at N = 48, 27 tiles, is 25% slower than 8 wide)
@@ -2967,16 +2984,16 @@ void stage_go(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, 
 }
 
 // Stage nodes one phase-1 block bins together: two where a node's LDS bins exceed 40 KB
-// (single-node blocks are then limited by LDS to two per CU anyway) and two fit in 128 KB,
+// (single-node blocks are then limited by LDS to two per CU anyway) and two fit in LDS,
 // given many (representative, flow) pairs; else one.  Measured: two nodes per block at
 // N = 128 save 5% of phase 1; five per block at N = 48 (more blocks per CU without them)
 // cost 27-33%.
 template <typename R>
 int nodes_per_block(const DevGeom& g, const BinPlan& bp, int nRb, int nf) {
-    const size_t per = static_cast<size_t>(g.NN) * sizeof(R);
+    const size_t per = bins_lds_bytes(g.N, sizeof(R));
     if (g.gflow || bp.n <= 1 || bins_mode<R>(g) != 0) return 1;
     if (static_cast<long>(nRb) * nf < 4096) return 1;
-    return per > 40960 && 2 * per <= 131072 ? 2 : 1;
+    return per > 40960 && 2 * per <= static_cast<size_t>(g.lds_max) ? 2 : 1;
 }
 
 // Stage argument plus the plan's phase 1 in one launch (without phase 1: k_stage).  Few
@@ -2991,7 +3008,7 @@ void stage_nodes(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& 
     // bins in LDS above 40 KB leave room for at most three blocks per CU: 256-thread blocks
     // would keep three waves or fewer per SIMD to hide the scan's dependent steps
     const bool big = nRb > 0 && bins_mode<R>(g) == 0 &&
-                     static_cast<size_t>(per_block) * g.NN * sizeof(R) > 40960;
+                     per_block * bins_lds_bytes(g.N, sizeof(R)) > 40960;
     const long nblk = static_cast<long>(nRb) * ((bp.n + NODES - 1) / NODES) * nf;
     const bool wide = nblk <= 256 || (big && bp.n > 0);
     if (wide_force >= 0 && bp.n > 0) {       // a fixed launch shape (timing, or the caller's)
@@ -3011,14 +3028,14 @@ void stage_t(hipStream_t s, const DevGeom& g, const DevZ& z, const Buffers& b, i
         return;
     }
     // a fixed shape (b.ph1var 1..4: 256 or 1024 threads, one or two nodes per block) where
-    // it applies (two nodes need several nodes and two bin matrices within 128 KB of LDS),
+    // it applies (two nodes need several nodes and two bin matrices within the LDS),
     // else the rule
     const int v = b.ph1var;
     int nodes = b.bins ? nodes_per_block<R>(g, bp, g.nRp + g.nRd, nf) : 1;
     int wide = -1;
     if (v >= 1 && v <= 4 && b.bins && bp.n > 0) {
         wide = (v - 1) % 2;
-        nodes = (v >= 3 && bp.n > 1 && 2 * static_cast<size_t>(g.NN) * sizeof(R) <= 131072) ? 2 : 1;
+        nodes = (v >= 3 && bp.n > 1 && 2 * bins_lds_bytes(g.N, sizeof(R)) <= static_cast<size_t>(g.lds_max)) ? 2 : 1;
     }
     if (nodes == 2) stage_nodes<R, 0, 2>(s, g, z, b, nf, sc, bp, write_new, Vbase, wide);
     else stage_nodes<R, 0, 1>(s, g, z, b, nf, sc, bp, write_new, Vbase, wide);
