@@ -713,7 +713,92 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
         px += px < 0 ? L : (px >= L ? -L : 0);
         py += py < 0 ? L : (py >= L ? -L : 0);
     };
-    if (L % 16 == 0) {
+    // the rows the pairing fixes (at most two): one column of each column pair, few points,
+    // one atomic per key
+    auto fixed_rows = [&]() {
+        for (int t = threadIdx.x; t < hy.nfix * ncol; t += BT) {
+            const int fr = t >= ncol ? 1 : 0;
+            const int jx = half_map(hx, t - fr * ncol), jy = half_fix(hy, fr, L);
+            int px, py;
+            partner(jx, jy, px, py);
+            R xa, xb;
+            int qa, qb;
+            xi_patch(g, jy * L + jx, xa, qa);
+            xi_patch(g, py * L + px, xb, qb);
+            const int k1 = qa * S + qb, k2 = pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa);
+#pragma unroll
+            for (int j = 0; j < NODES; ++j) {
+                if (j >= nn) break;                    // uniform over the block
+                const R w = weight(xa, xb, j);
+                const R x = kMode == 0 ? w : w * scale[j];
+                atomicAdd(&acc[j * NS + k1], x);
+                if constexpr (kMode == 1) atomicAdd(&acc[k2], x);
+            }
+        }
+    };
+    if constexpr (kMode == 0) {
+        // Column walks (bins in LDS): a lane takes one grid column -- consecutive lanes take
+        // consecutive columns, so the loads of a row are contiguous over the wave -- and one
+        // segment of the visited rows, and walks down it keeping each node's sum over the
+        // current run of equal keys in a register.  The sum goes to LDS when the key changes
+        // (along a column only where the point or its partner crosses a patch boundary) and
+        // at the segment's end: no scan across lanes, one atomic per run.
+        const int nseg = BT > L ? BT / L : 1;
+        const int seglen = (nrow + nseg - 1) / nseg;
+        for (int it = threadIdx.x; it < L * nseg; it += BT) {
+            const int jx = it % L, sg = it / L;
+            const int r0 = sg * seglen, r1 = min(r0 + seglen, nrow);
+            int px = pp ? mx - jx - 1 : jx + mx;
+            px += px < 0 ? L : (px >= L ? -L : 0);
+            int prev = -1;                             // key of the current run (none yet)
+            R run[NODES];
+#pragma unroll
+            for (int j = 0; j < NODES; ++j) run[j] = R(0);
+            for (int rb = r0; rb < r1; rb += kBinBatch) {   // uniform over the wave
+                R xu[kBinBatch], xv[kBinBatch];
+                int ka[kBinBatch];
+#pragma unroll
+                for (int i = 0; i < kBinBatch; ++i) {
+                    const int rr = min(rb + i, r1 - 1);
+                    const int jy = half ? half_map(hy, rr) : rr;
+                    int py = pp ? my - jy - 1 : jy + my;
+                    py += py < 0 ? L : (py >= L ? -L : 0);
+                    int qa, qb;
+                    xi_patch(g, static_cast<int>(__umul24(jy, L)) + jx, xu[i], qa);
+                    xi_patch(g, static_cast<int>(__umul24(py, L)) + px, xv[i], qb);
+                    ka[i] = static_cast<int>(__umul24(qa, S)) + qb;
+                }
+#pragma unroll
+                for (int i = 0; i < kBinBatch; ++i) {
+                    const bool ok = rb + i < r1;
+                    const int key = ok ? ka[i] : prev;
+                    const bool chg = key != prev;
+                    if (chg && prev >= 0) {
+#pragma unroll
+                        for (int j = 0; j < NODES; ++j) {
+                            if (j >= nn) break;        // uniform over the block
+                            atomicAdd(&acc[j * NS + prev], run[j]);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NODES; ++j) {
+                        if (j >= nn) break;            // uniform over the block
+                        const R w = weight(xu[i], xv[i], j);
+                        run[j] = (chg ? R(0) : run[j]) + (ok ? w : R(0));
+                    }
+                    prev = key;
+                }
+            }
+            if (prev >= 0) {
+#pragma unroll
+                for (int j = 0; j < NODES; ++j) {
+                    if (j >= nn) break;                // uniform over the block
+                    atomicAdd(&acc[j * NS + prev], run[j]);
+                }
+            }
+        }
+        if (half) fixed_rows();
+    } else if (L % 16 == 0) {
         // The visited rows in full: a 16-point unit never crosses a grid row, so the row is
         // found once per unit and the column is the lane's offset.  The loop is specialised
         // per kind: a particle-particle partner coordinate m - j - 1 can only fall below 0,
@@ -794,28 +879,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
         };
         if (pp) main_rows(std::true_type{});
         else main_rows(std::false_type{});
-        // the rows the pairing fixes (at most two): one column of each column pair, few
-        // points, one atomic per key
-        if (half)
-            for (int t = threadIdx.x; t < hy.nfix * ncol; t += BT) {
-                const int fr = t >= ncol ? 1 : 0;
-                const int jx = half_map(hx, t - fr * ncol), jy = half_fix(hy, fr, L);
-                int px, py;
-                partner(jx, jy, px, py);
-                R xa, xb;
-                int qa, qb;
-                xi_patch(g, jy * L + jx, xa, qa);
-                xi_patch(g, py * L + px, xb, qb);
-                const int k1 = qa * S + qb, k2 = pp ? qb * N + qa : inv_patch(g, qb) * N + inv_patch(g, qa);
-#pragma unroll
-                for (int j = 0; j < NODES; ++j) {
-                    if (j >= nn) break;                // uniform over the block
-                    const R w = weight(xa, xb, j);
-                    const R x = kMode == 0 ? w : w * scale[j];
-                    atomicAdd(&acc[j * NS + k1], x);
-                    if constexpr (kMode == 1) atomicAdd(&acc[k2], x);
-                }
-            }
+        if (half) fixed_rows();
     } else {
         // any L: visited rows and fixed rows as one numbered list of points
         const int nunits = (npt + 15) / 16;
