@@ -179,6 +179,22 @@ typedef struct {
                                  block (where the bins fit in LDS; else one); 0 = chosen by
                                  timing all four on the first call (kept per shape for the
                                  process) */
+    int sym_state;            /* 1: the caller's states are invariant under the square
+                                 lattice's point group: V(pi a, pi b, pi c) = V(a, b, c) for
+                                 the patch permutation pi of each of its 8 operations, and
+                                 every Z and K table row too (Z_{pi a} = Z_a).  The flow
+                                 equation keeps that symmetry (as from V = U), and a transfer
+                                 q = o(r) then has the products Y_q[g][n] = Y_r[pi^-1 g]
+                                 [pi^-1 n] of its orbit representative r: phase 2 computes the
+                                 representatives' products only and the contraction reads them
+                                 through the permutations.  Same results for such states; for
+                                 a state without the symmetry they are wrong.  Needs the
+                                 geometry's point-group symmetry (fm_geometry_query: n_rep
+                                 below the transfer counts), a phase 2 with product buffers
+                                 (not FM_FP64_DIRECT, y_kernel 0 or 3: the orbit kernel) and
+                                 symmetric Z and K tables (checked to 1e-12 relative, also
+                                 per-flow tables of fm_flow_run_batch); FM_EINVAL otherwise.
+                                 0: no assumption. */
 } fm_config;
 
 typedef struct {

@@ -110,9 +110,45 @@ struct Layout {
 // y_kernel 4 asks for it alone (and the workspace then holds no product buffers), y_kernel 0
 // lets the tuner choose between it and the two-kernel path by timing.
 bool fusable(const fm_config& c) {
-    return (c.precision == FM_FP32_BF16MFMA || c.precision == FM_FP32_BF16X3) && c.N <= 128;
+    return (c.precision == FM_FP32_BF16MFMA || c.precision == FM_FP32_BF16X3) && c.N <= 128 &&
+           !c.sym_state;
+}
+
+// Rows of a [n][N] table that are invariant under the point group's patch permutations
+// (perm: [8][N]), to 1e-12 relative.
+bool rows_symmetric(const std::vector<int>& perm, const double* tab, int n, int N) {
+    for (int i = 0; i < n; ++i) {
+        const double* t = tab + static_cast<size_t>(i) * N;
+        for (int o = 1; o < 8; ++o)
+            for (int a = 0; a < N; ++a) {
+                const double x = t[a], y = t[perm[static_cast<size_t>(o) * N + a]];
+                if (!(std::fabs(x - y) <= 1e-12 * std::max(1.0, std::fabs(x)))) return false;
+            }
+    }
+    return true;
 }
 bool fused_phase2(const fm_config& c) { return fusable(c) && c.y_kernel == 4; }
+
+// sym_state: the geometry is invariant under the point group, and the representatives' own
+// transfers (operation 0) lead each kind's transfer list in representative order (transfer r
+// holds representative r's products); the configured Z and K tables are invariant too.
+bool sym_ok(const fm_config& c, const HostGeometry& hg, std::string& why) {
+    if (!c.sym_state) return true;
+    bool lead = hg.sym;
+    for (int k = 0; k < 2 && lead; ++k) {
+        const std::vector<int>& qr = k == 0 ? hg.qrep_pp : hg.qrep_ph;
+        const std::vector<int>& qg = k == 0 ? hg.qg_pp : hg.qg_ph;
+        const size_t nr = k == 0 ? hg.rep_pp.size() : hg.rep_ph.size();
+        for (size_t r = 0; r < nr && lead; ++r) lead = qr[r] == static_cast<int>(r) && qg[r] == 0;
+    }
+    if (!lead) { why = "sym_state needs a geometry invariant under the point group"; return false; }
+    if (c.n_zT > 0 && (!rows_symmetric(hg.perm, c.z_table, c.n_zT, c.N) ||
+                       (c.k_table && !rows_symmetric(hg.perm, c.k_table, c.n_zT, c.N)))) {
+        why = "sym_state needs Z and K tables invariant under the point group";
+        return false;
+    }
+    return true;
+}
 
 int resolve(const fm_config* in, fm_config& c, std::string& why) {
     if (!in) { why = "null config"; return FM_EINVAL; }
@@ -161,6 +197,11 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
         return FM_EINVAL;
     }
     if (c.sync_batch < 0) { why = "sync_batch must be >= 0"; return FM_EINVAL; }
+    if (c.sym_state != 0 && c.sym_state != 1) { why = "sym_state must be 0 or 1"; return FM_EINVAL; }
+    if (c.sym_state && (c.precision == FM_FP64_DIRECT || (c.y_kernel != 0 && c.y_kernel != 3))) {
+        why = "sym_state needs product buffers from the orbit kernel (not FM_FP64_DIRECT, y_kernel 0 or 3)";
+        return FM_EINVAL;
+    }
     return FM_OK;
 }
 
@@ -410,7 +451,7 @@ void stage_launch(fm_flow* h, int nf, const StageCoef& sc, const BinPlan& bp, in
 // which cuts the bins' re-reads where they dominate the traffic.
 // Every later stage recomputes these products, so the timing runs change no result.
 // Choices are kept for the process, per shape, settings and number of flows.
-using TuneKey = std::tuple<int, int, int, int, int, double, double, double, int, int>;
+using TuneKey = std::tuple<int, int, int, int, int, double, double, double, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
 
@@ -479,6 +520,7 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     std::vector<std::pair<int, int>> cand;    // (variant, tiles per wavefront)
     for (int var = 1; var <= 3; ++var) {
         if (c.y_kernel != 0 && var != c.y_kernel) continue;
+        if (c.sym_state && var != 3) continue;        // representatives' products: the orbit kernel
         if (c.tile_rows > 0) { cand.emplace_back(var, c.tile_rows); continue; }
         const int maxt = var == 3 ? y_orb_max_tpw(h->g, mma)
                          : var == 2 ? y_max_tpw(h->g) : y_rows_max_tpw(h->g);
@@ -488,7 +530,7 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     if (cand.size() == 1) { h->yvar = cand[0].first; h->tpw = cand[0].second; return FM_OK; }
     if (h->tuned_nf == nf) return FM_OK;
     const TuneKey key{c.N, c.L, c.precision, nf, c.geometry, c.t, c.tp, c.mu, c.y_kernel,
-                      c.tile_rows};
+                      c.tile_rows, c.n_shells, c.sym_state};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -650,6 +692,7 @@ int fm_flow_workspace_bytes(const fm_config* in, size_t* bytes) {
     if (!bytes) return fail(FM_EINVAL, "null bytes");
     HostGeometry g;
     if (!build_geometry(c, g, why)) return fail(FM_EINVAL, why);
+    if (!sym_ok(c, g, why)) return fail(FM_EINVAL, why);
     fm_flow tmp;
     return carve(tmp, c, g, nullptr, bytes);
 }
@@ -664,6 +707,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     fm_flow* h = new fm_flow;
     h->cfg = c;
     if (!build_geometry(c, h->hg, why)) { delete h; return fail(FM_EINVAL, why); }
+    if (!sym_ok(c, h->hg, why)) { delete h; return fail(FM_EINVAL, why); }
     size_t need = 0;
     carve(*h, c, h->hg, nullptr, &need);
     if (!ws || bytes < need) {
@@ -706,6 +750,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.pI = h->b.pI;
     g.inv_ok = hg.inv_ok ? 1 : 0;
     g.gflow = c.flow == FM_FLOW_INTERACTION ? 1 : 0;
+    g.sym = c.sym_state;
     {
         int dev = 0, lds = 0;
         hipError_t e = hipGetDevice(&dev);
@@ -794,6 +839,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
                 delete h;
                 return fail(FM_EINVAL, "Z must be positive and finite");
             }
+
         rc = upload_z(h, c.max_batch, nullptr, nullptr);
         if (rc) { delete h; return rc; }
     }
@@ -1017,6 +1063,8 @@ int fm_flow_run_batch(fm_flow* h, int n, const double* U, const double* T0, cons
             for (size_t i = 0; i < static_cast<size_t>(nz) * N; ++i)
                 if (!(t[i] > 0.0 && std::isfinite(t[i])))
                     return fail(FM_EINVAL, "per-flow Z must be positive and finite");
+            if (h->g.sym && !rows_symmetric(h->hg.perm, t, nz, N))
+                return fail(FM_EINVAL, "sym_state needs per-flow Z tables invariant under the point group");
         }
     }
     const fm_config& c = h->cfg;

@@ -127,6 +127,8 @@ struct DevGeom {
     int inv_rot;           // pI[a] = (a + N/2) mod N
     int gflow;             // interaction flow: bins of chi instead of T d/dT chi
     int lds_max;           // LDS bytes one work group may allocate on the device
+    int sym;               // states invariant under the point group: products of
+                           // representatives only, read through the permutations
     const int* pp_off; const int* pp_pairs;
     const int* cr_off; const int* cr_pairs;
     const int* d_off;  const int* d_pairs;

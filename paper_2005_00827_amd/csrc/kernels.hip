@@ -1044,7 +1044,8 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     if (!running(fs, f) || !args.on[kind]) return;
     const int N = g.N, NN = g.NN;
     const bool ppk = kind == 0;
-    const int M = ppk ? g.nP : g.nD;
+    // symmetric states: the representatives' own transfers (the first nR) only
+    const int M = g.sym ? (ppk ? g.nRp : g.nRd) : (ppk ? g.nP : g.nD);
     const int ntn = (N + TN - 1) / TN;
     const int tm = blockIdx.x / ntn, tn = blockIdx.x - tm * ntn;
     if (tm * TM >= M) return;
@@ -1932,6 +1933,7 @@ __device__ inline void y_orbit_block(const DevGeom& g, const float* Bf, const fl
     __syncthreads();                                   // tables; every thread of the block
     int bmask = 0;                                     // operations used by the block's tiles
     for (int t = 0; t < tn - tb; ++t) bmask |= msk[t];
+    if (g.sym) bmask &= 1;                             // symmetric states: representatives only
 #pragma unroll 1
     for (int o = 0; o < 8; ++o) {
         if (!((bmask >> o) & 1)) continue;             // uniform over the block
@@ -2098,10 +2100,13 @@ __device__ inline void load_cols(const YT* p, R* out) {
 // rows at a time) are loaded into registers while the item's pair vectors are gathered into
 // LDS (zero-padded to KC, laid out [x][pair] so one x is a 128-bit broadcast read), so
 // every group costs one memory round trip.
+// pm (symmetric states, item transfer q = o(r), o != 0): perm_o.  Y_q[x][n] = Y_r[pinv_o x]
+// [pinv_o n], so the item reads representative r's rows x' in order with the pair vectors
+// taken at x = perm_o x', and the lane holding Y_r column n' writes output column perm_o n'.
 template <typename R, typename YT, int KIND, int CW, int KC>
 __device__ __attribute__((always_inline)) inline void contract_item(
     const DevGeom& g, const R* V, const R* VA, const R* VC, const YT* Ya, const YT* Yb,
-    const int* pairs, int cnt, R* vu, R* vw, R* Kf) {
+    const int* pairs, int cnt, R* vu, R* vw, R* Kf, const int* pm) {
     constexpr int G = (KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v) / CW;
     const int N = g.N, NN = g.NN;
     // the item's output pairs, read once with the first loads (the stores at the end would
@@ -2134,7 +2139,8 @@ __device__ __attribute__((always_inline)) inline void contract_item(
 #pragma unroll
                 for (int v = 0; v < kVec; ++v) {
                     const int e = min(e0 + static_cast<int>(threadIdx.x) + 64 * v, KC * N - 1);
-                    const int i = e / N, x = e - i * N;
+                    const int i = e / N, xr = e - i * N;
+                    const int x = pm ? pm[xr] : xr;
                     const int xy = pairs[min(i, cnt - 1)];
                     const int u = xy / N, w = xy - u * N;
                     // contiguous in x: V(u,w,x) = v0[u][w][x], V(x,u,w) = vc[w][u][x],
@@ -2203,12 +2209,15 @@ __device__ __attribute__((always_inline)) inline void contract_item(
             }
         }
         if (n0 + CW * static_cast<int>(threadIdx.x) >= N) continue;
+        int col[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) col[c] = pm ? pm[n + c] : n + c;
 #pragma unroll
         for (int i = 0; i < KC; ++i) {   // every part at (pair) N + n: contiguous in n
             if (i >= cnt) break;
 #pragma unroll
             for (int c = 0; c < CW; ++c)
-                Kf[static_cast<size_t>(pr[i]) * N + n + c] = KIND == 0 ? -acc[i][c] : acc[i][c];
+                Kf[static_cast<size_t>(pr[i]) * N + col[c]] = KIND == 0 ? -acc[i][c] : acc[i][c];
         }
     }
 }
@@ -2245,8 +2254,16 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     const R* V = v0 + f * N3;
     const R* VA = va + f * N3;
     const R* VC = vc + f * N3;
-    const YT* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + q) * NN;
-    const YT* Yb = y4 + (static_cast<size_t>(f) * nq + q) * NN;
+    // symmetric states: the products of the transfer's representative, through perm_o
+    int qy = q;
+    const int* pm = nullptr;
+    if (g.sym) {
+        qy = (kind == 0 ? g.qrep_pp : g.qrep_ph)[q];
+        const int o = (kind == 0 ? g.qg_pp : g.qg_ph)[q];
+        if (o != 0) pm = g.perm + o * N;
+    }
+    const YT* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + qy) * NN;
+    const YT* Yb = y4 + (static_cast<size_t>(f) * nq + qy) * NN;
     R* vu = reinterpret_cast<R*>(smem_raw);            // [N][kChunk]
     R* vw = vu + kChunk * N;                            // [N][kChunk] (direct only)
     // two columns per lane where one per lane would take more than one pass over the row
@@ -2255,25 +2272,25 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     // column instead of eight, half of them padding
     if (sizeof(R) == 4 && (N & 1) == 0 && N > 64) {
         if (cnt <= 4) {
-            if (kind == 0) contract_item<R, YT, 0, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-            else if (kind == 1) contract_item<R, YT, 1, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-            else contract_item<R, YT, 2, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+            if (kind == 0) contract_item<R, YT, 0, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+            else if (kind == 1) contract_item<R, YT, 1, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+            else contract_item<R, YT, 2, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
             return;
         }
-        if (kind == 0) contract_item<R, YT, 0, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-        else if (kind == 1) contract_item<R, YT, 1, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-        else contract_item<R, YT, 2, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        if (kind == 0) contract_item<R, YT, 0, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        else if (kind == 1) contract_item<R, YT, 1, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        else contract_item<R, YT, 2, 2, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
         return;
     }
     if (cnt <= 4) {
-        if (kind == 0) contract_item<R, YT, 0, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-        else if (kind == 1) contract_item<R, YT, 1, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-        else contract_item<R, YT, 2, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+        if (kind == 0) contract_item<R, YT, 0, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        else if (kind == 1) contract_item<R, YT, 1, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        else contract_item<R, YT, 2, 1, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
         return;
     }
-    if (kind == 0) contract_item<R, YT, 0, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-    else if (kind == 1) contract_item<R, YT, 1, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
-    else contract_item<R, YT, 2, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf);
+    if (kind == 0) contract_item<R, YT, 0, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+    else if (kind == 1) contract_item<R, YT, 1, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+    else contract_item<R, YT, 2, 1, kChunk>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
 }
 
 // ------------------------------------------------------------------------------------

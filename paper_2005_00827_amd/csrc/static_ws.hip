@@ -52,7 +52,7 @@ bool same_config(const Slot& s, const fm_config& c) {
                       a.sync_batch == c.sync_batch && a.n_shells == c.n_shells &&
                       a.shell_edges == nullptr && c.shell_edges == nullptr &&
                       a.k_table == nullptr && c.k_table == nullptr &&
-                      a.phase1_variant == c.phase1_variant;
+                      a.phase1_variant == c.phase1_variant && a.sym_state == c.sym_state;
     if (!same) return false;
     if (c.n_zT <= 0) return true;
     const size_t nz = static_cast<size_t>(c.n_zT), nt = nz * static_cast<size_t>(c.N);

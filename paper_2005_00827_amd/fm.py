@@ -49,7 +49,8 @@ class Config(ctypes.Structure):
                 ("stream", c_void_p), ("max_batch", c_int), ("tile_rows", c_int),
                 ("flow", c_int), ("g_end", c_double), ("v_rel", c_double), ("y_kernel", c_int),
                 ("sync_batch", c_int), ("n_shells", c_int), ("shell_edges", POINTER(c_double)),
-                ("k_table", POINTER(c_double)), ("phase1_variant", c_int)]
+                ("k_table", POINTER(c_double)), ("phase1_variant", c_int),
+                ("sym_state", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -126,7 +127,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
                 v_max=20.0, channels=CH_ALL, precision="fp64", z_lnT=None, z_table=None,
                 stream=None, max_batch=1, tile_rows=0, flow="temperature", g_end=0.0,
                 v_rel=0.0, y_kernel=0, sync_batch=False, n_shells=0, shell_edges=None,
-                k_table=None, phase1_variant=0):
+                k_table=None, phase1_variant=0, sym_state=False):
     cfg = Config()
     cfg.t, cfg.tp, cfg.mu, cfg.U = float(t), float(tp), float(mu), float(U)
     cfg.geometry = GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry)
@@ -156,6 +157,7 @@ def make_config(N, L, U=1.0, t=1.0, tp=0.0, mu=0.0, geometry="angular", T0=1.0, 
     cfg.y_kernel = int(y_kernel)
     cfg.sync_batch = int(sync_batch)
     cfg.phase1_variant = int(phase1_variant)
+    cfg.sym_state = int(sym_state)
     cfg.n_shells = int(n_shells)
     if shell_edges is not None:
         se = np.ascontiguousarray(shell_edges, np.float64)

@@ -108,6 +108,11 @@ def test_representative_counts_are_point_group_orbits(N, L, tp, mu):
     (dict(N=24, L=32, geometry="shells", n_shells=5), "odd n_shells"),
     (dict(N=24, L=32, geometry="shells", n_shells=3, shell_edges=[-0.5]), "shell edges"),
     (dict(N=136, L=128, precision="bf16x3"), "N <= 128"),
+    (dict(N=16, L=32, sym_state=2), "sym_state must be 0 or 1"),
+    (dict(N=16, L=32, precision="fp64_direct", sym_state=1), "product buffers"),
+    (dict(N=16, L=32, precision="fp32", y_kernel=1, sym_state=1), "product buffers"),
+    (dict(N=16, L=32, precision="fp32", z_lnT=[0.0, 1.0],
+          z_table=[[1.0 - 0.01 * a for a in range(16)]] * 2, sym_state=1), "invariant"),
 ])
 def test_invalid_configs_rejected(kw, msg):
     cfg = fm.make_config(**kw)
