@@ -10,7 +10,11 @@ precision state / error estimate / stop test (stop at max|V| > 20t).
 One benchmark step is the whole 16-flow batch (every right-hand side, stage, error estimate
 and stop test until every flow has stopped) with its inputs already on the device.  The
 metric counts 3 N^3 L^2 coupling-loop-point updates per right-hand side of each flow (the
-direct form's nominal work).
+direct form's nominal work).  The flows start from V = U and their Z tables depend on the
+patch through cos 4 theta only, so every state is invariant under the lattice's point group
+and the headline runs the symmetric-state mode (sym_state = 1: phase 2 from the orbit
+representatives' products, the same right-hand side); --sym 0 runs the full mode, which the
+extra figures also report.
 
 Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
 """
@@ -70,7 +74,8 @@ def bin_density(fm, N, L, stride=16):
     return out[0], out[1]
 
 
-def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", nbin_flows=1):
+def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", nbin_flows=1,
+                sym=0):
     """Algorithmic work of one launch of each timed kernel group for one flow (phase 1: for
     nbin_flows flows that bin, one per step-sharing group).
 
@@ -79,7 +84,8 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", 
               involution once: nsets (nRp + nRd) L^2 / 2 weight evaluations at OPS_PER_WEIGHT
               lane-ops each, against the plain vector issue rate (bound "alu")
     y:        the contraction over the bins, weighted by their density rho = (rho_pp, rho_ph):
-              2 (nP rho_pp + 3 nD rho_ph) N^3 flops on the matrix cores of the mode; bytes =
+              2 (nP rho_pp + 3 nD rho_ph) N^3 flops on the matrix cores of the mode (symmetric
+              states: the representatives' products, nRp and nRd in place of nP and nD); bytes =
               representative bins (plus the transposed particle-hole bins) + 3 operand slabs
               (the products Y that this build stores between phase 2a and 2b are not the
               method's work and are not counted); bound by HBM or the matrix cores, whichever
@@ -100,7 +106,8 @@ def kernel_work(name, N, L, nP, nD, rsize, nRp, nRd, rho, nsets=5, prec="fp32", 
         return {"bound": "hbm", "bytes": N3 * (8 + (3 + 3) * rsize + (1 + 3) * rsize),
                 "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
     if name == "y":
-        flops = 2.0 * (nP * rho[0] + 3 * nD * rho[1]) * N3
+        mp, md = (nRp, nRd) if sym else (nP, nD)
+        flops = 2.0 * (mp * rho[0] + 3 * md * rho[1]) * N3
         nbytes = (nRp + 2 * nRd) * NN * rsize + 3 * N3 * opsz
         # the binding roof: whichever takes longer at its peak for this work
         if nbytes / (PEAK["hbm_GBs"] * 1e9) > flops / (MFMA_PEAK[prec] * 1e12):
@@ -227,10 +234,10 @@ def c5_tables(inputs, w):
     return np.stack([t[0] for t in tabs]), np.stack([t[1] for t in tabs])
 
 
-def c5_flow(fm, w, zl, zt, dev, prec, rtol=0.0, sync=0):
+def c5_flow(fm, w, zl, zt, dev, prec, rtol=0.0, sync=0, sym=0):
     return fm.Flow(N=w["N"], L=w["L"], U=w["U"][0], T0=1.0, T_end=w["T_end"], integrator="rk45",
                    precision=prec, rtol=rtol, z_lnT=zl[0], z_table=zt[0], max_batch=len(w["U"]),
-                   sync_batch=sync, device=dev)
+                   sync_batch=sync, sym_state=sym, device=dev)
 
 
 def timed_batch(f, torch, w, zl, zt):
@@ -248,14 +255,17 @@ def tc_diff(res, ref):
 
 
 def c5_other_modes(fm, inputs, torch, dev, w, zl, zt, ref_tc):
-    """The 16-flow batch with every flow stepping on its own, in step-sharing groups of 2 and
-    of all 16, and in the other precisions (each at its default rtol): flows/hour, RHS count,
-    the largest T_c difference from the converged FP64 reference, and the phase-1 launch."""
+    """The 16-flow batch in the full and the symmetric-state mode, with every flow stepping on
+    its own, in step-sharing groups of 2 and of all 16, and in the other precisions (each at
+    its default rtol): flows/hour, RHS count, the largest T_c difference from the converged
+    FP64 reference, and the phase-1 launch."""
     out = {}
-    for key, prec, sync in (("bf16_independent", "bf16", 0), ("bf16_sync2", "bf16", 2),
-                            ("bf16_sync16", "bf16", 1), ("bf16x3_sync2", "bf16x3", 2),
-                            ("fp32_sync2", "fp32", 2), ("fp64", "fp64", 0)):
-        f = c5_flow(fm, w, zl, zt, dev, prec, sync=sync)
+    for key, prec, sync, sym in (("bf16_full_sync2", "bf16", 2, 0), ("bf16_sym_independent", "bf16", 0, 1),
+                                 ("bf16_sym_sync2", "bf16", 2, 1), ("bf16_sym_sync16", "bf16", 1, 1),
+                                 ("bf16x3_sym_sync2", "bf16x3", 2, 1), ("bf16x3_full_sync2", "bf16x3", 2, 0),
+                                 ("fp32_sym_sync2", "fp32", 2, 1), ("fp32_full_sync2", "fp32", 2, 0),
+                                 ("fp64_full", "fp64", 0, 0), ("fp64_sym", "fp64", 0, 1)):
+        f = c5_flow(fm, w, zl, zt, dev, prec, sync=sync, sym=sym)
         if prec != "fp64":    # tuning and the batch's step graph, outside the timed run
             f.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
         res, dt = timed_batch(f, torch, w, zl, zt)
@@ -269,15 +279,15 @@ def c5_other_modes(fm, inputs, torch, dev, w, zl, zt, ref_tc):
 
 def c2_single_flow(fm, inputs, torch, dev, steps=5):
     """The quasi-particle workload of one flow (N=48, L=128, U=3, Z table, f32): updates/s and
-    flows/hour, and its T_c against the FP64 path."""
+    flows/hour in the full and the symmetric-state mode, and its T_c against the FP64 path."""
     w = inputs.workload("C2")
     N, L, U, Te = w["N"], w["L"], w["U"][0], w["T_end"]
     zl, zt = inputs.synthetic_z_table(N, U, 1.0, Te)
     out = {}
     tc = {}
-    for prec in ("fp32", "fp64"):
+    for prec, sym in (("fp32", 0), ("fp64", 0), ("fp32", 1)):
         f = fm.Flow(N=N, L=L, U=U, T0=1.0, T_end=Te, integrator="rk45", precision=prec,
-                    z_lnT=zl, z_table=zt, device=dev)
+                    z_lnT=zl, z_table=zt, sym_state=sym, device=dev)
         f.run_batch([U], [1.0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -286,11 +296,13 @@ def c2_single_flow(fm, inputs, torch, dev, steps=5):
         dt = time.perf_counter() - t0
         f.close()
         rhs = sum(r["n_rhs"] for r in res)
-        tc[prec] = res[0]["T_c"]
-        out["updates_per_s_" + prec] = rhs * 3.0 * N ** 3 * L ** 2 / dt
-        out["ms_per_flow_" + prec] = dt / steps * 1e3
-        out["rhs_per_flow_" + prec] = rhs / steps
+        key = prec + ("_sym" if sym else "")
+        tc[key] = res[0]["T_c"]
+        out["updates_per_s_" + key] = rhs * 3.0 * N ** 3 * L ** 2 / dt
+        out["ms_per_flow_" + key] = dt / steps * 1e3
+        out["rhs_per_flow_" + key] = rhs / steps
     out["Tc_rel_diff_fp32_fp64"] = abs(tc["fp32"] / tc["fp64"] - 1.0)
+    out["Tc_rel_diff_fp32_sym_fp64"] = abs(tc["fp32_sym"] / tc["fp64"] - 1.0)
     return out
 
 
@@ -374,6 +386,9 @@ def main():
     ap.add_argument("--sync", type=int, default=2,
                     help="step-sharing groups of at most this many flows (0: every flow steps "
                          "on its own)")
+    ap.add_argument("--sym", type=int, default=1, choices=(0, 1),
+                    help="1: symmetric-state mode (the batch's states are point-group "
+                         "invariant); 0: full mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline batch (for profiling)")
@@ -399,8 +414,9 @@ def main():
     w = inputs.workload("C5")
     N, L, nf = w["N"], w["L"], len(w["U"])
     zl, zt = c5_tables(inputs, w)
-    print("bench: 16 flows N=%d L=%d U=1..4, Z per flow, %s rhs, rk45; steps=%d warmup=%d"
-          % (N, L, args.prec, args.steps, args.warmup), file=sys.stderr, flush=True)
+    print("bench: 16 flows N=%d L=%d U=1..4, Z per flow, %s rhs, rk45, sym_state %d; steps=%d "
+          "warmup=%d" % (N, L, args.prec, args.sym, args.steps, args.warmup), file=sys.stderr,
+          flush=True)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -409,7 +425,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    flow = c5_flow(fm, w, zl, zt, dev, args.prec, sync=args.sync)
+    flow = c5_flow(fm, w, zl, zt, dev, args.prec, sync=args.sync, sym=args.sym)
     for _ in range(args.warmup):          # the first call also times the phase-2a variants
         flow.run_batch(w["U"], w["T0"], z_lnT=zl, z_tables=zt)
     torch.cuda.synchronize()
@@ -446,7 +462,8 @@ def main():
         # flows that bin in phase 1: one per step-sharing group
         nbin = nf if args.sync == 0 else (nf + (args.sync if args.sync > 1 else nf) - 1) // \
             (args.sync if args.sync > 1 else nf)
-        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, rho, prec=args.prec, nbin_flows=nbin)
+        wk = kernel_work(name, N, L, nP, nD, 4, nRp, nRd, rho, prec=args.prec, nbin_flows=nbin,
+                         sym=args.sym)
         ach = achieved(wk, us * 1e-6, nf)
         batch_ms, launches = tm.get(name, (0.0, 0))
         kernels[name] = {"avg_us": us, "launches_per_batch": launches,
@@ -516,9 +533,12 @@ def main():
             "config": {"workload": "16 flows, U_i = 1 + 3i/15, N=128 patches, L=512 loop grid, "
                                    "t'=0, mu=0, T 1.0t->0.01t, Dormand-Prince in ln T, synthetic "
                                    "Z table per flow, %s contraction, f64 state, stop at "
-                                   "max|V|>20t; one step = the whole 16-flow batch" % args.prec,
+                                   "max|V|>20t; one step = the whole 16-flow batch; %s"
+                                   % (args.prec, "symmetric-state mode (point-group invariant "
+                                      "states: phase 2 from the orbit representatives' "
+                                      "products)" if args.sym else "full mode"),
                        "N": N, "L": L, "flows_per_step": nf,
-                       "step_sharing_groups": args.sync},
+                       "step_sharing_groups": args.sync, "sym_state": args.sym},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line))
 
