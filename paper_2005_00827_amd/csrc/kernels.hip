@@ -2078,17 +2078,17 @@ template <> struct YGroup<float> { static constexpr int v = 48; };
 template <> struct YGroup<double> { static constexpr int v = 24; };
 // the direct channel holds two Y columns, so half as many rows each
 
-// CW consecutive columns of a Y row at p (CW = 2: one 4-byte bf16 pair or 8-byte f32 pair,
-// p even-aligned), widened to R.
+// CW consecutive columns of a Y row at p (CW = 2 or 4: one bf16 or f32 vector load, p
+// CW-aligned), widened to R.
 template <typename R, typename YT, int CW>
 __device__ inline void load_cols(const YT* p, R* out) {
     if constexpr (CW == 1) {
         out[0] = static_cast<R>(p[0]);
     } else {
-        typedef YT yt2 __attribute__((ext_vector_type(2)));
-        const yt2 v = *reinterpret_cast<const yt2*>(p);
-        out[0] = static_cast<R>(v[0]);
-        out[1] = static_cast<R>(v[1]);
+        typedef YT ytn __attribute__((ext_vector_type(CW)));
+        const ytn v = *reinterpret_cast<const ytn*>(p);
+#pragma unroll
+        for (int c = 0; c < CW; ++c) out[c] = static_cast<R>(v[c]);
     }
 }
 
@@ -2103,29 +2103,36 @@ __device__ inline void load_cols(const YT* p, R* out) {
 // pm (symmetric states, item transfer q = o(r), o != 0): perm_o.  Y_q[x][n] = Y_r[pinv_o x]
 // [pinv_o n], so the item reads representative r's rows x' in order with the pair vectors
 // taken at x = perm_o x', and the lane holding Y_r column n' writes output column perm_o n'.
-template <typename R, typename YT, int KIND, int CW, int KC>
+// XH = 2 (N a multiple of 128, CW = 4): the two half-waves take alternate rows x with the
+// same 32 x 4 columns and their sums are added at the end, so one broadcast LDS read of a
+// row's pair values feeds 4 columns per lane (LDS bytes per multiply-add halved; with 2
+// columns per lane the broadcast reads bound the kernel together with the multiply-adds).
+template <typename R, typename YT, int KIND, int CW, int KC, int XH = 1>
 __device__ __attribute__((always_inline)) inline void contract_item(
     const DevGeom& g, const R* V, const R* VA, const R* VC, const YT* Ya, const YT* Yb,
     const int* pairs, int cnt, R* vu, R* vw, R* Kf, const int* pm) {
-    constexpr int G = (KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v) / CW;
+    constexpr int G = (KIND == 2 ? YGroup<R>::v / 2 : YGroup<R>::v) / CW;   // rows per lane
+    constexpr int GR = G * XH;                                              // rows per group
     const int N = g.N, NN = g.NN;
+    const int lc = XH == 2 ? static_cast<int>(threadIdx.x & 31) : static_cast<int>(threadIdx.x);
+    const int h = XH == 2 ? static_cast<int>(threadIdx.x >> 5) : 0;
     // the item's output pairs, read once with the first loads (the stores at the end would
     // otherwise each wait for their pair's load)
     int pr[KC];
 #pragma unroll
     for (int i = 0; i < KC; ++i) pr[i] = pairs[min(i, cnt - 1)];
-    for (int n0 = 0; n0 < N; n0 += 64 * CW) {
-        const int n = min(n0 + CW * static_cast<int>(threadIdx.x), N - CW);
+    for (int n0 = 0; n0 < N; n0 += 64 / XH * CW) {
+        const int n = min(n0 + CW * lc, N - CW);
         R acc[KC][CW];
 #pragma unroll
         for (int i = 0; i < KC; ++i)
 #pragma unroll
             for (int c = 0; c < CW; ++c) acc[i][c] = R(0);
-        for (int xg = 0; xg < N; xg += G) {
+        for (int xg = 0; xg < N; xg += GR) {
             R ya[G][CW], yb[KIND == 2 ? G : 1][CW];
 #pragma unroll
             for (int j = 0; j < G; ++j) {
-                const int x = min(xg + j, N - 1);
+                const int x = min(xg + XH * j + h, N - 1);
                 load_cols<R, YT, CW>(Ya + static_cast<size_t>(x) * N + n, ya[j]);
                 if (KIND == 2) load_cols<R, YT, CW>(Yb + static_cast<size_t>(x) * N + n, yb[j]);
             }
@@ -2172,16 +2179,16 @@ __device__ __attribute__((always_inline)) inline void contract_item(
             }
             // rows past N repeat row N-1 (clamped loads) and are weighted by zero; a group
             // wholly below N needs no weights
-            if (xg + G <= N) {
+            if (xg + GR <= N) {
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
-                    const R* u = vu + (xg + j) * KC;
+                    const R* u = vu + (xg + XH * j + h) * KC;
 #pragma unroll
                     for (int i = 0; i < KC; ++i)
 #pragma unroll
                         for (int c = 0; c < CW; ++c) acc[i][c] += u[i] * ya[j][c];
                     if (KIND == 2) {
-                        const R* w = vw + (xg + j) * KC;
+                        const R* w = vw + (xg + XH * j + h) * KC;
 #pragma unroll
                         for (int i = 0; i < KC; ++i)
 #pragma unroll
@@ -2191,8 +2198,8 @@ __device__ __attribute__((always_inline)) inline void contract_item(
             } else {
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
-                    const int x = min(xg + j, N - 1);
-                    const R mask = xg + j < N ? R(1) : R(0);
+                    const int x = min(xg + XH * j + h, N - 1);
+                    const R mask = xg + XH * j + h < N ? R(1) : R(0);
                     const R* u = vu + x * KC;
 #pragma unroll
                     for (int i = 0; i < KC; ++i)
@@ -2208,7 +2215,15 @@ __device__ __attribute__((always_inline)) inline void contract_item(
                 }
             }
         }
-        if (n0 + CW * static_cast<int>(threadIdx.x) >= N) continue;
+        if constexpr (XH == 2) {
+            // the two halves' sums over alternate rows
+#pragma unroll
+            for (int i = 0; i < KC; ++i)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) acc[i][c] += __shfl_xor(acc[i][c], 32);
+            if (h) continue;
+        }
+        if (n0 + CW * lc >= N) continue;
         int col[CW];
 #pragma unroll
         for (int c = 0; c < CW; ++c) col[c] = pm ? pm[n + c] : n + c;
@@ -2270,6 +2285,18 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
     // (N > 64; at N = 48 two per lane leave 40 of 64 lanes idle: 11.6 -> 13.5 us measured)
     // items of at most four pairs (most transfers have four) carry four accumulators per
     // column instead of eight, half of them padding
+    if (sizeof(R) == 4 && N % 128 == 0) {
+        if (cnt <= 4) {
+            if (kind == 0) contract_item<R, YT, 0, 4, 4, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+            else if (kind == 1) contract_item<R, YT, 1, 4, 4, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+            else contract_item<R, YT, 2, 4, 4, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+            return;
+        }
+        if (kind == 0) contract_item<R, YT, 0, 4, kChunk, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        else if (kind == 1) contract_item<R, YT, 1, 4, kChunk, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        else contract_item<R, YT, 2, 4, kChunk, 2>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
+        return;
+    }
     if (sizeof(R) == 4 && (N & 1) == 0 && N > 64) {
         if (cnt <= 4) {
             if (kind == 0) contract_item<R, YT, 0, 2, 4>(g, V, VA, VC, Ya, Yb, pairs, cnt, vu, vw, Kf, pm);
