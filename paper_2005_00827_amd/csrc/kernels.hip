@@ -1044,8 +1044,10 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
     if (!running(fs, f) || !args.on[kind]) return;
     const int N = g.N, NN = g.NN;
     const bool ppk = kind == 0;
-    // symmetric states: the representatives' own transfers (the first nR) only
-    const int M = g.sym ? (ppk ? g.nRp : g.nRd) : (ppk ? g.nP : g.nD);
+    // transfers of the kind (the per-flow stride of Y); symmetric states compute the
+    // representatives' own transfers (the first nR) only
+    const int Mq = ppk ? g.nP : g.nD;
+    const int M = g.sym ? (ppk ? g.nRp : g.nRd) : Mq;
     const int ntn = (N + TN - 1) / TN;
     const int tm = blockIdx.x / ntn, tn = blockIdx.x - tm * ntn;
     if (tm * TM >= M) return;
@@ -1123,7 +1125,7 @@ __global__ void __launch_bounds__(kThreads) k_y(DevGeom g, const FlowState* fs,
         }
         __syncthreads();
     }
-    R* Y = args.Y[kind] + static_cast<size_t>(f) * M * NN;
+    R* Y = args.Y[kind] + static_cast<size_t>(f) * Mq * NN;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int q = tm * TM + ty * 4 + i;

@@ -115,17 +115,20 @@ def test_rhs_sym_every_tile_choice(torch_dev, prec, tile_rows):
     assert rel(got, ref) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3"])
 def test_rhs_sym_full_size_sampled(torch_dev, prec):
-    """N = 128, L = 512 (the batch workload's size): sampled outputs against the oracle."""
+    """N = 128, L = 512 (the batch workload's size): sampled outputs against the oracle, for
+    two flows in one batch (the second reads its products at the batch's per-flow stride)."""
     N, L, T = 128, 512, 0.08
     m = O.model(N, L)
-    V = symmetrise(inputs.noisy_state(N, 3.0), group_perms(m))
+    perms = group_perms(m)
+    V = np.stack([symmetrise(inputs.noisy_state(N, 3.0, seed=s), perms) for s in (1, 2)])
     lnT, tab, Z = sym_z(N, 3.0, T)
     abc = inputs.sample_indices(N, 48)
-    ref = O.rhs_points(m, T, V, abc, Z=Z)
-    got = lib_rhs(torch_dev, N, L, T, V, prec, sym_state=1, z_lnT=lnT, z_table=tab)[0]
-    assert rel(got[abc[:, 0], abc[:, 1], abc[:, 2]], ref) <= TOL[prec]
+    got = lib_rhs(torch_dev, N, L, [T, T], V, prec, sym_state=1, z_lnT=lnT, z_table=tab)
+    for i in range(2):
+        ref = O.rhs_points(m, T, V[i], abc, Z=Z)
+        assert rel(got[i][abc[:, 0], abc[:, 1], abc[:, 2]], ref) <= TOL[prec], (i, prec)
 
 
 def c2_golden():
@@ -188,7 +191,7 @@ def test_sym_c5_batch_against_converged_fp64(torch_dev):
 
     ref = run("fp64", 0, 1e-8)
     assert sum(r["status"] == fm.DIVERGED for r in ref) >= 12
-    for prec in ("bf16", "bf16x3", "fp32"):
+    for prec in ("bf16", "bf16x3", "fp32", "fp64"):
         res = run(prec, 1)
         for i, (r, q) in enumerate(zip(res, ref)):
             assert r["status"] == q["status"], (prec, i, r, q)
