@@ -289,6 +289,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     b.item_q = L.take<int>(hg.item_q.size());
     b.item_p0 = L.take<int>(hg.item_p0.size());
     b.item_rec = L.take<int>(hg.item_rec.size());
+    b.sym_rec = L.take<int>(hg.sym_rec.size());
     b.fz_row = L.take<int>(hg.fz_row.size());
     b.fz_pair = L.take<int>(hg.fz_pair.size());
     b.fz_blk = L.take<int>(hg.fz_blk.size());
@@ -772,6 +773,8 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     g.d_off = h->b.d_off; g.d_pairs = h->b.d_pairs;
     g.item_q = h->b.item_q; g.item_p0 = h->b.item_p0; g.item_rec = h->b.item_rec;
     for (int k = 0; k < 3; ++k) g.n_items[k] = hg.n_items[k];
+    g.sym_rec = h->b.sym_rec;
+    for (int k = 0; k < 3; ++k) g.n_sym_items[k] = hg.n_sym_items[k];
     g.fz_row = h->b.fz_row; g.fz_pair = h->b.fz_pair; g.fz_blk = h->b.fz_blk;
     for (int k = 0; k < 3; ++k) g.fz_nblk[k] = hg.fz_nblk[k];
     auto up = [&](void* dst, const void* src, size_t n) {
@@ -817,6 +820,7 @@ int fm_flow_init(const fm_config* in, void* ws, size_t bytes, fm_flow** out) {
     if (e == hipSuccess) e = upv(h->b.item_q, hg.item_q);
     if (e == hipSuccess) e = upv(h->b.item_p0, hg.item_p0);
     if (e == hipSuccess) e = upv(h->b.item_rec, hg.item_rec);
+    if (e == hipSuccess) e = upv(h->b.sym_rec, hg.sym_rec);
     if (e == hipSuccess) e = upv(h->b.fz_row, hg.fz_row);
     if (e == hipSuccess) e = upv(h->b.fz_pair, hg.fz_pair);
     if (e == hipSuccess) e = upv(h->b.fz_blk, hg.fz_blk);

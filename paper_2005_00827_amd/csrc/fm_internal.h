@@ -65,11 +65,19 @@ struct HostGeometry {
     std::vector<int> fz_pair;        // [rows][kFusedPairs] packed pair or -1
     std::vector<int> fz_blk;         // [blocks][2] operation, first row
     int fz_nblk[3] = {0, 0, 0};      // blocks of the pp, crossed and direct kinds, in order
+    // Phase 2b of symmetric states on the matrix cores: per channel kind and representative
+    // r, records of 4 + kSymPairs ints: r, pair count, kind, 0, then (pair * 8 + o) of the
+    // transfers q = o(r) of r's orbit (-1 pads)
+    std::vector<int> sym_rec;
+    int n_sym_items[3] = {0, 0, 0};
 };
 
 // Fused phase 2: output pairs per row and rows per block (16-row tiles, one per wavefront).
 constexpr int kFusedPairs = 4;
 constexpr int kFusedRows = 128;
+// Matrix-core phase 2b of symmetric states: output pairs per work item (4 wavefronts of
+// 16-row tiles) of one representative's orbit.
+constexpr int kSymPairs = 64;
 
 bool build_geometry(const fm_config& cfg, HostGeometry& g, std::string& err);
 
@@ -139,6 +147,8 @@ struct DevGeom {
     const int* fz_pair;
     const int* fz_blk;
     int fz_nblk[3];
+    const int* sym_rec;    // matrix-core phase 2b of symmetric states (see HostGeometry)
+    int n_sym_items[3];
     const double* xi;      // [np]
     const int* patch;      // [np]
     const int2* xp;        // [np] (xi as float bits, patch): single-precision phase 1
@@ -193,7 +203,7 @@ struct Buffers {
     int* orb_rows; int* orb_q; int* orb_mask; int* porder;
     int* pI;
     int* pp_off; int* pp_pairs; int* cr_off; int* cr_pairs; int* d_off; int* d_pairs;
-    int* item_q; int* item_p0; int* item_rec;
+    int* item_q; int* item_p0; int* item_rec; int* sym_rec;
     int* fz_row; int* fz_pair; int* fz_blk;
     void* bins;                        // [S][B][nRp + nRd][NN] real, representative transfers
     void* binsT;                       // [S][B][nRd][NN] real, particle-hole bins transposed

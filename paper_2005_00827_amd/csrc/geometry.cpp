@@ -354,6 +354,30 @@ void build_pairs(HostGeometry& g) {
         }
         g.fz_nblk[k] = nb;
     }
+    // symmetric states: per channel kind and representative r, the output pairs of every
+    // transfer q = o(r) of r's orbit, each with its o, in items of at most kSymPairs
+    g.sym_rec.clear();
+    for (int k = 0; k < 3; ++k) {
+        const std::vector<int>& off = *offs[k];
+        const std::vector<int>& pr = *prs[k];
+        const std::vector<int>& qrep = k == 0 ? g.qrep_pp : g.qrep_ph;
+        const std::vector<int>& qg = k == 0 ? g.qg_pp : g.qg_ph;
+        const int nr = static_cast<int>(k == 0 ? g.rep_pp.size() : g.rep_ph.size());
+        std::vector<std::vector<int>> ent(nr);
+        for (size_t q = 0; q + 1 < off.size(); ++q)
+            for (int p = off[q]; p < off[q + 1]; ++p) ent[qrep[q]].push_back(pr[p] * 8 + qg[q]);
+        int n = 0;
+        for (int r = 0; r < nr; ++r)
+            for (size_t e0 = 0; e0 < ent[r].size(); e0 += kSymPairs) {
+                const int cnt = static_cast<int>(std::min<size_t>(kSymPairs, ent[r].size() - e0));
+                const int head[4] = {r, cnt, k, 0};
+                g.sym_rec.insert(g.sym_rec.end(), head, head + 4);
+                for (int i = 0; i < kSymPairs; ++i)
+                    g.sym_rec.push_back(i < cnt ? ent[r][e0 + i] : -1);
+                ++n;
+            }
+        g.n_sym_items[k] = n;
+    }
 }
 
 }  // namespace

@@ -2323,6 +2323,125 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
 }
 
 // ------------------------------------------------------------------------------------
+// Phase 2b of symmetric states on the matrix cores (bf16 products, N <= 128, N % 16 == 0).
+// One 4-wavefront block per (channel kind, representative r, at most kSymPairs output pairs
+// of the transfers q = o(r) of r's orbit) and flow.  Every such transfer's products are r's,
+// Y_q[x][n] = Y_r[pinv_o x][pinv_o n], so for a pair of transfer o(r)
+//   out(pair, perm_o n') = sum_x' L(pair, perm_o x') Y_r[x'][n']
+// (L the pair's vector of its channel, as in k_contract): one product of the pairs' vectors,
+// gathered at perm_o x' and split into bf16 high and low parts (two products: the vectors
+// keep f32 accuracy), with Y_r as stored (bf16), which the block stages once in LDS in the
+// B operand layout [n'][x'] and shares between its four 16-pair tiles.  The direct channel
+// adds a second product, (V(x,a,c) - 2 V(a,x,c)) Y3 + V(a,x,c) Y4.  A lane ends with four
+// consecutive n' of its tile row (the staged operand goes first) and writes them to columns
+// perm_o n'.
+// ------------------------------------------------------------------------------------
+constexpr int kMmaKE = 32;                        // k values per lane: x' < 128
+constexpr int kMmaKBS = 4 * kMmaKE + 8;           // staged row stride (bf16 values)
+
+__global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState* fs,
+                                                      const float* v0, const float* va,
+                                                      const float* vc, const __bf16* y1,
+                                                      const __bf16* y2, const __bf16* y3,
+                                                      const __bf16* y4, float* K, unsigned ch,
+                                                      int slot, int B, int it0) {
+    constexpr int KE = kMmaKE, KBS = kMmaKBS;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);   // [1 or 2][128][KBS]: Y_r^T (Y4_r^T)
+    const int f = blockIdx.y;
+    if (!running(fs, f)) return;
+    const int* rec = g.sym_rec + static_cast<size_t>(blockIdx.x + it0) * (kSymPairs + 4);
+    const int r = rec[0], cnt = rec[1], kind = rec[2];
+    const int* ent = rec + 4;
+    const int N = g.N, NN = g.NN;
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    float* Kf = K + ((static_cast<size_t>(slot) * B + f) * 3 + kind) * N3;
+    const unsigned bit = kind == 0 ? FM_CH_PP : (kind == 1 ? FM_CH_CR : FM_CH_D);
+    if (!(ch & bit)) {   // a channel that is switched off contributes zero
+        for (int e = threadIdx.x; e < cnt * N; e += blockDim.x) {
+            const int i = e / N, n = e - i * N;
+            Kf[static_cast<size_t>(ent[i] >> 3) * N + n] = 0.f;
+        }
+        return;
+    }
+    const bool two = kind == 2;
+    const int nq = kind == 0 ? g.nP : g.nD;
+    const __bf16* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + r) * NN;
+    const __bf16* Yb = y4 + (static_cast<size_t>(f) * nq + r) * NN;
+    // stage Y_r^T: a task is 8 consecutive n' of one row x' (one 16-byte load), written as
+    // 8 values down the staged columns (consecutive lanes, consecutive x'); zero past N
+    // (N % 16 == 0: a task lies wholly below N or at or above it)
+    for (int task = threadIdx.x; task < 128 * (128 / 8); task += 256) {
+        const int x = task & 127, nb = 8 * (task >> 7);
+        const bool ok = x < N && nb < N;
+        const size_t ix = static_cast<size_t>(min(x, N - 1)) * N + min(nb, N - 8);
+        fm_bf8 h0 = *reinterpret_cast<const fm_bf8*>(Ya + ix);
+        fm_bf8 h1 = h0;
+        if (two) h1 = *reinterpret_cast<const fm_bf8*>(Yb + ix);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            Bs[(nb + e) * KBS + x] = ok ? h0[e] : static_cast<__bf16>(0.f);
+            if (two) Bs[128 * KBS + (nb + e) * KBS + x] = ok ? h1[e] : static_cast<__bf16>(0.f);
+        }
+    }
+    // the wave's tile rows: pairs 16 w .. 16 w + 15 of the record; lane % 16 the row
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int pi = 16 * wv + (lane & 15);
+    const int en = pi < cnt ? ent[pi] : -1;
+    const int o = en >= 0 ? (en & 7) : 0, xy = en >= 0 ? (en >> 3) : 0;
+    const int u = xy / N, w = xy - u * N;
+    // contiguous in x: V(u,w,x) = v0[u][w][x], V(x,u,w) = vc[w][u][x], V(u,x,w) = va[w][u][x]
+    const size_t base = static_cast<size_t>(f) * N3 +
+                        (kind == 0 ? static_cast<size_t>(xy) * N : static_cast<size_t>(w) * NN + static_cast<size_t>(u) * N);
+    const int* pm = g.perm + o * N;
+    float a1[KE], a2[KE];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+        const int xr = mfma_k<1>(e, lane);              // x' of the lane's e-th value
+        const bool ok = en >= 0 && xr < N;
+        const int x = o ? pm[min(xr, N - 1)] : min(xr, N - 1);
+        float va1 = 0.f, va2 = 0.f;
+        if (kind == 0) va1 = v0[base + x];
+        else if (kind == 1) va1 = vc[base + x];
+        else {
+            const float c = vc[base + x], b = va[base + x];
+            va1 = c - 2.f * b;
+            va2 = b;
+        }
+        a1[e] = ok ? va1 : 0.f;
+        a2[e] = ok ? va2 : 0.f;
+    }
+    const AFrag<2, KE> A1 = make_afrag<2, KE>(a1);
+    const AFrag<2, KE> A2 = make_afrag<2, KE>(a2);
+    __syncthreads();                                   // Y_r^T staged; every thread
+    if (16 * wv >= cnt) return;                        // a wave without pairs (uniform)
+    const int col = lane & 15;
+    for (int t = 0; t < N / 16; ++t) {
+        fm_f4 c = fm_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KE / 8; ++s) {
+            const int ob = (16 * t + col) * KBS + 32 * s + 8 * (lane >> 4);
+            const fm_bf8 b3 = *reinterpret_cast<const fm_bf8*>(Bs + ob);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.l[s], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.h[s], c, 0, 0, 0);
+            if (two) {
+                const fm_bf8 b4 = *reinterpret_cast<const fm_bf8*>(Bs + 128 * KBS + ob);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.l[s], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.h[s], c, 0, 0, 0);
+            }
+        }
+        if (en < 0) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int n = 16 * t + 4 * (lane >> 4) + q;
+            const int cn = o ? pm[n] : n;
+            Kf[static_cast<size_t>(xy) * N + cn] = kind == 0 ? -c[q] : c[q];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // Fused phase 2 (bf16 and split-bf16 operands, N <= 128): the grouped products and the
 // contraction they feed in one kernel, so the products never leave registers (no Y buffers).
 // A block takes kFusedRows rows of one channel kind, all from transfers q = o(r) of one
@@ -3287,6 +3406,25 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
 
 template <typename R, typename YT>
 void contract_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
+    if constexpr (sizeof(R) == 4 && sizeof(YT) == 2) {
+        if (g.sym && g.N % 16 == 0 && g.N <= 128) {   // symmetric states on the matrix cores
+            // the pp and crossed items stage one product (more blocks per CU), the direct
+            // items two
+            const size_t one = 128 * static_cast<size_t>(kMmaKBS) * sizeof(__bf16);
+            const int n01 = g.n_sym_items[0] + g.n_sym_items[1], n2 = g.n_sym_items[2];
+            for (int part = 0; part < 2; ++part) {
+                const int items = part ? n2 : n01;
+                if (items == 0) continue;
+                hipLaunchKernelGGL(k_contract_mma, dim3(items, nf), dim3(256), (part + 1) * one, s,
+                                   g, b.fs, static_cast<const float*>(b.v0),
+                                   static_cast<const float*>(b.va), static_cast<const float*>(b.vc),
+                                   static_cast<const __bf16*>(b.y1), static_cast<const __bf16*>(b.y2),
+                                   static_cast<const __bf16*>(b.y3), static_cast<const __bf16*>(b.y4),
+                                   static_cast<float*>(b.k), ch, slot, b.bstride, part ? n01 : 0);
+            }
+            return;
+        }
+    }
     const size_t lds = 2 * static_cast<size_t>(kChunk) * g.N * sizeof(R);
     const int items = g.n_items[0] + g.n_items[1] + g.n_items[2];
     hipLaunchKernelGGL((k_contract<R, YT>), dim3(items, nf), dim3(64), lds, s, g, b.fs,
