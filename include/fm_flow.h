@@ -191,7 +191,8 @@ typedef struct {
                                  a state without the symmetry they are wrong.  Needs the
                                  geometry's point-group symmetry (fm_geometry_query: n_rep
                                  below the transfer counts), a phase 2 with product buffers
-                                 (not FM_FP64_DIRECT, y_kernel 0 or 3: the orbit kernel) and
+                                 (not FM_FP64_DIRECT, y_kernel 0, 2 or 3: the class kernel
+                                 on class 0 or the orbit kernel on operation 0) and
                                  symmetric Z and K tables (checked to 1e-12 relative, also
                                  per-flow tables of fm_flow_run_batch); FM_EINVAL otherwise.
                                  0: no assumption. */

@@ -198,8 +198,8 @@ int resolve(const fm_config* in, fm_config& c, std::string& why) {
     }
     if (c.sync_batch < 0) { why = "sync_batch must be >= 0"; return FM_EINVAL; }
     if (c.sym_state != 0 && c.sym_state != 1) { why = "sym_state must be 0 or 1"; return FM_EINVAL; }
-    if (c.sym_state && (c.precision == FM_FP64_DIRECT || (c.y_kernel != 0 && c.y_kernel != 3))) {
-        why = "sym_state needs product buffers from the orbit kernel (not FM_FP64_DIRECT, y_kernel 0 or 3)";
+    if (c.sym_state && (c.precision == FM_FP64_DIRECT || c.y_kernel == 1 || c.y_kernel == 4)) {
+        why = "sym_state needs product buffers from the class or orbit kernel (not FM_FP64_DIRECT, y_kernel 0, 2 or 3)";
         return FM_EINVAL;
     }
     return FM_OK;
@@ -521,7 +521,9 @@ int ensure_tuned(fm_flow* h, int nf, const double* Vbase) {
     std::vector<std::pair<int, int>> cand;    // (variant, tiles per wavefront)
     for (int var = 1; var <= 3; ++var) {
         if (c.y_kernel != 0 && var != c.y_kernel) continue;
-        if (c.sym_state && var != 3) continue;        // representatives' products: the orbit kernel
+        // representatives' products: the operation-class kernel on class 0, or the orbit
+        // kernel on operation 0
+        if (c.sym_state && var == 1) continue;
         if (c.tile_rows > 0) { cand.emplace_back(var, c.tile_rows); continue; }
         const int maxt = var == 3 ? y_orb_max_tpw(h->g, mma)
                          : var == 2 ? y_max_tpw(h->g) : y_rows_max_tpw(h->g);

@@ -3297,7 +3297,7 @@ void y_mfma_cls(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
     tpw = tpw <= 0 ? 1 : (tpw > maxt ? maxt : tpw);
     YRuns runs{};
     for (int c = 0; c < 2; ++c)
-        for (int o = 0; o < 8; ++o) {
+        for (int o = 0; o < (g.sym ? 1 : 8); ++o) {   // symmetric states: class 0 only
             const int nt = (g.cls[c][o + 1] - g.cls[c][o] + 15) / 16;
             runs.nr[c][o] = (nt + 4 * tpw - 1) / (4 * tpw);
             runs.tot[c] += runs.nr[c][o];

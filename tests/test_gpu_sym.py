@@ -106,13 +106,18 @@ def test_rhs_sym_small(torch_dev, prec, N, L, T, kw):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("tile_rows", [1, 2, 4])
-def test_rhs_sym_every_tile_choice(torch_dev, prec, tile_rows):
+@pytest.mark.parametrize("y_kernel", [2, 3])
+def test_rhs_sym_every_tile_choice(torch_dev, prec, tile_rows, y_kernel):
+    """Phase 2a on the class kernel (class 0) or the orbit kernel (operation 0), every tile
+    count; two flows per batch."""
     N, L, T = 32, 64, 0.09
     m = O.model(N, L)
-    V = symmetrise(inputs.noisy_state(N, 2.5), group_perms(m))
-    ref = O.rhs(m, T, V)
-    got = lib_rhs(torch_dev, N, L, T, V, prec, sym_state=1, y_kernel=3, tile_rows=tile_rows)[0]
-    assert rel(got, ref) <= TOL[prec]
+    perms = group_perms(m)
+    V = np.stack([symmetrise(inputs.noisy_state(N, 2.5, seed=s), perms) for s in (3, 4)])
+    got = lib_rhs(torch_dev, N, L, [T, T], V, prec, sym_state=1, y_kernel=y_kernel,
+                  tile_rows=tile_rows)
+    for i in range(2):
+        assert rel(got[i], O.rhs(m, T, V[i])) <= TOL[prec], i
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3"])
