@@ -329,6 +329,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
         // the products of bf16 operands are stored as bf16 (the same 8-bit significand); the
         // fused phase 2 keeps them in registers and needs no buffers for them
         b.y_bf16 = c.precision == FM_FP32_BF16MFMA ? 1 : 0;
+        b.y_split = c.precision == FM_FP32_BF16X3 ? 1 : 0;
         const size_t ys = b.y_bf16 ? 2 : rs;
         const bool fz = fused_phase2(c);
         b.y1 = fz ? nullptr : L.take<char>(static_cast<size_t>(B) * nP * NN * ys);
@@ -339,6 +340,7 @@ int carve(fm_flow& h, const fm_config& c, const HostGeometry& hg, char* base, si
     } else {
         b.bins = b.binsT = b.y1 = b.y2 = b.y3 = b.y4 = nullptr;
         b.y_bf16 = 0;
+        b.y_split = 0;
         b.bins_bytes = b.binsT_bytes = 0;
         b.nbset = 0;
         b.wtab = L.take<double>(static_cast<size_t>(B) * (nP + nD) * np);

@@ -211,6 +211,7 @@ struct Buffers {
     size_t bins_bytes, binsT_bytes;    // with kBinPad values of zeroed padding each
     void* y1; void* y2; void* y3; void* y4;  // [B][n][NN] real (bf16 when y_bf16)
     int y_bf16;                        // bf16 operands: the products Y are stored as bf16
+    int y_split;                       // split-bf16 operands (f32 products)
     void* v0; void* va; void* vc;      // operands [B][N^3] real
     void* k;                           // [7][B][3][N^3] real: per stage, flow and channel (parts in phase-2b order)
     void* ksum;                        // [7][B][N^3] real: a slot's three parts summed, V order

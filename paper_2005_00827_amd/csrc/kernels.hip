@@ -2339,15 +2339,21 @@ __global__ void __launch_bounds__(64) k_contract(DevGeom g, const FlowState* fs,
 constexpr int kMmaKE = 32;                        // k values per lane: x' < 128
 constexpr int kMmaKBS = 4 * kMmaKE + 8;           // staged row stride (bf16 values)
 
+// YT = __bf16: bf16 products as stored, all of an item's products staged at once.  YT = float
+// (split-bf16 products): each product staged as high and low bf16 planes, one product per
+// pass, three products per k-step (the low-by-low term dropped, as in phase 2a's split mode).
+template <typename YT>
 __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState* fs,
                                                       const float* v0, const float* va,
-                                                      const float* vc, const __bf16* y1,
-                                                      const __bf16* y2, const __bf16* y3,
-                                                      const __bf16* y4, float* K, unsigned ch,
+                                                      const float* vc, const YT* y1,
+                                                      const YT* y2, const YT* y3,
+                                                      const YT* y4, float* K, unsigned ch,
                                                       int slot, int B, int it0) {
-    constexpr int KE = kMmaKE, KBS = kMmaKBS;
+    constexpr int KE = kMmaKE, KBS = kMmaKBS, PLANE = 128 * kMmaKBS;
+    constexpr bool kSplit = sizeof(YT) == 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);   // [1 or 2][128][KBS]: Y_r^T (Y4_r^T)
+    // [1 or 2][128][KBS]: Y_r^T (and Y4_r^T), or the high and low planes of one product
+    __bf16* Bs = reinterpret_cast<__bf16*>(smem_raw);
     const int f = blockIdx.y;
     if (!running(fs, f)) return;
     const int* rec = g.sym_rec + static_cast<size_t>(blockIdx.x + it0) * (kSymPairs + 4);
@@ -2366,24 +2372,41 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
     }
     const bool two = kind == 2;
     const int nq = kind == 0 ? g.nP : g.nD;
-    const __bf16* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + r) * NN;
-    const __bf16* Yb = y4 + (static_cast<size_t>(f) * nq + r) * NN;
-    // stage Y_r^T: a task is 8 consecutive n' of one row x' (one 16-byte load), written as
-    // 8 values down the staged columns (consecutive lanes, consecutive x'); zero past N
+    const YT* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + r) * NN;
+    const YT* Yb = y4 + (static_cast<size_t>(f) * nq + r) * NN;
+    // stage Y_r^T: a task is 8 consecutive n' of one row x' (16-byte loads), written as 8
+    // values down the staged columns (consecutive lanes, consecutive x'); zero past N
     // (N % 16 == 0: a task lies wholly below N or at or above it)
-    for (int task = threadIdx.x; task < 128 * (128 / 8); task += 256) {
-        const int x = task & 127, nb = 8 * (task >> 7);
-        const bool ok = x < N && nb < N;
-        const size_t ix = static_cast<size_t>(min(x, N - 1)) * N + min(nb, N - 8);
-        fm_bf8 h0 = *reinterpret_cast<const fm_bf8*>(Ya + ix);
-        fm_bf8 h1 = h0;
-        if (two) h1 = *reinterpret_cast<const fm_bf8*>(Yb + ix);
+    auto stage = [&](const YT* Y0, const YT* Y1, bool both) {
+        for (int task = threadIdx.x; task < 128 * (128 / 8); task += 256) {
+            const int x = task & 127, nb = 8 * (task >> 7);
+            const bool ok = x < N && nb < N;
+            const size_t ix = static_cast<size_t>(min(x, N - 1)) * N + min(nb, N - 8);
+            if constexpr (kSplit) {
+                const float4 p0 = *reinterpret_cast<const float4*>(Y0 + ix);
+                const float4 p1 = *reinterpret_cast<const float4*>(Y0 + ix + 4);
+                const float v[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            Bs[(nb + e) * KBS + x] = ok ? h0[e] : static_cast<__bf16>(0.f);
-            if (two) Bs[128 * KBS + (nb + e) * KBS + x] = ok ? h1[e] : static_cast<__bf16>(0.f);
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 hi = static_cast<__bf16>(v[e]);
+                    const __bf16 lo = static_cast<__bf16>(v[e] - static_cast<float>(hi));
+                    Bs[(nb + e) * KBS + x] = ok ? hi : static_cast<__bf16>(0.f);
+                    Bs[PLANE + (nb + e) * KBS + x] = ok ? lo : static_cast<__bf16>(0.f);
+                }
+            } else {
+                const fm_bf8 h0 = *reinterpret_cast<const fm_bf8*>(Y0 + ix);
+                fm_bf8 h1 = h0;
+                if (both) h1 = *reinterpret_cast<const fm_bf8*>(Y1 + ix);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    Bs[(nb + e) * KBS + x] = ok ? h0[e] : static_cast<__bf16>(0.f);
+                    if (both) Bs[PLANE + (nb + e) * KBS + x] = ok ? h1[e] : static_cast<__bf16>(0.f);
+                }
+            }
         }
-    }
+    };
+    if constexpr (!kSplit) stage(Ya, Yb, two);
+    else stage(Ya, Ya, false);
     // the wave's tile rows: pairs 16 w .. 16 w + 15 of the record; lane % 16 the row
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -2415,28 +2438,67 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
     const AFrag<2, KE> A1 = make_afrag<2, KE>(a1);
     const AFrag<2, KE> A2 = make_afrag<2, KE>(a2);
     __syncthreads();                                   // Y_r^T staged; every thread
-    if (16 * wv >= cnt) return;                        // a wave without pairs (uniform)
+    const bool active = 16 * wv < cnt;                 // a wave with pairs (uniform)
     const int col = lane & 15;
-    for (int t = 0; t < N / 16; ++t) {
-        fm_f4 c = fm_f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < KE / 8; ++s) {
-            const int ob = (16 * t + col) * KBS + 32 * s + 8 * (lane >> 4);
-            const fm_bf8 b3 = *reinterpret_cast<const fm_bf8*>(Bs + ob);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.l[s], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.h[s], c, 0, 0, 0);
-            if (two) {
-                const fm_bf8 b4 = *reinterpret_cast<const fm_bf8*>(Bs + 128 * KBS + ob);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.l[s], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.h[s], c, 0, 0, 0);
-            }
-        }
-        if (en < 0) continue;
+    auto store = [&](int t, const fm_f4& c) {
+        if (en < 0) return;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int n = 16 * t + 4 * (lane >> 4) + q;
             const int cn = o ? pm[n] : n;
             Kf[static_cast<size_t>(xy) * N + cn] = kind == 0 ? -c[q] : c[q];
+        }
+    };
+    if constexpr (!kSplit) {
+        if (!active) return;
+        for (int t = 0; t < N / 16; ++t) {
+            fm_f4 c = fm_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KE / 8; ++s) {
+                const int ob = (16 * t + col) * KBS + 32 * s + 8 * (lane >> 4);
+                const fm_bf8 b3 = *reinterpret_cast<const fm_bf8*>(Bs + ob);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.l[s], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.h[s], c, 0, 0, 0);
+                if (two) {
+                    const fm_bf8 b4 = *reinterpret_cast<const fm_bf8*>(Bs + PLANE + ob);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.l[s], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.h[s], c, 0, 0, 0);
+                }
+            }
+            store(t, c);
+        }
+    } else {
+        // every tile's accumulators held across the passes (N <= 128: at most 8 tiles)
+        fm_f4 c[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) c[t] = fm_f4{0.f, 0.f, 0.f, 0.f};
+        auto products = [&](const AFrag<2, KE>& A) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t >= N / 16) break;
+#pragma unroll
+                for (int s = 0; s < KE / 8; ++s) {
+                    const int ob = (16 * t + col) * KBS + 32 * s + 8 * (lane >> 4);
+                    const fm_bf8 bh = *reinterpret_cast<const fm_bf8*>(Bs + ob);
+                    const fm_bf8 bl = *reinterpret_cast<const fm_bf8*>(Bs + PLANE + ob);
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, A.l[s], c[t], 0, 0, 0);
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, A.h[s], c[t], 0, 0, 0);
+                    c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, A.h[s], c[t], 0, 0, 0);
+                }
+            }
+        };
+        if (active) products(A1);
+        if (two) {                                     // uniform over the block
+            __syncthreads();                           // the first product is consumed
+            stage(Yb, Yb, false);
+            __syncthreads();
+            if (active) products(A2);
+        }
+        if (!active) return;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t >= N / 16) break;
+            store(t, c[t]);
         }
     }
 }
@@ -3406,20 +3468,23 @@ void y_t(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch,
 
 template <typename R, typename YT>
 void contract_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsigned ch, int slot) {
-    if constexpr (sizeof(R) == 4 && sizeof(YT) == 2) {
-        if (g.sym && g.N % 16 == 0 && g.N <= 128) {   // symmetric states on the matrix cores
-            // the pp and crossed items stage one product (more blocks per CU), the direct
-            // items two
+    if constexpr (sizeof(R) == 4) {
+        // symmetric states on the matrix cores: bf16 products, or split-bf16 products (f32 Y
+        // of the split mode; the f32 mode keeps its f32 phase 2b)
+        if (g.sym && g.N % 16 == 0 && g.N <= 128 && (sizeof(YT) == 2 || b.y_split)) {
+            // bf16: the pp and crossed items stage one product (more blocks per CU), the
+            // direct items two; split: two planes of one product at a time
             const size_t one = 128 * static_cast<size_t>(kMmaKBS) * sizeof(__bf16);
             const int n01 = g.n_sym_items[0] + g.n_sym_items[1], n2 = g.n_sym_items[2];
             for (int part = 0; part < 2; ++part) {
                 const int items = part ? n2 : n01;
                 if (items == 0) continue;
-                hipLaunchKernelGGL(k_contract_mma, dim3(items, nf), dim3(256), (part + 1) * one, s,
+                const size_t lds = (sizeof(YT) == 4 || part) ? 2 * one : one;
+                hipLaunchKernelGGL(k_contract_mma<YT>, dim3(items, nf), dim3(256), lds, s,
                                    g, b.fs, static_cast<const float*>(b.v0),
                                    static_cast<const float*>(b.va), static_cast<const float*>(b.vc),
-                                   static_cast<const __bf16*>(b.y1), static_cast<const __bf16*>(b.y2),
-                                   static_cast<const __bf16*>(b.y3), static_cast<const __bf16*>(b.y4),
+                                   static_cast<const YT*>(b.y1), static_cast<const YT*>(b.y2),
+                                   static_cast<const YT*>(b.y3), static_cast<const YT*>(b.y4),
                                    static_cast<float*>(b.k), ch, slot, b.bstride, part ? n01 : 0);
             }
             return;
