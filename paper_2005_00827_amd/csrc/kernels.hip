@@ -2342,7 +2342,9 @@ constexpr int kMmaKBS = 4 * kMmaKE + 8;           // staged row stride (bf16 val
 // YT = __bf16: bf16 products as stored, all of an item's products staged at once.  YT = float
 // (split-bf16 products): each product staged as high and low bf16 planes, one product per
 // pass, three products per k-step (the low-by-low term dropped, as in phase 2a's split mode).
-template <typename YT>
+// TWO: the launch of the direct channel's items (two products); the pp and crossed items'
+// launch holds no second operand (fewer registers, more blocks per CU).
+template <typename YT, bool TWO>
 __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState* fs,
                                                       const float* v0, const float* va,
                                                       const float* vc, const YT* y1,
@@ -2370,7 +2372,7 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
         }
         return;
     }
-    const bool two = kind == 2;
+    constexpr bool two = TWO;                          // kind == 2 exactly for this launch
     const int nq = kind == 0 ? g.nP : g.nD;
     const YT* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + r) * NN;
     const YT* Yb = y4 + (static_cast<size_t>(f) * nq + r) * NN;
@@ -2418,25 +2420,23 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
     const size_t base = static_cast<size_t>(f) * N3 +
                         (kind == 0 ? static_cast<size_t>(xy) * N : static_cast<size_t>(w) * NN + static_cast<size_t>(u) * N);
     const int* pm = g.perm + o * N;
-    float a1[KE], a2[KE];
+    float a1[KE], a2[TWO ? KE : 1];
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
         const int xr = mfma_k<1>(e, lane);              // x' of the lane's e-th value
         const bool ok = en >= 0 && xr < N;
         const int x = o ? pm[min(xr, N - 1)] : min(xr, N - 1);
-        float va1 = 0.f, va2 = 0.f;
-        if (kind == 0) va1 = v0[base + x];
-        else if (kind == 1) va1 = vc[base + x];
-        else {
+        if constexpr (TWO) {
             const float c = vc[base + x], b = va[base + x];
-            va1 = c - 2.f * b;
-            va2 = b;
+            a1[e] = ok ? c - 2.f * b : 0.f;
+            a2[e] = ok ? b : 0.f;
+        } else {
+            a1[e] = ok ? (kind == 0 ? v0[base + x] : vc[base + x]) : 0.f;
         }
-        a1[e] = ok ? va1 : 0.f;
-        a2[e] = ok ? va2 : 0.f;
     }
     const AFrag<2, KE> A1 = make_afrag<2, KE>(a1);
-    const AFrag<2, KE> A2 = make_afrag<2, KE>(a2);
+    AFrag<2, KE> A2;
+    if constexpr (TWO) A2 = make_afrag<2, KE>(a2);
     __syncthreads();                                   // Y_r^T staged; every thread
     const bool active = 16 * wv < cnt;                 // a wave with pairs (uniform)
     const int col = lane & 15;
@@ -2459,7 +2459,7 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
                 const fm_bf8 b3 = *reinterpret_cast<const fm_bf8*>(Bs + ob);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.l[s], c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b3, A1.h[s], c, 0, 0, 0);
-                if (two) {
+                if constexpr (TWO) {
                     const fm_bf8 b4 = *reinterpret_cast<const fm_bf8*>(Bs + PLANE + ob);
                     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.l[s], c, 0, 0, 0);
                     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b4, A2.h[s], c, 0, 0, 0);
@@ -2488,7 +2488,7 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
             }
         };
         if (active) products(A1);
-        if (two) {                                     // uniform over the block
+        if constexpr (TWO) {
             __syncthreads();                           // the first product is consumed
             stage(Yb, Yb, false);
             __syncthreads();
@@ -3480,7 +3480,8 @@ void contract_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf, unsi
                 const int items = part ? n2 : n01;
                 if (items == 0) continue;
                 const size_t lds = (sizeof(YT) == 4 || part) ? 2 * one : one;
-                hipLaunchKernelGGL(k_contract_mma<YT>, dim3(items, nf), dim3(256), lds, s,
+                auto kern = part ? k_contract_mma<YT, true> : k_contract_mma<YT, false>;
+                hipLaunchKernelGGL(kern, dim3(items, nf), dim3(256), lds, s,
                                    g, b.fs, static_cast<const float*>(b.v0),
                                    static_cast<const float*>(b.va), static_cast<const float*>(b.vc),
                                    static_cast<const YT*>(b.y1), static_cast<const YT*>(b.y2),
