@@ -176,8 +176,10 @@ def test_sym_c2_flow_against_oracle_golden(torch_dev, prec):
 
 def test_sym_c5_batch_against_converged_fp64(torch_dev):
     """The 16-flow batch (N = 128, L = 512, U = 1..4, Z per flow) in the symmetric mode: T_c
-    of the bf16, split-bf16 and FP32 right-hand sides against a converged FP64 run of the
-    full mode (rtol 1e-8) to 1e-3, and the same statuses."""
+    of the bf16, split-bf16, FP32 and FP64 right-hand sides against a converged FP64 run of
+    the full mode (rtol 1e-8) to 1e-3 (bf16 to its unit roundoff 2^-9: its products are
+    rounded to 8 bits and its trajectory varies with the order of the bins' float atomics),
+    and the same statuses."""
     from paper_2005_00827_amd import fm
     w = inputs.workload("C5")
     N, L, U, T0 = w["N"], w["L"], w["U"], w["T0"]
@@ -201,7 +203,8 @@ def test_sym_c5_batch_against_converged_fp64(torch_dev):
         for i, (r, q) in enumerate(zip(res, ref)):
             assert r["status"] == q["status"], (prec, i, r, q)
             if q["status"] == fm.DIVERGED:
-                assert abs(r["T_c"] / q["T_c"] - 1.0) <= 1e-3, (prec, i, r["T_c"], q["T_c"])
+                tol = 2.0 ** -9 if prec == "bf16" else 1e-3
+                assert abs(r["T_c"] / q["T_c"] - 1.0) <= tol, (prec, i, r["T_c"], q["T_c"])
 
 
 def test_sym_rejects_asymmetric_per_flow_tables(torch_dev):

@@ -2,7 +2,8 @@
 
 * the 16-flow batch (N = 128, L = 512, U = 1..4, Z per flow): T_c of the bf16, split-bf16
   and FP32 right-hand sides against a converged FP64 run of the same batch (rtol 1e-8) to
-  1e-3 (the oracle would need hours per right-hand side here);
+  1e-3, bf16 to its unit roundoff 2^-9 (the oracle would need hours per right-hand side
+  here);
 * the quasi-particle flow (N = 48, L = 128, U = 3, Z table) against the oracle's flow stored
   in tests/golden/c2_flow.txt, in FP64 and FP32, and the FP32 path replayed on the FP64
   path's schedule (every accepted step to 1e-4);
@@ -72,6 +73,12 @@ def c4_golden():
     return rows
 
 
+# T_c of a whole 16-flow batch against the converged FP64 run.  The bf16 products carry a
+# rounding of up to 2^-9 each, and the LDS bins' float atomics add in no fixed order, so the
+# bf16 trajectory differs from launch to launch; its T_c is held to bf16's unit roundoff.
+TC_TOL = {"bf16": 2.0 ** -9, "bf16x3": 1e-3, "fp32": 1e-3, "fp64": 1e-3}
+
+
 def test_c5_batch_tc_against_converged_fp64(torch_dev):
     fm = _fm()
     torch, dev = torch_dev
@@ -97,7 +104,7 @@ def test_c5_batch_tc_against_converged_fp64(torch_dev):
         for i, (r, q) in enumerate(zip(res, ref)):
             assert r["status"] == q["status"], (prec, i, r, q)
             if q["status"] == fm.DIVERGED:
-                assert abs(r["T_c"] / q["T_c"] - 1.0) <= 1e-3, (prec, i, r["T_c"], q["T_c"])
+                assert abs(r["T_c"] / q["T_c"] - 1.0) <= TC_TOL[prec], (prec, i, r["T_c"], q["T_c"])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
