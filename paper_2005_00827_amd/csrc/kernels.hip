@@ -420,15 +420,15 @@ __device__ inline double phi_dd_pt(double2 u, double2 v) { return phi_dd<double>
 __device__ inline float4 flip(float4 v) { return make_float4(-v.x, -v.y, v.z, v.w); }
 __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 
-// Single-precision weight of one loop-point pair for phase 1, straight from xi: the same
-// quantity as phi_dd_pt(point_q(.), point_q(.)).  With e = exp(-2|x|), p = 1 + e and
-// sech^2 x = 4e/p^2, the quotient away from the diagonal is
+// Single-precision weight of one loop-point pair for phase 1, straight from xi: a quarter of
+// phi_dd_pt(point_q(.), point_q(.)) (the factor 4 goes into the bins' scale).  With
+// e = exp(-2|x|), p = 1 + e and sech^2 x = 4e/p^2, the quotient away from the diagonal is
 //   phi[a,b] = (a s_a - b s_b)/(a - b) = 4 (a e_a p_b^2 - b e_b p_a^2) / ((a - b) p_a^2 p_b^2)
 // (p in [1, 2]: one reciprocal instead of three).  Arguments: tp = 1/2T, tq = 1/2T, or -1/2T
 // for particle-particle (b = -xv/2T), and ce = -log2(e)/T, so that e_a = exp2(ce |xu|).
 // phi', phi3 and the trapezoid are evaluated only when a lane of the wave has |a - b| < 0.05
 // (the branch is uniform over the wave), with tanh entering only as |a| tanh|a| and tanh^2.
-__device__ inline float pair_weight(float xu, float xv, float tp, float tq, float ce) {
+__device__ inline float pair_weight_q(float xu, float xv, float tp, float tq, float ce) {
     const float a = xu * tp, b = xv * tq;
     const float ea = __builtin_amdgcn_exp2f(ce * fabsf(xu));
     const float eb = __builtin_amdgcn_exp2f(ce * fabsf(xv));
@@ -436,19 +436,18 @@ __device__ inline float pair_weight(float xu, float xv, float tp, float tq, floa
     const float pa2 = pa * pa, pb2 = pb * pb;
     const float d = a - b;
     const float num = (a * ea) * pb2 - (b * eb) * pa2;
-    float w = 4.0f * num * __builtin_amdgcn_rcpf(d * pa2 * pb2);
+    float w = num * __builtin_amdgcn_rcpf(d * pa2 * pb2);
     const bool near = fabsf(d) < 0.05f;
-    if (__ballot(near)) {
-        if (near) {
-            const float ra = __builtin_amdgcn_rcpf(pa), rb = __builtin_amdgcn_rcpf(pb);
-            const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;   // sech^2
-            const float ta = (1.0f - ea) * ra, tb = (1.0f - eb) * rb;         // tanh|a|, tanh|b|
-            const float xa = fabsf(a) * ta, xb = fabsf(b) * tb, qa = ta * ta, qb = tb * tb;
-            const float d1 = sa * (1.0f - 2.0f * xa) + sb * (1.0f - 2.0f * xb);
-            const float d3 = sa * (-6.0f * (1.0f - 3.0f * qa) + 8.0f * xa * (2.0f - 3.0f * qa)) +
-                             sb * (-6.0f * (1.0f - 3.0f * qb) + 8.0f * xb * (2.0f - 3.0f * qb));
-            w = 0.5f * d1 - (d * d) * d3 * (1.0f / 24.0f);
-        }
+    if (__ballot(near)) {                              // every lane computes, the near ones keep it
+        const float ra = __builtin_amdgcn_rcpf(pa), rb = __builtin_amdgcn_rcpf(pb);
+        const float sa = ea * ra * ra, sb = eb * rb * rb;       // sech^2 / 4
+        const float ta = (1.0f - ea) * ra, tb = (1.0f - eb) * rb;   // tanh|a|, tanh|b|
+        const float xa = fabsf(a) * ta, xb = fabsf(b) * tb, qa = ta * ta, qb = tb * tb;
+        const float d1 = sa * (1.0f - 2.0f * xa) + sb * (1.0f - 2.0f * xb);
+        const float d3 = sa * (-6.0f * (1.0f - 3.0f * qa) + 8.0f * xa * (2.0f - 3.0f * qa)) +
+                         sb * (-6.0f * (1.0f - 3.0f * qb) + 8.0f * xb * (2.0f - 3.0f * qb));
+        const float ws = 0.5f * d1 - (d * d) * d3 * (1.0f / 24.0f);
+        if (near) w = ws;
     }
     return w;
 }
@@ -640,10 +639,11 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
     R* out = bins + (static_cast<size_t>(f) * nR + r) * NN;
     R scale[NODES], tp[NODES];
     float tq[NODES], ce[NODES];                        // single-precision weight: +-1/2T, -log2(e)/T
+    constexpr double kWq = (!kG && sizeof(R) == 4) ? 4.0 : 1.0;   // that weight is a quarter
 #pragma unroll
     for (int j = 0; j < NODES; ++j) {
         const double Tj = T[j];
-        scale[j] = static_cast<R>((kG ? 1.0 : -1.0) / (4.0 * Tj * np));
+        scale[j] = static_cast<R>(kWq * (kG ? 1.0 : -1.0) / (4.0 * Tj * np));
         tp[j] = static_cast<R>(sizeof(R) == 4 ? 1.0 / (2.0 * Tj) : 2.0 * Tj);   // 1/2T or 2T
         tq[j] = static_cast<float>((pp ? -1.0 : 1.0) / (2.0 * Tj));
         ce[j] = static_cast<float>(-1.4426950408889634 / Tj);
@@ -670,7 +670,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
     // the pairing).
     auto weight = [&](R xa, R xb, int j) -> R {
         if constexpr (kG) return pair_chi(xa, xb, tp[j], pp);
-        else if constexpr (sizeof(R) == 4) return pair_weight(xa, xb, tp[j], tq[j], ce[j]);
+        else if constexpr (sizeof(R) == 4) return pair_weight_q(xa, xb, tp[j], tq[j], ce[j]);
         else return pair_weight(xa, xb, tp[j], pp);
     };
     auto add_batch = [&](const R (&xu)[kBinBatch], const R (&xv)[kBinBatch],
@@ -745,6 +745,75 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
         // at the segment's end: no scan across lanes, one atomic per run.
         const int nseg = BT > L ? BT / L : 1;
         const int seglen = (nrow + nseg - 1) / nseg;
+        bool walked = false;
+        if constexpr (sizeof(R) == 4) if (L % 64 == 0) {
+            // L a multiple of 64 (single precision): a wave's 64 lanes take 64 consecutive
+            // columns of one segment, so the row of each step, its partner row and both rows'
+            // offsets are the same for every lane and are formed on the scalar unit; the
+            // table is read by raw buffer loads (lane offset in a vector register, row offset
+            // in a scalar one, range np entries), so per point a lane forms only its key, the
+            // weights and the run update.  The run starts at key 0 with a zero sum, so its
+            // first flush adds nothing.
+            // resource word 3: raw buffer with a 32-bit data format (gfx9 encoding)
+            const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<int2*>(g.xp), 0, np * 8, 0x00020000);
+            const int wave0 = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) & ~63);
+            for (int it0 = wave0; it0 < L * nseg; it0 += BT) {
+                const int sg = it0 / L;
+                const int jx = it0 - sg * L + lane;
+                const int r0 = sg * seglen, r1 = min(r0 + seglen, nrow);
+                int px = pp ? mx - jx - 1 : jx + mx;
+                px += px < 0 ? L : (px >= L ? -L : 0);
+                const unsigned ou = static_cast<unsigned>(jx) * 8u, ov = static_cast<unsigned>(px) * 8u;
+                int prev = 0;
+                R run[NODES];
+#pragma unroll
+                for (int j = 0; j < NODES; ++j) run[j] = R(0);
+                for (int rb = r0; rb < r1; rb += kBinBatch) {
+                    R xu[kBinBatch], xv[kBinBatch];
+                    int ka[kBinBatch];
+#pragma unroll
+                    for (int i = 0; i < kBinBatch; ++i) {
+                        const int rr = min(rb + i, r1 - 1);
+                        const int jy = half ? half_map(hy, rr) : rr;
+                        int py = pp ? my - jy - 1 : jy + my;
+                        py += py < 0 ? L : (py >= L ? -L : 0);
+                        const auto u = __builtin_amdgcn_raw_buffer_load_b64(xr, ou, jy * L * 8, 0);
+                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, ov, py * L * 8, 0);
+                        xu[i] = __int_as_float(static_cast<int>(u[0]));
+                        xv[i] = __int_as_float(static_cast<int>(v[0]));
+                        ka[i] = static_cast<int>(__umul24(u[1], S)) + static_cast<int>(v[1]);
+                    }
+#pragma unroll
+                    for (int i = 0; i < kBinBatch; ++i) {
+                        if (rb + i >= r1) break;            // uniform over the wave
+                        const int key = ka[i];
+                        const bool chg = key != prev;
+                        if (chg) {
+#pragma unroll
+                            for (int j = 0; j < NODES; ++j) {
+                                if (j >= nn) break;        // uniform over the block
+                                atomicAdd(&acc[j * NS + prev], run[j]);
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < NODES; ++j) {
+                            if (j >= nn) break;            // uniform over the block
+                            const R w = weight(xu[i], xv[i], j);
+                            run[j] = (chg ? R(0) : run[j]) + w;
+                        }
+                        prev = key;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NODES; ++j) {
+                    if (j >= nn) break;                    // uniform over the block
+                    atomicAdd(&acc[j * NS + prev], run[j]);
+                }
+            }
+            walked = true;
+        }
+        if (!walked)
         for (int it = threadIdx.x; it < L * nseg; it += BT) {
             const int jx = it % L, sg = it / L;
             const int r0 = sg * seglen, r1 = min(r0 + seglen, nrow);
