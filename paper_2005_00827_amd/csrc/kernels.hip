@@ -769,24 +769,33 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
                 R run[NODES];
 #pragma unroll
                 for (int j = 0; j < NODES; ++j) run[j] = R(0);
-                for (int rb = r0; rb < r1; rb += kBinBatch) {
+                // The segment in pieces over which the row and the partner row each advance
+                // by one per step (a piece ends at the pairing's jump from visited row h1 to
+                // grid row c + 1 and where the partner row wraps), so a step's two row
+                // offsets are the previous ones plus constants.  Full batches of a piece add
+                // every point; the last, partial one repeats the piece's last row in its
+                // unused slots and stops at the piece's end.
+                const int L8 = L * 8;
+                // one batch: kTail = false, kBinBatch rows; true, cnt < kBinBatch rows
+                auto batch = [&](auto tail, int& su, int& sv, int dv, int su1, int sv1, int cnt) {
+                    constexpr bool kTail = decltype(tail)::value;
                     R xu[kBinBatch], xv[kBinBatch];
                     int ka[kBinBatch];
 #pragma unroll
                     for (int i = 0; i < kBinBatch; ++i) {
-                        const int rr = min(rb + i, r1 - 1);
-                        const int jy = half ? half_map(hy, rr) : rr;
-                        int py = pp ? my - jy - 1 : jy + my;
-                        py += py < 0 ? L : (py >= L ? -L : 0);
-                        const auto u = __builtin_amdgcn_raw_buffer_load_b64(xr, ou, jy * L * 8, 0);
-                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, ov, py * L * 8, 0);
+                        const int oy = kTail ? min(su, su1) : su;
+                        const int oq = kTail ? (pp ? max(sv, sv1) : min(sv, sv1)) : sv;
+                        const auto u = __builtin_amdgcn_raw_buffer_load_b64(xr, ou, oy, 0);
+                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, ov, oq, 0);
                         xu[i] = __int_as_float(static_cast<int>(u[0]));
                         xv[i] = __int_as_float(static_cast<int>(v[0]));
                         ka[i] = static_cast<int>(__umul24(u[1], S)) + static_cast<int>(v[1]);
+                        su += L8;
+                        sv += dv;
                     }
 #pragma unroll
                     for (int i = 0; i < kBinBatch; ++i) {
-                        if (rb + i >= r1) break;            // uniform over the wave
+                        if (kTail && i >= cnt) break;       // uniform over the wave
                         const int key = ka[i];
                         const bool chg = key != prev;
                         if (chg) {
@@ -804,6 +813,22 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
                         }
                         prev = key;
                     }
+                };
+                for (int rr = r0; rr < r1;) {                // uniform over the wave
+                    const int jy0 = half ? half_map(hy, rr) : rr;
+                    int py0 = pp ? my - jy0 - 1 : jy0 + my;
+                    py0 += py0 < 0 ? L : (py0 >= L ? -L : 0);
+                    int len = r1 - rr;
+                    if (half && rr < hy.h1) len = min(len, hy.h1 - rr);
+                    len = min(len, pp ? py0 + 1 : L - py0);
+                    const int dv = pp ? -L8 : L8;
+                    int su = jy0 * L8, sv = py0 * L8;
+                    const int su1 = su + (len - 1) * L8, sv1 = sv + (len - 1) * dv;
+                    int t0 = 0;
+                    for (; t0 + kBinBatch <= len; t0 += kBinBatch)
+                        batch(std::false_type{}, su, sv, dv, su1, sv1, kBinBatch);
+                    if (t0 < len) batch(std::true_type{}, su, sv, dv, su1, sv1, len - t0);
+                    rr += len;
                 }
 #pragma unroll
                 for (int j = 0; j < NODES; ++j) {
@@ -1009,11 +1034,19 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
             // (P b, P a), and the particle-hole transpose T(a, b) = bin (b, a); every LDS
             // read walks a row or a column (stride N + 1), every store a row
             const R* lj = lb + j * NS;
-            for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-                const int a = i / N, b = i - a * N;
+            // (a, b) of element i, advanced by blockDim.x elements per round without a division
+            const int bd = blockDim.x, da = bd / N, db = bd - da * N;
+            int a = static_cast<int>(threadIdx.x) / N, b = static_cast<int>(threadIdx.x) - a * N;
+            for (int i = threadIdx.x; i < NN; i += bd) {
                 const int pa = pp ? a : inv_patch(g, a), pb = pp ? b : inv_patch(g, b);
                 oj[i] = (lj[a * S + b] + (half ? lj[pb * S + pa] : R(0))) * scale[j];
                 if (oTj) oTj[i] = (lj[b * S + a] + (half ? lj[pa * S + pb] : R(0))) * scale[j];
+                a += da;
+                b += db;
+                if (b >= N) {
+                    b -= N;
+                    ++a;
+                }
             }
         } else if (oTj) {
             for (int i = threadIdx.x; i < NN; i += blockDim.x) {
