@@ -426,8 +426,8 @@ __device__ inline double2 flip(double2 v) { return make_double2(-v.x, -v.y); }
 //   phi[a,b] = (a s_a - b s_b)/(a - b) = 4 (a e_a p_b^2 - b e_b p_a^2) / ((a - b) p_a^2 p_b^2)
 // (p in [1, 2]: one reciprocal instead of three).  Arguments: tp = 1/2T, tq = 1/2T, or -1/2T
 // for particle-particle (b = -xv/2T), and ce = -log2(e)/T, so that e_a = exp2(ce |xu|).
-// phi', phi3 and the trapezoid are evaluated only when a lane of the wave has |a - b| < 0.05
-// (the branch is uniform over the wave), with tanh entering only as |a| tanh|a| and tanh^2.
+// phi', phi3 and the trapezoid are evaluated for the lanes with |a - b| < 0.05 only (a branch
+// the wave skips when none has), with tanh entering only as |a| tanh|a| and tanh^2.
 __device__ inline float pair_weight_q(float xu, float xv, float tp, float tq, float ce) {
     const float a = xu * tp, b = xv * tq;
     const float ea = __builtin_amdgcn_exp2f(ce * fabsf(xu));
@@ -438,7 +438,7 @@ __device__ inline float pair_weight_q(float xu, float xv, float tp, float tq, fl
     const float num = (a * ea) * pb2 - (b * eb) * pa2;
     float w = num * __builtin_amdgcn_rcpf(d * pa2 * pb2);
     const bool near = fabsf(d) < 0.05f;
-    if (__ballot(near)) {                              // every lane computes, the near ones keep it
+    if (near) {
         const float ra = __builtin_amdgcn_rcpf(pa), rb = __builtin_amdgcn_rcpf(pb);
         const float sa = ea * ra * ra, sb = eb * rb * rb;       // sech^2 / 4
         const float ta = (1.0f - ea) * ra, tb = (1.0f - eb) * rb;   // tanh|a|, tanh|b|
@@ -446,8 +446,7 @@ __device__ inline float pair_weight_q(float xu, float xv, float tp, float tq, fl
         const float d1 = sa * (1.0f - 2.0f * xa) + sb * (1.0f - 2.0f * xb);
         const float d3 = sa * (-6.0f * (1.0f - 3.0f * qa) + 8.0f * xa * (2.0f - 3.0f * qa)) +
                          sb * (-6.0f * (1.0f - 3.0f * qb) + 8.0f * xb * (2.0f - 3.0f * qb));
-        const float ws = 0.5f * d1 - (d * d) * d3 * (1.0f / 24.0f);
-        if (near) w = ws;
+        w = 0.5f * d1 - (d * d) * d3 * (1.0f / 24.0f);
     }
     return w;
 }
@@ -463,8 +462,8 @@ __device__ inline double pair_weight(double xu, double xv, double twoT, bool pp)
 // cancellation.
 // Near the diagonal (|a - b| < 0.05) the trapezoid value with its end correction,
 //   tanh[a,b] = (s_a + s_b)/2 - (a-b)^2 (s_a (6 t_a^2 - 2) + s_b (6 t_b^2 - 2))/24 + O((a-b)^4),
-// with s = sech^2, t = tanh (the third derivative of tanh is sech^2 (6 tanh^2 - 2)), taken
-// only when a lane of the wave needs it.
+// with s = sech^2, t = tanh (the third derivative of tanh is sech^2 (6 tanh^2 - 2)), for the
+// lanes that need it only.
 __device__ inline float pair_chi(float xu, float xv, float inv2T, bool pp) {
     const float a = xu * inv2T;
     const float b0 = xv * inv2T;
@@ -477,12 +476,10 @@ __device__ inline float pair_chi(float xu, float xv, float inv2T, bool pp) {
     const float d = a - b;
     float w = diff * __builtin_amdgcn_rcpf(d);
     const bool near = fabsf(d) < 0.05f;
-    if (__ballot(near)) {
-        if (near) {
-            const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;
-            const float c3 = sa * (6.0f * ta * ta - 2.0f) + sb * (6.0f * tb * tb - 2.0f);
-            w = 0.5f * (sa + sb) - (d * d) * c3 * (1.0f / 24.0f);
-        }
+    if (near) {
+        const float sa = 4.0f * ea * ra * ra, sb = 4.0f * eb * rb * rb;
+        const float c3 = sa * (6.0f * ta * ta - 2.0f) + sb * (6.0f * tb * tb - 2.0f);
+        w = 0.5f * (sa + sb) - (d * d) * c3 * (1.0f / 24.0f);
     }
     return w;
 }
@@ -629,6 +626,7 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
                                  int nn, R* bins, R* binsT, size_t set_bins, size_t set_binsT,
                                  R* lb) {
     static_assert(kMode == 0 || NODES == 1, "several nodes per block need the LDS bins");
+    static_assert(NODES <= 2, "a block's last node group holds NODES or one node");
     const int N = g.N, NN = g.NN, L = g.L, np = g.np;
     // LDS bin rows have stride N + 1, so the column walks of the store fall on distinct banks
     const int S = kMode == 0 ? N + 1 : N, NS = kMode == 0 ? N * (N + 1) : NN;
@@ -757,85 +755,89 @@ __device__ inline void bins_part(const DevGeom& g, int f, int r, const double (&
             // resource word 3: raw buffer with a 32-bit data format (gfx9 encoding)
             const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<int2*>(g.xp), 0, np * 8, 0x00020000);
-            const int wave0 = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) & ~63);
-            for (int it0 = wave0; it0 < L * nseg; it0 += BT) {
-                const int sg = it0 / L;
-                const int jx = it0 - sg * L + lane;
-                const int r0 = sg * seglen, r1 = min(r0 + seglen, nrow);
-                int px = pp ? mx - jx - 1 : jx + mx;
-                px += px < 0 ? L : (px >= L ? -L : 0);
-                const unsigned ou = static_cast<unsigned>(jx) * 8u, ov = static_cast<unsigned>(px) * 8u;
-                int prev = 0;
-                R run[NODES];
-#pragma unroll
-                for (int j = 0; j < NODES; ++j) run[j] = R(0);
-                // The segment in pieces over which the row and the partner row each advance
-                // by one per step (a piece ends at the pairing's jump from visited row h1 to
-                // grid row c + 1 and where the partner row wraps), so a step's two row
-                // offsets are the previous ones plus constants.  Full batches of a piece add
-                // every point; the last, partial one repeats the piece's last row in its
-                // unused slots and stops at the piece's end.
-                const int L8 = L * 8;
-                // one batch: kTail = false, kBinBatch rows; true, cnt < kBinBatch rows
-                auto batch = [&](auto tail, int& su, int& sv, int dv, int su1, int sv1, int cnt) {
-                    constexpr bool kTail = decltype(tail)::value;
-                    R xu[kBinBatch], xv[kBinBatch];
-                    int ka[kBinBatch];
-#pragma unroll
-                    for (int i = 0; i < kBinBatch; ++i) {
-                        const int oy = kTail ? min(su, su1) : su;
-                        const int oq = kTail ? (pp ? max(sv, sv1) : min(sv, sv1)) : sv;
-                        const auto u = __builtin_amdgcn_raw_buffer_load_b64(xr, ou, oy, 0);
-                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, ov, oq, 0);
-                        xu[i] = __int_as_float(static_cast<int>(u[0]));
-                        xv[i] = __int_as_float(static_cast<int>(v[0]));
-                        ka[i] = static_cast<int>(__umul24(u[1], S)) + static_cast<int>(v[1]);
-                        su += L8;
-                        sv += dv;
-                    }
-#pragma unroll
-                    for (int i = 0; i < kBinBatch; ++i) {
-                        if (kTail && i >= cnt) break;       // uniform over the wave
-                        const int key = ka[i];
-                        const bool chg = key != prev;
-                        if (chg) {
-#pragma unroll
-                            for (int j = 0; j < NODES; ++j) {
-                                if (j >= nn) break;        // uniform over the block
-                                atomicAdd(&acc[j * NS + prev], run[j]);
+            // the walk for KN nodes (all of a block's nodes, or one for the last group)
+            auto walk64 = [&](auto kn) {
+                constexpr int KN = decltype(kn)::value;
+                const int wave0 = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) & ~63);
+                for (int it0 = wave0; it0 < L * nseg; it0 += BT) {
+                    const int sg = it0 / L;
+                    const int jx = it0 - sg * L + lane;
+                    const int r0 = sg * seglen, r1 = min(r0 + seglen, nrow);
+                    int px = pp ? mx - jx - 1 : jx + mx;
+                    px += px < 0 ? L : (px >= L ? -L : 0);
+                    const unsigned ou = static_cast<unsigned>(jx) * 8u, ov = static_cast<unsigned>(px) * 8u;
+                    int prev = 0;
+                    R run[KN];
+    #pragma unroll
+                    for (int j = 0; j < KN; ++j) run[j] = R(0);
+                    // The segment in pieces over which the row and the partner row each advance
+                    // by one per step (a piece ends at the pairing's jump from visited row h1 to
+                    // grid row c + 1 and where the partner row wraps), so a step's two row
+                    // offsets are the previous ones plus constants.  Full batches of a piece add
+                    // every point; the last, partial one repeats the piece's last row in its
+                    // unused slots and stops at the piece's end.
+                    const int L8 = L * 8;
+                    // one batch: kTail = false, kBinBatch rows; true, cnt < kBinBatch rows
+                    auto batch = [&](auto tail, int& su, int& sv, int dv, int su1, int sv1, int cnt) {
+                        constexpr bool kTail = decltype(tail)::value;
+                        R xu[kBinBatch], xv[kBinBatch];
+                        int ka[kBinBatch];
+    #pragma unroll
+                        for (int i = 0; i < kBinBatch; ++i) {
+                            const int oy = kTail ? min(su, su1) : su;
+                            const int oq = kTail ? (pp ? max(sv, sv1) : min(sv, sv1)) : sv;
+                            const auto u = __builtin_amdgcn_raw_buffer_load_b64(xr, ou, oy, 0);
+                            const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, ov, oq, 0);
+                            xu[i] = __int_as_float(static_cast<int>(u[0]));
+                            xv[i] = __int_as_float(static_cast<int>(v[0]));
+                            ka[i] = static_cast<int>(__umul24(u[1], S)) + static_cast<int>(v[1]);
+                            su += L8;
+                            sv += dv;
+                        }
+    #pragma unroll
+                        for (int i = 0; i < kBinBatch; ++i) {
+                            if (kTail && i >= cnt) break;       // uniform over the wave
+                            const int key = ka[i];
+                            const bool chg = key != prev;
+                            if (chg) {
+    #pragma unroll
+                                for (int j = 0; j < KN; ++j) {
+                                    atomicAdd(&acc[j * NS + prev], run[j]);
+                                }
                             }
+    #pragma unroll
+                            for (int j = 0; j < KN; ++j) {
+                                const R w = weight(xu[i], xv[i], j);
+                                run[j] = (chg ? R(0) : run[j]) + w;
+                            }
+                            prev = key;
                         }
-#pragma unroll
-                        for (int j = 0; j < NODES; ++j) {
-                            if (j >= nn) break;            // uniform over the block
-                            const R w = weight(xu[i], xv[i], j);
-                            run[j] = (chg ? R(0) : run[j]) + w;
-                        }
-                        prev = key;
+                    };
+                    for (int rr = r0; rr < r1;) {                // uniform over the wave
+                        const int jy0 = half ? half_map(hy, rr) : rr;
+                        int py0 = pp ? my - jy0 - 1 : jy0 + my;
+                        py0 += py0 < 0 ? L : (py0 >= L ? -L : 0);
+                        int len = r1 - rr;
+                        if (half && rr < hy.h1) len = min(len, hy.h1 - rr);
+                        len = min(len, pp ? py0 + 1 : L - py0);
+                        const int dv = pp ? -L8 : L8;
+                        int su = jy0 * L8, sv = py0 * L8;
+                        const int su1 = su + (len - 1) * L8, sv1 = sv + (len - 1) * dv;
+                        int t0 = 0;
+                        for (; t0 + kBinBatch <= len; t0 += kBinBatch)
+                            batch(std::false_type{}, su, sv, dv, su1, sv1, kBinBatch);
+                        if (t0 < len) batch(std::true_type{}, su, sv, dv, su1, sv1, len - t0);
+                        rr += len;
                     }
-                };
-                for (int rr = r0; rr < r1;) {                // uniform over the wave
-                    const int jy0 = half ? half_map(hy, rr) : rr;
-                    int py0 = pp ? my - jy0 - 1 : jy0 + my;
-                    py0 += py0 < 0 ? L : (py0 >= L ? -L : 0);
-                    int len = r1 - rr;
-                    if (half && rr < hy.h1) len = min(len, hy.h1 - rr);
-                    len = min(len, pp ? py0 + 1 : L - py0);
-                    const int dv = pp ? -L8 : L8;
-                    int su = jy0 * L8, sv = py0 * L8;
-                    const int su1 = su + (len - 1) * L8, sv1 = sv + (len - 1) * dv;
-                    int t0 = 0;
-                    for (; t0 + kBinBatch <= len; t0 += kBinBatch)
-                        batch(std::false_type{}, su, sv, dv, su1, sv1, kBinBatch);
-                    if (t0 < len) batch(std::true_type{}, su, sv, dv, su1, sv1, len - t0);
-                    rr += len;
+    #pragma unroll
+                    for (int j = 0; j < KN; ++j) {
+                        atomicAdd(&acc[j * NS + prev], run[j]);
+                    }
                 }
-#pragma unroll
-                for (int j = 0; j < NODES; ++j) {
-                    if (j >= nn) break;                    // uniform over the block
-                    atomicAdd(&acc[j * NS + prev], run[j]);
-                }
-            }
+            };
+            if constexpr (NODES == 1) walk64(std::integral_constant<int, 1>{});
+            else if (nn == NODES) walk64(std::integral_constant<int, NODES>{});
+            else walk64(std::integral_constant<int, 1>{});   // nn == 1 (NODES <= 2)
             walked = true;
         }
         if (!walked)
