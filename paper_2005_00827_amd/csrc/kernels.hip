@@ -2477,6 +2477,19 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
         return;
     }
     constexpr bool two = TWO;                          // kind == 2 exactly for this launch
+    // perm_o of every operation in LDS (a wave's pairs may belong to different operations),
+    // operation 0 as the identity
+    __shared__ int pms[8 * 128];
+    {
+        int pv[4];                                     // loads first (valid addresses), then stores
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pv[v] = g.perm[min(static_cast<int>(threadIdx.x) + 256 * v, 8 * N - 1)];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = threadIdx.x + 256 * v;
+            if (i < 8 * N) pms[i] = i < N ? i : pv[v];
+        }
+    }
     const int nq = kind == 0 ? g.nP : g.nD;
     const YT* Ya = (kind == 0 ? y1 : (kind == 1 ? y2 : y3)) + (static_cast<size_t>(f) * nq + r) * NN;
     const YT* Yb = y4 + (static_cast<size_t>(f) * nq + r) * NN;
@@ -2484,7 +2497,8 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
     // values down the staged columns (consecutive lanes, consecutive x'); zero past N
     // (N % 16 == 0: a task lies wholly below N or at or above it)
     auto stage = [&](const YT* Y0, const YT* Y1, bool both) {
-        for (int task = threadIdx.x; task < 128 * (128 / 8); task += 256) {
+#pragma unroll
+        for (int task = threadIdx.x; task < 128 * (128 / 8); task += 256) {   // 8 rounds
             const int x = task & 127, nb = 8 * (task >> 7);
             const bool ok = x < N && nb < N;
             const size_t ix = static_cast<size_t>(min(x, N - 1)) * N + min(nb, N - 8);
@@ -2511,7 +2525,30 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
             }
         }
     };
-    if constexpr (!kSplit) stage(Ya, Yb, two);
+    // bf16: every task's loads first (8 rounds of 16 bytes per product, valid addresses), then
+    // the LDS writes, so the block waits for one memory round trip
+    auto stage_bf16 = [&](const YT* Y0, const YT* Y1) {
+        constexpr int kR = 128 * (128 / 8) / 256;
+        fm_bf8 h0[kR], h1[TWO ? kR : 1];
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const int task = threadIdx.x + 256 * k, x = task & 127, nb = 8 * (task >> 7);
+            const size_t ix = static_cast<size_t>(min(x, N - 1)) * N + min(nb, N - 8);
+            h0[k] = *reinterpret_cast<const fm_bf8*>(Y0 + ix);
+            if constexpr (TWO) h1[k] = *reinterpret_cast<const fm_bf8*>(Y1 + ix);
+        }
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const int task = threadIdx.x + 256 * k, x = task & 127, nb = 8 * (task >> 7);
+            const bool ok = x < N && nb < N;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                Bs[(nb + e) * KBS + x] = ok ? h0[k][e] : static_cast<__bf16>(0.f);
+                if constexpr (TWO) Bs[PLANE + (nb + e) * KBS + x] = ok ? h1[k][e] : static_cast<__bf16>(0.f);
+            }
+        }
+    };
+    if constexpr (!kSplit) stage_bf16(Ya, Yb);
     else stage(Ya, Ya, false);
     // the wave's tile rows: pairs 16 w .. 16 w + 15 of the record; lane % 16 the row
     const int lane = threadIdx.x & 63;
@@ -2523,19 +2560,23 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
     // contiguous in x: V(u,w,x) = v0[u][w][x], V(x,u,w) = vc[w][u][x], V(u,x,w) = va[w][u][x]
     const size_t base = static_cast<size_t>(f) * N3 +
                         (kind == 0 ? static_cast<size_t>(xy) * N : static_cast<size_t>(w) * NN + static_cast<size_t>(u) * N);
-    const int* pm = g.perm + o * N;
+    const int* pm = pms + o * N;
+    __syncthreads();                                   // perm_o in LDS; every thread
     float a1[KE], a2[TWO ? KE : 1];
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
         const int xr = mfma_k<1>(e, lane);              // x' of the lane's e-th value
         const bool ok = en >= 0 && xr < N;
-        const int x = o ? pm[min(xr, N - 1)] : min(xr, N - 1);
+        const int x = pm[min(xr, N - 1)];
+        // every address is valid (x < N, and a padding lane reads pair 0), so the loads are
+        // issued unconditionally and the values selected
         if constexpr (TWO) {
             const float c = vc[base + x], b = va[base + x];
             a1[e] = ok ? c - 2.f * b : 0.f;
             a2[e] = ok ? b : 0.f;
         } else {
-            a1[e] = ok ? (kind == 0 ? v0[base + x] : vc[base + x]) : 0.f;
+            const float c = (kind == 0 ? v0 : vc)[base + x];
+            a1[e] = ok ? c : 0.f;
         }
     }
     const AFrag<2, KE> A1 = make_afrag<2, KE>(a1);
@@ -2549,7 +2590,7 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int n = 16 * t + 4 * (lane >> 4) + q;
-            const int cn = o ? pm[n] : n;
+            const int cn = pm[n];
             Kf[static_cast<size_t>(xy) * N + cn] = kind == 0 ? -c[q] : c[q];
         }
     };
