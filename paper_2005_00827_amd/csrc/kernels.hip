@@ -1865,21 +1865,21 @@ constexpr int stage_group(int per) {
 // Stages B'_o[k'][n] = fac(k) Vsrc[k][n0 + n], k = perm_o k' (fac from the stage's Z), for
 // one or two operand slabs into the block's chunk(s).  Loads are issued in groups before
 // any of them is used, so a thread has a group in flight instead of one.
-template <int kM, int KE, int NT, bool kTwo>
+template <int kM, int KE, int NT, bool kTwo, int BT = kThreads>
 __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const float* V1,
                                      const int* pm, const float* zs, float zg, float wg,
                                      float al, float be, int N, int n0) {
     constexpr int S = b_stride<NT>(), KP = 4 * KE, W = 16 * NT, KBS = KP + 8;
     constexpr int kBytes = kM == 0 ? KP * S * 4 : W * KBS * 2 * kM;
-    constexpr int kPer = KP * W / kThreads;
-    static_assert(KP * W % kThreads == 0, "staging covers the chunk in whole rounds");
+    constexpr int kPer = KP * W / BT > 0 ? KP * W / BT : 1;
+    static_assert(kM > 0 || KP * W % BT == 0, "staging covers the chunk in whole rounds");
     constexpr int kGrp = stage_group(kPer);
     if constexpr (kM > 0) {
         // bf16 planes [n][k']: a task is 8 consecutive k' of one column n, loaded together
         // (each load coalesced over the wave's columns) and stored as one 16-byte row
         // segment per plane
         constexpr int kTasks = KP / 8 * W;
-        constexpr int kTPT = (kTasks + kThreads - 1) / kThreads;
+        constexpr int kTPT = (kTasks + BT - 1) / BT;
         constexpr int R = kTPT < 2 ? kTPT : 2;          // tasks whose loads are in flight
         __bf16* Bh = reinterpret_cast<__bf16*>(Braw);
 #pragma unroll 1
@@ -1888,7 +1888,7 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
             int kq[R][8];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const int task = min(static_cast<int>(threadIdx.x) + (j0 + j) * kThreads, kTasks - 1);
+                const int task = min(static_cast<int>(threadIdx.x) + (j0 + j) * BT, kTasks - 1);
                 const int n = task % W, kb = 8 * (task / W);
                 const int nc = min(n0 + n, N - 1);
 #pragma unroll
@@ -1901,7 +1901,7 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
             }
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const int task = static_cast<int>(threadIdx.x) + (j0 + j) * kThreads;
+                const int task = static_cast<int>(threadIdx.x) + (j0 + j) * BT;
                 if (task >= kTasks) continue;
                 const int n = task % W, kb = 8 * (task / W);
                 const bool nok = n0 + n < N;
@@ -1936,7 +1936,7 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
         int kq[kGrp];
 #pragma unroll
         for (int j = 0; j < kGrp; ++j) {
-            const int e = threadIdx.x + (j0 + j) * kThreads;
+            const int e = threadIdx.x + (j0 + j) * BT;
             const int k = e / W, n = e - k * W;
             const int kp = pm[min(k, N - 1)];
             kq[j] = kp;
@@ -1946,7 +1946,7 @@ __device__ inline void stage_orbit_b(unsigned char* Braw, const float* V0, const
         }
 #pragma unroll
         for (int j = 0; j < kGrp; ++j) {
-            const int e = threadIdx.x + (j0 + j) * kThreads;
+            const int e = threadIdx.x + (j0 + j) * BT;
             const int k = e / W, n = e - k * W;
             const bool ok = k < N && n0 + n < N;
             const float zk = zs[kq[j]], wk = zs[N + kq[j]];
@@ -2164,6 +2164,126 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
                                               toff, chunk * 16 * NT, al, be,
                                               Z_stage + static_cast<size_t>(f) * 2 * N, Braw, pms, zs,
                                               qs, msk);
+}
+
+// Orbit kernel for point-group-invariant states with bf16 products: only operation 0 yields
+// products (the representatives' own), so B'_0 of a (flow, channel, bin row p, column chunk)
+// serves every representative tile.  A 1024-thread block stages it once and its 16 waves
+// take the tiles, wave w tiles w and w + 16 (then w + 32, w + 48, ...), both tiles' A rows
+// (row p of the 16 representatives' bins) loaded together and kept for the direct channel's
+// second product.  Products and stores are the orbit kernel's for
+// operation 0.  Grid: unit u = (flow, channel, p), numbered (flow * 3 + channel) N + p; its
+// nchunk blocks go to one XCD:
+//   id = (u / 8) * 8 nchunk + chunk * 8 + u % 8.
+constexpr int kSymThreads = 1024;
+
+template <int kM, int KE, int NT>
+__device__ inline void mfma_bt(const AFrag<kM, KE>& A, const __bf16* Bh, fm_f4 (&c)[NT], int lane);
+
+template <int KE, int NT, bool kTwo>
+__device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, const float* Vs0,
+                                       const float* Vs1, __bf16* Y0, __bf16* Y1, int p, int nt,
+                                       int toff, int n0, float al, float be, const double* Zf,
+                                       unsigned char* Braw, int* pm0, float* zs) {
+    constexpr int kM = 1, KBS = 4 * KE + 8, W = 16 * NT;
+    constexpr int kBytes = W * KBS * 2;
+    constexpr int kWaves = kSymThreads / 64;
+    const int N = g.N, NN = g.NN;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int col = lane & 15;
+    if (static_cast<int>(threadIdx.x) < N) {
+        pm0[threadIdx.x] = g.perm[threadIdx.x];
+        zs[threadIdx.x] = static_cast<float>(Zf[threadIdx.x]);
+        zs[N + threadIdx.x] = static_cast<float>(Zf[N + threadIdx.x]);
+    }
+    __syncthreads();                                   // tables; every thread of the block
+    const int grp = pm0[p];
+    stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw, Vs0 + static_cast<size_t>(grp) * NN,
+                                                 Vs1 + static_cast<size_t>(grp) * NN, pm0, zs,
+                                                 zs[grp], zs[N + grp], al, be, N, n0);
+    __syncthreads();                                   // B'_0 staged; every thread
+    auto arow = [&](int t) {                           // row p of the bins of tile t's row col
+        const int rr = g.orb_rows[16 * (toff + min(t, nt - 1)) + col];
+        return Bf + static_cast<size_t>(max(rr, 0)) * NN + static_cast<size_t>(p) * N;
+    };
+    for (int t0 = wv; t0 < nt; t0 += 2 * kWaves) {     // uniform over the wave
+        float a[2][KE];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
+        AFrag<kM, KE> A[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
+#pragma unroll
+        for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
+            const __bf16* Bw = reinterpret_cast<const __bf16*>(Braw + w * kBytes);
+            __bf16* Yw = w ? Y1 : Y0;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int t = t0 + j * kWaves;
+                if (t >= nt) continue;
+                if (!(g.orb_mask[toff + t] & 1)) continue;
+                const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
+                fm_f4 c[NT];
+#pragma unroll
+                for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+                mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
+                if (q >= 0) {
+                    __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+#pragma unroll
+                    for (int u = 0; u < NT; ++u) {
+                        const int n = n0 + 16 * u + 4 * (lane >> 4);
+                        if ((N & 3) == 0) {
+                            if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int KE, int NT>
+__global__ void __launch_bounds__(kSymThreads) k_y_orb_sym(DevGeom g, const FlowState* fs,
+                                                           const double* Z_stage, const double* zw,
+                                                           const float* bins, const float* binsT,
+                                                           YArgs<float> args, int nchunk, int nu) {
+    constexpr int KBS = 4 * KE + 8, W = 16 * NT, kBytes = W * KBS * 2;
+    __shared__ __align__(16) unsigned char Braw[2 * kBytes];
+    __shared__ int pm0[128];
+    __shared__ float zs[256];
+    const int id = blockIdx.x;
+    const int u = (id / (8 * nchunk)) * 8 + id % 8;
+    const int chunk = (id % (8 * nchunk)) / 8;
+    if (u >= nu) return;                              // padding of the last 8 units
+    const int N = g.N, NN = g.NN;
+    const int p = u % N, ch = (u / N) % 3, f = u / (3 * N);
+    if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
+    const int cc = ch == 0 ? 0 : 1;
+    const int nt = g.orb_nt[cc], toff = cc == 0 ? 0 : g.orb_nt[0];
+    const int M = ch == 0 ? g.nP : g.nD;
+    const int nR = g.nRp + g.nRd;
+    const int fb = bin_flow(fs, f);
+    const float* Bf = ch == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
+                              : bins + static_cast<size_t>(fb) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
+    const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
+    const size_t N3 = static_cast<size_t>(NN) * N;
+    const size_t yoff = static_cast<size_t>(f) * M * NN;
+    const double* Zf = Z_stage + static_cast<size_t>(f) * 2 * N;
+    if (ch == 2)
+        y_orb_sym_block<KE, NT, true>(g, Bf, args.Vs[2] + f * N3, args.Vs[3] + f * N3,
+                                      reinterpret_cast<__bf16*>(args.Y[2]) + yoff,
+                                      reinterpret_cast<__bf16*>(args.Y[3]) + yoff, p, nt, toff,
+                                      chunk * W, al, be, Zf, Braw, pm0, zs);
+    else
+        y_orb_sym_block<KE, NT, false>(g, Bf, args.Vs[ch] + f * N3, args.Vs[ch] + f * N3,
+                                       reinterpret_cast<__bf16*>(args.Y[ch]) + yoff,
+                                       reinterpret_cast<__bf16*>(args.Y[ch]) + yoff, p, nt, toff,
+                                       chunk * W, al, be, Zf, Braw, pm0, zs);
 }
 
 // ------------------------------------------------------------------------------------
@@ -3524,6 +3644,20 @@ void y_mfma_cls(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
 template <int kM, int KE, int NT, int TPW>
 void y_mfma_orb_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
                    const YArgs<float>& a) {
+    if constexpr (kM == 1) {
+        if (g.sym) {                                   // operation 0 only: one staging per unit
+            const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
+            const long nu = 3L * g.N * nf;
+            const long nblocks = (nu + 7) / 8 * 8 * nchunk;
+            if (nblocks == 0) return;
+            hipLaunchKernelGGL((k_y_orb_sym<KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+                               dim3(kSymThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
+                               static_cast<const float*>(b.bins),
+                               static_cast<const float*>(b.binsT), a, nchunk,
+                               static_cast<int>(nu));
+            return;
+        }
+    }
     const int ntmax = g.orb_nt[0] > g.orb_nt[1] ? g.orb_nt[0] : g.orb_nt[1];
     const int bx = (ntmax + 4 * TPW - 1) / (4 * TPW);
     const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
