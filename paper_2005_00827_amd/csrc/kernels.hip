@@ -2705,13 +2705,22 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
     __syncthreads();                                   // Y_r^T staged; every thread
     const bool active = 16 * wv < cnt;                 // a wave with pairs (uniform)
     const int col = lane & 15;
+    // a lane's four consecutive n' go to columns perm_o n'; where those are four consecutive
+    // columns starting at a multiple of 4 (ascending, or descending for a reflection) they are
+    // one 16-byte store, else four
     auto store = [&](int t, const fm_f4& c) {
         if (en < 0) return;
+        const int n = 16 * t + 4 * (lane >> 4);
+        const fm_f4 v = kind == 0 ? -c : c;
+        const int c0 = pm[n], c3 = pm[n + 3];
+        float* row = Kf + static_cast<size_t>(xy) * N;
+        if (c3 == c0 + 3 && (c0 & 3) == 0 && pm[n + 1] == c0 + 1 && pm[n + 2] == c0 + 2) {
+            *reinterpret_cast<fm_f4*>(row + c0) = v;
+        } else if (c0 == c3 + 3 && (c3 & 3) == 0 && pm[n + 1] == c3 + 2 && pm[n + 2] == c3 + 1) {
+            *reinterpret_cast<fm_f4*>(row + c3) = fm_f4{v[3], v[2], v[1], v[0]};
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int n = 16 * t + 4 * (lane >> 4) + q;
-            const int cn = pm[n];
-            Kf[static_cast<size_t>(xy) * N + cn] = kind == 0 ? -c[q] : c[q];
+            for (int q = 0; q < 4; ++q) row[pm[n + q]] = v[q];
         }
     };
     if constexpr (!kSplit) {
