@@ -2168,13 +2168,12 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
 
 // Orbit kernel for point-group-invariant states with bf16 products: only operation 0 yields
 // products (the representatives' own), so B'_0 of a (flow, channel, bin row p, column chunk)
-// serves every representative tile.  A 1024-thread block stages it once and its 16 waves
-// take the tiles, wave w tiles w and w + 16 (then w + 32, w + 48, ...), both tiles' A rows
-// (row p of the 16 representatives' bins) loaded together and kept for the direct channel's
-// second product.  Products and stores are the orbit kernel's for
-// operation 0.  Grid: unit u = (flow, channel, p), numbered (flow * 3 + channel) N + p; its
-// nchunk blocks go to one XCD:
-//   id = (u / 8) * 8 nchunk + chunk * 8 + u % 8.
+// serves every representative tile.  A 1024-thread block takes one (flow, channel, p).  For
+// each column chunk all its threads stage B'_0 once, and its 16 waves take the tiles, wave w
+// tiles w and w + 16 (then w + 32, w + 48, ...); both tiles' A rows (row p of the 16
+// representatives' bins) are loaded together once and kept in registers for every chunk and
+// for the direct channel's second product.  Products and stores are the orbit kernel's for
+// operation 0.  Grid: one block per unit u = (flow * 3 + channel) N + p.
 constexpr int kSymThreads = 1024;
 
 template <int kM, int KE, int NT>
@@ -2183,7 +2182,7 @@ __device__ inline void mfma_bt(const AFrag<kM, KE>& A, const __bf16* Bh, fm_f4 (
 template <int KE, int NT, bool kTwo>
 __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, const float* Vs0,
                                        const float* Vs1, __bf16* Y0, __bf16* Y1, int p, int nt,
-                                       int toff, int n0, float al, float be, const double* Zf,
+                                       int toff, int nchunk, float al, float be, const double* Zf,
                                        unsigned char* Braw, int* pm0, float* zs) {
     constexpr int kM = 1, KBS = 4 * KE + 8, W = 16 * NT;
     constexpr int kBytes = W * KBS * 2;
@@ -2199,46 +2198,53 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, const 
     }
     __syncthreads();                                   // tables; every thread of the block
     const int grp = pm0[p];
-    stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw, Vs0 + static_cast<size_t>(grp) * NN,
-                                                 Vs1 + static_cast<size_t>(grp) * NN, pm0, zs,
-                                                 zs[grp], zs[N + grp], al, be, N, n0);
-    __syncthreads();                                   // B'_0 staged; every thread
     auto arow = [&](int t) {                           // row p of the bins of tile t's row col
         const int rr = g.orb_rows[16 * (toff + min(t, nt - 1)) + col];
         return Bf + static_cast<size_t>(max(rr, 0)) * NN + static_cast<size_t>(p) * N;
     };
-    for (int t0 = wv; t0 < nt; t0 += 2 * kWaves) {     // uniform over the wave
-        float a[2][KE];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
+    for (int tb = 0; tb < nt; tb += 2 * kWaves) {      // uniform over the block
+        const int t0 = tb + wv;
         AFrag<kM, KE> A[2];
+        for (int chunk = 0; chunk < nchunk; ++chunk) { // uniform over the block
+            const int n0 = chunk * W;
+            if (tb + chunk > 0) __syncthreads();       // the previous chunk's B'_0 consumed
+            stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw, Vs0 + static_cast<size_t>(grp) * NN,
+                                                         Vs1 + static_cast<size_t>(grp) * NN, pm0,
+                                                         zs, zs[grp], zs[N + grp], al, be, N, n0);
+            __syncthreads();                           // B'_0 staged; every thread
+            if (chunk == 0) {                          // the tiles' A rows, for every chunk
+                float a[2][KE];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
+                for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
 #pragma unroll
-        for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
-            const __bf16* Bw = reinterpret_cast<const __bf16*>(Braw + w * kBytes);
-            __bf16* Yw = w ? Y1 : Y0;
+                for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
+            }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int t = t0 + j * kWaves;
-                if (t >= nt) continue;
-                if (!(g.orb_mask[toff + t] & 1)) continue;
-                const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
-                fm_f4 c[NT];
+            for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
+                const __bf16* Bw = reinterpret_cast<const __bf16*>(Braw + w * kBytes);
+                __bf16* Yw = w ? Y1 : Y0;
 #pragma unroll
-                for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
-                mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
-                if (q >= 0) {
-                    __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+                for (int j = 0; j < 2; ++j) {
+                    const int t = t0 + j * kWaves;
+                    if (t >= nt) continue;
+                    if (!(g.orb_mask[toff + t] & 1)) continue;
+                    const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
+                    fm_f4 c[NT];
 #pragma unroll
-                    for (int u = 0; u < NT; ++u) {
-                        const int n = n0 + 16 * u + 4 * (lane >> 4);
-                        if ((N & 3) == 0) {
-                            if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
-                        } else {
+                    for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+                    mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
+                    if (q >= 0) {
+                        __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
 #pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
+                        for (int u = 0; u < NT; ++u) {
+                            const int n = n0 + 16 * u + 4 * (lane >> 4);
+                            if ((N & 3) == 0) {
+                                if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
+                            }
                         }
                     }
                 }
@@ -2252,14 +2258,12 @@ __global__ void __launch_bounds__(kSymThreads) k_y_orb_sym(DevGeom g, const Flow
                                                            const double* Z_stage, const double* zw,
                                                            const float* bins, const float* binsT,
                                                            YArgs<float> args, int nchunk, int nu) {
-    constexpr int KBS = 4 * KE + 8, W = 16 * NT, kBytes = W * KBS * 2;
+    constexpr int KBS = 4 * KE + 8, kBytes = 16 * NT * KBS * 2;
     __shared__ __align__(16) unsigned char Braw[2 * kBytes];
     __shared__ int pm0[128];
     __shared__ float zs[256];
-    const int id = blockIdx.x;
-    const int u = (id / (8 * nchunk)) * 8 + id % 8;
-    const int chunk = (id % (8 * nchunk)) / 8;
-    if (u >= nu) return;                              // padding of the last 8 units
+    const int u = blockIdx.x;
+    if (u >= nu) return;
     const int N = g.N, NN = g.NN;
     const int p = u % N, ch = (u / N) % 3, f = u / (3 * N);
     if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
@@ -2278,12 +2282,12 @@ __global__ void __launch_bounds__(kSymThreads) k_y_orb_sym(DevGeom g, const Flow
         y_orb_sym_block<KE, NT, true>(g, Bf, args.Vs[2] + f * N3, args.Vs[3] + f * N3,
                                       reinterpret_cast<__bf16*>(args.Y[2]) + yoff,
                                       reinterpret_cast<__bf16*>(args.Y[3]) + yoff, p, nt, toff,
-                                      chunk * W, al, be, Zf, Braw, pm0, zs);
+                                      nchunk, al, be, Zf, Braw, pm0, zs);
     else
         y_orb_sym_block<KE, NT, false>(g, Bf, args.Vs[ch] + f * N3, args.Vs[ch] + f * N3,
                                        reinterpret_cast<__bf16*>(args.Y[ch]) + yoff,
                                        reinterpret_cast<__bf16*>(args.Y[ch]) + yoff, p, nt, toff,
-                                       chunk * W, al, be, Zf, Braw, pm0, zs);
+                                       nchunk, al, be, Zf, Braw, pm0, zs);
 }
 
 // ------------------------------------------------------------------------------------
@@ -2596,7 +2600,6 @@ __global__ void __launch_bounds__(256) k_contract_mma(DevGeom g, const FlowState
         }
         return;
     }
-    constexpr bool two = TWO;                          // kind == 2 exactly for this launch
     // perm_o of every operation in LDS (a wave's pairs may belong to different operations),
     // operation 0 as the identity
     __shared__ int pms[8 * 128];
@@ -3657,9 +3660,8 @@ void y_mfma_orb_go(hipStream_t s, const DevGeom& g, const Buffers& b, int nf,
         if (g.sym) {                                   // operation 0 only: one staging per unit
             const int nchunk = (g.N + 16 * NT - 1) / (16 * NT);
             const long nu = 3L * g.N * nf;
-            const long nblocks = (nu + 7) / 8 * 8 * nchunk;
-            if (nblocks == 0) return;
-            hipLaunchKernelGGL((k_y_orb_sym<KE, NT>), dim3(static_cast<unsigned>(nblocks)),
+            if (nu == 0) return;
+            hipLaunchKernelGGL((k_y_orb_sym<KE, NT>), dim3(static_cast<unsigned>(nu)),
                                dim3(kSymThreads), 0, s, g, b.fs, b.Z_stage, b.zw_stage,
                                static_cast<const float*>(b.bins),
                                static_cast<const float*>(b.binsT), a, nchunk,
