@@ -2168,22 +2168,34 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
 
 // Orbit kernel for point-group-invariant states with bf16 products: only operation 0 yields
 // products (the representatives' own), so B'_0 of a (flow, channel, bin row p, column chunk)
-// serves every representative tile.  A 1024-thread block takes one (flow, channel, p).  For
-// each column chunk all its threads stage B'_0 once, and its 16 waves take the tiles, wave w
-// tiles w and w + 16 (then w + 32, w + 48, ...); both tiles' A rows (row p of the 16
-// representatives' bins) are loaded together once and kept in registers for every chunk and
-// for the direct channel's second product.  Products and stores are the orbit kernel's for
-// operation 0.  Grid: one block per unit u = (flow * 3 + channel) N + p.
+// serves every representative tile.  A 1024-thread block takes one (channel, p) of one flow,
+// or of two flows that read the same bins (flows of a step-sharing group sit at the same
+// stage temperatures).  Its 16 waves take the tiles, wave w tiles w and w + 16 (then w + 32,
+// w + 48, ...); both tiles' A rows (row p of the 16 representatives' bins) are loaded
+// together once and kept in registers for every chunk, every flow of the block and the
+// direct channel's second product.  For each column chunk and flow all threads stage that
+// flow's B'_0.  Products and stores are the orbit kernel's for operation 0.
+// Grid: one block per unit u = (flow * 3 + channel) N + p.  The running flows that share a
+// flow's bins are taken in pairs in index order; the block of a pair's second flow returns.
 constexpr int kSymThreads = 1024;
 
 template <int kM, int KE, int NT>
 __device__ inline void mfma_bt(const AFrag<kM, KE>& A, const __bf16* Bh, fm_f4 (&c)[NT], int lane);
 
+// One flow's operands and outputs in a symmetric phase-2a block.
+struct SymFlow {
+    const float* V0;     // operand slab base (the direct channel's first)
+    const float* V1;     // the direct channel's second operand (else = V0)
+    __bf16* Y0;          // products of the representatives
+    __bf16* Y1;          // the direct channel's second products (else = Y0)
+    const double* Z;     // the flow's Z at the stage nodes, 2N values
+    float al, be;        // stage weights of the two Z factors
+};
+
 template <int KE, int NT, bool kTwo>
-__device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, const float* Vs0,
-                                       const float* Vs1, __bf16* Y0, __bf16* Y1, int p, int nt,
-                                       int toff, int nchunk, float al, float be, const double* Zf,
-                                       unsigned char* Braw, int* pm0, float* zs) {
+__device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, SymFlow F0,
+                                       SymFlow F1, int nfl, int p, int nt, int toff,
+                                       int nchunk, unsigned char* Braw, int* pm0, float* zs) {
     constexpr int kM = 1, KBS = 4 * KE + 8, W = 16 * NT;
     constexpr int kBytes = W * KBS * 2;
     constexpr int kWaves = kSymThreads / 64;
@@ -2193,8 +2205,12 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, const 
     const int col = lane & 15;
     if (static_cast<int>(threadIdx.x) < N) {
         pm0[threadIdx.x] = g.perm[threadIdx.x];
-        zs[threadIdx.x] = static_cast<float>(Zf[threadIdx.x]);
-        zs[N + threadIdx.x] = static_cast<float>(Zf[N + threadIdx.x]);
+        zs[threadIdx.x] = static_cast<float>(F0.Z[threadIdx.x]);
+        zs[N + threadIdx.x] = static_cast<float>(F0.Z[N + threadIdx.x]);
+        if (nfl > 1) {
+            zs[256 + threadIdx.x] = static_cast<float>(F1.Z[threadIdx.x]);
+            zs[256 + N + threadIdx.x] = static_cast<float>(F1.Z[N + threadIdx.x]);
+        }
     }
     __syncthreads();                                   // tables; every thread of the block
     const int grp = pm0[p];
@@ -2207,43 +2223,52 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, const 
         AFrag<kM, KE> A[2];
         for (int chunk = 0; chunk < nchunk; ++chunk) { // uniform over the block
             const int n0 = chunk * W;
-            if (tb + chunk > 0) __syncthreads();       // the previous chunk's B'_0 consumed
-            stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw, Vs0 + static_cast<size_t>(grp) * NN,
-                                                         Vs1 + static_cast<size_t>(grp) * NN, pm0,
-                                                         zs, zs[grp], zs[N + grp], al, be, N, n0);
-            __syncthreads();                           // B'_0 staged; every thread
-            if (chunk == 0) {                          // the tiles' A rows, for every chunk
-                float a[2][KE];
+            for (int fl = 0; fl < nfl; ++fl) {         // uniform over the block
+                const float* V0 = fl ? F1.V0 : F0.V0;
+                const float* V1 = fl ? F1.V1 : F0.V1;
+                __bf16* Y0 = fl ? F1.Y0 : F0.Y0;
+                __bf16* Y1 = fl ? F1.Y1 : F0.Y1;
+                const float al = fl ? F1.al : F0.al, be = fl ? F1.be : F0.be;
+                const float* zf = zs + (fl ? 256 : 0);
+                if (tb + chunk + fl > 0) __syncthreads();   // the previous B'_0 consumed
+                stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw, V0 + static_cast<size_t>(grp) * NN,
+                                                             V1 + static_cast<size_t>(grp) * NN,
+                                                             pm0, zf, zf[grp], zf[N + grp], al, be,
+                                                             N, n0);
+                __syncthreads();                       // B'_0 staged; every thread
+                if (chunk == 0 && fl == 0) {           // the tiles' A rows, for every chunk and flow
+                    float a[2][KE];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
+                    for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
 #pragma unroll
-                for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
-            }
+                    for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
+                }
 #pragma unroll
-            for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
-                const __bf16* Bw = reinterpret_cast<const __bf16*>(Braw + w * kBytes);
-                __bf16* Yw = w ? Y1 : Y0;
+                for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
+                    const __bf16* Bw = reinterpret_cast<const __bf16*>(Braw + w * kBytes);
+                    __bf16* Yw = w ? Y1 : Y0;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int t = t0 + j * kWaves;
-                    if (t >= nt) continue;
-                    if (!(g.orb_mask[toff + t] & 1)) continue;
-                    const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
-                    fm_f4 c[NT];
+                    for (int j = 0; j < 2; ++j) {
+                        const int t = t0 + j * kWaves;
+                        if (t >= nt) continue;
+                        if (!(g.orb_mask[toff + t] & 1)) continue;
+                        const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
+                        fm_f4 c[NT];
 #pragma unroll
-                    for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
-                    mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
-                    if (q >= 0) {
-                        __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+                        for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+                        mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
+                        if (q >= 0) {
+                            __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
 #pragma unroll
-                        for (int u = 0; u < NT; ++u) {
-                            const int n = n0 + 16 * u + 4 * (lane >> 4);
-                            if ((N & 3) == 0) {
-                                if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
-                            } else {
+                            for (int u = 0; u < NT; ++u) {
+                                const int n = n0 + 16 * u + 4 * (lane >> 4);
+                                if ((N & 3) == 0) {
+                                    if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
+                                } else {
 #pragma unroll
-                                for (int r = 0; r < 4; ++r)
-                                    if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
+                                    for (int r = 0; r < 4; ++r)
+                                        if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
+                                }
                             }
                         }
                     }
@@ -2261,33 +2286,48 @@ __global__ void __launch_bounds__(kSymThreads) k_y_orb_sym(DevGeom g, const Flow
     constexpr int KBS = 4 * KE + 8, kBytes = 16 * NT * KBS * 2;
     __shared__ __align__(16) unsigned char Braw[2 * kBytes];
     __shared__ int pm0[128];
-    __shared__ float zs[256];
+    __shared__ float zs[512];
     const int u = blockIdx.x;
     if (u >= nu) return;
     const int N = g.N, NN = g.NN;
     const int p = u % N, ch = (u / N) % 3, f = u / (3 * N);
     if (!running(fs, f) || !args.on[ch]) return;      // uniform over the block
+    const int fb = bin_flow(fs, f);
+    // the running flows reading the same bins, in index order, are taken two at a time:
+    // this block serves f and the next such flow when f's rank among them is even
+    const int nf = nu / (3 * N);
+    int rank = 0, f2 = -1;
+    for (int k = 0; k < nf; ++k) {                     // uniform over the block
+        if (k == f || !running(fs, k) || bin_flow(fs, k) != fb) continue;
+        if (k < f) ++rank;
+        else if (f2 < 0) f2 = k;
+    }
+    if (rank & 1) return;                              // the pair's first flow's block serves f
+    const int nfl = f2 >= 0 ? 2 : 1;
     const int cc = ch == 0 ? 0 : 1;
     const int nt = g.orb_nt[cc], toff = cc == 0 ? 0 : g.orb_nt[0];
     const int M = ch == 0 ? g.nP : g.nD;
     const int nR = g.nRp + g.nRd;
-    const int fb = bin_flow(fs, f);
     const float* Bf = ch == 1 ? binsT + static_cast<size_t>(fb) * g.nRd * NN
                               : bins + static_cast<size_t>(fb) * nR * NN + (ch == 0 ? 0 : static_cast<size_t>(g.nRp) * NN);
-    const float al = static_cast<float>(zw[2 * f]), be = static_cast<float>(zw[2 * f + 1]);
     const size_t N3 = static_cast<size_t>(NN) * N;
-    const size_t yoff = static_cast<size_t>(f) * M * NN;
-    const double* Zf = Z_stage + static_cast<size_t>(f) * 2 * N;
+    auto flow = [&](int h) {
+        SymFlow F;
+        const size_t yoff = static_cast<size_t>(h) * M * NN;
+        F.V0 = args.Vs[ch] + h * N3;
+        F.V1 = args.Vs[ch == 2 ? 3 : ch] + h * N3;
+        F.Y0 = reinterpret_cast<__bf16*>(args.Y[ch]) + yoff;
+        F.Y1 = reinterpret_cast<__bf16*>(args.Y[ch == 2 ? 3 : ch]) + yoff;
+        F.Z = Z_stage + static_cast<size_t>(h) * 2 * N;
+        F.al = static_cast<float>(zw[2 * h]);
+        F.be = static_cast<float>(zw[2 * h + 1]);
+        return F;
+    };
+    const SymFlow F0 = flow(f), F1 = flow(nfl > 1 ? f2 : f);
     if (ch == 2)
-        y_orb_sym_block<KE, NT, true>(g, Bf, args.Vs[2] + f * N3, args.Vs[3] + f * N3,
-                                      reinterpret_cast<__bf16*>(args.Y[2]) + yoff,
-                                      reinterpret_cast<__bf16*>(args.Y[3]) + yoff, p, nt, toff,
-                                      nchunk, al, be, Zf, Braw, pm0, zs);
+        y_orb_sym_block<KE, NT, true>(g, Bf, F0, F1, nfl, p, nt, toff, nchunk, Braw, pm0, zs);
     else
-        y_orb_sym_block<KE, NT, false>(g, Bf, args.Vs[ch] + f * N3, args.Vs[ch] + f * N3,
-                                       reinterpret_cast<__bf16*>(args.Y[ch]) + yoff,
-                                       reinterpret_cast<__bf16*>(args.Y[ch]) + yoff, p, nt, toff,
-                                       nchunk, al, be, Zf, Braw, pm0, zs);
+        y_orb_sym_block<KE, NT, false>(g, Bf, F0, F1, nfl, p, nt, toff, nchunk, Braw, pm0, zs);
 }
 
 // ------------------------------------------------------------------------------------

@@ -220,3 +220,38 @@ def test_sym_rejects_asymmetric_per_flow_tables(torch_dev):
             f.run_batch([2.5], [1.0], z_lnT=lnT[None], z_tables=bad[None])
     finally:
         f.close()
+
+
+_ORACLE_FLOWS = {}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_sym_step_sharing_group_against_oracle(torch_dev, prec):
+    """A step-sharing group of five flows (one T0, U = 2.5 ... 1.5, one Z table) in the
+    symmetric mode on the orbit kernel: the running flows that read one group's bins are
+    served two per phase-2a block (pairs, and a lone flow when their number is odd, which
+    changes as flows diverge).  Against the oracle's shared-schedule flows: the same
+    statuses, and T_c to 1e-3 in FP32 and 1e-2 in bf16 (its products carry 8 bits; a pair
+    that mixed up its flows' operands or outputs would move T_c by several per cent, since
+    the couplings differ by 0.25 U)."""
+    from paper_2005_00827_amd import fm
+    N, L = 16, 32
+    U = [2.5, 2.25, 2.0, 1.75, 1.5]
+    zl, zt = inputs.synthetic_z_table(N, 2.0, 1.0, 0.01)
+    f = fm.Flow(N=N, L=L, U=U[0], T0=1.0, precision=prec, integrator="rk45", z_lnT=zl,
+                z_table=zt, sym_state=1, y_kernel=3, max_batch=len(U), sync_batch=True,
+                device=torch_dev[1])
+    try:
+        res = f.run_batch(U, [1.0] * len(U))
+    finally:
+        f.close()
+    if "group5" not in _ORACLE_FLOWS:   # the same oracle flows serve both precisions
+        _ORACLE_FLOWS["group5"] = O.flow_sync(
+            O.model(N, L), O.flowcfg(T0=1.0, integrator=1, atol=0.0, z_lnT=zl, z_tab=zt), U)[1]
+    ro = _ORACLE_FLOWS["group5"]
+    assert sum(r["status"] == O.DIVERGED for r in ro) >= 3
+    tol = 1e-2 if prec == "bf16" else 1e-3
+    for i, (r, q) in enumerate(zip(res, ro)):
+        assert r["status"] == q["status"], (i, r, q)
+        if q["status"] == O.DIVERGED:
+            assert abs(r["T_c"] / q["T_c"] - 1.0) <= tol, (i, r["T_c"], q["T_c"])
