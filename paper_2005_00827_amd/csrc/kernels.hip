@@ -2174,7 +2174,8 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
 // w + 48, ...); both tiles' A rows (row p of the 16 representatives' bins) are loaded
 // together once and kept in registers for every chunk, every flow of the block and the
 // direct channel's second product.  For each column chunk and flow all threads stage that
-// flow's B'_0.  Products and stores are the orbit kernel's for operation 0.
+// flow's B'_0, into one of two LDS buffers while the other one's products are formed.
+// Products and stores are the orbit kernel's for operation 0.
 // Grid: one block per unit u = (flow * 3 + channel) N + p.  The running flows that share a
 // flow's bins are taken in pairs in index order; the block of a pair's second flow returns.
 constexpr int kSymThreads = 1024;
@@ -2218,58 +2219,64 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, SymFlo
         const int rr = g.orb_rows[16 * (toff + min(t, nt - 1)) + col];
         return Bf + static_cast<size_t>(max(rr, 0)) * NN + static_cast<size_t>(p) * N;
     };
-    for (int tb = 0; tb < nt; tb += 2 * kWaves) {      // uniform over the block
-        const int t0 = tb + wv;
-        AFrag<kM, KE> A[2];
-        for (int chunk = 0; chunk < nchunk; ++chunk) { // uniform over the block
-            const int n0 = chunk * W;
-            for (int fl = 0; fl < nfl; ++fl) {         // uniform over the block
-                const float* V0 = fl ? F1.V0 : F0.V0;
-                const float* V1 = fl ? F1.V1 : F0.V1;
-                __bf16* Y0 = fl ? F1.Y0 : F0.Y0;
-                __bf16* Y1 = fl ? F1.Y1 : F0.Y1;
-                const float al = fl ? F1.al : F0.al, be = fl ? F1.be : F0.be;
-                const float* zf = zs + (fl ? 256 : 0);
-                if (tb + chunk + fl > 0) __syncthreads();   // the previous B'_0 consumed
-                stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw, V0 + static_cast<size_t>(grp) * NN,
-                                                             V1 + static_cast<size_t>(grp) * NN,
-                                                             pm0, zf, zf[grp], zf[N + grp], al, be,
-                                                             N, n0);
-                __syncthreads();                       // B'_0 staged; every thread
-                if (chunk == 0 && fl == 0) {           // the tiles' A rows, for every chunk and flow
-                    float a[2][KE];
+    // steps i = ((tile run) nchunk + chunk) nfl + flow; step i's B'_0 sits in buffer i & 1 and
+    // step i + 1's is staged into the other one while step i is multiplied, so one barrier
+    // per step separates a buffer's staging from its use and its use from its next staging
+    const int nsteps = (nt + 2 * kWaves - 1) / (2 * kWaves) * nchunk * nfl;
+    auto stage = [&](int i) {
+        const int fl = i % nfl, n0 = (i / nfl) % nchunk * W;
+        const float* V0 = fl ? F1.V0 : F0.V0;
+        const float* V1 = fl ? F1.V1 : F0.V1;
+        const float al = fl ? F1.al : F0.al, be = fl ? F1.be : F0.be;
+        const float* zf = zs + (fl ? 256 : 0);
+        stage_orbit_b<kM, KE, NT, kTwo, kSymThreads>(Braw + (i & 1) * 2 * kBytes,
+                                                     V0 + static_cast<size_t>(grp) * NN,
+                                                     V1 + static_cast<size_t>(grp) * NN, pm0, zf,
+                                                     zf[grp], zf[N + grp], al, be, N, n0);
+    };
+    AFrag<kM, KE> A[2];
+    if (nsteps > 0) stage(0);
+    for (int i = 0; i < nsteps; ++i) {                 // uniform over the block
+        const int fl = i % nfl, chunk = (i / nfl) % nchunk;
+        const int t0 = i / (nfl * nchunk) * 2 * kWaves + wv;
+        const int n0 = chunk * W;
+        if (chunk == 0 && fl == 0) {                   // the tiles' A rows, for every chunk and flow
+            float a[2][KE];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
+            for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
-                }
+            for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
+        }
+        __syncthreads();                               // step i staged; step i - 1's buffer free
+        if (i + 1 < nsteps) stage(i + 1);
+        __bf16* Y0 = fl ? F1.Y0 : F0.Y0;
+        __bf16* Y1 = fl ? F1.Y1 : F0.Y1;
+        const unsigned char* Bi = Braw + (i & 1) * 2 * kBytes;
 #pragma unroll
-                for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
-                    const __bf16* Bw = reinterpret_cast<const __bf16*>(Braw + w * kBytes);
-                    __bf16* Yw = w ? Y1 : Y0;
+        for (int w = 0; w < (kTwo ? 2 : 1); ++w) {
+            const __bf16* Bw = reinterpret_cast<const __bf16*>(Bi + w * kBytes);
+            __bf16* Yw = w ? Y1 : Y0;
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const int t = t0 + j * kWaves;
-                        if (t >= nt) continue;
-                        if (!(g.orb_mask[toff + t] & 1)) continue;
-                        const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
-                        fm_f4 c[NT];
+            for (int j = 0; j < 2; ++j) {
+                const int t = t0 + j * kWaves;
+                if (t >= nt) continue;
+                if (!(g.orb_mask[toff + t] & 1)) continue;
+                const int q = g.orb_q[static_cast<size_t>(toff + t) * 128 + col];   // operation 0
+                fm_f4 c[NT];
 #pragma unroll
-                        for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
-                        mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
-                        if (q >= 0) {
-                            __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
+                for (int u = 0; u < NT; ++u) c[u] = fm_f4{0.f, 0.f, 0.f, 0.f};
+                mfma_bt<kM, KE, NT>(A[j], Bw, c, lane);
+                if (q >= 0) {
+                    __bf16* yrow = Yw + static_cast<size_t>(q) * NN + static_cast<size_t>(grp) * N;
 #pragma unroll
-                            for (int u = 0; u < NT; ++u) {
-                                const int n = n0 + 16 * u + 4 * (lane >> 4);
-                                if ((N & 3) == 0) {
-                                    if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
-                                } else {
+                    for (int u = 0; u < NT; ++u) {
+                        const int n = n0 + 16 * u + 4 * (lane >> 4);
+                        if ((N & 3) == 0) {
+                            if (n < N) *reinterpret_cast<fm_bf4*>(yrow + n) = __builtin_convertvector(c[u], fm_bf4);
+                        } else {
 #pragma unroll
-                                    for (int r = 0; r < 4; ++r)
-                                        if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
-                                }
-                            }
+                            for (int r = 0; r < 4; ++r)
+                                if (n + r < N) yrow[n + r] = static_cast<__bf16>(c[u][r]);
                         }
                     }
                 }
@@ -2284,7 +2291,7 @@ __global__ void __launch_bounds__(kSymThreads) k_y_orb_sym(DevGeom g, const Flow
                                                            const float* bins, const float* binsT,
                                                            YArgs<float> args, int nchunk, int nu) {
     constexpr int KBS = 4 * KE + 8, kBytes = 16 * NT * KBS * 2;
-    __shared__ __align__(16) unsigned char Braw[2 * kBytes];
+    __shared__ __align__(16) unsigned char Braw[2 * 2 * kBytes];   // two buffers of two planes
     __shared__ int pm0[128];
     __shared__ float zs[512];
     const int u = blockIdx.x;
