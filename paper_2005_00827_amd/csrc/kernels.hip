@@ -2170,10 +2170,11 @@ __global__ void __launch_bounds__(kThreads) k_y_mfma_orb(DevGeom g, const FlowSt
 // products (the representatives' own), so B'_0 of a (flow, channel, bin row p, column chunk)
 // serves every representative tile.  A 1024-thread block takes one (channel, p) of one flow,
 // or of two flows that read the same bins (flows of a step-sharing group sit at the same
-// stage temperatures).  Its 16 waves take the tiles, wave w tiles w and w + 16 (then w + 32,
-// w + 48, ...); both tiles' A rows (row p of the 16 representatives' bins) are loaded
-// together once and kept in registers for every chunk, every flow of the block and the
-// direct channel's second product.  For each column chunk and flow all threads stage that
+// stage temperatures).  Its 16 waves take the tiles, wave w tiles w, w + 16 and w + 32 (then
+// w + 48, ...: at N = 128 the 34 tiles of a class are one run, staged once per chunk and
+// flow); the tiles' A rows (row p of the 16 representatives' bins) are loaded once and kept
+// in registers for every chunk, every flow of the block and the direct channel's second
+// product.  For each column chunk and flow all threads stage that
 // flow's B'_0, into one of two LDS buffers while the other one's products are formed.
 // Products and stores are the orbit kernel's for operation 0.
 // Grid: one block per unit u = (flow * 3 + channel) N + p.  The running flows that share a
@@ -2200,6 +2201,7 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, SymFlo
     constexpr int kM = 1, KBS = 4 * KE + 8, W = 16 * NT;
     constexpr int kBytes = W * KBS * 2;
     constexpr int kWaves = kSymThreads / 64;
+    constexpr int kTiles = 3;                          // tiles per wave in a run of tiles
     const int N = g.N, NN = g.NN;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -2222,7 +2224,7 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, SymFlo
     // steps i = ((tile run) nchunk + chunk) nfl + flow; step i's B'_0 sits in buffer i & 1 and
     // step i + 1's is staged into the other one while step i is multiplied, so one barrier
     // per step separates a buffer's staging from its use and its use from its next staging
-    const int nsteps = (nt + 2 * kWaves - 1) / (2 * kWaves) * nchunk * nfl;
+    const int nsteps = (nt + kTiles * kWaves - 1) / (kTiles * kWaves) * nchunk * nfl;
     auto stage = [&](int i) {
         const int fl = i % nfl, n0 = (i / nfl) % nchunk * W;
         const float* V0 = fl ? F1.V0 : F0.V0;
@@ -2234,18 +2236,20 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, SymFlo
                                                      V1 + static_cast<size_t>(grp) * NN, pm0, zf,
                                                      zf[grp], zf[N + grp], al, be, N, n0);
     };
-    AFrag<kM, KE> A[2];
+    AFrag<kM, KE> A[kTiles];
     if (nsteps > 0) stage(0);
     for (int i = 0; i < nsteps; ++i) {                 // uniform over the block
         const int fl = i % nfl, chunk = (i / nfl) % nchunk;
-        const int t0 = i / (nfl * nchunk) * 2 * kWaves + wv;
+        const int t0 = i / (nfl * nchunk) * kTiles * kWaves + wv;
         const int n0 = chunk * W;
         if (chunk == 0 && fl == 0) {                   // the tiles' A rows, for every chunk and flow
-            float a[2][KE];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) gather_a<kM, KE>(a[j], arow(t0 + j * kWaves), N, lane);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) A[j] = make_afrag<kM, KE>(a[j]);
+            for (int j = 0; j < kTiles; ++j) {
+                if (t0 + j * kWaves >= nt) break;      // uniform over the wave
+                float a[KE];
+                gather_a<kM, KE>(a, arow(t0 + j * kWaves), N, lane);
+                A[j] = make_afrag<kM, KE>(a);
+            }
         }
         __syncthreads();                               // step i staged; step i - 1's buffer free
         if (i + 1 < nsteps) stage(i + 1);
@@ -2257,7 +2261,7 @@ __device__ inline void y_orb_sym_block(const DevGeom& g, const float* Bf, SymFlo
             const __bf16* Bw = reinterpret_cast<const __bf16*>(Bi + w * kBytes);
             __bf16* Yw = w ? Y1 : Y0;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < kTiles; ++j) {
                 const int t = t0 + j * kWaves;
                 if (t >= nt) continue;
                 if (!(g.orb_mask[toff + t] & 1)) continue;
